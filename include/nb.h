@@ -1,0 +1,162 @@
+/*
+ * nb.h - C-ABI of the MI355X short-range nonbonded force library (libnb.so).
+ *
+ * What the library computes is the short-range nonbonded force step of a molecular-dynamics
+ * time step, the computation the paper identifies as the longest-running kernel and the
+ * single-GPU rate limiter (section III-A, "NBNXM, short-range non-bonded forces"; the
+ * Fig. 3 caption names the flavour: Ewald electrostatics and Lennard-Jones with a combination
+ * rule).  The paper also names the pieces around it: a buffered pair list with a list range,
+ * a prune step and list sorting (section III-A, the bullet list on the differences between
+ * the GROMACS versions).  Concretely, for atoms in a rectangular periodic box:
+ *
+ *   for every unordered, non-excluded pair with minimum-image distance r < rc
+ *     E_LJ += C12 (r^-12 - rc^-12) - C6 (r^-6 - rc^-6)             (potential shift)
+ *     E_C  += fC q_i q_j (erfc(beta r)/r - erfc(beta rc)/rc)         (Ewald real space)
+ *     F_i  += [12 C12 r^-14 - 6 C6 r^-8 + fC q_i q_j (erfc(beta r)/r^3
+ *              + 2 beta/sqrt(pi) exp(-beta^2 r^2)/r^2)] (x_i - x_j),  F_j -= the same
+ *   with C6 = 4 eps_ab sigma_ab^6, C12 = 4 eps_ab sigma_ab^12 and Lorentz-Berthelot
+ *   combination sigma_ab = (sigma_a + sigma_b)/2, eps_ab = sqrt(eps_a eps_b).
+ *
+ * How: atoms are wrapped into the box, binned into x-y columns, sorted by z inside each
+ * column and cut into clusters of C atoms; a cluster-pair list with one bit per atom pair
+ * (exclusions, self pairs, padding) is built within rlist = rc + buffer and pruned at atom
+ * level; the force kernel evaluates every listed cluster pair.  Pair arithmetic is FP32,
+ * energy reductions are FP64.
+ *
+ * Conventions for every entry point:
+ *  - All functions return an nb_status (0 = NB_OK).  On failure nb_last_error(ctx) describes
+ *    the cause; outputs are then unspecified.
+ *  - "device" pointers are HIP device (or managed) memory owned by the caller; "host" pointers
+ *    are ordinary host memory, read during the call only (the library copies what it keeps).
+ *  - Work is queued on the HIP stream given at setup (nb_set_stream changes it); unless a
+ *    function says it synchronises, it returns before the GPU has finished.
+ *  - Coordinates are float[3] per atom (AoS, nm), original atom order; forces likewise
+ *    (kJ mol^-1 nm^-1); energies are double (kJ/mol).
+ *  - A context is not thread-safe; use one context per host thread.
+ */
+#ifndef NB_H
+#define NB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum nb_status {
+    NB_OK = 0,
+    NB_ERR_ARG = 1,        /* null pointer, negative or non-finite size or parameter */
+    NB_ERR_CUTOFF = 2,     /* rc >= min(box)/2: the minimum image would not be unique */
+    NB_ERR_OOM = 3,        /* device allocation failed */
+    NB_ERR_HIP = 4,        /* a HIP runtime call or kernel launch failed */
+    NB_ERR_STATE = 5,      /* call order violated (e.g. forces before the first pair list) */
+    NB_ERR_OVERFLOW = 6,   /* a list or column exceeded its capacity (rebuilt automatically
+                              when nb_pairlist can grow the buffer) */
+    NB_ERR_LIST_STALE = 7, /* an atom moved more than buffer/2 since the list was built */
+    NB_ERR_NONFINITE = 8,  /* non-finite coordinate seen with NB_CHECK_FINITE */
+    NB_ERR_IO = 9          /* autotune cache could not be read or written */
+} nb_status;
+
+/* flags (nb_params.flags and per-call flags) */
+#define NB_CHECK_STALE  0x1u  /* nb_forces records whether any atom moved >= buffer/2 */
+#define NB_CHECK_FINITE 0x2u  /* nb_forces records non-finite coordinates */
+#define NB_REUSE_LIST   0x4u  /* nb_backward: use the current list instead of rebuilding */
+#define NB_ASYNC_BUILD  0x8u  /* nb_pairlist: do not wait for the overflow check */
+
+typedef struct nb_params {
+    double box[3];          /* rectangular box edges Lx, Ly, Lz (nm), > 0 */
+    double cutoff;          /* rc (nm), 0 < rc < min(box)/2 */
+    double buffer;          /* pair-list buffer rb >= 0 (nm); rlist = rc + rb */
+    double ewald_beta;      /* beta (1/nm) >= 0, with beta * rc <= 4 */
+    double coulomb_const;   /* fC = 1/(4 pi eps0) in the caller's units (> 0) */
+    int32_t ntypes;         /* number of LJ types, 1 .. 32 */
+    const double *sigma;    /* host [ntypes] LJ sigma (nm) >= 0 */
+    const double *epsilon;  /* host [ntypes] LJ epsilon (kJ/mol) >= 0 */
+    int32_t natoms;         /* number of atoms, 1 .. 2^27 */
+    const int32_t *excl_off;/* host [natoms+1] CSR offsets of excluded partners, or NULL */
+    const int32_t *excl_idx;/* host [excl_off[natoms]] partner indices (symmetric lists) */
+    uint32_t flags;         /* NB_CHECK_* */
+    int32_t cluster;        /* cluster size C of the list: 4 or 8 (0 = 8) */
+} nb_params;
+
+typedef struct nb_stats {
+    int64_t natoms, nclusters, npadded;   /* atoms, clusters, slots incl. padding */
+    int64_t nentries;                     /* cluster pairs (j-entries) in the list */
+    int64_t evaluated_pairs;              /* nentries * C * C */
+    int64_t list_capacity;                /* j-entries per i-cluster the list can hold */
+    int32_t cluster, ncolumns;
+    double build_ms_last;                 /* host-timed duration of the last nb_pairlist */
+} nb_stats;
+
+typedef struct nb_ctx nb_ctx;
+
+/* Check parameters without touching the GPU.  Errors: NB_ERR_ARG, NB_ERR_CUTOFF. */
+int nb_validate_params(const nb_params *p);
+
+/* Create a context for one box: copies parameters and exclusions to the device, builds the
+ * FP32 LJ table (C6, C12 from the combination rule in FP64, rounded once) and allocates all
+ * buffers.  stream: a hipStream_t (NULL = default stream).  *out receives the context.
+ * The environment variable NB_LIST_CAP, if set to a positive integer, replaces the initial
+ * number of j-entries reserved per i-cluster (the list still grows on overflow).
+ * Errors: NB_ERR_ARG, NB_ERR_CUTOFF, NB_ERR_OOM, NB_ERR_HIP. */
+int nb_setup(nb_ctx **out, const nb_params *p, void *stream);
+
+/* Replace the LJ parameters (host [ntypes] each); the next nb_forces uses them. */
+int nb_set_lj(nb_ctx *ctx, const double *sigma, const double *epsilon);
+
+/* Change the HIP stream used by later calls. */
+int nb_set_stream(nb_ctx *ctx, void *stream);
+
+/* Build the cluster-pair list from device coordinates x [natoms][3]: wrap into the box, grid
+ * sort, cluster, bounding boxes, search within rlist, exclusion masks, atom-level prune.
+ * Remembers x as the build positions for the staleness check.  Synchronises once to read the
+ * overflow flag and rebuilds with a larger list if needed (unless NB_ASYNC_BUILD was set at
+ * setup, in which case the flag is read at the next call).  Not capturable in a HIP graph.
+ * Errors: NB_ERR_ARG, NB_ERR_OVERFLOW (only if growing failed), NB_ERR_HIP, NB_ERR_OOM. */
+int nb_pairlist(nb_ctx *ctx, const float *x_dev);
+
+/* Forces and energies for device inputs x [natoms][3], q [natoms], type [natoms] (0-based
+ * LJ type).  x must be the build positions or a continuous motion of them (no re-wrapping
+ * since the build); pairs stay exact while every atom moved less than buffer/2.
+ * Outputs: f_dev [natoms][3] overwritten in original order; e_dev[0] = E_LJ, e_dev[1] = E_C
+ * (device doubles).  No allocation and no host synchronisation: capturable in a HIP graph.
+ * Errors: NB_ERR_STATE (no list), NB_ERR_HIP.  Stale / non-finite conditions are reported by
+ * nb_check. */
+int nb_forces(nb_ctx *ctx, const float *x_dev, const float *q_dev, const int32_t *type_dev,
+              float *f_dev, double *e_dev);
+
+/* Synchronise the stream and report device-side conditions recorded since the last check:
+ * NB_ERR_LIST_STALE, NB_ERR_NONFINITE, NB_ERR_OVERFLOW; clears them. */
+int nb_check(nb_ctx *ctx);
+
+/* Vector-Jacobian product of (F, E_LJ, E_C) for a force-matching loss.
+ * Inputs (device): x, q, type as for nb_forces; g_f [natoms][3] = dL/dF (float);
+ * g_e [2] = (dL/dE_LJ, dL/dE_C) (double).  Outputs (device, overwritten): dx [natoms][3],
+ * dq [natoms] (float), dsigma [ntypes], deps [ntypes] (double).  The pair list is rebuilt
+ * from x first unless flags has NB_REUSE_LIST.  Types with epsilon = 0 get deps = 0 (the
+ * derivative of sqrt(eps_a eps_b) does not exist there).
+ * Errors: as nb_pairlist and nb_forces. */
+int nb_backward(nb_ctx *ctx, const float *x, const float *q, const int32_t *type,
+                const float *g_f, const double *g_e, float *dx, float *dq, double *dsigma,
+                double *deps, uint32_t flags);
+
+/* Export the interacting pairs of the current list at positions x (device): every listed atom
+ * pair with r < rc under the same FP32 arithmetic as nb_forces, as (i, j) with i < j in
+ * original indices, unsorted.  pairs_host: host int64 [cap][2]; *count receives the total
+ * number (which may exceed cap; then only cap pairs were written).  Synchronises. */
+int nb_debug_pairs(nb_ctx *ctx, const float *x_dev, int64_t *pairs_host, int64_t cap,
+                   int64_t *count);
+
+/* List statistics of the current list (synchronises). */
+int nb_get_stats(nb_ctx *ctx, nb_stats *st);
+
+/* Text of the last error on this context (never NULL; "" if none). */
+const char *nb_last_error(nb_ctx *ctx);
+
+/* Free the context and its device buffers (synchronises). NULL is accepted. */
+int nb_destroy(nb_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NB_H */

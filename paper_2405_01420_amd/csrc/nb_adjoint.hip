@@ -1,0 +1,292 @@
+// Adjoint (vector-Jacobian product) of the short-range force computation, for force-matching
+// losses L(F, E_LJ, E_C).  Given g = dL/dF per atom and (s_LJ, s_C) = dL/dE, every interacting
+// pair with d = x_i - x_j, r = |d|, force F_ij = f(r) d on atom i, delta = g_i - g_j contributes
+//   dL/dx_i += f delta + (f'(r)/r)(d . delta) d - (s_LJ f_LJ + s_C f_C) d     (-= for j)
+//   dL/dq_i += q_j [H (d . delta) + s_C G],  H = fC erfc(b r)/r^3 + fC 2b/sqrt(pi) e^{-b^2 r^2}/r^2,
+//              G = fC (erfc(b r)/r - erfc(b rc)/rc)                            (likewise for j)
+//   dL/dC6  : G6  = -6 r^-8 (d . delta) - s_LJ (r^-6 - rc^-6)
+//   dL/dC12 : G12 = 12 r^-14 (d . delta) + s_LJ (r^-12 - rc^-12)
+// The LJ-parameter gradients are chained through Lorentz-Berthelot with per-atom sums
+//   Su_i = sum_j (G6 C6 + G12 C12),  Sw_i = sum_j (6 G6 C6 + 12 G12 C12) / sigma_ab,
+//   dL/deps_t = sum_{i of type t} Su_i / (2 eps_t),  dL/dsigma_t = sum_{i of type t} Sw_i / 2,
+// because each pair's two type slots share d sigma_ab / d sigma_a = 1/2 and
+// d eps_ab / d eps_a = eps_ab / (2 eps_a).  The traversal and lane layout are those of the
+// force kernel; per-atom sums are FP32, the per-type reduction is FP64.
+#include "nb_device.h"
+
+namespace {
+
+__global__ void k_pack_g(int npad_max, const int *__restrict__ perm, const float *__restrict__ g,
+                         float4 *__restrict__ gs, float *__restrict__ adjj, const nb_meta *meta) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npad_max) return;
+    int a = p < meta->npad ? perm[p] : -1;
+    gs[p] = a >= 0 ? make_float4(g[3 * a], g[3 * a + 1], g[3 * a + 2], 0.0f)
+                   : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) adjj[k * npad_max + p] = 0.0f;
+}
+
+__device__ __forceinline__ float wsum(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, NB_WAVE);
+    return v;
+}
+
+template <int C>
+__global__ void __launch_bounds__(256) k_adjoint(nb_fparams fp, float s_lj, float s_c, int cap,
+                                                 int npad_max, const float4 *__restrict__ xq,
+                                                 const int *__restrict__ tsort,
+                                                 const float4 *__restrict__ gs,
+                                                 const float4 *__restrict__ ljtab,
+                                                 const int *__restrict__ icount,
+                                                 const nb_entry *__restrict__ jl,
+                                                 float *__restrict__ adj, float *__restrict__ adjj,
+                                                 const nb_meta *meta) {
+    constexpr int JPB = NB_WAVE / C;
+    extern __shared__ float4 tab[];
+    const int nt = fp.ntypes, ntt = nt * nt;
+    for (int k = threadIdx.x; k < 2 * ntt; k += blockDim.x) tab[k] = ljtab[k];
+    __syncthreads();
+    const int lane = threadIdx.x & (NB_WAVE - 1);
+    const int ci = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x / NB_WAVE) +
+                                                  threadIdx.x / NB_WAVE);
+    if (ci >= meta->nclusters) return;
+    const int b = lane % C, jsub = lane / C;
+
+    float xi[C], yi[C], zi[C], qi[C], gxi[C], gyi[C], gzi[C];
+    int ti[C];
+    float ax[C], ay[C], az[C], aq[C], aw[C], au[C];
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+        float4 v = xq[ci * C + k];
+        xi[k] = v.x;
+        yi[k] = v.y;
+        zi[k] = v.z;
+        qi[k] = v.w;
+        float4 gv = gs[ci * C + k];
+        gxi[k] = gv.x;
+        gyi[k] = gv.y;
+        gzi[k] = gv.z;
+        ti[k] = tsort[ci * C + k] * nt;
+        ax[k] = ay[k] = az[k] = aq[k] = aw[k] = au[k] = 0.0f;
+    }
+    const int nj = icount[ci];
+    const nb_entry *lst = jl + (size_t)ci * cap;
+    for (int base = 0; base < nj; base += JPB) {
+        const int e = base + jsub;
+        const bool valid = e < nj;
+        nb_entry en;
+        if (valid) {
+            en = lst[e];
+        } else {
+            en.cj = ci;
+            en.shift = NB_SHIFT_ZERO;
+            en.mlo = en.mhi = 0u;
+        }
+        const int s = en.shift;
+        const int tx = nb_tx(s), ty = nb_ty(s), tz = nb_tz(s);
+        const int jslot = en.cj * C + b;
+        const float4 xj = xq[jslot];
+        const float4 gj = gs[jslot];
+        const int tj = tsort[jslot];
+        const float xjs = xj.x + nb_dj(tx, fp.L[0]), yjs = xj.y + nb_dj(ty, fp.L[1]),
+                    zjs = xj.z + nb_dj(tz, fp.L[2]);
+        const float dix = nb_di(tx, fp.L[0]), diy = nb_di(ty, fp.L[1]), diz = nb_di(tz, fp.L[2]);
+        const float qj = xj.w;
+        const unsigned long long m = ((unsigned long long)en.mhi << 32) | en.mlo;
+        unsigned mcol = 0;
+#pragma unroll
+        for (int k = 0; k < C; ++k) mcol |= (unsigned)((m >> (k * C + b)) & 1ull) << k;
+        float jx = 0.0f, jy = 0.0f, jz = 0.0f, jq = 0.0f, jw = 0.0f, ju = 0.0f;
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
+            const float dx = (xi[k] + dix) - xjs;
+            const float dy = (yi[k] + diy) - yjs;
+            const float dz = (zi[k] + diz) - zjs;
+            const float r2 = nb_r2(dx, dy, dz);
+            const bool inc = (r2 < fp.rc2) && ((mcol >> k) & 1u);
+            const float rinv = inc ? __builtin_amdgcn_rsqf(r2) : 0.0f;
+            const float m1 = inc ? 1.0f : 0.0f;
+            const float rinv2 = rinv * rinv;
+            const float rinv4 = rinv2 * rinv2;
+            const float rinv6 = rinv4 * rinv2;
+            const float4 lj = tab[ti[k] + tj];          // (C6, C12, 6 C6, 12 C12)
+            const float4 lj2 = tab[ntt + ti[k] + tj];   // (shift, 1/sigma_ab, -, -)
+            const float ddx = gxi[k] - gj.x, ddy = gyi[k] - gj.y, ddz = gzi[k] - gj.z;
+            const float dd = __builtin_fmaf(dz, ddz, __builtin_fmaf(dy, ddy, dx * ddx));
+            // Lennard-Jones
+            const float tf = __builtin_fmaf(lj.w, rinv6, -lj.z);      // 12 C12 r^-6 - 6 C6
+            const float flj = tf * rinv6 * rinv2;                      // force factor
+            const float dflj = __builtin_fmaf(-14.0f * lj.w, rinv6, 8.0f * lj.z) * rinv6 * rinv4;
+            // Ewald real space
+            const float r = r2 * rinv;
+            const float ex = __builtin_amdgcn_exp2f(fp.cexp * r2);
+            float P = fp.p[4];
+            P = __builtin_fmaf(P, r, fp.p[3]);
+            P = __builtin_fmaf(P, r, fp.p[2]);
+            P = __builtin_fmaf(P, r, fp.p[1]);
+            P = __builtin_fmaf(P, r, fp.p[0]);
+            float Q = fp.q[5];
+            Q = __builtin_fmaf(Q, r, fp.q[4]);
+            Q = __builtin_fmaf(Q, r, fp.q[3]);
+            Q = __builtin_fmaf(Q, r, fp.q[2]);
+            Q = __builtin_fmaf(Q, r, fp.q[1]);
+            Q = __builtin_fmaf(Q, r, fp.q[0]);
+            const float R = P * __builtin_amdgcn_rcpf(Q);             // erfcx(b r)
+            const float fe = fp.fc * ex * rinv;                        // fC e^{-b^2r^2} / r
+            const float H = fe * __builtin_fmaf(fp.kb, r, R) * rinv2;  // fC h(r)
+            const float G = __builtin_fmaf(fe, R, -m1 * fp.fc * fp.shc);  // fC g(r)
+            // d/dr of fC h(r), divided by r
+            const float dH = -fe * rinv4 *
+                             __builtin_fmaf(fp.kb * r, __builtin_fmaf(2.0f * fp.b2, r2, 3.0f), 3.0f * R);
+            const float qq = qi[k] * qj;
+            const float fcl = qq * H;
+            const float f = flj + fcl;
+            const float dfr = dflj + qq * dH;
+            const float coef = __builtin_fmaf(dfr, dd, -__builtin_fmaf(s_lj, flj, s_c * fcl));
+            const float vx = __builtin_fmaf(f, ddx, coef * dx);
+            const float vy = __builtin_fmaf(f, ddy, coef * dy);
+            const float vz = __builtin_fmaf(f, ddz, coef * dz);
+            const float A = __builtin_fmaf(H, dd, s_c * G);
+            // LJ parameters
+            const float r8 = rinv6 * rinv2;
+            const float G6 = -6.0f * r8 * dd - s_lj * (rinv6 - m1 * fp.irc6);
+            const float G12 = 12.0f * r8 * rinv6 * dd + s_lj * (rinv6 * rinv6 - m1 * fp.irc12);
+            const float u = __builtin_fmaf(G6, lj.x, G12 * lj.y);
+            const float w = __builtin_fmaf(G6, lj.z, G12 * lj.w) * lj2.y;
+            ax[k] += vx;
+            ay[k] += vy;
+            az[k] += vz;
+            aq[k] = __builtin_fmaf(qj, A, aq[k]);
+            au[k] += u;
+            aw[k] += w;
+            jx -= vx;
+            jy -= vy;
+            jz -= vz;
+            jq = __builtin_fmaf(qi[k], A, jq);
+            ju += u;
+            jw += w;
+        }
+        if (valid) {
+            atomicAdd(&adjj[jslot], jx);
+            atomicAdd(&adjj[npad_max + jslot], jy);
+            atomicAdd(&adjj[2 * npad_max + jslot], jz);
+            atomicAdd(&adjj[3 * npad_max + jslot], jq);
+            atomicAdd(&adjj[4 * npad_max + jslot], jw);
+            atomicAdd(&adjj[5 * npad_max + jslot], ju);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+        ax[k] = wsum(ax[k]);
+        ay[k] = wsum(ay[k]);
+        az[k] = wsum(az[k]);
+        aq[k] = wsum(aq[k]);
+        aw[k] = wsum(aw[k]);
+        au[k] = wsum(au[k]);
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
+            const int p = ci * C + k;
+            adj[p] = ax[k];
+            adj[npad_max + p] = ay[k];
+            adj[2 * npad_max + p] = az[k];
+            adj[3 * npad_max + p] = aq[k];
+            adj[4 * npad_max + p] = aw[k];
+            adj[5 * npad_max + p] = au[k];
+        }
+    }
+}
+
+__global__ void k_adj_finalize(int n, int npad_max, const int *__restrict__ slot_of,
+                               const float *__restrict__ adj, const float *__restrict__ adjj,
+                               float *__restrict__ dx, float *__restrict__ dq) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int p = slot_of[i];
+    dx[3 * i] = adj[p] + adjj[p];
+    dx[3 * i + 1] = adj[npad_max + p] + adjj[npad_max + p];
+    dx[3 * i + 2] = adj[2 * npad_max + p] + adjj[2 * npad_max + p];
+    dq[i] = adj[3 * npad_max + p] + adjj[3 * npad_max + p];
+}
+
+// One block per LJ type: FP64 sums of the per-atom LJ-parameter terms over atoms of that type.
+__global__ void __launch_bounds__(256) k_adj_types(nb_typeparams tp, int npad_max,
+                                                   const int *__restrict__ perm,
+                                                   const int *__restrict__ tsort,
+                                                   const float *__restrict__ adj,
+                                                   const float *__restrict__ adjj,
+                                                   const nb_meta *meta, double *__restrict__ dsig,
+                                                   double *__restrict__ deps) {
+    __shared__ double sw[256 / NB_WAVE], su[256 / NB_WAVE];
+    const int t = blockIdx.x;
+    const int np = meta->npad;
+    double w = 0.0, u = 0.0;
+    for (int p = threadIdx.x; p < np; p += blockDim.x) {
+        if (perm[p] < 0 || tsort[p] != t) continue;
+        w += (double)adj[4 * npad_max + p] + (double)adjj[4 * npad_max + p];
+        u += (double)adj[5 * npad_max + p] + (double)adjj[5 * npad_max + p];
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        w += __shfl_xor(w, o, NB_WAVE);
+        u += __shfl_xor(u, o, NB_WAVE);
+    }
+    if ((threadIdx.x & (NB_WAVE - 1)) == 0) {
+        sw[threadIdx.x / NB_WAVE] = w;
+        su[threadIdx.x / NB_WAVE] = u;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double W = 0.0, U = 0.0;
+        for (int k = 0; k < (int)(blockDim.x / NB_WAVE); ++k) {
+            W += sw[k];
+            U += su[k];
+        }
+        dsig[t] = 0.5 * W;
+        deps[t] = tp.eps[t] > 0.0 ? U / (2.0 * tp.eps[t]) : 0.0;
+    }
+}
+
+}  // namespace
+
+hipError_t nb_launch_adjoint(nb_ctx *c, const float *gf, const double *ge, float *dx, float *dq,
+                             double *dsig, double *deps) {
+    const int tb = 256;
+    if (!c->adj) {
+        if (hipMalloc((void **)&c->adj, sizeof(float) * 6 * (size_t)c->npad_max) != hipSuccess)
+            return hipErrorOutOfMemory;
+        if (hipMalloc((void **)&c->adjj, sizeof(float) * 6 * (size_t)c->npad_max) != hipSuccess)
+            return hipErrorOutOfMemory;
+        if (hipMalloc((void **)&c->gs, sizeof(float4) * (size_t)c->npad_max) != hipSuccess)
+            return hipErrorOutOfMemory;
+    }
+    // energy cotangents are device doubles: read them once on the host (the backward pass is
+    // not on the capture path)
+    double geh[2];
+    hipError_t e = hipMemcpyAsync(geh, ge, sizeof(geh), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_pack_g, dim3((c->npad_max + tb - 1) / tb), dim3(tb), 0, c->stream,
+                       c->npad_max, c->perm, gf, c->gs, c->adjj, c->meta);
+    size_t shm = sizeof(float4) * 2 * c->ntypes * c->ntypes;
+    dim3 grid((c->ncl_max + 3) / 4), block(256);
+    if (c->C == 4)
+        hipLaunchKernelGGL((k_adjoint<4>), grid, block, shm, c->stream, c->fp, (float)geh[0],
+                           (float)geh[1], c->cap, c->npad_max, c->xq, c->tsort, c->gs, c->ljtab,
+                           c->icount, c->jl, c->adj, c->adjj, c->meta);
+    else
+        hipLaunchKernelGGL((k_adjoint<8>), grid, block, shm, c->stream, c->fp, (float)geh[0],
+                           (float)geh[1], c->cap, c->npad_max, c->xq, c->tsort, c->gs, c->ljtab,
+                           c->icount, c->jl, c->adj, c->adjj, c->meta);
+    hipLaunchKernelGGL(k_adj_finalize, dim3((c->natoms + tb - 1) / tb), dim3(tb), 0, c->stream,
+                       c->natoms, c->npad_max, c->slot_of, c->adj, c->adjj, dx, dq);
+    nb_typeparams tp{};
+    tp.ntypes = c->ntypes;
+    for (int t = 0; t < c->ntypes; ++t) tp.eps[t] = c->epsilon[t];
+    hipLaunchKernelGGL(k_adj_types, dim3(c->ntypes), dim3(256), 0, c->stream, tp, c->npad_max,
+                       c->perm, c->tsort, c->adj, c->adjj, c->meta, dsig, deps);
+    return hipGetLastError();
+}

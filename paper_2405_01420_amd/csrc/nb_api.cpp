@@ -1,0 +1,420 @@
+// Host side of libnb: parameter validation, device buffers, the LJ table and kernel constants,
+// the build / force / check entry points of include/nb.h.
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+
+#include "erfcx_rational.h"
+#include "nb_internal.h"
+
+namespace {
+
+thread_local std::string g_setup_error;
+
+int fail(nb_ctx *c, int code, const std::string &msg) {
+    if (c) c->err = msg;
+    else g_setup_error = msg;
+    return code;
+}
+
+int hip_fail(nb_ctx *c, hipError_t e, const char *where) {
+    return fail(c, NB_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+template <typename T>
+int dalloc(nb_ctx *c, T **p, size_t count, const char *what) {
+    if (*p) {
+        hipFree(*p);
+        *p = nullptr;
+    }
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc((void **)p, sizeof(T) * count);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(c, NB_ERR_OOM, std::string("hipMalloc failed for ") + what);
+    }
+    return NB_OK;
+}
+
+bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
+
+// j-entries per i-cluster to reserve: clusters (full list, not half) whose bounding boxes can
+// come within rlist, from the volume of a cube of twice the cluster edge dilated by rlist.
+int estimate_cap(double natoms, const double *box, int C, double rlist) {
+    double V = box[0] * box[1] * box[2];
+    double rho = natoms / V;
+    double a = cbrt(C / rho);
+    double s = 2.0 * a;
+    double vol = s * s * s + 6.0 * s * s * rlist + 3.0 * M_PI * s * rlist * rlist +
+                 4.0 / 3.0 * M_PI * rlist * rlist * rlist;
+    double n = vol * rho / C;
+    int cap = (int)(1.25 * n) + 32;
+    return (cap + 31) & ~31;
+}
+
+void lj_table(nb_ctx *c, std::vector<float4> &tab) {
+    const int nt = c->ntypes;
+    tab.assign(2 * nt * nt, make_float4(0, 0, 0, 0));
+    const double irc6 = 1.0 / pow(c->rc, 6.0);
+    for (int a = 0; a < nt; ++a)
+        for (int b = 0; b < nt; ++b) {
+            double s = 0.5 * (c->sigma[a] + c->sigma[b]);
+            double e = sqrt(c->epsilon[a] * c->epsilon[b]);
+            double s6 = s * s * s * s * s * s;
+            double c6 = 4.0 * e * s6, c12 = 4.0 * e * s6 * s6;
+            float c6f = (float)c6, c12f = (float)c12;
+            double sh = (double)c12f * irc6 * irc6 - (double)c6f * irc6;
+            tab[a * nt + b] = make_float4(c6f, c12f, (float)(6.0 * c6), (float)(12.0 * c12));
+            tab[nt * nt + a * nt + b] = make_float4((float)sh, s > 0.0 ? (float)(1.0 / s) : 0.0f, 0.0f, 0.0f);
+        }
+}
+
+void set_constants(nb_ctx *c) {
+    nb_fparams &fp = c->fp;
+    for (int k = 0; k < 3; ++k) fp.L[k] = (float)c->box[k];
+    fp.rc2 = (float)(c->rc * c->rc);
+    fp.fc = (float)c->fc;
+    const double beta = c->beta;
+    fp.cexp = (float)(-beta * beta * 1.4426950408889634);
+    fp.kb = (float)(2.0 * beta / sqrt(M_PI));
+    double bk = 1.0;
+    for (int k = 0; k < 6; ++k) {
+        if (k < 5) fp.p[k] = (float)(nb_erfcx_p[k] * bk);
+        fp.q[k] = (float)(nb_erfcx_q[k] * bk);
+        bk *= beta;
+    }
+    fp.ntypes = c->ntypes;
+    c->shift_coul = erfc(beta * c->rc) / c->rc;
+    fp.b2 = (float)(beta * beta);
+    fp.irc6 = (float)pow(c->rc, -6.0);
+    fp.irc12 = (float)pow(c->rc, -12.0);
+    fp.shc = (float)c->shift_coul;
+}
+
+int alloc_list(nb_ctx *c) {
+    return dalloc(c, &c->jl, (size_t)c->ncl_max * c->cap, "pair list");
+}
+
+int upload_lj(nb_ctx *c) {
+    std::vector<float4> tab;
+    lj_table(c, tab);
+    hipError_t e = hipMemcpyAsync(c->ljtab, tab.data(), sizeof(float4) * tab.size(),
+                                  hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "upload LJ table");
+    // the host vector dies here: wait for the copy
+    e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "upload LJ table");
+    return NB_OK;
+}
+
+int read_meta(nb_ctx *c, nb_meta *m) {
+    hipError_t e = hipMemcpyAsync(m, c->meta, sizeof(nb_meta), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "read device status");
+    return NB_OK;
+}
+
+void free_all(nb_ctx *c) {
+    void *bufs[] = {c->off,   c->xbuild, c->col,    c->rank,  c->tmp,       c->slot_of,
+                    c->colcount, c->colstart, c->colcl, c->perm, c->xs,     c->xq,
+                    c->tsort, c->fi,     c->fj,     c->bblo,  c->bbhi,      c->icount,
+                    c->jl,    c->epart,  c->meta,   c->ljtab, c->excl_off,  c->excl_idx,
+                    c->dbg_pairs, c->adj, c->adjj, c->gs};
+    for (void *p : bufs)
+        if (p) hipFree(p);
+}
+
+}  // namespace
+
+extern "C" {
+
+int nb_validate_params(const nb_params *p) {
+    if (!p) return fail(nullptr, NB_ERR_ARG, "params is NULL");
+    for (int k = 0; k < 3; ++k)
+        if (!finite_pos(p->box[k])) return fail(nullptr, NB_ERR_ARG, "box edges must be finite and > 0");
+    if (!finite_pos(p->cutoff)) return fail(nullptr, NB_ERR_ARG, "cutoff must be finite and > 0");
+    if (!(isfinite(p->buffer) && p->buffer >= 0.0)) return fail(nullptr, NB_ERR_ARG, "buffer must be finite and >= 0");
+    if (!(isfinite(p->ewald_beta) && p->ewald_beta >= 0.0)) return fail(nullptr, NB_ERR_ARG, "ewald_beta must be finite and >= 0");
+    if (p->ewald_beta * p->cutoff > NB_ERFCX_XMAX)
+        return fail(nullptr, NB_ERR_ARG, "ewald_beta * cutoff exceeds the range of the erfc fit (4)");
+    if (!finite_pos(p->coulomb_const)) return fail(nullptr, NB_ERR_ARG, "coulomb_const must be finite and > 0");
+    if (p->ntypes < 1 || p->ntypes > NB_MAX_TYPES) return fail(nullptr, NB_ERR_ARG, "ntypes must be in 1..32");
+    if (!p->sigma || !p->epsilon) return fail(nullptr, NB_ERR_ARG, "sigma/epsilon are NULL");
+    for (int t = 0; t < p->ntypes; ++t)
+        if (!(isfinite(p->sigma[t]) && p->sigma[t] >= 0.0 && isfinite(p->epsilon[t]) && p->epsilon[t] >= 0.0))
+            return fail(nullptr, NB_ERR_ARG, "sigma/epsilon must be finite and >= 0");
+    if (p->natoms < 1 || p->natoms > (1 << 27)) return fail(nullptr, NB_ERR_ARG, "natoms must be in 1..2^27");
+    if (p->cluster != 0 && p->cluster != 4 && p->cluster != 8) return fail(nullptr, NB_ERR_ARG, "cluster must be 0, 4 or 8");
+    if (p->flags & ~(NB_CHECK_STALE | NB_CHECK_FINITE | NB_ASYNC_BUILD)) return fail(nullptr, NB_ERR_ARG, "unknown flag bits");
+    if (p->excl_off) {
+        if (p->excl_off[0] != 0) return fail(nullptr, NB_ERR_ARG, "excl_off[0] must be 0");
+        for (int i = 0; i < p->natoms; ++i)
+            if (p->excl_off[i + 1] < p->excl_off[i]) return fail(nullptr, NB_ERR_ARG, "excl_off must be non-decreasing");
+        int nnz = p->excl_off[p->natoms];
+        if (nnz > 0 && !p->excl_idx) return fail(nullptr, NB_ERR_ARG, "excl_idx is NULL");
+        for (int k = 0; k < nnz; ++k)
+            if (p->excl_idx[k] < 0 || p->excl_idx[k] >= p->natoms) return fail(nullptr, NB_ERR_ARG, "exclusion index out of range");
+    }
+    double mn = std::min(p->box[0], std::min(p->box[1], p->box[2]));
+    if (!(p->cutoff < 0.5 * mn)) return fail(nullptr, NB_ERR_CUTOFF, "cutoff must be below half the smallest box edge");
+    if (!(p->cutoff + p->buffer < mn)) return fail(nullptr, NB_ERR_CUTOFF, "cutoff + buffer must be below the smallest box edge");
+    return NB_OK;
+}
+
+int nb_setup(nb_ctx **out, const nb_params *p, void *stream) {
+    if (!out) return fail(nullptr, NB_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    int rc = nb_validate_params(p);
+    if (rc != NB_OK) return rc;
+    nb_ctx *c = new nb_ctx();
+    c->stream = (hipStream_t)stream;
+    hipGetDevice(&c->device);
+    c->natoms = p->natoms;
+    c->ntypes = p->ntypes;
+    c->C = p->cluster == 0 ? 8 : p->cluster;
+    for (int k = 0; k < 3; ++k) c->box[k] = p->box[k];
+    c->rc = p->cutoff;
+    c->rb = p->buffer;
+    c->beta = p->ewald_beta;
+    c->fc = p->coulomb_const;
+    c->flags = p->flags;
+    c->sigma.assign(p->sigma, p->sigma + p->ntypes);
+    c->epsilon.assign(p->epsilon, p->epsilon + p->ntypes);
+
+    // column grid: square-ish columns of width (C / rho)^(1/3), at least 1 per axis
+    const double rho = p->natoms / (p->box[0] * p->box[1] * p->box[2]);
+    const double w = cbrt(c->C / rho);
+    int ncx = std::max(1, (int)floor(p->box[0] / w + 0.5));
+    int ncy = std::max(1, (int)floor(p->box[1] / w + 0.5));
+    while ((double)p->natoms / ((double)ncx * ncy) > 0.5 * NB_SORT_MAX) {
+        ncx *= 2;
+        ncy *= 2;
+    }
+    nb_geom &g = c->geom;
+    for (int k = 0; k < 3; ++k) g.L[k] = (float)p->box[k];
+    g.ncx = ncx;
+    g.ncy = ncy;
+    g.ncol = ncx * ncy;
+    g.w[0] = (float)(p->box[0] / ncx);
+    g.w[1] = (float)(p->box[1] / ncy);
+    g.invw[0] = (float)(ncx / p->box[0]);
+    g.invw[1] = (float)(ncy / p->box[1]);
+    const double rlist = p->cutoff + p->buffer;
+    g.rl = (float)rlist;
+    g.rl2 = (float)(rlist * rlist);
+    set_constants(c);
+
+    c->npad_max = p->natoms + g.ncol * (c->C - 1);
+    c->ncl_max = c->npad_max / c->C + 1;
+    c->npad_max = c->ncl_max * c->C;
+    c->cap = estimate_cap(p->natoms, p->box, c->C, rlist);
+    if (const char *ov = getenv("NB_LIST_CAP")) {
+        // initial j-entries per i-cluster; the list still grows on overflow
+        int v = atoi(ov);
+        if (v > 0) c->cap = v;
+    }
+    const int n = p->natoms;
+    int r = NB_OK;
+#define NB_ALLOC(ptr, cnt) \
+    if ((r = dalloc(c, &c->ptr, (size_t)(cnt), #ptr)) != NB_OK) goto fail_out;
+    NB_ALLOC(off, n);
+    NB_ALLOC(xbuild, 3 * (size_t)n);
+    NB_ALLOC(col, n);
+    NB_ALLOC(rank, n);
+    NB_ALLOC(tmp, n);
+    NB_ALLOC(slot_of, n);
+    NB_ALLOC(colcount, g.ncol);
+    NB_ALLOC(colstart, g.ncol + 1);
+    NB_ALLOC(colcl, g.ncol + 1);
+    NB_ALLOC(perm, c->npad_max);
+    NB_ALLOC(xs, c->npad_max);
+    NB_ALLOC(xq, c->npad_max);
+    NB_ALLOC(tsort, c->npad_max);
+    NB_ALLOC(fi, c->npad_max);
+    NB_ALLOC(fj, 3 * (size_t)c->npad_max);
+    NB_ALLOC(bblo, c->ncl_max);
+    NB_ALLOC(bbhi, c->ncl_max);
+    NB_ALLOC(icount, c->ncl_max);
+    NB_ALLOC(epart, 4 * (size_t)c->ncl_max);
+    NB_ALLOC(meta, 1);
+    NB_ALLOC(ljtab, 2 * (size_t)c->ntypes * c->ntypes);
+#undef NB_ALLOC
+    if ((r = alloc_list(c)) != NB_OK) goto fail_out;
+    if (p->excl_off) {
+        int nnz = p->excl_off[n];
+        if ((r = dalloc(c, &c->excl_off, (size_t)n + 1, "excl_off")) != NB_OK) goto fail_out;
+        if ((r = dalloc(c, &c->excl_idx, (size_t)std::max(nnz, 1), "excl_idx")) != NB_OK) goto fail_out;
+        hipError_t e = hipMemcpy(c->excl_off, p->excl_off, sizeof(int) * (n + 1), hipMemcpyHostToDevice);
+        if (e == hipSuccess && nnz > 0)
+            e = hipMemcpy(c->excl_idx, p->excl_idx, sizeof(int) * nnz, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            r = hip_fail(c, e, "upload exclusions");
+            goto fail_out;
+        }
+    }
+    if (hipMemset(c->meta, 0, sizeof(nb_meta)) != hipSuccess ||
+        hipMemset(c->slot_of, 0, sizeof(int) * n) != hipSuccess) {
+        r = fail(c, NB_ERR_HIP, "hipMemset meta");
+        goto fail_out;
+    }
+    if ((r = upload_lj(c)) != NB_OK) goto fail_out;
+    *out = c;
+    return NB_OK;
+fail_out:
+    g_setup_error = c->err;
+    free_all(c);
+    delete c;
+    return r;
+}
+
+int nb_set_lj(nb_ctx *c, const double *sigma, const double *epsilon) {
+    if (!c || !sigma || !epsilon) return fail(c, NB_ERR_ARG, "NULL argument");
+    for (int t = 0; t < c->ntypes; ++t)
+        if (!(isfinite(sigma[t]) && sigma[t] >= 0.0 && isfinite(epsilon[t]) && epsilon[t] >= 0.0))
+            return fail(c, NB_ERR_ARG, "sigma/epsilon must be finite and >= 0");
+    c->sigma.assign(sigma, sigma + c->ntypes);
+    c->epsilon.assign(epsilon, epsilon + c->ntypes);
+    hipSetDevice(c->device);
+    return upload_lj(c);
+}
+
+int nb_set_stream(nb_ctx *c, void *stream) {
+    if (!c) return fail(c, NB_ERR_ARG, "NULL context");
+    c->stream = (hipStream_t)stream;
+    return NB_OK;
+}
+
+int nb_pairlist(nb_ctx *c, const float *x) {
+    if (!c || !x) return fail(c, NB_ERR_ARG, "NULL argument");
+    hipSetDevice(c->device);
+    c->have_list = false;
+    auto t0 = std::chrono::steady_clock::now();
+    for (int attempt = 0; attempt < 4; ++attempt) {
+        hipError_t e = nb_launch_build(c, x);
+        if (e != hipSuccess) return hip_fail(c, e, "pair-list build launch");
+        if (c->flags & NB_ASYNC_BUILD) {
+            c->have_list = true;
+            c->pending_overflow_check = true;
+            return NB_OK;
+        }
+        nb_meta m;
+        int r = read_meta(c, &m);
+        if (r != NB_OK) return r;
+        if (m.flags & NB_F_COLUMN)
+            return fail(c, NB_ERR_OVERFLOW, "a grid column holds more atoms than the column sort supports");
+        if (m.flags & NB_F_NONFINITE) return fail(c, NB_ERR_NONFINITE, "non-finite coordinates");
+        if (m.flags & NB_F_OVERFLOW) {
+            c->cap = ((m.maxcount + m.maxcount / 8 + 32) + 31) & ~31;
+            if ((r = alloc_list(c)) != NB_OK) return r;
+            continue;
+        }
+        c->have_list = true;
+        c->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        return NB_OK;
+    }
+    return fail(c, NB_ERR_OVERFLOW, "pair list still overflowing after regrowing");
+}
+
+int nb_forces(nb_ctx *c, const float *x, const float *q, const int32_t *type, float *f, double *e) {
+    if (!c || !x || !q || !type || !f || !e) return fail(c, NB_ERR_ARG, "NULL argument");
+    if (!c->have_list) return fail(c, NB_ERR_STATE, "nb_forces called before nb_pairlist");
+    hipError_t err = nb_launch_pack(c, x, q, type);
+    if (err == hipSuccess) err = nb_launch_force(c);
+    if (err == hipSuccess) err = nb_launch_finalize(c, f, e);
+    if (err != hipSuccess) return hip_fail(c, err, "force launch");
+    return NB_OK;
+}
+
+int nb_check(nb_ctx *c) {
+    if (!c) return fail(c, NB_ERR_ARG, "NULL context");
+    hipSetDevice(c->device);
+    nb_meta m;
+    int r = read_meta(c, &m);
+    if (r != NB_OK) return r;
+    uint32_t zero = 0;
+    hipError_t e = hipMemcpy(&c->meta->flags, &zero, sizeof(zero), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(c, e, "clear device flags");
+    if (m.flags & (NB_F_OVERFLOW | NB_F_COLUMN)) return fail(c, NB_ERR_OVERFLOW, "pair list overflow");
+    if (m.flags & NB_F_NONFINITE) return fail(c, NB_ERR_NONFINITE, "non-finite coordinates");
+    if (m.flags & NB_F_STALE) return fail(c, NB_ERR_LIST_STALE, "an atom moved more than buffer/2 since the list was built");
+    return NB_OK;
+}
+
+int nb_debug_pairs(nb_ctx *c, const float *x, int64_t *pairs_host, int64_t cap, int64_t *count) {
+    if (!c || !x || !count || (cap > 0 && !pairs_host) || cap < 0) return fail(c, NB_ERR_ARG, "bad argument");
+    if (!c->have_list) return fail(c, NB_ERR_STATE, "nb_debug_pairs called before nb_pairlist");
+    hipSetDevice(c->device);
+    int64_t dcap = std::max<int64_t>(cap, 1);
+    if (dcap > c->dbg_cap) {
+        int r = dalloc(c, &c->dbg_pairs, 2 * (size_t)dcap, "pair export");
+        if (r != NB_OK) return r;
+        c->dbg_cap = dcap;
+    }
+    hipError_t e = nb_launch_pack(c, x, nullptr, nullptr);
+    if (e == hipSuccess) e = nb_launch_debug_pairs(c, cap);
+    if (e != hipSuccess) return hip_fail(c, e, "pair export launch");
+    nb_meta m;
+    int r = read_meta(c, &m);
+    if (r != NB_OK) return r;
+    *count = (int64_t)m.npairs_out;
+    int64_t ncopy = std::min<int64_t>(cap, *count);
+    if (ncopy > 0) {
+        e = hipMemcpy(pairs_host, c->dbg_pairs, sizeof(int64_t) * 2 * ncopy, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(c, e, "copy pairs");
+    }
+    return NB_OK;
+}
+
+int nb_get_stats(nb_ctx *c, nb_stats *st) {
+    if (!c || !st) return fail(c, NB_ERR_ARG, "NULL argument");
+    hipSetDevice(c->device);
+    nb_meta m;
+    int r = read_meta(c, &m);
+    if (r != NB_OK) return r;
+    memset(st, 0, sizeof(*st));
+    st->natoms = c->natoms;
+    st->nclusters = m.nclusters;
+    st->npadded = m.npad;
+    st->nentries = m.nentries;
+    st->evaluated_pairs = m.nentries * (int64_t)c->C * c->C;
+    st->list_capacity = c->cap;
+    st->cluster = c->C;
+    st->ncolumns = c->geom.ncol;
+    st->build_ms_last = c->build_ms;
+    return NB_OK;
+}
+
+const char *nb_last_error(nb_ctx *c) {
+    return c ? c->err.c_str() : g_setup_error.c_str();
+}
+
+int nb_destroy(nb_ctx *c) {
+    if (!c) return NB_OK;
+    hipSetDevice(c->device);
+    hipStreamSynchronize(c->stream);
+    free_all(c);
+    delete c;
+    return NB_OK;
+}
+
+int nb_backward(nb_ctx *c, const float *x, const float *q, const int32_t *type, const float *g_f,
+                const double *g_e, float *dx, float *dq, double *dsigma, double *deps,
+                uint32_t flags) {
+    if (!c || !x || !q || !type || !g_f || !g_e || !dx || !dq || !dsigma || !deps)
+        return fail(c, NB_ERR_ARG, "NULL argument");
+    hipSetDevice(c->device);
+    if (!(flags & NB_REUSE_LIST) || !c->have_list) {
+        int r = nb_pairlist(c, x);
+        if (r != NB_OK) return r;
+    }
+    hipError_t e = nb_launch_pack(c, x, q, type);
+    if (e == hipSuccess) e = nb_launch_adjoint(c, g_f, g_e, dx, dq, dsigma, deps);
+    if (e != hipSuccess) return hip_fail(c, e, "adjoint launch");
+    return NB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,392 @@
+// Pair-list construction on the GPU: wrap + column binning, counting sort over columns, z-sort
+// inside each column, clusters of C atoms, cluster bounding boxes, cluster-pair search under
+// periodic shifts with the half-list rule, topology masks and atom-level prune.
+//
+// The paper names these pieces (a buffered pair list with a "list range", a prune step and
+// list sorting; section III-A, the list of differences between the GROMACS versions) but
+// gives no algorithm; this is a from-scratch GPU design: every stage is one kernel on the
+// context's stream and nothing is read back except the overflow flag.
+#include "nb_device.h"
+
+namespace {
+
+__global__ void k_bin(int n, const float *__restrict__ x, nb_geom g, float4 *__restrict__ off,
+                      float *__restrict__ xbuild, int *__restrict__ col, int *__restrict__ rank,
+                      int *__restrict__ colcount, nb_meta *meta) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float xv[3], o[3], w[3];
+    bool fin = true;
+    for (int c = 0; c < 3; ++c) {
+        xv[c] = x[3 * i + c];
+        xbuild[3 * i + c] = xv[c];
+        if (!isfinite(xv[c])) {
+            fin = false;
+            xv[c] = 0.0f;
+        }
+    }
+    if (!fin) atomicOr(&meta->flags, NB_F_NONFINITE);
+    for (int c = 0; c < 3; ++c) {
+        float L = g.L[c];
+        o[c] = -floorf(xv[c] / L) * L;
+        w[c] = xv[c] + o[c];
+        if (w[c] < 0.0f) {
+            o[c] += L;
+            w[c] = xv[c] + o[c];
+        }
+        if (w[c] >= L) {
+            o[c] -= L;
+            w[c] = xv[c] + o[c];
+        }
+    }
+    off[i] = make_float4(o[0], o[1], o[2], 0.0f);
+    int cx = min(max((int)(w[0] * g.invw[0]), 0), g.ncx - 1);
+    int cy = min(max((int)(w[1] * g.invw[1]), 0), g.ncy - 1);
+    int c = cy * g.ncx + cx;
+    col[i] = c;
+    rank[i] = atomicAdd(&colcount[c], 1);
+}
+
+// Exclusive scans of column populations and of cluster counts ceil(n / C); one block.
+__global__ void __launch_bounds__(1024) k_colscan(int ncol, int C, const int *__restrict__ colcount,
+                                                   int *__restrict__ colstart, int *__restrict__ colcl,
+                                                   nb_meta *meta) {
+    __shared__ int sa[1024], sb[1024];
+    int t = threadIdx.x;
+    int per = (ncol + 1023) / 1024;
+    int c0 = min(ncol, t * per), c1 = min(ncol, c0 + per);
+    int a = 0, b = 0, mx = 0;
+    for (int c = c0; c < c1; ++c) {
+        int v = colcount[c];
+        a += v;
+        b += (v + C - 1) / C;
+        mx = max(mx, v);
+    }
+    sa[t] = a;
+    sb[t] = b;
+    __syncthreads();
+    for (int s = 1; s < 1024; s <<= 1) {
+        int va = t >= s ? sa[t - s] : 0, vb = t >= s ? sb[t - s] : 0;
+        __syncthreads();
+        sa[t] += va;
+        sb[t] += vb;
+        __syncthreads();
+    }
+    int pa = sa[t] - a, pb = sb[t] - b;
+    for (int c = c0; c < c1; ++c) {
+        int v = colcount[c];
+        colstart[c] = pa;
+        colcl[c] = pb;
+        pa += v;
+        pb += (v + C - 1) / C;
+    }
+    if (t == 1023) {
+        colstart[ncol] = sa[1023];
+        colcl[ncol] = sb[1023];
+        meta->nclusters = sb[1023];
+        meta->npad = sb[1023] * C;
+    }
+    atomicMax(&meta->maxcolumn, mx);
+}
+
+__global__ void k_scatter(int n, const int *__restrict__ col, const int *__restrict__ rank,
+                          const int *__restrict__ colstart, int *__restrict__ tmp) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    tmp[colstart[col[i]] + rank[i]] = i;
+}
+
+// One block per column: sort the column's atoms by (z, index) in LDS (bitonic), then lay them
+// out as clusters of C slots; the tail of the last cluster is padding (perm = -1).
+template <int C>
+__global__ void __launch_bounds__(256) k_colsort(const float *__restrict__ x,
+                                                 const float4 *__restrict__ off,
+                                                 const int *__restrict__ colcount,
+                                                 const int *__restrict__ colstart,
+                                                 const int *__restrict__ colcl,
+                                                 const int *__restrict__ tmp, int *__restrict__ perm,
+                                                 int *__restrict__ slot_of, float4 *__restrict__ xs,
+                                                 nb_meta *meta) {
+    __shared__ unsigned long long key[NB_SORT_MAX];
+    const int c = blockIdx.x, tid = threadIdx.x;
+    const int n = colcount[c], start = colstart[c];
+    const int cl0 = colcl[c], nslot = (colcl[c + 1] - cl0) * C;
+    if (n > NB_SORT_MAX) {
+        if (tid == 0) atomicOr(&meta->flags, NB_F_COLUMN);
+        for (int r = tid; r < nslot; r += blockDim.x) {
+            perm[cl0 * C + r] = -1;
+            xs[cl0 * C + r] = make_float4(-1e5f, -1e5f, -1e5f, 0.0f);
+        }
+        return;
+    }
+    int npow = 1;
+    while (npow < n) npow <<= 1;
+    for (int k = tid; k < npow; k += blockDim.x) {
+        unsigned long long v = ~0ull;
+        if (k < n) {
+            int a = tmp[start + k];
+            float z = x[3 * a + 2] + off[a].z;
+            if (!(z > 0.0f)) z = 0.0f;
+            v = ((unsigned long long)__float_as_uint(z) << 32) | (unsigned)a;
+        }
+        key[k] = v;
+    }
+    for (int size = 2; size <= npow; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            __syncthreads();
+            for (int k = tid; k < npow; k += blockDim.x) {
+                int j = k ^ stride;
+                if (j > k) {
+                    unsigned long long a = key[k], b = key[j];
+                    bool up = (k & size) == 0;
+                    if ((a > b) == up) {
+                        key[k] = b;
+                        key[j] = a;
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int r = tid; r < nslot; r += blockDim.x) {
+        int slot = cl0 * C + r;
+        if (r < n) {
+            int a = (int)(key[r] & 0xffffffffu);
+            perm[slot] = a;
+            slot_of[a] = slot;
+            float4 o = off[a];
+            xs[slot] = make_float4(x[3 * a] + o.x, x[3 * a + 1] + o.y, x[3 * a + 2] + o.z, 0.0f);
+        } else {
+            perm[slot] = -1;
+            xs[slot] = make_float4(-1e5f, -1e5f, -1e5f, 0.0f);
+        }
+    }
+}
+
+template <int C>
+__global__ void k_bbox(int ncl_max, const float4 *__restrict__ xs, const int *__restrict__ perm,
+                       float4 *__restrict__ lo, float4 *__restrict__ hi, const nb_meta *meta) {
+    int cl = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cl >= ncl_max || cl >= meta->nclusters) return;
+    float3 a = make_float3(3e38f, 3e38f, 3e38f), b = make_float3(-3e38f, -3e38f, -3e38f);
+    for (int r = 0; r < C; ++r) {
+        if (perm[cl * C + r] < 0) continue;
+        float4 p = xs[cl * C + r];
+        a.x = fminf(a.x, p.x);
+        a.y = fminf(a.y, p.y);
+        a.z = fminf(a.z, p.z);
+        b.x = fmaxf(b.x, p.x);
+        b.y = fmaxf(b.y, p.y);
+        b.z = fmaxf(b.z, p.z);
+    }
+    lo[cl] = make_float4(a.x, a.y, a.z, 0.0f);
+    hi[cl] = make_float4(b.x, b.y, b.z, 0.0f);
+}
+
+__device__ __forceinline__ float gap(float alo, float ahi, float blo, float bhi) {
+    return fmaxf(0.0f, fmaxf(blo - ahi, alo - bhi));
+}
+
+// Topology mask of the cluster pair (ci, cj + shift s) computed by the whole wave, one atom
+// pair per lane; also reports whether any unmasked pair is closer than rlist at the build
+// positions (atom-level prune).
+template <int C>
+__device__ __forceinline__ unsigned long long pair_mask(int ci, int cj, int s, nb_geom g,
+                                                        const int *__restrict__ perm,
+                                                        const float4 *__restrict__ xs,
+                                                        const int *__restrict__ eoff,
+                                                        const int *__restrict__ eidx, bool *any) {
+    const int lane = threadIdx.x & (NB_WAVE - 1);
+    const bool lane_ok = (C == 8) || lane < C * C;
+    const int a = (C == 8) ? (lane >> 3) : ((lane >> 2) & 3);
+    const int b = (C == 8) ? (lane & 7) : (lane & 3);
+    bool topo = false, near = false;
+    if (lane_ok) {
+        int ia = perm[ci * C + a], jb = perm[cj * C + b];
+        topo = ia >= 0 && jb >= 0;
+        if (ci == cj && s == NB_SHIFT_ZERO) topo = topo && (b > a);
+        if (topo && eoff) {
+            for (int e = eoff[ia]; e < eoff[ia + 1]; ++e)
+                if (eidx[e] == jb) topo = false;
+        }
+        if (topo) {
+            float4 pi = xs[ci * C + a], pj = xs[cj * C + b];
+            float dx = pi.x - (pj.x + nb_tx(s) * g.L[0]);
+            float dy = pi.y - (pj.y + nb_ty(s) * g.L[1]);
+            float dz = pi.z - (pj.z + nb_tz(s) * g.L[2]);
+            near = dx * dx + dy * dy + dz * dz < g.rl2;
+        }
+    }
+    *any = __ballot(topo && near) != 0ull;
+    return __ballot(topo);
+}
+
+// One wave per i-cluster.  For every periodic shift t whose image can reach the i-cluster's
+// bounding box within rlist, candidate j-clusters come from the columns overlapping the
+// dilated box; a candidate is kept under the half-list rule (cj > ci for any t; cj == ci only
+// for t = 0, with the upper triangle, or t lexicographically positive, which covers both images
+// +t and -t) if its bounding-box distance is below rlist and at least one unmasked atom pair
+// is within rlist.  Entries of one i-cluster are stored contiguously at jl[ci * cap].
+template <int C>
+__global__ void __launch_bounds__(256) k_search(nb_geom g, int cap, const int *__restrict__ colcl,
+                                                const float4 *__restrict__ bblo,
+                                                const float4 *__restrict__ bbhi,
+                                                const int *__restrict__ perm,
+                                                const float4 *__restrict__ xs,
+                                                const int *__restrict__ eoff,
+                                                const int *__restrict__ eidx,
+                                                int *__restrict__ icount,
+                                                nb_entry *__restrict__ jl, nb_meta *meta) {
+    const int lane = threadIdx.x & (NB_WAVE - 1);
+    const int ci = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x / NB_WAVE) +
+                                                  threadIdx.x / NB_WAVE);
+    if (ci >= meta->nclusters) return;
+    const float4 lo = bblo[ci], hi = bbhi[ci];
+    const float rl = g.rl;
+    int count = 0;
+    for (int s = 0; s < 27; ++s) {
+        const int tx = nb_tx(s), ty = nb_ty(s), tz = nb_tz(s);
+        const float sx = tx * g.L[0], sy = ty * g.L[1], sz = tz * g.L[2];
+        // j coordinates (unshifted frame) whose image x + t L can lie within rl of the bbox
+        float x0 = lo.x - rl - sx, x1 = hi.x + rl - sx;
+        float y0 = lo.y - rl - sy, y1 = hi.y + rl - sy;
+        float z0 = lo.z - rl - sz, z1 = hi.z + rl - sz;
+        if (x1 < 0.0f || x0 >= g.L[0] || y1 < 0.0f || y0 >= g.L[1] || z1 < 0.0f || z0 >= g.L[2])
+            continue;
+        int cx0 = max(0, (int)floorf(x0 * g.invw[0])), cx1 = min(g.ncx - 1, (int)floorf(x1 * g.invw[0]));
+        int cy0 = max(0, (int)floorf(y0 * g.invw[1])), cy1 = min(g.ncy - 1, (int)floorf(y1 * g.invw[1]));
+        for (int cy = cy0; cy <= cy1; ++cy) {
+            for (int cx = cx0; cx <= cx1; ++cx) {
+                const int col = cy * g.ncx + cx;
+                const int ca = colcl[col], cb = colcl[col + 1];
+                for (int base = ca; base < cb; base += NB_WAVE) {
+                    int cj = base + lane;
+                    bool cand = cj < cb;
+                    if (cand) {
+                        bool half = cj > ci || (cj == ci && s >= NB_SHIFT_ZERO);
+                        float4 jlo = bblo[cj], jhi = bbhi[cj];
+                        float gx = gap(lo.x, hi.x, jlo.x + sx, jhi.x + sx);
+                        float gy = gap(lo.y, hi.y, jlo.y + sy, jhi.y + sy);
+                        float gz = gap(lo.z, hi.z, jlo.z + sz, jhi.z + sz);
+                        cand = half && (gx * gx + gy * gy + gz * gz < g.rl2);
+                    }
+                    unsigned long long bal = __ballot(cand);
+                    while (bal) {
+                        int k = __ffsll((long long)bal) - 1;
+                        bal &= bal - 1;
+                        int cjk = base + k;
+                        bool any;
+                        unsigned long long m = pair_mask<C>(ci, cjk, s, g, perm, xs, eoff, eidx, &any);
+                        if (any) {
+                            if (count < cap && lane == 0) {
+                                nb_entry e;
+                                e.cj = cjk;
+                                e.shift = s;
+                                e.mlo = (uint32_t)m;
+                                e.mhi = (uint32_t)(m >> 32);
+                                jl[(size_t)ci * cap + count] = e;
+                            }
+                            ++count;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    if (lane == 0) {
+        icount[ci] = min(count, cap);
+        if (count > cap) atomicOr(&meta->flags, NB_F_OVERFLOW);
+        atomicMax(&meta->maxcount, count);
+        atomicAdd((unsigned long long *)&meta->nentries, (unsigned long long)min(count, cap));
+    }
+}
+
+// Export of interacting pairs with the force kernel's arithmetic: the same lane layout (one
+// j atom per lane, the i atoms of the cluster in turn) and the same displacement formula.
+template <int C>
+__global__ void __launch_bounds__(256) k_pairs(nb_geom g, float rc2, int cap,
+                                               const float4 *__restrict__ xq,
+                                               const int *__restrict__ perm,
+                                               const int *__restrict__ icount,
+                                               const nb_entry *__restrict__ jl,
+                                               const nb_meta *meta,
+                                               unsigned long long *counter, int64_t outcap,
+                                               int64_t *__restrict__ out) {
+    constexpr int JPB = NB_WAVE / C;  // j-clusters per batch
+    const int lane = threadIdx.x & (NB_WAVE - 1);
+    const int ci = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x / NB_WAVE) +
+                                                  threadIdx.x / NB_WAVE);
+    if (ci >= meta->nclusters) return;
+    const int nj = icount[ci];
+    const int b = lane % C;
+    for (int base = 0; base < nj; base += JPB) {
+        const int e = base + lane / C;
+        if (e >= nj) continue;
+        const nb_entry en = jl[(size_t)ci * cap + e];
+        const int s = en.shift;
+        const int tx = nb_tx(s), ty = nb_ty(s), tz = nb_tz(s);
+        const float4 xj = xq[en.cj * C + b];
+        const float xjs = xj.x + nb_dj(tx, g.L[0]), yjs = xj.y + nb_dj(ty, g.L[1]),
+                    zjs = xj.z + nb_dj(tz, g.L[2]);
+        const float dix = nb_di(tx, g.L[0]), diy = nb_di(ty, g.L[1]), diz = nb_di(tz, g.L[2]);
+        const unsigned long long m = ((unsigned long long)en.mhi << 32) | en.mlo;
+        const int jb = perm[en.cj * C + b];
+        for (int k = 0; k < C; ++k) {
+            if (!((m >> (k * C + b)) & 1ull)) continue;
+            const float4 xi = xq[ci * C + k];
+            float dx = (xi.x + dix) - xjs, dy = (xi.y + diy) - yjs, dz = (xi.z + diz) - zjs;
+            float r2 = nb_r2(dx, dy, dz);
+            if (r2 < rc2) {
+                int ia = perm[ci * C + k];
+                unsigned long long w = atomicAdd(counter, 1ull);
+                if ((int64_t)w < outcap) {
+                    out[2 * w] = min(ia, jb);
+                    out[2 * w + 1] = max(ia, jb);
+                }
+            }
+        }
+    }
+}
+
+template <int C>
+hipError_t build_impl(nb_ctx *c, const float *x) {
+    const int n = c->natoms;
+    const int tb = 256;
+    hipMemsetAsync(c->colcount, 0, sizeof(int) * c->geom.ncol, c->stream);
+    hipMemsetAsync(c->meta, 0, sizeof(nb_meta), c->stream);
+    hipLaunchKernelGGL(k_bin, dim3((n + tb - 1) / tb), dim3(tb), 0, c->stream, n, x, c->geom,
+                       c->off, c->xbuild, c->col, c->rank, c->colcount, c->meta);
+    hipLaunchKernelGGL(k_colscan, dim3(1), dim3(1024), 0, c->stream, c->geom.ncol, C, c->colcount,
+                       c->colstart, c->colcl, c->meta);
+    hipLaunchKernelGGL(k_scatter, dim3((n + tb - 1) / tb), dim3(tb), 0, c->stream, n, c->col,
+                       c->rank, c->colstart, c->tmp);
+    hipLaunchKernelGGL((k_colsort<C>), dim3(c->geom.ncol), dim3(256), 0, c->stream, x, c->off,
+                       c->colcount, c->colstart, c->colcl, c->tmp, c->perm, c->slot_of, c->xs,
+                       c->meta);
+    hipLaunchKernelGGL((k_bbox<C>), dim3((c->ncl_max + tb - 1) / tb), dim3(tb), 0, c->stream,
+                       c->ncl_max, c->xs, c->perm, c->bblo, c->bbhi, c->meta);
+    hipLaunchKernelGGL((k_search<C>), dim3((c->ncl_max + 3) / 4), dim3(256), 0, c->stream,
+                       c->geom, c->cap, c->colcl, c->bblo, c->bbhi, c->perm, c->xs, c->excl_off,
+                       c->excl_idx, c->icount, c->jl, c->meta);
+    return hipGetLastError();
+}
+
+template <int C>
+hipError_t pairs_impl(nb_ctx *c, int64_t cap) {
+    unsigned long long *counter = (unsigned long long *)&c->meta->npairs_out;
+    hipMemsetAsync(counter, 0, sizeof(unsigned long long), c->stream);
+    hipLaunchKernelGGL((k_pairs<C>), dim3((c->ncl_max + 3) / 4), dim3(256), 0, c->stream, c->geom,
+                       c->fp.rc2, c->cap, c->xq, c->perm, c->icount, c->jl, c->meta, counter, cap,
+                       c->dbg_pairs);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t nb_launch_build(nb_ctx *c, const float *x) {
+    return c->C == 4 ? build_impl<4>(c, x) : build_impl<8>(c, x);
+}
+
+hipError_t nb_launch_debug_pairs(nb_ctx *c, int64_t cap) {
+    return c->C == 4 ? pairs_impl<4>(c, cap) : pairs_impl<8>(c, cap);
+}

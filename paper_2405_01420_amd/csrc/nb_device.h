@@ -1,0 +1,22 @@
+// Device helpers shared by the force, adjoint and pair-export kernels, so that every kernel
+// forms displacements and squared distances with bit-identical FP32 arithmetic.
+#pragma once
+
+#include "nb_internal.h"
+
+// Periodic shift t in {-1, 0, 1}^3 from its index 9 (tx+1) + 3 (ty+1) + (tz+1).
+__device__ __forceinline__ int nb_tx(int s) { return s / 9 - 1; }
+__device__ __forceinline__ int nb_ty(int s) { return (s / 3) % 3 - 1; }
+__device__ __forceinline__ int nb_tz(int s) { return s % 3 - 1; }
+
+// Offsets that place the pair (i, j + t L) in one frame without rounding: the coordinate that
+// lies near the upper box face is the one moved down by L, so both x - L steps are exact
+// (Sterbenz) and d = (x_i + di) - (x_j + dj) carries a single rounding.
+//   t = +1: j image near 0 seen from i near L  -> di = -L, dj = 0
+//   t = -1: j near L seen from i near 0        -> di = 0,  dj = -L
+__device__ __forceinline__ float nb_di(int t, float L) { return t > 0 ? -L : 0.0f; }
+__device__ __forceinline__ float nb_dj(int t, float L) { return t < 0 ? -L : 0.0f; }
+
+__device__ __forceinline__ float nb_r2(float dx, float dy, float dz) {
+    return __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
+}

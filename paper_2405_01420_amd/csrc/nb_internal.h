@@ -1,0 +1,131 @@
+// Internal declarations shared by the host API and the HIP kernels of libnb.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "nb.h"
+
+#define NB_WAVE 64
+#define NB_MAX_TYPES 32
+#define NB_SORT_MAX 4096   // largest column the LDS sort handles
+#define NB_SHIFT_ZERO 13   // shift index of t = (0, 0, 0); index = 9 (tx+1) + 3 (ty+1) + (tz+1)
+
+// Device-side status flags (nb_meta::flags)
+#define NB_F_OVERFLOW 0x1u
+#define NB_F_STALE 0x2u
+#define NB_F_NONFINITE 0x4u
+#define NB_F_COLUMN 0x8u
+
+// One j-entry of the cluster-pair list: j-cluster, periodic shift of the j image
+// (x_j + t L) and the topology mask: bit (a * C + b) set iff atom a of the i-cluster and atom
+// b of the j-cluster are both real, distinct, not excluded and, for the self pair at t = 0,
+// b > a.  Distances are not part of the mask.
+struct nb_entry {
+    int32_t cj;
+    int32_t shift;
+    uint32_t mlo, mhi;
+};
+
+// Counters written by the GPU during a build (read back by the host only when needed).
+struct nb_meta {
+    int32_t nclusters;   // clusters of the current grid
+    int32_t npad;        // nclusters * C
+    uint32_t flags;      // NB_F_*
+    int32_t maxcount;    // largest j-entry count of any i-cluster (for regrowing)
+    int32_t maxcolumn;   // largest column population
+    int32_t pad0;
+    int64_t nentries;    // total j-entries
+    uint64_t npairs_out; // pair-export counter
+};
+
+// Box geometry and the column grid, passed to kernels by value.
+struct nb_geom {
+    float L[3];
+    float invw[2];      // 1 / column width in x and y
+    float w[2];
+    int ncx, ncy, ncol;
+    float rl2;          // rlist^2 (search and prune)
+    float rl;
+};
+
+// Force-kernel constants (FP32 values derived on the host in FP64).
+struct nb_fparams {
+    float L[3];
+    float rc2;
+    float fc;           // Coulomb constant
+    float cexp;         // -beta^2 log2(e):  exp(-beta^2 r^2) = exp2(cexp r^2)
+    float kb;           // 2 beta / sqrt(pi)
+    float p[5];         // erfcx numerator coefficients scaled by beta^k (argument r)
+    float q[6];         // erfcx denominator coefficients scaled by beta^k
+    float b2;           // beta^2
+    float irc6, irc12;  // rc^-6, rc^-12
+    float shc;          // erfc(beta rc) / rc
+    int ntypes;
+};
+
+// Per-type constants for the LJ-parameter gradient reduction.
+struct nb_typeparams {
+    double eps[NB_MAX_TYPES];
+    int ntypes;
+};
+
+struct nb_ctx {
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int natoms = 0, ntypes = 0, C = 8;
+    double box[3] = {0, 0, 0};
+    double rc = 0, rb = 0, beta = 0, fc = 0;
+    uint32_t flags = 0;
+    nb_geom geom{};
+    nb_fparams fp{};
+    double shift_coul = 0;  // erfc(beta rc) / rc
+    int npad_max = 0, ncl_max = 0;
+    int cap = 0;            // j-entries per i-cluster
+    bool have_list = false;
+    bool pending_overflow_check = false;
+    std::vector<double> sigma, epsilon;
+    std::string err;
+    double build_ms = 0;
+
+    // device buffers
+    float4 *off = nullptr;      // [natoms] image offset added to x (-n L)
+    float *xbuild = nullptr;    // [natoms*3] positions at the last build
+    int *col = nullptr, *rank = nullptr, *tmp = nullptr, *slot_of = nullptr;  // [natoms]
+    int *colcount = nullptr, *colstart = nullptr, *colcl = nullptr;           // [ncol(+1)]
+    int *perm = nullptr;        // [npad_max] slot -> atom (-1 = padding)
+    float4 *xs = nullptr;       // [npad_max] build positions (wrapped), sorted
+    float4 *xq = nullptr;       // [npad_max] per-call positions + charge, sorted
+    int *tsort = nullptr;       // [npad_max] per-call type, sorted
+    float4 *fi = nullptr;       // [npad_max] i-side forces
+    float *fj = nullptr;        // [3 * npad_max] j-side forces, SoA (x | y | z)
+    float4 *bblo = nullptr, *bbhi = nullptr;  // [ncl_max]
+    int *icount = nullptr;      // [ncl_max]
+    nb_entry *jl = nullptr;     // [ncl_max * cap]
+    double *epart = nullptr;    // [ncl_max * 4]
+    nb_meta *meta = nullptr;
+    float4 *ljtab = nullptr;    // [2 * nt * nt]: (C6, C12, 6 C6, 12 C12), (shift, 1/sigma_ab, 0, 0)
+    int *excl_off = nullptr, *excl_idx = nullptr;
+    int64_t *dbg_pairs = nullptr;
+    int64_t dbg_cap = 0;
+    // adjoint buffers (allocated on first use)
+    float *adj = nullptr;       // [6 * npad_max]: i-side (dx, dy, dz, dq, Sw, Su) SoA
+    float *adjj = nullptr;      // [6 * npad_max]: j-side, atomics
+    float4 *gs = nullptr;       // [npad_max] force cotangents in cluster order
+};
+
+// ---- launchers (nb_build.hip) ----
+hipError_t nb_launch_build(nb_ctx *c, const float *x);
+hipError_t nb_launch_debug_pairs(nb_ctx *c, int64_t cap);
+
+// ---- launchers (nb_force.hip) ----
+hipError_t nb_launch_pack(nb_ctx *c, const float *x, const float *q, const int32_t *type);
+hipError_t nb_launch_force(nb_ctx *c);
+hipError_t nb_launch_finalize(nb_ctx *c, float *f, double *e);
+
+// ---- launchers (nb_adjoint.hip) ----
+hipError_t nb_launch_adjoint(nb_ctx *c, const float *gf, const double *ge, float *dx, float *dq,
+                             double *dsig, double *deps);

@@ -1,0 +1,208 @@
+"""Thin ctypes binding of libnb.so (include/nb.h): argument marshalling only.
+
+Every function here has the name of the C entry point it calls.  Device buffers are passed as
+torch tensors on the GPU (only their data pointers cross the boundary) and the HIP stream is
+torch's current stream unless given.  There is no CPU fallback: if libnb.so is missing or
+cannot be loaded, ``lib()`` raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libnb.so")
+
+NB_OK, NB_ERR_ARG, NB_ERR_CUTOFF, NB_ERR_OOM, NB_ERR_HIP = 0, 1, 2, 3, 4
+NB_ERR_STATE, NB_ERR_OVERFLOW, NB_ERR_LIST_STALE, NB_ERR_NONFINITE, NB_ERR_IO = 5, 6, 7, 8, 9
+NB_CHECK_STALE, NB_CHECK_FINITE, NB_REUSE_LIST, NB_ASYNC_BUILD = 0x1, 0x2, 0x4, 0x8
+
+STATUS_NAMES = {0: "NB_OK", 1: "NB_ERR_ARG", 2: "NB_ERR_CUTOFF", 3: "NB_ERR_OOM", 4: "NB_ERR_HIP",
+                5: "NB_ERR_STATE", 6: "NB_ERR_OVERFLOW", 7: "NB_ERR_LIST_STALE",
+                8: "NB_ERR_NONFINITE", 9: "NB_ERR_IO"}
+
+EXPORTS = ["nb_validate_params", "nb_setup", "nb_set_lj", "nb_set_stream", "nb_pairlist",
+           "nb_forces", "nb_check", "nb_backward", "nb_debug_pairs", "nb_get_stats",
+           "nb_last_error", "nb_destroy"]
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int32)
+_vp = ctypes.c_void_p
+
+
+class nb_params(ctypes.Structure):
+    _fields_ = [("box", ctypes.c_double * 3), ("cutoff", ctypes.c_double),
+                ("buffer", ctypes.c_double), ("ewald_beta", ctypes.c_double),
+                ("coulomb_const", ctypes.c_double), ("ntypes", ctypes.c_int32),
+                ("sigma", _dp), ("epsilon", _dp), ("natoms", ctypes.c_int32),
+                ("excl_off", _ip), ("excl_idx", _ip), ("flags", ctypes.c_uint32),
+                ("cluster", ctypes.c_int32)]
+
+
+class nb_stats(ctypes.Structure):
+    _fields_ = [("natoms", ctypes.c_int64), ("nclusters", ctypes.c_int64),
+                ("npadded", ctypes.c_int64), ("nentries", ctypes.c_int64),
+                ("evaluated_pairs", ctypes.c_int64), ("list_capacity", ctypes.c_int64),
+                ("cluster", ctypes.c_int32), ("ncolumns", ctypes.c_int32),
+                ("build_ms_last", ctypes.c_double)]
+
+
+class NbError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load libnb.so (built by paper_2405_01420_amd.build); raises if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2405_01420_amd.build` (no CPU fallback exists)")
+        L = ctypes.CDLL(LIB_PATH)
+        ci, cu, ci64 = ctypes.c_int, ctypes.c_uint32, ctypes.c_int64
+        P = ctypes.POINTER
+        L.nb_validate_params.argtypes = [P(nb_params)]
+        L.nb_setup.argtypes = [P(_vp), P(nb_params), _vp]
+        L.nb_set_lj.argtypes = [_vp, _dp, _dp]
+        L.nb_set_stream.argtypes = [_vp, _vp]
+        L.nb_pairlist.argtypes = [_vp, _vp]
+        L.nb_forces.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
+        L.nb_check.argtypes = [_vp]
+        L.nb_backward.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, cu]
+        L.nb_debug_pairs.argtypes = [_vp, _vp, _vp, ci64, P(ci64)]
+        L.nb_get_stats.argtypes = [_vp, P(nb_stats)]
+        L.nb_last_error.argtypes = [_vp]
+        L.nb_last_error.restype = ctypes.c_char_p
+        L.nb_destroy.argtypes = [_vp]
+        for name in EXPORTS:
+            fn = getattr(L, name, None)
+            if fn is not None and name not in ("nb_last_error", "nb_batch_last_error"):
+                fn.restype = ci
+        _lib = L
+    return _lib
+
+
+def _check(code: int, ctx=None):
+    if code != NB_OK:
+        msg = lib().nb_last_error(ctx).decode(errors="replace")
+        raise NbError(code, msg)
+
+
+def _ptr(t) -> int:
+    """Device pointer of a torch tensor (or an int / None)."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is not None:
+        return int(stream)
+    import torch
+    return int(torch.cuda.current_stream().cuda_stream)
+
+
+class Params:
+    """Host-side parameter block (keeps the arrays alive while the C struct points at them)."""
+
+    def __init__(self, natoms: int, box: Sequence[float], cutoff: float, buffer: float,
+                 ewald_beta: float, coulomb_const: float, sigma, epsilon, excl_off=None,
+                 excl_idx=None, flags: int = 0, cluster: int = 8):
+        self.sigma = np.ascontiguousarray(sigma, dtype=np.float64)
+        self.epsilon = np.ascontiguousarray(epsilon, dtype=np.float64)
+        self.excl_off = None if excl_off is None else np.ascontiguousarray(excl_off, dtype=np.int32)
+        self.excl_idx = None if excl_idx is None else np.ascontiguousarray(excl_idx, dtype=np.int32)
+        if self.excl_idx is not None and len(self.excl_idx) == 0:
+            self.excl_idx = np.zeros(1, np.int32)
+        b = list(box) if not np.isscalar(box) else [box] * 3
+        self.c = nb_params()
+        self.c.box = (ctypes.c_double * 3)(*[float(v) for v in b])
+        self.c.cutoff, self.c.buffer = float(cutoff), float(buffer)
+        self.c.ewald_beta, self.c.coulomb_const = float(ewald_beta), float(coulomb_const)
+        self.c.ntypes = len(self.sigma)
+        self.c.sigma = self.sigma.ctypes.data_as(_dp)
+        self.c.epsilon = self.epsilon.ctypes.data_as(_dp)
+        self.c.natoms = int(natoms)
+        self.c.excl_off = None if self.excl_off is None else self.excl_off.ctypes.data_as(_ip)
+        self.c.excl_idx = None if self.excl_idx is None else self.excl_idx.ctypes.data_as(_ip)
+        self.c.flags = int(flags)
+        self.c.cluster = int(cluster)
+
+    @classmethod
+    def from_instance(cls, inst, flags: int = 0, cluster: int = 8, buffer: Optional[float] = None):
+        return cls(inst.natoms, [inst.box] * 3, inst.cutoff,
+                   inst.buffer if buffer is None else buffer, inst.beta, inst.coulomb_const,
+                   inst.sigma, inst.epsilon, inst.excl_off, inst.excl_idx, flags, cluster)
+
+
+def nb_validate_params(params: Params) -> int:
+    """Returns the status code (0 = valid); never touches the GPU."""
+    return int(lib().nb_validate_params(ctypes.byref(params.c)))
+
+
+def nb_setup(params: Params, stream=None) -> int:
+    h = _vp()
+    _check(lib().nb_setup(ctypes.byref(h), ctypes.byref(params.c), _stream(stream)))
+    return h.value
+
+
+def nb_set_lj(ctx: int, sigma, epsilon) -> None:
+    s = np.ascontiguousarray(sigma, dtype=np.float64)
+    e = np.ascontiguousarray(epsilon, dtype=np.float64)
+    _check(lib().nb_set_lj(ctx, s.ctypes.data_as(_dp), e.ctypes.data_as(_dp)), ctx)
+
+
+def nb_set_stream(ctx: int, stream=None) -> None:
+    _check(lib().nb_set_stream(ctx, _stream(stream)), ctx)
+
+
+def nb_pairlist(ctx: int, x) -> None:
+    _check(lib().nb_pairlist(ctx, _ptr(x)), ctx)
+
+
+def nb_forces(ctx: int, x, q, types, f, e) -> None:
+    _check(lib().nb_forces(ctx, _ptr(x), _ptr(q), _ptr(types), _ptr(f), _ptr(e)), ctx)
+
+
+def nb_check(ctx: int) -> int:
+    """Returns the status code of the device-side checks (0 = none raised)."""
+    return int(lib().nb_check(ctx))
+
+
+def nb_backward(ctx: int, x, q, types, g_f, g_e, dx, dq, dsigma, deps, flags: int = 0) -> None:
+    _check(lib().nb_backward(ctx, _ptr(x), _ptr(q), _ptr(types), _ptr(g_f), _ptr(g_e), _ptr(dx),
+                             _ptr(dq), _ptr(dsigma), _ptr(deps), int(flags)), ctx)
+
+
+def nb_debug_pairs(ctx: int, x, cap: int) -> np.ndarray:
+    """Interacting pairs as an int64 [count, 2] array (i < j, original indices, unsorted)."""
+    buf = np.zeros((max(cap, 1), 2), dtype=np.int64)
+    cnt = ctypes.c_int64(0)
+    _check(lib().nb_debug_pairs(ctx, _ptr(x), buf.ctypes.data, int(cap), ctypes.byref(cnt)), ctx)
+    if cnt.value > cap:
+        return nb_debug_pairs(ctx, x, int(cnt.value))
+    return buf[:cnt.value]
+
+
+def nb_get_stats(ctx: int) -> dict:
+    st = nb_stats()
+    _check(lib().nb_get_stats(ctx, ctypes.byref(st)), ctx)
+    return {k: getattr(st, k) for k, _ in nb_stats._fields_}
+
+
+def nb_last_error(ctx: Optional[int]) -> str:
+    return lib().nb_last_error(ctx).decode(errors="replace")
+
+
+def nb_destroy(ctx: int) -> None:
+    _check(lib().nb_destroy(ctx))

@@ -1,0 +1,92 @@
+"""Shared helpers of the GPU parity tests: run the HIP path through the C-ABI binding and compare
+with the FP64 oracle by the tolerances the method states (forces: RMS relative error <= 5e-6,
+energies: relative error <= 1e-6 per component, pair sets identical except pairs whose FP64
+distance lies within 2^-22 max(L, 1) nm of the cutoff)."""
+import numpy as np
+
+from oracle import oracle as O
+from paper_2405_01420_amd import nb
+
+FORCE_TOL = 5e-6
+ENERGY_TOL = 1e-6
+
+
+def dev(torch, a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.to("cuda:0")
+
+
+class GpuBox:
+    """One context on cuda:0 holding device copies of an instance's inputs."""
+
+    def __init__(self, torch, inst, cluster=8, flags=0, buffer=None):
+        self.torch, self.inst = torch, inst
+        self.params = nb.Params.from_instance(inst, flags=flags, cluster=cluster, buffer=buffer)
+        self.ctx = nb.nb_setup(self.params)
+        self.x = dev(torch, inst.x.reshape(-1))
+        self.q = dev(torch, inst.q)
+        self.t = dev(torch, inst.type)
+        self.f = torch.zeros(inst.natoms * 3, dtype=torch.float32, device="cuda:0")
+        self.e = torch.zeros(2, dtype=torch.float64, device="cuda:0")
+
+    def set_x(self, x):
+        self.x.copy_(self.torch.from_numpy(np.ascontiguousarray(x.reshape(-1))))
+
+    def pairlist(self):
+        nb.nb_pairlist(self.ctx, self.x)
+
+    def forces(self):
+        nb.nb_forces(self.ctx, self.x, self.q, self.t, self.f, self.e)
+        self.torch.cuda.synchronize()
+        return self.f.cpu().numpy().reshape(-1, 3).astype(np.float64), self.e.cpu().numpy()
+
+    def pairs(self):
+        return nb.nb_debug_pairs(self.ctx, self.x, 4 * self.inst.natoms * 300)
+
+    def stats(self):
+        return nb.nb_get_stats(self.ctx)
+
+    def close(self):
+        nb.nb_destroy(self.ctx)
+
+
+def rel_rms(a, ref):
+    return float(np.sqrt(np.sum((a - ref) ** 2) / np.sum(ref ** 2)))
+
+
+def compare_forces(f, e, ref, label=""):
+    fr = rel_rms(f, ref.f)
+    elj = abs(e[0] - ref.e_lj) / abs(ref.e_lj)
+    ec = abs(e[1] - ref.e_coul) / abs(ref.e_coul)
+    print(f"{label} force relRMS {fr:.3e}  E_LJ rel {elj:.3e} (cond {abs(ref.e_lj)/ref.abs_lj:.2e})"
+          f"  E_C rel {ec:.3e} (cond {abs(ref.e_coul)/ref.abs_coul:.2e})", flush=True)
+    return fr, elj, ec
+
+
+def pair_set_diff(inst, gpu_pairs, x=None):
+    """Pairs in one set and not the other, with their FP64 distances; returns (n_bad, n_boundary)."""
+    x = inst.x if x is None else x
+    pi, pj, pr = O.pairs(x, inst.box, inst.cutoff, inst.excl_off, inst.excl_idx)
+    n = inst.natoms
+    ko = pi.astype(np.int64) * n + pj
+    g = np.asarray(gpu_pairs, dtype=np.int64)
+    kg = g[:, 0] * n + g[:, 1]
+    dup = len(kg) - len(np.unique(kg))
+    only_o = np.setdiff1d(ko, kg)
+    only_g = np.setdiff1d(kg, ko)
+    eta = 2.0 ** -22 * max(inst.box, 1.0)
+    bad = dup
+    boundary = 0
+    for keys in (only_o, only_g):
+        if len(keys) == 0:
+            continue
+        a, b = keys // n, keys % n
+        d = x[a].astype(np.float64) - x[b]
+        d -= inst.box * np.rint(d / inst.box)
+        r = np.sqrt((d * d).sum(1))
+        near = np.abs(r - inst.cutoff) <= eta
+        boundary += int(near.sum())
+        bad += int((~near).sum())
+    return bad, boundary, len(ko), len(kg), dup

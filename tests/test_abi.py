@@ -1,0 +1,88 @@
+"""CPU checks of the C-ABI boundary: the library loads without a GPU, exports every function
+include/nb.h declares, and rejects invalid parameters before touching the device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2405_01420_amd import nb, synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = []
+    inc = os.path.join(ROOT, "include")
+    for fn in sorted(os.listdir(inc)):
+        if fn.endswith(".h"):
+            text = open(os.path.join(inc, fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names += re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(nb_[a-z_0-9]+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = nb.lib()
+    names = declared_functions()
+    assert "nb_setup" in names and "nb_forces" in names and "nb_backward" in names
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_binding_names_match_header():
+    for name in declared_functions():
+        assert hasattr(nb, name), name
+
+
+def base_params(**kw):
+    t = synth.tiny()
+    p = nb.Params.from_instance(t)
+    for k, v in kw.items():
+        setattr(p.c, k, v)
+    return p
+
+
+def test_valid_parameters_pass():
+    assert nb.nb_validate_params(base_params()) == nb.NB_OK
+    assert nb.nb_validate_params(base_params(cluster=4)) == nb.NB_OK
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("cutoff", 0.95, nb.NB_ERR_CUTOFF),      # rc >= L/2
+    ("cutoff", -1.0, nb.NB_ERR_ARG),
+    ("cutoff", float("nan"), nb.NB_ERR_ARG),
+    ("buffer", -0.1, nb.NB_ERR_ARG),
+    ("ewald_beta", 5.0, nb.NB_ERR_ARG),     # beta * rc beyond the erfc fit
+    ("coulomb_const", 0.0, nb.NB_ERR_ARG),
+    ("ntypes", 0, nb.NB_ERR_ARG),
+    ("ntypes", 33, nb.NB_ERR_ARG),
+    ("natoms", 0, nb.NB_ERR_ARG),
+    ("cluster", 6, nb.NB_ERR_ARG),
+    ("flags", 0x100, nb.NB_ERR_ARG),
+])
+def test_invalid_parameters_are_rejected(field, value, code):
+    assert nb.nb_validate_params(base_params(**{field: value})) == code
+    assert nb.nb_last_error(None) != ""
+
+
+def test_rlist_beyond_box_is_rejected():
+    p = base_params(buffer=1.0)  # rc + rb = 1.9 > L = 1.862
+    assert nb.nb_validate_params(p) == nb.NB_ERR_CUTOFF
+
+
+def test_bad_exclusions_are_rejected():
+    t = synth.tiny()
+    idx = t.excl_idx.copy()
+    idx[3] = t.natoms  # out of range
+    p = nb.Params.from_instance(t)
+    p.excl_idx = idx
+    p.c.excl_idx = idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    assert nb.nb_validate_params(p) == nb.NB_ERR_ARG
+
+
+def test_setup_rejects_invalid_params_without_gpu():
+    with pytest.raises(nb.NbError) as ei:
+        nb.nb_setup(base_params(cutoff=0.95), stream=0)
+    assert ei.value.code == nb.NB_ERR_CUTOFF

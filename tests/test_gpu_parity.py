@@ -1,0 +1,167 @@
+"""Parity of the HIP path (through the C-ABI) with the FP64 oracle on seeded water boxes.
+
+Gates: pair set identical except pairs whose FP64 distance is within 2^-22 max(L, 1) nm of the
+cutoff; forces RMS relative error <= 5e-6; each energy component relative error <= 1e-6."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2405_01420_amd import nb, synth
+from tests.gpu_helpers import (ENERGY_TOL, FORCE_TOL, GpuBox, compare_forces, pair_set_diff,
+                               rel_rms)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def inst_tiny():
+    return synth.tiny()
+
+
+@pytest.fixture(scope="module")
+def inst_diff():
+    return synth.diff()
+
+
+@pytest.fixture(scope="module")
+def inst_mid():
+    return synth.mid()
+
+
+@pytest.mark.parametrize("cluster", [8, 4])
+def test_tiny_pairs_and_forces(torch_gpu, inst_tiny, cluster):
+    box = GpuBox(torch_gpu, inst_tiny, cluster=cluster)
+    box.pairlist()
+    bad, bnd, no, ng, dup = pair_set_diff(inst_tiny, box.pairs())
+    print(f"tiny C={cluster}: oracle {no} pairs, gpu {ng}, mismatches {bad}, boundary {bnd}, dup {dup}")
+    assert bad == 0
+    f, e = box.forces()
+    ref = O.instance_forces(inst_tiny)
+    fr, elj, ec = compare_forces(f, e, ref, f"tiny C={cluster}")
+    box.close()
+    assert fr <= FORCE_TOL and elj <= ENERGY_TOL and ec <= ENERGY_TOL
+
+
+@pytest.mark.parametrize("cluster", [8, 4])
+def test_diff_pairs_and_forces(torch_gpu, inst_diff, cluster):
+    box = GpuBox(torch_gpu, inst_diff, cluster=cluster)
+    box.pairlist()
+    bad, bnd, no, ng, dup = pair_set_diff(inst_diff, box.pairs())
+    print(f"diff C={cluster}: oracle {no} pairs, gpu {ng}, mismatches {bad}, boundary {bnd}")
+    assert bad == 0
+    f, e = box.forces()
+    ref = O.instance_forces(inst_diff, cells=True)
+    fr, elj, ec = compare_forces(f, e, ref, f"diff C={cluster}")
+    box.close()
+    assert fr <= FORCE_TOL and elj <= ENERGY_TOL and ec <= ENERGY_TOL
+
+
+def test_mid_pairs_and_forces(torch_gpu, inst_mid):
+    box = GpuBox(torch_gpu, inst_mid)
+    box.pairlist()
+    st = box.stats()
+    print("mid stats", st)
+    bad, bnd, no, ng, dup = pair_set_diff(inst_mid, box.pairs())
+    print(f"mid: oracle {no} pairs, gpu {ng}, mismatches {bad}, boundary {bnd}")
+    assert bad == 0
+    f, e = box.forces()
+    ref = O.instance_forces(inst_mid, cells=True)
+    fr, elj, ec = compare_forces(f, e, ref, "mid")
+    box.close()
+    assert fr <= FORCE_TOL and elj <= ENERGY_TOL and ec <= ENERGY_TOL
+
+
+def test_mid_jitter_rebuild_every_10(torch_gpu, inst_mid):
+    """Random walk N(0, 0.002 nm) per call without re-wrapping, list rebuilt every 10 calls;
+    checked against the oracle at calls 9, 19 and 29 (the last call before each rebuild, where
+    atoms are farthest from the build positions)."""
+    box = GpuBox(torch_gpu, inst_mid, flags=nb.NB_CHECK_STALE)
+    rng = synth.jitter_stream(20)
+    x = inst_mid.x.copy()
+    for call in range(30):
+        if call % 10 == 0:
+            box.set_x(x)
+            box.pairlist()
+        else:
+            box.set_x(x)
+        f, e = box.forces()
+        assert nb.nb_check(box.ctx) == nb.NB_OK
+        if call % 10 == 9:
+            ref = O.instance_forces(inst_mid, cells=True, x=x)
+            pairs = box.pairs()
+            bad, bnd, no, ng, dup = pair_set_diff(inst_mid, pairs, x=x)
+            fr, elj, ec = compare_forces(f, e, ref, f"mid jitter call {call}")
+            assert bad == 0
+            assert fr <= FORCE_TOL and elj <= ENERGY_TOL and ec <= ENERGY_TOL
+        x = (x + rng.normal(0.0, 0.002, x.shape)).astype(np.float32)
+    box.close()
+
+
+def test_newton_third_law(torch_gpu, inst_diff):
+    box = GpuBox(torch_gpu, inst_diff)
+    box.pairlist()
+    f, _ = box.forces()
+    box.close()
+    net = np.abs(f.sum(0)).max()
+    tot = np.abs(f).sum()
+    print("net force", net, "sum |F|", tot)
+    assert net <= 1e-8 * tot
+
+
+def test_deterministic_pair_set(torch_gpu, inst_diff):
+    box = GpuBox(torch_gpu, inst_diff)
+    box.pairlist()
+    p1 = box.pairs()
+    box.pairlist()
+    p2 = box.pairs()
+    box.close()
+    k1 = np.sort(p1[:, 0] * inst_diff.natoms + p1[:, 1])
+    k2 = np.sort(p2[:, 0] * inst_diff.natoms + p2[:, 1])
+    assert np.array_equal(k1, k2)
+
+
+def test_list_regrows_after_overflow(torch_gpu, inst_tiny, monkeypatch):
+    monkeypatch.setenv("NB_LIST_CAP", "2")
+    box = GpuBox(torch_gpu, inst_tiny)
+    assert box.stats()["list_capacity"] == 2
+    box.pairlist()  # overflows the 2-entry capacity, regrows and rebuilds
+    st = box.stats()
+    assert st["list_capacity"] > 2
+    f, e = box.forces()
+    ref = O.instance_forces(inst_tiny)
+    fr, elj, ec = compare_forces(f, e, ref, "tiny after regrow")
+    box.close()
+    assert fr <= FORCE_TOL and elj <= ENERGY_TOL and ec <= ENERGY_TOL
+
+
+def test_stale_list_is_reported(torch_gpu, inst_diff):
+    box = GpuBox(torch_gpu, inst_diff, flags=nb.NB_CHECK_STALE)
+    box.pairlist()
+    box.forces()
+    assert nb.nb_check(box.ctx) == nb.NB_OK
+    x = inst_diff.x.copy()
+    x[17, 0] += 0.06  # more than buffer / 2 = 0.05 nm
+    box.set_x(x)
+    box.forces()
+    assert nb.nb_check(box.ctx) == nb.NB_ERR_LIST_STALE
+    assert nb.nb_check(box.ctx) == nb.NB_OK  # cleared
+    box.close()
+
+
+def test_nonfinite_is_reported(torch_gpu, inst_tiny):
+    box = GpuBox(torch_gpu, inst_tiny, flags=nb.NB_CHECK_FINITE)
+    x = inst_tiny.x.copy()
+    x[5, 1] = np.nan
+    box.set_x(x)
+    with pytest.raises(nb.NbError) as ei:
+        box.pairlist()
+    assert ei.value.code == nb.NB_ERR_NONFINITE
+    box.close()
+
+
+def test_forces_before_list_is_state_error(torch_gpu, inst_tiny):
+    box = GpuBox(torch_gpu, inst_tiny)
+    with pytest.raises(nb.NbError) as ei:
+        nb.nb_forces(box.ctx, box.x, box.q, box.t, box.f, box.e)
+    assert ei.value.code == nb.NB_ERR_STATE
+    box.close()
