@@ -150,6 +150,13 @@ int nb_debug_pairs(nb_ctx *ctx, const float *x_dev, int64_t *pairs_host, int64_t
 /* List statistics of the current list (synchronises). */
 int nb_get_stats(nb_ctx *ctx, nb_stats *st);
 
+/* Kernel timing: with on != 0, every later nb_forces records a HIP event pair around its force
+ * kernel on the context's stream (a few microseconds of host overhead per call; off by default).
+ * nb_get_timing synchronises, returns the summed kernel time in milliseconds and the number of
+ * timed launches since the last nb_get_timing, and resets both. */
+int nb_set_timing(nb_ctx *ctx, int on);
+int nb_get_timing(nb_ctx *ctx, double *force_kernel_ms, int64_t *launches);
+
 /* Text of the last error on this context (never NULL; "" if none). */
 const char *nb_last_error(nb_ctx *ctx);
 

@@ -106,7 +106,7 @@ __global__ void __launch_bounds__(256) k_adjoint(nb_fparams fp, float s_lj, floa
             const float dz = (zi[k] + diz) - zjs;
             const float r2 = nb_r2(dx, dy, dz);
             const bool inc = (r2 < fp.rc2) && ((mcol >> k) & 1u);
-            const float rinv = inc ? __builtin_amdgcn_rsqf(r2) : 0.0f;
+            const float rinv = inc ? nb_rsq(r2) : 0.0f;
             const float m1 = inc ? 1.0f : 0.0f;
             const float rinv2 = rinv * rinv;
             const float rinv4 = rinv2 * rinv2;
@@ -133,7 +133,7 @@ __global__ void __launch_bounds__(256) k_adjoint(nb_fparams fp, float s_lj, floa
             Q = __builtin_fmaf(Q, r, fp.q[2]);
             Q = __builtin_fmaf(Q, r, fp.q[1]);
             Q = __builtin_fmaf(Q, r, fp.q[0]);
-            const float R = P * __builtin_amdgcn_rcpf(Q);             // erfcx(b r)
+            const float R = P * nb_rcp(Q);             // erfcx(b r)
             const float fe = fp.fc * ex * rinv;                        // fC e^{-b^2r^2} / r
             const float H = fe * __builtin_fmaf(fp.kb, r, R) * rinv2;  // fC h(r)
             const float G = __builtin_fmaf(fe, R, -m1 * fp.fc * fp.shc);  // fC g(r)

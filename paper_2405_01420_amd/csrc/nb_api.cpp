@@ -111,6 +111,20 @@ int upload_lj(nb_ctx *c) {
     return NB_OK;
 }
 
+// Sum the recorded event pairs into timed_ms (synchronises on the last stop event).
+int drain_events(nb_ctx *c) {
+    for (size_t k = 0; k < c->ev_used; ++k) {
+        hipError_t e = hipEventSynchronize(c->ev[2 * k + 1]);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, c->ev[2 * k], c->ev[2 * k + 1]);
+        if (e != hipSuccess) return hip_fail(c, e, "kernel timing");
+        c->timed_ms += ms;
+        c->timed_n += 1;
+    }
+    c->ev_used = 0;
+    return NB_OK;
+}
+
 int read_meta(nb_ctx *c, nb_meta *m) {
     hipError_t e = hipMemcpyAsync(m, c->meta, sizeof(nb_meta), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -323,9 +337,46 @@ int nb_forces(nb_ctx *c, const float *x, const float *q, const int32_t *type, fl
     if (!c || !x || !q || !type || !f || !e) return fail(c, NB_ERR_ARG, "NULL argument");
     if (!c->have_list) return fail(c, NB_ERR_STATE, "nb_forces called before nb_pairlist");
     hipError_t err = nb_launch_pack(c, x, q, type);
+    if (c->timing && err == hipSuccess) {
+        const size_t kMaxPairs = 4096;
+        if (c->ev_used == kMaxPairs) {
+            int r = drain_events(c);
+            if (r != NB_OK) return r;
+        }
+        if (c->ev.size() < 2 * (c->ev_used + 1)) {
+            hipEvent_t a, b;
+            if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+                return fail(c, NB_ERR_HIP, "hipEventCreate");
+            c->ev.push_back(a);
+            c->ev.push_back(b);
+        }
+        err = hipEventRecord(c->ev[2 * c->ev_used], c->stream);
+    }
     if (err == hipSuccess) err = nb_launch_force(c);
+    if (c->timing && err == hipSuccess) {
+        err = hipEventRecord(c->ev[2 * c->ev_used + 1], c->stream);
+        c->ev_used += 1;
+    }
     if (err == hipSuccess) err = nb_launch_finalize(c, f, e);
     if (err != hipSuccess) return hip_fail(c, err, "force launch");
+    return NB_OK;
+}
+
+int nb_set_timing(nb_ctx *c, int on) {
+    if (!c) return fail(c, NB_ERR_ARG, "NULL context");
+    c->timing = on != 0;
+    return NB_OK;
+}
+
+int nb_get_timing(nb_ctx *c, double *ms, int64_t *n) {
+    if (!c || !ms || !n) return fail(c, NB_ERR_ARG, "NULL argument");
+    hipSetDevice(c->device);
+    int r = drain_events(c);
+    if (r != NB_OK) return r;
+    *ms = c->timed_ms;
+    *n = c->timed_n;
+    c->timed_ms = 0;
+    c->timed_n = 0;
     return NB_OK;
 }
 
@@ -396,6 +447,7 @@ int nb_destroy(nb_ctx *c) {
     if (!c) return NB_OK;
     hipSetDevice(c->device);
     hipStreamSynchronize(c->stream);
+    for (hipEvent_t ev : c->ev) hipEventDestroy(ev);
     free_all(c);
     delete c;
     return NB_OK;

@@ -20,3 +20,19 @@ __device__ __forceinline__ float nb_dj(int t, float L) { return t < 0 ? -L : 0.0
 __device__ __forceinline__ float nb_r2(float dx, float dy, float dz) {
     return __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
 }
+
+// Hardware reciprocal square root and reciprocal (about 1 ulp) followed by one Newton step, so
+// that the result carries only the rounding of the last fused multiply-add.  A systematic bias
+// of the raw instruction would otherwise be amplified twelve-fold in r^-12 energy sums.
+__device__ __forceinline__ float nb_rsq(float x) {
+    const float y = __builtin_amdgcn_rsqf(x);
+    const float h = x * y;
+    const float e = __builtin_fmaf(-h, y, 1.0f);   // 1 - x y^2
+    return __builtin_fmaf(0.5f * y, e, y);
+}
+
+__device__ __forceinline__ float nb_rcp(float x) {
+    const float y = __builtin_amdgcn_rcpf(x);
+    const float e = __builtin_fmaf(-x, y, 1.0f);
+    return __builtin_fmaf(y, e, y);
+}

@@ -134,7 +134,7 @@ __global__ void __launch_bounds__(256) k_force(nb_fparams fp, int cap, int npad_
             const float dz = (zi[k] + diz) - zjs;
             const float r2 = nb_r2(dx, dy, dz);
             const bool inc = (r2 < fp.rc2) && ((mcol >> k) & 1u);
-            const float rinv = inc ? __builtin_amdgcn_rsqf(r2) : 0.0f;
+            const float rinv = inc ? nb_rsq(r2) : 0.0f;
             const float rinv2 = rinv * rinv;
             const float rinv6 = rinv2 * rinv2 * rinv2;
             const float4 lj = tab[ti[k] + tj];   // (C6, C12, 6 C6, 12 C12)
@@ -160,7 +160,7 @@ __global__ void __launch_bounds__(256) k_force(nb_fparams fp, int cap, int npad_
             Q = __builtin_fmaf(Q, r, fp.q[2]);
             Q = __builtin_fmaf(Q, r, fp.q[1]);
             Q = __builtin_fmaf(Q, r, fp.q[0]);
-            const float R = P * __builtin_amdgcn_rcpf(Q);
+            const float R = P * nb_rcp(Q);
             const float qq = qi[k] * qj;
             const float qe = qq * ex;
             const float t1 = qe * rinv;               // fC q_i q_j exp(-b^2 r^2) / r

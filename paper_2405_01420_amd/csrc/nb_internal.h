@@ -115,6 +115,12 @@ struct nb_ctx {
     float *adj = nullptr;       // [6 * npad_max]: i-side (dx, dy, dz, dq, Sw, Su) SoA
     float *adjj = nullptr;      // [6 * npad_max]: j-side, atomics
     float4 *gs = nullptr;       // [npad_max] force cotangents in cluster order
+    // kernel timing
+    bool timing = false;
+    std::vector<hipEvent_t> ev;  // pairs (start, stop)
+    size_t ev_used = 0;          // pairs recorded
+    double timed_ms = 0;
+    int64_t timed_n = 0;
 };
 
 // ---- launchers (nb_build.hip) ----

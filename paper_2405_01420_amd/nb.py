@@ -26,7 +26,7 @@ STATUS_NAMES = {0: "NB_OK", 1: "NB_ERR_ARG", 2: "NB_ERR_CUTOFF", 3: "NB_ERR_OOM"
 
 EXPORTS = ["nb_validate_params", "nb_setup", "nb_set_lj", "nb_set_stream", "nb_pairlist",
            "nb_forces", "nb_check", "nb_backward", "nb_debug_pairs", "nb_get_stats",
-           "nb_last_error", "nb_destroy"]
+           "nb_last_error", "nb_destroy", "nb_set_timing", "nb_get_timing"]
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _ip = ctypes.POINTER(ctypes.c_int32)
@@ -82,6 +82,8 @@ def lib():
         L.nb_last_error.argtypes = [_vp]
         L.nb_last_error.restype = ctypes.c_char_p
         L.nb_destroy.argtypes = [_vp]
+        L.nb_set_timing.argtypes = [_vp, ci]
+        L.nb_get_timing.argtypes = [_vp, P(ctypes.c_double), P(ci64)]
         for name in EXPORTS:
             fn = getattr(L, name, None)
             if fn is not None and name not in ("nb_last_error", "nb_batch_last_error"):
@@ -206,3 +208,15 @@ def nb_last_error(ctx: Optional[int]) -> str:
 
 def nb_destroy(ctx: int) -> None:
     _check(lib().nb_destroy(ctx))
+
+
+def nb_set_timing(ctx: int, on: bool) -> None:
+    _check(lib().nb_set_timing(ctx, int(bool(on))), ctx)
+
+
+def nb_get_timing(ctx: int):
+    """(summed force-kernel milliseconds, number of timed launches); resets the counters."""
+    ms = ctypes.c_double(0)
+    n = ctypes.c_int64(0)
+    _check(lib().nb_get_timing(ctx, ctypes.byref(ms), ctypes.byref(n)), ctx)
+    return ms.value, n.value
