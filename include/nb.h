@@ -163,6 +163,65 @@ const char *nb_last_error(nb_ctx *ctx);
 /* Free the context and its device buffers (synchronises). NULL is accepted. */
 int nb_destroy(nb_ctx *ctx);
 
+/* ---------------------------------------------------------------------------------------
+ * Batched form: many independent boxes of uneven size, one list per box, and one persistent
+ * force launch per cluster shape over the i-clusters of all boxes.  Ensemble-level
+ * parallelism (independent simulations) is the outermost level of parallelism the paper
+ * describes (section I-A); here the ensemble shares one GPU launch so that small boxes, which
+ * alone cannot fill the GPU (the latency-bound regime of Fig. 2, section III-A), are processed
+ * together, and the tail of uneven work is handled by a work queue in descending cost order.
+ * ------------------------------------------------------------------------------------- */
+typedef struct nb_batch nb_batch;
+
+typedef struct nb_batch_info {
+    int32_t nbox;
+    int32_t sorted;           /* work items in descending cost order (1) or box order (0) */
+    int64_t natoms;           /* atoms over all boxes */
+    int64_t nitems;           /* i-clusters (work items) over all boxes */
+    int64_t nentries;         /* j-entries over all boxes */
+    int64_t evaluated_pairs;  /* sum over boxes of nentries * C^2 */
+    int32_t grid_blocks[2];   /* persistent blocks per launch for C = 4 and C = 8 (0 = unused) */
+    int32_t graph_ready;      /* 1 if a captured graph exists for the current lists */
+    int32_t pad;
+    double build_ms_last;     /* host-timed duration of the last nb_batch_pairlist */
+} nb_batch_info;
+
+/* Create a batch of nbox boxes.  atom_off: host [nbox+1] offsets of each box's atoms in the
+ * concatenated arrays (atom_off[0] = 0, atom_off[nbox] = common->natoms); boxes: host
+ * [nbox][3] box edges; clusters: host [nbox] cluster size per box (4 or 8), or NULL to use
+ * common->cluster for all.  common supplies cutoff, buffer, beta, fC, LJ types and the
+ * exclusions over the concatenated atoms (global indices; no exclusion may cross boxes);
+ * common->box is ignored.  stream: hipStream_t used by all batch calls; graph capture needs a
+ * stream other than the legacy default stream.
+ * Errors: NB_ERR_ARG, NB_ERR_CUTOFF (any box), NB_ERR_OOM, NB_ERR_HIP. */
+int nb_batch_setup(nb_batch **out, int32_t nbox, const int32_t *atom_off, const double *boxes,
+                   const int32_t *clusters, const nb_params *common, void *stream);
+
+/* Work schedule: sorted != 0 orders work items by descending j-list length (the default);
+ * blocks_per_cu > 0 fixes the persistent grid to that many 256-thread blocks per compute unit
+ * (0 = as many as fit). Invalidates a captured graph. */
+int nb_batch_set_schedule(nb_batch *bt, int32_t sorted, int32_t blocks_per_cu);
+
+/* Build every box's pair list from device coordinates x [natoms][3] (concatenated), then the
+ * work list.  Synchronises (overflow checks, work-list upload). Not capturable. */
+int nb_batch_pairlist(nb_batch *bt, const float *x_dev);
+
+/* Forces (f [natoms][3], concatenated, original order) and per-box energies e [nbox][2]
+ * (E_LJ, E_C) for device inputs x, q, type.  Four launches on the batch stream; no allocation
+ * or host synchronisation.  Errors: NB_ERR_STATE (no lists), NB_ERR_HIP. */
+int nb_batch_forces(nb_batch *bt, const float *x, const float *q, const int32_t *type, float *f,
+                    double *e);
+
+/* As nb_batch_forces, through a HIP graph: the first call after a list build (or with other
+ * pointers) captures the launches and instantiates the graph, later calls replay it with one
+ * hipGraphLaunch. */
+int nb_batch_graph_forces(nb_batch *bt, const float *x, const float *q, const int32_t *type,
+                          float *f, double *e);
+
+int nb_batch_get_info(nb_batch *bt, nb_batch_info *info);
+const char *nb_batch_last_error(nb_batch *bt);
+int nb_batch_destroy(nb_batch *bt);
+
 #ifdef __cplusplus
 }
 #endif

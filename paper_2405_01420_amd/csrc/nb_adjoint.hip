@@ -95,9 +95,7 @@ __global__ void __launch_bounds__(256) k_adjoint(nb_fparams fp, float s_lj, floa
         const float dix = nb_di(tx, fp.L[0]), diy = nb_di(ty, fp.L[1]), diz = nb_di(tz, fp.L[2]);
         const float qj = xj.w;
         const unsigned long long m = ((unsigned long long)en.mhi << 32) | en.mlo;
-        unsigned mcol = 0;
-#pragma unroll
-        for (int k = 0; k < C; ++k) mcol |= (unsigned)((m >> (k * C + b)) & 1ull) << k;
+        const unsigned mcol = nb_mask_column<C>(m, b);
         float jx = 0.0f, jy = 0.0f, jz = 0.0f, jq = 0.0f, jw = 0.0f, ju = 0.0f;
 #pragma unroll
         for (int k = 0; k < C; ++k) {

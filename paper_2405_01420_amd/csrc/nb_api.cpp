@@ -144,6 +144,13 @@ void free_all(nb_ctx *c) {
 
 }  // namespace
 
+int nb_read_meta(nb_ctx *c, nb_meta *m) { return read_meta(c, m); }
+
+int nb_regrow_list(nb_ctx *c, int maxcount) {
+    c->cap = ((maxcount + maxcount / 8 + 32) + 31) & ~31;
+    return alloc_list(c);
+}
+
 extern "C" {
 
 int nb_validate_params(const nb_params *p) {

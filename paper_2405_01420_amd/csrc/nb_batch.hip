@@ -1,0 +1,486 @@
+// Batched form: independent boxes (an ensemble) evaluated together.  Every box keeps its own
+// context (grid, list, buffers); the force phase is one persistent launch per cluster shape in
+// which each wavefront pulls (box, i-cluster) work items from an atomic counter, in descending
+// order of j-list length so that the longest items start first and the tail is short.  Pack,
+// finalize and energy reduction each run as one launch over all boxes (2-D grids), so the
+// whole force call is four launches that a HIP graph replays with one host call.
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <vector>
+
+#include "nb_force_body.h"
+
+struct nb_box_desc {
+    const int *perm;
+    const int *slot_of;
+    const float4 *off;
+    float4 *xq;
+    int *tsort;
+    const int *icount;
+    const nb_entry *jl;
+    float4 *fi;
+    float *fj;
+    double *epart;
+    const nb_meta *meta;
+    int cap, npad_max, natoms, atom_off;
+    float L[3];
+    int pad;
+};
+
+struct nb_batch {
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int nbox = 0;
+    int64_t natoms = 0;
+    std::vector<nb_ctx *> box;
+    std::vector<int> atom_off, cluster;
+    nb_fparams fp{};        // shared constants (L is set per box on the device)
+    double shift_coul = 0;
+    float4 *ljtab = nullptr;  // the LJ table of box 0 (identical for all boxes)
+    int ntypes = 0;
+    nb_box_desc *d_desc = nullptr;
+    int2 *d_items[2] = {nullptr, nullptr};  // work items for C = 4 and C = 8
+    int nitems[2] = {0, 0};
+    int item_cap[2] = {0, 0};
+    unsigned *d_counter = nullptr;           // two queue heads
+    int max_npad = 0, max_natoms = 0;
+    int sorted = 1, blocks_per_cu = 0;
+    int grid[2] = {0, 0};
+    bool have_list = false;
+    bool graph_ready = false;
+    hipGraphExec_t gexec = nullptr;
+    const void *gptr[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    int64_t nentries = 0, evaluated = 0;
+    double build_ms = 0;
+    std::string err;
+};
+
+namespace {
+
+__global__ void k_batch_pack(const nb_box_desc *__restrict__ desc, const float *__restrict__ x,
+                             const float *__restrict__ q, const int32_t *__restrict__ type,
+                             int ntypes, unsigned *counter) {
+    const int bidx = blockIdx.y;
+    const nb_box_desc d = desc[bidx];
+    if (bidx == 0 && blockIdx.x == 0 && threadIdx.x < 2) counter[threadIdx.x] = 0u;
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= d.npad_max || p >= d.meta->npad) return;
+    const int a = d.perm[p];
+    if (a >= 0) {
+        const int g = d.atom_off + a;
+        const float4 o = d.off[a];
+        int t = type[g];
+        t = min(max(t, 0), ntypes - 1);
+        d.xq[p] = make_float4(x[3 * g] + o.x, x[3 * g + 1] + o.y, x[3 * g + 2] + o.z, q[g]);
+        d.tsort[p] = t;
+    } else {
+        d.xq[p] = make_float4(-1e5f, -1e5f, -1e5f, 0.0f);
+        d.tsort[p] = 0;
+    }
+    d.fj[p] = 0.0f;
+    d.fj[d.npad_max + p] = 0.0f;
+    d.fj[2 * d.npad_max + p] = 0.0f;
+}
+
+// Persistent force kernel: every wavefront loops, taking the next work item from the queue,
+// until the queue is empty; every wave reaches that exit.
+template <int C>
+__global__ void __launch_bounds__(256) k_batch_force(nb_fparams fp, const nb_box_desc *__restrict__ desc,
+                                                     const int2 *__restrict__ items, int nitems,
+                                                     const float4 *__restrict__ ljtab,
+                                                     unsigned *counter) {
+    extern __shared__ float4 tab[];
+    const int ntt = fp.ntypes * fp.ntypes;
+    for (int k = threadIdx.x; k < 2 * ntt; k += blockDim.x) tab[k] = ljtab[k];
+    __syncthreads();
+    const int lane = threadIdx.x & (NB_WAVE - 1);
+    for (;;) {
+        unsigned it = 0;
+        if (lane == 0) it = atomicAdd(counter, 1u);
+        it = (unsigned)__builtin_amdgcn_readfirstlane((int)__shfl((int)it, 0, NB_WAVE));
+        if (it >= (unsigned)nitems) break;
+        const int2 w = items[it];
+        const int b = __builtin_amdgcn_readfirstlane(w.x);
+        const int ci = __builtin_amdgcn_readfirstlane(w.y);
+        const nb_box_desc &d = desc[b];
+        nb_fparams f = fp;
+        f.L[0] = d.L[0];
+        f.L[1] = d.L[1];
+        f.L[2] = d.L[2];
+        nb_force_cluster<C>(f, tab, ci, d.cap, d.npad_max, d.xq, d.tsort, d.icount, d.jl, d.fi, d.fj,
+                            d.epart);
+    }
+}
+
+__global__ void k_batch_finalize(const nb_box_desc *__restrict__ desc, float *__restrict__ f) {
+    const nb_box_desc d = desc[blockIdx.y];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= d.natoms) return;
+    const int p = d.slot_of[i];
+    const float4 a = d.fi[p];
+    const int g = d.atom_off + i;
+    f[3 * g] = a.x + d.fj[p];
+    f[3 * g + 1] = a.y + d.fj[d.npad_max + p];
+    f[3 * g + 2] = a.z + d.fj[2 * d.npad_max + p];
+}
+
+__global__ void __launch_bounds__(256) k_batch_energy(const nb_box_desc *__restrict__ desc,
+                                                      double shift_coul, double *__restrict__ e) {
+    __shared__ double s[3][256 / NB_WAVE];
+    const nb_box_desc d = desc[blockIdx.x];
+    const int ncl = d.meta->nclusters;
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int k = threadIdx.x; k < ncl; k += blockDim.x) {
+        a += d.epart[4 * k];
+        b += d.epart[4 * k + 1];
+        c += d.epart[4 * k + 2];
+    }
+    a = nb_wave_sum_d(a);
+    b = nb_wave_sum_d(b);
+    c = nb_wave_sum_d(c);
+    const int w = threadIdx.x / NB_WAVE;
+    if ((threadIdx.x & (NB_WAVE - 1)) == 0) {
+        s[0][w] = a;
+        s[1][w] = b;
+        s[2][w] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double ta = 0.0, tb = 0.0, tc = 0.0;
+        for (int k = 0; k < (int)(blockDim.x / NB_WAVE); ++k) {
+            ta += s[0][k];
+            tb += s[1][k];
+            tc += s[2][k];
+        }
+        e[2 * blockIdx.x] = ta;
+        e[2 * blockIdx.x + 1] = tb - shift_coul * tc;
+    }
+}
+
+thread_local std::string g_batch_error;
+
+int bfail(nb_batch *bt, int code, const std::string &msg) {
+    if (bt) bt->err = msg;
+    else g_batch_error = msg;
+    return code;
+}
+
+void free_batch(nb_batch *bt) {
+    for (nb_ctx *c : bt->box)
+        if (c) nb_destroy(c);
+    if (bt->gexec) hipGraphExecDestroy(bt->gexec);
+    void *bufs[] = {bt->d_desc, bt->d_items[0], bt->d_items[1], bt->d_counter};
+    for (void *p : bufs)
+        if (p) hipFree(p);
+}
+
+int upload_desc(nb_batch *bt) {
+    std::vector<nb_box_desc> h(bt->nbox);
+    for (int b = 0; b < bt->nbox; ++b) {
+        nb_ctx *c = bt->box[b];
+        nb_box_desc &d = h[b];
+        d.perm = c->perm;
+        d.slot_of = c->slot_of;
+        d.off = c->off;
+        d.xq = c->xq;
+        d.tsort = c->tsort;
+        d.icount = c->icount;
+        d.jl = c->jl;
+        d.fi = c->fi;
+        d.fj = c->fj;
+        d.epart = c->epart;
+        d.meta = c->meta;
+        d.cap = c->cap;
+        d.npad_max = c->npad_max;
+        d.natoms = c->natoms;
+        d.atom_off = bt->atom_off[b];
+        for (int k = 0; k < 3; ++k) d.L[k] = (float)c->box[k];
+        d.pad = 0;
+    }
+    hipError_t e = hipMemcpy(bt->d_desc, h.data(), sizeof(nb_box_desc) * h.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return bfail(bt, NB_ERR_HIP, std::string("upload box descriptors: ") + hipGetErrorString(e));
+    return NB_OK;
+}
+
+template <int C>
+int grid_for(nb_batch *bt) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, bt->device) != hipSuccess) return 0;
+    int per_cu = bt->blocks_per_cu;
+    if (per_cu <= 0) {
+        size_t shm = sizeof(float4) * 2 * bt->ntypes * bt->ntypes;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_force<C>, 256, shm) != hipSuccess ||
+            per_cu <= 0)
+            per_cu = 1;
+    }
+    return per_cu * prop.multiProcessorCount;
+}
+
+hipError_t launch_forces(nb_batch *bt, const float *x, const float *q, const int32_t *type, float *f,
+                         double *e) {
+    const int tb = 256;
+    hipLaunchKernelGGL(k_batch_pack, dim3((bt->max_npad + tb - 1) / tb, bt->nbox), dim3(tb), 0,
+                       bt->stream, bt->d_desc, x, q, type, bt->ntypes, bt->d_counter);
+    const size_t shm = sizeof(float4) * 2 * bt->ntypes * bt->ntypes;
+    if (bt->nitems[0] > 0)
+        hipLaunchKernelGGL(k_batch_force<4>, dim3(bt->grid[0]), dim3(256), shm, bt->stream, bt->fp,
+                           bt->d_desc, bt->d_items[0], bt->nitems[0], bt->ljtab, bt->d_counter);
+    if (bt->nitems[1] > 0)
+        hipLaunchKernelGGL(k_batch_force<8>, dim3(bt->grid[1]), dim3(256), shm, bt->stream, bt->fp,
+                           bt->d_desc, bt->d_items[1], bt->nitems[1], bt->ljtab, bt->d_counter + 1);
+    hipLaunchKernelGGL(k_batch_finalize, dim3((bt->max_natoms + tb - 1) / tb, bt->nbox), dim3(tb), 0,
+                       bt->stream, bt->d_desc, f);
+    hipLaunchKernelGGL(k_batch_energy, dim3(bt->nbox), dim3(256), 0, bt->stream, bt->d_desc,
+                       bt->shift_coul, e);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+extern "C" {
+
+int nb_batch_setup(nb_batch **out, int32_t nbox, const int32_t *atom_off, const double *boxes,
+                   const int32_t *clusters, const nb_params *common, void *stream) {
+    if (!out || !atom_off || !boxes || !common || nbox < 1) return bfail(nullptr, NB_ERR_ARG, "bad argument");
+    *out = nullptr;
+    if (atom_off[0] != 0 || atom_off[nbox] != common->natoms)
+        return bfail(nullptr, NB_ERR_ARG, "atom_off must start at 0 and end at common->natoms");
+    for (int b = 0; b < nbox; ++b)
+        if (atom_off[b + 1] <= atom_off[b]) return bfail(nullptr, NB_ERR_ARG, "every box needs at least one atom");
+    nb_batch *bt = new nb_batch();
+    bt->stream = (hipStream_t)stream;
+    hipGetDevice(&bt->device);
+    bt->nbox = nbox;
+    bt->natoms = common->natoms;
+    bt->atom_off.assign(atom_off, atom_off + nbox + 1);
+    bt->ntypes = common->ntypes;
+    int64_t items_max[2] = {0, 0};
+    for (int b = 0; b < nbox; ++b) {
+        const int n = atom_off[b + 1] - atom_off[b];
+        nb_params pb = *common;
+        pb.natoms = n;
+        for (int k = 0; k < 3; ++k) pb.box[k] = boxes[3 * b + k];
+        pb.cluster = clusters ? clusters[b] : common->cluster;
+        pb.flags = common->flags & ~NB_ASYNC_BUILD;
+        std::vector<int32_t> eo, ei;
+        if (common->excl_off) {
+            const int a0 = atom_off[b], base = common->excl_off[a0];
+            eo.resize(n + 1);
+            for (int i = 0; i <= n; ++i) eo[i] = common->excl_off[a0 + i] - base;
+            ei.resize(std::max(eo[n], 1));
+            for (int k = 0; k < eo[n]; ++k) {
+                int g = common->excl_idx[base + k] - a0;
+                if (g < 0 || g >= n) {
+                    free_batch(bt);
+                    delete bt;
+                    return bfail(nullptr, NB_ERR_ARG, "an exclusion crosses two boxes");
+                }
+                ei[k] = g;
+            }
+            pb.excl_off = eo.data();
+            pb.excl_idx = ei.data();
+        }
+        nb_ctx *c = nullptr;
+        int r = nb_setup(&c, &pb, stream);
+        if (r != NB_OK) {
+            std::string msg = std::string("box ") + std::to_string(b) + ": " + nb_last_error(nullptr);
+            free_batch(bt);
+            delete bt;
+            return bfail(nullptr, r, msg);
+        }
+        bt->box.push_back(c);
+        bt->cluster.push_back(c->C);
+        items_max[c->C == 8] += c->ncl_max;
+        bt->max_npad = std::max(bt->max_npad, c->npad_max);
+        bt->max_natoms = std::max(bt->max_natoms, n);
+    }
+    bt->fp = bt->box[0]->fp;
+    bt->shift_coul = bt->box[0]->shift_coul;
+    bt->ljtab = bt->box[0]->ljtab;
+    hipError_t e = hipMalloc((void **)&bt->d_desc, sizeof(nb_box_desc) * nbox);
+    if (e == hipSuccess) e = hipMalloc((void **)&bt->d_counter, sizeof(unsigned) * 2);
+    for (int s = 0; s < 2 && e == hipSuccess; ++s) {
+        bt->item_cap[s] = (int)std::max<int64_t>(items_max[s], 1);
+        e = hipMalloc((void **)&bt->d_items[s], sizeof(int2) * bt->item_cap[s]);
+    }
+    if (e != hipSuccess) {
+        free_batch(bt);
+        delete bt;
+        return bfail(nullptr, NB_ERR_OOM, "batch buffers");
+    }
+    int r = upload_desc(bt);
+    if (r != NB_OK) {
+        std::string msg = bt->err;
+        free_batch(bt);
+        delete bt;
+        return bfail(nullptr, r, msg);
+    }
+    bt->grid[0] = items_max[0] > 0 ? grid_for<4>(bt) : 0;
+    bt->grid[1] = items_max[1] > 0 ? grid_for<8>(bt) : 0;
+    *out = bt;
+    return NB_OK;
+}
+
+int nb_batch_set_schedule(nb_batch *bt, int32_t sorted, int32_t blocks_per_cu) {
+    if (!bt || blocks_per_cu < 0) return bfail(bt, NB_ERR_ARG, "bad argument");
+    bt->sorted = sorted != 0;
+    bt->blocks_per_cu = blocks_per_cu;
+    hipSetDevice(bt->device);
+    bool any4 = false, any8 = false;
+    for (int c : bt->cluster) (c == 8 ? any8 : any4) = true;
+    bt->grid[0] = any4 ? grid_for<4>(bt) : 0;
+    bt->grid[1] = any8 ? grid_for<8>(bt) : 0;
+    bt->graph_ready = false;
+    if (bt->have_list) {
+        // re-order the existing work list
+        return nb_batch_pairlist(bt, nullptr);
+    }
+    return NB_OK;
+}
+
+int nb_batch_pairlist(nb_batch *bt, const float *x) {
+    if (!bt) return bfail(bt, NB_ERR_ARG, "NULL batch");
+    hipSetDevice(bt->device);
+    auto t0 = std::chrono::steady_clock::now();
+    if (x) {
+        bt->have_list = false;
+        std::vector<bool> todo(bt->nbox, true);
+        for (int attempt = 0; attempt < 4; ++attempt) {
+            for (int b = 0; b < bt->nbox; ++b)
+                if (todo[b]) {
+                    nb_ctx *c = bt->box[b];
+                    hipError_t e = nb_launch_build(c, x + 3 * (size_t)bt->atom_off[b]);
+                    if (e != hipSuccess) return bfail(bt, NB_ERR_HIP, std::string("build: ") + hipGetErrorString(e));
+                }
+            hipError_t e = hipStreamSynchronize(bt->stream);
+            if (e != hipSuccess) return bfail(bt, NB_ERR_HIP, std::string("build: ") + hipGetErrorString(e));
+            bool again = false;
+            for (int b = 0; b < bt->nbox; ++b) {
+                if (!todo[b]) continue;
+                nb_ctx *c = bt->box[b];
+                nb_meta m;
+                if (nb_read_meta(c, &m) != NB_OK) return bfail(bt, NB_ERR_HIP, c->err);
+                todo[b] = false;
+                if (m.flags & NB_F_COLUMN) return bfail(bt, NB_ERR_OVERFLOW, "a grid column overflowed");
+                if (m.flags & NB_F_NONFINITE) return bfail(bt, NB_ERR_NONFINITE, "non-finite coordinates");
+                if (m.flags & NB_F_OVERFLOW) {
+                    if (nb_regrow_list(c, m.maxcount) != NB_OK) return bfail(bt, NB_ERR_OOM, c->err);
+                    todo[b] = true;
+                    again = true;
+                }
+                c->have_list = !todo[b];
+            }
+            if (!again) break;
+            if (attempt == 3) return bfail(bt, NB_ERR_OVERFLOW, "pair list still overflowing");
+        }
+    } else if (!bt->have_list) {
+        return bfail(bt, NB_ERR_STATE, "no pair lists");
+    }
+    // work list: (box, i-cluster) with the j-list length as cost
+    std::vector<std::pair<int, int2>> items[2];
+    bt->nentries = 0;
+    bt->evaluated = 0;
+    for (int b = 0; b < bt->nbox; ++b) {
+        nb_ctx *c = bt->box[b];
+        nb_meta m;
+        if (nb_read_meta(c, &m) != NB_OK) return bfail(bt, NB_ERR_HIP, c->err);
+        std::vector<int> cnt(std::max(m.nclusters, 1));
+        if (m.nclusters > 0 &&
+            hipMemcpy(cnt.data(), c->icount, sizeof(int) * m.nclusters, hipMemcpyDeviceToHost) != hipSuccess)
+            return bfail(bt, NB_ERR_HIP, "read list lengths");
+        const int s = c->C == 8;
+        for (int ci = 0; ci < m.nclusters; ++ci) items[s].push_back({cnt[ci], make_int2(b, ci)});
+        bt->nentries += m.nentries;
+        bt->evaluated += m.nentries * (int64_t)c->C * c->C;
+    }
+    for (int s = 0; s < 2; ++s) {
+        if (bt->sorted)
+            std::stable_sort(items[s].begin(), items[s].end(),
+                             [](const std::pair<int, int2> &a, const std::pair<int, int2> &b) { return a.first > b.first; });
+        std::vector<int2> flat(items[s].size());
+        for (size_t k = 0; k < flat.size(); ++k) flat[k] = items[s][k].second;
+        bt->nitems[s] = (int)flat.size();
+        if (bt->nitems[s] > bt->item_cap[s]) return bfail(bt, NB_ERR_OVERFLOW, "work list capacity");
+        if (!flat.empty() &&
+            hipMemcpy(bt->d_items[s], flat.data(), sizeof(int2) * flat.size(), hipMemcpyHostToDevice) != hipSuccess)
+            return bfail(bt, NB_ERR_HIP, "upload work list");
+    }
+    int r = upload_desc(bt);
+    if (r != NB_OK) return r;
+    bt->have_list = true;
+    bt->graph_ready = false;
+    bt->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return NB_OK;
+}
+
+int nb_batch_forces(nb_batch *bt, const float *x, const float *q, const int32_t *type, float *f,
+                    double *e) {
+    if (!bt || !x || !q || !type || !f || !e) return bfail(bt, NB_ERR_ARG, "NULL argument");
+    if (!bt->have_list) return bfail(bt, NB_ERR_STATE, "nb_batch_forces before nb_batch_pairlist");
+    hipError_t err = launch_forces(bt, x, q, type, f, e);
+    if (err != hipSuccess) return bfail(bt, NB_ERR_HIP, std::string("batch force launch: ") + hipGetErrorString(err));
+    return NB_OK;
+}
+
+int nb_batch_graph_forces(nb_batch *bt, const float *x, const float *q, const int32_t *type,
+                          float *f, double *e) {
+    if (!bt || !x || !q || !type || !f || !e) return bfail(bt, NB_ERR_ARG, "NULL argument");
+    if (!bt->have_list) return bfail(bt, NB_ERR_STATE, "nb_batch_graph_forces before nb_batch_pairlist");
+    const void *ptrs[5] = {x, q, type, f, e};
+    bool same = bt->graph_ready;
+    for (int k = 0; k < 5 && same; ++k) same = ptrs[k] == bt->gptr[k];
+    if (!same) {
+        if (bt->gexec) {
+            hipGraphExecDestroy(bt->gexec);
+            bt->gexec = nullptr;
+        }
+        hipGraph_t g = nullptr;
+        hipError_t err = hipStreamBeginCapture(bt->stream, hipStreamCaptureModeThreadLocal);
+        if (err != hipSuccess) return bfail(bt, NB_ERR_HIP, std::string("begin capture: ") + hipGetErrorString(err));
+        hipError_t lerr = launch_forces(bt, x, q, type, f, e);
+        err = hipStreamEndCapture(bt->stream, &g);
+        if (lerr != hipSuccess || err != hipSuccess) {
+            if (g) hipGraphDestroy(g);
+            return bfail(bt, NB_ERR_HIP, std::string("capture: ") + hipGetErrorString(lerr != hipSuccess ? lerr : err));
+        }
+        err = hipGraphInstantiate(&bt->gexec, g, nullptr, nullptr, 0);
+        hipGraphDestroy(g);
+        if (err != hipSuccess) return bfail(bt, NB_ERR_HIP, std::string("instantiate: ") + hipGetErrorString(err));
+        for (int k = 0; k < 5; ++k) bt->gptr[k] = ptrs[k];
+        bt->graph_ready = true;
+    }
+    hipError_t err = hipGraphLaunch(bt->gexec, bt->stream);
+    if (err != hipSuccess) return bfail(bt, NB_ERR_HIP, std::string("graph launch: ") + hipGetErrorString(err));
+    return NB_OK;
+}
+
+int nb_batch_get_info(nb_batch *bt, nb_batch_info *info) {
+    if (!bt || !info) return bfail(bt, NB_ERR_ARG, "NULL argument");
+    memset(info, 0, sizeof(*info));
+    info->nbox = bt->nbox;
+    info->sorted = bt->sorted;
+    info->natoms = bt->natoms;
+    info->nitems = (int64_t)bt->nitems[0] + bt->nitems[1];
+    info->nentries = bt->nentries;
+    info->evaluated_pairs = bt->evaluated;
+    info->grid_blocks[0] = bt->grid[0];
+    info->grid_blocks[1] = bt->grid[1];
+    info->graph_ready = bt->graph_ready;
+    info->build_ms_last = bt->build_ms;
+    return NB_OK;
+}
+
+const char *nb_batch_last_error(nb_batch *bt) { return bt ? bt->err.c_str() : g_batch_error.c_str(); }
+
+int nb_batch_destroy(nb_batch *bt) {
+    if (!bt) return NB_OK;
+    hipSetDevice(bt->device);
+    hipStreamSynchronize(bt->stream);
+    free_batch(bt);
+    delete bt;
+    return NB_OK;
+}
+
+}  // extern "C"

@@ -198,8 +198,10 @@ __device__ __forceinline__ unsigned long long pair_mask(int ci, int cj, int s, n
                                                         const int *__restrict__ eidx, bool *any) {
     const int lane = threadIdx.x & (NB_WAVE - 1);
     const bool lane_ok = (C == 8) || lane < C * C;
-    const int a = (C == 8) ? (lane >> 3) : ((lane >> 2) & 3);
-    const int b = (C == 8) ? (lane & 7) : (lane & 3);
+    // lane = b * C + a, so the ballot bit of pair (a, b) is b * C + a: the mask is stored
+    // column-major (one C-bit column per j-atom b)
+    const int a = lane % C;
+    const int b = (lane / C) % C;
     bool topo = false, near = false;
     if (lane_ok) {
         int ia = perm[ci * C + a], jb = perm[cj * C + b];
@@ -332,7 +334,7 @@ __global__ void __launch_bounds__(256) k_pairs(nb_geom g, float rc2, int cap,
         const unsigned long long m = ((unsigned long long)en.mhi << 32) | en.mlo;
         const int jb = perm[en.cj * C + b];
         for (int k = 0; k < C; ++k) {
-            if (!((m >> (k * C + b)) & 1ull)) continue;
+            if (!((m >> (b * C + k)) & 1ull)) continue;
             const float4 xi = xq[ci * C + k];
             float dx = (xi.x + dix) - xjs, dy = (xi.y + diy) - yjs, dz = (xi.z + diz) - zjs;
             float r2 = nb_r2(dx, dy, dz);

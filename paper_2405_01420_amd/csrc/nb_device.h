@@ -36,3 +36,26 @@ __device__ __forceinline__ float nb_rcp(float x) {
     const float e = __builtin_fmaf(-x, y, 1.0f);
     return __builtin_fmaf(y, e, y);
 }
+
+// The C mask bits of j-atom b (bit k: i-atom k interacts with j-atom b).
+template <int C>
+__device__ __forceinline__ unsigned nb_mask_column(unsigned long long m, int b) {
+    return (unsigned)(m >> (b * C)) & ((1u << C) - 1u);
+}
+
+// Sum of v over the 64 lanes, valid in lane 63 only: butterfly within each 16-lane row with
+// DPP quad permutations and mirrors, then the row sums are chained with the row broadcasts.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float nb_dpp(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xf, false));
+}
+
+__device__ __forceinline__ float nb_wave_sum_lane63(float v) {
+    v += nb_dpp<0xB1, 0xf>(v);   // quad_perm [1,0,3,2]
+    v += nb_dpp<0x4E, 0xf>(v);   // quad_perm [2,3,0,1]
+    v += nb_dpp<0x141, 0xf>(v);  // row_half_mirror
+    v += nb_dpp<0x140, 0xf>(v);  // row_mirror
+    v += nb_dpp<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+    v += nb_dpp<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+    return v;
+}

@@ -3,20 +3,9 @@
 // and the finalize step (un-permute, f = f_i + f_j, FP64 energies with the shifts applied).
 //
 // This is the computation the paper identifies as the single-GPU rate limiter (section III-A;
-// the flavour named in the Fig. 3 caption).  Kernel layout (a from-scratch design for a
-// 64-wide wavefront, not the paper's SYCL layout):
-//  * one wavefront per i-cluster; the C i-atoms are wave-uniform values, so every i-coordinate
-//    is a scalar operand of the vector instructions;
-//  * each lane owns one j-atom of one of the 64 / C j-clusters of the current batch and loops
-//    over the C i-atoms, so the j-force of the lane's atom accumulates in registers and needs
-//    one atomic add per component per batch (the only atomics);
-//  * the i-forces accumulate per lane over the whole list and are reduced across the 64 lanes
-//    once per i-cluster with cross-lane shuffles;
-//  * erfc(beta r) = exp(-beta^2 r^2) P(r)/Q(r) with a (4,5) rational fit of the scaled
-//    complementary error function (see fit_erfcx.py): one v_exp, one v_rcp, one v_rsq per pair;
-//  * per-pair energies are rounded once to FP32 and accumulated in FP64; the Coulomb potential
-//    shift is applied in FP64 at the end from the sum of q_i q_j over interacting pairs.
-#include "nb_device.h"
+// the flavour named in the Fig. 3 caption).  The per-cluster body and its lane layout are in
+// nb_force_body.h; here one wavefront is launched per i-cluster.
+#include "nb_force_body.h"
 
 namespace {
 
@@ -71,135 +60,14 @@ __global__ void __launch_bounds__(256) k_force(nb_fparams fp, int cap, int npad_
                                                const nb_entry *__restrict__ jl,
                                                float4 *__restrict__ fi_out, float *__restrict__ fj,
                                                double *__restrict__ epart, const nb_meta *meta) {
-    constexpr int JPB = NB_WAVE / C;  // j-clusters per batch
     extern __shared__ float4 tab[];
-    const int nt = fp.ntypes, ntt = nt * nt;
+    const int ntt = fp.ntypes * fp.ntypes;
     for (int k = threadIdx.x; k < 2 * ntt; k += blockDim.x) tab[k] = ljtab[k];
     __syncthreads();
-    const int lane = threadIdx.x & (NB_WAVE - 1);
     const int ci = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x / NB_WAVE) +
                                                   threadIdx.x / NB_WAVE);
     if (ci >= meta->nclusters) return;
-    const int b = lane % C, jsub = lane / C;
-
-    float xi[C], yi[C], zi[C], qi[C];
-    int ti[C];
-#pragma unroll
-    for (int k = 0; k < C; ++k) {
-        float4 v = xq[ci * C + k];
-        xi[k] = v.x;
-        yi[k] = v.y;
-        zi[k] = v.z;
-        qi[k] = v.w * fp.fc;
-        ti[k] = tsort[ci * C + k] * nt;
-    }
-    float fix[C], fiy[C], fiz[C];
-#pragma unroll
-    for (int k = 0; k < C; ++k) fix[k] = fiy[k] = fiz[k] = 0.0f;
-    double elj = 0.0, ec = 0.0;
-    float qqs = 0.0f;
-
-    const int nj = icount[ci];
-    const nb_entry *lst = jl + (size_t)ci * cap;
-    for (int base = 0; base < nj; base += JPB) {
-        const int e = base + jsub;
-        const bool valid = e < nj;
-        nb_entry en;
-        if (valid) {
-            en = lst[e];
-        } else {
-            en.cj = ci;
-            en.shift = NB_SHIFT_ZERO;
-            en.mlo = en.mhi = 0u;
-        }
-        const int s = en.shift;
-        const int tx = nb_tx(s), ty = nb_ty(s), tz = nb_tz(s);
-        const int jslot = en.cj * C + b;
-        const float4 xj = xq[jslot];
-        const int tj = tsort[jslot];
-        const float xjs = xj.x + nb_dj(tx, fp.L[0]), yjs = xj.y + nb_dj(ty, fp.L[1]),
-                    zjs = xj.z + nb_dj(tz, fp.L[2]);
-        const float dix = nb_di(tx, fp.L[0]), diy = nb_di(ty, fp.L[1]), diz = nb_di(tz, fp.L[2]);
-        const float qj = xj.w;
-        const unsigned long long m = ((unsigned long long)en.mhi << 32) | en.mlo;
-        unsigned mcol = 0;
-#pragma unroll
-        for (int k = 0; k < C; ++k) mcol |= (unsigned)((m >> (k * C + b)) & 1ull) << k;
-
-        float fjx = 0.0f, fjy = 0.0f, fjz = 0.0f;
-#pragma unroll
-        for (int k = 0; k < C; ++k) {
-            const float dx = (xi[k] + dix) - xjs;
-            const float dy = (yi[k] + diy) - yjs;
-            const float dz = (zi[k] + diz) - zjs;
-            const float r2 = nb_r2(dx, dy, dz);
-            const bool inc = (r2 < fp.rc2) && ((mcol >> k) & 1u);
-            const float rinv = inc ? nb_rsq(r2) : 0.0f;
-            const float rinv2 = rinv * rinv;
-            const float rinv6 = rinv2 * rinv2 * rinv2;
-            const float4 lj = tab[ti[k] + tj];   // (C6, C12, 6 C6, 12 C12)
-            const float shv = tab[ntt + ti[k] + tj].x;
-            const float m1 = inc ? 1.0f : 0.0f;
-            // Lennard-Jones: energy C12 r^-12 - C6 r^-6 - shift, force factor
-            // (12 C12 r^-6 - 6 C6) r^-6 r^-2
-            const float u = __builtin_fmaf(lj.y, rinv6, -lj.x);
-            const float elj_p = __builtin_fmaf(u, rinv6, -m1 * shv);
-            const float tf = __builtin_fmaf(lj.w, rinv6, -lj.z);
-            const float flj = tf * rinv6;
-            // Ewald real space: erfc(beta r) = exp(-beta^2 r^2) P(r) / Q(r)
-            const float r = r2 * rinv;
-            const float ex = __builtin_amdgcn_exp2f(fp.cexp * r2);
-            float P = fp.p[4];
-            P = __builtin_fmaf(P, r, fp.p[3]);
-            P = __builtin_fmaf(P, r, fp.p[2]);
-            P = __builtin_fmaf(P, r, fp.p[1]);
-            P = __builtin_fmaf(P, r, fp.p[0]);
-            float Q = fp.q[5];
-            Q = __builtin_fmaf(Q, r, fp.q[4]);
-            Q = __builtin_fmaf(Q, r, fp.q[3]);
-            Q = __builtin_fmaf(Q, r, fp.q[2]);
-            Q = __builtin_fmaf(Q, r, fp.q[1]);
-            Q = __builtin_fmaf(Q, r, fp.q[0]);
-            const float R = P * nb_rcp(Q);
-            const float qq = qi[k] * qj;
-            const float qe = qq * ex;
-            const float t1 = qe * rinv;               // fC q_i q_j exp(-b^2 r^2) / r
-            const float ec_p = t1 * R;                // fC q_i q_j erfc(b r) / r
-            const float uu = __builtin_fmaf(fp.kb, r, R);
-            const float fs = __builtin_fmaf(t1, uu, flj) * rinv2;
-            elj += (double)elj_p;
-            ec += (double)ec_p;
-            qqs = __builtin_fmaf(m1, qq, qqs);
-            const float fx = fs * dx, fy = fs * dy, fz = fs * dz;
-            fix[k] += fx;
-            fiy[k] += fy;
-            fiz[k] += fz;
-            fjx -= fx;
-            fjy -= fy;
-            fjz -= fz;
-        }
-        if (valid) {
-            atomicAdd(&fj[jslot], fjx);
-            atomicAdd(&fj[npad_max + jslot], fjy);
-            atomicAdd(&fj[2 * npad_max + jslot], fjz);
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < C; ++k) {
-        fix[k] = wave_sum(fix[k]);
-        fiy[k] = wave_sum(fiy[k]);
-        fiz[k] = wave_sum(fiz[k]);
-    }
-    elj = wave_sum(elj);
-    ec = wave_sum(ec);
-    double qqd = wave_sum((double)qqs);
-    if (lane == 0) {
-#pragma unroll
-        for (int k = 0; k < C; ++k) fi_out[ci * C + k] = make_float4(fix[k], fiy[k], fiz[k], 0.0f);
-        epart[4 * ci] = elj;
-        epart[4 * ci + 1] = ec;
-        epart[4 * ci + 2] = qqd;
-    }
+    nb_force_cluster<C>(fp, tab, ci, cap, npad_max, xq, tsort, icount, jl, fi_out, fj, epart);
 }
 
 __global__ void k_finalize(int n, int npad_max, const int *__restrict__ slot_of,

@@ -1,0 +1,223 @@
+// Body of the short-range force computation for one i-cluster, shared by the single-box
+// kernel and the persistent batched kernel.  Layout (a from-scratch design for a 64-wide
+// wavefront):
+//  * one wavefront per i-cluster; the C i-atoms are wave-uniform values, so every i-coordinate
+//    is a scalar operand of the vector instructions;
+//  * each lane owns one j-atom of one of the 64 / C j-clusters of the current batch and loops
+//    over the C i-atoms, so the j-force of the lane's atom accumulates in registers and needs
+//    one atomic add per component per batch (the only atomics);
+//  * batches whose entries share one periodic shift (the common case, since the list is grouped
+//    by shift) use i-coordinates moved into that frame once and cached in scalar registers;
+//    batches with no excluded or padding pair skip the mask test;
+//  * the i-forces accumulate per lane over the whole list and are reduced across the 64 lanes
+//    once per i-cluster with DPP row operations;
+//  * erfc(beta r) = exp(-beta^2 r^2) P(r) / Q(r) with a (4,5) rational fit of the scaled
+//    complementary error function (fit_erfcx.py), Newton-refined reciprocal square root and
+//    reciprocal;
+//  * per-pair energies are rounded once to FP32 and accumulated in FP64; the Coulomb potential
+//    shift is applied in FP64 at the end from the sum of q_i q_j over interacting pairs.
+#pragma once
+#include "nb_device.h"
+
+__device__ __forceinline__ double nb_wave_sum_d(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, NB_WAVE);
+    return v;
+}
+
+// Per-lane state of one batch: the lane's j-atom (shifted into the pair frame), its charge,
+// type row offset and mask column; accumulators for its j-force.
+struct nb_jlane {
+    float x, y, z, q;
+    int t;
+    unsigned mcol;
+    float fx, fy, fz;
+};
+
+// All C pairs (i-atom k, the lane's j-atom) of one batch.  xs/ys/zs hold the i-coordinates
+// already moved into the pair frame (uniform over the wave in the fast path).  MASKED applies
+// the topology mask; without it every unordered pair within rc interacts.
+template <int C, bool MASKED>
+__device__ __forceinline__ void pair_block(const nb_fparams &fp, const float4 *tab, int ntt,
+                                           const float *xs, const float *ys, const float *zs,
+                                           const float *qi, const int *ti, nb_jlane &j,
+                                           float *fix, float *fiy, float *fiz, double &elj,
+                                           double &ec, float &qqs) {
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+        const float dx = xs[k] - j.x;
+        const float dy = ys[k] - j.y;
+        const float dz = zs[k] - j.z;
+        const float r2 = nb_r2(dx, dy, dz);
+        const bool inc = MASKED ? ((r2 < fp.rc2) && ((j.mcol >> k) & 1u)) : (r2 < fp.rc2);
+        const float rinv = inc ? nb_rsq(r2) : 0.0f;
+        const float rinv2 = rinv * rinv;
+        const float rinv6 = rinv2 * rinv2 * rinv2;
+        const float4 lj = tab[ti[k] + j.t];   // (C6, C12, 6 C6, 12 C12)
+        const float shv = tab[ntt + ti[k] + j.t].x;
+        const float m1 = inc ? 1.0f : 0.0f;
+        // Lennard-Jones: energy C12 r^-12 - C6 r^-6 - shift, force factor (12 C12 r^-6 - 6 C6) r^-8
+        const float u = __builtin_fmaf(lj.y, rinv6, -lj.x);
+        const float elj_p = __builtin_fmaf(u, rinv6, -m1 * shv);
+        const float tf = __builtin_fmaf(lj.w, rinv6, -lj.z);
+        const float flj = tf * rinv6;
+        // Ewald real space: erfc(beta r) = exp(-beta^2 r^2) P(r) / Q(r)
+        const float r = r2 * rinv;
+        const float ex = __builtin_amdgcn_exp2f(fp.cexp * r2);
+        float P = fp.p[4];
+        P = __builtin_fmaf(P, r, fp.p[3]);
+        P = __builtin_fmaf(P, r, fp.p[2]);
+        P = __builtin_fmaf(P, r, fp.p[1]);
+        P = __builtin_fmaf(P, r, fp.p[0]);
+        float Q = fp.q[5];
+        Q = __builtin_fmaf(Q, r, fp.q[4]);
+        Q = __builtin_fmaf(Q, r, fp.q[3]);
+        Q = __builtin_fmaf(Q, r, fp.q[2]);
+        Q = __builtin_fmaf(Q, r, fp.q[1]);
+        Q = __builtin_fmaf(Q, r, fp.q[0]);
+        const float R = P * nb_rcp(Q);
+        const float qq = qi[k] * j.q;
+        const float qe = qq * ex;
+        const float t1 = qe * rinv;               // fC q_i q_j exp(-b^2 r^2) / r
+        const float ec_p = t1 * R;                // fC q_i q_j erfc(b r) / r
+        const float uu = __builtin_fmaf(fp.kb, r, R);
+        const float fs = __builtin_fmaf(t1, uu, flj) * rinv2;
+        elj += (double)elj_p;
+        ec += (double)ec_p;
+        qqs = __builtin_fmaf(m1, qq, qqs);
+        fix[k] = __builtin_fmaf(fs, dx, fix[k]);
+        fiy[k] = __builtin_fmaf(fs, dy, fiy[k]);
+        fiz[k] = __builtin_fmaf(fs, dz, fiz[k]);
+        j.fx = __builtin_fmaf(-fs, dx, j.fx);
+        j.fy = __builtin_fmaf(-fs, dy, j.fy);
+        j.fz = __builtin_fmaf(-fs, dz, j.fz);
+    }
+}
+
+__device__ __forceinline__ float nb_uniform(float v) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
+// Forces and energy partials of one i-cluster ci over its whole j-list, computed by one
+// wavefront.  fp.L holds the box of the cluster.  i-forces are stored (not accumulated) to
+// fi_out, j-forces are added atomically to fj, energy partials are stored to epart[4 ci ..].
+template <int C>
+__device__ __forceinline__ void nb_force_cluster(const nb_fparams &fp, const float4 *tab, int ci,
+                                                 int cap, int npad_max,
+                                                 const float4 *__restrict__ xq,
+                                                 const int *__restrict__ tsort,
+                                                 const int *__restrict__ icount,
+                                                 const nb_entry *__restrict__ jl,
+                                                 float4 *__restrict__ fi_out,
+                                                 float *__restrict__ fj,
+                                                 double *__restrict__ epart) {
+    constexpr int JPB = NB_WAVE / C;  // j-clusters per batch
+    constexpr unsigned FULL = (1u << C) - 1u;
+    const int nt = fp.ntypes, ntt = nt * nt;
+    const int lane = threadIdx.x & (NB_WAVE - 1);
+    const int b = lane % C, jsub = lane / C;
+
+    float xi[C], yi[C], zi[C], qi[C], xs[C], ys[C], zs[C];
+    int ti[C];
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+        const float4 v = xq[ci * C + k];
+        xi[k] = v.x;
+        yi[k] = v.y;
+        zi[k] = v.z;
+        qi[k] = nb_uniform(v.w * fp.fc);
+        ti[k] = tsort[ci * C + k] * nt;
+        xs[k] = xi[k];
+        ys[k] = yi[k];
+        zs[k] = zi[k];
+    }
+    int cur_shift = NB_SHIFT_ZERO;  // shift the cached i-frame coordinates xs/ys/zs belong to
+    float fix[C], fiy[C], fiz[C];
+#pragma unroll
+    for (int k = 0; k < C; ++k) fix[k] = fiy[k] = fiz[k] = 0.0f;
+    double elj = 0.0, ec = 0.0;
+    float qqs = 0.0f;
+
+    const int nj = icount[ci];
+    const nb_entry *lst = jl + (size_t)ci * cap;
+    for (int base = 0; base < nj; base += JPB) {
+        const int e = base + jsub;
+        const bool valid = e < nj;
+        nb_entry en;
+        if (valid) {
+            en = lst[e];
+        } else {
+            en.cj = ci;
+            en.shift = NB_SHIFT_ZERO;
+            en.mlo = en.mhi = 0u;
+        }
+        const int s = en.shift;
+        const int jslot = en.cj * C + b;
+        const float4 xj = xq[jslot];
+        nb_jlane jv;
+        jv.q = xj.w;
+        jv.t = tsort[jslot];
+        jv.mcol = nb_mask_column<C>(((unsigned long long)en.mhi << 32) | en.mlo, b);
+        jv.fx = jv.fy = jv.fz = 0.0f;
+        const int s0 = __builtin_amdgcn_readfirstlane(s);
+        const bool uniform = __ballot(valid && s != s0) == 0ull;
+        if (uniform) {
+            // one periodic shift for the whole batch: i-coordinates of that frame are cached
+            const int tx = nb_tx(s0), ty = nb_ty(s0), tz = nb_tz(s0);
+            if (s0 != cur_shift) {
+                cur_shift = s0;
+                const float dix = nb_di(tx, fp.L[0]), diy = nb_di(ty, fp.L[1]), diz = nb_di(tz, fp.L[2]);
+#pragma unroll
+                for (int k = 0; k < C; ++k) {
+                    xs[k] = nb_uniform(xi[k] + dix);
+                    ys[k] = nb_uniform(yi[k] + diy);
+                    zs[k] = nb_uniform(zi[k] + diz);
+                }
+            }
+            jv.x = xj.x + nb_dj(tx, fp.L[0]);
+            jv.y = xj.y + nb_dj(ty, fp.L[1]);
+            jv.z = xj.z + nb_dj(tz, fp.L[2]);
+            const bool full = __ballot(!valid || jv.mcol != FULL) == 0ull;
+            if (full)
+                pair_block<C, false>(fp, tab, ntt, xs, ys, zs, qi, ti, jv, fix, fiy, fiz, elj, ec, qqs);
+            else
+                pair_block<C, true>(fp, tab, ntt, xs, ys, zs, qi, ti, jv, fix, fiy, fiz, elj, ec, qqs);
+        } else {
+            // shifts differ across the batch: per-lane frame offsets
+            const int tx = nb_tx(s), ty = nb_ty(s), tz = nb_tz(s);
+            const float dix = nb_di(tx, fp.L[0]), diy = nb_di(ty, fp.L[1]), diz = nb_di(tz, fp.L[2]);
+            jv.x = xj.x + nb_dj(tx, fp.L[0]);
+            jv.y = xj.y + nb_dj(ty, fp.L[1]);
+            jv.z = xj.z + nb_dj(tz, fp.L[2]);
+            float xl[C], yl[C], zl[C];
+#pragma unroll
+            for (int k = 0; k < C; ++k) {
+                xl[k] = xi[k] + dix;
+                yl[k] = yi[k] + diy;
+                zl[k] = zi[k] + diz;
+            }
+            pair_block<C, true>(fp, tab, ntt, xl, yl, zl, qi, ti, jv, fix, fiy, fiz, elj, ec, qqs);
+        }
+        if (valid) {
+            atomicAdd(&fj[jslot], jv.fx);
+            atomicAdd(&fj[npad_max + jslot], jv.fy);
+            atomicAdd(&fj[2 * npad_max + jslot], jv.fz);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+        fix[k] = nb_wave_sum_lane63(fix[k]);
+        fiy[k] = nb_wave_sum_lane63(fiy[k]);
+        fiz[k] = nb_wave_sum_lane63(fiz[k]);
+    }
+    elj = nb_wave_sum_d(elj);
+    ec = nb_wave_sum_d(ec);
+    const double qqd = nb_wave_sum_d((double)qqs);
+    if (lane == NB_WAVE - 1) {
+#pragma unroll
+        for (int k = 0; k < C; ++k) fi_out[ci * C + k] = make_float4(fix[k], fiy[k], fiz[k], 0.0f);
+        epart[4 * ci] = elj;
+        epart[4 * ci + 1] = ec;
+        epart[4 * ci + 2] = qqd;
+    }
+}

@@ -21,9 +21,10 @@
 #define NB_F_COLUMN 0x8u
 
 // One j-entry of the cluster-pair list: j-cluster, periodic shift of the j image
-// (x_j + t L) and the topology mask: bit (a * C + b) set iff atom a of the i-cluster and atom
+// (x_j + t L) and the topology mask: bit (b * C + a) set iff atom a of the i-cluster and atom
 // b of the j-cluster are both real, distinct, not excluded and, for the self pair at t = 0,
-// b > a.  Distances are not part of the mask.
+// b > a.  The mask is column-major so that the lane holding j-atom b extracts its C bits with
+// one shift.  Distances are not part of the mask.
 struct nb_entry {
     int32_t cj;
     int32_t shift;
@@ -122,6 +123,10 @@ struct nb_ctx {
     double timed_ms = 0;
     int64_t timed_n = 0;
 };
+
+// ---- host helpers (nb_api.cpp) ----
+int nb_read_meta(nb_ctx *c, nb_meta *m);
+int nb_regrow_list(nb_ctx *c, int maxcount);
 
 // ---- launchers (nb_build.hip) ----
 hipError_t nb_launch_build(nb_ctx *c, const float *x);

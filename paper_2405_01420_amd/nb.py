@@ -26,7 +26,10 @@ STATUS_NAMES = {0: "NB_OK", 1: "NB_ERR_ARG", 2: "NB_ERR_CUTOFF", 3: "NB_ERR_OOM"
 
 EXPORTS = ["nb_validate_params", "nb_setup", "nb_set_lj", "nb_set_stream", "nb_pairlist",
            "nb_forces", "nb_check", "nb_backward", "nb_debug_pairs", "nb_get_stats",
-           "nb_last_error", "nb_destroy", "nb_set_timing", "nb_get_timing"]
+           "nb_last_error", "nb_destroy", "nb_set_timing", "nb_get_timing", "nb_batch_setup",
+           "nb_batch_set_schedule", "nb_batch_pairlist", "nb_batch_forces",
+           "nb_batch_graph_forces", "nb_batch_get_info", "nb_batch_last_error",
+           "nb_batch_destroy"]
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _ip = ctypes.POINTER(ctypes.c_int32)
@@ -47,6 +50,14 @@ class nb_stats(ctypes.Structure):
                 ("npadded", ctypes.c_int64), ("nentries", ctypes.c_int64),
                 ("evaluated_pairs", ctypes.c_int64), ("list_capacity", ctypes.c_int64),
                 ("cluster", ctypes.c_int32), ("ncolumns", ctypes.c_int32),
+                ("build_ms_last", ctypes.c_double)]
+
+
+class nb_batch_info(ctypes.Structure):
+    _fields_ = [("nbox", ctypes.c_int32), ("sorted", ctypes.c_int32), ("natoms", ctypes.c_int64),
+                ("nitems", ctypes.c_int64), ("nentries", ctypes.c_int64),
+                ("evaluated_pairs", ctypes.c_int64), ("grid_blocks", ctypes.c_int32 * 2),
+                ("graph_ready", ctypes.c_int32), ("pad", ctypes.c_int32),
                 ("build_ms_last", ctypes.c_double)]
 
 
@@ -83,6 +94,15 @@ def lib():
         L.nb_last_error.restype = ctypes.c_char_p
         L.nb_destroy.argtypes = [_vp]
         L.nb_set_timing.argtypes = [_vp, ci]
+        L.nb_batch_setup.argtypes = [P(_vp), ctypes.c_int32, _vp, _vp, _vp, P(nb_params), _vp]
+        L.nb_batch_set_schedule.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32]
+        L.nb_batch_pairlist.argtypes = [_vp, _vp]
+        L.nb_batch_forces.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
+        L.nb_batch_graph_forces.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
+        L.nb_batch_get_info.argtypes = [_vp, P(nb_batch_info)]
+        L.nb_batch_last_error.argtypes = [_vp]
+        L.nb_batch_last_error.restype = ctypes.c_char_p
+        L.nb_batch_destroy.argtypes = [_vp]
         L.nb_get_timing.argtypes = [_vp, P(ctypes.c_double), P(ci64)]
         for name in EXPORTS:
             fn = getattr(L, name, None)
@@ -220,3 +240,78 @@ def nb_get_timing(ctx: int):
     n = ctypes.c_int64(0)
     _check(lib().nb_get_timing(ctx, ctypes.byref(ms), ctypes.byref(n)), ctx)
     return ms.value, n.value
+
+
+# ---- batched form ------------------------------------------------------------------------
+
+def _bcheck(code: int, bt=None):
+    if code != NB_OK:
+        raise NbError(code, lib().nb_batch_last_error(bt).decode(errors="replace"))
+
+
+def nb_batch_setup(atom_off, boxes, common: Params, clusters=None, stream=None) -> int:
+    """atom_off: [nbox+1] ints, boxes: [nbox, 3] floats, common: Params over all atoms."""
+    ao = np.ascontiguousarray(atom_off, dtype=np.int32)
+    bx = np.ascontiguousarray(boxes, dtype=np.float64).reshape(-1, 3)
+    cl = None if clusters is None else np.ascontiguousarray(clusters, dtype=np.int32)
+    h = _vp()
+    _bcheck(lib().nb_batch_setup(ctypes.byref(h), len(ao) - 1, ao.ctypes.data, bx.ctypes.data,
+                                 None if cl is None else cl.ctypes.data, ctypes.byref(common.c),
+                                 _stream(stream)))
+    return h.value
+
+
+def nb_batch_set_schedule(bt: int, sorted: bool = True, blocks_per_cu: int = 0) -> None:
+    _bcheck(lib().nb_batch_set_schedule(bt, int(bool(sorted)), int(blocks_per_cu)), bt)
+
+
+def nb_batch_pairlist(bt: int, x) -> None:
+    _bcheck(lib().nb_batch_pairlist(bt, _ptr(x)), bt)
+
+
+def nb_batch_forces(bt: int, x, q, types, f, e) -> None:
+    _bcheck(lib().nb_batch_forces(bt, _ptr(x), _ptr(q), _ptr(types), _ptr(f), _ptr(e)), bt)
+
+
+def nb_batch_graph_forces(bt: int, x, q, types, f, e) -> None:
+    _bcheck(lib().nb_batch_graph_forces(bt, _ptr(x), _ptr(q), _ptr(types), _ptr(f), _ptr(e)), bt)
+
+
+def nb_batch_get_info(bt: int) -> dict:
+    st = nb_batch_info()
+    _bcheck(lib().nb_batch_get_info(bt, ctypes.byref(st)), bt)
+    out = {k: getattr(st, k) for k, _ in nb_batch_info._fields_ if k != "pad"}
+    out["grid_blocks"] = list(st.grid_blocks)
+    return out
+
+
+def nb_batch_last_error(bt: Optional[int]) -> str:
+    return lib().nb_batch_last_error(bt).decode(errors="replace")
+
+
+def nb_batch_destroy(bt: int) -> None:
+    _bcheck(lib().nb_batch_destroy(bt))
+
+
+def concat_instances(insts, cluster: int = 8, flags: int = 0, clusters=None):
+    """Concatenate independent boxes into (atom_off, boxes, Params, x, q, type) for the batch
+    API: exclusions are shifted to global indices, every box shares the LJ table of the first."""
+    n = [i.natoms for i in insts]
+    ao = np.concatenate([[0], np.cumsum(n)]).astype(np.int32)
+    boxes = np.array([[i.box] * 3 for i in insts], dtype=np.float64)
+    eo = [np.zeros(1, np.int64)]
+    ei = []
+    base = 0
+    for k, inst in enumerate(insts):
+        eo.append(inst.excl_off[1:].astype(np.int64) + base)
+        ei.append(inst.excl_idx.astype(np.int64) + ao[k])
+        base += int(inst.excl_off[-1])
+    excl_off = np.concatenate(eo).astype(np.int32)
+    excl_idx = np.concatenate(ei).astype(np.int32)
+    i0 = insts[0]
+    params = Params(int(ao[-1]), [i0.box] * 3, i0.cutoff, i0.buffer, i0.beta, i0.coulomb_const,
+                    i0.sigma, i0.epsilon, excl_off, excl_idx, flags, cluster)
+    x = np.concatenate([i.x for i in insts]).astype(np.float32)
+    q = np.concatenate([i.q for i in insts]).astype(np.float32)
+    t = np.concatenate([i.type for i in insts]).astype(np.int32)
+    return ao, boxes, params, x, q, t
