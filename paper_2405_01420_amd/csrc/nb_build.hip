@@ -155,7 +155,7 @@ __global__ void __launch_bounds__(256) k_colsort(const float *__restrict__ x,
             perm[slot] = a;
             slot_of[a] = slot;
             float4 o = off[a];
-            xs[slot] = make_float4(x[3 * a] + o.x, x[3 * a + 1] + o.y, x[3 * a + 2] + o.z, 0.0f);
+            xs[slot] = make_float4(x[3 * a] + o.x, x[3 * a + 1] + o.y, x[3 * a + 2] + o.z, 1.0f);
         } else {
             perm[slot] = -1;
             xs[slot] = make_float4(-1e5f, -1e5f, -1e5f, 0.0f);
@@ -187,48 +187,25 @@ __device__ __forceinline__ float gap(float alo, float ahi, float blo, float bhi)
     return fmaxf(0.0f, fmaxf(blo - ahi, alo - bhi));
 }
 
-// Topology mask of the cluster pair (ci, cj + shift s) computed by the whole wave, one atom
-// pair per lane; also reports whether any unmasked pair is closer than rlist at the build
-// positions (atom-level prune).
-template <int C>
-__device__ __forceinline__ unsigned long long pair_mask(int ci, int cj, int s, nb_geom g,
-                                                        const int *__restrict__ perm,
-                                                        const float4 *__restrict__ xs,
-                                                        const int *__restrict__ eoff,
-                                                        const int *__restrict__ eidx, bool *any) {
-    const int lane = threadIdx.x & (NB_WAVE - 1);
-    const bool lane_ok = (C == 8) || lane < C * C;
-    // lane = b * C + a, so the ballot bit of pair (a, b) is b * C + a: the mask is stored
-    // column-major (one C-bit column per j-atom b)
-    const int a = lane % C;
-    const int b = (lane / C) % C;
-    bool topo = false, near = false;
-    if (lane_ok) {
-        int ia = perm[ci * C + a], jb = perm[cj * C + b];
-        topo = ia >= 0 && jb >= 0;
-        if (ci == cj && s == NB_SHIFT_ZERO) topo = topo && (b > a);
-        if (topo && eoff) {
-            for (int e = eoff[ia]; e < eoff[ia + 1]; ++e)
-                if (eidx[e] == jb) topo = false;
-        }
-        if (topo) {
-            float4 pi = xs[ci * C + a], pj = xs[cj * C + b];
-            float dx = pi.x - (pj.x + nb_tx(s) * g.L[0]);
-            float dy = pi.y - (pj.y + nb_ty(s) * g.L[1]);
-            float dz = pi.z - (pj.z + nb_tz(s) * g.L[2]);
-            near = dx * dx + dy * dy + dz * dz < g.rl2;
-        }
-    }
-    *any = __ballot(topo && near) != 0ull;
-    return __ballot(topo);
+// Exclusion partners of every slot, as slots: exs[e] = slot_of[excl_idx[e]] for the CSR of
+// the atom in that slot.  Lets the search compare slot numbers without gathering atom indices.
+__global__ void k_excl_slots(int nnz, const int *__restrict__ eidx, const int *__restrict__ slot_of,
+                             int *__restrict__ exs) {
+    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < nnz) exs[e] = slot_of[eidx[e]];
 }
+
+#define NB_EXCL_REG 4  // exclusion partners held in registers per atom; more are looped over
 
 // One wave per i-cluster.  For every periodic shift t whose image can reach the i-cluster's
 // bounding box within rlist, candidate j-clusters come from the columns overlapping the
 // dilated box; a candidate is kept under the half-list rule (cj > ci for any t; cj == ci only
 // for t = 0, with the upper triangle, or t lexicographically positive, which covers both images
 // +t and -t) if its bounding-box distance is below rlist and at least one unmasked atom pair
-// is within rlist.  Entries of one i-cluster are stored contiguously at jl[ci * cap].
+// is within rlist.  Entries of one i-cluster are stored contiguously at jl[ci * cap], grouped by
+// shift.  The topology mask of a candidate is computed with one atom pair per lane (lane =
+// b * C + a); for C = 4 four candidates share a wavefront, for C = 8 four candidates are
+// processed per iteration so that their loads overlap.
 template <int C>
 __global__ void __launch_bounds__(256) k_search(nb_geom g, int cap, const int *__restrict__ colcl,
                                                 const float4 *__restrict__ bblo,
@@ -236,59 +213,117 @@ __global__ void __launch_bounds__(256) k_search(nb_geom g, int cap, const int *_
                                                 const int *__restrict__ perm,
                                                 const float4 *__restrict__ xs,
                                                 const int *__restrict__ eoff,
-                                                const int *__restrict__ eidx,
+                                                const int *__restrict__ exs,
                                                 int *__restrict__ icount,
                                                 nb_entry *__restrict__ jl, nb_meta *meta) {
+    constexpr int PAIRS = C * C;               // lanes per candidate
+    constexpr int PER_WAVE = NB_WAVE / PAIRS;  // candidates side by side (1 for C = 8, 4 for C = 4)
+    constexpr int UNROLL = 4 / PER_WAVE;       // candidate groups per iteration
     const int lane = threadIdx.x & (NB_WAVE - 1);
     const int ci = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x / NB_WAVE) +
                                                   threadIdx.x / NB_WAVE);
     if (ci >= meta->nclusters) return;
     const float4 lo = bblo[ci], hi = bbhi[ci];
     const float rl = g.rl;
+    // this lane's pair within a candidate: i-atom a, j-atom b, candidate slot grp
+    const int a = lane % C, b = (lane / C) % C, grp = lane / PAIRS;
+    const float4 pi = xs[ci * C + a];
+    const bool ireal = pi.w > 0.0f;
+    int ex[NB_EXCL_REG];
+    int ne = 0, ebeg = 0;
+#pragma unroll
+    for (int k = 0; k < NB_EXCL_REG; ++k) ex[k] = -1;
+    if (ireal && eoff) {
+        const int ia = perm[ci * C + a];
+        ebeg = eoff[ia];
+        ne = eoff[ia + 1] - ebeg;
+#pragma unroll
+        for (int k = 0; k < NB_EXCL_REG; ++k)
+            if (k < ne) ex[k] = exs[ebeg + k];
+    }
     int count = 0;
     for (int s = 0; s < 27; ++s) {
         const int tx = nb_tx(s), ty = nb_ty(s), tz = nb_tz(s);
         const float sx = tx * g.L[0], sy = ty * g.L[1], sz = tz * g.L[2];
         // j coordinates (unshifted frame) whose image x + t L can lie within rl of the bbox
-        float x0 = lo.x - rl - sx, x1 = hi.x + rl - sx;
-        float y0 = lo.y - rl - sy, y1 = hi.y + rl - sy;
-        float z0 = lo.z - rl - sz, z1 = hi.z + rl - sz;
+        const float x0 = lo.x - rl - sx, x1 = hi.x + rl - sx;
+        const float y0 = lo.y - rl - sy, y1 = hi.y + rl - sy;
+        const float z0 = lo.z - rl - sz, z1 = hi.z + rl - sz;
         if (x1 < 0.0f || x0 >= g.L[0] || y1 < 0.0f || y0 >= g.L[1] || z1 < 0.0f || z0 >= g.L[2])
             continue;
-        int cx0 = max(0, (int)floorf(x0 * g.invw[0])), cx1 = min(g.ncx - 1, (int)floorf(x1 * g.invw[0]));
-        int cy0 = max(0, (int)floorf(y0 * g.invw[1])), cy1 = min(g.ncy - 1, (int)floorf(y1 * g.invw[1]));
+        const int cx0 = max(0, (int)floorf(x0 * g.invw[0])), cx1 = min(g.ncx - 1, (int)floorf(x1 * g.invw[0]));
+        const int cy0 = max(0, (int)floorf(y0 * g.invw[1])), cy1 = min(g.ncy - 1, (int)floorf(y1 * g.invw[1]));
+        const bool self_t0 = s == NB_SHIFT_ZERO;
         for (int cy = cy0; cy <= cy1; ++cy) {
             for (int cx = cx0; cx <= cx1; ++cx) {
                 const int col = cy * g.ncx + cx;
                 const int ca = colcl[col], cb = colcl[col + 1];
                 for (int base = ca; base < cb; base += NB_WAVE) {
-                    int cj = base + lane;
-                    bool cand = cj < cb;
+                    const int cjl = base + lane;
+                    bool cand = cjl < cb;
                     if (cand) {
-                        bool half = cj > ci || (cj == ci && s >= NB_SHIFT_ZERO);
-                        float4 jlo = bblo[cj], jhi = bbhi[cj];
-                        float gx = gap(lo.x, hi.x, jlo.x + sx, jhi.x + sx);
-                        float gy = gap(lo.y, hi.y, jlo.y + sy, jhi.y + sy);
-                        float gz = gap(lo.z, hi.z, jlo.z + sz, jhi.z + sz);
+                        const bool half = cjl > ci || (cjl == ci && s >= NB_SHIFT_ZERO);
+                        const float4 jlo = bblo[cjl], jhi = bbhi[cjl];
+                        const float gx = gap(lo.x, hi.x, jlo.x + sx, jhi.x + sx);
+                        const float gy = gap(lo.y, hi.y, jlo.y + sy, jhi.y + sy);
+                        const float gz = gap(lo.z, hi.z, jlo.z + sz, jhi.z + sz);
                         cand = half && (gx * gx + gy * gy + gz * gz < g.rl2);
                     }
                     unsigned long long bal = __ballot(cand);
                     while (bal) {
-                        int k = __ffsll((long long)bal) - 1;
-                        bal &= bal - 1;
-                        int cjk = base + k;
-                        bool any;
-                        unsigned long long m = pair_mask<C>(ci, cjk, s, g, perm, xs, eoff, eidx, &any);
-                        if (any) {
-                            if (count < cap && lane == 0) {
-                                nb_entry e;
-                                e.cj = cjk;
-                                e.shift = s;
-                                e.mlo = (uint32_t)m;
-                                e.mhi = (uint32_t)(m >> 32);
-                                jl[(size_t)ci * cap + count] = e;
+                        // up to 4 candidates: lane group grp (C = 4) or unrolled step u (C = 8)
+                        int cand_j[4];
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            cand_j[k] = -1;
+                            if (bal) {
+                                cand_j[k] = base + __ffsll((long long)bal) - 1;
+                                bal &= bal - 1;
                             }
-                            ++count;
+                        }
+                        unsigned long long mk[4];
+                        bool anyk[4];
+#pragma unroll
+                        for (int u = 0; u < UNROLL; ++u) {
+                            const int cj = cand_j[u * PER_WAVE + grp];  // per lane group
+                            bool topo = false, near = false;
+                            if (cj >= 0) {
+                                const int jslot = cj * C + b;
+                                const float4 pj = xs[jslot];
+                                topo = ireal && pj.w > 0.0f;
+                                if (cj == ci && self_t0) topo = topo && (b > a);
+#pragma unroll
+                                for (int k = 0; k < NB_EXCL_REG; ++k) topo = topo && ex[k] != jslot;
+                                for (int k = NB_EXCL_REG; k < ne; ++k) topo = topo && exs[ebeg + k] != jslot;
+                                const float dx = pi.x - (pj.x + sx);
+                                const float dy = pi.y - (pj.y + sy);
+                                const float dz = pi.z - (pj.z + sz);
+                                near = dx * dx + dy * dy + dz * dz < g.rl2;
+                            }
+                            const unsigned long long bt = __ballot(topo);
+                            const unsigned long long bn = __ballot(topo && near);
+#pragma unroll
+                            for (int p = 0; p < PER_WAVE; ++p) {
+                                const int slotk = u * PER_WAVE + p;
+                                const unsigned long long sel =
+                                    PAIRS == 64 ? ~0ull : (((1ull << PAIRS) - 1ull) << (p * PAIRS));
+                                mk[slotk] = (bt & sel) >> (p * PAIRS);
+                                anyk[slotk] = (bn & sel) != 0ull;
+                            }
+                        }
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            if (cand_j[k] >= 0 && anyk[k]) {
+                                if (count < cap && lane == 0) {
+                                    nb_entry e;
+                                    e.cj = cand_j[k];
+                                    e.shift = s;
+                                    e.mlo = (uint32_t)mk[k];
+                                    e.mhi = (uint32_t)(mk[k] >> 32);
+                                    jl[(size_t)ci * cap + count] = e;
+                                }
+                                ++count;
+                            }
                         }
                     }
                 }
@@ -367,9 +402,13 @@ hipError_t build_impl(nb_ctx *c, const float *x) {
                        c->meta);
     hipLaunchKernelGGL((k_bbox<C>), dim3((c->ncl_max + tb - 1) / tb), dim3(tb), 0, c->stream,
                        c->ncl_max, c->xs, c->perm, c->bblo, c->bbhi, c->meta);
+    if (c->excl_off && c->nnz_excl > 0)
+        hipLaunchKernelGGL(k_excl_slots, dim3((c->nnz_excl + tb - 1) / tb), dim3(tb), 0, c->stream,
+                           c->nnz_excl, c->excl_idx, c->slot_of, c->excl_slot);
     hipLaunchKernelGGL((k_search<C>), dim3((c->ncl_max + 3) / 4), dim3(256), 0, c->stream,
-                       c->geom, c->cap, c->colcl, c->bblo, c->bbhi, c->perm, c->xs, c->excl_off,
-                       c->excl_idx, c->icount, c->jl, c->meta);
+                       c->geom, c->cap, c->colcl, c->bblo, c->bbhi, c->perm, c->xs,
+                       c->nnz_excl > 0 ? c->excl_off : nullptr, c->excl_slot, c->icount, c->jl,
+                       c->meta);
     return hipGetLastError();
 }
 

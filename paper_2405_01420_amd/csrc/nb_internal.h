@@ -110,6 +110,8 @@ struct nb_ctx {
     nb_meta *meta = nullptr;
     float4 *ljtab = nullptr;    // [2 * nt * nt]: (C6, C12, 6 C6, 12 C12), (shift, 1/sigma_ab, 0, 0)
     int *excl_off = nullptr, *excl_idx = nullptr;
+    int *excl_slot = nullptr;   // [nnz] exclusion partners as slots (rebuilt with every list)
+    int nnz_excl = 0;
     int64_t *dbg_pairs = nullptr;
     int64_t dbg_cap = 0;
     // adjoint buffers (allocated on first use)
