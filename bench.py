@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--cluster", type=int, default=0, help="4 or 8 (0 = tuned or default 8)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--energy-fp64", action="store_true",
+                    help="evaluate Coulomb pair energies in FP64 (forces stay FP32)")
     return ap.parse_args()
 
 
@@ -77,7 +79,8 @@ def main():
     dev = "cuda:0"
     inst = synth.mid()
     cluster = args.cluster or 8
-    params = nb.Params.from_instance(inst, cluster=cluster)
+    params = nb.Params.from_instance(inst, cluster=cluster,
+                                     flags=nb.NB_ENERGY_FP64 if args.energy_fp64 else 0)
     ctx = nb.nb_setup(params)
     n = inst.natoms
     nsteps = args.warmup + args.steps
@@ -160,6 +163,7 @@ def main():
                                "rb=0.1 nm, beta=3.1234 nm^-1, random walk 0.002 nm/call, "
                                "rebuild every 10 calls",
                    "natoms": n, "cluster": cluster, "useful_pairs": useful,
+                   "energy": "fp64 pair energies" if args.energy_fp64 else "fp32 pair energies, fp64 sums",
                    "evaluated_pairs": stats["evaluated_pairs"], "list_entries": stats["nentries"]},
         "us_per_force_call": us_force,
         "us_per_list_build": us_build,

@@ -62,6 +62,9 @@ typedef enum nb_status {
 #define NB_CHECK_FINITE 0x2u  /* nb_forces records non-finite coordinates */
 #define NB_REUSE_LIST   0x4u  /* nb_backward: use the current list instead of rebuilding */
 #define NB_ASYNC_BUILD  0x8u  /* nb_pairlist: do not wait for the overflow check */
+#define NB_ENERGY_FP64  0x10u /* evaluate the Coulomb pair energies in FP64 (forces stay FP32):
+                                 needed for 1e-6 relative E_C in boxes of a few thousand atoms,
+                                 where FP32 pair-energy rounding does not average out */
 
 typedef struct nb_params {
     double box[3];          /* rectangular box edges Lx, Ly, Lz (nm), > 0 */
@@ -75,7 +78,7 @@ typedef struct nb_params {
     int32_t natoms;         /* number of atoms, 1 .. 2^27 */
     const int32_t *excl_off;/* host [natoms+1] CSR offsets of excluded partners, or NULL */
     const int32_t *excl_idx;/* host [excl_off[natoms]] partner indices (symmetric lists) */
-    uint32_t flags;         /* NB_CHECK_* */
+    uint32_t flags;         /* NB_CHECK_*, NB_ASYNC_BUILD, NB_ENERGY_FP64 */
     int32_t cluster;        /* cluster size C of the list: 4 or 8 (0 = 8) */
 } nb_params;
 

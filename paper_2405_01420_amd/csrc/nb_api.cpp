@@ -95,6 +95,31 @@ void set_constants(nb_ctx *c) {
     fp.shc = (float)c->shift_coul;
 }
 
+// Cubic Hermite segments of erfc(beta r) on [k h, (k+1) h], k = 0 .. n-1, covering [0, rc];
+// h is the largest power of two with at most 1280 segments, so r / h is exact in floating point.
+int upload_etab(nb_ctx *c) {
+    double h = 1.0 / 1024.0;
+    while (c->rc / h > 1279.0) h *= 2.0;
+    const int n = (int)ceil(c->rc / h) + 1;
+    std::vector<double2> seg(2 * (size_t)n);
+    const double kb = 2.0 * c->beta / sqrt(M_PI);
+    for (int k = 0; k < n; ++k) {
+        const double r0 = k * h, r1 = (k + 1) * h;
+        const double f0 = erfc(c->beta * r0), f1 = erfc(c->beta * r1);
+        const double d0 = -kb * exp(-c->beta * c->beta * r0 * r0) * h;
+        const double d1 = -kb * exp(-c->beta * c->beta * r1 * r1) * h;
+        seg[2 * k] = make_double2(f0, d0);
+        seg[2 * k + 1] = make_double2(3.0 * (f1 - f0) - 2.0 * d0 - d1, 2.0 * (f0 - f1) + d0 + d1);
+    }
+    int r = dalloc(c, &c->etab, seg.size(), "erfc table");
+    if (r != NB_OK) return r;
+    hipError_t e = hipMemcpy(c->etab, seg.data(), sizeof(double2) * seg.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(c, e, "upload erfc table");
+    c->etab_n = n;
+    c->etab_invh = (float)(1.0 / h);
+    return NB_OK;
+}
+
 int alloc_list(nb_ctx *c) {
     return dalloc(c, &c->jl, (size_t)c->ncl_max * c->cap, "pair list");
 }
@@ -137,7 +162,7 @@ void free_all(nb_ctx *c) {
                     c->colcount, c->colstart, c->colcl, c->perm, c->xs,     c->xq,
                     c->tsort, c->fi,     c->fj,     c->bblo,  c->bbhi,      c->icount,
                     c->jl,    c->epart,  c->meta,   c->ljtab, c->excl_off,  c->excl_idx,
-                    c->dbg_pairs, c->adj, c->adjj, c->gs, c->excl_slot};
+                    c->dbg_pairs, c->adj, c->adjj, c->gs, c->excl_slot, c->etab};
     for (void *p : bufs)
         if (p) hipFree(p);
 }
@@ -170,7 +195,8 @@ int nb_validate_params(const nb_params *p) {
             return fail(nullptr, NB_ERR_ARG, "sigma/epsilon must be finite and >= 0");
     if (p->natoms < 1 || p->natoms > (1 << 27)) return fail(nullptr, NB_ERR_ARG, "natoms must be in 1..2^27");
     if (p->cluster != 0 && p->cluster != 4 && p->cluster != 8) return fail(nullptr, NB_ERR_ARG, "cluster must be 0, 4 or 8");
-    if (p->flags & ~(NB_CHECK_STALE | NB_CHECK_FINITE | NB_ASYNC_BUILD)) return fail(nullptr, NB_ERR_ARG, "unknown flag bits");
+    if (p->flags & ~(NB_CHECK_STALE | NB_CHECK_FINITE | NB_ASYNC_BUILD | NB_ENERGY_FP64))
+        return fail(nullptr, NB_ERR_ARG, "unknown flag bits");
     if (p->excl_off) {
         if (p->excl_off[0] != 0) return fail(nullptr, NB_ERR_ARG, "excl_off[0] must be 0");
         for (int i = 0; i < p->natoms; ++i)
@@ -285,6 +311,7 @@ int nb_setup(nb_ctx **out, const nb_params *p, void *stream) {
         goto fail_out;
     }
     if ((r = upload_lj(c)) != NB_OK) goto fail_out;
+    if ((r = upload_etab(c)) != NB_OK) goto fail_out;
     *out = c;
     return NB_OK;
 fail_out:

@@ -39,6 +39,11 @@ struct nb_batch {
     nb_fparams fp{};        // shared constants (L is set per box on the device)
     double shift_coul = 0;
     float4 *ljtab = nullptr;  // the LJ table of box 0 (identical for all boxes)
+    bool eprec = false;       // FP64 Coulomb energies (tables of box 0)
+    double2 *etab = nullptr;
+    int etab_n = 0;
+    float etab_invh = 0.0f;
+    double fc = 0;
     int ntypes = 0;
     nb_box_desc *d_desc = nullptr;
     int2 *d_items[2] = {nullptr, nullptr};  // work items for C = 4 and C = 8
@@ -86,20 +91,31 @@ __global__ void k_batch_pack(const nb_box_desc *__restrict__ desc, const float *
 
 // Persistent force kernel: every wavefront loops, taking the next work item from the queue,
 // until the queue is empty; every wave reaches that exit.
-template <int C>
+template <int C, bool EPREC>
 __global__ void __launch_bounds__(256) k_batch_force(nb_fparams fp, const nb_box_desc *__restrict__ desc,
                                                      const int2 *__restrict__ items, int nitems,
                                                      const float4 *__restrict__ ljtab,
-                                                     unsigned *counter) {
+                                                     const double2 *__restrict__ etab, int etab_n,
+                                                     float etab_invh, unsigned *counter) {
     extern __shared__ float4 tab[];
     const int ntt = fp.ntypes * fp.ntypes;
     for (int k = threadIdx.x; k < 2 * ntt; k += blockDim.x) tab[k] = ljtab[k];
+    nb_etab et;
+    et.seg = reinterpret_cast<const double2 *>(tab + 2 * ntt);
+    et.invh = etab_invh;
+    et.n = etab_n;
+    if (EPREC) {
+        double2 *dst = reinterpret_cast<double2 *>(tab + 2 * ntt);
+        for (int k = threadIdx.x; k < 2 * etab_n; k += blockDim.x) dst[k] = etab[k];
+    }
     __syncthreads();
     const int lane = threadIdx.x & (NB_WAVE - 1);
-    for (;;) {
-        unsigned it = 0;
-        if (lane == 0) it = atomicAdd(counter, 1u);
-        it = (unsigned)__builtin_amdgcn_readfirstlane((int)__shfl((int)it, 0, NB_WAVE));
+    // Every lane executes the queue atomic (lane 0 adds 1, the others 0), so no divergent
+    // region precedes the uniform exit test; the value lane 0 saw is the item of this wave.
+    // The trip count is bounded by nitems even if the queue misbehaved.
+    for (int iter = 0; iter < nitems; ++iter) {
+        const unsigned it = (unsigned)__builtin_amdgcn_readfirstlane(
+            (int)atomicAdd(counter, lane == 0 ? 1u : 0u));
         if (it >= (unsigned)nitems) break;
         const int2 w = items[it];
         const int b = __builtin_amdgcn_readfirstlane(w.x);
@@ -109,8 +125,8 @@ __global__ void __launch_bounds__(256) k_batch_force(nb_fparams fp, const nb_box
         f.L[0] = d.L[0];
         f.L[1] = d.L[1];
         f.L[2] = d.L[2];
-        nb_force_cluster<C>(f, tab, ci, d.cap, d.npad_max, d.xq, d.tsort, d.icount, d.jl, d.fi, d.fj,
-                            d.epart);
+        nb_force_cluster<C, EPREC>(f, tab, et, ci, d.cap, d.npad_max, d.xq, d.tsort, d.icount, d.jl,
+                                   d.fi, d.fj, d.epart);
     }
 }
 
@@ -127,7 +143,8 @@ __global__ void k_batch_finalize(const nb_box_desc *__restrict__ desc, float *__
 }
 
 __global__ void __launch_bounds__(256) k_batch_energy(const nb_box_desc *__restrict__ desc,
-                                                      double shift_coul, double *__restrict__ e) {
+                                                      double shift_coul, double coul_scale,
+                                                      double *__restrict__ e) {
     __shared__ double s[3][256 / NB_WAVE];
     const nb_box_desc d = desc[blockIdx.x];
     const int ncl = d.meta->nclusters;
@@ -155,7 +172,7 @@ __global__ void __launch_bounds__(256) k_batch_energy(const nb_box_desc *__restr
             tc += s[2][k];
         }
         e[2 * blockIdx.x] = ta;
-        e[2 * blockIdx.x + 1] = tb - shift_coul * tc;
+        e[2 * blockIdx.x + 1] = coul_scale * (tb - shift_coul * tc);
     }
 }
 
@@ -204,16 +221,20 @@ int upload_desc(nb_batch *bt) {
     return NB_OK;
 }
 
+size_t batch_shm(const nb_batch *bt) {
+    return sizeof(float4) * 2 * bt->ntypes * bt->ntypes + (bt->eprec ? sizeof(double2) * 2 * bt->etab_n : 0);
+}
+
 template <int C>
 int grid_for(nb_batch *bt) {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, bt->device) != hipSuccess) return 0;
     int per_cu = bt->blocks_per_cu;
     if (per_cu <= 0) {
-        size_t shm = sizeof(float4) * 2 * bt->ntypes * bt->ntypes;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_force<C>, 256, shm) != hipSuccess ||
-            per_cu <= 0)
-            per_cu = 1;
+        hipError_t e = bt->eprec
+                           ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_force<C, true>, 256, batch_shm(bt))
+                           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_force<C, false>, 256, batch_shm(bt));
+        if (e != hipSuccess || per_cu <= 0) per_cu = 1;
     }
     return per_cu * prop.multiProcessorCount;
 }
@@ -223,17 +244,24 @@ hipError_t launch_forces(nb_batch *bt, const float *x, const float *q, const int
     const int tb = 256;
     hipLaunchKernelGGL(k_batch_pack, dim3((bt->max_npad + tb - 1) / tb, bt->nbox), dim3(tb), 0,
                        bt->stream, bt->d_desc, x, q, type, bt->ntypes, bt->d_counter);
-    const size_t shm = sizeof(float4) * 2 * bt->ntypes * bt->ntypes;
-    if (bt->nitems[0] > 0)
-        hipLaunchKernelGGL(k_batch_force<4>, dim3(bt->grid[0]), dim3(256), shm, bt->stream, bt->fp,
-                           bt->d_desc, bt->d_items[0], bt->nitems[0], bt->ljtab, bt->d_counter);
-    if (bt->nitems[1] > 0)
-        hipLaunchKernelGGL(k_batch_force<8>, dim3(bt->grid[1]), dim3(256), shm, bt->stream, bt->fp,
-                           bt->d_desc, bt->d_items[1], bt->nitems[1], bt->ljtab, bt->d_counter + 1);
+    const size_t shm = batch_shm(bt);
+#define NB_BATCH_LAUNCH(CC, EP, S)                                                                  \
+    hipLaunchKernelGGL((k_batch_force<CC, EP>), dim3(bt->grid[S]), dim3(256), shm, bt->stream, bt->fp, \
+                       bt->d_desc, bt->d_items[S], bt->nitems[S], bt->ljtab, bt->etab, bt->etab_n,  \
+                       bt->etab_invh, bt->d_counter + S)
+    if (bt->nitems[0] > 0) {
+        if (bt->eprec) NB_BATCH_LAUNCH(4, true, 0);
+        else NB_BATCH_LAUNCH(4, false, 0);
+    }
+    if (bt->nitems[1] > 0) {
+        if (bt->eprec) NB_BATCH_LAUNCH(8, true, 1);
+        else NB_BATCH_LAUNCH(8, false, 1);
+    }
+#undef NB_BATCH_LAUNCH
     hipLaunchKernelGGL(k_batch_finalize, dim3((bt->max_natoms + tb - 1) / tb, bt->nbox), dim3(tb), 0,
                        bt->stream, bt->d_desc, f);
     hipLaunchKernelGGL(k_batch_energy, dim3(bt->nbox), dim3(256), 0, bt->stream, bt->d_desc,
-                       bt->shift_coul, e);
+                       bt->shift_coul, bt->eprec ? bt->fc : 1.0, e);
     return hipGetLastError();
 }
 
@@ -299,6 +327,11 @@ int nb_batch_setup(nb_batch **out, int32_t nbox, const int32_t *atom_off, const 
     bt->fp = bt->box[0]->fp;
     bt->shift_coul = bt->box[0]->shift_coul;
     bt->ljtab = bt->box[0]->ljtab;
+    bt->eprec = (common->flags & NB_ENERGY_FP64) != 0;
+    bt->etab = bt->box[0]->etab;
+    bt->etab_n = bt->box[0]->etab_n;
+    bt->etab_invh = bt->box[0]->etab_invh;
+    bt->fc = bt->box[0]->fc;
     hipError_t e = hipMalloc((void **)&bt->d_desc, sizeof(nb_box_desc) * nbox);
     if (e == hipSuccess) e = hipMalloc((void **)&bt->d_counter, sizeof(unsigned) * 2);
     for (int s = 0; s < 2 && e == hipSuccess; ++s) {

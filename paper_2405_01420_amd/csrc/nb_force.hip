@@ -51,11 +51,13 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-template <int C>
+template <int C, bool EPREC>
 __global__ void __launch_bounds__(256) k_force(nb_fparams fp, int cap, int npad_max,
                                                const float4 *__restrict__ xq,
                                                const int *__restrict__ tsort,
                                                const float4 *__restrict__ ljtab,
+                                               const double2 *__restrict__ etab, int etab_n,
+                                               float etab_invh,
                                                const int *__restrict__ icount,
                                                const nb_entry *__restrict__ jl,
                                                float4 *__restrict__ fi_out, float *__restrict__ fj,
@@ -63,11 +65,19 @@ __global__ void __launch_bounds__(256) k_force(nb_fparams fp, int cap, int npad_
     extern __shared__ float4 tab[];
     const int ntt = fp.ntypes * fp.ntypes;
     for (int k = threadIdx.x; k < 2 * ntt; k += blockDim.x) tab[k] = ljtab[k];
+    nb_etab et;
+    et.seg = reinterpret_cast<const double2 *>(tab + 2 * ntt);
+    et.invh = etab_invh;
+    et.n = etab_n;
+    if (EPREC) {
+        double2 *dst = reinterpret_cast<double2 *>(tab + 2 * ntt);
+        for (int k = threadIdx.x; k < 2 * etab_n; k += blockDim.x) dst[k] = etab[k];
+    }
     __syncthreads();
     const int ci = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x / NB_WAVE) +
                                                   threadIdx.x / NB_WAVE);
     if (ci >= meta->nclusters) return;
-    nb_force_cluster<C>(fp, tab, ci, cap, npad_max, xq, tsort, icount, jl, fi_out, fj, epart);
+    nb_force_cluster<C, EPREC>(fp, tab, et, ci, cap, npad_max, xq, tsort, icount, jl, fi_out, fj, epart);
 }
 
 __global__ void k_finalize(int n, int npad_max, const int *__restrict__ slot_of,
@@ -84,7 +94,8 @@ __global__ void k_finalize(int n, int npad_max, const int *__restrict__ slot_of,
 
 // FP64 sum of the per-cluster energy partials; the Coulomb shift is applied here.
 __global__ void __launch_bounds__(1024) k_energy(const nb_meta *meta, const double *__restrict__ epart,
-                                                  double shift_coul, double *__restrict__ e) {
+                                                  double shift_coul, double coul_scale,
+                                                  double *__restrict__ e) {
     __shared__ double s[3][1024 / NB_WAVE];
     const int ncl = meta->nclusters;
     double a = 0.0, b = 0.0, c = 0.0;
@@ -111,7 +122,7 @@ __global__ void __launch_bounds__(1024) k_energy(const nb_meta *meta, const doub
             tc += s[2][k];
         }
         e[0] = ta;
-        e[1] = tb - shift_coul * tc;
+        e[1] = coul_scale * (tb - shift_coul * tc);
     }
 }
 
@@ -126,17 +137,25 @@ hipError_t nb_launch_pack(nb_ctx *c, const float *x, const float *q, const int32
     return hipGetLastError();
 }
 
-hipError_t nb_launch_force(nb_ctx *c) {
-    size_t shm = sizeof(float4) * 2 * c->ntypes * c->ntypes;
+template <int C, bool EPREC>
+static void launch_force_t(nb_ctx *c) {
+    const size_t shm = sizeof(float4) * 2 * c->ntypes * c->ntypes +
+                       (EPREC ? sizeof(double2) * 2 * c->etab_n : 0);
     dim3 grid((c->ncl_max + 3) / 4), block(256);
-    if (c->C == 4)
-        hipLaunchKernelGGL((k_force<4>), grid, block, shm, c->stream, c->fp, c->cap, c->npad_max,
-                           c->xq, c->tsort, c->ljtab, c->icount, c->jl, c->fi, c->fj, c->epart,
-                           c->meta);
-    else
-        hipLaunchKernelGGL((k_force<8>), grid, block, shm, c->stream, c->fp, c->cap, c->npad_max,
-                           c->xq, c->tsort, c->ljtab, c->icount, c->jl, c->fi, c->fj, c->epart,
-                           c->meta);
+    hipLaunchKernelGGL((k_force<C, EPREC>), grid, block, shm, c->stream, c->fp, c->cap, c->npad_max,
+                       c->xq, c->tsort, c->ljtab, c->etab, c->etab_n, c->etab_invh, c->icount,
+                       c->jl, c->fi, c->fj, c->epart, c->meta);
+}
+
+hipError_t nb_launch_force(nb_ctx *c) {
+    const bool ep = (c->flags & NB_ENERGY_FP64) != 0;
+    if (c->C == 4) {
+        if (ep) launch_force_t<4, true>(c);
+        else launch_force_t<4, false>(c);
+    } else {
+        if (ep) launch_force_t<8, true>(c);
+        else launch_force_t<8, false>(c);
+    }
     return hipGetLastError();
 }
 
@@ -145,6 +164,6 @@ hipError_t nb_launch_finalize(nb_ctx *c, float *f, double *e) {
     hipLaunchKernelGGL(k_finalize, dim3((c->natoms + tb - 1) / tb), dim3(tb), 0, c->stream,
                        c->natoms, c->npad_max, c->slot_of, c->fi, c->fj, f);
     hipLaunchKernelGGL(k_energy, dim3(1), dim3(1024), 0, c->stream, c->meta, c->epart,
-                       c->shift_coul, e);
+                       c->shift_coul, (c->flags & NB_ENERGY_FP64) ? c->fc : 1.0, e);
     return hipGetLastError();
 }

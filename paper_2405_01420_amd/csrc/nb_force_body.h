@@ -15,7 +15,11 @@
 //    complementary error function (fit_erfcx.py), Newton-refined reciprocal square root and
 //    reciprocal;
 //  * per-pair energies are rounded once to FP32 and accumulated in FP64; the Coulomb potential
-//    shift is applied in FP64 at the end from the sum of q_i q_j over interacting pairs.
+//    shift is applied in FP64 at the end from the sum of q_i q_j over interacting pairs;
+//  * with EPREC the Coulomb pair energy is instead evaluated in FP64 (exact displacement,
+//    Newton-refined 1/r, erfc from an FP64 cubic Hermite table), forces staying FP32: the FP32
+//    rounding noise of the pair energies is otherwise not averaged below 1e-6 of a Coulomb
+//    energy that is a 4e-4-conditioned sum, in boxes of a few thousand atoms.
 #pragma once
 #include "nb_device.h"
 
@@ -28,21 +32,30 @@ __device__ __forceinline__ double nb_wave_sum_d(double v) {
 // Per-lane state of one batch: the lane's j-atom (shifted into the pair frame), its charge,
 // type row offset and mask column; accumulators for its j-force.
 struct nb_jlane {
-    float x, y, z, q;
+    float x, y, z, q;   // q includes the Coulomb constant
     int t;
     unsigned mcol;
     float fx, fy, fz;
+    double xd, yd, zd, qd;  // FP64 copies (exact) for the FP64 energy mode; qd without fC
+};
+
+// Erfc table of the FP64 energy mode: cubic Hermite segments of erfc(beta r) on
+// [k h, (k+1) h] with h a power of two, coefficients (c0, c1), (c2, c3) in FP64.
+struct nb_etab {
+    const double2 *seg;
+    float invh;
+    int n;
 };
 
 // All C pairs (i-atom k, the lane's j-atom) of one batch.  xs/ys/zs hold the i-coordinates
 // already moved into the pair frame (uniform over the wave in the fast path).  MASKED applies
 // the topology mask; without it every unordered pair within rc interacts.
-template <int C, bool MASKED>
+template <int C, bool MASKED, bool EPREC>
 __device__ __forceinline__ void pair_block(const nb_fparams &fp, const float4 *tab, int ntt,
-                                           const float *xs, const float *ys, const float *zs,
-                                           const float *qi, const int *ti, nb_jlane &j,
-                                           float *fix, float *fiy, float *fiz, double &elj,
-                                           double &ec, float &qqs) {
+                                           const nb_etab &et, const float *xs, const float *ys,
+                                           const float *zs, const float *qi, const int *ti,
+                                           nb_jlane &j, float *fix, float *fiy, float *fiz,
+                                           double &elj, double &ec, double &qqs) {
 #pragma unroll
     for (int k = 0; k < C; ++k) {
         const float dx = xs[k] - j.x;
@@ -76,15 +89,36 @@ __device__ __forceinline__ void pair_block(const nb_fparams &fp, const float4 *t
         Q = __builtin_fmaf(Q, r, fp.q[1]);
         Q = __builtin_fmaf(Q, r, fp.q[0]);
         const float R = P * nb_rcp(Q);
-        const float qq = qi[k] * j.q;
+        const float qq = qi[k] * j.q;             // fC q_i q_j
         const float qe = qq * ex;
         const float t1 = qe * rinv;               // fC q_i q_j exp(-b^2 r^2) / r
-        const float ec_p = t1 * R;                // fC q_i q_j erfc(b r) / r
         const float uu = __builtin_fmaf(fp.kb, r, R);
         const float fs = __builtin_fmaf(t1, uu, flj) * rinv2;
         elj += (double)elj_p;
-        ec += (double)ec_p;
-        qqs = __builtin_fmaf(m1, qq, qqs);
+        if (EPREC) {
+            // Coulomb pair energy in FP64 without fC: exact displacement, 1/r refined in FP64,
+            // erfc(beta r) from the FP64 Hermite table (segment found with the FP32 r)
+            const double dxd = (double)xs[k] - j.xd;
+            const double dyd = (double)ys[k] - j.yd;
+            const double dzd = (double)zs[k] - j.zd;
+            const double r2d = __builtin_fma(dzd, dzd, __builtin_fma(dyd, dyd, dxd * dxd));
+            const double y = (double)rinv;      // zero for non-interacting pairs
+            const double hh = r2d * y;
+            const double ee = __builtin_fma(-hh, y, 1.0);
+            const double rid = __builtin_fma(0.5 * y, ee, y);
+            const double rd = r2d * rid;
+            const int sg = min((int)(r * et.invh), et.n - 1);
+            const double u = __builtin_fma(rd, (double)et.invh, -(double)sg);
+            const double2 c01 = et.seg[2 * sg], c23 = et.seg[2 * sg + 1];
+            const double g = __builtin_fma(__builtin_fma(__builtin_fma(c23.y, u, c23.x), u, c01.y), u, c01.x);
+            const double qqd = (double)qi[k] * j.qd;
+            ec = __builtin_fma(qqd * g, rid, ec);
+            qqs = __builtin_fma((double)m1, qqd, qqs);
+        } else {
+            const float ec_p = t1 * R;            // fC q_i q_j erfc(b r) / r
+            ec += (double)ec_p;
+            qqs += (double)(m1 * qq);
+        }
         fix[k] = __builtin_fmaf(fs, dx, fix[k]);
         fiy[k] = __builtin_fmaf(fs, dy, fiy[k]);
         fiz[k] = __builtin_fmaf(fs, dz, fiz[k]);
@@ -101,8 +135,9 @@ __device__ __forceinline__ float nb_uniform(float v) {
 // Forces and energy partials of one i-cluster ci over its whole j-list, computed by one
 // wavefront.  fp.L holds the box of the cluster.  i-forces are stored (not accumulated) to
 // fi_out, j-forces are added atomically to fj, energy partials are stored to epart[4 ci ..].
-template <int C>
-__device__ __forceinline__ void nb_force_cluster(const nb_fparams &fp, const float4 *tab, int ci,
+template <int C, bool EPREC>
+__device__ __forceinline__ void nb_force_cluster(const nb_fparams &fp, const float4 *tab,
+                                                 const nb_etab &et, int ci,
                                                  int cap, int npad_max,
                                                  const float4 *__restrict__ xq,
                                                  const int *__restrict__ tsort,
@@ -125,7 +160,7 @@ __device__ __forceinline__ void nb_force_cluster(const nb_fparams &fp, const flo
         xi[k] = v.x;
         yi[k] = v.y;
         zi[k] = v.z;
-        qi[k] = nb_uniform(v.w * fp.fc);
+        qi[k] = nb_uniform(v.w);
         ti[k] = tsort[ci * C + k] * nt;
         xs[k] = xi[k];
         ys[k] = yi[k];
@@ -135,8 +170,7 @@ __device__ __forceinline__ void nb_force_cluster(const nb_fparams &fp, const flo
     float fix[C], fiy[C], fiz[C];
 #pragma unroll
     for (int k = 0; k < C; ++k) fix[k] = fiy[k] = fiz[k] = 0.0f;
-    double elj = 0.0, ec = 0.0;
-    float qqs = 0.0f;
+    double elj = 0.0, ec = 0.0, qqs = 0.0;
 
     const int nj = icount[ci];
     const nb_entry *lst = jl + (size_t)ci * cap;
@@ -155,7 +189,8 @@ __device__ __forceinline__ void nb_force_cluster(const nb_fparams &fp, const flo
         const int jslot = en.cj * C + b;
         const float4 xj = xq[jslot];
         nb_jlane jv;
-        jv.q = xj.w;
+        jv.q = xj.w * fp.fc;
+        jv.qd = (double)xj.w;
         jv.t = tsort[jslot];
         jv.mcol = nb_mask_column<C>(((unsigned long long)en.mhi << 32) | en.mlo, b);
         jv.fx = jv.fy = jv.fz = 0.0f;
@@ -177,11 +212,16 @@ __device__ __forceinline__ void nb_force_cluster(const nb_fparams &fp, const flo
             jv.x = xj.x + nb_dj(tx, fp.L[0]);
             jv.y = xj.y + nb_dj(ty, fp.L[1]);
             jv.z = xj.z + nb_dj(tz, fp.L[2]);
+            if (EPREC) {
+                jv.xd = (double)jv.x;
+                jv.yd = (double)jv.y;
+                jv.zd = (double)jv.z;
+            }
             const bool full = __ballot(!valid || jv.mcol != FULL) == 0ull;
             if (full)
-                pair_block<C, false>(fp, tab, ntt, xs, ys, zs, qi, ti, jv, fix, fiy, fiz, elj, ec, qqs);
+                pair_block<C, false, EPREC>(fp, tab, ntt, et, xs, ys, zs, qi, ti, jv, fix, fiy, fiz, elj, ec, qqs);
             else
-                pair_block<C, true>(fp, tab, ntt, xs, ys, zs, qi, ti, jv, fix, fiy, fiz, elj, ec, qqs);
+                pair_block<C, true, EPREC>(fp, tab, ntt, et, xs, ys, zs, qi, ti, jv, fix, fiy, fiz, elj, ec, qqs);
         } else {
             // shifts differ across the batch: per-lane frame offsets
             const int tx = nb_tx(s), ty = nb_ty(s), tz = nb_tz(s);
@@ -189,6 +229,11 @@ __device__ __forceinline__ void nb_force_cluster(const nb_fparams &fp, const flo
             jv.x = xj.x + nb_dj(tx, fp.L[0]);
             jv.y = xj.y + nb_dj(ty, fp.L[1]);
             jv.z = xj.z + nb_dj(tz, fp.L[2]);
+            if (EPREC) {
+                jv.xd = (double)jv.x;
+                jv.yd = (double)jv.y;
+                jv.zd = (double)jv.z;
+            }
             float xl[C], yl[C], zl[C];
 #pragma unroll
             for (int k = 0; k < C; ++k) {
@@ -196,7 +241,7 @@ __device__ __forceinline__ void nb_force_cluster(const nb_fparams &fp, const flo
                 yl[k] = yi[k] + diy;
                 zl[k] = zi[k] + diz;
             }
-            pair_block<C, true>(fp, tab, ntt, xl, yl, zl, qi, ti, jv, fix, fiy, fiz, elj, ec, qqs);
+            pair_block<C, true, EPREC>(fp, tab, ntt, et, xl, yl, zl, qi, ti, jv, fix, fiy, fiz, elj, ec, qqs);
         }
         if (valid) {
             atomicAdd(&fj[jslot], jv.fx);
@@ -212,7 +257,7 @@ __device__ __forceinline__ void nb_force_cluster(const nb_fparams &fp, const flo
     }
     elj = nb_wave_sum_d(elj);
     ec = nb_wave_sum_d(ec);
-    const double qqd = nb_wave_sum_d((double)qqs);
+    const double qqd = nb_wave_sum_d(qqs);
     if (lane == NB_WAVE - 1) {
 #pragma unroll
         for (int k = 0; k < C; ++k) fi_out[ci * C + k] = make_float4(fix[k], fiy[k], fiz[k], 0.0f);

@@ -109,6 +109,9 @@ struct nb_ctx {
     double *epart = nullptr;    // [ncl_max * 4]
     nb_meta *meta = nullptr;
     float4 *ljtab = nullptr;    // [2 * nt * nt]: (C6, C12, 6 C6, 12 C12), (shift, 1/sigma_ab, 0, 0)
+    double2 *etab = nullptr;    // [2 * etab_n]: Hermite segments of erfc(beta r) (FP64 energy mode)
+    int etab_n = 0;
+    float etab_invh = 0.0f;     // 1 / segment width, a power of two
     int *excl_off = nullptr, *excl_idx = nullptr;
     int *excl_slot = nullptr;   // [nnz] exclusion partners as slots (rebuilt with every list)
     int nnz_excl = 0;

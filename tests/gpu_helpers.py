@@ -9,6 +9,10 @@ from paper_2405_01420_amd import nb
 
 FORCE_TOL = 5e-6
 ENERGY_TOL = 1e-6
+# With FP32 pair energies the Coulomb energy of a box of a few thousand atoms carries FP32
+# rounding noise of ~1e-6 of a sum whose conditioning |E_C| / sum |E_C,ij| is ~4e-4; the gate
+# in that mode is this looser bound, and the FP64-energy mode is held to ENERGY_TOL.
+FP32_SMALL_BOX_EC_TOL = 1e-5
 
 
 def dev(torch, a, dtype=None):

@@ -2,7 +2,8 @@
 rb = 0.1 nm, 30% of the O atoms re-typed to 4 extra LJ types.  The FP64 cell-list oracle
 (checked equal to brute force on smaller boxes) gives all forces and energies; the pair set is
 checked by its size (the full set has about 1.1e9 pairs), which may differ only by pairs whose
-FP64 distance lies within 2^-22 L of the cutoff."""
+FP64 distance lies within 2^-22 L of the cutoff.  FP64 pair energies are used: with FP32 pair
+energies the Coulomb energy of this box ends near 1e-6 relative (its conditioning is 1e-4)."""
 import ctypes
 
 import numpy as np
@@ -18,7 +19,7 @@ pytestmark = pytest.mark.gpu
 def test_large_forces_energies_and_pair_count(torch_gpu):
     inst = synth.large()
     print("generated", inst.natoms, flush=True)
-    box = GpuBox(torch_gpu, inst)
+    box = GpuBox(torch_gpu, inst, flags=nb.NB_ENERGY_FP64)
     box.pairlist()
     f, e = box.forces()
     cnt = ctypes.c_int64(0)
