@@ -12,7 +12,15 @@ counted at the start positions) over the timed steps.  The JSON line also carrie
 force-kernel roofline (algorithmic FP32 flops per useful pair x useful pairs / measured kernel
 time, against the FP32 vector peak) and the FP64 oracle timed on the host as cpu_baseline.
 
+Beside the headline line the JSON carries the two other forms against the plain kernel:
+  batched - 256 independent boxes (3,000-30,000 atoms, log-uniform, rc 0.9 nm) in one persistent
+            launch replayed from a HIP graph, with the autotuner's cluster sizes and schedule,
+            against 256 sequential plain force calls on the same boxes;
+  adjoint - the 24,000-atom four-type box: nb_backward (list reused, and with the list rebuilt
+            from x) against nb_forces on the same box.
+
 Usage: python bench.py [--gpus 1] [--steps 1000] [--warmup 20] [--cluster 8] [--cpu-seconds 12]
+                       [--no-batch] [--no-adjoint] [--no-tune] [--no-cpu]
 """
 import argparse
 import json
@@ -41,6 +49,11 @@ def parse():
     ap.add_argument("--cluster", type=int, default=0, help="4 or 8 (0 = tuned or default 8)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="end with one 256 MiB device-to-device copy (calibrates HBM byte counters)")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="batched form with C = 8 everywhere")
     ap.add_argument("--energy-fp64", action="store_true",
                     help="evaluate Coulomb pair energies in FP64 (forces stay FP32)")
     return ap.parse_args()
@@ -63,6 +76,121 @@ def cpu_baseline(inst, useful_pairs, seconds):
             "cores": O.get_threads(), "kind": "oracle",
             "sample": f"{calls} full force+energy calls of the FP64 cell-list oracle on the "
                       f"96,000-atom box ({el:.1f} s); per call {1e6 * el / calls:.0f} us"}
+
+
+def _event_us(torch, stream, fn, reps):
+    """Average microseconds of fn() over reps calls, HIP events on `stream`."""
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    stream.synchronize()
+    return 1e3 * e0.elapsed_time(e1) / reps
+
+
+def bench_batched(torch, nb, synth, tune_on, reps=20):
+    """256 uneven boxes: one persistent graph-replayed launch vs 256 sequential plain calls."""
+    from paper_2405_01420_amd import tune
+    dev = "cuda:0"
+    insts = synth.batch(256)
+    stream = torch.cuda.Stream()
+    tuned = None
+    if tune_on:
+        tuned = tune.autotune(insts)
+        clusters, srt, bpc = tuned["clusters"], tuned["sorted"], tuned["blocks_per_cu"]
+    else:
+        clusters, srt, bpc = [8] * len(insts), True, 0
+    ao, bx, params, x, q, t = nb.concat_instances(insts, clusters=clusters)
+    n = int(ao[-1])
+    bt = nb.nb_batch_setup(ao, bx, params, clusters=clusters, stream=stream.cuda_stream)
+    nb.nb_batch_set_schedule(bt, srt, bpc)
+    with torch.cuda.stream(stream):
+        dx = torch.from_numpy(x.reshape(-1)).to(dev)
+        dq = torch.from_numpy(q).to(dev)
+        dt = torch.from_numpy(t).to(dev)
+        f = torch.empty(3 * n, dtype=torch.float32, device=dev)
+        e = torch.empty(2 * len(insts), dtype=torch.float64, device=dev)
+    stream.synchronize()
+    nb.nb_batch_pairlist(bt, dx)
+    info = nb.nb_batch_get_info(bt)
+    for _ in range(3):
+        nb.nb_batch_graph_forces(bt, dx, dq, dt, f, e)
+        nb.nb_batch_forces(bt, dx, dq, dt, f, e)
+    us_graph = _event_us(torch, stream, lambda: nb.nb_batch_graph_forces(bt, dx, dq, dt, f, e), reps)
+    us_eager = _event_us(torch, stream, lambda: nb.nb_batch_forces(bt, dx, dq, dt, f, e), reps)
+    nb.nb_batch_destroy(bt)
+    # the same boxes one after another through the plain path (C = 8, lists prebuilt)
+    plain = []
+    useful = 0
+    for k, inst in enumerate(insts):
+        ctx = nb.nb_setup(nb.Params.from_instance(inst), stream=stream.cuda_stream)
+        a, b = int(ao[k]), int(ao[k + 1])
+        xs, qs, ts = dx[3 * a:3 * b], dq[a:b], dt[a:b]
+        fs = f[3 * a:3 * b]
+        es = e[2 * k:2 * k + 2]
+        nb.nb_pairlist(ctx, xs)
+        useful += nb.nb_debug_pairs(ctx, xs, 0, count_only=True)
+        plain.append((ctx, xs, qs, ts, fs, es))
+
+    def seq():
+        for ctx, xs, qs, ts, fs, es in plain:
+            nb.nb_forces(ctx, xs, qs, ts, fs, es)
+    seq()
+    us_seq = _event_us(torch, stream, seq, max(3, reps // 4))
+    for p in plain:
+        nb.nb_destroy(p[0])
+    out = {"workload": "256 water boxes, 3,000-30,000 atoms log-uniform (multiples of 3), "
+                       "100 atoms/nm^3, rc 0.9 nm, rb 0.1 nm",
+           "natoms": n, "useful_pairs": useful,
+           "us_per_batch_call_graph": us_graph, "us_per_batch_call_eager": us_eager,
+           "us_256_sequential_plain_calls": us_seq,
+           "pair_interactions_per_s_graph": useful / (us_graph * 1e-6),
+           "pair_interactions_per_s_sequential": useful / (us_seq * 1e-6),
+           "speedup_vs_sequential": us_seq / us_graph,
+           "clusters": {"4": clusters.count(4), "8": clusters.count(8)},
+           "schedule": {"sorted": bool(srt), "blocks_per_cu": int(bpc)},
+           "evaluated_pairs": info["evaluated_pairs"]}
+    if tuned is not None:
+        out["tune_s"] = tuned["tune_s"]
+    return out
+
+
+def bench_adjoint(torch, nb, synth, reps=50):
+    """nb_backward vs nb_forces on the 24,000-atom differentiation box."""
+    dev = "cuda:0"
+    inst = synth.diff()
+    stream = torch.cuda.current_stream()
+    ctx = nb.nb_setup(nb.Params.from_instance(inst), stream=stream.cuda_stream)
+    n = inst.natoms
+    x = torch.from_numpy(inst.x.reshape(-1).copy()).to(dev)
+    q = torch.from_numpy(inst.q.copy()).to(dev)
+    t = torch.from_numpy(inst.type.copy()).to(dev)
+    f = torch.empty(3 * n, dtype=torch.float32, device=dev)
+    e = torch.empty(2, dtype=torch.float64, device=dev)
+    g = torch.Generator(device=dev)
+    g.manual_seed(7)
+    gf = torch.randn(3 * n, generator=g, device=dev)
+    ge = torch.tensor([0.3, -0.7], dtype=torch.float64, device=dev)
+    ddx = torch.empty(3 * n, dtype=torch.float32, device=dev)
+    ddq = torch.empty(n, dtype=torch.float32, device=dev)
+    ds = torch.empty(inst.ntypes, dtype=torch.float64, device=dev)
+    de = torch.empty(inst.ntypes, dtype=torch.float64, device=dev)
+    nb.nb_pairlist(ctx, x)
+    useful = nb.nb_debug_pairs(ctx, x, 0, count_only=True)
+    nb.nb_forces(ctx, x, q, t, f, e)
+    us_f = _event_us(torch, stream, lambda: nb.nb_forces(ctx, x, q, t, f, e), reps)
+    bw = lambda fl: nb.nb_backward(ctx, x, q, t, gf, ge, ddx, ddq, ds, de, fl)
+    bw(nb.NB_REUSE_LIST)
+    us_b = _event_us(torch, stream, lambda: bw(nb.NB_REUSE_LIST), reps)
+    us_b_build = _event_us(torch, stream, lambda: bw(0), max(5, reps // 5))
+    nb.nb_destroy(ctx)
+    return {"workload": "24,000-atom water box (8,000 waters, L 6.21 nm), 4 LJ types, "
+                        "charges perturbed, rc 1.0 nm",
+            "useful_pairs": useful, "us_per_force_call": us_f,
+            "us_per_backward_call": us_b, "us_per_backward_call_with_list_rebuild": us_b_build,
+            "backward_over_forces": us_b / us_f,
+            "pair_interactions_per_s_backward": useful / (us_b * 1e-6)}
 
 
 def main():
@@ -173,9 +301,20 @@ def main():
                      "traffic": None, "kernel": "k_force", "kernel_us": kernel_us,
                      "flops_per_pair": FLOPS_PER_PAIR},
     }
+    nb.nb_destroy(ctx)
+    if not args.no_adjoint:
+        out["adjoint"] = bench_adjoint(torch, nb, synth)
+    if not args.no_batch:
+        out["batched"] = bench_batched(torch, nb, synth, not args.no_tune)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(inst, useful, args.cpu_seconds)
-    nb.nb_destroy(ctx)
+    if args.copy_probe:
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = {"read": src.numel() * 4, "write": dst.numel() * 4}
     print(json.dumps(out))
 
 

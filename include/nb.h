@@ -58,6 +58,8 @@ typedef enum nb_status {
 } nb_status;
 
 /* flags (nb_params.flags and per-call flags) */
+#define NB_MAX_EXCL_PER_ATOM 32 /* excluded partners per atom accepted by nb_setup */
+
 #define NB_CHECK_STALE  0x1u  /* nb_forces records whether any atom moved >= buffer/2 */
 #define NB_CHECK_FINITE 0x2u  /* nb_forces records non-finite coordinates */
 #define NB_REUSE_LIST   0x4u  /* nb_backward: use the current list instead of rebuilding */
@@ -77,15 +79,16 @@ typedef struct nb_params {
     const double *epsilon;  /* host [ntypes] LJ epsilon (kJ/mol) >= 0 */
     int32_t natoms;         /* number of atoms, 1 .. 2^27 */
     const int32_t *excl_off;/* host [natoms+1] CSR offsets of excluded partners, or NULL */
-    const int32_t *excl_idx;/* host [excl_off[natoms]] partner indices (symmetric lists) */
+    const int32_t *excl_idx;/* host [excl_off[natoms]] partner indices (symmetric lists),
+                             * at most NB_MAX_EXCL_PER_ATOM per atom */
     uint32_t flags;         /* NB_CHECK_*, NB_ASYNC_BUILD, NB_ENERGY_FP64 */
     int32_t cluster;        /* cluster size C of the list: 4 or 8 (0 = 8) */
 } nb_params;
 
 typedef struct nb_stats {
     int64_t natoms, nclusters, npadded;   /* atoms, clusters, slots incl. padding */
-    int64_t nentries;                     /* cluster pairs (j-entries) in the list */
-    int64_t evaluated_pairs;              /* nentries * C * C */
+    int64_t nentries;                     /* j-entries in the list (i-cluster x 4-atom j-group) */
+    int64_t evaluated_pairs;              /* nentries * C * 4 */
     int64_t list_capacity;                /* j-entries per i-cluster the list can hold */
     int32_t cluster, ncolumns;
     double build_ms_last;                 /* host-timed duration of the last nb_pairlist */
@@ -182,7 +185,7 @@ typedef struct nb_batch_info {
     int64_t natoms;           /* atoms over all boxes */
     int64_t nitems;           /* i-clusters (work items) over all boxes */
     int64_t nentries;         /* j-entries over all boxes */
-    int64_t evaluated_pairs;  /* sum over boxes of nentries * C^2 */
+    int64_t evaluated_pairs;  /* sum over boxes of nentries * C * 4 */
     int32_t grid_blocks[2];   /* persistent blocks per launch for C = 4 and C = 8 (0 = unused) */
     int32_t graph_ready;      /* 1 if a captured graph exists for the current lists */
     int32_t pad;

@@ -43,7 +43,6 @@ __global__ void __launch_bounds__(256) k_adjoint(nb_fparams fp, float s_lj, floa
                                                  const nb_entry *__restrict__ jl,
                                                  float *__restrict__ adj, float *__restrict__ adjj,
                                                  const nb_meta *meta) {
-    constexpr int JPB = NB_WAVE / C;
     extern __shared__ float4 tab[];
     const int nt = fp.ntypes, ntt = nt * nt;
     for (int k = threadIdx.x; k < 2 * ntt; k += blockDim.x) tab[k] = ljtab[k];
@@ -52,7 +51,7 @@ __global__ void __launch_bounds__(256) k_adjoint(nb_fparams fp, float s_lj, floa
     const int ci = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x / NB_WAVE) +
                                                   threadIdx.x / NB_WAVE);
     if (ci >= meta->nclusters) return;
-    const int b = lane % C, jsub = lane / C;
+    const int b = lane % NB_JG, jsub = lane / NB_JG;
 
     float xi[C], yi[C], zi[C], qi[C], gxi[C], gyi[C], gzi[C];
     int ti[C];
@@ -73,20 +72,13 @@ __global__ void __launch_bounds__(256) k_adjoint(nb_fparams fp, float s_lj, floa
     }
     const int nj = icount[ci];
     const nb_entry *lst = jl + (size_t)ci * cap;
-    for (int base = 0; base < nj; base += JPB) {
+    for (int base = 0; base < nj; base += NB_JPB) {
         const int e = base + jsub;
         const bool valid = e < nj;
-        nb_entry en;
-        if (valid) {
-            en = lst[e];
-        } else {
-            en.cj = ci;
-            en.shift = NB_SHIFT_ZERO;
-            en.mlo = en.mhi = 0u;
-        }
-        const int s = en.shift;
+        const nb_entry en = valid ? lst[e] : nb_make_entry(ci * (C / NB_JG), NB_SHIFT_ZERO, 0u);
+        const int s = nb_entry_shift(en);
         const int tx = nb_tx(s), ty = nb_ty(s), tz = nb_tz(s);
-        const int jslot = en.cj * C + b;
+        const int jslot = nb_entry_group(en) * NB_JG + b;
         const float4 xj = xq[jslot];
         const float4 gj = gs[jslot];
         const int tj = tsort[jslot];
@@ -94,8 +86,7 @@ __global__ void __launch_bounds__(256) k_adjoint(nb_fparams fp, float s_lj, floa
                     zjs = xj.z + nb_dj(tz, fp.L[2]);
         const float dix = nb_di(tx, fp.L[0]), diy = nb_di(ty, fp.L[1]), diz = nb_di(tz, fp.L[2]);
         const float qj = xj.w;
-        const unsigned long long m = ((unsigned long long)en.mhi << 32) | en.mlo;
-        const unsigned mcol = nb_mask_column<C>(m, b);
+        const unsigned mcol = nb_mask_column<C>(en.mask, b);
         float jx = 0.0f, jy = 0.0f, jz = 0.0f, jq = 0.0f, jw = 0.0f, ju = 0.0f;
 #pragma unroll
         for (int k = 0; k < C; ++k) {
@@ -109,8 +100,8 @@ __global__ void __launch_bounds__(256) k_adjoint(nb_fparams fp, float s_lj, floa
             const float rinv2 = rinv * rinv;
             const float rinv4 = rinv2 * rinv2;
             const float rinv6 = rinv4 * rinv2;
-            const float4 lj = tab[ti[k] + tj];          // (C6, C12, 6 C6, 12 C12)
-            const float4 lj2 = tab[ntt + ti[k] + tj];   // (shift, 1/sigma_ab, -, -)
+            const float4 lj = tab[2 * (ti[k] + tj)];       // (C6, C12, 6 C6, 12 C12)
+            const float4 lj2 = tab[2 * (ti[k] + tj) + 1];  // (shift, 1/sigma_ab, -, -)
             const float ddx = gxi[k] - gj.x, ddy = gyi[k] - gj.y, ddz = gzi[k] - gj.z;
             const float dd = __builtin_fmaf(dz, ddz, __builtin_fmaf(dy, ddy, dx * ddx));
             // Lennard-Jones

@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <vector>
 
 #include "erfcx_rational.h"
 #include "nb_internal.h"
@@ -51,7 +52,7 @@ int estimate_cap(double natoms, const double *box, int C, double rlist) {
     double s = 2.0 * a;
     double vol = s * s * s + 6.0 * s * s * rlist + 3.0 * M_PI * s * rlist * rlist +
                  4.0 / 3.0 * M_PI * rlist * rlist * rlist;
-    double n = vol * rho / C;
+    double n = vol * rho / NB_JG;  // j-groups of NB_JG atoms within the dilated i-cluster
     int cap = (int)(1.25 * n) + 32;
     return (cap + 31) & ~31;
 }
@@ -68,8 +69,9 @@ void lj_table(nb_ctx *c, std::vector<float4> &tab) {
             double c6 = 4.0 * e * s6, c12 = 4.0 * e * s6 * s6;
             float c6f = (float)c6, c12f = (float)c12;
             double sh = (double)c12f * irc6 * irc6 - (double)c6f * irc6;
-            tab[a * nt + b] = make_float4(c6f, c12f, (float)(6.0 * c6), (float)(12.0 * c12));
-            tab[nt * nt + a * nt + b] = make_float4((float)sh, s > 0.0 ? (float)(1.0 / s) : 0.0f, 0.0f, 0.0f);
+            // two float4 per type pair, side by side: one address serves both LDS reads
+            tab[2 * (a * nt + b)] = make_float4(c6f, c12f, (float)(6.0 * c6), (float)(12.0 * c12));
+            tab[2 * (a * nt + b) + 1] = make_float4((float)sh, s > 0.0 ? (float)(1.0 / s) : 0.0f, 0.0f, 0.0f);
         }
 }
 
@@ -171,6 +173,16 @@ void free_all(nb_ctx *c) {
 
 int nb_read_meta(nb_ctx *c, nb_meta *m) { return read_meta(c, m); }
 
+int nb_list_entries(nb_ctx *c, int nclusters, int64_t *total) {
+    *total = 0;
+    if (!c->have_list || nclusters <= 0) return NB_OK;
+    std::vector<int> cnt(nclusters);
+    hipError_t e = hipMemcpy(cnt.data(), c->icount, sizeof(int) * nclusters, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(c, e, "read list lengths");
+    for (int v : cnt) *total += v;
+    return NB_OK;
+}
+
 int nb_regrow_list(nb_ctx *c, int maxcount) {
     c->cap = ((maxcount + maxcount / 8 + 32) + 31) & ~31;
     return alloc_list(c);
@@ -201,6 +213,9 @@ int nb_validate_params(const nb_params *p) {
         if (p->excl_off[0] != 0) return fail(nullptr, NB_ERR_ARG, "excl_off[0] must be 0");
         for (int i = 0; i < p->natoms; ++i)
             if (p->excl_off[i + 1] < p->excl_off[i]) return fail(nullptr, NB_ERR_ARG, "excl_off must be non-decreasing");
+        for (int i = 0; i < p->natoms; ++i)
+            if (p->excl_off[i + 1] - p->excl_off[i] > NB_MAX_EXCL_PER_ATOM)
+                return fail(nullptr, NB_ERR_ARG, "an atom has more than 32 excluded partners");
         int nnz = p->excl_off[p->natoms];
         if (nnz > 0 && !p->excl_idx) return fail(nullptr, NB_ERR_ARG, "excl_idx is NULL");
         for (int k = 0; k < nnz; ++k)
@@ -355,7 +370,7 @@ int nb_pairlist(nb_ctx *c, const float *x) {
         int r = read_meta(c, &m);
         if (r != NB_OK) return r;
         if (m.flags & NB_F_COLUMN)
-            return fail(c, NB_ERR_OVERFLOW, "a grid column holds more atoms than the column sort supports");
+            return fail(c, NB_ERR_OVERFLOW, "a grid column or the exclusions of one cluster exceed the build kernels' capacity");
         if (m.flags & NB_F_NONFINITE) return fail(c, NB_ERR_NONFINITE, "non-finite coordinates");
         if (m.flags & NB_F_OVERFLOW) {
             c->cap = ((m.maxcount + m.maxcount / 8 + 32) + 31) & ~31;
@@ -466,8 +481,8 @@ int nb_get_stats(nb_ctx *c, nb_stats *st) {
     st->natoms = c->natoms;
     st->nclusters = m.nclusters;
     st->npadded = m.npad;
-    st->nentries = m.nentries;
-    st->evaluated_pairs = m.nentries * (int64_t)c->C * c->C;
+    if ((r = nb_list_entries(c, m.nclusters, &st->nentries)) != NB_OK) return r;
+    st->evaluated_pairs = st->nentries * (int64_t)c->C * NB_JG;
     st->list_capacity = c->cap;
     st->cluster = c->C;
     st->ncolumns = c->geom.ncol;

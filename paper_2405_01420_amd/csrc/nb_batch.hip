@@ -1,7 +1,9 @@
 // Batched form: independent boxes (an ensemble) evaluated together.  Every box keeps its own
 // context (grid, list, buffers); the force phase is one persistent launch per cluster shape in
-// which each wavefront pulls (box, i-cluster) work items from an atomic counter, in descending
-// order of j-list length so that the longest items start first and the tail is short.  Pack,
+// which each wavefront pulls chunks of (box, i-cluster) work items from an atomic counter.  The
+// items are in descending order of j-list length so that the longest start first, and the chunks
+// are cut by guided self-scheduling (each holds about 1/(2W) of the work still left, W waves), so
+// the queue head is touched a few times per wave instead of once per i-cluster.  Pack,
 // finalize and energy reduction each run as one launch over all boxes (2-D grids), so the
 // whole force call is four launches that a HIP graph replays with one host call.
 #include <string.h>
@@ -47,7 +49,9 @@ struct nb_batch {
     int ntypes = 0;
     nb_box_desc *d_desc = nullptr;
     int2 *d_items[2] = {nullptr, nullptr};  // work items for C = 4 and C = 8
+    int *d_chunks[2] = {nullptr, nullptr};  // chunk boundaries into the work items
     int nitems[2] = {0, 0};
+    int nchunks[2] = {0, 0};
     int item_cap[2] = {0, 0};
     unsigned *d_counter = nullptr;           // two queue heads
     int max_npad = 0, max_natoms = 0;
@@ -70,8 +74,9 @@ __global__ void k_batch_pack(const nb_box_desc *__restrict__ desc, const float *
     const int bidx = blockIdx.y;
     const nb_box_desc d = desc[bidx];
     if (bidx == 0 && blockIdx.x == 0 && threadIdx.x < 2) counter[threadIdx.x] = 0u;
+    // slots past a box's current padded count hold perm = -1 (set at every build)
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= d.npad_max || p >= d.meta->npad) return;
+    if (p >= d.npad_max) return;
     const int a = d.perm[p];
     if (a >= 0) {
         const int g = d.atom_off + a;
@@ -89,11 +94,12 @@ __global__ void k_batch_pack(const nb_box_desc *__restrict__ desc, const float *
     d.fj[2 * d.npad_max + p] = 0.0f;
 }
 
-// Persistent force kernel: every wavefront loops, taking the next work item from the queue,
-// until the queue is empty; every wave reaches that exit.
+// Persistent force kernel: every wavefront loops, taking the next chunk of work items from the
+// queue, until the queue is empty; every wave reaches that exit.
 template <int C, bool EPREC>
-__global__ void __launch_bounds__(256) k_batch_force(nb_fparams fp, const nb_box_desc *__restrict__ desc,
-                                                     const int2 *__restrict__ items, int nitems,
+__global__ void __launch_bounds__(256) NB_FORCE_OCCUPANCY k_batch_force(nb_fparams fp, const nb_box_desc *__restrict__ desc,
+                                                     const int2 *__restrict__ items,
+                                                     const int *__restrict__ chunks, int nchunks,
                                                      const float4 *__restrict__ ljtab,
                                                      const double2 *__restrict__ etab, int etab_n,
                                                      float etab_invh, unsigned *counter) {
@@ -110,23 +116,30 @@ __global__ void __launch_bounds__(256) k_batch_force(nb_fparams fp, const nb_box
     }
     __syncthreads();
     const int lane = threadIdx.x & (NB_WAVE - 1);
-    // Every lane executes the queue atomic (lane 0 adds 1, the others 0), so no divergent
-    // region precedes the uniform exit test; the value lane 0 saw is the item of this wave.
-    // The trip count is bounded by nitems even if the queue misbehaved.
-    for (int iter = 0; iter < nitems; ++iter) {
-        const unsigned it = (unsigned)__builtin_amdgcn_readfirstlane(
+    // Every lane executes the queue atomic (lane 0 adds 1, the others 0; the compiler issues
+    // one atomic per wave), so no divergent region precedes the uniform exit test; the value
+    // lane 0 saw is the chunk of this wave.  The trip count is bounded by nchunks even if the
+    // queue misbehaved.
+    for (int iter = 0; iter < nchunks; ++iter) {
+        const unsigned c = (unsigned)__builtin_amdgcn_readfirstlane(
             (int)atomicAdd(counter, lane == 0 ? 1u : 0u));
-        if (it >= (unsigned)nitems) break;
-        const int2 w = items[it];
-        const int b = __builtin_amdgcn_readfirstlane(w.x);
-        const int ci = __builtin_amdgcn_readfirstlane(w.y);
-        const nb_box_desc &d = desc[b];
-        nb_fparams f = fp;
-        f.L[0] = d.L[0];
-        f.L[1] = d.L[1];
-        f.L[2] = d.L[2];
-        nb_force_cluster<C, EPREC>(f, tab, et, ci, d.cap, d.npad_max, d.xq, d.tsort, d.icount, d.jl,
-                                   d.fi, d.fj, d.epart);
+        if (c >= (unsigned)nchunks) break;
+        const int i0 = __builtin_amdgcn_readfirstlane(chunks[c]);
+        const int i1 = __builtin_amdgcn_readfirstlane(chunks[c + 1]);
+        for (int it = i0; it < i1; ++it) {
+            const int2 w = items[it];
+            const int b = __builtin_amdgcn_readfirstlane(w.x);
+            const int ci = __builtin_amdgcn_readfirstlane(w.y);
+            const nb_box_desc &d = desc[b];
+            nb_fparams f = fp;
+            f.L[0] = d.L[0];
+            f.L[1] = d.L[1];
+            f.L[2] = d.L[2];
+            // the descriptor's pointers are global memory; typed so, their accesses are global
+            nb_force_cluster<C, EPREC>(f, tab, et, ci, d.cap, d.npad_max, nb_g(d.xq), nb_g(d.tsort),
+                                       nb_g(d.icount), nb_g(d.jl), nb_g(d.fi), nb_g(d.fj),
+                                       nb_g(d.epart));
+        }
     }
 }
 
@@ -188,7 +201,8 @@ void free_batch(nb_batch *bt) {
     for (nb_ctx *c : bt->box)
         if (c) nb_destroy(c);
     if (bt->gexec) hipGraphExecDestroy(bt->gexec);
-    void *bufs[] = {bt->d_desc, bt->d_items[0], bt->d_items[1], bt->d_counter};
+    void *bufs[] = {bt->d_desc, bt->d_items[0], bt->d_items[1], bt->d_chunks[0], bt->d_chunks[1],
+                    bt->d_counter};
     for (void *p : bufs)
         if (p) hipFree(p);
 }
@@ -247,7 +261,8 @@ hipError_t launch_forces(nb_batch *bt, const float *x, const float *q, const int
     const size_t shm = batch_shm(bt);
 #define NB_BATCH_LAUNCH(CC, EP, S)                                                                  \
     hipLaunchKernelGGL((k_batch_force<CC, EP>), dim3(bt->grid[S]), dim3(256), shm, bt->stream, bt->fp, \
-                       bt->d_desc, bt->d_items[S], bt->nitems[S], bt->ljtab, bt->etab, bt->etab_n,  \
+                       bt->d_desc, bt->d_items[S], bt->d_chunks[S], bt->nchunks[S], bt->ljtab,      \
+                       bt->etab, bt->etab_n,                                                        \
                        bt->etab_invh, bt->d_counter + S)
     if (bt->nitems[0] > 0) {
         if (bt->eprec) NB_BATCH_LAUNCH(4, true, 0);
@@ -337,6 +352,7 @@ int nb_batch_setup(nb_batch **out, int32_t nbox, const int32_t *atom_off, const 
     for (int s = 0; s < 2 && e == hipSuccess; ++s) {
         bt->item_cap[s] = (int)std::max<int64_t>(items_max[s], 1);
         e = hipMalloc((void **)&bt->d_items[s], sizeof(int2) * bt->item_cap[s]);
+        if (e == hipSuccess) e = hipMalloc((void **)&bt->d_chunks[s], sizeof(int) * (bt->item_cap[s] + 1));
     }
     if (e != hipSuccess) {
         free_batch(bt);
@@ -424,9 +440,13 @@ int nb_batch_pairlist(nb_batch *bt, const float *x) {
             hipMemcpy(cnt.data(), c->icount, sizeof(int) * m.nclusters, hipMemcpyDeviceToHost) != hipSuccess)
             return bfail(bt, NB_ERR_HIP, "read list lengths");
         const int s = c->C == 8;
-        for (int ci = 0; ci < m.nclusters; ++ci) items[s].push_back({cnt[ci], make_int2(b, ci)});
-        bt->nentries += m.nentries;
-        bt->evaluated += m.nentries * (int64_t)c->C * c->C;
+        int64_t ne = 0;
+        for (int ci = 0; ci < m.nclusters; ++ci) {
+            items[s].push_back({cnt[ci], make_int2(b, ci)});
+            ne += cnt[ci];
+        }
+        bt->nentries += ne;
+        bt->evaluated += ne * (int64_t)c->C * NB_JG;
     }
     for (int s = 0; s < 2; ++s) {
         if (bt->sorted)
@@ -436,8 +456,26 @@ int nb_batch_pairlist(nb_batch *bt, const float *x) {
         for (size_t k = 0; k < flat.size(); ++k) flat[k] = items[s][k].second;
         bt->nitems[s] = (int)flat.size();
         if (bt->nitems[s] > bt->item_cap[s]) return bfail(bt, NB_ERR_OVERFLOW, "work list capacity");
+        // guided chunks: each takes about 1/(2W) of the remaining cost (j-entries plus one batch
+        // of per-cluster overhead per item), at least one item
+        std::vector<int> chunks(1, 0);
+        double remaining = 0.0;
+        for (const auto &it : items[s]) remaining += it.first + NB_JPB;
+        const double waves = 4.0 * std::max(bt->grid[s], 1);
+        double acc = 0.0, target = remaining / (2.0 * waves);
+        for (size_t k = 0; k < items[s].size(); ++k) {
+            acc += items[s][k].first + NB_JPB;
+            if (acc >= target || k + 1 == items[s].size()) {
+                chunks.push_back((int)k + 1);
+                remaining -= acc;
+                acc = 0.0;
+                target = remaining / (2.0 * waves);
+            }
+        }
+        bt->nchunks[s] = (int)chunks.size() - 1;
         if (!flat.empty() &&
-            hipMemcpy(bt->d_items[s], flat.data(), sizeof(int2) * flat.size(), hipMemcpyHostToDevice) != hipSuccess)
+            (hipMemcpy(bt->d_items[s], flat.data(), sizeof(int2) * flat.size(), hipMemcpyHostToDevice) != hipSuccess ||
+             hipMemcpy(bt->d_chunks[s], chunks.data(), sizeof(int) * chunks.size(), hipMemcpyHostToDevice) != hipSuccess))
             return bfail(bt, NB_ERR_HIP, "upload work list");
     }
     int r = upload_desc(bt);

@@ -10,41 +10,66 @@
 
 namespace {
 
-__global__ void k_bin(int n, const float *__restrict__ x, nb_geom g, float4 *__restrict__ off,
-                      float *__restrict__ xbuild, int *__restrict__ col, int *__restrict__ rank,
-                      int *__restrict__ colcount, nb_meta *meta) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    float xv[3], o[3], w[3];
-    bool fin = true;
-    for (int c = 0; c < 3; ++c) {
-        xv[c] = x[3 * i + c];
-        xbuild[3 * i + c] = xv[c];
-        if (!isfinite(xv[c])) {
-            fin = false;
-            xv[c] = 0.0f;
-        }
+#define NB_BIN_LDS_MAX 12288  // columns the per-block LDS histogram of k_bin holds
+
+// Wrap into the box, column index, rank inside the column.  With lds != 0 each block first
+// counts its atoms per column in LDS and then takes one global atomic per column it touched,
+// which keeps the global atomics few (atoms in input order are spatially coherent); the rank is
+// the block's base in the column plus the LDS rank.  The order inside a column is arbitrary
+// here: the column sort orders atoms by (z, index).
+__global__ void __launch_bounds__(256) k_bin(int n, const float *__restrict__ x, nb_geom g,
+                                             float4 *__restrict__ off, float *__restrict__ xbuild,
+                                             int *__restrict__ col, int *__restrict__ rank,
+                                             int *__restrict__ colcount, nb_meta *meta, int lds) {
+    extern __shared__ int hist[];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (lds) {
+        for (int k = threadIdx.x; k < g.ncol; k += blockDim.x) hist[k] = 0;
+        __syncthreads();
     }
-    if (!fin) atomicOr(&meta->flags, NB_F_NONFINITE);
-    for (int c = 0; c < 3; ++c) {
-        float L = g.L[c];
-        o[c] = -floorf(xv[c] / L) * L;
-        w[c] = xv[c] + o[c];
-        if (w[c] < 0.0f) {
-            o[c] += L;
-            w[c] = xv[c] + o[c];
+    int c = -1, lrank = 0;
+    if (i < n) {
+        float xv[3], o[3], w[3];
+        bool fin = true;
+        for (int d = 0; d < 3; ++d) {
+            xv[d] = x[3 * i + d];
+            xbuild[3 * i + d] = xv[d];
+            if (!isfinite(xv[d])) {
+                fin = false;
+                xv[d] = 0.0f;
+            }
         }
-        if (w[c] >= L) {
-            o[c] -= L;
-            w[c] = xv[c] + o[c];
+        if (!fin) atomicOr(&meta->flags, NB_F_NONFINITE);
+        for (int d = 0; d < 3; ++d) {
+            const float L = g.L[d];
+            o[d] = -floorf(xv[d] / L) * L;
+            w[d] = xv[d] + o[d];
+            if (w[d] < 0.0f) {
+                o[d] += L;
+                w[d] = xv[d] + o[d];
+            }
+            if (w[d] >= L) {
+                o[d] -= L;
+                w[d] = xv[d] + o[d];
+            }
         }
+        off[i] = make_float4(o[0], o[1], o[2], 0.0f);
+        const int cx = min(max((int)(w[0] * g.invw[0]), 0), g.ncx - 1);
+        const int cy = min(max((int)(w[1] * g.invw[1]), 0), g.ncy - 1);
+        c = cy * g.ncx + cx;
+        col[i] = c;
+        if (lds) lrank = atomicAdd(&hist[c], 1);
+        else rank[i] = atomicAdd(&colcount[c], 1);
     }
-    off[i] = make_float4(o[0], o[1], o[2], 0.0f);
-    int cx = min(max((int)(w[0] * g.invw[0]), 0), g.ncx - 1);
-    int cy = min(max((int)(w[1] * g.invw[1]), 0), g.ncy - 1);
-    int c = cy * g.ncx + cx;
-    col[i] = c;
-    rank[i] = atomicAdd(&colcount[c], 1);
+    if (lds) {
+        __syncthreads();
+        for (int k = threadIdx.x; k < g.ncol; k += blockDim.x) {
+            const int h = hist[k];
+            if (h) hist[k] = atomicAdd(&colcount[k], h);
+        }
+        __syncthreads();
+        if (i < n) rank[i] = hist[c] + lrank;
+    }
 }
 
 // Exclusive scans of column populations and of cluster counts ceil(n / C); one block.
@@ -195,17 +220,38 @@ __global__ void k_excl_slots(int nnz, const int *__restrict__ eidx, const int *_
     if (e < nnz) exs[e] = slot_of[eidx[e]];
 }
 
-#define NB_EXCL_REG 4  // exclusion partners held in registers per atom; more are looped over
+#define NB_QCAP 128       // candidate queue slots per wavefront
+#define NB_PART_MAX 256   // exclusion partners of one i-cluster held in LDS
+
+// Wave-local ordering of LDS writes before reads by other lanes of the same wavefront.
+__device__ __forceinline__ void nb_wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Mask bits (b * C + a) with b > a: the upper triangle kept for the self pair at t = 0.
+template <int C>
+__device__ __forceinline__ unsigned long long nb_triangle() {
+    unsigned long long m = 0ull;
+#pragma unroll
+    for (int b = 0; b < C; ++b)
+#pragma unroll
+        for (int a = 0; a < C; ++a)
+            if (b > a) m |= 1ull << (b * C + a);
+    return m;
+}
 
 // One wave per i-cluster.  For every periodic shift t whose image can reach the i-cluster's
-// bounding box within rlist, candidate j-clusters come from the columns overlapping the
-// dilated box; a candidate is kept under the half-list rule (cj > ci for any t; cj == ci only
-// for t = 0, with the upper triangle, or t lexicographically positive, which covers both images
-// +t and -t) if its bounding-box distance is below rlist and at least one unmasked atom pair
-// is within rlist.  Entries of one i-cluster are stored contiguously at jl[ci * cap], grouped by
-// shift.  The topology mask of a candidate is computed with one atom pair per lane (lane =
-// b * C + a); for C = 4 four candidates share a wavefront, for C = 8 four candidates are
-// processed per iteration so that their loads overlap.
+// bounding box within rlist, the clusters of the columns overlapping the dilated box are tested
+// one per lane (bounding-box distance below rlist and the half-list rule: cj > ci for any t;
+// cj == ci only for t = 0, with the upper triangle, or t lexicographically positive, which covers
+// both images +t and -t).  Passing candidates are appended, in order, to a per-wave queue in
+// LDS; every 64 queued candidates are evaluated one per lane: the topology mask (real atoms,
+// self triangle, exclusions looked up as slot numbers) and whether any unmasked atom pair is
+// within rlist at the build positions (atom-level prune), separately for each 4-atom j-group of
+// the candidate.  Kept group entries are written in queue order, so the entries of one
+// i-cluster are contiguous at jl[ci * cap] and grouped by shift.
 template <int C>
 __global__ void __launch_bounds__(256) k_search(nb_geom g, int cap, const int *__restrict__ colcl,
                                                 const float4 *__restrict__ bblo,
@@ -216,32 +262,107 @@ __global__ void __launch_bounds__(256) k_search(nb_geom g, int cap, const int *_
                                                 const int *__restrict__ exs,
                                                 int *__restrict__ icount,
                                                 nb_entry *__restrict__ jl, nb_meta *meta) {
-    constexpr int PAIRS = C * C;               // lanes per candidate
-    constexpr int PER_WAVE = NB_WAVE / PAIRS;  // candidates side by side (1 for C = 8, 4 for C = 4)
-    constexpr int UNROLL = 4 / PER_WAVE;       // candidate groups per iteration
+    __shared__ int q_cj[4][NB_QCAP], q_s[4][NB_QCAP];
+    __shared__ int part[4][NB_PART_MAX];  // (a << 24) | partner slot
     const int lane = threadIdx.x & (NB_WAVE - 1);
-    const int ci = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x / NB_WAVE) +
-                                                  threadIdx.x / NB_WAVE);
+    const int wv = threadIdx.x / NB_WAVE;
+    const int ci = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x / NB_WAVE) + wv);
     if (ci >= meta->nclusters) return;
     const float4 lo = bblo[ci], hi = bbhi[ci];
     const float rl = g.rl;
-    // this lane's pair within a candidate: i-atom a, j-atom b, candidate slot grp
-    const int a = lane % C, b = (lane / C) % C, grp = lane / PAIRS;
-    const float4 pi = xs[ci * C + a];
-    const bool ireal = pi.w > 0.0f;
-    int ex[NB_EXCL_REG];
-    int ne = 0, ebeg = 0;
+    // i-cluster atoms (wave-uniform)
+    float xi[C], yi[C], zi[C];
+    unsigned ireal = 0u;
 #pragma unroll
-    for (int k = 0; k < NB_EXCL_REG; ++k) ex[k] = -1;
-    if (ireal && eoff) {
-        const int ia = perm[ci * C + a];
-        ebeg = eoff[ia];
-        ne = eoff[ia + 1] - ebeg;
-#pragma unroll
-        for (int k = 0; k < NB_EXCL_REG; ++k)
-            if (k < ne) ex[k] = exs[ebeg + k];
+    for (int a = 0; a < C; ++a) {
+        const float4 p = xs[ci * C + a];
+        xi[a] = p.x;
+        yi[a] = p.y;
+        zi[a] = p.z;
+        if (p.w > 0.0f) ireal |= 1u << a;
     }
-    int count = 0;
+    // exclusion partners of the i-cluster atoms, as slots, into LDS
+    int npart = 0;
+    if (eoff) {
+        int ne = 0, eb = 0;
+        if (lane < C && ((ireal >> lane) & 1u)) {
+            const int ia = perm[ci * C + lane];
+            eb = eoff[ia];
+            ne = eoff[ia + 1] - eb;
+        }
+        // exclusive prefix of ne over lanes 0 .. C-1
+        int pre = 0;
+        for (int a = 0; a < C; ++a) {
+            const int na = __shfl(ne, a, NB_WAVE);
+            if (a < lane) pre += na;
+            npart += na;
+        }
+        npart = __builtin_amdgcn_readfirstlane(npart);
+        if (npart > NB_PART_MAX) {
+            if (lane == 0) atomicOr(&meta->flags, NB_F_OVERFLOW | NB_F_COLUMN);
+            npart = 0;
+        } else if (lane < C) {
+            for (int k = 0; k < ne; ++k) part[wv][pre + k] = (lane << 24) | exs[eb + k];
+        }
+        nb_wave_sync();
+    }
+    const unsigned long long tri = nb_triangle<C>();
+    int count = 0, nq = 0;
+
+    // evaluate queue slots 0 .. n-1 (n <= 64), one candidate per lane, and append kept entries
+    auto flush = [&](int n) {
+        bool keep0 = false, keep1 = false;
+        unsigned long long m = 0ull;
+        int cj = 0, s = 0;
+        if (lane < n) {
+            cj = q_cj[wv][lane];
+            s = q_s[wv][lane];
+            const float sx = nb_tx(s) * g.L[0], sy = nb_ty(s) * g.L[1], sz = nb_tz(s) * g.L[2];
+            float jx[C], jy[C], jz[C];
+            unsigned jreal = 0u;
+#pragma unroll
+            for (int b = 0; b < C; ++b) {
+                const float4 p = xs[cj * C + b];
+                jx[b] = p.x + sx;
+                jy[b] = p.y + sy;
+                jz[b] = p.z + sz;
+                if (p.w > 0.0f) jreal |= 1u << b;
+            }
+#pragma unroll
+            for (int b = 0; b < C; ++b)
+                if ((jreal >> b) & 1u) m |= (unsigned long long)ireal << (b * C);
+            if (cj == ci && s == NB_SHIFT_ZERO) m &= tri;
+            for (int k = 0; k < npart; ++k) {
+                const int pe = part[wv][k];
+                const int ps = pe & 0xffffff;
+                if (ps / C == cj) m &= ~(1ull << ((ps % C) * C + (pe >> 24)));
+            }
+            // atom-level prune per j-group (the whole cluster for C = 4, each half for C = 8)
+#pragma unroll
+            for (int b = 0; b < C; ++b) {
+#pragma unroll
+                for (int a = 0; a < C; ++a) {
+                    const float dx = xi[a] - jx[b], dy = yi[a] - jy[b], dz = zi[a] - jz[b];
+                    const bool in = (dx * dx + dy * dy + dz * dz < g.rl2) && ((m >> (b * C + a)) & 1ull);
+                    if (b < NB_JG) keep0 |= in;
+                    else keep1 |= in;
+                }
+            }
+        }
+        // kept groups in (lane, half) order: the list stays in queue order, grouped by shift
+        const unsigned long long k0 = __ballot(keep0), k1 = __ballot(keep1);
+        const unsigned below0 = __builtin_amdgcn_mbcnt_hi((unsigned)(k0 >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)k0, 0u));
+        const unsigned below1 = __builtin_amdgcn_mbcnt_hi((unsigned)(k1 >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)k1, 0u));
+        const int pos0 = count + (int)(below0 + below1);
+        nb_entry *out = jl + (size_t)ci * cap;
+        if (keep0 && pos0 < cap) out[pos0] = nb_make_entry(cj * (C / NB_JG), s, (uint32_t)m);
+        if (C == 8 && keep1) {
+            const int pos1 = pos0 + (keep0 ? 1 : 0);
+            if (pos1 < cap) out[pos1] = nb_make_entry(cj * 2 + 1, s, (uint32_t)(m >> 32));
+        }
+        count += __popcll(k0) + __popcll(k1);
+    };
+
     for (int s = 0; s < 27; ++s) {
         const int tx = nb_tx(s), ty = nb_ty(s), tz = nb_tz(s);
         const float sx = tx * g.L[0], sy = ty * g.L[1], sz = tz * g.L[2];
@@ -253,7 +374,6 @@ __global__ void __launch_bounds__(256) k_search(nb_geom g, int cap, const int *_
             continue;
         const int cx0 = max(0, (int)floorf(x0 * g.invw[0])), cx1 = min(g.ncx - 1, (int)floorf(x1 * g.invw[0]));
         const int cy0 = max(0, (int)floorf(y0 * g.invw[1])), cy1 = min(g.ncy - 1, (int)floorf(y1 * g.invw[1]));
-        const bool self_t0 = s == NB_SHIFT_ZERO;
         for (int cy = cy0; cy <= cy1; ++cy) {
             for (int cx = cx0; cx <= cx1; ++cx) {
                 const int col = cy * g.ncx + cx;
@@ -269,72 +389,46 @@ __global__ void __launch_bounds__(256) k_search(nb_geom g, int cap, const int *_
                         const float gz = gap(lo.z, hi.z, jlo.z + sz, jhi.z + sz);
                         cand = half && (gx * gx + gy * gy + gz * gz < g.rl2);
                     }
-                    unsigned long long bal = __ballot(cand);
-                    while (bal) {
-                        // up to 4 candidates: lane group grp (C = 4) or unrolled step u (C = 8)
-                        int cand_j[4];
-#pragma unroll
-                        for (int k = 0; k < 4; ++k) {
-                            cand_j[k] = -1;
-                            if (bal) {
-                                cand_j[k] = base + __ffsll((long long)bal) - 1;
-                                bal &= bal - 1;
-                            }
+                    const unsigned long long cbal = __ballot(cand);
+                    if (cbal == 0ull) continue;
+                    if (cand) {
+                        const int pos = nq + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(cbal >> 32),
+                                                                           __builtin_amdgcn_mbcnt_lo((unsigned)cbal, 0u));
+                        q_cj[wv][pos] = cjl;
+                        q_s[wv][pos] = s;
+                    }
+                    nq += __popcll(cbal);
+                    nb_wave_sync();
+                    if (nq >= NB_WAVE) {
+                        flush(NB_WAVE);
+                        // move the overflow (slots 64 .. nq-1) to the front
+                        const int rest = nq - NB_WAVE;
+                        int mc = 0, ms = 0;
+                        if (lane < rest) {
+                            mc = q_cj[wv][NB_WAVE + lane];
+                            ms = q_s[wv][NB_WAVE + lane];
                         }
-                        unsigned long long mk[4];
-                        bool anyk[4];
-#pragma unroll
-                        for (int u = 0; u < UNROLL; ++u) {
-                            const int cj = cand_j[u * PER_WAVE + grp];  // per lane group
-                            bool topo = false, near = false;
-                            if (cj >= 0) {
-                                const int jslot = cj * C + b;
-                                const float4 pj = xs[jslot];
-                                topo = ireal && pj.w > 0.0f;
-                                if (cj == ci && self_t0) topo = topo && (b > a);
-#pragma unroll
-                                for (int k = 0; k < NB_EXCL_REG; ++k) topo = topo && ex[k] != jslot;
-                                for (int k = NB_EXCL_REG; k < ne; ++k) topo = topo && exs[ebeg + k] != jslot;
-                                const float dx = pi.x - (pj.x + sx);
-                                const float dy = pi.y - (pj.y + sy);
-                                const float dz = pi.z - (pj.z + sz);
-                                near = dx * dx + dy * dy + dz * dz < g.rl2;
-                            }
-                            const unsigned long long bt = __ballot(topo);
-                            const unsigned long long bn = __ballot(topo && near);
-#pragma unroll
-                            for (int p = 0; p < PER_WAVE; ++p) {
-                                const int slotk = u * PER_WAVE + p;
-                                const unsigned long long sel =
-                                    PAIRS == 64 ? ~0ull : (((1ull << PAIRS) - 1ull) << (p * PAIRS));
-                                mk[slotk] = (bt & sel) >> (p * PAIRS);
-                                anyk[slotk] = (bn & sel) != 0ull;
-                            }
+                        nb_wave_sync();
+                        if (lane < rest) {
+                            q_cj[wv][lane] = mc;
+                            q_s[wv][lane] = ms;
                         }
-#pragma unroll
-                        for (int k = 0; k < 4; ++k) {
-                            if (cand_j[k] >= 0 && anyk[k]) {
-                                if (count < cap && lane == 0) {
-                                    nb_entry e;
-                                    e.cj = cand_j[k];
-                                    e.shift = s;
-                                    e.mlo = (uint32_t)mk[k];
-                                    e.mhi = (uint32_t)(mk[k] >> 32);
-                                    jl[(size_t)ci * cap + count] = e;
-                                }
-                                ++count;
-                            }
-                        }
+                        nq = rest;
+                        nb_wave_sync();
                     }
                 }
             }
         }
     }
+    if (nq > 0) flush(nq);
+    // No per-wave atomics on shared counters (they serialise across the whole grid): only an
+    // overflowing i-cluster touches meta; list totals are summed from icount on request.
     if (lane == 0) {
         icount[ci] = min(count, cap);
-        if (count > cap) atomicOr(&meta->flags, NB_F_OVERFLOW);
-        atomicMax(&meta->maxcount, count);
-        atomicAdd((unsigned long long *)&meta->nentries, (unsigned long long)min(count, cap));
+        if (count > cap) {
+            atomicOr(&meta->flags, NB_F_OVERFLOW);
+            atomicMax(&meta->maxcount, count);
+        }
     }
 }
 
@@ -349,27 +443,27 @@ __global__ void __launch_bounds__(256) k_pairs(nb_geom g, float rc2, int cap,
                                                const nb_meta *meta,
                                                unsigned long long *counter, int64_t outcap,
                                                int64_t *__restrict__ out) {
-    constexpr int JPB = NB_WAVE / C;  // j-clusters per batch
     const int lane = threadIdx.x & (NB_WAVE - 1);
     const int ci = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x / NB_WAVE) +
                                                   threadIdx.x / NB_WAVE);
     if (ci >= meta->nclusters) return;
     const int nj = icount[ci];
-    const int b = lane % C;
-    for (int base = 0; base < nj; base += JPB) {
-        const int e = base + lane / C;
+    const int b = lane % NB_JG;
+    for (int base = 0; base < nj; base += NB_JPB) {
+        const int e = base + lane / NB_JG;
         if (e >= nj) continue;
         const nb_entry en = jl[(size_t)ci * cap + e];
-        const int s = en.shift;
+        const int s = nb_entry_shift(en);
         const int tx = nb_tx(s), ty = nb_ty(s), tz = nb_tz(s);
-        const float4 xj = xq[en.cj * C + b];
+        const int jslot = nb_entry_group(en) * NB_JG + b;
+        const float4 xj = xq[jslot];
         const float xjs = xj.x + nb_dj(tx, g.L[0]), yjs = xj.y + nb_dj(ty, g.L[1]),
                     zjs = xj.z + nb_dj(tz, g.L[2]);
         const float dix = nb_di(tx, g.L[0]), diy = nb_di(ty, g.L[1]), diz = nb_di(tz, g.L[2]);
-        const unsigned long long m = ((unsigned long long)en.mhi << 32) | en.mlo;
-        const int jb = perm[en.cj * C + b];
+        const unsigned mcol = nb_mask_column<C>(en.mask, b);
+        const int jb = perm[jslot];
         for (int k = 0; k < C; ++k) {
-            if (!((m >> (b * C + k)) & 1ull)) continue;
+            if (!((mcol >> k) & 1u)) continue;
             const float4 xi = xq[ci * C + k];
             float dx = (xi.x + dix) - xjs, dy = (xi.y + diy) - yjs, dz = (xi.z + diz) - zjs;
             float r2 = nb_r2(dx, dy, dz);
@@ -391,12 +485,16 @@ hipError_t build_impl(nb_ctx *c, const float *x) {
     const int tb = 256;
     hipMemsetAsync(c->colcount, 0, sizeof(int) * c->geom.ncol, c->stream);
     hipMemsetAsync(c->meta, 0, sizeof(nb_meta), c->stream);
-    hipLaunchKernelGGL(k_bin, dim3((n + tb - 1) / tb), dim3(tb), 0, c->stream, n, x, c->geom,
-                       c->off, c->xbuild, c->col, c->rank, c->colcount, c->meta);
+    const int lds = c->geom.ncol <= NB_BIN_LDS_MAX;
+    hipLaunchKernelGGL(k_bin, dim3((n + tb - 1) / tb), dim3(tb), lds ? sizeof(int) * c->geom.ncol : 0,
+                       c->stream, n, x, c->geom, c->off, c->xbuild, c->col, c->rank, c->colcount,
+                       c->meta, lds);
     hipLaunchKernelGGL(k_colscan, dim3(1), dim3(1024), 0, c->stream, c->geom.ncol, C, c->colcount,
                        c->colstart, c->colcl, c->meta);
     hipLaunchKernelGGL(k_scatter, dim3((n + tb - 1) / tb), dim3(tb), 0, c->stream, n, c->col,
                        c->rank, c->colstart, c->tmp);
+    // every slot the per-call pack visits is either written by the column sort or padding
+    hipMemsetAsync(c->perm, 0xff, sizeof(int) * c->npad_max, c->stream);
     hipLaunchKernelGGL((k_colsort<C>), dim3(c->geom.ncol), dim3(256), 0, c->stream, x, c->off,
                        c->colcount, c->colstart, c->colcl, c->tmp, c->perm, c->slot_of, c->xs,
                        c->meta);

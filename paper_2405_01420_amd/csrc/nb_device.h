@@ -37,10 +37,23 @@ __device__ __forceinline__ float nb_rcp(float x) {
     return __builtin_fmaf(y, e, y);
 }
 
-// The C mask bits of j-atom b (bit k: i-atom k interacts with j-atom b).
+// Global-memory (address space 1) pointers.  Pointers that the force body receives from a
+// descriptor in memory would otherwise be generic, and every access through them a flat
+// instruction; typed as global, the accesses compile to global loads, stores and atomics.
+#define NB_G __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ const NB_G T *nb_g(const T *p) { return (const NB_G T *)p; }
+template <class T>
+__device__ __forceinline__ NB_G T *nb_g(T *p) { return (NB_G T *)p; }
+template <class T>
+__device__ __forceinline__ T nb_ld(const NB_G T *p) { return *(const T *)p; }
+template <class T>
+__device__ __forceinline__ void nb_st(NB_G T *p, const T &v) { *(T *)p = v; }
+
+// The C mask bits of j-atom b of an entry (bit k: i-atom k interacts with j-atom b).
 template <int C>
-__device__ __forceinline__ unsigned nb_mask_column(unsigned long long m, int b) {
-    return (unsigned)(m >> (b * C)) & ((1u << C) - 1u);
+__device__ __forceinline__ unsigned nb_mask_column(uint32_t m, int b) {
+    return (m >> (b * C)) & ((1u << C) - 1u);
 }
 
 // Sum of v over the 64 lanes, valid in lane 63 only: butterfly within each 16-lane row with

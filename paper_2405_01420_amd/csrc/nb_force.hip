@@ -5,17 +5,23 @@
 // This is the computation the paper identifies as the single-GPU rate limiter (section III-A;
 // the flavour named in the Fig. 3 caption).  The per-cluster body and its lane layout are in
 // nb_force_body.h; here one wavefront is launched per i-cluster.
+#include <algorithm>
+
 #include "nb_force_body.h"
 
 namespace {
+
+#define NB_FIN_BLOCK 512
 
 __global__ void k_pack(int npad_max, const int *__restrict__ perm, const float *__restrict__ x,
                        const float *__restrict__ q, const int32_t *__restrict__ type, int ntypes,
                        const float4 *__restrict__ off, const float *__restrict__ xbuild,
                        uint32_t checks, float stale2, float4 *__restrict__ xq,
                        int *__restrict__ tsort, float *__restrict__ fj, nb_meta *meta) {
+    // slots past the current grid's padded count hold perm = -1 (set at every build), so all
+    // npad_max slots are visited without waiting for the grid size
     int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= npad_max || p >= meta->npad) return;
+    if (p >= npad_max) return;
     int a = perm[p];
     if (a >= 0) {
         float x0 = x[3 * a], x1 = x[3 * a + 1], x2 = x[3 * a + 2];
@@ -52,7 +58,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 template <int C, bool EPREC>
-__global__ void __launch_bounds__(256) k_force(nb_fparams fp, int cap, int npad_max,
+__global__ void __launch_bounds__(256) NB_FORCE_OCCUPANCY k_force(nb_fparams fp, int cap, int npad_max,
                                                const float4 *__restrict__ xq,
                                                const int *__restrict__ tsort,
                                                const float4 *__restrict__ ljtab,
@@ -77,52 +83,58 @@ __global__ void __launch_bounds__(256) k_force(nb_fparams fp, int cap, int npad_
     const int ci = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x / NB_WAVE) +
                                                   threadIdx.x / NB_WAVE);
     if (ci >= meta->nclusters) return;
-    nb_force_cluster<C, EPREC>(fp, tab, et, ci, cap, npad_max, xq, tsort, icount, jl, fi_out, fj, epart);
+    nb_force_cluster<C, EPREC>(fp, tab, et, ci, cap, npad_max, nb_g(xq), nb_g(tsort), nb_g(icount),
+                               nb_g(jl), nb_g(fi_out), nb_g(fj), nb_g(epart));
 }
 
-__global__ void k_finalize(int n, int npad_max, const int *__restrict__ slot_of,
-                           const float4 *__restrict__ fi, const float *__restrict__ fj,
-                           float *__restrict__ f) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int p = slot_of[i];
-    float4 a = fi[p];
-    f[3 * i] = a.x + fj[p];
-    f[3 * i + 1] = a.y + fj[npad_max + p];
-    f[3 * i + 2] = a.z + fj[2 * npad_max + p];
-}
-
-// FP64 sum of the per-cluster energy partials; the Coulomb shift is applied here.
-__global__ void __launch_bounds__(1024) k_energy(const nb_meta *meta, const double *__restrict__ epart,
-                                                  double shift_coul, double coul_scale,
-                                                  double *__restrict__ e) {
-    __shared__ double s[3][1024 / NB_WAVE];
-    const int ncl = meta->nclusters;
-    double a = 0.0, b = 0.0, c = 0.0;
-    for (int k = threadIdx.x; k < ncl; k += blockDim.x) {
-        a += epart[4 * k];
-        b += epart[4 * k + 1];
-        c += epart[4 * k + 2];
+// f[atom] = f_i + f_j in original order, and the FP64 energy sums.  Block 0 additionally adds
+// the per-cluster energy partials in a fixed order (strided per thread, then the wave and block
+// trees) and applies the Coulomb shift; it is dispatched first, so this runs beside the other
+// blocks' force gathers and needs no inter-block synchronisation.
+__global__ void __launch_bounds__(NB_FIN_BLOCK) k_finalize(int n, int npad_max,
+                                                           const int *__restrict__ slot_of,
+                                                           const float4 *__restrict__ fi,
+                                                           const float *__restrict__ fj,
+                                                           float *__restrict__ f, const nb_meta *meta,
+                                                           const double *__restrict__ epart,
+                                                           double shift_coul, double coul_scale,
+                                                           double *__restrict__ e) {
+    __shared__ double s[3][NB_FIN_BLOCK / NB_WAVE];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        const int p = slot_of[i];
+        const float4 a = fi[p];
+        f[3 * i] = a.x + fj[p];
+        f[3 * i + 1] = a.y + fj[npad_max + p];
+        f[3 * i + 2] = a.z + fj[2 * npad_max + p];
     }
-    a = wave_sum(a);
-    b = wave_sum(b);
-    c = wave_sum(c);
+    if (blockIdx.x != 0) return;
+    const int ncl = meta->nclusters;
+    double x = 0.0, y = 0.0, z = 0.0;
+    for (int k = threadIdx.x; k < ncl; k += blockDim.x) {
+        x += epart[4 * k];
+        y += epart[4 * k + 1];
+        z += epart[4 * k + 2];
+    }
+    x = nb_wave_sum_d(x);
+    y = nb_wave_sum_d(y);
+    z = nb_wave_sum_d(z);
     const int w = threadIdx.x / NB_WAVE;
     if ((threadIdx.x & (NB_WAVE - 1)) == 0) {
-        s[0][w] = a;
-        s[1][w] = b;
-        s[2][w] = c;
+        s[0][w] = x;
+        s[1][w] = y;
+        s[2][w] = z;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double ta = 0.0, tb = 0.0, tc = 0.0;
-        for (int k = 0; k < (int)(blockDim.x / NB_WAVE); ++k) {
-            ta += s[0][k];
-            tb += s[1][k];
-            tc += s[2][k];
+        double tx = 0.0, ty = 0.0, tz = 0.0;
+        for (int k = 0; k < NB_FIN_BLOCK / NB_WAVE; ++k) {
+            tx += s[0][k];
+            ty += s[1][k];
+            tz += s[2][k];
         }
-        e[0] = ta;
-        e[1] = coul_scale * (tb - shift_coul * tc);
+        e[0] = tx;
+        e[1] = coul_scale * (ty - shift_coul * tz);
     }
 }
 
@@ -160,10 +172,9 @@ hipError_t nb_launch_force(nb_ctx *c) {
 }
 
 hipError_t nb_launch_finalize(nb_ctx *c, float *f, double *e) {
-    const int tb = 256;
-    hipLaunchKernelGGL(k_finalize, dim3((c->natoms + tb - 1) / tb), dim3(tb), 0, c->stream,
-                       c->natoms, c->npad_max, c->slot_of, c->fi, c->fj, f);
-    hipLaunchKernelGGL(k_energy, dim3(1), dim3(1024), 0, c->stream, c->meta, c->epart,
+    const int nblk = std::max(1, (c->natoms + NB_FIN_BLOCK - 1) / NB_FIN_BLOCK);
+    hipLaunchKernelGGL(k_finalize, dim3(nblk), dim3(NB_FIN_BLOCK), 0, c->stream, c->natoms,
+                       c->npad_max, c->slot_of, c->fi, c->fj, f, c->meta, c->epart,
                        c->shift_coul, (c->flags & NB_ENERGY_FP64) ? c->fc : 1.0, e);
     return hipGetLastError();
 }

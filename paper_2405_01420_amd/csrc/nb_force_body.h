@@ -3,9 +3,9 @@
 // wavefront):
 //  * one wavefront per i-cluster; the C i-atoms are wave-uniform values, so every i-coordinate
 //    is a scalar operand of the vector instructions;
-//  * each lane owns one j-atom of one of the 64 / C j-clusters of the current batch and loops
-//    over the C i-atoms, so the j-force of the lane's atom accumulates in registers and needs
-//    one atomic add per component per batch (the only atomics);
+//  * each lane owns one j-atom of one of the 16 four-atom j-groups of the current batch and
+//    loops over the C i-atoms, so the j-force of the lane's atom accumulates in registers and
+//    needs one atomic add per component per batch (the only atomics);
 //  * batches whose entries share one periodic shift (the common case, since the list is grouped
 //    by shift) use i-coordinates moved into that frame once and cached in scalar registers;
 //    batches with no excluded or padding pair skip the mask test;
@@ -14,7 +14,8 @@
 //  * erfc(beta r) = exp(-beta^2 r^2) P(r) / Q(r) with a (4,5) rational fit of the scaled
 //    complementary error function (fit_erfcx.py), Newton-refined reciprocal square root and
 //    reciprocal;
-//  * per-pair energies are rounded once to FP32 and accumulated in FP64; the Coulomb potential
+//  * per-pair energies are summed in FP32 over the C pairs of a lane's batch and accumulated in
+//    FP64 from there on; the Coulomb potential
 //    shift is applied in FP64 at the end from the sum of q_i q_j over interacting pairs;
 //  * with EPREC the Coulomb pair energy is instead evaluated in FP64 (exact displacement,
 //    Newton-refined 1/r, erfc from an FP64 cubic Hermite table), forces staying FP32: the FP32
@@ -22,6 +23,11 @@
 //    energy that is a 4e-4-conditioned sum, in boxes of a few thousand atoms.
 #pragma once
 #include "nb_device.h"
+
+// Four waves per SIMD (at most 128 VGPRs) for the force kernels: the FP32 C = 8 body needs
+// about that many, and the compiler's unconstrained choice lands just above, at three waves.
+// The FP64-energy variant is register-bound either way and is left to the compiler.
+#define NB_FORCE_OCCUPANCY __attribute__((amdgpu_waves_per_eu(EPREC ? 1 : 4)))
 
 __device__ __forceinline__ double nb_wave_sum_d(double v) {
 #pragma unroll
@@ -55,7 +61,11 @@ __device__ __forceinline__ void pair_block(const nb_fparams &fp, const float4 *t
                                            const nb_etab &et, const float *xs, const float *ys,
                                            const float *zs, const float *qi, const int *ti,
                                            nb_jlane &j, float *fix, float *fiy, float *fiz,
-                                           double &elj, double &ec, double &qqs) {
+                                           double &elj, double &ec, float &qqs, double &qqsd,
+                                           float p4v, float q5v) {
+    // FP32 partial sums of the batch's C pair energies, added to the FP64 sums once per batch
+    // (starting from -0 lets the first addition fold away)
+    float eljb = -0.0f, ecb = -0.0f;
 #pragma unroll
     for (int k = 0; k < C; ++k) {
         const float dx = xs[k] - j.x;
@@ -66,35 +76,34 @@ __device__ __forceinline__ void pair_block(const nb_fparams &fp, const float4 *t
         const float rinv = inc ? nb_rsq(r2) : 0.0f;
         const float rinv2 = rinv * rinv;
         const float rinv6 = rinv2 * rinv2 * rinv2;
-        const float4 lj = tab[ti[k] + j.t];   // (C6, C12, 6 C6, 12 C12)
-        const float shv = tab[ntt + ti[k] + j.t].x;
-        const float m1 = inc ? 1.0f : 0.0f;
+        const float4 *ljp = tab + 2 * (ti[k] + j.t);
+        const float4 lj = ljp[0];             // (C6, C12, 6 C6, 12 C12)
+        const float shv = ljp[1].x;
         // Lennard-Jones: energy C12 r^-12 - C6 r^-6 - shift, force factor (12 C12 r^-6 - 6 C6) r^-8
         const float u = __builtin_fmaf(lj.y, rinv6, -lj.x);
-        const float elj_p = __builtin_fmaf(u, rinv6, -m1 * shv);
+        const float elj_p = inc ? __builtin_fmaf(u, rinv6, -shv) : 0.0f;
         const float tf = __builtin_fmaf(lj.w, rinv6, -lj.z);
         const float flj = tf * rinv6;
         // Ewald real space: erfc(beta r) = exp(-beta^2 r^2) P(r) / Q(r)
         const float r = r2 * rinv;
         const float ex = __builtin_amdgcn_exp2f(fp.cexp * r2);
-        float P = fp.p[4];
-        P = __builtin_fmaf(P, r, fp.p[3]);
+        float P = __builtin_fmaf(p4v, r, fp.p[3]);
         P = __builtin_fmaf(P, r, fp.p[2]);
         P = __builtin_fmaf(P, r, fp.p[1]);
         P = __builtin_fmaf(P, r, fp.p[0]);
-        float Q = fp.q[5];
-        Q = __builtin_fmaf(Q, r, fp.q[4]);
+        float Q = __builtin_fmaf(q5v, r, fp.q[4]);
         Q = __builtin_fmaf(Q, r, fp.q[3]);
         Q = __builtin_fmaf(Q, r, fp.q[2]);
         Q = __builtin_fmaf(Q, r, fp.q[1]);
         Q = __builtin_fmaf(Q, r, fp.q[0]);
+        // refined reciprocal: the raw one's error pattern follows Q(r) and does not average out
         const float R = P * nb_rcp(Q);
         const float qq = qi[k] * j.q;             // fC q_i q_j
         const float qe = qq * ex;
         const float t1 = qe * rinv;               // fC q_i q_j exp(-b^2 r^2) / r
         const float uu = __builtin_fmaf(fp.kb, r, R);
         const float fs = __builtin_fmaf(t1, uu, flj) * rinv2;
-        elj += (double)elj_p;
+        eljb += elj_p;
         if (EPREC) {
             // Coulomb pair energy in FP64 without fC: exact displacement, 1/r refined in FP64,
             // erfc(beta r) from the FP64 Hermite table (segment found with the FP32 r)
@@ -113,11 +122,10 @@ __device__ __forceinline__ void pair_block(const nb_fparams &fp, const float4 *t
             const double g = __builtin_fma(__builtin_fma(__builtin_fma(c23.y, u, c23.x), u, c01.y), u, c01.x);
             const double qqd = (double)qi[k] * j.qd;
             ec = __builtin_fma(qqd * g, rid, ec);
-            qqs = __builtin_fma((double)m1, qqd, qqs);
+            qqsd += inc ? qqd : 0.0;
         } else {
-            const float ec_p = t1 * R;            // fC q_i q_j erfc(b r) / r
-            ec += (double)ec_p;
-            qqs += (double)(m1 * qq);
+            ecb = __builtin_fmaf(t1, R, ecb);     // += fC q_i q_j erfc(b r) / r
+            qqs += inc ? qq : 0.0f;
         }
         fix[k] = __builtin_fmaf(fs, dx, fix[k]);
         fiy[k] = __builtin_fmaf(fs, dy, fiy[k]);
@@ -126,6 +134,8 @@ __device__ __forceinline__ void pair_block(const nb_fparams &fp, const float4 *t
         j.fy = __builtin_fmaf(-fs, dy, j.fy);
         j.fz = __builtin_fmaf(-fs, dz, j.fz);
     }
+    elj += (double)eljb;
+    if (!EPREC) ec += (double)ecb;
 }
 
 __device__ __forceinline__ float nb_uniform(float v) {
@@ -139,29 +149,28 @@ template <int C, bool EPREC>
 __device__ __forceinline__ void nb_force_cluster(const nb_fparams &fp, const float4 *tab,
                                                  const nb_etab &et, int ci,
                                                  int cap, int npad_max,
-                                                 const float4 *__restrict__ xq,
-                                                 const int *__restrict__ tsort,
-                                                 const int *__restrict__ icount,
-                                                 const nb_entry *__restrict__ jl,
-                                                 float4 *__restrict__ fi_out,
-                                                 float *__restrict__ fj,
-                                                 double *__restrict__ epart) {
-    constexpr int JPB = NB_WAVE / C;  // j-clusters per batch
+                                                 const NB_G float4 *__restrict__ xq,
+                                                 const NB_G int *__restrict__ tsort,
+                                                 const NB_G int *__restrict__ icount,
+                                                 const NB_G nb_entry *__restrict__ jl,
+                                                 NB_G float4 *__restrict__ fi_out,
+                                                 NB_G float *__restrict__ fj,
+                                                 NB_G double *__restrict__ epart) {
     constexpr unsigned FULL = (1u << C) - 1u;
     const int nt = fp.ntypes, ntt = nt * nt;
     const int lane = threadIdx.x & (NB_WAVE - 1);
-    const int b = lane % C, jsub = lane / C;
+    const int b = lane % NB_JG, jsub = lane / NB_JG;  // j-atom within the group, entry in batch
 
     float xi[C], yi[C], zi[C], qi[C], xs[C], ys[C], zs[C];
     int ti[C];
 #pragma unroll
     for (int k = 0; k < C; ++k) {
-        const float4 v = xq[ci * C + k];
+        const float4 v = nb_ld(xq + ci * C + k);
         xi[k] = v.x;
         yi[k] = v.y;
         zi[k] = v.z;
         qi[k] = nb_uniform(v.w);
-        ti[k] = tsort[ci * C + k] * nt;
+        ti[k] = nb_ld(tsort + ci * C + k) * nt;
         xs[k] = xi[k];
         ys[k] = yi[k];
         zs[k] = zi[k];
@@ -170,29 +179,30 @@ __device__ __forceinline__ void nb_force_cluster(const nb_fparams &fp, const flo
     float fix[C], fiy[C], fiz[C];
 #pragma unroll
     for (int k = 0; k < C; ++k) fix[k] = fiy[k] = fiz[k] = 0.0f;
-    double elj = 0.0, ec = 0.0, qqs = 0.0;
+    double elj = 0.0, ec = 0.0, qqsd = 0.0;  // qqsd: FP64-energy mode sum of q_i q_j
+    float qqs = 0.0f;                        // FP32 mode: sum of fC q_i q_j (shift weight)
 
-    const int nj = icount[ci];
-    const nb_entry *lst = jl + (size_t)ci * cap;
-    for (int base = 0; base < nj; base += JPB) {
+    // the leading coefficients of the erfcx numerator and denominator live in vector registers
+    // for the whole list: the first Horner step then reads one scalar register, which is all a
+    // VOP3 instruction can take, instead of copying a constant into a VGPR for every pair
+    float p4v, q5v;
+    asm("v_mov_b32 %0, %1" : "=v"(p4v) : "s"(fp.p[4]));
+    asm("v_mov_b32 %0, %1" : "=v"(q5v) : "s"(fp.q[5]));
+    const int nj = nb_ld(icount + ci);
+    const NB_G nb_entry *lst = jl + (size_t)ci * cap;
+    for (int base = 0; base < nj; base += NB_JPB) {
         const int e = base + jsub;
         const bool valid = e < nj;
-        nb_entry en;
-        if (valid) {
-            en = lst[e];
-        } else {
-            en.cj = ci;
-            en.shift = NB_SHIFT_ZERO;
-            en.mlo = en.mhi = 0u;
-        }
-        const int s = en.shift;
-        const int jslot = en.cj * C + b;
-        const float4 xj = xq[jslot];
+        // lanes past the end of the list read the i-cluster's own first group with an empty mask
+        const nb_entry en = valid ? nb_ld(lst + e) : nb_make_entry(ci * (C / NB_JG), NB_SHIFT_ZERO, 0u);
+        const int s = nb_entry_shift(en);
+        const int jslot = nb_entry_group(en) * NB_JG + b;
+        const float4 xj = nb_ld(xq + jslot);
         nb_jlane jv;
         jv.q = xj.w * fp.fc;
         jv.qd = (double)xj.w;
-        jv.t = tsort[jslot];
-        jv.mcol = nb_mask_column<C>(((unsigned long long)en.mhi << 32) | en.mlo, b);
+        jv.t = nb_ld(tsort + jslot);
+        jv.mcol = nb_mask_column<C>(en.mask, b);
         jv.fx = jv.fy = jv.fz = 0.0f;
         const int s0 = __builtin_amdgcn_readfirstlane(s);
         const bool uniform = __ballot(valid && s != s0) == 0ull;
@@ -219,9 +229,9 @@ __device__ __forceinline__ void nb_force_cluster(const nb_fparams &fp, const flo
             }
             const bool full = __ballot(!valid || jv.mcol != FULL) == 0ull;
             if (full)
-                pair_block<C, false, EPREC>(fp, tab, ntt, et, xs, ys, zs, qi, ti, jv, fix, fiy, fiz, elj, ec, qqs);
+                pair_block<C, false, EPREC>(fp, tab, ntt, et, xs, ys, zs, qi, ti, jv, fix, fiy, fiz, elj, ec, qqs, qqsd, p4v, q5v);
             else
-                pair_block<C, true, EPREC>(fp, tab, ntt, et, xs, ys, zs, qi, ti, jv, fix, fiy, fiz, elj, ec, qqs);
+                pair_block<C, true, EPREC>(fp, tab, ntt, et, xs, ys, zs, qi, ti, jv, fix, fiy, fiz, elj, ec, qqs, qqsd, p4v, q5v);
         } else {
             // shifts differ across the batch: per-lane frame offsets
             const int tx = nb_tx(s), ty = nb_ty(s), tz = nb_tz(s);
@@ -241,12 +251,12 @@ __device__ __forceinline__ void nb_force_cluster(const nb_fparams &fp, const flo
                 yl[k] = yi[k] + diy;
                 zl[k] = zi[k] + diz;
             }
-            pair_block<C, true, EPREC>(fp, tab, ntt, et, xl, yl, zl, qi, ti, jv, fix, fiy, fiz, elj, ec, qqs);
+            pair_block<C, true, EPREC>(fp, tab, ntt, et, xl, yl, zl, qi, ti, jv, fix, fiy, fiz, elj, ec, qqs, qqsd, p4v, q5v);
         }
         if (valid) {
-            atomicAdd(&fj[jslot], jv.fx);
-            atomicAdd(&fj[npad_max + jslot], jv.fy);
-            atomicAdd(&fj[2 * npad_max + jslot], jv.fz);
+            atomicAdd((float *)(fj + jslot), jv.fx);
+            atomicAdd((float *)(fj + npad_max + jslot), jv.fy);
+            atomicAdd((float *)(fj + 2 * npad_max + jslot), jv.fz);
         }
     }
 #pragma unroll
@@ -257,12 +267,12 @@ __device__ __forceinline__ void nb_force_cluster(const nb_fparams &fp, const flo
     }
     elj = nb_wave_sum_d(elj);
     ec = nb_wave_sum_d(ec);
-    const double qqd = nb_wave_sum_d(qqs);
+    const double qqd = nb_wave_sum_d(EPREC ? qqsd : (double)qqs);
     if (lane == NB_WAVE - 1) {
 #pragma unroll
-        for (int k = 0; k < C; ++k) fi_out[ci * C + k] = make_float4(fix[k], fiy[k], fiz[k], 0.0f);
-        epart[4 * ci] = elj;
-        epart[4 * ci + 1] = ec;
-        epart[4 * ci + 2] = qqd;
+        for (int k = 0; k < C; ++k) nb_st(fi_out + ci * C + k, make_float4(fix[k], fiy[k], fiz[k], 0.0f));
+        nb_st(epart + 4 * ci, elj);
+        nb_st(epart + 4 * ci + 1, ec);
+        nb_st(epart + 4 * ci + 2, qqd);
     }
 }

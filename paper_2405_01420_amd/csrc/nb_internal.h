@@ -20,26 +20,37 @@
 #define NB_F_NONFINITE 0x4u
 #define NB_F_COLUMN 0x8u
 
-// One j-entry of the cluster-pair list: j-cluster, periodic shift of the j image
-// (x_j + t L) and the topology mask: bit (b * C + a) set iff atom a of the i-cluster and atom
-// b of the j-cluster are both real, distinct, not excluded and, for the self pair at t = 0,
-// b > a.  The mask is column-major so that the lane holding j-atom b extracts its C bits with
-// one shift.  Distances are not part of the mask.
+// One j-entry of the cluster-pair list.  The j side of every entry is a group of NB_JG = 4
+// consecutive slots: a whole cluster when C = 4, one half (lower or upper four in z order) of
+// a cluster when C = 8, so an 8-atom i-cluster meets 4-atom j-groups (8 x 4 pairs per entry)
+// and half-clusters with no atom pair in range are not listed.  gs packs the group index and
+// the periodic shift of the j image (x_j + t L); mask bit (b * C + a) is set iff i-atom a and
+// j-atom b of the group are both real, distinct, not excluded and, for the self pair at t = 0,
+// in increasing slot order.  The mask is column-major so that the lane holding j-atom b
+// extracts its C bits with one shift.  Distances are not part of the mask.
+#define NB_JG 4
+#define NB_JPB (NB_WAVE / NB_JG)  // entries per batch of 64 lanes
 struct nb_entry {
-    int32_t cj;
-    int32_t shift;
-    uint32_t mlo, mhi;
+    uint32_t gs;    // (j-group << 5) | shift index
+    uint32_t mask;
 };
+__host__ __device__ __forceinline__ int nb_entry_group(const nb_entry &e) { return (int)(e.gs >> 5); }
+__host__ __device__ __forceinline__ int nb_entry_shift(const nb_entry &e) { return (int)(e.gs & 31u); }
+__host__ __device__ __forceinline__ nb_entry nb_make_entry(int group, int shift, uint32_t mask) {
+    nb_entry e;
+    e.gs = ((uint32_t)group << 5) | (uint32_t)shift;
+    e.mask = mask;
+    return e;
+}
 
 // Counters written by the GPU during a build (read back by the host only when needed).
 struct nb_meta {
     int32_t nclusters;   // clusters of the current grid
     int32_t npad;        // nclusters * C
     uint32_t flags;      // NB_F_*
-    int32_t maxcount;    // largest j-entry count of any i-cluster (for regrowing)
+    int32_t maxcount;    // largest j-entry count of an overflowing i-cluster (for regrowing)
     int32_t maxcolumn;   // largest column population
     int32_t pad0;
-    int64_t nentries;    // total j-entries
     uint64_t npairs_out; // pair-export counter
 };
 
@@ -60,6 +71,8 @@ struct nb_fparams {
     float fc;           // Coulomb constant
     float cexp;         // -beta^2 log2(e):  exp(-beta^2 r^2) = exp2(cexp r^2)
     float kb;           // 2 beta / sqrt(pi)
+    // LJ table in LDS/global: per type pair (a * ntypes + b) two float4,
+    // (C6, C12, 6 C6, 12 C12) and (potential shift, 1 / sigma_ab, 0, 0)
     float p[5];         // erfcx numerator coefficients scaled by beta^k (argument r)
     float q[6];         // erfcx denominator coefficients scaled by beta^k
     float b2;           // beta^2
@@ -132,6 +145,7 @@ struct nb_ctx {
 // ---- host helpers (nb_api.cpp) ----
 int nb_read_meta(nb_ctx *c, nb_meta *m);
 int nb_regrow_list(nb_ctx *c, int maxcount);
+int nb_list_entries(nb_ctx *c, int nclusters, int64_t *total);  // sum of icount (synchronous)
 
 // ---- launchers (nb_build.hip) ----
 hipError_t nb_launch_build(nb_ctx *c, const float *x);

@@ -20,6 +20,7 @@ NB_OK, NB_ERR_ARG, NB_ERR_CUTOFF, NB_ERR_OOM, NB_ERR_HIP = 0, 1, 2, 3, 4
 NB_ERR_STATE, NB_ERR_OVERFLOW, NB_ERR_LIST_STALE, NB_ERR_NONFINITE, NB_ERR_IO = 5, 6, 7, 8, 9
 NB_CHECK_STALE, NB_CHECK_FINITE, NB_REUSE_LIST, NB_ASYNC_BUILD = 0x1, 0x2, 0x4, 0x8
 NB_ENERGY_FP64 = 0x10
+NB_MAX_EXCL_PER_ATOM = 32
 
 STATUS_NAMES = {0: "NB_OK", 1: "NB_ERR_ARG", 2: "NB_ERR_CUTOFF", 3: "NB_ERR_OOM", 4: "NB_ERR_HIP",
                 5: "NB_ERR_STATE", 6: "NB_ERR_OVERFLOW", 7: "NB_ERR_LIST_STALE",
@@ -207,10 +208,14 @@ def nb_backward(ctx: int, x, q, types, g_f, g_e, dx, dq, dsigma, deps, flags: in
                              _ptr(dq), _ptr(dsigma), _ptr(deps), int(flags)), ctx)
 
 
-def nb_debug_pairs(ctx: int, x, cap: int) -> np.ndarray:
-    """Interacting pairs as an int64 [count, 2] array (i < j, original indices, unsorted)."""
-    buf = np.zeros((max(cap, 1), 2), dtype=np.int64)
+def nb_debug_pairs(ctx: int, x, cap: int, count_only: bool = False):
+    """Interacting pairs as an int64 [count, 2] array (i < j, original indices, unsorted);
+    with count_only, just the number of interacting pairs."""
     cnt = ctypes.c_int64(0)
+    if count_only:
+        _check(lib().nb_debug_pairs(ctx, _ptr(x), None, 0, ctypes.byref(cnt)), ctx)
+        return int(cnt.value)
+    buf = np.zeros((max(cap, 1), 2), dtype=np.int64)
     _check(lib().nb_debug_pairs(ctx, _ptr(x), buf.ctypes.data, int(cap), ctypes.byref(cnt)), ctx)
     if cnt.value > cap:
         return nb_debug_pairs(ctx, x, int(cnt.value))

@@ -82,6 +82,28 @@ def test_bad_exclusions_are_rejected():
     assert nb.nb_validate_params(p) == nb.NB_ERR_ARG
 
 
+def test_too_many_exclusions_per_atom_are_rejected():
+    """Atom 0 gets NB_MAX_EXCL_PER_ATOM + 1 partners (symmetric lists)."""
+    t = synth.tiny()
+    n = t.natoms
+    lists = [list(t.excl_idx[t.excl_off[i]:t.excl_off[i + 1]]) for i in range(n)]
+    for k in range(1, nb.NB_MAX_EXCL_PER_ATOM + 2):
+        j = 3 * k  # an oxygen of another molecule
+        if j not in lists[0]:
+            lists[0].append(j)
+            lists[j].append(0)
+    off = np.zeros(n + 1, np.int32)
+    off[1:] = np.cumsum([len(l) for l in lists])
+    idx = np.concatenate([np.asarray(l, np.int32) for l in lists]).astype(np.int32)
+    assert off[1] - off[0] > nb.NB_MAX_EXCL_PER_ATOM
+    p = nb.Params.from_instance(t)
+    p.excl_off, p.excl_idx = off, idx
+    p.c.excl_off = off.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    p.c.excl_idx = idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    assert nb.nb_validate_params(p) == nb.NB_ERR_ARG
+    assert "32" in nb.nb_last_error(None)
+
+
 def test_setup_rejects_invalid_params_without_gpu():
     with pytest.raises(nb.NbError) as ei:
         nb.nb_setup(base_params(cutoff=0.95), stream=0)
