@@ -140,7 +140,9 @@ int nb_check(nb_ctx *ctx);
  * g_e [2] = (dL/dE_LJ, dL/dE_C) (double).  Outputs (device, overwritten): dx [natoms][3],
  * dq [natoms] (float), dsigma [ntypes], deps [ntypes] (double).  The pair list is rebuilt
  * from x first unless flags has NB_REUSE_LIST.  Types with epsilon = 0 get deps = 0 (the
- * derivative of sqrt(eps_a eps_b) does not exist there).
+ * derivative of sqrt(eps_a eps_b) does not exist there).  The first call allocates the adjoint
+ * work buffers; later calls with NB_REUSE_LIST enqueue kernels only (g_e is read on the device,
+ * no host synchronisation), while a list rebuild synchronises once as nb_pairlist does.
  * Errors: as nb_pairlist and nb_forces. */
 int nb_backward(nb_ctx *ctx, const float *x, const float *q, const int32_t *type,
                 const float *g_f, const double *g_e, float *dx, float *dq, double *dsigma,

@@ -34,7 +34,7 @@ __device__ __forceinline__ float wsum(float v) {
 }
 
 template <int C>
-__global__ void __launch_bounds__(256) k_adjoint(nb_fparams fp, float s_lj, float s_c, int cap,
+__global__ void __launch_bounds__(256) k_adjoint(nb_fparams fp, const double *__restrict__ ge, int cap,
                                                  int npad_max, const float4 *__restrict__ xq,
                                                  const int *__restrict__ tsort,
                                                  const float4 *__restrict__ gs,
@@ -52,6 +52,8 @@ __global__ void __launch_bounds__(256) k_adjoint(nb_fparams fp, float s_lj, floa
                                                   threadIdx.x / NB_WAVE);
     if (ci >= meta->nclusters) return;
     const int b = lane % NB_JG, jsub = lane / NB_JG;
+    // energy cotangents (dL/dE_LJ, dL/dE_C), read on the device: no host round trip
+    const float s_lj = (float)ge[0], s_c = (float)ge[1];
 
     float xi[C], yi[C], zi[C], qi[C], gxi[C], gyi[C], gzi[C];
     int ti[C];
@@ -157,7 +159,8 @@ __global__ void __launch_bounds__(256) k_adjoint(nb_fparams fp, float s_lj, floa
             ju += u;
             jw += w;
         }
-        if (valid) {
+        // lanes without an interacting pair in this batch (all six sums zero) skip the atomics
+        if (valid && (jx != 0.0f || jy != 0.0f || jz != 0.0f || jq != 0.0f || jw != 0.0f || ju != 0.0f)) {
             atomicAdd(&adjj[jslot], jx);
             atomicAdd(&adjj[npad_max + jslot], jy);
             atomicAdd(&adjj[2 * npad_max + jslot], jz);
@@ -201,22 +204,71 @@ __global__ void k_adj_finalize(int n, int npad_max, const int *__restrict__ slot
     dq[i] = adj[3 * npad_max + p] + adjj[3 * npad_max + p];
 }
 
-// One block per LJ type: FP64 sums of the per-atom LJ-parameter terms over atoms of that type.
-__global__ void __launch_bounds__(256) k_adj_types(nb_typeparams tp, int npad_max,
-                                                   const int *__restrict__ perm,
-                                                   const int *__restrict__ tsort,
-                                                   const float *__restrict__ adj,
-                                                   const float *__restrict__ adjj,
-                                                   const nb_meta *meta, double *__restrict__ dsig,
-                                                   double *__restrict__ deps) {
+// Per-type FP64 sums of the per-atom LJ-parameter terms, in two deterministic steps.  Step 1:
+// each block takes NB_TYPE_SPAN consecutive slots per thread and reduces, type by type, the
+// terms of its real atoms of that type (thread, wave and block trees in fixed order) into
+// part[block][type][2].  Step 2: one block per type adds the block partials in block order.
+#define NB_TYPE_SPAN 8
+
+__global__ void __launch_bounds__(256) k_adj_types_part(int ntypes, int npad_max,
+                                                        const int *__restrict__ perm,
+                                                        const int *__restrict__ tsort,
+                                                        const float *__restrict__ adj,
+                                                        const float *__restrict__ adjj,
+                                                        double *__restrict__ part) {
+    __shared__ double sw[256 / NB_WAVE], su[256 / NB_WAVE];
+    const int p0 = (blockIdx.x * blockDim.x + threadIdx.x) * NB_TYPE_SPAN;
+    float w[NB_TYPE_SPAN], u[NB_TYPE_SPAN];
+    int t[NB_TYPE_SPAN];
+#pragma unroll
+    for (int k = 0; k < NB_TYPE_SPAN; ++k) {
+        const int p = p0 + k;
+        const bool real = p < npad_max && perm[p] >= 0;
+        t[k] = real ? tsort[p] : -1;
+        w[k] = real ? adj[4 * npad_max + p] + adjj[4 * npad_max + p] : 0.0f;
+        u[k] = real ? adj[5 * npad_max + p] + adjj[5 * npad_max + p] : 0.0f;
+    }
+    for (int ty = 0; ty < ntypes; ++ty) {
+        double W = 0.0, U = 0.0;
+#pragma unroll
+        for (int k = 0; k < NB_TYPE_SPAN; ++k) {
+            if (t[k] == ty) {
+                W += (double)w[k];
+                U += (double)u[k];
+            }
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            W += __shfl_xor(W, o, NB_WAVE);
+            U += __shfl_xor(U, o, NB_WAVE);
+        }
+        __syncthreads();  // the previous type's block sums have been read
+        if ((threadIdx.x & (NB_WAVE - 1)) == 0) {
+            sw[threadIdx.x / NB_WAVE] = W;
+            su[threadIdx.x / NB_WAVE] = U;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double bw = 0.0, bu = 0.0;
+            for (int k = 0; k < (int)(blockDim.x / NB_WAVE); ++k) {
+                bw += sw[k];
+                bu += su[k];
+            }
+            part[2 * (blockIdx.x * ntypes + ty)] = bw;
+            part[2 * (blockIdx.x * ntypes + ty) + 1] = bu;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) k_adj_types(nb_typeparams tp, int nblk,
+                                                   const double *__restrict__ part,
+                                                   double *__restrict__ dsig, double *__restrict__ deps) {
     __shared__ double sw[256 / NB_WAVE], su[256 / NB_WAVE];
     const int t = blockIdx.x;
-    const int np = meta->npad;
     double w = 0.0, u = 0.0;
-    for (int p = threadIdx.x; p < np; p += blockDim.x) {
-        if (perm[p] < 0 || tsort[p] != t) continue;
-        w += (double)adj[4 * npad_max + p] + (double)adjj[4 * npad_max + p];
-        u += (double)adj[5 * npad_max + p] + (double)adjj[5 * npad_max + p];
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+        w += part[2 * (b * tp.ntypes + t)];
+        u += part[2 * (b * tp.ntypes + t) + 1];
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -251,31 +303,31 @@ hipError_t nb_launch_adjoint(nb_ctx *c, const float *gf, const double *ge, float
             return hipErrorOutOfMemory;
         if (hipMalloc((void **)&c->gs, sizeof(float4) * (size_t)c->npad_max) != hipSuccess)
             return hipErrorOutOfMemory;
+        const size_t nblk = (c->npad_max + tb * NB_TYPE_SPAN - 1) / (tb * NB_TYPE_SPAN);
+        if (hipMalloc((void **)&c->tpart, sizeof(double) * 2 * nblk * c->ntypes) != hipSuccess)
+            return hipErrorOutOfMemory;
     }
-    // energy cotangents are device doubles: read them once on the host (the backward pass is
-    // not on the capture path)
-    double geh[2];
-    hipError_t e = hipMemcpyAsync(geh, ge, sizeof(geh), hipMemcpyDeviceToHost, c->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_pack_g, dim3((c->npad_max + tb - 1) / tb), dim3(tb), 0, c->stream,
                        c->npad_max, c->perm, gf, c->gs, c->adjj, c->meta);
     size_t shm = sizeof(float4) * 2 * c->ntypes * c->ntypes;
     dim3 grid((c->ncl_max + 3) / 4), block(256);
     if (c->C == 4)
-        hipLaunchKernelGGL((k_adjoint<4>), grid, block, shm, c->stream, c->fp, (float)geh[0],
-                           (float)geh[1], c->cap, c->npad_max, c->xq, c->tsort, c->gs, c->ljtab,
-                           c->icount, c->jl, c->adj, c->adjj, c->meta);
+        hipLaunchKernelGGL((k_adjoint<4>), grid, block, shm, c->stream, c->fp, ge, c->cap,
+                           c->npad_max, c->xq, c->tsort, c->gs, c->ljtab, c->icount, c->jl, c->adj,
+                           c->adjj, c->meta);
     else
-        hipLaunchKernelGGL((k_adjoint<8>), grid, block, shm, c->stream, c->fp, (float)geh[0],
-                           (float)geh[1], c->cap, c->npad_max, c->xq, c->tsort, c->gs, c->ljtab,
-                           c->icount, c->jl, c->adj, c->adjj, c->meta);
+        hipLaunchKernelGGL((k_adjoint<8>), grid, block, shm, c->stream, c->fp, ge, c->cap,
+                           c->npad_max, c->xq, c->tsort, c->gs, c->ljtab, c->icount, c->jl, c->adj,
+                           c->adjj, c->meta);
     hipLaunchKernelGGL(k_adj_finalize, dim3((c->natoms + tb - 1) / tb), dim3(tb), 0, c->stream,
                        c->natoms, c->npad_max, c->slot_of, c->adj, c->adjj, dx, dq);
     nb_typeparams tp{};
     tp.ntypes = c->ntypes;
     for (int t = 0; t < c->ntypes; ++t) tp.eps[t] = c->epsilon[t];
-    hipLaunchKernelGGL(k_adj_types, dim3(c->ntypes), dim3(256), 0, c->stream, tp, c->npad_max,
-                       c->perm, c->tsort, c->adj, c->adjj, c->meta, dsig, deps);
+    const int nblk = (c->npad_max + tb * NB_TYPE_SPAN - 1) / (tb * NB_TYPE_SPAN);
+    hipLaunchKernelGGL(k_adj_types_part, dim3(nblk), dim3(tb), 0, c->stream, c->ntypes, c->npad_max,
+                       c->perm, c->tsort, c->adj, c->adjj, c->tpart);
+    hipLaunchKernelGGL(k_adj_types, dim3(c->ntypes), dim3(256), 0, c->stream, tp, nblk, c->tpart,
+                       dsig, deps);
     return hipGetLastError();
 }

@@ -164,7 +164,7 @@ void free_all(nb_ctx *c) {
                     c->colcount, c->colstart, c->colcl, c->perm, c->xs,     c->xq,
                     c->tsort, c->fi,     c->fj,     c->bblo,  c->bbhi,      c->icount,
                     c->jl,    c->epart,  c->meta,   c->ljtab, c->excl_off,  c->excl_idx,
-                    c->dbg_pairs, c->adj, c->adjj, c->gs, c->excl_slot, c->etab};
+                    c->dbg_pairs, c->adj, c->adjj, c->gs, c->tpart, c->excl_slot, c->etab};
     for (void *p : bufs)
         if (p) hipFree(p);
 }

@@ -111,7 +111,22 @@ __global__ void __launch_bounds__(NB_FIN_BLOCK) k_finalize(int n, int npad_max,
     if (blockIdx.x != 0) return;
     const int ncl = meta->nclusters;
     double x = 0.0, y = 0.0, z = 0.0;
-    for (int k = threadIdx.x; k < ncl; k += blockDim.x) {
+    // eight clusters per thread and step: their loads are issued together, not one latency
+    // after another
+    constexpr int U = 8;
+    int k = threadIdx.x;
+    for (; k + (U - 1) * NB_FIN_BLOCK < ncl; k += U * NB_FIN_BLOCK) {
+        double4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = *reinterpret_cast<const double4 *>(epart + 4 * (k + u * NB_FIN_BLOCK));
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            x += v[u].x;
+            y += v[u].y;
+            z += v[u].z;
+        }
+    }
+    for (; k < ncl; k += NB_FIN_BLOCK) {
         x += epart[4 * k];
         y += epart[4 * k + 1];
         z += epart[4 * k + 2];

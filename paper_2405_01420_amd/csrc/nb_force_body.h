@@ -253,7 +253,9 @@ __device__ __forceinline__ void nb_force_cluster(const nb_fparams &fp, const flo
             }
             pair_block<C, true, EPREC>(fp, tab, ntt, et, xl, yl, zl, qi, ti, jv, fix, fiy, fiz, elj, ec, qqs, qqsd, p4v, q5v);
         }
-        if (valid) {
+        // about 40% of the lanes of a batch have no pair within rc (their entry was kept for
+        // another atom of the group, at rlist); they skip their atomics
+        if (valid && (jv.fx != 0.0f || jv.fy != 0.0f || jv.fz != 0.0f)) {
             atomicAdd((float *)(fj + jslot), jv.fx);
             atomicAdd((float *)(fj + npad_max + jslot), jv.fy);
             atomicAdd((float *)(fj + 2 * npad_max + jslot), jv.fz);

@@ -134,6 +134,7 @@ struct nb_ctx {
     float *adj = nullptr;       // [6 * npad_max]: i-side (dx, dy, dz, dq, Sw, Su) SoA
     float *adjj = nullptr;      // [6 * npad_max]: j-side, atomics
     float4 *gs = nullptr;       // [npad_max] force cotangents in cluster order
+    double *tpart = nullptr;    // [adjoint type-sum blocks][ntypes][2] block partials
     // kernel timing
     bool timing = false;
     std::vector<hipEvent_t> ev;  // pairs (start, stop)
