@@ -19,8 +19,10 @@ Beside the headline line the JSON carries the two other forms against the plain 
   adjoint - the 24,000-atom four-type box: nb_backward (list reused, and with the list rebuilt
             from x) against nb_forces on the same box.
 
+With --large it also times single force calls on the 3,000,000-atom box (median of 20).
+
 Usage: python bench.py [--gpus 1] [--steps 1000] [--warmup 20] [--cluster 8] [--cpu-seconds 12]
-                       [--no-batch] [--no-adjoint] [--no-tune] [--no-cpu]
+                       [--no-batch] [--no-adjoint] [--no-tune] [--no-cpu] [--large]
 """
 import argparse
 import json
@@ -51,6 +53,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="end with one 256 MiB device-to-device copy (calibrates HBM byte counters)")
+    ap.add_argument("--large", action="store_true",
+                    help="also time the 3,000,000-atom box (median of 20 force calls)")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="batched form with C = 8 everywhere")
@@ -193,6 +197,39 @@ def bench_adjoint(torch, nb, synth, reps=50):
             "pair_interactions_per_s_backward": useful / (us_b * 1e-6)}
 
 
+def bench_large(torch, nb, synth, reps=20, warmup=3):
+    """3,000,000-atom box (rc 1.2 nm, 5 LJ types): median and IQR of single force calls."""
+    import numpy as np
+    dev = "cuda:0"
+    inst = synth.large()
+    stream = torch.cuda.current_stream()
+    ctx = nb.nb_setup(nb.Params.from_instance(inst), stream=stream.cuda_stream)
+    n = inst.natoms
+    x = torch.from_numpy(inst.x.reshape(-1).copy()).to(dev)
+    q = torch.from_numpy(inst.q.copy()).to(dev)
+    t = torch.from_numpy(inst.type.copy()).to(dev)
+    f = torch.empty(3 * n, dtype=torch.float32, device=dev)
+    e = torch.empty(2, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    nb.nb_pairlist(ctx, x)
+    torch.cuda.synchronize()
+    build_ms = 1e3 * (time.perf_counter() - tb)
+    useful = nb.nb_debug_pairs(ctx, x, 0, count_only=True)
+    stats = nb.nb_get_stats(ctx)
+    for _ in range(warmup):
+        nb.nb_forces(ctx, x, q, t, f, e)
+    us = [_event_us(torch, stream, lambda: nb.nb_forces(ctx, x, q, t, f, e), 1) for _ in range(reps)]
+    nb.nb_destroy(ctx)
+    med = float(np.median(us))
+    q1, q3 = (float(v) for v in np.percentile(us, [25, 75]))
+    return {"workload": "3,000,000 atoms (1,000,000 waters), L 31.1 nm, rc 1.2 nm, rb 0.1 nm, "
+                        "10% of atoms on 4 extra LJ types",
+            "useful_pairs": useful, "evaluated_pairs": stats["evaluated_pairs"],
+            "us_per_force_call_median": med, "us_per_force_call_iqr": [q1, q3],
+            "pair_interactions_per_s": useful / (med * 1e-6), "ms_list_build": build_ms}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -306,6 +343,8 @@ def main():
         out["adjoint"] = bench_adjoint(torch, nb, synth)
     if not args.no_batch:
         out["batched"] = bench_batched(torch, nb, synth, not args.no_tune)
+    if args.large:
+        out["large"] = bench_large(torch, nb, synth)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(inst, useful, args.cpu_seconds)
     if args.copy_probe:

@@ -374,48 +374,101 @@ __global__ void __launch_bounds__(256) k_search(nb_geom g, int cap, const int *_
             continue;
         const int cx0 = max(0, (int)floorf(x0 * g.invw[0])), cx1 = min(g.ncx - 1, (int)floorf(x1 * g.invw[0]));
         const int cy0 = max(0, (int)floorf(y0 * g.invw[1])), cy1 = min(g.ncy - 1, (int)floorf(y1 * g.invw[1]));
-        for (int cy = cy0; cy <= cy1; ++cy) {
-            for (int cx = cx0; cx <= cx1; ++cx) {
-                const int col = cy * g.ncx + cx;
-                const int ca = colcl[col], cb = colcl[col + 1];
-                for (int base = ca; base < cb; base += NB_WAVE) {
-                    const int cjl = base + lane;
-                    bool cand = cjl < cb;
-                    if (cand) {
-                        const bool half = cjl > ci || (cjl == ci && s >= NB_SHIFT_ZERO);
-                        const float4 jlo = bblo[cjl], jhi = bbhi[cjl];
-                        const float gx = gap(lo.x, hi.x, jlo.x + sx, jhi.x + sx);
-                        const float gy = gap(lo.y, hi.y, jlo.y + sy, jhi.y + sy);
-                        const float gz = gap(lo.z, hi.z, jlo.z + sz, jhi.z + sz);
-                        cand = half && (gx * gx + gy * gy + gz * gz < g.rl2);
+        // The candidate columns of this shift, up to 64 at a time: lane c holds the z-window of
+        // column c's clusters, and the wave walks the concatenated windows 64 clusters per pass,
+        // so the loads of one pass are independent of each other.
+        if (cx1 < cx0 || cy1 < cy0) continue;
+        const int ncx_r = cx1 - cx0 + 1;
+        const int ncols = ncx_r * (cy1 - cy0 + 1);
+        for (int c0 = 0; c0 < ncols; c0 += NB_WAVE) {
+            const int c = c0 + lane;
+            int cstart = 0, cnt = 0;
+            if (c < ncols) {
+                const int col = (cy0 + c / ncx_r) * g.ncx + cx0 + c % ncx_r;
+                cstart = colcl[col];
+                cnt = colcl[col + 1] - cstart;
+                // clusters are z-ordered within a column, so both bounding-box z ends increase
+                // with the index: keep only the run whose z extent meets [z0, z1], widened by
+                // 2^-10 nm so that it contains every cluster the bounding-box test below passes
+                const float zw0 = z0 - 0x1p-10f, zw1 = z1 + 0x1p-10f;
+                int a = 0, n = cnt;  // first cluster with hi.z >= z0
+                while (n > 0) {
+                    const int h = n >> 1;
+                    if (bbhi[cstart + a + h].z < zw0) {
+                        a += h + 1;
+                        n -= h + 1;
+                    } else {
+                        n = h;
                     }
-                    const unsigned long long cbal = __ballot(cand);
-                    if (cbal == 0ull) continue;
-                    if (cand) {
-                        const int pos = nq + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(cbal >> 32),
-                                                                           __builtin_amdgcn_mbcnt_lo((unsigned)cbal, 0u));
-                        q_cj[wv][pos] = cjl;
-                        q_s[wv][pos] = s;
+                }
+                int e = a, m = cnt - a;  // first cluster with lo.z > z1
+                while (m > 0) {
+                    const int h = m >> 1;
+                    if (bblo[cstart + e + h].z <= zw1) {
+                        e += h + 1;
+                        m -= h + 1;
+                    } else {
+                        m = h;
                     }
-                    nq += __popcll(cbal);
+                }
+                cstart += a;
+                cnt = e - a;
+            }
+            int incl = cnt;  // inclusive prefix sum of the counts over the lanes
+#pragma unroll
+            for (int o = 1; o < NB_WAVE; o <<= 1) {
+                const int v = __shfl_up(incl, o, NB_WAVE);
+                if (lane >= o) incl += v;
+            }
+            const int total = __builtin_amdgcn_readlane(incl, NB_WAVE - 1);
+            for (int f0 = 0; f0 < total; f0 += NB_WAVE) {
+                const int f = f0 + lane;
+                // column lane q: the first lane whose inclusive prefix exceeds f
+                int q = 0;
+#pragma unroll
+                for (int step = NB_WAVE / 2; step >= 1; step >>= 1) {
+                    const int v = __shfl(incl, q + step - 1, NB_WAVE);
+                    if (v <= f) q += step;
+                }
+                q = min(q, NB_WAVE - 1);
+                const int qstart = __shfl(cstart, q, NB_WAVE);
+                const int qexcl = __shfl(incl, q, NB_WAVE) - __shfl(cnt, q, NB_WAVE);
+                const int cjl = qstart + (f - qexcl);
+                bool cand = f < total;
+                if (cand) {
+                    const bool half = cjl > ci || (cjl == ci && s >= NB_SHIFT_ZERO);
+                    const float4 jlo = bblo[cjl], jhi = bbhi[cjl];
+                    const float gx = gap(lo.x, hi.x, jlo.x + sx, jhi.x + sx);
+                    const float gy = gap(lo.y, hi.y, jlo.y + sy, jhi.y + sy);
+                    const float gz = gap(lo.z, hi.z, jlo.z + sz, jhi.z + sz);
+                    cand = half && (gx * gx + gy * gy + gz * gz < g.rl2);
+                }
+                const unsigned long long cbal = __ballot(cand);
+                if (cbal == 0ull) continue;
+                if (cand) {
+                    const int pos = nq + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(cbal >> 32),
+                                                                       __builtin_amdgcn_mbcnt_lo((unsigned)cbal, 0u));
+                    q_cj[wv][pos] = cjl;
+                    q_s[wv][pos] = s;
+                }
+                nq += __popcll(cbal);
+                nb_wave_sync();
+                if (nq >= NB_WAVE) {
+                    flush(NB_WAVE);
+                    // move the overflow (slots 64 .. nq-1) to the front
+                    const int rest = nq - NB_WAVE;
+                    int mc = 0, ms = 0;
+                    if (lane < rest) {
+                        mc = q_cj[wv][NB_WAVE + lane];
+                        ms = q_s[wv][NB_WAVE + lane];
+                    }
                     nb_wave_sync();
-                    if (nq >= NB_WAVE) {
-                        flush(NB_WAVE);
-                        // move the overflow (slots 64 .. nq-1) to the front
-                        const int rest = nq - NB_WAVE;
-                        int mc = 0, ms = 0;
-                        if (lane < rest) {
-                            mc = q_cj[wv][NB_WAVE + lane];
-                            ms = q_s[wv][NB_WAVE + lane];
-                        }
-                        nb_wave_sync();
-                        if (lane < rest) {
-                            q_cj[wv][lane] = mc;
-                            q_s[wv][lane] = ms;
-                        }
-                        nq = rest;
-                        nb_wave_sync();
+                    if (lane < rest) {
+                        q_cj[wv][lane] = mc;
+                        q_s[wv][lane] = ms;
                     }
+                    nq = rest;
+                    nb_wave_sync();
                 }
             }
         }
