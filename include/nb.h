@@ -92,6 +92,10 @@ typedef struct nb_stats {
     int64_t list_capacity;                /* j-entries per i-cluster the list can hold */
     int32_t cluster, ncolumns;
     double build_ms_last;                 /* host-timed duration of the last nb_pairlist */
+    int32_t work_units;                   /* force-kernel work units (parts of i-cluster lists) */
+    int32_t unit_batches;                 /* 64-lane batches per work unit at most */
+    int32_t max_list_batches;             /* longest i-cluster list, in 64-lane batches */
+    int32_t pad;
 } nb_stats;
 
 typedef struct nb_ctx nb_ctx;

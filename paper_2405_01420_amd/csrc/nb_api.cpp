@@ -162,7 +162,7 @@ int read_meta(nb_ctx *c, nb_meta *m) {
 void free_all(nb_ctx *c) {
     void *bufs[] = {c->off,   c->xbuild, c->col,    c->rank,  c->tmp,       c->slot_of,
                     c->colcount, c->colstart, c->colcl, c->perm, c->xs,     c->xq,
-                    c->tsort, c->fi,     c->fj,     c->bblo,  c->bbhi,      c->icount,
+                    c->tsort, c->units,  c->fj,     c->bblo,  c->bbhi,      c->icount,
                     c->jl,    c->epart,  c->meta,   c->ljtab, c->excl_off,  c->excl_idx,
                     c->dbg_pairs, c->adj, c->adjj, c->gs, c->tpart, c->excl_slot, c->etab};
     for (void *p : bufs)
@@ -273,6 +273,13 @@ int nb_setup(nb_ctx **out, const nb_params *p, void *stream) {
     c->npad_max = p->natoms + g.ncol * (c->C - 1);
     c->ncl_max = c->npad_max / c->C + 1;
     c->npad_max = c->ncl_max * c->C;
+    {
+        int ncu = 0;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess || ncu <= 0)
+            ncu = 256;
+        c->slots = ncu * 4;  // SIMDs
+        c->unit_cap = c->ncl_max + 2 * c->slots + 64;
+    }
     c->cap = estimate_cap(p->natoms, p->box, c->C, rlist);
     if (const char *ov = getenv("NB_LIST_CAP")) {
         // initial j-entries per i-cluster; the list still grows on overflow
@@ -296,12 +303,13 @@ int nb_setup(nb_ctx **out, const nb_params *p, void *stream) {
     NB_ALLOC(xs, c->npad_max);
     NB_ALLOC(xq, c->npad_max);
     NB_ALLOC(tsort, c->npad_max);
-    NB_ALLOC(fi, c->npad_max);
+
     NB_ALLOC(fj, 3 * (size_t)c->npad_max);
     NB_ALLOC(bblo, c->ncl_max);
     NB_ALLOC(bbhi, c->ncl_max);
     NB_ALLOC(icount, c->ncl_max);
-    NB_ALLOC(epart, 4 * (size_t)c->ncl_max);
+    NB_ALLOC(units, c->unit_cap);
+    NB_ALLOC(epart, 4 * (size_t)c->unit_cap);
     NB_ALLOC(meta, 1);
     NB_ALLOC(ljtab, 2 * (size_t)c->ntypes * c->ntypes);
 #undef NB_ALLOC
@@ -487,6 +495,9 @@ int nb_get_stats(nb_ctx *c, nb_stats *st) {
     st->cluster = c->C;
     st->ncolumns = c->geom.ncol;
     st->build_ms_last = c->build_ms;
+    st->work_units = m.nunits;
+    st->unit_batches = m.split;
+    st->max_list_batches = m.maxbatches;
     return NB_OK;
 }
 

@@ -22,7 +22,6 @@ struct nb_box_desc {
     int *tsort;
     const int *icount;
     const nb_entry *jl;
-    float4 *fi;
     float *fj;
     double *epart;
     const nb_meta *meta;
@@ -136,9 +135,9 @@ __global__ void __launch_bounds__(256) NB_FORCE_OCCUPANCY k_batch_force(nb_fpara
             f.L[1] = d.L[1];
             f.L[2] = d.L[2];
             // the descriptor's pointers are global memory; typed so, their accesses are global
-            nb_force_cluster<C, EPREC>(f, tab, et, ci, d.cap, d.npad_max, nb_g(d.xq), nb_g(d.tsort),
-                                       nb_g(d.icount), nb_g(d.jl), nb_g(d.fi), nb_g(d.fj),
-                                       nb_g(d.epart));
+            nb_force_cluster<C, EPREC>(f, tab, et, ci, 0, 1 << 20, ci, d.cap, d.npad_max,
+                                       nb_g(d.xq), nb_g(d.tsort), nb_g(d.icount), nb_g(d.jl),
+                                       nb_g(d.fj), nb_g(d.epart));
         }
     }
 }
@@ -148,11 +147,10 @@ __global__ void k_batch_finalize(const nb_box_desc *__restrict__ desc, float *__
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= d.natoms) return;
     const int p = d.slot_of[i];
-    const float4 a = d.fi[p];
     const int g = d.atom_off + i;
-    f[3 * g] = a.x + d.fj[p];
-    f[3 * g + 1] = a.y + d.fj[d.npad_max + p];
-    f[3 * g + 2] = a.z + d.fj[2 * d.npad_max + p];
+    f[3 * g] = d.fj[p];
+    f[3 * g + 1] = d.fj[d.npad_max + p];
+    f[3 * g + 2] = d.fj[2 * d.npad_max + p];
 }
 
 __global__ void __launch_bounds__(256) k_batch_energy(const nb_box_desc *__restrict__ desc,
@@ -219,7 +217,6 @@ int upload_desc(nb_batch *bt) {
         d.tsort = c->tsort;
         d.icount = c->icount;
         d.jl = c->jl;
-        d.fi = c->fi;
         d.fj = c->fj;
         d.epart = c->epart;
         d.meta = c->meta;

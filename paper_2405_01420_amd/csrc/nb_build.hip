@@ -485,6 +485,74 @@ __global__ void __launch_bounds__(256) k_search(nb_geom g, int cap, const int *_
     }
 }
 
+#define NB_UNIT_MIN 4  // batches per work unit at least (a unit's fixed cost is about one)
+
+// Work units of the force kernel, in one block: every i-cluster with a non-empty list becomes
+// ceil(nb / P) units of at most P 64-lane batches, nb being its list length in batches and
+// P = max(4, ceil(total batches / (2 * SIMDs))).  The SIMDs share their time among resident
+// waves, so a kernel lasts about max(total batches / SIMDs, longest list) batch times; lists are
+// split only when the longest list would set that (small boxes), never at 96k atoms.  Units stay in cluster order: neighbouring waves then work on neighbouring
+// clusters, whose j-atoms they share in the caches.  (Ordering the units longest first was
+// measured slower at 96k atoms: it scatters that locality, and the half-list rule already gives
+// the early clusters the longer lists.)  The unit index is also its energy slot.
+__global__ void __launch_bounds__(1024) k_units(int slots, int unit_cap, const int *__restrict__ icount,
+                                                int4 *__restrict__ units, nb_meta *meta) {
+    __shared__ int red[1024];
+    __shared__ int s_p;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int ncl = meta->nclusters;
+    const int chunk = (ncl + nthr - 1) / nthr;
+    const int c_lo = min(ncl, tid * chunk), c_hi = min(ncl, c_lo + chunk);
+    // total batches and the longest list
+    int nb_sum = 0, nb_max = 0;
+    for (int c = c_lo; c < c_hi; ++c) {
+        const int nb = (icount[c] + NB_JPB - 1) / NB_JPB;
+        nb_sum += nb;
+        nb_max = max(nb_max, nb);
+    }
+    red[tid] = nb_sum;
+    __syncthreads();
+    for (int o = nthr / 2; o > 0; o >>= 1) {
+        if (tid < o) red[tid] += red[tid + o];
+        __syncthreads();
+    }
+    if (tid == 0) s_p = max(NB_UNIT_MIN, (red[0] + 2 * slots - 1) / (2 * slots));
+    __syncthreads();
+    red[tid] = nb_max;
+    __syncthreads();
+    for (int o = nthr / 2; o > 0; o >>= 1) {
+        if (tid < o) red[tid] = max(red[tid], red[tid + o]);
+        __syncthreads();
+    }
+    const int P = s_p;
+    if (tid == 0) meta->maxbatches = red[0];
+    __syncthreads();
+    // units of this thread's clusters and their exclusive prefix over the threads
+    int nu = 0;
+    for (int c = c_lo; c < c_hi; ++c) nu += ((icount[c] + NB_JPB - 1) / NB_JPB + P - 1) / P;
+    red[tid] = nu;
+    __syncthreads();
+    for (int o = 1; o < nthr; o <<= 1) {  // inclusive scan (Hillis-Steele)
+        const int v = tid >= o ? red[tid - o] : 0;
+        __syncthreads();
+        red[tid] += v;
+        __syncthreads();
+    }
+    int u = red[tid] - nu;
+    if (tid == nthr - 1) {
+        meta->nunits = min(red[tid], unit_cap);
+        meta->split = P;
+        if (red[tid] > unit_cap) atomicOr(&meta->flags, NB_F_COLUMN);  // not reachable: <= ncl + 2 slots
+    }
+    for (int c = c_lo; c < c_hi; ++c) {
+        const int nb = (icount[c] + NB_JPB - 1) / NB_JPB;
+        for (int b = 0; b < nb; b += P) {
+            if (u < unit_cap) units[u] = make_int4(c, b, min(P, nb - b), u);
+            ++u;
+        }
+    }
+}
+
 // Export of interacting pairs with the force kernel's arithmetic: the same lane layout (one
 // j atom per lane, the i atoms of the cluster in turn) and the same displacement formula.
 template <int C>
@@ -560,6 +628,8 @@ hipError_t build_impl(nb_ctx *c, const float *x) {
                        c->geom, c->cap, c->colcl, c->bblo, c->bbhi, c->perm, c->xs,
                        c->nnz_excl > 0 ? c->excl_off : nullptr, c->excl_slot, c->icount, c->jl,
                        c->meta);
+    hipLaunchKernelGGL(k_units, dim3(1), dim3(1024), 0, c->stream, c->slots, c->unit_cap, c->icount,
+                       c->units, c->meta);
     return hipGetLastError();
 }
 

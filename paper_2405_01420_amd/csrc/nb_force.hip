@@ -66,7 +66,7 @@ __global__ void __launch_bounds__(256) NB_FORCE_OCCUPANCY k_force(nb_fparams fp,
                                                float etab_invh,
                                                const int *__restrict__ icount,
                                                const nb_entry *__restrict__ jl,
-                                               float4 *__restrict__ fi_out, float *__restrict__ fj,
+                                               const int4 *__restrict__ units, float *__restrict__ fj,
                                                double *__restrict__ epart, const nb_meta *meta) {
     extern __shared__ float4 tab[];
     const int ntt = fp.ntypes * fp.ntypes;
@@ -80,20 +80,23 @@ __global__ void __launch_bounds__(256) NB_FORCE_OCCUPANCY k_force(nb_fparams fp,
         for (int k = threadIdx.x; k < 2 * etab_n; k += blockDim.x) dst[k] = etab[k];
     }
     __syncthreads();
-    const int ci = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x / NB_WAVE) +
-                                                  threadIdx.x / NB_WAVE);
-    if (ci >= meta->nclusters) return;
-    nb_force_cluster<C, EPREC>(fp, tab, et, ci, cap, npad_max, nb_g(xq), nb_g(tsort), nb_g(icount),
-                               nb_g(jl), nb_g(fi_out), nb_g(fj), nb_g(epart));
+    // one wave per work unit
+    const int u = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x / NB_WAVE) +
+                                                 threadIdx.x / NB_WAVE);
+    if (u >= meta->nunits) return;
+    const int4 w = units[u];
+    nb_force_cluster<C, EPREC>(fp, tab, et, __builtin_amdgcn_readfirstlane(w.x),
+                               __builtin_amdgcn_readfirstlane(w.y), __builtin_amdgcn_readfirstlane(w.z),
+                               __builtin_amdgcn_readfirstlane(w.w), cap, npad_max, nb_g(xq),
+                               nb_g(tsort), nb_g(icount), nb_g(jl), nb_g(fj), nb_g(epart));
 }
 
-// f[atom] = f_i + f_j in original order, and the FP64 energy sums.  Block 0 additionally adds
-// the per-cluster energy partials in a fixed order (strided per thread, then the wave and block
-// trees) and applies the Coulomb shift; it is dispatched first, so this runs beside the other
-// blocks' force gathers and needs no inter-block synchronisation.
+// f[atom] in original order, and the FP64 energy sums.  Block 0 additionally adds the energy
+// partials of the work units in slot order (strided per thread, then the wave and block trees)
+// and applies the Coulomb shift; it is dispatched first, so this runs beside the other blocks'
+// force gathers and needs no inter-block synchronisation.
 __global__ void __launch_bounds__(NB_FIN_BLOCK) k_finalize(int n, int npad_max,
                                                            const int *__restrict__ slot_of,
-                                                           const float4 *__restrict__ fi,
                                                            const float *__restrict__ fj,
                                                            float *__restrict__ f, const nb_meta *meta,
                                                            const double *__restrict__ epart,
@@ -103,13 +106,12 @@ __global__ void __launch_bounds__(NB_FIN_BLOCK) k_finalize(int n, int npad_max,
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) {
         const int p = slot_of[i];
-        const float4 a = fi[p];
-        f[3 * i] = a.x + fj[p];
-        f[3 * i + 1] = a.y + fj[npad_max + p];
-        f[3 * i + 2] = a.z + fj[2 * npad_max + p];
+        f[3 * i] = fj[p];
+        f[3 * i + 1] = fj[npad_max + p];
+        f[3 * i + 2] = fj[2 * npad_max + p];
     }
     if (blockIdx.x != 0) return;
-    const int ncl = meta->nclusters;
+    const int ncl = meta->nunits;
     double x = 0.0, y = 0.0, z = 0.0;
     // eight clusters per thread and step: their loads are issued together, not one latency
     // after another
@@ -168,10 +170,10 @@ template <int C, bool EPREC>
 static void launch_force_t(nb_ctx *c) {
     const size_t shm = sizeof(float4) * 2 * c->ntypes * c->ntypes +
                        (EPREC ? sizeof(double2) * 2 * c->etab_n : 0);
-    dim3 grid((c->ncl_max + 3) / 4), block(256);
+    dim3 grid((c->unit_cap + 3) / 4), block(256);
     hipLaunchKernelGGL((k_force<C, EPREC>), grid, block, shm, c->stream, c->fp, c->cap, c->npad_max,
                        c->xq, c->tsort, c->ljtab, c->etab, c->etab_n, c->etab_invh, c->icount,
-                       c->jl, c->fi, c->fj, c->epart, c->meta);
+                       c->jl, c->units, c->fj, c->epart, c->meta);
 }
 
 hipError_t nb_launch_force(nb_ctx *c) {
@@ -189,7 +191,7 @@ hipError_t nb_launch_force(nb_ctx *c) {
 hipError_t nb_launch_finalize(nb_ctx *c, float *f, double *e) {
     const int nblk = std::max(1, (c->natoms + NB_FIN_BLOCK - 1) / NB_FIN_BLOCK);
     hipLaunchKernelGGL(k_finalize, dim3(nblk), dim3(NB_FIN_BLOCK), 0, c->stream, c->natoms,
-                       c->npad_max, c->slot_of, c->fi, c->fj, f, c->meta, c->epart,
+                       c->npad_max, c->slot_of, c->fj, f, c->meta, c->epart,
                        c->shift_coul, (c->flags & NB_ENERGY_FP64) ? c->fc : 1.0, e);
     return hipGetLastError();
 }

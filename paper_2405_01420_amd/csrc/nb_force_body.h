@@ -142,18 +142,19 @@ __device__ __forceinline__ float nb_uniform(float v) {
     return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
 }
 
-// Forces and energy partials of one i-cluster ci over its whole j-list, computed by one
-// wavefront.  fp.L holds the box of the cluster.  i-forces are stored (not accumulated) to
-// fi_out, j-forces are added atomically to fj, energy partials are stored to epart[4 ci ..].
+// Forces and energy partials of one work unit, computed by one wavefront: the batches
+// [b0, b0 + nbat) of i-cluster ci's j-list (all of them, or one part of a long list).  fp.L
+// holds the box of the cluster.  Both the j-forces and the unit's i-force sums are added
+// atomically to fj (several units may share an i-cluster); the energy partials are stored to
+// epart[4 slot ..].
 template <int C, bool EPREC>
 __device__ __forceinline__ void nb_force_cluster(const nb_fparams &fp, const float4 *tab,
-                                                 const nb_etab &et, int ci,
-                                                 int cap, int npad_max,
+                                                 const nb_etab &et, int ci, int b0, int nbat,
+                                                 int slot, int cap, int npad_max,
                                                  const NB_G float4 *__restrict__ xq,
                                                  const NB_G int *__restrict__ tsort,
                                                  const NB_G int *__restrict__ icount,
                                                  const NB_G nb_entry *__restrict__ jl,
-                                                 NB_G float4 *__restrict__ fi_out,
                                                  NB_G float *__restrict__ fj,
                                                  NB_G double *__restrict__ epart) {
     constexpr unsigned FULL = (1u << C) - 1u;
@@ -188,9 +189,9 @@ __device__ __forceinline__ void nb_force_cluster(const nb_fparams &fp, const flo
     float p4v, q5v;
     asm("v_mov_b32 %0, %1" : "=v"(p4v) : "s"(fp.p[4]));
     asm("v_mov_b32 %0, %1" : "=v"(q5v) : "s"(fp.q[5]));
-    const int nj = nb_ld(icount + ci);
+    const int nj = min(nb_ld(icount + ci), (b0 + nbat) * NB_JPB);
     const NB_G nb_entry *lst = jl + (size_t)ci * cap;
-    for (int base = 0; base < nj; base += NB_JPB) {
+    for (int base = b0 * NB_JPB; base < nj; base += NB_JPB) {
         const int e = base + jsub;
         const bool valid = e < nj;
         // lanes past the end of the list read the i-cluster's own first group with an empty mask
@@ -270,11 +271,27 @@ __device__ __forceinline__ void nb_force_cluster(const nb_fparams &fp, const flo
     elj = nb_wave_sum_d(elj);
     ec = nb_wave_sum_d(ec);
     const double qqd = nb_wave_sum_d(EPREC ? qqsd : (double)qqs);
-    if (lane == NB_WAVE - 1) {
+    // the unit's i-force sums (in lane 63) go to lanes 0 .. C-1, one atom each, so that three
+    // atomics of C lanes add them
+    float vx = 0.0f, vy = 0.0f, vz = 0.0f;
 #pragma unroll
-        for (int k = 0; k < C; ++k) nb_st(fi_out + ci * C + k, make_float4(fix[k], fiy[k], fiz[k], 0.0f));
-        nb_st(epart + 4 * ci, elj);
-        nb_st(epart + 4 * ci + 1, ec);
-        nb_st(epart + 4 * ci + 2, qqd);
+    for (int k = 0; k < C; ++k) {
+        const float sx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(fix[k]), NB_WAVE - 1));
+        const float sy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(fiy[k]), NB_WAVE - 1));
+        const float sz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(fiz[k]), NB_WAVE - 1));
+        vx = lane == k ? sx : vx;
+        vy = lane == k ? sy : vy;
+        vz = lane == k ? sz : vz;
+    }
+    if (lane < C) {
+        const int p = ci * C + lane;
+        atomicAdd((float *)(fj + p), vx);
+        atomicAdd((float *)(fj + npad_max + p), vy);
+        atomicAdd((float *)(fj + 2 * npad_max + p), vz);
+    }
+    if (lane == NB_WAVE - 1) {
+        nb_st(epart + 4 * slot, elj);
+        nb_st(epart + 4 * slot + 1, ec);
+        nb_st(epart + 4 * slot + 2, qqd);
     }
 }

@@ -50,7 +50,9 @@ struct nb_meta {
     uint32_t flags;      // NB_F_*
     int32_t maxcount;    // largest j-entry count of an overflowing i-cluster (for regrowing)
     int32_t maxcolumn;   // largest column population
-    int32_t pad0;
+    int32_t nunits;      // work units of the force kernel (i-cluster list parts)
+    int32_t split;       // batches per work unit at most
+    int32_t maxbatches;  // longest j-list, in 64-lane batches
     uint64_t npairs_out; // pair-export counter
 };
 
@@ -99,6 +101,8 @@ struct nb_ctx {
     double shift_coul = 0;  // erfc(beta rc) / rc
     int npad_max = 0, ncl_max = 0;
     int cap = 0;            // j-entries per i-cluster
+    int slots = 0;          // SIMDs of the device (4 per compute unit)
+    int unit_cap = 0;       // work units at most: ncl_max + 2 slots
     bool have_list = false;
     bool pending_overflow_check = false;
     std::vector<double> sigma, epsilon;
@@ -114,12 +118,14 @@ struct nb_ctx {
     float4 *xs = nullptr;       // [npad_max] build positions (wrapped), sorted
     float4 *xq = nullptr;       // [npad_max] per-call positions + charge, sorted
     int *tsort = nullptr;       // [npad_max] per-call type, sorted
-    float4 *fi = nullptr;       // [npad_max] i-side forces
-    float *fj = nullptr;        // [3 * npad_max] j-side forces, SoA (x | y | z)
+    float *fj = nullptr;        // [3 * npad_max] forces in cluster order, SoA (x | y | z),
+                                // accumulated with atomics by the force kernel
     float4 *bblo = nullptr, *bbhi = nullptr;  // [ncl_max]
     int *icount = nullptr;      // [ncl_max]
     nb_entry *jl = nullptr;     // [ncl_max * cap]
-    double *epart = nullptr;    // [ncl_max * 4]
+    int4 *units = nullptr;      // [unit_cap] (i-cluster, first batch, batches, energy slot),
+                                // longest first
+    double *epart = nullptr;    // [unit_cap * 4] energy partials per work unit
     nb_meta *meta = nullptr;
     float4 *ljtab = nullptr;    // [2 * nt * nt]: (C6, C12, 6 C6, 12 C12), (shift, 1/sigma_ab, 0, 0)
     double2 *etab = nullptr;    // [2 * etab_n]: Hermite segments of erfc(beta r) (FP64 energy mode)

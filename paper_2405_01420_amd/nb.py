@@ -52,7 +52,9 @@ class nb_stats(ctypes.Structure):
                 ("npadded", ctypes.c_int64), ("nentries", ctypes.c_int64),
                 ("evaluated_pairs", ctypes.c_int64), ("list_capacity", ctypes.c_int64),
                 ("cluster", ctypes.c_int32), ("ncolumns", ctypes.c_int32),
-                ("build_ms_last", ctypes.c_double)]
+                ("build_ms_last", ctypes.c_double), ("work_units", ctypes.c_int32),
+                ("unit_batches", ctypes.c_int32), ("max_list_batches", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
 
 
 class nb_batch_info(ctypes.Structure):

@@ -67,7 +67,9 @@ def test_batch_matches_single_box_path(torch_gpu, boxes):
         fs, es = box.forces()
         box.close()
         assert rel_rms(fa[ao[k]:ao[k + 1]], fs) <= 1e-6
-        assert np.all(np.abs(ea[k] - es) <= 1e-9 * np.abs(es) + 1e-9)
+        # the same pair terms summed in another grouping (the plain path may split a list
+        # over several waves): equal up to the FP32 partial sums, far below the 1e-6 gate
+        assert np.all(np.abs(ea[k] - es) <= 1e-7 * np.abs(es))
 
 
 def test_graph_replays_match_eager(torch_gpu, boxes):
