@@ -42,6 +42,27 @@ FLOPS_PER_PAIR = 65
 PEAK_FP32_VECTOR_TFLOPS = 157.3
 REBUILD_EVERY = 10
 
+# rocprofv3 counters of k_force on the 96k-atom box (profiles/k_force_water96k_hbm_counters.md):
+# HBM bytes per launch from FETCH_SIZE and WRITE_SIZE, each scaled by the reading for a 256 MiB
+# device copy (factors 2.0 and 1.0), and the counted FP32 VALU flops per launch
+# (SQ_INSTS_VALU_FLOPS_FP32 x 64 lanes).  They describe the kernel built from the sources with
+# this digest and are reported only while the sources are unchanged.
+K_FORCE_COUNTERS = {
+    "sources": ["nb_force_body.h", "nb_force.hip", "nb_device.h", "nb_internal.h", "erfcx_rational.h"],
+    "sha256": "4086f01c464bd0c592a88ebf5bb40cea90fd453fb074f73d95d7ec4bc4bdb260",
+    "read_bytes": 32.84e6, "write_bytes": 83.65e6,
+    "counted_fp32_flop": 72748284.4 * 64,
+}
+
+
+def _counters_current():
+    import hashlib
+    h = hashlib.sha256()
+    for f in K_FORCE_COUNTERS["sources"]:
+        with open(os.path.join(ROOT, "paper_2405_01420_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest() == K_FORCE_COUNTERS["sha256"]
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -310,6 +331,10 @@ def main():
     nb.nb_set_timing(ctx, False)
     kernel_us = 1e3 * kms / klaunch
     achieved = FLOPS_PER_PAIR * useful / (kernel_us * 1e-6) / 1e12
+    traffic = counted = None
+    if cluster == 8 and not args.energy_fp64 and _counters_current():
+        traffic = K_FORCE_COUNTERS["read_bytes"] + K_FORCE_COUNTERS["write_bytes"]
+        counted = K_FORCE_COUNTERS["counted_fp32_flop"] / (kernel_us * 1e-6) / 1e12
 
     out = {
         "metric": "pair-interactions/s (96k-atom water box, force+energy call, list rebuilt every 10 calls)",
@@ -335,8 +360,8 @@ def main():
         "us_per_call_amortised": 1e3 * ms_per_step,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
-                     "traffic": None, "kernel": "k_force", "kernel_us": kernel_us,
-                     "flops_per_pair": FLOPS_PER_PAIR},
+                     "traffic": traffic, "kernel": "k_force", "kernel_us": kernel_us,
+                     "flops_per_pair": FLOPS_PER_PAIR, "counted_fp32_tflops": counted},
     }
     nb.nb_destroy(ctx)
     if not args.no_adjoint:
