@@ -39,6 +39,13 @@ sys.path.insert(0, ROOT)
 # q_i q_j 1, Coulomb factor products 3, force factor 5, force vector 3, i/j force updates 6,
 # energy sums 2, shift sums 3.
 FLOPS_PER_PAIR = 65
+# The other interaction flavours, counted the same way: the reaction field replaces the 27 flops
+# of the Ewald Coulomb part (r, exp argument, exp, erfcx numerator and denominator, reciprocal
+# and product, q_i q_j, Coulomb products) by 7 (q_i q_j 1, force factor 2, energy 4); the force
+# switch adds 23 (t 2, t^2 1, force polynomials 4, combination 3, force update 3, energy
+# polynomials 4, combination 3, energy update 3), plus r (1) where the reaction field left it out.
+FLOPS_PER_PAIR_FLAVOUR = {("ewald", "shift"): 65, ("rf", "shift"): 45,
+                          ("ewald", "fswitch"): 88, ("rf", "fswitch"): 69}
 PEAK_FP32_VECTOR_TFLOPS = 157.3
 REBUILD_EVERY = 10
 
@@ -74,6 +81,11 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="end with one 256 MiB device-to-device copy (calibrates HBM byte counters)")
+    ap.add_argument("--elec", choices=["ewald", "rf"], default="ewald",
+                    help="electrostatics of the headline box (reaction field: eps_rf = infinity)")
+    ap.add_argument("--vdw", choices=["shift", "fswitch"], default="shift",
+                    help="Lennard-Jones cutoff treatment (force switch from --rswitch)")
+    ap.add_argument("--rswitch", type=float, default=0.8)
     ap.add_argument("--large", action="store_true",
                     help="also time the 3,000,000-atom box (median of 20 force calls)")
     ap.add_argument("--no-batch", action="store_true")
@@ -265,8 +277,12 @@ def main():
     dev = "cuda:0"
     inst = synth.mid()
     cluster = args.cluster or 8
+    flav = dict(elec=nb.NB_ELEC_RF if args.elec == "rf" else nb.NB_ELEC_EWALD,
+                vdw=nb.NB_VDW_FSWITCH if args.vdw == "fswitch" else nb.NB_VDW_SHIFT,
+                rswitch=args.rswitch if args.vdw == "fswitch" else 0.0)
+    flops_per_pair = FLOPS_PER_PAIR_FLAVOUR[(args.elec, args.vdw)]
     params = nb.Params.from_instance(inst, cluster=cluster,
-                                     flags=nb.NB_ENERGY_FP64 if args.energy_fp64 else 0)
+                                     flags=nb.NB_ENERGY_FP64 if args.energy_fp64 else 0, **flav)
     ctx = nb.nb_setup(params)
     n = inst.natoms
     nsteps = args.warmup + args.steps
@@ -330,9 +346,10 @@ def main():
     kms, klaunch = nb.nb_get_timing(ctx)
     nb.nb_set_timing(ctx, False)
     kernel_us = 1e3 * kms / klaunch
-    achieved = FLOPS_PER_PAIR * useful / (kernel_us * 1e-6) / 1e12
+    achieved = flops_per_pair * useful / (kernel_us * 1e-6) / 1e12
     traffic = counted = None
-    if cluster == 8 and not args.energy_fp64 and _counters_current():
+    default_flavour = args.elec == "ewald" and args.vdw == "shift"
+    if cluster == 8 and not args.energy_fp64 and default_flavour and _counters_current():
         traffic = K_FORCE_COUNTERS["read_bytes"] + K_FORCE_COUNTERS["write_bytes"]
         counted = K_FORCE_COUNTERS["counted_fp32_flop"] / (kernel_us * 1e-6) / 1e12
 
@@ -354,6 +371,8 @@ def main():
                                "rebuild every 10 calls",
                    "natoms": n, "cluster": cluster, "useful_pairs": useful,
                    "energy": "fp64 pair energies" if args.energy_fp64 else "fp32 pair energies, fp64 sums",
+                   "interactions": ("Ewald real space" if args.elec == "ewald" else "reaction field (eps_rf inf)")
+                   + (", LJ potential shift" if args.vdw == "shift" else f", LJ force switch from {args.rswitch} nm"),
                    "evaluated_pairs": stats["evaluated_pairs"], "list_entries": stats["nentries"]},
         "us_per_force_call": us_force,
         "us_per_list_build": us_build,
@@ -361,7 +380,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
                      "traffic": traffic, "kernel": "k_force", "kernel_us": kernel_us,
-                     "flops_per_pair": FLOPS_PER_PAIR, "counted_fp32_tflops": counted},
+                     "flops_per_pair": flops_per_pair, "counted_fp32_tflops": counted},
     }
     nb.nb_destroy(ctx)
     if not args.no_adjoint:

@@ -60,13 +60,31 @@ typedef enum nb_status {
 /* flags (nb_params.flags and per-call flags) */
 #define NB_MAX_EXCL_PER_ATOM 32 /* excluded partners per atom accepted by nb_setup */
 
+/* Interaction flavours (nb_params.elec, nb_params.vdw).  Every pair term is cut at rc and
+ * shifted so that its energy is zero there.
+ *   NB_ELEC_EWALD   real-space Ewald:  fC q_i q_j (erfc(beta r)/r - erfc(beta rc)/rc)
+ *   NB_ELEC_RF      reaction field:    fC q_i q_j (1/r + k_rf r^2 - c_rf),
+ *                   k_rf = (eps_rf - 1) / ((2 eps_rf + 1) rc^3)  (1 / (2 rc^3) for eps_rf = 0,
+ *                   meaning infinity), c_rf = 1/rc + k_rf rc^2
+ *   NB_VDW_SHIFT    C12 (r^-12 - rc^-12) - C6 (r^-6 - rc^-6)
+ *   NB_VDW_FSWITCH  the force of each power r^-a (a = 6, 12) is switched smoothly to zero
+ *                   between rswitch and rc: a r^-(a+1) + A_a (r - rswitch)^2 + B_a (r - rswitch)^3
+ *                   beyond rswitch, with A_a, B_a making the force and its derivative vanish at
+ *                   rc; the potential is the matching integral, shifted to zero at rc. */
+#define NB_ELEC_EWALD   0
+#define NB_ELEC_RF      1
+#define NB_VDW_SHIFT    0
+#define NB_VDW_FSWITCH  1
+
 #define NB_CHECK_STALE  0x1u  /* nb_forces records whether any atom moved >= buffer/2 */
 #define NB_CHECK_FINITE 0x2u  /* nb_forces records non-finite coordinates */
 #define NB_REUSE_LIST   0x4u  /* nb_backward: use the current list instead of rebuilding */
 #define NB_ASYNC_BUILD  0x8u  /* nb_pairlist: do not wait for the overflow check */
 #define NB_ENERGY_FP64  0x10u /* evaluate the Coulomb pair energies in FP64 (forces stay FP32):
                                  needed for 1e-6 relative E_C in boxes of a few thousand atoms,
-                                 where FP32 pair-energy rounding does not average out */
+                                 where FP32 pair-energy rounding does not average out
+                                 (for the reaction field, whose terms do not decay towards rc,
+                                 also in larger boxes) */
 
 typedef struct nb_params {
     double box[3];          /* rectangular box edges Lx, Ly, Lz (nm), > 0 */
@@ -83,6 +101,10 @@ typedef struct nb_params {
                              * at most NB_MAX_EXCL_PER_ATOM per atom */
     uint32_t flags;         /* NB_CHECK_*, NB_ASYNC_BUILD, NB_ENERGY_FP64 */
     int32_t cluster;        /* cluster size C of the list: 4 or 8 (0 = 8) */
+    int32_t elec;           /* NB_ELEC_EWALD (ewald_beta used) or NB_ELEC_RF */
+    int32_t vdw;            /* NB_VDW_SHIFT or NB_VDW_FSWITCH */
+    double epsilon_rf;      /* reaction-field dielectric: 0 (infinity) or >= 1 */
+    double rswitch;         /* force-switch start, 0 <= rswitch < cutoff (NB_VDW_FSWITCH) */
 } nb_params;
 
 typedef struct nb_stats {
@@ -147,6 +169,7 @@ int nb_check(nb_ctx *ctx);
  * derivative of sqrt(eps_a eps_b) does not exist there).  The first call allocates the adjoint
  * work buffers; later calls with NB_REUSE_LIST enqueue kernels only (g_e is read on the device,
  * no host synchronisation), while a list rebuild synchronises once as nb_pairlist does.
+ * Defined for NB_ELEC_EWALD with NB_VDW_SHIFT (NB_ERR_ARG for other flavours).
  * Errors: as nb_pairlist and nb_forces. */
 int nb_backward(nb_ctx *ctx, const float *x, const float *q, const int32_t *type,
                 const float *g_f, const double *g_e, float *dx, float *dq, double *dsigma,

@@ -24,6 +24,19 @@
  *   sigma_ab = (sigma_a + sigma_b) / 2, eps_ab = sqrt(eps_a eps_b).
  *   Excluded pairs contribute nothing (no reciprocal-space exclusion correction here).
  *
+ * Other flavours (oracle_set_flavor; the paper's runs also use reaction-field electrostatics and
+ * force-switched Lennard-Jones, section IV):
+ *   reaction field, dielectric eps_rf (0 = infinity):
+ *     k_rf = (eps_rf - 1) / ((2 eps_rf + 1) rc^3)  (1 / (2 rc^3) for eps_rf = 0),
+ *     c_rf = 1/rc + k_rf rc^2,
+ *     E_C,ij = fC q_i q_j (1/r + k_rf r^2 - c_rf),  F_C,ij = fC q_i q_j (1/r^3 - 2 k_rf) d;
+ *   force switch from r1 to rc, for each power r^-a of the LJ form (a = 6, 12) with t = r - r1:
+ *     force  a r^-(a+1) + A_a t^2 + B_a t^3 for t > 0 (a r^-(a+1) otherwise),
+ *     A_a = -a ((a+4) rc - (a+1) r1) / (rc^(a+2) (rc - r1)^2),
+ *     B_a =  a ((a+3) rc - (a+1) r1) / (rc^(a+2) (rc - r1)^3),
+ *     potential r^-a - (A_a/3) t^3 - (B_a/4) t^4 - K_a, K_a its value at rc without K_a;
+ *     E_LJ,ij = C12 Phi_12 - C6 Phi_6,  F_LJ,ij = (C12 F_12 - C6 F_6) d / r.
+ *
  * Everything is FP64 with libm erfc/exp.  Loops are plain: a full double loop over atoms
  * (each unordered pair visited twice, each visit adding only to atom i) or the same loop over
  * 27 neighbouring cells.  Parallelism is an OpenMP loop over i with no shared writes.
@@ -88,6 +101,28 @@ static int is_excluded(int i, int j, const int *off, const int *idx) {
     return 0;
 }
 
+/* Interaction flavour: 0 = Ewald real space / LJ potential shift (the default); see above. */
+static int g_elec = 0, g_vdw = 0;
+static double g_eps_rf = 0.0, g_rswitch = 0.0;
+
+void oracle_set_flavor(int elec, int vdw, double eps_rf, double rswitch) {
+    g_elec = elec;
+    g_vdw = vdw;
+    g_eps_rf = eps_rf;
+    g_rswitch = rswitch;
+}
+
+/* Force-switched power r^-a: potential (shifted to zero at rc) and force magnitude at r. */
+static void switched_power(double a, double r, double r1, double rc, double *phi, double *force) {
+    double d = rc - r1;
+    double A = -a * ((a + 4.0) * rc - (a + 1.0) * r1) / (pow(rc, a + 2.0) * d * d);
+    double B = a * ((a + 3.0) * rc - (a + 1.0) * r1) / (pow(rc, a + 2.0) * d * d * d);
+    double K = pow(rc, -a) - A / 3.0 * d * d * d - B / 4.0 * d * d * d * d;
+    double t = r > r1 ? r - r1 : 0.0;
+    *phi = pow(r, -a) - A / 3.0 * t * t * t - B / 4.0 * t * t * t * t - K;
+    *force = a * pow(r, -a - 1.0) + A * t * t + B * t * t * t;
+}
+
 /* Energies (shifted LJ, shifted and unshifted Coulomb) and the force factor f with
  * F_ij = f * d for one pair at distance r < rc. */
 typedef struct {
@@ -99,12 +134,31 @@ static pair_out pair_terms(double r, double c6, double c12, double qq, double rc
     pair_out o;
     double ir = 1.0 / r, ir2 = ir * ir, ir6 = ir2 * ir2 * ir2;
     double irc = 1.0 / rc, irc6 = irc * irc * irc * irc * irc * irc;
-    o.elj = c12 * (ir6 * ir6 - irc6 * irc6) - c6 * (ir6 - irc6);
-    double flj = 12.0 * c12 * ir6 * ir6 * ir2 - 6.0 * c6 * ir6 * ir2;
-    double ercf = erfc(beta * r);
-    o.ec_unshifted = fc * qq * ercf * ir;
-    o.ec = fc * qq * (ercf * ir - erfc(beta * rc) * irc);
-    double fcoul = fc * qq * (ercf * ir2 * ir + TWO_OVER_SQRT_PI * beta * exp(-beta * beta * r * r) * ir2);
+    double flj;
+    if (g_vdw == 0) {
+        o.elj = c12 * (ir6 * ir6 - irc6 * irc6) - c6 * (ir6 - irc6);
+        flj = 12.0 * c12 * ir6 * ir6 * ir2 - 6.0 * c6 * ir6 * ir2;
+    } else {
+        double p6, f6, p12, f12;
+        switched_power(6.0, r, g_rswitch, rc, &p6, &f6);
+        switched_power(12.0, r, g_rswitch, rc, &p12, &f12);
+        o.elj = c12 * p12 - c6 * p6;
+        flj = (c12 * f12 - c6 * f6) * ir;
+    }
+    double fcoul;
+    if (g_elec == 0) {
+        double ercf = erfc(beta * r);
+        o.ec_unshifted = fc * qq * ercf * ir;
+        o.ec = fc * qq * (ercf * ir - erfc(beta * rc) * irc);
+        fcoul = fc * qq * (ercf * ir2 * ir + TWO_OVER_SQRT_PI * beta * exp(-beta * beta * r * r) * ir2);
+    } else {
+        double krf = g_eps_rf == 0.0 ? 0.5 / (rc * rc * rc)
+                                     : (g_eps_rf - 1.0) / ((2.0 * g_eps_rf + 1.0) * rc * rc * rc);
+        double crf = 1.0 / rc + krf * rc * rc;
+        o.ec_unshifted = fc * qq * (ir + krf * r * r);
+        o.ec = fc * qq * (ir + krf * r * r - crf);
+        fcoul = fc * qq * (ir2 * ir - 2.0 * krf);
+    }
     o.fscal = flj + fcoul;
     return o;
 }
@@ -344,6 +398,7 @@ int oracle_vjp(int n, const double *x, const double *q, const int *type, int nt,
                const double *sigma, const double *eps, const double *box, double rc, double beta,
                double fc, const int *eoff, const int *eidx, const double *gF, const double *gE,
                double *dx, double *dq, double *dsig, double *deps) {
+    if (g_elec != 0 || g_vdw != 0) return -2; /* defined for Ewald / potential shift only */
     double *c6 = (double *)malloc(sizeof(double) * (size_t)nt * nt);
     double *c12 = (double *)malloc(sizeof(double) * (size_t)nt * nt);
     /* per-atom partial type gradients: [n][nt] for sigma and eps, summed serially afterwards */

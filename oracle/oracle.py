@@ -55,6 +55,7 @@ def lib():
         L.oracle_vjp.argtypes = [c_i, dp, dp, ip, c_i, dp, dp, dp, c_d, c_d, c_d, ip, ip, dp, dp,
                                  dp, dp, dp, dp]
         L.oracle_vjp.restype = c_i
+        L.oracle_set_flavor.argtypes = [c_i, c_i, c_d, c_d]
         _lib = L
     return _lib
 
@@ -114,8 +115,26 @@ def _common(x, q, typ, sigma, epsilon, box, c6c12=None, round32=True):
     return n, c6, c12, bx
 
 
+class _flavor:
+    """Sets the oracle's interaction flavour for the duration of one call (Ewald real space
+    with LJ potential shift is the default state)."""
+
+    def __init__(self, elec: int, vdw: int, epsilon_rf: float, rswitch: float):
+        self.args = (int(elec), int(vdw), float(epsilon_rf), float(rswitch))
+
+    def __enter__(self):
+        lib().oracle_set_flavor(*self.args)
+
+    def __exit__(self, *exc):
+        lib().oracle_set_flavor(0, 0, 0.0, 0.0)
+        return False
+
+
 def forces(x, q, typ, sigma, epsilon, box, rc, beta, fc, excl_off=None, excl_idx=None,
-           cells: bool = False, round32: bool = True, c6c12=None) -> Result:
+           cells: bool = False, round32: bool = True, c6c12=None, elec: int = 0, vdw: int = 0,
+           epsilon_rf: float = 0.0, rswitch: float = 0.0) -> Result:
+    """elec: 0 Ewald real space, 1 reaction field (epsilon_rf, 0 = infinity); vdw: 0 potential
+    shift, 1 force switch from rswitch."""
     n, c6, c12, bx = _common(x, q, typ, sigma, epsilon, box, c6c12, round32)
     xa, xp = _d(np.asarray(x, dtype=np.float64).reshape(-1))
     qa, qp = _d(q)
@@ -133,8 +152,9 @@ def forces(x, q, typ, sigma, epsilon, box, rc, beta, fc, excl_off=None, excl_idx
     ec, ecp = _d(np.zeros(n))
     out, outp = _d(np.zeros(8))
     fn = lib().oracle_forces_cells if cells else lib().oracle_forces
-    rc_ = fn(n, xp, qp, tp, len(c6), c6p, c12p, bp, float(rc), float(beta), float(fc), op, ipp,
-             fp, elp, ecp, outp)
+    with _flavor(elec, vdw, epsilon_rf, rswitch):
+        rc_ = fn(n, xp, qp, tp, len(c6), c6p, c12p, bp, float(rc), float(beta), float(fc), op, ipp,
+                 fp, elp, ecp, outp)
     if rc_ != 0:
         raise RuntimeError("oracle_forces failed")
     return Result(f.reshape(n, 3), out, el, ec)
@@ -210,15 +230,17 @@ def vjp(x, q, typ, sigma, epsilon, box, rc, beta, fc, excl_off, excl_idx, gF, gE
 # ---- conveniences over an Instance ---------------------------------------------------------
 
 def instance_forces(inst, cells: Optional[bool] = None, x=None, q=None, sigma=None,
-                    epsilon=None, round32: bool = True) -> Result:
-    """Oracle forces/energies for an Instance (optionally with replaced x, q, sigma, eps)."""
+                    epsilon=None, round32: bool = True, elec: int = 0, vdw: int = 0,
+                    epsilon_rf: float = 0.0, rswitch: float = 0.0) -> Result:
+    """Oracle forces/energies for an Instance (optionally with replaced x, q, sigma, eps, and
+    another interaction flavour)."""
     if cells is None:
         cells = inst.natoms > 20000
     return forces(inst.x if x is None else x, inst.q if q is None else q, inst.type,
                   inst.sigma if sigma is None else sigma,
                   inst.epsilon if epsilon is None else epsilon, inst.box, inst.cutoff,
                   inst.beta, inst.coulomb_const, inst.excl_off, inst.excl_idx, cells=cells,
-                  round32=round32)
+                  round32=round32, elec=elec, vdw=vdw, epsilon_rf=epsilon_rf, rswitch=rswitch)
 
 
 def loss(inst, x, q, sigma, epsilon, f_target, e_target, cells: bool = False):

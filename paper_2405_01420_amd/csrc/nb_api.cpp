@@ -57,10 +57,30 @@ int estimate_cap(double natoms, const double *box, int C, double rlist) {
     return (cap + 31) & ~31;
 }
 
+// Force-switch constants for the power r^-a between r1 and rc: the force a r^-(a+1) gains
+// A t^2 + B t^3 (t = r - r1) so that it and its derivative vanish at rc; the potential
+// r^-a - (A/3) t^3 - (B/4) t^4 is shifted by its value at rc.
+struct fswitch_c {
+    double A, B, shift;
+};
+fswitch_c fswitch_consts(double a, double r1, double rc) {
+    const double d = rc - r1;
+    fswitch_c k;
+    k.A = -a * ((a + 4.0) * rc - (a + 1.0) * r1) / (pow(rc, a + 2.0) * d * d);
+    k.B = a * ((a + 3.0) * rc - (a + 1.0) * r1) / (pow(rc, a + 2.0) * d * d * d);
+    k.shift = pow(rc, -a) - k.A / 3.0 * d * d * d - k.B / 4.0 * d * d * d * d;
+    return k;
+}
+
 void lj_table(nb_ctx *c, std::vector<float4> &tab) {
     const int nt = c->ntypes;
     tab.assign(2 * nt * nt, make_float4(0, 0, 0, 0));
-    const double irc6 = 1.0 / pow(c->rc, 6.0);
+    // potential shift of the r^-6 and r^-12 parts (their value at rc)
+    double irc6 = 1.0 / pow(c->rc, 6.0), irc12 = irc6 * irc6;
+    if (c->vdw == NB_VDW_FSWITCH) {
+        irc6 = fswitch_consts(6.0, c->rsw, c->rc).shift;
+        irc12 = fswitch_consts(12.0, c->rsw, c->rc).shift;
+    }
     for (int a = 0; a < nt; ++a)
         for (int b = 0; b < nt; ++b) {
             double s = 0.5 * (c->sigma[a] + c->sigma[b]);
@@ -68,7 +88,7 @@ void lj_table(nb_ctx *c, std::vector<float4> &tab) {
             double s6 = s * s * s * s * s * s;
             double c6 = 4.0 * e * s6, c12 = 4.0 * e * s6 * s6;
             float c6f = (float)c6, c12f = (float)c12;
-            double sh = (double)c12f * irc6 * irc6 - (double)c6f * irc6;
+            double sh = (double)c12f * irc12 - (double)c6f * irc6;
             // two float4 per type pair, side by side: one address serves both LDS reads
             tab[2 * (a * nt + b)] = make_float4(c6f, c12f, (float)(6.0 * c6), (float)(12.0 * c12));
             tab[2 * (a * nt + b) + 1] = make_float4((float)sh, s > 0.0 ? (float)(1.0 / s) : 0.0f, 0.0f, 0.0f);
@@ -91,6 +111,36 @@ void set_constants(nb_ctx *c) {
     }
     fp.ntypes = c->ntypes;
     c->shift_coul = erfc(beta * c->rc) / c->rc;
+    if (c->elec == NB_ELEC_RF) {
+        const double rc = c->rc;
+        const double krf = c->eps_rf == 0.0 ? 0.5 / (rc * rc * rc)
+                                            : (c->eps_rf - 1.0) / ((2.0 * c->eps_rf + 1.0) * rc * rc * rc);
+        fp.krf = (float)krf;
+        fp.krf_d = krf;
+        // c_rf; the FP32-energy path sums q_i q_j without fC, so fC goes into the shift there
+        c->shift_coul = (1.0 / rc + krf * rc * rc) * ((c->flags & NB_ENERGY_FP64) ? 1.0 : (double)fp.fc);
+    }
+    fp.lj_k6 = pow(c->rc, -6.0);
+    fp.lj_k12 = pow(c->rc, -12.0);
+    if (c->vdw == NB_VDW_FSWITCH) {
+        const fswitch_c k6 = fswitch_consts(6.0, c->rsw, c->rc), k12 = fswitch_consts(12.0, c->rsw, c->rc);
+        fp.lj_k6 = k6.shift;
+        fp.lj_k12 = k12.shift;
+        fp.sw_r1_d = c->rsw;
+        fp.sw_ea6_d = k6.A / 3.0;
+        fp.sw_eb6_d = k6.B / 4.0;
+        fp.sw_ea12_d = k12.A / 3.0;
+        fp.sw_eb12_d = k12.B / 4.0;
+        fp.sw_r1 = (float)c->rsw;
+        fp.sw_a6 = (float)k6.A;
+        fp.sw_b6 = (float)k6.B;
+        fp.sw_a12 = (float)k12.A;
+        fp.sw_b12 = (float)k12.B;
+        fp.sw_ea6 = (float)(k6.A / 3.0);
+        fp.sw_eb6 = (float)(k6.B / 4.0);
+        fp.sw_ea12 = (float)(k12.A / 3.0);
+        fp.sw_eb12 = (float)(k12.B / 4.0);
+    }
     fp.b2 = (float)(beta * beta);
     fp.irc6 = (float)pow(c->rc, -6.0);
     fp.irc12 = (float)pow(c->rc, -12.0);
@@ -209,6 +259,12 @@ int nb_validate_params(const nb_params *p) {
     if (p->cluster != 0 && p->cluster != 4 && p->cluster != 8) return fail(nullptr, NB_ERR_ARG, "cluster must be 0, 4 or 8");
     if (p->flags & ~(NB_CHECK_STALE | NB_CHECK_FINITE | NB_ASYNC_BUILD | NB_ENERGY_FP64))
         return fail(nullptr, NB_ERR_ARG, "unknown flag bits");
+    if (p->elec != NB_ELEC_EWALD && p->elec != NB_ELEC_RF) return fail(nullptr, NB_ERR_ARG, "elec must be NB_ELEC_EWALD or NB_ELEC_RF");
+    if (p->vdw != NB_VDW_SHIFT && p->vdw != NB_VDW_FSWITCH) return fail(nullptr, NB_ERR_ARG, "vdw must be NB_VDW_SHIFT or NB_VDW_FSWITCH");
+    if (p->elec == NB_ELEC_RF && !(isfinite(p->epsilon_rf) && (p->epsilon_rf == 0.0 || p->epsilon_rf >= 1.0)))
+        return fail(nullptr, NB_ERR_ARG, "epsilon_rf must be 0 (infinity) or >= 1");
+    if (p->vdw == NB_VDW_FSWITCH && !(isfinite(p->rswitch) && p->rswitch >= 0.0 && p->rswitch < p->cutoff))
+        return fail(nullptr, NB_ERR_ARG, "rswitch must be in [0, cutoff)");
     if (p->excl_off) {
         if (p->excl_off[0] != 0) return fail(nullptr, NB_ERR_ARG, "excl_off[0] must be 0");
         for (int i = 0; i < p->natoms; ++i)
@@ -242,6 +298,10 @@ int nb_setup(nb_ctx **out, const nb_params *p, void *stream) {
     c->rc = p->cutoff;
     c->rb = p->buffer;
     c->beta = p->ewald_beta;
+    c->elec = p->elec;
+    c->vdw = p->vdw;
+    c->eps_rf = p->epsilon_rf;
+    c->rsw = p->rswitch;
     c->fc = p->coulomb_const;
     c->flags = p->flags;
     c->sigma.assign(p->sigma, p->sigma + p->ntypes);
@@ -520,6 +580,8 @@ int nb_backward(nb_ctx *c, const float *x, const float *q, const int32_t *type, 
                 uint32_t flags) {
     if (!c || !x || !q || !type || !g_f || !g_e || !dx || !dq || !dsigma || !deps)
         return fail(c, NB_ERR_ARG, "NULL argument");
+    if (c->elec != NB_ELEC_EWALD || c->vdw != NB_VDW_SHIFT)
+        return fail(c, NB_ERR_ARG, "nb_backward supports NB_ELEC_EWALD with NB_VDW_SHIFT only");
     hipSetDevice(c->device);
     if (!(flags & NB_REUSE_LIST) || !c->have_list) {
         int r = nb_pairlist(c, x);

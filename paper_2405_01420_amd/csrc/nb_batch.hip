@@ -41,6 +41,7 @@ struct nb_batch {
     double shift_coul = 0;
     float4 *ljtab = nullptr;  // the LJ table of box 0 (identical for all boxes)
     bool eprec = false;       // FP64 Coulomb energies (tables of box 0)
+    int flav = 0;             // NB_FLAV(elec, vdw) of all boxes
     double2 *etab = nullptr;
     int etab_n = 0;
     float etab_invh = 0.0f;
@@ -95,7 +96,7 @@ __global__ void k_batch_pack(const nb_box_desc *__restrict__ desc, const float *
 
 // Persistent force kernel: every wavefront loops, taking the next chunk of work items from the
 // queue, until the queue is empty; every wave reaches that exit.
-template <int C, bool EPREC>
+template <int C, bool EPREC, int FLAV>
 __global__ void __launch_bounds__(256) NB_FORCE_OCCUPANCY k_batch_force(nb_fparams fp, const nb_box_desc *__restrict__ desc,
                                                      const int2 *__restrict__ items,
                                                      const int *__restrict__ chunks, int nchunks,
@@ -135,7 +136,7 @@ __global__ void __launch_bounds__(256) NB_FORCE_OCCUPANCY k_batch_force(nb_fpara
             f.L[1] = d.L[1];
             f.L[2] = d.L[2];
             // the descriptor's pointers are global memory; typed so, their accesses are global
-            nb_force_cluster<C, EPREC>(f, tab, et, ci, 0, 1 << 20, ci, d.cap, d.npad_max,
+            nb_force_cluster<C, EPREC, FLAV>(f, tab, et, ci, 0, 1 << 20, ci, d.cap, d.npad_max,
                                        nb_g(d.xq), nb_g(d.tsort), nb_g(d.icount), nb_g(d.jl),
                                        nb_g(d.fj), nb_g(d.epart));
         }
@@ -243,11 +244,40 @@ int grid_for(nb_batch *bt) {
     int per_cu = bt->blocks_per_cu;
     if (per_cu <= 0) {
         hipError_t e = bt->eprec
-                           ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_force<C, true>, 256, batch_shm(bt))
-                           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_force<C, false>, 256, batch_shm(bt));
+                           ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_force<C, true, 0>, 256, batch_shm(bt))
+                           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_force<C, false, 0>, 256, batch_shm(bt));
         if (e != hipSuccess || per_cu <= 0) per_cu = 1;
     }
     return per_cu * prop.multiProcessorCount;
+}
+
+template <int C, bool EPREC, int FLAV>
+void launch_batch_t(nb_batch *bt, int s) {
+    hipLaunchKernelGGL((k_batch_force<C, EPREC, FLAV>), dim3(bt->grid[s]), dim3(256), batch_shm(bt),
+                       bt->stream, bt->fp, bt->d_desc, bt->d_items[s], bt->d_chunks[s], bt->nchunks[s],
+                       bt->ljtab, bt->etab, bt->etab_n, bt->etab_invh, bt->d_counter + s);
+}
+
+template <int C>
+void launch_batch_c(nb_batch *bt, int s) {
+    switch (bt->flav) {
+    case NB_FLAV(NB_ELEC_EWALD, NB_VDW_SHIFT):
+        if (bt->eprec) launch_batch_t<C, true, NB_FLAV(NB_ELEC_EWALD, NB_VDW_SHIFT)>(bt, s);
+        else launch_batch_t<C, false, NB_FLAV(NB_ELEC_EWALD, NB_VDW_SHIFT)>(bt, s);
+        break;
+    case NB_FLAV(NB_ELEC_EWALD, NB_VDW_FSWITCH):
+        if (bt->eprec) launch_batch_t<C, true, NB_FLAV(NB_ELEC_EWALD, NB_VDW_FSWITCH)>(bt, s);
+        else launch_batch_t<C, false, NB_FLAV(NB_ELEC_EWALD, NB_VDW_FSWITCH)>(bt, s);
+        break;
+    case NB_FLAV(NB_ELEC_RF, NB_VDW_SHIFT):
+        if (bt->eprec) launch_batch_t<C, true, NB_FLAV(NB_ELEC_RF, NB_VDW_SHIFT)>(bt, s);
+        else launch_batch_t<C, false, NB_FLAV(NB_ELEC_RF, NB_VDW_SHIFT)>(bt, s);
+        break;
+    default:
+        if (bt->eprec) launch_batch_t<C, true, NB_FLAV(NB_ELEC_RF, NB_VDW_FSWITCH)>(bt, s);
+        else launch_batch_t<C, false, NB_FLAV(NB_ELEC_RF, NB_VDW_FSWITCH)>(bt, s);
+        break;
+    }
 }
 
 hipError_t launch_forces(nb_batch *bt, const float *x, const float *q, const int32_t *type, float *f,
@@ -255,21 +285,8 @@ hipError_t launch_forces(nb_batch *bt, const float *x, const float *q, const int
     const int tb = 256;
     hipLaunchKernelGGL(k_batch_pack, dim3((bt->max_npad + tb - 1) / tb, bt->nbox), dim3(tb), 0,
                        bt->stream, bt->d_desc, x, q, type, bt->ntypes, bt->d_counter);
-    const size_t shm = batch_shm(bt);
-#define NB_BATCH_LAUNCH(CC, EP, S)                                                                  \
-    hipLaunchKernelGGL((k_batch_force<CC, EP>), dim3(bt->grid[S]), dim3(256), shm, bt->stream, bt->fp, \
-                       bt->d_desc, bt->d_items[S], bt->d_chunks[S], bt->nchunks[S], bt->ljtab,      \
-                       bt->etab, bt->etab_n,                                                        \
-                       bt->etab_invh, bt->d_counter + S)
-    if (bt->nitems[0] > 0) {
-        if (bt->eprec) NB_BATCH_LAUNCH(4, true, 0);
-        else NB_BATCH_LAUNCH(4, false, 0);
-    }
-    if (bt->nitems[1] > 0) {
-        if (bt->eprec) NB_BATCH_LAUNCH(8, true, 1);
-        else NB_BATCH_LAUNCH(8, false, 1);
-    }
-#undef NB_BATCH_LAUNCH
+    if (bt->nitems[0] > 0) launch_batch_c<4>(bt, 0);
+    if (bt->nitems[1] > 0) launch_batch_c<8>(bt, 1);
     hipLaunchKernelGGL(k_batch_finalize, dim3((bt->max_natoms + tb - 1) / tb, bt->nbox), dim3(tb), 0,
                        bt->stream, bt->d_desc, f);
     hipLaunchKernelGGL(k_batch_energy, dim3(bt->nbox), dim3(256), 0, bt->stream, bt->d_desc,
@@ -340,6 +357,7 @@ int nb_batch_setup(nb_batch **out, int32_t nbox, const int32_t *atom_off, const 
     bt->shift_coul = bt->box[0]->shift_coul;
     bt->ljtab = bt->box[0]->ljtab;
     bt->eprec = (common->flags & NB_ENERGY_FP64) != 0;
+    bt->flav = NB_FLAV(common->elec, common->vdw);
     bt->etab = bt->box[0]->etab;
     bt->etab_n = bt->box[0]->etab_n;
     bt->etab_invh = bt->box[0]->etab_invh;

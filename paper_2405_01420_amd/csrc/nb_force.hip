@@ -57,7 +57,7 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-template <int C, bool EPREC>
+template <int C, bool EPREC, int FLAV>
 __global__ void __launch_bounds__(256) NB_FORCE_OCCUPANCY k_force(nb_fparams fp, int cap, int npad_max,
                                                const float4 *__restrict__ xq,
                                                const int *__restrict__ tsort,
@@ -85,7 +85,7 @@ __global__ void __launch_bounds__(256) NB_FORCE_OCCUPANCY k_force(nb_fparams fp,
                                                  threadIdx.x / NB_WAVE);
     if (u >= meta->nunits) return;
     const int4 w = units[u];
-    nb_force_cluster<C, EPREC>(fp, tab, et, __builtin_amdgcn_readfirstlane(w.x),
+    nb_force_cluster<C, EPREC, FLAV>(fp, tab, et, __builtin_amdgcn_readfirstlane(w.x),
                                __builtin_amdgcn_readfirstlane(w.y), __builtin_amdgcn_readfirstlane(w.z),
                                __builtin_amdgcn_readfirstlane(w.w), cap, npad_max, nb_g(xq),
                                nb_g(tsort), nb_g(icount), nb_g(jl), nb_g(fj), nb_g(epart));
@@ -166,25 +166,42 @@ hipError_t nb_launch_pack(nb_ctx *c, const float *x, const float *q, const int32
     return hipGetLastError();
 }
 
-template <int C, bool EPREC>
+template <int C, bool EPREC, int FLAV>
 static void launch_force_t(nb_ctx *c) {
     const size_t shm = sizeof(float4) * 2 * c->ntypes * c->ntypes +
                        (EPREC ? sizeof(double2) * 2 * c->etab_n : 0);
     dim3 grid((c->unit_cap + 3) / 4), block(256);
-    hipLaunchKernelGGL((k_force<C, EPREC>), grid, block, shm, c->stream, c->fp, c->cap, c->npad_max,
+    hipLaunchKernelGGL((k_force<C, EPREC, FLAV>), grid, block, shm, c->stream, c->fp, c->cap, c->npad_max,
                        c->xq, c->tsort, c->ljtab, c->etab, c->etab_n, c->etab_invh, c->icount,
                        c->jl, c->units, c->fj, c->epart, c->meta);
 }
 
-hipError_t nb_launch_force(nb_ctx *c) {
+template <int C>
+static void launch_force_c(nb_ctx *c) {
     const bool ep = (c->flags & NB_ENERGY_FP64) != 0;
-    if (c->C == 4) {
-        if (ep) launch_force_t<4, true>(c);
-        else launch_force_t<4, false>(c);
-    } else {
-        if (ep) launch_force_t<8, true>(c);
-        else launch_force_t<8, false>(c);
+    switch (NB_FLAV(c->elec, c->vdw)) {
+    case NB_FLAV(NB_ELEC_EWALD, NB_VDW_SHIFT):
+        if (ep) launch_force_t<C, true, NB_FLAV(NB_ELEC_EWALD, NB_VDW_SHIFT)>(c);
+        else launch_force_t<C, false, NB_FLAV(NB_ELEC_EWALD, NB_VDW_SHIFT)>(c);
+        break;
+    case NB_FLAV(NB_ELEC_EWALD, NB_VDW_FSWITCH):
+        if (ep) launch_force_t<C, true, NB_FLAV(NB_ELEC_EWALD, NB_VDW_FSWITCH)>(c);
+        else launch_force_t<C, false, NB_FLAV(NB_ELEC_EWALD, NB_VDW_FSWITCH)>(c);
+        break;
+    case NB_FLAV(NB_ELEC_RF, NB_VDW_SHIFT):
+        if (ep) launch_force_t<C, true, NB_FLAV(NB_ELEC_RF, NB_VDW_SHIFT)>(c);
+        else launch_force_t<C, false, NB_FLAV(NB_ELEC_RF, NB_VDW_SHIFT)>(c);
+        break;
+    default:
+        if (ep) launch_force_t<C, true, NB_FLAV(NB_ELEC_RF, NB_VDW_FSWITCH)>(c);
+        else launch_force_t<C, false, NB_FLAV(NB_ELEC_RF, NB_VDW_FSWITCH)>(c);
+        break;
     }
+}
+
+hipError_t nb_launch_force(nb_ctx *c) {
+    if (c->C == 4) launch_force_c<4>(c);
+    else launch_force_c<8>(c);
     return hipGetLastError();
 }
 

@@ -17,10 +17,10 @@
 //  * per-pair energies are summed in FP32 over the C pairs of a lane's batch and accumulated in
 //    FP64 from there on; the Coulomb potential
 //    shift is applied in FP64 at the end from the sum of q_i q_j over interacting pairs;
-//  * with EPREC the Coulomb pair energy is instead evaluated in FP64 (exact displacement,
+//  * with EPREC the pair energies are instead evaluated in FP64 (exact displacement,
 //    Newton-refined 1/r, erfc from an FP64 cubic Hermite table), forces staying FP32: the FP32
-//    rounding noise of the pair energies is otherwise not averaged below 1e-6 of a Coulomb
-//    energy that is a 4e-4-conditioned sum, in boxes of a few thousand atoms.
+//    rounding noise of the pair energies is otherwise not averaged below 1e-6 of an energy
+//    that is a 1e-4 .. 1e-3-conditioned sum, in boxes of a few thousand atoms.
 #pragma once
 #include "nb_device.h"
 
@@ -55,14 +55,18 @@ struct nb_etab {
 
 // All C pairs (i-atom k, the lane's j-atom) of one batch.  xs/ys/zs hold the i-coordinates
 // already moved into the pair frame (uniform over the wave in the fast path).  MASKED applies
-// the topology mask; without it every unordered pair within rc interacts.
-template <int C, bool MASKED, bool EPREC>
+// the topology mask; without it every unordered pair within rc interacts.  FLAV selects the
+// electrostatics (Ewald real space or reaction field) and the Lennard-Jones cutoff treatment
+// (potential shift or force switch), NB_FLAV(elec, vdw).
+template <int C, bool MASKED, bool EPREC, int FLAV>
 __device__ __forceinline__ void pair_block(const nb_fparams &fp, const float4 *tab, int ntt,
                                            const nb_etab &et, const float *xs, const float *ys,
                                            const float *zs, const float *qi, const int *ti,
                                            nb_jlane &j, float *fix, float *fiy, float *fiz,
                                            double &elj, double &ec, float &qqs, double &qqsd,
                                            float p4v, float q5v) {
+    constexpr bool RF = FLAV / 2 == NB_ELEC_RF;
+    constexpr bool FSW = FLAV % 2 == NB_VDW_FSWITCH;
     // FP32 partial sums of the batch's C pair energies, added to the FP64 sums once per batch
     // (starting from -0 lets the first addition fold away)
     float eljb = -0.0f, ecb = -0.0f;
@@ -81,52 +85,102 @@ __device__ __forceinline__ void pair_block(const nb_fparams &fp, const float4 *t
         const float shv = ljp[1].x;
         // Lennard-Jones: energy C12 r^-12 - C6 r^-6 - shift, force factor (12 C12 r^-6 - 6 C6) r^-8
         const float u = __builtin_fmaf(lj.y, rinv6, -lj.x);
-        const float elj_p = inc ? __builtin_fmaf(u, rinv6, -shv) : 0.0f;
+        float elj_p = inc ? __builtin_fmaf(u, rinv6, -shv) : 0.0f;
         const float tf = __builtin_fmaf(lj.w, rinv6, -lj.z);
-        const float flj = tf * rinv6;
-        // Ewald real space: erfc(beta r) = exp(-beta^2 r^2) P(r) / Q(r)
-        const float r = r2 * rinv;
-        const float ex = __builtin_amdgcn_exp2f(fp.cexp * r2);
-        float P = __builtin_fmaf(p4v, r, fp.p[3]);
-        P = __builtin_fmaf(P, r, fp.p[2]);
-        P = __builtin_fmaf(P, r, fp.p[1]);
-        P = __builtin_fmaf(P, r, fp.p[0]);
-        float Q = __builtin_fmaf(q5v, r, fp.q[4]);
-        Q = __builtin_fmaf(Q, r, fp.q[3]);
-        Q = __builtin_fmaf(Q, r, fp.q[2]);
-        Q = __builtin_fmaf(Q, r, fp.q[1]);
-        Q = __builtin_fmaf(Q, r, fp.q[0]);
-        // refined reciprocal: the raw one's error pattern follows Q(r) and does not average out
-        const float R = P * nb_rcp(Q);
-        const float qq = qi[k] * j.q;             // fC q_i q_j
-        const float qe = qq * ex;
-        const float t1 = qe * rinv;               // fC q_i q_j exp(-b^2 r^2) / r
-        const float uu = __builtin_fmaf(fp.kb, r, R);
-        const float fs = __builtin_fmaf(t1, uu, flj) * rinv2;
-        eljb += elj_p;
+        float flj = tf * rinv6;
+        const float r = r2 * rinv;            // zero for non-interacting pairs
+        // FP64 pair energies (EPREC): exact displacement, 1/r refined in FP64 from the FP32 one
+        double rid = 0.0, r2d = 0.0;
         if (EPREC) {
-            // Coulomb pair energy in FP64 without fC: exact displacement, 1/r refined in FP64,
-            // erfc(beta r) from the FP64 Hermite table (segment found with the FP32 r)
             const double dxd = (double)xs[k] - j.xd;
             const double dyd = (double)ys[k] - j.yd;
             const double dzd = (double)zs[k] - j.zd;
-            const double r2d = __builtin_fma(dzd, dzd, __builtin_fma(dyd, dyd, dxd * dxd));
-            const double y = (double)rinv;      // zero for non-interacting pairs
-            const double hh = r2d * y;
-            const double ee = __builtin_fma(-hh, y, 1.0);
-            const double rid = __builtin_fma(0.5 * y, ee, y);
-            const double rd = r2d * rid;
-            const int sg = min((int)(r * et.invh), et.n - 1);
-            const double u = __builtin_fma(rd, (double)et.invh, -(double)sg);
-            const double2 c01 = et.seg[2 * sg], c23 = et.seg[2 * sg + 1];
-            const double g = __builtin_fma(__builtin_fma(__builtin_fma(c23.y, u, c23.x), u, c01.y), u, c01.x);
-            const double qqd = (double)qi[k] * j.qd;
-            ec = __builtin_fma(qqd * g, rid, ec);
-            qqsd += inc ? qqd : 0.0;
-        } else {
-            ecb = __builtin_fmaf(t1, R, ecb);     // += fC q_i q_j erfc(b r) / r
-            qqs += inc ? qq : 0.0f;
+            r2d = __builtin_fma(dzd, dzd, __builtin_fma(dyd, dyd, dxd * dxd));
+            const double y = (double)rinv;    // zero for non-interacting pairs
+            const double ee = __builtin_fma(-(r2d * y), y, 1.0);
+            rid = __builtin_fma(0.5 * y, ee, y);
+            // Lennard-Jones pair energy in FP64 (C6, C12 are the FP32 instance values)
+            const double c6d = lj.x, c12d = lj.y;
+            const double rid2 = rid * rid, rid6 = rid2 * rid2 * rid2;
+            double el = __builtin_fma(__builtin_fma(c12d, rid6, -c6d), rid6,
+                                      -__builtin_fma(c12d, fp.lj_k12, -c6d * fp.lj_k6));
+            if (FSW) {
+                const double td = fmax(r2d * rid - fp.sw_r1_d, 0.0);
+                const double e12 = __builtin_fma(fp.sw_eb12_d, td, fp.sw_ea12_d);
+                const double e6 = __builtin_fma(fp.sw_eb6_d, td, fp.sw_ea6_d);
+                el = __builtin_fma(-__builtin_fma(c12d, e12, -c6d * e6), td * td * td, el);
+            }
+            elj += inc ? el : 0.0;
         }
+        if (FSW) {
+            // force switch beyond sw_r1 (t = r - sw_r1 > 0; t = 0 for non-interacting pairs):
+            // force (C12 (A12 + B12 t) - C6 (A6 + B6 t)) t^2 added to the magnitude, and
+            // -(C12 (A12/3 + B12/4 t) - C6 (A6/3 + B6/4 t)) t^3 to the energy
+            const float t = fmaxf(r - fp.sw_r1, 0.0f);
+            const float t2 = t * t;
+            const float p12 = __builtin_fmaf(fp.sw_b12, t, fp.sw_a12);
+            const float p6 = __builtin_fmaf(fp.sw_b6, t, fp.sw_a6);
+            const float sw = __builtin_fmaf(lj.y, p12, -lj.x * p6);
+            flj = __builtin_fmaf(sw * t2, r, flj);  // the magnitude times r (the force factor carries r^-2)
+            const float e12 = __builtin_fmaf(fp.sw_eb12, t, fp.sw_ea12);
+            const float e6 = __builtin_fmaf(fp.sw_eb6, t, fp.sw_ea6);
+            const float esw = __builtin_fmaf(lj.y, e12, -lj.x * e6);
+            elj_p = __builtin_fmaf(-esw, t2 * t, elj_p);
+        }
+        const float qq = qi[k] * j.q;             // fC q_i q_j
+        float fs;
+        if (RF) {
+            // reaction field: force factor fC q q (1/r^3 - 2 k_rf), energy fC q q (1/r + k_rf r^2);
+            // c_rf is applied at the end to the sum of q_i q_j, accumulated exactly in FP64 (the
+            // product of two FP32 charges is exact there): unlike erfc(beta rc)/rc, c_rf is not
+            // small, and an FP32 running sum of the products would dominate the energy error
+            const float cr = __builtin_fmaf(-2.0f * fp.krf, r2, rinv);
+            fs = __builtin_fmaf(qq, cr, flj) * rinv2;
+            const double qqd = (double)qi[k] * j.qd;
+            qqsd += inc ? qqd : 0.0;
+            if (EPREC) {
+                // pair energy in FP64 without fC
+                const double v = __builtin_fma(fp.krf_d, r2d, rid);
+                ec = __builtin_fma(qqd, inc ? v : 0.0, ec);
+            } else {
+                const float r2m = inc ? r2 : 0.0f;
+                ecb = __builtin_fmaf(qq, __builtin_fmaf(fp.krf, r2m, rinv), ecb);
+            }
+        } else {
+            // Ewald real space: erfc(beta r) = exp(-beta^2 r^2) P(r) / Q(r)
+            const float ex = __builtin_amdgcn_exp2f(fp.cexp * r2);
+            float P = __builtin_fmaf(p4v, r, fp.p[3]);
+            P = __builtin_fmaf(P, r, fp.p[2]);
+            P = __builtin_fmaf(P, r, fp.p[1]);
+            P = __builtin_fmaf(P, r, fp.p[0]);
+            float Q = __builtin_fmaf(q5v, r, fp.q[4]);
+            Q = __builtin_fmaf(Q, r, fp.q[3]);
+            Q = __builtin_fmaf(Q, r, fp.q[2]);
+            Q = __builtin_fmaf(Q, r, fp.q[1]);
+            Q = __builtin_fmaf(Q, r, fp.q[0]);
+            // refined reciprocal: the raw one's error pattern follows Q(r) and does not average out
+            const float R = P * nb_rcp(Q);
+            const float qe = qq * ex;
+            const float t1 = qe * rinv;               // fC q_i q_j exp(-b^2 r^2) / r
+            const float uu = __builtin_fmaf(fp.kb, r, R);
+            fs = __builtin_fmaf(t1, uu, flj) * rinv2;
+            if (EPREC) {
+                // Coulomb pair energy in FP64 without fC, erfc(beta r) from the FP64 Hermite table
+                // (segment found with the FP32 r)
+                const double rd = r2d * rid;
+                const int sg = min((int)(r * et.invh), et.n - 1);
+                const double uq = __builtin_fma(rd, (double)et.invh, -(double)sg);
+                const double2 c01 = et.seg[2 * sg], c23 = et.seg[2 * sg + 1];
+                const double g = __builtin_fma(__builtin_fma(__builtin_fma(c23.y, uq, c23.x), uq, c01.y), uq, c01.x);
+                const double qqd = (double)qi[k] * j.qd;
+                ec = __builtin_fma(qqd * g, rid, ec);
+                qqsd += inc ? qqd : 0.0;
+            } else {
+                ecb = __builtin_fmaf(t1, R, ecb);     // += fC q_i q_j erfc(b r) / r
+                qqs += inc ? qq : 0.0f;
+            }
+        }
+        if (!EPREC) eljb += elj_p;
         fix[k] = __builtin_fmaf(fs, dx, fix[k]);
         fiy[k] = __builtin_fmaf(fs, dy, fiy[k]);
         fiz[k] = __builtin_fmaf(fs, dz, fiz[k]);
@@ -134,9 +188,16 @@ __device__ __forceinline__ void pair_block(const nb_fparams &fp, const float4 *t
         j.fy = __builtin_fmaf(-fs, dy, j.fy);
         j.fz = __builtin_fmaf(-fs, dz, j.fz);
     }
-    elj += (double)eljb;
-    if (!EPREC) ec += (double)ecb;
+    if (!EPREC) {
+        elj += (double)eljb;
+        ec += (double)ecb;
+    }
 }
+
+// Whether the shift weight (sum of q_i q_j over interacting pairs) is accumulated in FP64
+// without fC (FP64 energy mode, and reaction field) or in FP32 with fC (Ewald, FP32 energies).
+template <bool EPREC, int FLAV>
+constexpr bool nb_qq64() { return EPREC || FLAV / 2 == NB_ELEC_RF; }
 
 __device__ __forceinline__ float nb_uniform(float v) {
     return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
@@ -147,7 +208,7 @@ __device__ __forceinline__ float nb_uniform(float v) {
 // holds the box of the cluster.  Both the j-forces and the unit's i-force sums are added
 // atomically to fj (several units may share an i-cluster); the energy partials are stored to
 // epart[4 slot ..].
-template <int C, bool EPREC>
+template <int C, bool EPREC, int FLAV>
 __device__ __forceinline__ void nb_force_cluster(const nb_fparams &fp, const float4 *tab,
                                                  const nb_etab &et, int ci, int b0, int nbat,
                                                  int slot, int cap, int npad_max,
@@ -230,9 +291,9 @@ __device__ __forceinline__ void nb_force_cluster(const nb_fparams &fp, const flo
             }
             const bool full = __ballot(!valid || jv.mcol != FULL) == 0ull;
             if (full)
-                pair_block<C, false, EPREC>(fp, tab, ntt, et, xs, ys, zs, qi, ti, jv, fix, fiy, fiz, elj, ec, qqs, qqsd, p4v, q5v);
+                pair_block<C, false, EPREC, FLAV>(fp, tab, ntt, et, xs, ys, zs, qi, ti, jv, fix, fiy, fiz, elj, ec, qqs, qqsd, p4v, q5v);
             else
-                pair_block<C, true, EPREC>(fp, tab, ntt, et, xs, ys, zs, qi, ti, jv, fix, fiy, fiz, elj, ec, qqs, qqsd, p4v, q5v);
+                pair_block<C, true, EPREC, FLAV>(fp, tab, ntt, et, xs, ys, zs, qi, ti, jv, fix, fiy, fiz, elj, ec, qqs, qqsd, p4v, q5v);
         } else {
             // shifts differ across the batch: per-lane frame offsets
             const int tx = nb_tx(s), ty = nb_ty(s), tz = nb_tz(s);
@@ -252,7 +313,7 @@ __device__ __forceinline__ void nb_force_cluster(const nb_fparams &fp, const flo
                 yl[k] = yi[k] + diy;
                 zl[k] = zi[k] + diz;
             }
-            pair_block<C, true, EPREC>(fp, tab, ntt, et, xl, yl, zl, qi, ti, jv, fix, fiy, fiz, elj, ec, qqs, qqsd, p4v, q5v);
+            pair_block<C, true, EPREC, FLAV>(fp, tab, ntt, et, xl, yl, zl, qi, ti, jv, fix, fiy, fiz, elj, ec, qqs, qqsd, p4v, q5v);
         }
         // about 40% of the lanes of a batch have no pair within rc (their entry was kept for
         // another atom of the group, at rlist); they skip their atomics
@@ -270,7 +331,7 @@ __device__ __forceinline__ void nb_force_cluster(const nb_fparams &fp, const flo
     }
     elj = nb_wave_sum_d(elj);
     ec = nb_wave_sum_d(ec);
-    const double qqd = nb_wave_sum_d(EPREC ? qqsd : (double)qqs);
+    const double qqd = nb_wave_sum_d(nb_qq64<EPREC, FLAV>() ? qqsd : (double)qqs);
     // the unit's i-force sums (in lane 63) go to lanes 0 .. C-1, one atom each, so that three
     // atomics of C lanes add them
     float vx = 0.0f, vy = 0.0f, vz = 0.0f;

@@ -81,7 +81,18 @@ struct nb_fparams {
     float irc6, irc12;  // rc^-6, rc^-12
     float shc;          // erfc(beta rc) / rc
     int ntypes;
+    // reaction field: force factor 1/r^3 - 2 k_rf, energy 1/r + k_rf r^2 (c_rf applied at the end)
+    float krf;
+    // force switch from sw_r1 to rc: force terms A t^2 + B t^3, energy terms -(A/3) t^3 - (B/4) t^4
+    // with t = r - sw_r1, for the r^-6 and r^-12 parts
+    float sw_r1, sw_a6, sw_b6, sw_a12, sw_b12, sw_ea6, sw_eb6, sw_ea12, sw_eb12;
+    // FP64 pair-energy constants: k_rf; LJ shift constants (value at rc of the r^-6 and r^-12
+    // parts: rc^-a, or the force-switch constant); force-switch energy coefficients
+    double krf_d, lj_k6, lj_k12, sw_r1_d, sw_ea6_d, sw_eb6_d, sw_ea12_d, sw_eb12_d;
 };
+
+// Flavour of a force kernel: electrostatics * 2 + van der Waals (NB_ELEC_*, NB_VDW_*).
+#define NB_FLAV(elec, vdw) ((elec) * 2 + (vdw))
 
 // Per-type constants for the LJ-parameter gradient reduction.
 struct nb_typeparams {
@@ -95,6 +106,8 @@ struct nb_ctx {
     int natoms = 0, ntypes = 0, C = 8;
     double box[3] = {0, 0, 0};
     double rc = 0, rb = 0, beta = 0, fc = 0;
+    int elec = NB_ELEC_EWALD, vdw = NB_VDW_SHIFT;
+    double eps_rf = 0, rsw = 0;
     uint32_t flags = 0;
     nb_geom geom{};
     nb_fparams fp{};

@@ -21,6 +21,8 @@ NB_ERR_STATE, NB_ERR_OVERFLOW, NB_ERR_LIST_STALE, NB_ERR_NONFINITE, NB_ERR_IO = 
 NB_CHECK_STALE, NB_CHECK_FINITE, NB_REUSE_LIST, NB_ASYNC_BUILD = 0x1, 0x2, 0x4, 0x8
 NB_ENERGY_FP64 = 0x10
 NB_MAX_EXCL_PER_ATOM = 32
+NB_ELEC_EWALD, NB_ELEC_RF = 0, 1
+NB_VDW_SHIFT, NB_VDW_FSWITCH = 0, 1
 
 STATUS_NAMES = {0: "NB_OK", 1: "NB_ERR_ARG", 2: "NB_ERR_CUTOFF", 3: "NB_ERR_OOM", 4: "NB_ERR_HIP",
                 5: "NB_ERR_STATE", 6: "NB_ERR_OVERFLOW", 7: "NB_ERR_LIST_STALE",
@@ -44,7 +46,8 @@ class nb_params(ctypes.Structure):
                 ("coulomb_const", ctypes.c_double), ("ntypes", ctypes.c_int32),
                 ("sigma", _dp), ("epsilon", _dp), ("natoms", ctypes.c_int32),
                 ("excl_off", _ip), ("excl_idx", _ip), ("flags", ctypes.c_uint32),
-                ("cluster", ctypes.c_int32)]
+                ("cluster", ctypes.c_int32), ("elec", ctypes.c_int32), ("vdw", ctypes.c_int32),
+                ("epsilon_rf", ctypes.c_double), ("rswitch", ctypes.c_double)]
 
 
 class nb_stats(ctypes.Structure):
@@ -143,7 +146,8 @@ class Params:
 
     def __init__(self, natoms: int, box: Sequence[float], cutoff: float, buffer: float,
                  ewald_beta: float, coulomb_const: float, sigma, epsilon, excl_off=None,
-                 excl_idx=None, flags: int = 0, cluster: int = 8):
+                 excl_idx=None, flags: int = 0, cluster: int = 8, elec: int = 0, vdw: int = 0,
+                 epsilon_rf: float = 0.0, rswitch: float = 0.0):
         self.sigma = np.ascontiguousarray(sigma, dtype=np.float64)
         self.epsilon = np.ascontiguousarray(epsilon, dtype=np.float64)
         self.excl_off = None if excl_off is None else np.ascontiguousarray(excl_off, dtype=np.int32)
@@ -163,12 +167,16 @@ class Params:
         self.c.excl_idx = None if self.excl_idx is None else self.excl_idx.ctypes.data_as(_ip)
         self.c.flags = int(flags)
         self.c.cluster = int(cluster)
+        self.c.elec, self.c.vdw = int(elec), int(vdw)
+        self.c.epsilon_rf, self.c.rswitch = float(epsilon_rf), float(rswitch)
 
     @classmethod
-    def from_instance(cls, inst, flags: int = 0, cluster: int = 8, buffer: Optional[float] = None):
+    def from_instance(cls, inst, flags: int = 0, cluster: int = 8, buffer: Optional[float] = None,
+                      elec: int = 0, vdw: int = 0, epsilon_rf: float = 0.0, rswitch: float = 0.0):
         return cls(inst.natoms, [inst.box] * 3, inst.cutoff,
                    inst.buffer if buffer is None else buffer, inst.beta, inst.coulomb_const,
-                   inst.sigma, inst.epsilon, inst.excl_off, inst.excl_idx, flags, cluster)
+                   inst.sigma, inst.epsilon, inst.excl_off, inst.excl_idx, flags, cluster,
+                   elec, vdw, epsilon_rf, rswitch)
 
 
 def nb_validate_params(params: Params) -> int:
@@ -301,7 +309,8 @@ def nb_batch_destroy(bt: int) -> None:
     _bcheck(lib().nb_batch_destroy(bt))
 
 
-def concat_instances(insts, cluster: int = 8, flags: int = 0, clusters=None):
+def concat_instances(insts, cluster: int = 8, flags: int = 0, clusters=None, elec: int = 0,
+                     vdw: int = 0, epsilon_rf: float = 0.0, rswitch: float = 0.0):
     """Concatenate independent boxes into (atom_off, boxes, Params, x, q, type) for the batch
     API: exclusions are shifted to global indices, every box shares the LJ table of the first."""
     n = [i.natoms for i in insts]
@@ -318,7 +327,8 @@ def concat_instances(insts, cluster: int = 8, flags: int = 0, clusters=None):
     excl_idx = np.concatenate(ei).astype(np.int32)
     i0 = insts[0]
     params = Params(int(ao[-1]), [i0.box] * 3, i0.cutoff, i0.buffer, i0.beta, i0.coulomb_const,
-                    i0.sigma, i0.epsilon, excl_off, excl_idx, flags, cluster)
+                    i0.sigma, i0.epsilon, excl_off, excl_idx, flags, cluster, elec, vdw,
+                    epsilon_rf, rswitch)
     x = np.concatenate([i.x for i in insts]).astype(np.float32)
     q = np.concatenate([i.q for i in insts]).astype(np.float32)
     t = np.concatenate([i.type for i in insts]).astype(np.int32)

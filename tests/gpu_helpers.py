@@ -25,9 +25,10 @@ def dev(torch, a, dtype=None):
 class GpuBox:
     """One context on cuda:0 holding device copies of an instance's inputs."""
 
-    def __init__(self, torch, inst, cluster=8, flags=0, buffer=None):
+    def __init__(self, torch, inst, cluster=8, flags=0, buffer=None, **flavour):
         self.torch, self.inst = torch, inst
-        self.params = nb.Params.from_instance(inst, flags=flags, cluster=cluster, buffer=buffer)
+        self.params = nb.Params.from_instance(inst, flags=flags, cluster=cluster, buffer=buffer,
+                                              **flavour)
         self.ctx = nb.nb_setup(self.params)
         self.x = dev(torch, inst.x.reshape(-1))
         self.q = dev(torch, inst.q)

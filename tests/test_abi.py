@@ -61,10 +61,27 @@ def test_valid_parameters_pass():
     ("natoms", 0, nb.NB_ERR_ARG),
     ("cluster", 6, nb.NB_ERR_ARG),
     ("flags", 0x100, nb.NB_ERR_ARG),
+    ("elec", 2, nb.NB_ERR_ARG),
+    ("vdw", 5, nb.NB_ERR_ARG),
 ])
 def test_invalid_parameters_are_rejected(field, value, code):
     assert nb.nb_validate_params(base_params(**{field: value})) == code
     assert nb.nb_last_error(None) != ""
+
+
+@pytest.mark.parametrize("kw", [
+    dict(vdw=1, rswitch=0.9),               # rswitch must lie below rc = 0.9
+    dict(vdw=1, rswitch=-0.1),
+    dict(elec=1, epsilon_rf=0.5),           # 0 (infinity) or >= 1
+])
+def test_invalid_flavour_parameters_are_rejected(kw):
+    assert nb.nb_validate_params(base_params(**kw)) == nb.NB_ERR_ARG
+
+
+def test_valid_flavours_pass():
+    for kw in (dict(elec=1), dict(elec=1, epsilon_rf=78.0), dict(vdw=1, rswitch=0.7),
+               dict(elec=1, vdw=1, rswitch=0.0)):
+        assert nb.nb_validate_params(base_params(**kw)) == nb.NB_OK
 
 
 def test_rlist_beyond_box_is_rejected():
