@@ -79,7 +79,8 @@ typedef enum nb_status {
 #define NB_CHECK_STALE  0x1u  /* nb_forces records whether any atom moved >= buffer/2 */
 #define NB_CHECK_FINITE 0x2u  /* nb_forces records non-finite coordinates */
 #define NB_REUSE_LIST   0x4u  /* nb_backward: use the current list instead of rebuilding */
-#define NB_ASYNC_BUILD  0x8u  /* nb_pairlist: do not wait for the overflow check */
+#define NB_ASYNC_BUILD  0x8u  /* nb_pairlist: do not wait for the build; its overflow check
+                                 is read at the next nb_pairlist (first build: synchronous) */
 #define NB_ENERGY_FP64  0x10u /* evaluate the Coulomb pair energies in FP64 (forces stay FP32):
                                  needed for 1e-6 relative E_C in boxes of a few thousand atoms,
                                  where FP32 pair-energy rounding does not average out
@@ -142,9 +143,15 @@ int nb_set_stream(nb_ctx *ctx, void *stream);
 /* Build the cluster-pair list from device coordinates x [natoms][3]: wrap into the box, grid
  * sort, cluster, bounding boxes, search within rlist, exclusion masks, atom-level prune.
  * Remembers x as the build positions for the staleness check.  Synchronises once to read the
- * overflow flag and rebuilds with a larger list if needed (unless NB_ASYNC_BUILD was set at
- * setup, in which case the flag is read at the next call).  Not capturable in a HIP graph.
- * Errors: NB_ERR_ARG, NB_ERR_OVERFLOW (only if growing failed), NB_ERR_HIP, NB_ERR_OOM. */
+ * overflow flag and rebuilds with a larger list if needed.  With NB_ASYNC_BUILD set at setup,
+ * every build after the first returns without waiting: its status block is copied to pinned
+ * host memory behind it on the stream and read at the next nb_pairlist, which waits only for
+ * that copy (done long before the force calls queued after the build).  If that build had
+ * overflowed, the forces computed with its list missed pairs: the next nb_pairlist regrows the
+ * list, rebuilds synchronously and returns NB_ERR_OVERFLOW with a complete new list in place.
+ * Not capturable in a HIP graph.
+ * Errors: NB_ERR_ARG, NB_ERR_OVERFLOW (growing failed, or as above), NB_ERR_NONFINITE,
+ * NB_ERR_HIP, NB_ERR_OOM. */
 int nb_pairlist(nb_ctx *ctx, const float *x_dev);
 
 /* Forces and energies for device inputs x [natoms][3], q [natoms], type [natoms] (0-based

@@ -395,10 +395,23 @@ int nb_setup(nb_ctx **out, const nb_params *p, void *stream) {
     }
     if ((r = upload_lj(c)) != NB_OK) goto fail_out;
     if ((r = upload_etab(c)) != NB_OK) goto fail_out;
+    if (c->flags & NB_ASYNC_BUILD) {
+        if (hipHostMalloc((void **)&c->host_meta, sizeof(nb_meta), hipHostMallocDefault) != hipSuccess) {
+            c->host_meta = nullptr;
+            r = fail(c, NB_ERR_OOM, "pinned status block");
+            goto fail_out;
+        }
+        if (hipEventCreateWithFlags(&c->build_ev, hipEventDisableTiming) != hipSuccess) {
+            c->build_ev = nullptr;
+            r = fail(c, NB_ERR_HIP, "hipEventCreate");
+            goto fail_out;
+        }
+    }
     *out = c;
     return NB_OK;
 fail_out:
     g_setup_error = c->err;
+    if (c->host_meta) hipHostFree(c->host_meta);
     free_all(c);
     delete c;
     return r;
@@ -426,10 +439,36 @@ int nb_pairlist(nb_ctx *c, const float *x) {
     hipSetDevice(c->device);
     c->have_list = false;
     auto t0 = std::chrono::steady_clock::now();
+    // NB_ASYNC_BUILD: the status of the previous build was copied to pinned memory behind it
+    // on the stream; that copy finished long before the force calls queued after the build,
+    // so waiting for its event does not drain the stream
+    bool prev_overflow = false;
+    if (c->pending_overflow_check) {
+        c->pending_overflow_check = false;
+        hipError_t e = hipEventSynchronize(c->build_ev);
+        if (e != hipSuccess) return hip_fail(c, e, "wait for the previous build's status");
+        const nb_meta m = *c->host_meta;
+        if (m.flags & NB_F_COLUMN)
+            return fail(c, NB_ERR_OVERFLOW, "a grid column or the exclusions of one cluster exceed the build kernels' capacity");
+        if (m.flags & NB_F_NONFINITE) return fail(c, NB_ERR_NONFINITE, "non-finite coordinates at the previous build");
+        if (m.flags & NB_F_OVERFLOW) {
+            prev_overflow = true;
+            // force calls queued after that build still read the old list
+            e = hipStreamSynchronize(c->stream);
+            if (e != hipSuccess) return hip_fail(c, e, "drain the stream before regrowing");
+            c->cap = ((m.maxcount + m.maxcount / 8 + 32) + 31) & ~31;
+            int r = alloc_list(c);
+            if (r != NB_OK) return r;
+        }
+    }
+    const bool async = (c->flags & NB_ASYNC_BUILD) && c->built_once && !prev_overflow;
     for (int attempt = 0; attempt < 4; ++attempt) {
         hipError_t e = nb_launch_build(c, x);
         if (e != hipSuccess) return hip_fail(c, e, "pair-list build launch");
-        if (c->flags & NB_ASYNC_BUILD) {
+        if (async) {
+            e = hipMemcpyAsync(c->host_meta, c->meta, sizeof(nb_meta), hipMemcpyDeviceToHost, c->stream);
+            if (e == hipSuccess) e = hipEventRecord(c->build_ev, c->stream);
+            if (e != hipSuccess) return hip_fail(c, e, "queue the build status copy");
             c->have_list = true;
             c->pending_overflow_check = true;
             return NB_OK;
@@ -446,7 +485,11 @@ int nb_pairlist(nb_ctx *c, const float *x) {
             continue;
         }
         c->have_list = true;
+        c->built_once = true;
         c->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        if (prev_overflow)
+            return fail(c, NB_ERR_OVERFLOW, "the previous pair list overflowed (forces computed with it "
+                                            "missed pairs); the list was regrown and this one is complete");
         return NB_OK;
     }
     return fail(c, NB_ERR_OVERFLOW, "pair list still overflowing after regrowing");
@@ -570,6 +613,8 @@ int nb_destroy(nb_ctx *c) {
     hipSetDevice(c->device);
     hipStreamSynchronize(c->stream);
     for (hipEvent_t ev : c->ev) hipEventDestroy(ev);
+    if (c->build_ev) hipEventDestroy(c->build_ev);
+    if (c->host_meta) hipHostFree(c->host_meta);
     free_all(c);
     delete c;
     return NB_OK;

@@ -72,57 +72,85 @@ __global__ void __launch_bounds__(256) k_bin(int n, const float *__restrict__ x,
     }
 }
 
-// Exclusive scans of column populations and of cluster counts ceil(n / C); one block.
+// Exclusive scans of column populations and of cluster counts ceil(n / C); one block of 1024
+// threads, each over a contiguous run of columns: wave scans, then one thread over the waves.
 __global__ void __launch_bounds__(1024) k_colscan(int ncol, int C, const int *__restrict__ colcount,
                                                    int *__restrict__ colstart, int *__restrict__ colcl,
                                                    nb_meta *meta) {
-    __shared__ int sa[1024], sb[1024];
-    int t = threadIdx.x;
-    int per = (ncol + 1023) / 1024;
-    int c0 = min(ncol, t * per), c1 = min(ncol, c0 + per);
+    __shared__ int wa[1024 / NB_WAVE], wb[1024 / NB_WAVE];
+    const int t = threadIdx.x, lane = t & (NB_WAVE - 1), wv = t / NB_WAVE;
+    const int per = (ncol + 1023) / 1024;
+    const int c0 = min(ncol, t * per), c1 = min(ncol, c0 + per);
     int a = 0, b = 0, mx = 0;
     for (int c = c0; c < c1; ++c) {
-        int v = colcount[c];
+        const int v = colcount[c];
         a += v;
         b += (v + C - 1) / C;
         mx = max(mx, v);
     }
-    sa[t] = a;
-    sb[t] = b;
-    __syncthreads();
-    for (int s = 1; s < 1024; s <<= 1) {
-        int va = t >= s ? sa[t - s] : 0, vb = t >= s ? sb[t - s] : 0;
-        __syncthreads();
-        sa[t] += va;
-        sb[t] += vb;
-        __syncthreads();
+    int ia = a, ib = b;
+#pragma unroll
+    for (int o = 1; o < NB_WAVE; o <<= 1) {
+        const int va = __shfl_up(ia, o, NB_WAVE), vb = __shfl_up(ib, o, NB_WAVE);
+        if (lane >= o) {
+            ia += va;
+            ib += vb;
+        }
+        mx = max(mx, __shfl_xor(mx, o, NB_WAVE));
     }
-    int pa = sa[t] - a, pb = sb[t] - b;
+    if (lane == NB_WAVE - 1) {
+        wa[wv] = ia;
+        wb[wv] = ib;
+    }
+    __syncthreads();
+    if (t == 0) {
+        int ra = 0, rb = 0;
+        for (int k = 0; k < 1024 / NB_WAVE; ++k) {
+            const int xa = wa[k], xb = wb[k];
+            wa[k] = ra;
+            wb[k] = rb;
+            ra += xa;
+            rb += xb;
+        }
+        colstart[ncol] = ra;
+        colcl[ncol] = rb;
+        meta->nclusters = rb;
+        meta->npad = rb * C;
+    }
+    __syncthreads();
+    int pa = wa[wv] + ia - a, pb = wb[wv] + ib - b;
     for (int c = c0; c < c1; ++c) {
-        int v = colcount[c];
+        const int v = colcount[c];
         colstart[c] = pa;
         colcl[c] = pb;
         pa += v;
         pb += (v + C - 1) / C;
     }
-    if (t == 1023) {
-        colstart[ncol] = sa[1023];
-        colcl[ncol] = sb[1023];
-        meta->nclusters = sb[1023];
-        meta->npad = sb[1023] * C;
-    }
-    atomicMax(&meta->maxcolumn, mx);
+    if (lane == 0) atomicMax(&meta->maxcolumn, mx);
 }
 
-__global__ void k_scatter(int n, const int *__restrict__ col, const int *__restrict__ rank,
-                          const int *__restrict__ colstart, int *__restrict__ tmp) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+// Clears the column histogram and the status block before a build (one launch instead of
+// a memset per buffer).
+__global__ void k_begin(int ncol, int *__restrict__ colcount, nb_meta *meta) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < ncol) colcount[i] = 0;
+    if (i == 0) *meta = nb_meta{};
+}
+
+// Atom indices in column order; also marks every slot of perm empty (-1) for the column sort,
+// which fills the slots of real atoms.
+__global__ void k_scatter(int n, int npad_max, const int *__restrict__ col,
+                          const int *__restrict__ rank, const int *__restrict__ colstart,
+                          int *__restrict__ tmp, int *__restrict__ perm) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    for (int p = i; p < npad_max; p += gridDim.x * blockDim.x) perm[p] = -1;
     if (i >= n) return;
     tmp[colstart[col[i]] + rank[i]] = i;
 }
 
-// One block per column: sort the column's atoms by (z, index) in LDS (bitonic), then lay them
-// out as clusters of C slots; the tail of the last cluster is padding (perm = -1).
+// One block per column: sort the column's atoms by (z, index) in LDS (by rank for columns of
+// at most one atom per thread, bitonic otherwise), then lay them out as clusters of C slots;
+// the tail of the last cluster is padding (perm = -1).
 template <int C>
 __global__ void __launch_bounds__(256) k_colsort(const float *__restrict__ x,
                                                  const float4 *__restrict__ off,
@@ -139,6 +167,34 @@ __global__ void __launch_bounds__(256) k_colsort(const float *__restrict__ x,
     if (n > NB_SORT_MAX) {
         if (tid == 0) atomicOr(&meta->flags, NB_F_COLUMN);
         for (int r = tid; r < nslot; r += blockDim.x) {
+            perm[cl0 * C + r] = -1;
+            xs[cl0 * C + r] = make_float4(-1e5f, -1e5f, -1e5f, 0.0f);
+        }
+        return;
+    }
+    if (n <= (int)blockDim.x) {
+        // one atom per thread: its place in the sorted column is the number of smaller keys
+        // (keys are distinct: the atom index is their low word), read from LDS as broadcasts
+        unsigned long long v = ~0ull;
+        int a = -1;
+        if (tid < n) {
+            a = tmp[start + tid];
+            float z = x[3 * a + 2] + off[a].z;
+            if (!(z > 0.0f)) z = 0.0f;
+            v = ((unsigned long long)__float_as_uint(z) << 32) | (unsigned)a;
+            key[tid] = v;
+        }
+        __syncthreads();
+        if (tid < n) {
+            int rank = 0;
+            for (int k = 0; k < n; ++k) rank += key[k] < v ? 1 : 0;
+            const int slot = cl0 * C + rank;
+            perm[slot] = a;
+            slot_of[a] = slot;
+            const float4 o = off[a];
+            xs[slot] = make_float4(x[3 * a] + o.x, x[3 * a + 1] + o.y, x[3 * a + 2] + o.z, 1.0f);
+        }
+        for (int r = n + tid; r < nslot; r += blockDim.x) {
             perm[cl0 * C + r] = -1;
             xs[cl0 * C + r] = make_float4(-1e5f, -1e5f, -1e5f, 0.0f);
         }
@@ -486,6 +542,7 @@ __global__ void __launch_bounds__(256) k_search(nb_geom g, int cap, const int *_
 }
 
 #define NB_UNIT_MIN 4  // batches per work unit at least (a unit's fixed cost is about one)
+#define NB_UNITS_REG 16  // clusters per thread whose batch counts k_units keeps in registers
 
 // Work units of the force kernel, in one block: every i-cluster with a non-empty list becomes
 // ceil(nb / P) units of at most P 64-lane batches, nb being its list length in batches and
@@ -497,60 +554,94 @@ __global__ void __launch_bounds__(256) k_search(nb_geom g, int cap, const int *_
 // the early clusters the longer lists.)  The unit index is also its energy slot.
 __global__ void __launch_bounds__(1024) k_units(int slots, int unit_cap, const int *__restrict__ icount,
                                                 int4 *__restrict__ units, nb_meta *meta) {
-    __shared__ int red[1024];
+    __shared__ int wa[1024 / NB_WAVE], wb[1024 / NB_WAVE];
     __shared__ int s_p;
     const int tid = threadIdx.x, nthr = blockDim.x;
+    const int lane = tid & (NB_WAVE - 1), wv = tid / NB_WAVE, nw = nthr / NB_WAVE;
     const int ncl = meta->nclusters;
     const int chunk = (ncl + nthr - 1) / nthr;
     const int c_lo = min(ncl, tid * chunk), c_hi = min(ncl, c_lo + chunk);
-    // total batches and the longest list
+    // The batch counts of this thread's first NB_UNITS_REG clusters stay in registers (loaded
+    // together from clamped indices, zero past the chunk); a longer chunk (more than
+    // 1024 * NB_UNITS_REG clusters) reads the rest from memory.  One block does all of this,
+    // so the per-cluster work is kept to a few instructions.
+    int nbr[NB_UNITS_REG];
+    const int c_last = max(ncl - 1, 0);
+#pragma unroll
+    for (int j = 0; j < NB_UNITS_REG; ++j) nbr[j] = icount[min(c_lo + j, c_last)];
+#pragma unroll
+    for (int j = 0; j < NB_UNITS_REG; ++j) nbr[j] = c_lo + j < c_hi ? (nbr[j] + NB_JPB - 1) / NB_JPB : 0;
+    const int c_rest = c_lo + NB_UNITS_REG;
+    // total batches and the longest list: wave trees, then one thread over the waves
     int nb_sum = 0, nb_max = 0;
-    for (int c = c_lo; c < c_hi; ++c) {
+#pragma unroll
+    for (int j = 0; j < NB_UNITS_REG; ++j) {
+        nb_sum += nbr[j];
+        nb_max = max(nb_max, nbr[j]);
+    }
+    for (int c = c_rest; c < c_hi; ++c) {
         const int nb = (icount[c] + NB_JPB - 1) / NB_JPB;
         nb_sum += nb;
         nb_max = max(nb_max, nb);
     }
-    red[tid] = nb_sum;
-    __syncthreads();
-    for (int o = nthr / 2; o > 0; o >>= 1) {
-        if (tid < o) red[tid] += red[tid + o];
-        __syncthreads();
+#pragma unroll
+    for (int o = NB_WAVE / 2; o > 0; o >>= 1) {
+        nb_sum += __shfl_xor(nb_sum, o, NB_WAVE);
+        nb_max = max(nb_max, __shfl_xor(nb_max, o, NB_WAVE));
     }
-    if (tid == 0) s_p = max(NB_UNIT_MIN, (red[0] + 2 * slots - 1) / (2 * slots));
-    __syncthreads();
-    red[tid] = nb_max;
-    __syncthreads();
-    for (int o = nthr / 2; o > 0; o >>= 1) {
-        if (tid < o) red[tid] = max(red[tid], red[tid + o]);
-        __syncthreads();
+    if (lane == 0) {
+        wa[wv] = nb_sum;
+        wb[wv] = nb_max;
     }
-    const int P = s_p;
-    if (tid == 0) meta->maxbatches = red[0];
     __syncthreads();
-    // units of this thread's clusters and their exclusive prefix over the threads
+    if (tid == 0) {
+        int t = 0, m = 0;
+        for (int k = 0; k < nw; ++k) {
+            t += wa[k];
+            m = max(m, wb[k]);
+        }
+        s_p = max(NB_UNIT_MIN, (t + 2 * slots - 1) / (2 * slots));
+        meta->maxbatches = m;
+    }
+    __syncthreads();
+    const int P = __builtin_amdgcn_readfirstlane(s_p);
+    // units of this thread's clusters and their exclusive prefix over the threads (wave scans,
+    // then one thread over the wave totals)
     int nu = 0;
-    for (int c = c_lo; c < c_hi; ++c) nu += ((icount[c] + NB_JPB - 1) / NB_JPB + P - 1) / P;
-    red[tid] = nu;
+#pragma unroll
+    for (int j = 0; j < NB_UNITS_REG; ++j) nu += (nbr[j] + P - 1) / P;
+    for (int c = c_rest; c < c_hi; ++c) nu += ((icount[c] + NB_JPB - 1) / NB_JPB + P - 1) / P;
+    int incl = nu;
+#pragma unroll
+    for (int o = 1; o < NB_WAVE; o <<= 1) {
+        const int v = __shfl_up(incl, o, NB_WAVE);
+        if (lane >= o) incl += v;
+    }
+    __syncthreads();  // wa is reused
+    if (lane == NB_WAVE - 1) wa[wv] = incl;
     __syncthreads();
-    for (int o = 1; o < nthr; o <<= 1) {  // inclusive scan (Hillis-Steele)
-        const int v = tid >= o ? red[tid - o] : 0;
-        __syncthreads();
-        red[tid] += v;
-        __syncthreads();
-    }
-    int u = red[tid] - nu;
-    if (tid == nthr - 1) {
-        meta->nunits = min(red[tid], unit_cap);
+    if (tid == 0) {
+        int run = 0;
+        for (int k = 0; k < nw; ++k) {
+            const int t = wa[k];
+            wa[k] = run;
+            run += t;
+        }
+        meta->nunits = min(run, unit_cap);
         meta->split = P;
-        if (red[tid] > unit_cap) atomicOr(&meta->flags, NB_F_COLUMN);  // not reachable: <= ncl + 2 slots
+        if (run > unit_cap) atomicOr(&meta->flags, NB_F_COLUMN);  // not reachable: <= ncl + 2 slots
     }
-    for (int c = c_lo; c < c_hi; ++c) {
-        const int nb = (icount[c] + NB_JPB - 1) / NB_JPB;
+    __syncthreads();
+    int u = wa[wv] + incl - nu;
+    auto emit = [&](int c, int nb) {
         for (int b = 0; b < nb; b += P) {
             if (u < unit_cap) units[u] = make_int4(c, b, min(P, nb - b), u);
             ++u;
         }
-    }
+    };
+#pragma unroll
+    for (int j = 0; j < NB_UNITS_REG; ++j) emit(c_lo + j, nbr[j]);
+    for (int c = c_rest; c < c_hi; ++c) emit(c, (icount[c] + NB_JPB - 1) / NB_JPB);
 }
 
 // Export of interacting pairs with the force kernel's arithmetic: the same lane layout (one
@@ -604,18 +695,17 @@ template <int C>
 hipError_t build_impl(nb_ctx *c, const float *x) {
     const int n = c->natoms;
     const int tb = 256;
-    hipMemsetAsync(c->colcount, 0, sizeof(int) * c->geom.ncol, c->stream);
-    hipMemsetAsync(c->meta, 0, sizeof(nb_meta), c->stream);
+    hipLaunchKernelGGL(k_begin, dim3((c->geom.ncol + tb - 1) / tb), dim3(tb), 0, c->stream,
+                       c->geom.ncol, c->colcount, c->meta);
     const int lds = c->geom.ncol <= NB_BIN_LDS_MAX;
     hipLaunchKernelGGL(k_bin, dim3((n + tb - 1) / tb), dim3(tb), lds ? sizeof(int) * c->geom.ncol : 0,
                        c->stream, n, x, c->geom, c->off, c->xbuild, c->col, c->rank, c->colcount,
                        c->meta, lds);
     hipLaunchKernelGGL(k_colscan, dim3(1), dim3(1024), 0, c->stream, c->geom.ncol, C, c->colcount,
                        c->colstart, c->colcl, c->meta);
-    hipLaunchKernelGGL(k_scatter, dim3((n + tb - 1) / tb), dim3(tb), 0, c->stream, n, c->col,
-                       c->rank, c->colstart, c->tmp);
     // every slot the per-call pack visits is either written by the column sort or padding
-    hipMemsetAsync(c->perm, 0xff, sizeof(int) * c->npad_max, c->stream);
+    hipLaunchKernelGGL(k_scatter, dim3((n + tb - 1) / tb), dim3(tb), 0, c->stream, n, c->npad_max,
+                       c->col, c->rank, c->colstart, c->tmp, c->perm);
     hipLaunchKernelGGL((k_colsort<C>), dim3(c->geom.ncol), dim3(256), 0, c->stream, x, c->off,
                        c->colcount, c->colstart, c->colcl, c->tmp, c->perm, c->slot_of, c->xs,
                        c->meta);

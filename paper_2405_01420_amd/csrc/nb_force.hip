@@ -4,7 +4,8 @@
 //
 // This is the computation the paper identifies as the single-GPU rate limiter (section III-A;
 // the flavour named in the Fig. 3 caption).  The per-cluster body and its lane layout are in
-// nb_force_body.h; here one wavefront is launched per i-cluster.
+// nb_force_body.h; here one wavefront is launched per work unit (an i-cluster's list or a part
+// of a long one).
 #include <algorithm>
 
 #include "nb_force_body.h"
@@ -57,8 +58,13 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// One work unit per wave, NB_FORCE_WAVES consecutive units per workgroup.  The energy sums of
+// the workgroup's waves are combined in LDS by whichever wave finishes last, in wave order, and
+// stored as the workgroup's partial (epart[4 blockIdx ..]); waves do not wait for each other.
+#define NB_FORCE_WAVES 4
+
 template <int C, bool EPREC, int FLAV>
-__global__ void __launch_bounds__(256) NB_FORCE_OCCUPANCY k_force(nb_fparams fp, int cap, int npad_max,
+__global__ void __launch_bounds__(NB_FORCE_WAVES * NB_WAVE) NB_FORCE_OCCUPANCY k_force(nb_fparams fp, int cap, int npad_max,
                                                const float4 *__restrict__ xq,
                                                const int *__restrict__ tsort,
                                                const float4 *__restrict__ ljtab,
@@ -69,7 +75,10 @@ __global__ void __launch_bounds__(256) NB_FORCE_OCCUPANCY k_force(nb_fparams fp,
                                                const int4 *__restrict__ units, float *__restrict__ fj,
                                                double *__restrict__ epart, const nb_meta *meta) {
     extern __shared__ float4 tab[];
+    __shared__ double esh[NB_FORCE_WAVES][3];
+    __shared__ int edone;
     const int ntt = fp.ntypes * fp.ntypes;
+    if (threadIdx.x == 0) edone = 0;
     for (int k = threadIdx.x; k < 2 * ntt; k += blockDim.x) tab[k] = ljtab[k];
     nb_etab et;
     et.seg = reinterpret_cast<const double2 *>(tab + 2 * ntt);
@@ -80,19 +89,43 @@ __global__ void __launch_bounds__(256) NB_FORCE_OCCUPANCY k_force(nb_fparams fp,
         for (int k = threadIdx.x; k < 2 * etab_n; k += blockDim.x) dst[k] = etab[k];
     }
     __syncthreads();
-    // one wave per work unit
-    const int u = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x / NB_WAVE) +
-                                                 threadIdx.x / NB_WAVE);
-    if (u >= meta->nunits) return;
-    const int4 w = units[u];
-    nb_force_cluster<C, EPREC, FLAV>(fp, tab, et, __builtin_amdgcn_readfirstlane(w.x),
-                               __builtin_amdgcn_readfirstlane(w.y), __builtin_amdgcn_readfirstlane(w.z),
-                               __builtin_amdgcn_readfirstlane(w.w), cap, npad_max, nb_g(xq),
-                               nb_g(tsort), nb_g(icount), nb_g(jl), nb_g(fj), nb_g(epart));
+    const int lane = threadIdx.x & (NB_WAVE - 1), wv = threadIdx.x / NB_WAVE;
+    const int u = __builtin_amdgcn_readfirstlane(blockIdx.x * NB_FORCE_WAVES + wv);
+    const int nunits = meta->nunits;
+    if (blockIdx.x * NB_FORCE_WAVES >= nunits) return;  // the whole workgroup is idle
+    nb_esum es{0.0, 0.0, 0.0};
+    if (u < nunits) {
+        const int4 w = units[u];
+        es = nb_force_cluster<C, EPREC, FLAV>(fp, tab, et, __builtin_amdgcn_readfirstlane(w.x),
+                                              __builtin_amdgcn_readfirstlane(w.y),
+                                              __builtin_amdgcn_readfirstlane(w.z), cap, npad_max,
+                                              nb_g(xq), nb_g(tsort), nb_g(icount), nb_g(jl), nb_g(fj));
+    }
+    int last = 0;
+    if (lane == 0) {
+        esh[wv][0] = es.elj;
+        esh[wv][1] = es.ec;
+        esh[wv][2] = es.qq;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        last = __hip_atomic_fetch_add(&edone, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) ==
+               NB_FORCE_WAVES - 1;
+        if (last) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            double a = 0.0, b = 0.0, c = 0.0;
+            for (int k = 0; k < NB_FORCE_WAVES; ++k) {
+                a += esh[k][0];
+                b += esh[k][1];
+                c += esh[k][2];
+            }
+            epart[4 * blockIdx.x] = a;
+            epart[4 * blockIdx.x + 1] = b;
+            epart[4 * blockIdx.x + 2] = c;
+        }
+    }
 }
 
 // f[atom] in original order, and the FP64 energy sums.  Block 0 additionally adds the energy
-// partials of the work units in slot order (strided per thread, then the wave and block trees)
+// partials of the force workgroups in order (strided per thread, then the wave and block trees)
 // and applies the Coulomb shift; it is dispatched first, so this runs beside the other blocks'
 // force gathers and needs no inter-block synchronisation.
 __global__ void __launch_bounds__(NB_FIN_BLOCK) k_finalize(int n, int npad_max,
@@ -111,13 +144,13 @@ __global__ void __launch_bounds__(NB_FIN_BLOCK) k_finalize(int n, int npad_max,
         f[3 * i + 2] = fj[2 * npad_max + p];
     }
     if (blockIdx.x != 0) return;
-    const int ncl = meta->nunits;
+    const int np = (meta->nunits + NB_FORCE_WAVES - 1) / NB_FORCE_WAVES;
     double x = 0.0, y = 0.0, z = 0.0;
-    // eight clusters per thread and step: their loads are issued together, not one latency
+    // several partials per thread and step: their loads are issued together, not one latency
     // after another
-    constexpr int U = 8;
+    constexpr int U = 4;
     int k = threadIdx.x;
-    for (; k + (U - 1) * NB_FIN_BLOCK < ncl; k += U * NB_FIN_BLOCK) {
+    for (; k + (U - 1) * NB_FIN_BLOCK < np; k += U * NB_FIN_BLOCK) {
         double4 v[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) v[u] = *reinterpret_cast<const double4 *>(epart + 4 * (k + u * NB_FIN_BLOCK));
@@ -128,7 +161,7 @@ __global__ void __launch_bounds__(NB_FIN_BLOCK) k_finalize(int n, int npad_max,
             z += v[u].z;
         }
     }
-    for (; k < ncl; k += NB_FIN_BLOCK) {
+    for (; k < np; k += NB_FIN_BLOCK) {
         x += epart[4 * k];
         y += epart[4 * k + 1];
         z += epart[4 * k + 2];
@@ -170,7 +203,7 @@ template <int C, bool EPREC, int FLAV>
 static void launch_force_t(nb_ctx *c) {
     const size_t shm = sizeof(float4) * 2 * c->ntypes * c->ntypes +
                        (EPREC ? sizeof(double2) * 2 * c->etab_n : 0);
-    dim3 grid((c->unit_cap + 3) / 4), block(256);
+    dim3 grid((c->unit_cap + NB_FORCE_WAVES - 1) / NB_FORCE_WAVES), block(NB_FORCE_WAVES * NB_WAVE);
     hipLaunchKernelGGL((k_force<C, EPREC, FLAV>), grid, block, shm, c->stream, c->fp, c->cap, c->npad_max,
                        c->xq, c->tsort, c->ljtab, c->etab, c->etab_n, c->etab_invh, c->icount,
                        c->jl, c->units, c->fj, c->epart, c->meta);
@@ -208,7 +241,6 @@ hipError_t nb_launch_force(nb_ctx *c) {
 hipError_t nb_launch_finalize(nb_ctx *c, float *f, double *e) {
     const int nblk = std::max(1, (c->natoms + NB_FIN_BLOCK - 1) / NB_FIN_BLOCK);
     hipLaunchKernelGGL(k_finalize, dim3(nblk), dim3(NB_FIN_BLOCK), 0, c->stream, c->natoms,
-                       c->npad_max, c->slot_of, c->fj, f, c->meta, c->epart,
-                       c->shift_coul, (c->flags & NB_ENERGY_FP64) ? c->fc : 1.0, e);
+                       c->npad_max, c->slot_of, c->fj, f, c->meta, c->epart, c->shift_coul, (c->flags & NB_ENERGY_FP64) ? c->fc : 1.0, e);
     return hipGetLastError();
 }

@@ -203,21 +203,25 @@ __device__ __forceinline__ float nb_uniform(float v) {
     return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
 }
 
-// Forces and energy partials of one work unit, computed by one wavefront: the batches
+// Energy sums of one work unit (every lane holds them): E_LJ, the Coulomb pair sum and the
+// Coulomb shift weight (sum of q_i q_j over interacting pairs).
+struct nb_esum {
+    double elj, ec, qq;
+};
+
+// Forces and energy sums of one work unit, computed by one wavefront: the batches
 // [b0, b0 + nbat) of i-cluster ci's j-list (all of them, or one part of a long list).  fp.L
 // holds the box of the cluster.  Both the j-forces and the unit's i-force sums are added
-// atomically to fj (several units may share an i-cluster); the energy partials are stored to
-// epart[4 slot ..].
+// atomically to fj (several units may share an i-cluster); the energy sums are returned.
 template <int C, bool EPREC, int FLAV>
-__device__ __forceinline__ void nb_force_cluster(const nb_fparams &fp, const float4 *tab,
+__device__ __forceinline__ nb_esum nb_force_cluster(const nb_fparams &fp, const float4 *tab,
                                                  const nb_etab &et, int ci, int b0, int nbat,
-                                                 int slot, int cap, int npad_max,
+                                                 int cap, int npad_max,
                                                  const NB_G float4 *__restrict__ xq,
                                                  const NB_G int *__restrict__ tsort,
                                                  const NB_G int *__restrict__ icount,
                                                  const NB_G nb_entry *__restrict__ jl,
-                                                 NB_G float *__restrict__ fj,
-                                                 NB_G double *__restrict__ epart) {
+                                                 NB_G float *__restrict__ fj) {
     constexpr unsigned FULL = (1u << C) - 1u;
     const int nt = fp.ntypes, ntt = nt * nt;
     const int lane = threadIdx.x & (NB_WAVE - 1);
@@ -350,9 +354,5 @@ __device__ __forceinline__ void nb_force_cluster(const nb_fparams &fp, const flo
         atomicAdd((float *)(fj + npad_max + p), vy);
         atomicAdd((float *)(fj + 2 * npad_max + p), vz);
     }
-    if (lane == NB_WAVE - 1) {
-        nb_st(epart + 4 * slot, elj);
-        nb_st(epart + 4 * slot + 1, ec);
-        nb_st(epart + 4 * slot + 2, qqd);
-    }
+    return nb_esum{elj, ec, qqd};
 }

@@ -118,6 +118,9 @@ struct nb_ctx {
     int unit_cap = 0;       // work units at most: ncl_max + 2 slots
     bool have_list = false;
     bool pending_overflow_check = false;
+    bool built_once = false;          // a build has completed (its capacity checked)
+    nb_meta *host_meta = nullptr;     // pinned copy of the status block of the last async build
+    hipEvent_t build_ev = nullptr;    // recorded after that copy
     std::vector<double> sigma, epsilon;
     std::string err;
     double build_ms = 0;

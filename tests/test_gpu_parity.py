@@ -171,3 +171,62 @@ def test_forces_before_list_is_state_error(torch_gpu, inst_tiny):
         nb.nb_forces(box.ctx, box.x, box.q, box.t, box.f, box.e)
     assert ei.value.code == nb.NB_ERR_STATE
     box.close()
+
+
+def test_async_builds_along_jitter(torch_gpu, inst_diff):
+    """Asynchronous list builds (status read at the next build) on a random walk rebuilt every
+    5 calls: forces and energies match the oracle at the last call before each rebuild (FP64
+    pair energies: with FP32 ones the Coulomb energy of this 24k-atom box reaches 1.5e-6 on
+    some of these configurations, a property of the energy precision, not of the list)."""
+    box = GpuBox(torch_gpu, inst_diff, flags=nb.NB_ASYNC_BUILD | nb.NB_CHECK_STALE | nb.NB_ENERGY_FP64)
+    rng = synth.jitter_stream(21)
+    x = inst_diff.x.copy()
+    for call in range(15):
+        box.set_x(x)
+        if call % 5 == 0:
+            box.pairlist()
+        f, e = box.forces()
+        if call % 5 == 4:
+            assert nb.nb_check(box.ctx) == nb.NB_OK
+            ref = O.instance_forces(inst_diff, cells=True, x=x)
+            fr, elj, ec = compare_forces(f, e, ref, f"diff async call {call}")
+            assert fr <= FORCE_TOL and elj <= ENERGY_TOL and ec <= ENERGY_TOL
+        x = (x + rng.normal(0.0, 0.002, x.shape)).astype(np.float32)
+    box.pairlist()  # reads the last build's status: no overflow
+    box.close()
+
+
+def test_async_build_reports_overflow_of_previous_build(torch_gpu, inst_diff):
+    """An asynchronous build whose lists overflow (4,000 atoms packed into a 0.6 nm cube) is
+    reported by the next nb_pairlist, which regrows the list and rebuilds completely."""
+    box = GpuBox(torch_gpu, inst_diff, flags=nb.NB_ASYNC_BUILD)
+    box.pairlist()  # first build: synchronous
+    cap0 = box.stats()["list_capacity"]
+    xc = inst_diff.x.copy()
+    c0 = 0.5 * inst_diff.box
+    rng = np.random.default_rng(3)
+    xc[:4000] = (c0 + rng.uniform(-0.3, 0.3, (4000, 3))).astype(np.float32)
+    box.set_x(xc)
+    box.pairlist()  # asynchronous: overflows
+    box.set_x(inst_diff.x)
+    with pytest.raises(nb.NbError) as ei:
+        box.pairlist()
+    assert ei.value.code == nb.NB_ERR_OVERFLOW
+    assert box.stats()["list_capacity"] > cap0
+    f, e = box.forces()
+    ref = O.instance_forces(inst_diff, cells=True)
+    fr, elj, ec = compare_forces(f, e, ref, "diff after async overflow")
+    box.close()
+    assert fr <= FORCE_TOL and elj <= ENERGY_TOL and ec <= ENERGY_TOL
+
+
+def test_energies_do_not_depend_on_scheduling(torch_gpu, inst_diff):
+    """Energy partials are summed per work unit, per finalize block and over blocks in fixed
+    orders: repeated calls give bit-identical energies."""
+    box = GpuBox(torch_gpu, inst_diff)
+    box.pairlist()
+    _, e1 = box.forces()
+    for _ in range(5):
+        _, e2 = box.forces()
+        assert np.array_equal(e1, e2)
+    box.close()
