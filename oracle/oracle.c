@@ -37,6 +37,14 @@
  *     potential r^-a - (A_a/3) t^3 - (B_a/4) t^4 - K_a, K_a its value at rc without K_a;
  *     E_LJ,ij = C12 Phi_12 - C6 Phi_6,  F_LJ,ij = (C12 F_12 - C6 F_6) d / r.
  *
+ * Ewald corrections (oracle_ewald_corrections), the terms that complete the real-space sum
+ * once a reciprocal-space part is added (the paper's runs use PME, section II-C):
+ *   every excluded pair {i, j}, at its minimum-image distance r (any r):
+ *     E_excl,ij = -fC q_i q_j erf(beta r) / r,
+ *     F_ij (on i) = fC q_i q_j [2 beta / sqrt(pi) exp(-beta^2 r^2) / r^2 - erf(beta r) / r^3] d,
+ *     (r = 0: E = -fC q_i q_j 2 beta / sqrt(pi), F = 0);
+ *   self term E_self = -fC beta / sqrt(pi) sum_i q_i^2 (no force).
+ *
  * Everything is FP64 with libm erfc/exp.  Loops are plain: a full double loop over atoms
  * (each unordered pair visited twice, each visit adding only to atom i) or the same loop over
  * 27 neighbouring cells.  Parallelism is an OpenMP loop over i with no shared writes.
@@ -470,5 +478,43 @@ int oracle_vjp(int n, const double *x, const double *q, const int *type, int nt,
     free(c12);
     free(ps);
     free(pe);
+    return 0;
+}
+
+/*
+ * Ewald exclusion correction and self term (see the header): out[0] = sum over excluded pairs
+ * of E_excl,ij, out[1] = E_self; f [n][3] receives the exclusion-correction forces (overwritten).
+ * Each excluded pair is visited from both atoms (the CSR lists are symmetric); each visit adds
+ * the force on its own atom, and the pair energy is taken once, at i < j.
+ */
+int oracle_ewald_corrections(int n, const double *x, const double *q, const double *box,
+                             double beta, double fc, const int *eoff, const int *eidx, double *f,
+                             double *out) {
+    double e_excl = 0.0, e_self = 0.0;
+    for (int i = 0; i < n; ++i) {
+        f[3 * i] = f[3 * i + 1] = f[3 * i + 2] = 0.0;
+        e_self -= fc * beta * (0.5 * TWO_OVER_SQRT_PI) * q[i] * q[i];
+        if (!eoff) continue;
+        for (int k = eoff[i]; k < eoff[i + 1]; ++k) {
+            const int j = eidx[k];
+            double d[3];
+            min_image(x + 3 * i, x + 3 * j, box, d);
+            const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            const double qq = fc * q[i] * q[j];
+            double e, fs;
+            if (r == 0.0) {
+                e = -qq * TWO_OVER_SQRT_PI * beta;
+                fs = 0.0;
+            } else {
+                const double er = erf(beta * r);
+                e = -qq * er / r;
+                fs = qq * (TWO_OVER_SQRT_PI * beta * exp(-beta * beta * r * r) / (r * r) - er / (r * r * r));
+            }
+            for (int c = 0; c < 3; ++c) f[3 * i + c] += fs * d[c];
+            if (i < j) e_excl += e;
+        }
+    }
+    out[0] = e_excl;
+    out[1] = e_self;
     return 0;
 }

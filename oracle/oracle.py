@@ -56,6 +56,8 @@ def lib():
                                  dp, dp, dp, dp]
         L.oracle_vjp.restype = c_i
         L.oracle_set_flavor.argtypes = [c_i, c_i, c_d, c_d]
+        L.oracle_ewald_corrections.argtypes = [c_i, dp, dp, dp, c_d, c_d, ip, ip, dp, dp]
+        L.oracle_ewald_corrections.restype = c_i
         _lib = L
     return _lib
 
@@ -225,6 +227,24 @@ def vjp(x, q, typ, sigma, epsilon, box, rc, beta, fc, excl_off, excl_idx, gF, gE
     if rc_ != 0:
         raise RuntimeError("oracle_vjp failed")
     return dx.reshape(n, 3), dq, ds, de
+
+
+def ewald_corrections(x, q, box, beta, fc, excl_off=None, excl_idx=None):
+    """Ewald exclusion correction and self term: returns (f [n][3] of the exclusion
+    correction, E_excl, E_self)."""
+    n = len(q)
+    xa, xp = _d(np.asarray(x, dtype=np.float64).reshape(-1))
+    qa, qp = _d(q)
+    ba, bp = _d(np.array([box] * 3 if np.isscalar(box) else box, dtype=np.float64))
+    if excl_off is not None:
+        oa, op = _i(excl_off)
+        ia, ipp = _i(excl_idx if len(excl_idx) else np.zeros(1, np.int32))
+    else:
+        op = ipp = None
+    f, fp = _d(np.zeros(3 * n))
+    out, outp = _d(np.zeros(2))
+    lib().oracle_ewald_corrections(n, xp, qp, bp, float(beta), float(fc), op, ipp, fp, outp)
+    return f.reshape(n, 3), float(out[0]), float(out[1])
 
 
 # ---- conveniences over an Instance ---------------------------------------------------------
