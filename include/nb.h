@@ -81,6 +81,14 @@ typedef enum nb_status {
 #define NB_REUSE_LIST   0x4u  /* nb_backward: use the current list instead of rebuilding */
 #define NB_ASYNC_BUILD  0x8u  /* nb_pairlist: do not wait for the build; its overflow check
                                  is read at the next nb_pairlist (first build: synchronous) */
+#define NB_EWALD_CORR   0x20u /* nb_forces also computes the Ewald exclusion correction and self
+                                 term that complete the real-space sum once a reciprocal part
+                                 is added: for every excluded pair -fC q_i q_j erf(beta r)/r
+                                 (minimum image, with its force, which f includes) and
+                                 -fC beta/sqrt(pi) sum q_i^2; e_dev then holds 4 doubles,
+                                 e_dev[2] = exclusion correction, e_dev[3] = self term (FP64).
+                                 Ewald electrostatics only; not for the batched form or
+                                 nb_backward (NB_ERR_ARG) */
 #define NB_ENERGY_FP64  0x10u /* evaluate the Coulomb pair energies in FP64 (forces stay FP32):
                                  needed for 1e-6 relative E_C in boxes of a few thousand atoms,
                                  where FP32 pair-energy rounding does not average out
@@ -100,7 +108,7 @@ typedef struct nb_params {
     const int32_t *excl_off;/* host [natoms+1] CSR offsets of excluded partners, or NULL */
     const int32_t *excl_idx;/* host [excl_off[natoms]] partner indices (symmetric lists),
                              * at most NB_MAX_EXCL_PER_ATOM per atom */
-    uint32_t flags;         /* NB_CHECK_*, NB_ASYNC_BUILD, NB_ENERGY_FP64 */
+    uint32_t flags;         /* NB_CHECK_*, NB_ASYNC_BUILD, NB_ENERGY_FP64, NB_EWALD_CORR */
     int32_t cluster;        /* cluster size C of the list: 4 or 8 (0 = 8) */
     int32_t elec;           /* NB_ELEC_EWALD (ewald_beta used) or NB_ELEC_RF */
     int32_t vdw;            /* NB_VDW_SHIFT or NB_VDW_FSWITCH */
@@ -158,7 +166,9 @@ int nb_pairlist(nb_ctx *ctx, const float *x_dev);
  * LJ type).  x must be the build positions or a continuous motion of them (no re-wrapping
  * since the build); pairs stay exact while every atom moved less than buffer/2.
  * Outputs: f_dev [natoms][3] overwritten in original order; e_dev[0] = E_LJ, e_dev[1] = E_C
- * (device doubles).  No allocation and no host synchronisation: capturable in a HIP graph.
+ * (device doubles; with NB_EWALD_CORR also e_dev[2] = Ewald exclusion correction, e_dev[3] =
+ * self term, and f includes the exclusion-correction forces).  No allocation and no host
+ * synchronisation: capturable in a HIP graph.
  * Errors: NB_ERR_STATE (no list), NB_ERR_HIP.  Stale / non-finite conditions are reported by
  * nb_check. */
 int nb_forces(nb_ctx *ctx, const float *x_dev, const float *q_dev, const int32_t *type_dev,

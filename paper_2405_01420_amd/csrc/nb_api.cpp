@@ -214,7 +214,8 @@ void free_all(nb_ctx *c) {
                     c->colcount, c->colstart, c->colcl, c->perm, c->xs,     c->xq,
                     c->tsort, c->units,  c->fj,     c->bblo,  c->bbhi,      c->icount,
                     c->jl,    c->epart,  c->meta,   c->ljtab, c->excl_off,  c->excl_idx,
-                    c->dbg_pairs, c->adj, c->adjj, c->gs, c->tpart, c->excl_slot, c->etab};
+                    c->dbg_pairs, c->adj, c->adjj, c->gs, c->tpart, c->excl_slot, c->etab,
+                    c->cpart};
     for (void *p : bufs)
         if (p) hipFree(p);
 }
@@ -257,8 +258,10 @@ int nb_validate_params(const nb_params *p) {
             return fail(nullptr, NB_ERR_ARG, "sigma/epsilon must be finite and >= 0");
     if (p->natoms < 1 || p->natoms > (1 << 27)) return fail(nullptr, NB_ERR_ARG, "natoms must be in 1..2^27");
     if (p->cluster != 0 && p->cluster != 4 && p->cluster != 8) return fail(nullptr, NB_ERR_ARG, "cluster must be 0, 4 or 8");
-    if (p->flags & ~(NB_CHECK_STALE | NB_CHECK_FINITE | NB_ASYNC_BUILD | NB_ENERGY_FP64))
+    if (p->flags & ~(NB_CHECK_STALE | NB_CHECK_FINITE | NB_ASYNC_BUILD | NB_ENERGY_FP64 | NB_EWALD_CORR))
         return fail(nullptr, NB_ERR_ARG, "unknown flag bits");
+    if ((p->flags & NB_EWALD_CORR) && p->elec != NB_ELEC_EWALD)
+        return fail(nullptr, NB_ERR_ARG, "NB_EWALD_CORR needs Ewald electrostatics");
     if (p->elec != NB_ELEC_EWALD && p->elec != NB_ELEC_RF) return fail(nullptr, NB_ERR_ARG, "elec must be NB_ELEC_EWALD or NB_ELEC_RF");
     if (p->vdw != NB_VDW_SHIFT && p->vdw != NB_VDW_FSWITCH) return fail(nullptr, NB_ERR_ARG, "vdw must be NB_VDW_SHIFT or NB_VDW_FSWITCH");
     if (p->elec == NB_ELEC_RF && !(isfinite(p->epsilon_rf) && (p->epsilon_rf == 0.0 || p->epsilon_rf >= 1.0)))
@@ -370,6 +373,7 @@ int nb_setup(nb_ctx **out, const nb_params *p, void *stream) {
     NB_ALLOC(icount, c->ncl_max);
     NB_ALLOC(units, c->unit_cap);
     NB_ALLOC(epart, 4 * (size_t)c->unit_cap);
+    if (c->flags & NB_EWALD_CORR) NB_ALLOC(cpart, 2 * (size_t)((n + NB_CORR_BLOCK - 1) / NB_CORR_BLOCK));
     NB_ALLOC(meta, 1);
     NB_ALLOC(ljtab, 2 * (size_t)c->ntypes * c->ntypes);
 #undef NB_ALLOC
@@ -519,6 +523,7 @@ int nb_forces(nb_ctx *c, const float *x, const float *q, const int32_t *type, fl
         err = hipEventRecord(c->ev[2 * c->ev_used + 1], c->stream);
         c->ev_used += 1;
     }
+    if (err == hipSuccess && (c->flags & NB_EWALD_CORR)) err = nb_launch_ewald_corr(c, x, q);
     if (err == hipSuccess) err = nb_launch_finalize(c, f, e);
     if (err != hipSuccess) return hip_fail(c, err, "force launch");
     return NB_OK;
@@ -627,6 +632,8 @@ int nb_backward(nb_ctx *c, const float *x, const float *q, const int32_t *type, 
         return fail(c, NB_ERR_ARG, "NULL argument");
     if (c->elec != NB_ELEC_EWALD || c->vdw != NB_VDW_SHIFT)
         return fail(c, NB_ERR_ARG, "nb_backward supports NB_ELEC_EWALD with NB_VDW_SHIFT only");
+    if (c->flags & NB_EWALD_CORR)
+        return fail(c, NB_ERR_ARG, "nb_backward does not include the Ewald corrections");
     hipSetDevice(c->device);
     if (!(flags & NB_REUSE_LIST) || !c->have_list) {
         int r = nb_pairlist(c, x);

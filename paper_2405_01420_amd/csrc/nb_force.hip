@@ -124,6 +124,78 @@ __global__ void __launch_bounds__(NB_FORCE_WAVES * NB_WAVE) NB_FORCE_OCCUPANCY k
     }
 }
 
+// Ewald exclusion correction and self term (NB_EWALD_CORR), run between the force kernel and
+// the finalize, one thread per atom, all in FP64: for each excluded partner j of atom i at the
+// minimum-image displacement d (r = |d|), the force fC q_i q_j (2 beta/sqrt(pi) exp(-beta^2 r^2)
+// / r^2 - erf(beta r) / r^3) d is added to atom i's slot of fj (each slot has one owner, and the
+// force kernel is complete), and the energy -fC q_i q_j erf(beta r) / r is counted at i < j;
+// the self term is -fC beta / sqrt(pi) q_i^2.  The block sums go to cpart[2 block ..].
+__global__ void __launch_bounds__(NB_CORR_BLOCK) k_ewald_corr(int n, int npad_max,
+                                                              const float *__restrict__ x,
+                                                              const float *__restrict__ q,
+                                                              const int *__restrict__ eoff,
+                                                              const int *__restrict__ eidx,
+                                                              const int *__restrict__ slot_of,
+                                                              double3 box, double beta, double fc,
+                                                              float *__restrict__ fj,
+                                                              double *__restrict__ cpart) {
+    constexpr double two_over_sqrt_pi = 1.1283791670955126;
+    __shared__ double s[2][NB_CORR_BLOCK / NB_WAVE];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double ex = 0.0, es = 0.0;
+    if (i < n) {
+        const double qi = q[i];
+        es = -fc * beta * (0.5 * two_over_sqrt_pi) * qi * qi;
+        if (eoff) {
+            const double xi = x[3 * i], yi = x[3 * i + 1], zi = x[3 * i + 2];
+            double fx = 0.0, fy = 0.0, fz = 0.0;
+            for (int k = eoff[i]; k < eoff[i + 1]; ++k) {
+                const int j = eidx[k];
+                double dx = xi - (double)x[3 * j], dy = yi - (double)x[3 * j + 1], dz = zi - (double)x[3 * j + 2];
+                dx -= box.x * rint(dx / box.x);
+                dy -= box.y * rint(dy / box.y);
+                dz -= box.z * rint(dz / box.z);
+                const double r2 = dx * dx + dy * dy + dz * dz;
+                const double qq = fc * qi * (double)q[j];
+                double e, fs;
+                if (r2 == 0.0) {
+                    e = -qq * two_over_sqrt_pi * beta;
+                    fs = 0.0;
+                } else {
+                    const double r = sqrt(r2), er = erf(beta * r);
+                    e = -qq * er / r;
+                    fs = qq * (two_over_sqrt_pi * beta * exp(-beta * beta * r2) / r2 - er / (r2 * r));
+                }
+                fx += fs * dx;
+                fy += fs * dy;
+                fz += fs * dz;
+                if (i < j) ex += e;
+            }
+            const int p = slot_of[i];
+            fj[p] += (float)fx;
+            fj[npad_max + p] += (float)fy;
+            fj[2 * npad_max + p] += (float)fz;
+        }
+    }
+    ex = nb_wave_sum_d(ex);
+    es = nb_wave_sum_d(es);
+    const int w = threadIdx.x / NB_WAVE;
+    if ((threadIdx.x & (NB_WAVE - 1)) == 0) {
+        s[0][w] = ex;
+        s[1][w] = es;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0.0, b = 0.0;
+        for (int k = 0; k < NB_CORR_BLOCK / NB_WAVE; ++k) {
+            a += s[0][k];
+            b += s[1][k];
+        }
+        cpart[2 * blockIdx.x] = a;
+        cpart[2 * blockIdx.x + 1] = b;
+    }
+}
+
 // f[atom] in original order, and the FP64 energy sums.  Block 0 additionally adds the energy
 // partials of the force workgroups in order (strided per thread, then the wave and block trees)
 // and applies the Coulomb shift; it is dispatched first, so this runs beside the other blocks'
@@ -133,7 +205,9 @@ __global__ void __launch_bounds__(NB_FIN_BLOCK) k_finalize(int n, int npad_max,
                                                            const float *__restrict__ fj,
                                                            float *__restrict__ f, const nb_meta *meta,
                                                            const double *__restrict__ epart,
-                                                           double shift_coul, double coul_scale,
+                                                           const double *__restrict__ cpart,
+                                                           int ncpart, double shift_coul,
+                                                           double coul_scale,
                                                            double *__restrict__ e) {
     __shared__ double s[3][NB_FIN_BLOCK / NB_WAVE];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -185,6 +259,16 @@ __global__ void __launch_bounds__(NB_FIN_BLOCK) k_finalize(int n, int npad_max,
         }
         e[0] = tx;
         e[1] = coul_scale * (ty - shift_coul * tz);
+        // Ewald corrections: a few hundred block sums, in block order
+        if (ncpart > 0) {
+            double a = 0.0, b = 0.0;
+            for (int k = 0; k < ncpart; ++k) {
+                a += cpart[2 * k];
+                b += cpart[2 * k + 1];
+            }
+            e[2] = a;
+            e[3] = b;
+        }
     }
 }
 
@@ -238,9 +322,20 @@ hipError_t nb_launch_force(nb_ctx *c) {
     return hipGetLastError();
 }
 
+hipError_t nb_launch_ewald_corr(nb_ctx *c, const float *x, const float *q) {
+    const int nblk = (c->natoms + NB_CORR_BLOCK - 1) / NB_CORR_BLOCK;
+    hipLaunchKernelGGL(k_ewald_corr, dim3(nblk), dim3(NB_CORR_BLOCK), 0, c->stream, c->natoms,
+                       c->npad_max, x, q, c->nnz_excl > 0 ? c->excl_off : nullptr, c->excl_idx,
+                       c->slot_of, make_double3(c->box[0], c->box[1], c->box[2]), c->beta, c->fc,
+                       c->fj, c->cpart);
+    return hipGetLastError();
+}
+
 hipError_t nb_launch_finalize(nb_ctx *c, float *f, double *e) {
     const int nblk = std::max(1, (c->natoms + NB_FIN_BLOCK - 1) / NB_FIN_BLOCK);
     hipLaunchKernelGGL(k_finalize, dim3(nblk), dim3(NB_FIN_BLOCK), 0, c->stream, c->natoms,
-                       c->npad_max, c->slot_of, c->fj, f, c->meta, c->epart, c->shift_coul, (c->flags & NB_ENERGY_FP64) ? c->fc : 1.0, e);
+                       c->npad_max, c->slot_of, c->fj, f, c->meta, c->epart, c->cpart,
+                       (c->flags & NB_EWALD_CORR) ? (c->natoms + NB_CORR_BLOCK - 1) / NB_CORR_BLOCK : 0,
+                       c->shift_coul, (c->flags & NB_ENERGY_FP64) ? c->fc : 1.0, e);
     return hipGetLastError();
 }

@@ -20,6 +20,7 @@ NB_OK, NB_ERR_ARG, NB_ERR_CUTOFF, NB_ERR_OOM, NB_ERR_HIP = 0, 1, 2, 3, 4
 NB_ERR_STATE, NB_ERR_OVERFLOW, NB_ERR_LIST_STALE, NB_ERR_NONFINITE, NB_ERR_IO = 5, 6, 7, 8, 9
 NB_CHECK_STALE, NB_CHECK_FINITE, NB_REUSE_LIST, NB_ASYNC_BUILD = 0x1, 0x2, 0x4, 0x8
 NB_ENERGY_FP64 = 0x10
+NB_EWALD_CORR = 0x20
 NB_MAX_EXCL_PER_ATOM = 32
 NB_ELEC_EWALD, NB_ELEC_RF = 0, 1
 NB_VDW_SHIFT, NB_VDW_FSWITCH = 0, 1

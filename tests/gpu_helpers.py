@@ -34,7 +34,7 @@ class GpuBox:
         self.q = dev(torch, inst.q)
         self.t = dev(torch, inst.type)
         self.f = torch.zeros(inst.natoms * 3, dtype=torch.float32, device="cuda:0")
-        self.e = torch.zeros(2, dtype=torch.float64, device="cuda:0")
+        self.e = torch.zeros(4 if flags & nb.NB_EWALD_CORR else 2, dtype=torch.float64, device="cuda:0")
 
     def set_x(self, x):
         self.x.copy_(self.torch.from_numpy(np.ascontiguousarray(x.reshape(-1))))

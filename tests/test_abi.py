@@ -78,6 +78,11 @@ def test_invalid_flavour_parameters_are_rejected(kw):
     assert nb.nb_validate_params(base_params(**kw)) == nb.NB_ERR_ARG
 
 
+def test_ewald_corrections_need_ewald_electrostatics():
+    assert nb.nb_validate_params(base_params(flags=nb.NB_EWALD_CORR)) == nb.NB_OK
+    assert nb.nb_validate_params(base_params(flags=nb.NB_EWALD_CORR, elec=1)) == nb.NB_ERR_ARG
+
+
 def test_valid_flavours_pass():
     for kw in (dict(elec=1), dict(elec=1, epsilon_rf=78.0), dict(vdw=1, rswitch=0.7),
                dict(elec=1, vdw=1, rswitch=0.0)):
