@@ -20,6 +20,7 @@
  *   F_ij    = [12 C12 r^-14 - 6 C6 r^-8
  *              + fC q_i q_j (erfc(beta r) / r^3 + 2 beta / sqrt(pi) exp(-beta^2 r^2) / r^2)] d
  *   F_i += F_ij,  F_j -= F_ij.
+ *   Virial (also reported): Xi = -1/2 sum over the same pairs of d (x) F_ij (3 x 3, symmetric).
  *   C6 = 4 eps_ab sigma_ab^6, C12 = 4 eps_ab sigma_ab^12 with Lorentz-Berthelot combination
  *   sigma_ab = (sigma_a + sigma_b) / 2, eps_ab = sqrt(eps_a eps_b).
  *   Excluded pairs contribute nothing (no reciprocal-space exclusion correction here).
@@ -175,6 +176,7 @@ static pair_out pair_terms(double r, double c6, double c12, double qq, double rc
  * half of each pair energy to atom i's energy.  Sums over atoms are done serially in atom order. */
 typedef struct {
     double elj, ec, ecu, abs_lj, abs_c, qq_in;
+    double vir[6]; /* xx, yy, zz, xy, xz, yz: a quarter of -d (x) F_ij per visit */
     int64_t npairs;
 } atom_acc;
 
@@ -197,6 +199,14 @@ static void visit(int i, int j, const double *x, const double *q, const int *typ
     acc->ecu += 0.5 * o.ec_unshifted;
     acc->abs_lj += 0.5 * fabs(o.elj);
     acc->abs_c += 0.5 * fabs(o.ec);
+    /* virial -1/2 sum over pairs of d (x) F_ij; each pair is visited twice with the same
+     * product d (x) F_ij */
+    acc->vir[0] -= 0.25 * o.fscal * d[0] * d[0];
+    acc->vir[1] -= 0.25 * o.fscal * d[1] * d[1];
+    acc->vir[2] -= 0.25 * o.fscal * d[2] * d[2];
+    acc->vir[3] -= 0.25 * o.fscal * d[0] * d[1];
+    acc->vir[4] -= 0.25 * o.fscal * d[0] * d[2];
+    acc->vir[5] -= 0.25 * o.fscal * d[1] * d[2];
     if (i < j) {
         acc->npairs += 1;
         acc->qq_in += q[i] * q[j];
@@ -204,9 +214,10 @@ static void visit(int i, int j, const double *x, const double *q, const int *typ
 }
 
 static void finish(int n, const atom_acc *acc, double *eatom_lj, double *eatom_c, double *out) {
-    double s[6] = {0, 0, 0, 0, 0, 0};
+    double s[6] = {0, 0, 0, 0, 0, 0}, v[6] = {0, 0, 0, 0, 0, 0};
     int64_t np = 0;
     for (int i = 0; i < n; ++i) {
+        for (int k = 0; k < 6; ++k) v[k] += acc[i].vir[k];
         s[0] += acc[i].elj;
         s[1] += acc[i].ec;
         s[2] += acc[i].ecu;
@@ -218,7 +229,9 @@ static void finish(int n, const atom_acc *acc, double *eatom_lj, double *eatom_c
         if (eatom_c) eatom_c[i] = acc[i].ec;
     }
     /* out: E_LJ, E_C, E_C without the potential shift, sum |E_LJ,ij|, sum |E_C,ij|,
-     *      number of interacting pairs, sum of q_i q_j over interacting pairs */
+     *      number of interacting pairs, sum of q_i q_j over interacting pairs, and from out[7]
+     *      the virial -1/2 sum d (x) F_ij as xx, yy, zz, xy, xz, yz */
+    for (int k = 0; k < 6; ++k) out[7 + k] = v[k];
     out[0] = s[0];
     out[1] = s[1];
     out[2] = s[2];
@@ -483,14 +496,16 @@ int oracle_vjp(int n, const double *x, const double *q, const int *type, int nt,
 
 /*
  * Ewald exclusion correction and self term (see the header): out[0] = sum over excluded pairs
- * of E_excl,ij, out[1] = E_self; f [n][3] receives the exclusion-correction forces (overwritten).
+ * of E_excl,ij, out[1] = E_self, out[2 ..] = the virial -1/2 sum d (x) F_ij of the exclusion
+ * correction (xx, yy, zz, xy, xz, yz); f [n][3] receives the exclusion-correction forces
+ * (overwritten).
  * Each excluded pair is visited from both atoms (the CSR lists are symmetric); each visit adds
  * the force on its own atom, and the pair energy is taken once, at i < j.
  */
 int oracle_ewald_corrections(int n, const double *x, const double *q, const double *box,
                              double beta, double fc, const int *eoff, const int *eidx, double *f,
                              double *out) {
-    double e_excl = 0.0, e_self = 0.0;
+    double e_excl = 0.0, e_self = 0.0, vir[6] = {0, 0, 0, 0, 0, 0};
     for (int i = 0; i < n; ++i) {
         f[3 * i] = f[3 * i + 1] = f[3 * i + 2] = 0.0;
         e_self -= fc * beta * (0.5 * TWO_OVER_SQRT_PI) * q[i] * q[i];
@@ -511,10 +526,19 @@ int oracle_ewald_corrections(int n, const double *x, const double *q, const doub
                 fs = qq * (TWO_OVER_SQRT_PI * beta * exp(-beta * beta * r * r) / (r * r) - er / (r * r * r));
             }
             for (int c = 0; c < 3; ++c) f[3 * i + c] += fs * d[c];
-            if (i < j) e_excl += e;
+            if (i < j) {
+                e_excl += e;
+                vir[0] -= 0.5 * fs * d[0] * d[0];
+                vir[1] -= 0.5 * fs * d[1] * d[1];
+                vir[2] -= 0.5 * fs * d[2] * d[2];
+                vir[3] -= 0.5 * fs * d[0] * d[1];
+                vir[4] -= 0.5 * fs * d[0] * d[2];
+                vir[5] -= 0.5 * fs * d[1] * d[2];
+            }
         }
     }
     out[0] = e_excl;
     out[1] = e_self;
+    for (int k = 0; k < 6; ++k) out[2 + k] = vir[k];
     return 0;
 }

@@ -96,7 +96,8 @@ class Result:
 
     e_lj, e_coul: potential-shifted energies; e_coul_unshifted: without the Coulomb shift;
     abs_lj, abs_coul: sums of |pair energy| (conditioning); npairs: interacting pairs;
-    qq_sum: sum of q_i q_j over interacting pairs; eatom_*: per-atom halves of pair energies."""
+    qq_sum: sum of q_i q_j over interacting pairs; eatom_*: per-atom halves of pair energies;
+    virial: -1/2 sum over interacting pairs of d (x) F_ij (3 x 3)."""
 
     def __init__(self, f, out, eatom_lj, eatom_c):
         self.f = f
@@ -104,6 +105,8 @@ class Result:
         self.abs_lj, self.abs_coul = out[3], out[4]
         self.npairs = int(round(out[5]))
         self.qq_sum = out[6]
+        v = out[7:13]
+        self.virial = np.array([[v[0], v[3], v[4]], [v[3], v[1], v[5]], [v[4], v[5], v[2]]])
         self.eatom_lj, self.eatom_c = eatom_lj, eatom_c
 
 
@@ -152,7 +155,7 @@ def forces(x, q, typ, sigma, epsilon, box, rc, beta, fc, excl_off=None, excl_idx
     f, fp = _d(np.zeros(3 * n))
     el, elp = _d(np.zeros(n))
     ec, ecp = _d(np.zeros(n))
-    out, outp = _d(np.zeros(8))
+    out, outp = _d(np.zeros(16))
     fn = lib().oracle_forces_cells if cells else lib().oracle_forces
     with _flavor(elec, vdw, epsilon_rf, rswitch):
         rc_ = fn(n, xp, qp, tp, len(c6), c6p, c12p, bp, float(rc), float(beta), float(fc), op, ipp,
@@ -231,7 +234,7 @@ def vjp(x, q, typ, sigma, epsilon, box, rc, beta, fc, excl_off, excl_idx, gF, gE
 
 def ewald_corrections(x, q, box, beta, fc, excl_off=None, excl_idx=None):
     """Ewald exclusion correction and self term: returns (f [n][3] of the exclusion
-    correction, E_excl, E_self)."""
+    correction, E_excl, E_self, virial 3 x 3 of the exclusion correction)."""
     n = len(q)
     xa, xp = _d(np.asarray(x, dtype=np.float64).reshape(-1))
     qa, qp = _d(q)
@@ -242,9 +245,11 @@ def ewald_corrections(x, q, box, beta, fc, excl_off=None, excl_idx=None):
     else:
         op = ipp = None
     f, fp = _d(np.zeros(3 * n))
-    out, outp = _d(np.zeros(2))
+    out, outp = _d(np.zeros(8))
     lib().oracle_ewald_corrections(n, xp, qp, bp, float(beta), float(fc), op, ipp, fp, outp)
-    return f.reshape(n, 3), float(out[0]), float(out[1])
+    v = out[2:8]
+    vir = np.array([[v[0], v[3], v[4]], [v[3], v[1], v[5]], [v[4], v[5], v[2]]])
+    return f.reshape(n, 3), float(out[0]), float(out[1]), vir
 
 
 # ---- conveniences over an Instance ---------------------------------------------------------

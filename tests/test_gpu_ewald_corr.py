@@ -22,7 +22,7 @@ def test_ewald_corrections_match_oracle(torch_gpu, name, flags):
     f, e = box.forces()
     box.close()
     ref = O.instance_forces(inst, cells=name != "tiny")
-    fcorr, e_excl, e_self = O.ewald_corrections(inst.x, inst.q, inst.box, inst.beta,
+    fcorr, e_excl, e_self, _ = O.ewald_corrections(inst.x, inst.q, inst.box, inst.beta,
                                                 inst.coulomb_const, inst.excl_off, inst.excl_idx)
     ref.f = ref.f + fcorr
     fr, elj, ec = compare_forces(f, e, ref, f"{name} with Ewald corrections")
@@ -47,7 +47,7 @@ def test_ewald_corrections_follow_the_positions(torch_gpu):
     f, e = box.forces()
     box.close()
     ref = O.instance_forces(inst, x=x)
-    fcorr, e_excl, e_self = O.ewald_corrections(x, inst.q, inst.box, inst.beta,
+    fcorr, e_excl, e_self, _ = O.ewald_corrections(x, inst.q, inst.box, inst.beta,
                                                 inst.coulomb_const, inst.excl_off, inst.excl_idx)
     ref.f = ref.f + fcorr
     fr, elj, ec = compare_forces(f, e, ref, "tiny moved, with Ewald corrections")

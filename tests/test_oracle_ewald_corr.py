@@ -38,7 +38,7 @@ def pair_list(x):
 
 def test_large_beta_gives_minus_bare_coulomb():
     x, q, off, idx = water()
-    f, e_excl, _ = corr(x, q, off, idx, beta=50.0)
+    f, e_excl, _, _ = corr(x, q, off, idx, beta=50.0)
     bare = sum(FC * q[i] * q[j] / r for i, j, r in pair_list(x))
     assert abs(e_excl + bare) <= 1e-10 * abs(bare)
     fb = np.zeros((3, 3))
@@ -52,7 +52,7 @@ def test_large_beta_gives_minus_bare_coulomb():
 def test_small_beta_self_and_exclusion_cancel_to_beta_cubed():
     x, q, off, idx = water()
     beta = 1e-3
-    _, e_excl, e_self = corr(x, q, off, idx, beta)
+    _, e_excl, e_self, _ = corr(x, q, off, idx, beta)
     lead = FC * 2.0 * beta ** 3 / (3.0 * math.sqrt(math.pi)) * sum(q[i] * q[j] * r * r for i, j, r in pair_list(x))
     assert abs((e_excl + e_self) - lead) <= 1e-5 * abs(lead)
     # each term alone is far larger than the sum: the cancellation is what is checked
@@ -62,7 +62,7 @@ def test_small_beta_self_and_exclusion_cancel_to_beta_cubed():
 @pytest.mark.parametrize("beta", [1.0, 3.47])
 def test_exclusion_forces_are_minus_gradient(beta):
     x, q, off, idx = water(center=(0.02, 9.97, 5.0))  # straddles two periodic faces
-    f, _, _ = corr(x, q, off, idx, beta)
+    f, _, _, _ = corr(x, q, off, idx, beta)
     h = 1e-6
     for a in range(3):
         for c in range(3):
@@ -79,17 +79,17 @@ def test_coincident_excluded_atoms_take_the_limit():
     off = np.array([0, 1, 2], np.int32)
     idx = np.array([1, 0], np.int32)
     beta = 3.0
-    f, e0, _ = corr(x, q, off, idx, beta)
+    f, e0, _, _ = corr(x, q, off, idx, beta)
     assert abs(e0 + FC * q[0] * q[1] * 2.0 * beta / math.sqrt(math.pi)) <= 1e-12 * abs(e0)
     assert np.all(f == 0.0)
     x[1, 2] += 1e-6
-    _, e1, _ = corr(x, q, off, idx, beta)
+    _, e1, _, _ = corr(x, q, off, idx, beta)
     assert abs(e1 - e0) <= 1e-9 * abs(e0)
 
 
 def test_water_box_obeys_newtons_third_law():
     inst = synth.tiny()
-    f, e_excl, e_self = O.ewald_corrections(inst.x, inst.q, inst.box, inst.beta, inst.coulomb_const,
+    f, e_excl, e_self, _ = O.ewald_corrections(inst.x, inst.q, inst.box, inst.beta, inst.coulomb_const,
                                             inst.excl_off, inst.excl_idx)
     assert np.abs(f.sum(0)).max() <= 1e-12 * np.abs(f).sum()
     assert e_self < 0.0 < e_excl
