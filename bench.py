@@ -334,6 +334,15 @@ def main():
     torch.cuda.synchronize()
     us_force = 1e3 * ev0.elapsed_time(ev1) / reps
 
+    # the same call with the virial output
+    vir = torch.zeros(9, dtype=torch.float64, device=dev)
+    ev0.record()
+    for k in range(reps):
+        nb.nb_forces_virial(ctx, traj[0], q, t, f, e, vir)
+    ev1.record()
+    torch.cuda.synchronize()
+    us_force_virial = 1e3 * ev0.elapsed_time(ev1) / reps
+
     # list build alone (each build waits for the previous one's status)
     torch.cuda.synchronize()
     tb = time.perf_counter()
@@ -381,6 +390,7 @@ def main():
                    + (", LJ potential shift" if args.vdw == "shift" else f", LJ force switch from {args.rswitch} nm"),
                    "evaluated_pairs": stats["evaluated_pairs"], "list_entries": stats["nentries"]},
         "us_per_force_call": us_force,
+        "us_per_force_call_with_virial": us_force_virial,
         "us_per_list_build": us_build,
         "us_per_call_amortised": 1e3 * ms_per_step,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS,

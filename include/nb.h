@@ -174,6 +174,15 @@ int nb_pairlist(nb_ctx *ctx, const float *x_dev);
 int nb_forces(nb_ctx *ctx, const float *x_dev, const float *q_dev, const int32_t *type_dev,
               float *f_dev, double *e_dev);
 
+/* nb_forces plus the virial of the computed forces, vir_dev [3][3] (device doubles, row-major,
+ * symmetric): Xi = -1/2 sum over the interacting pairs of d_ij (x) F_ij, with d_ij the
+ * minimum-image displacement x_i - x_j and F_ij the pair force on i; with NB_EWALD_CORR the
+ * excluded pairs' correction forces are included.  This is the pair-force part of the pressure
+ * an MD step reports on energy steps.  Same ownership, asynchrony and errors as nb_forces
+ * (NB_ERR_ARG if vir_dev is NULL); about 6 more FMAs per pair. */
+int nb_forces_virial(nb_ctx *ctx, const float *x_dev, const float *q_dev, const int32_t *type_dev,
+                     float *f_dev, double *e_dev, double *vir_dev);
+
 /* Synchronise the stream and report device-side conditions recorded since the last check:
  * NB_ERR_LIST_STALE, NB_ERR_NONFINITE, NB_ERR_OVERFLOW; clears them. */
 int nb_check(nb_ctx *ctx);

@@ -215,7 +215,7 @@ void free_all(nb_ctx *c) {
                     c->tsort, c->units,  c->fj,     c->bblo,  c->bbhi,      c->icount,
                     c->jl,    c->epart,  c->meta,   c->ljtab, c->excl_off,  c->excl_idx,
                     c->dbg_pairs, c->adj, c->adjj, c->gs, c->tpart, c->excl_slot, c->etab,
-                    c->cpart};
+                    c->cpart, c->vpart};
     for (void *p : bufs)
         if (p) hipFree(p);
 }
@@ -373,7 +373,8 @@ int nb_setup(nb_ctx **out, const nb_params *p, void *stream) {
     NB_ALLOC(icount, c->ncl_max);
     NB_ALLOC(units, c->unit_cap);
     NB_ALLOC(epart, 4 * (size_t)c->unit_cap);
-    if (c->flags & NB_EWALD_CORR) NB_ALLOC(cpart, 2 * (size_t)((n + NB_CORR_BLOCK - 1) / NB_CORR_BLOCK));
+    if (c->flags & NB_EWALD_CORR) NB_ALLOC(cpart, NB_CORR_PART * (size_t)((n + NB_CORR_BLOCK - 1) / NB_CORR_BLOCK));
+    NB_ALLOC(vpart, 6 * (size_t)((c->unit_cap + 3) / 4));
     NB_ALLOC(meta, 1);
     NB_ALLOC(ljtab, 2 * (size_t)c->ntypes * c->ntypes);
 #undef NB_ALLOC
@@ -499,7 +500,8 @@ int nb_pairlist(nb_ctx *c, const float *x) {
     return fail(c, NB_ERR_OVERFLOW, "pair list still overflowing after regrowing");
 }
 
-int nb_forces(nb_ctx *c, const float *x, const float *q, const int32_t *type, float *f, double *e) {
+static int forces_impl(nb_ctx *c, const float *x, const float *q, const int32_t *type, float *f,
+                       double *e, double *vir) {
     if (!c || !x || !q || !type || !f || !e) return fail(c, NB_ERR_ARG, "NULL argument");
     if (!c->have_list) return fail(c, NB_ERR_STATE, "nb_forces called before nb_pairlist");
     hipError_t err = nb_launch_pack(c, x, q, type);
@@ -518,15 +520,25 @@ int nb_forces(nb_ctx *c, const float *x, const float *q, const int32_t *type, fl
         }
         err = hipEventRecord(c->ev[2 * c->ev_used], c->stream);
     }
-    if (err == hipSuccess) err = nb_launch_force(c);
+    if (err == hipSuccess) err = nb_launch_force(c, vir != nullptr);
     if (c->timing && err == hipSuccess) {
         err = hipEventRecord(c->ev[2 * c->ev_used + 1], c->stream);
         c->ev_used += 1;
     }
     if (err == hipSuccess && (c->flags & NB_EWALD_CORR)) err = nb_launch_ewald_corr(c, x, q);
-    if (err == hipSuccess) err = nb_launch_finalize(c, f, e);
+    if (err == hipSuccess) err = nb_launch_finalize(c, f, e, vir);
     if (err != hipSuccess) return hip_fail(c, err, "force launch");
     return NB_OK;
+}
+
+int nb_forces(nb_ctx *c, const float *x, const float *q, const int32_t *type, float *f, double *e) {
+    return forces_impl(c, x, q, type, f, e, nullptr);
+}
+
+int nb_forces_virial(nb_ctx *c, const float *x, const float *q, const int32_t *type, float *f,
+                     double *e, double *vir) {
+    if (!vir) return fail(c, NB_ERR_ARG, "NULL argument");
+    return forces_impl(c, x, q, type, f, e, vir);
 }
 
 int nb_set_timing(nb_ctx *c, int on) {

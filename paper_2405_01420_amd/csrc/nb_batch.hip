@@ -136,7 +136,7 @@ __global__ void __launch_bounds__(256) NB_FORCE_OCCUPANCY k_batch_force(nb_fpara
             f.L[1] = d.L[1];
             f.L[2] = d.L[2];
             // the descriptor's pointers are global memory; typed so, their accesses are global
-            const nb_esum es = nb_force_cluster<C, EPREC, FLAV>(
+            const nb_esum es = nb_force_cluster<C, EPREC, FLAV, false>(
                 f, tab, et, ci, 0, 1 << 20, d.cap, d.npad_max, nb_g(d.xq), nb_g(d.tsort),
                 nb_g(d.icount), nb_g(d.jl), nb_g(d.fj));
             if (lane == 0) {

@@ -63,8 +63,8 @@ __device__ __forceinline__ double wave_sum(double v) {
 // stored as the workgroup's partial (epart[4 blockIdx ..]); waves do not wait for each other.
 #define NB_FORCE_WAVES 4
 
-template <int C, bool EPREC, int FLAV>
-__global__ void __launch_bounds__(NB_FORCE_WAVES * NB_WAVE) NB_FORCE_OCCUPANCY k_force(nb_fparams fp, int cap, int npad_max,
+template <int C, bool EPREC, int FLAV, bool VIR>
+__global__ void __launch_bounds__(NB_FORCE_WAVES * NB_WAVE) NB_FORCE_OCCUPANCY_VIR k_force(nb_fparams fp, int cap, int npad_max,
                                                const float4 *__restrict__ xq,
                                                const int *__restrict__ tsort,
                                                const float4 *__restrict__ ljtab,
@@ -73,9 +73,10 @@ __global__ void __launch_bounds__(NB_FORCE_WAVES * NB_WAVE) NB_FORCE_OCCUPANCY k
                                                const int *__restrict__ icount,
                                                const nb_entry *__restrict__ jl,
                                                const int4 *__restrict__ units, float *__restrict__ fj,
-                                               double *__restrict__ epart, const nb_meta *meta) {
+                                               double *__restrict__ epart, double *__restrict__ vpart,
+                                               const nb_meta *meta) {
     extern __shared__ float4 tab[];
-    __shared__ double esh[NB_FORCE_WAVES][3];
+    __shared__ double esh[NB_FORCE_WAVES][VIR ? 9 : 3];
     __shared__ int edone;
     const int ntt = fp.ntypes * fp.ntypes;
     if (threadIdx.x == 0) edone = 0;
@@ -93,10 +94,10 @@ __global__ void __launch_bounds__(NB_FORCE_WAVES * NB_WAVE) NB_FORCE_OCCUPANCY k
     const int u = __builtin_amdgcn_readfirstlane(blockIdx.x * NB_FORCE_WAVES + wv);
     const int nunits = meta->nunits;
     if (blockIdx.x * NB_FORCE_WAVES >= nunits) return;  // the whole workgroup is idle
-    nb_esum es{0.0, 0.0, 0.0};
+    nb_esum es{0.0, 0.0, 0.0, {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}};
     if (u < nunits) {
         const int4 w = units[u];
-        es = nb_force_cluster<C, EPREC, FLAV>(fp, tab, et, __builtin_amdgcn_readfirstlane(w.x),
+        es = nb_force_cluster<C, EPREC, FLAV, VIR>(fp, tab, et, __builtin_amdgcn_readfirstlane(w.x),
                                               __builtin_amdgcn_readfirstlane(w.y),
                                               __builtin_amdgcn_readfirstlane(w.z), cap, npad_max,
                                               nb_g(xq), nb_g(tsort), nb_g(icount), nb_g(jl), nb_g(fj));
@@ -106,6 +107,10 @@ __global__ void __launch_bounds__(NB_FORCE_WAVES * NB_WAVE) NB_FORCE_OCCUPANCY k
         esh[wv][0] = es.elj;
         esh[wv][1] = es.ec;
         esh[wv][2] = es.qq;
+        if (VIR) {
+#pragma unroll
+            for (int m = 0; m < 6; ++m) esh[wv][3 + m] = es.v[m];
+        }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         last = __hip_atomic_fetch_add(&edone, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) ==
                NB_FORCE_WAVES - 1;
@@ -120,6 +125,13 @@ __global__ void __launch_bounds__(NB_FORCE_WAVES * NB_WAVE) NB_FORCE_OCCUPANCY k
             epart[4 * blockIdx.x] = a;
             epart[4 * blockIdx.x + 1] = b;
             epart[4 * blockIdx.x + 2] = c;
+            if (VIR) {
+                for (int m = 0; m < 6; ++m) {
+                    double v = 0.0;
+                    for (int k = 0; k < NB_FORCE_WAVES; ++k) v += esh[k][3 + m];
+                    vpart[6 * blockIdx.x + m] = v;
+                }
+            }
         }
     }
 }
@@ -129,7 +141,8 @@ __global__ void __launch_bounds__(NB_FORCE_WAVES * NB_WAVE) NB_FORCE_OCCUPANCY k
 // minimum-image displacement d (r = |d|), the force fC q_i q_j (2 beta/sqrt(pi) exp(-beta^2 r^2)
 // / r^2 - erf(beta r) / r^3) d is added to atom i's slot of fj (each slot has one owner, and the
 // force kernel is complete), and the energy -fC q_i q_j erf(beta r) / r is counted at i < j;
-// the self term is -fC beta / sqrt(pi) q_i^2.  The block sums go to cpart[2 block ..].
+// the self term is -fC beta / sqrt(pi) q_i^2.  The block sums (the two energies and the pair
+// sums of f d_a d_b for the virial) go to cpart[NB_CORR_PART block ..].
 __global__ void __launch_bounds__(NB_CORR_BLOCK) k_ewald_corr(int n, int npad_max,
                                                               const float *__restrict__ x,
                                                               const float *__restrict__ q,
@@ -140,9 +153,9 @@ __global__ void __launch_bounds__(NB_CORR_BLOCK) k_ewald_corr(int n, int npad_ma
                                                               float *__restrict__ fj,
                                                               double *__restrict__ cpart) {
     constexpr double two_over_sqrt_pi = 1.1283791670955126;
-    __shared__ double s[2][NB_CORR_BLOCK / NB_WAVE];
+    __shared__ double s[NB_CORR_PART][NB_CORR_BLOCK / NB_WAVE];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    double ex = 0.0, es = 0.0;
+    double ex = 0.0, es = 0.0, v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     if (i < n) {
         const double qi = q[i];
         es = -fc * beta * (0.5 * two_over_sqrt_pi) * qi * qi;
@@ -169,7 +182,15 @@ __global__ void __launch_bounds__(NB_CORR_BLOCK) k_ewald_corr(int n, int npad_ma
                 fx += fs * dx;
                 fy += fs * dy;
                 fz += fs * dz;
-                if (i < j) ex += e;
+                if (i < j) {
+                    ex += e;
+                    v[0] += fs * dx * dx;
+                    v[1] += fs * dy * dy;
+                    v[2] += fs * dz * dz;
+                    v[3] += fs * dx * dy;
+                    v[4] += fs * dx * dz;
+                    v[5] += fs * dy * dz;
+                }
             }
             const int p = slot_of[i];
             fj[p] += (float)fx;
@@ -179,20 +200,19 @@ __global__ void __launch_bounds__(NB_CORR_BLOCK) k_ewald_corr(int n, int npad_ma
     }
     ex = nb_wave_sum_d(ex);
     es = nb_wave_sum_d(es);
+#pragma unroll
+    for (int m = 0; m < 6; ++m) v[m] = nb_wave_sum_d(v[m]);
     const int w = threadIdx.x / NB_WAVE;
     if ((threadIdx.x & (NB_WAVE - 1)) == 0) {
         s[0][w] = ex;
         s[1][w] = es;
+        for (int m = 0; m < 6; ++m) s[2 + m][w] = v[m];
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double a = 0.0, b = 0.0;
-        for (int k = 0; k < NB_CORR_BLOCK / NB_WAVE; ++k) {
-            a += s[0][k];
-            b += s[1][k];
-        }
-        cpart[2 * blockIdx.x] = a;
-        cpart[2 * blockIdx.x + 1] = b;
+    if (threadIdx.x < NB_CORR_PART) {
+        double a = 0.0;
+        for (int k = 0; k < NB_CORR_BLOCK / NB_WAVE; ++k) a += s[threadIdx.x][k];
+        cpart[NB_CORR_PART * blockIdx.x + threadIdx.x] = a;
     }
 }
 
@@ -208,7 +228,9 @@ __global__ void __launch_bounds__(NB_FIN_BLOCK) k_finalize(int n, int npad_max,
                                                            const double *__restrict__ cpart,
                                                            int ncpart, double shift_coul,
                                                            double coul_scale,
-                                                           double *__restrict__ e) {
+                                                           double *__restrict__ e,
+                                                           const double *__restrict__ vpart,
+                                                           double *__restrict__ vir) {
     __shared__ double s[3][NB_FIN_BLOCK / NB_WAVE];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) {
@@ -260,14 +282,31 @@ __global__ void __launch_bounds__(NB_FIN_BLOCK) k_finalize(int n, int npad_max,
         e[0] = tx;
         e[1] = coul_scale * (ty - shift_coul * tz);
         // Ewald corrections: a few hundred block sums, in block order
+        double vc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         if (ncpart > 0) {
             double a = 0.0, b = 0.0;
             for (int k = 0; k < ncpart; ++k) {
-                a += cpart[2 * k];
-                b += cpart[2 * k + 1];
+                a += cpart[NB_CORR_PART * k];
+                b += cpart[NB_CORR_PART * k + 1];
+                for (int m = 0; m < 6; ++m) vc[m] += cpart[NB_CORR_PART * k + 2 + m];
             }
             e[2] = a;
             e[3] = b;
+        }
+        if (vir) {
+            // Xi = -1/2 sum over pairs of d (x) F_ij, F_ij = f d: the force workgroups' sums in
+            // order, then the exclusion correction's
+            const int np = (meta->nunits + NB_FORCE_WAVES - 1) / NB_FORCE_WAVES;
+            double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            for (int k = 0; k < np; ++k)
+                for (int m = 0; m < 6; ++m) v[m] += vpart[6 * k + m];
+            for (int m = 0; m < 6; ++m) v[m] = -0.5 * (v[m] + vc[m]);
+            vir[0] = v[0];
+            vir[4] = v[1];
+            vir[8] = v[2];
+            vir[1] = vir[3] = v[3];
+            vir[2] = vir[6] = v[4];
+            vir[5] = vir[7] = v[5];
         }
     }
 }
@@ -283,42 +322,49 @@ hipError_t nb_launch_pack(nb_ctx *c, const float *x, const float *q, const int32
     return hipGetLastError();
 }
 
-template <int C, bool EPREC, int FLAV>
+template <int C, bool EPREC, int FLAV, bool VIR>
 static void launch_force_t(nb_ctx *c) {
     const size_t shm = sizeof(float4) * 2 * c->ntypes * c->ntypes +
                        (EPREC ? sizeof(double2) * 2 * c->etab_n : 0);
     dim3 grid((c->unit_cap + NB_FORCE_WAVES - 1) / NB_FORCE_WAVES), block(NB_FORCE_WAVES * NB_WAVE);
-    hipLaunchKernelGGL((k_force<C, EPREC, FLAV>), grid, block, shm, c->stream, c->fp, c->cap, c->npad_max,
-                       c->xq, c->tsort, c->ljtab, c->etab, c->etab_n, c->etab_invh, c->icount,
-                       c->jl, c->units, c->fj, c->epart, c->meta);
+    hipLaunchKernelGGL((k_force<C, EPREC, FLAV, VIR>), grid, block, shm, c->stream, c->fp, c->cap,
+                       c->npad_max, c->xq, c->tsort, c->ljtab, c->etab, c->etab_n, c->etab_invh,
+                       c->icount, c->jl, c->units, c->fj, c->epart, c->vpart, c->meta);
+}
+
+template <int C, int FLAV>
+static void launch_force_f(nb_ctx *c, bool vir) {
+    const bool ep = (c->flags & NB_ENERGY_FP64) != 0;
+    if (vir) {
+        if (ep) launch_force_t<C, true, FLAV, true>(c);
+        else launch_force_t<C, false, FLAV, true>(c);
+    } else {
+        if (ep) launch_force_t<C, true, FLAV, false>(c);
+        else launch_force_t<C, false, FLAV, false>(c);
+    }
 }
 
 template <int C>
-static void launch_force_c(nb_ctx *c) {
-    const bool ep = (c->flags & NB_ENERGY_FP64) != 0;
+static void launch_force_c(nb_ctx *c, bool vir) {
     switch (NB_FLAV(c->elec, c->vdw)) {
     case NB_FLAV(NB_ELEC_EWALD, NB_VDW_SHIFT):
-        if (ep) launch_force_t<C, true, NB_FLAV(NB_ELEC_EWALD, NB_VDW_SHIFT)>(c);
-        else launch_force_t<C, false, NB_FLAV(NB_ELEC_EWALD, NB_VDW_SHIFT)>(c);
+        launch_force_f<C, NB_FLAV(NB_ELEC_EWALD, NB_VDW_SHIFT)>(c, vir);
         break;
     case NB_FLAV(NB_ELEC_EWALD, NB_VDW_FSWITCH):
-        if (ep) launch_force_t<C, true, NB_FLAV(NB_ELEC_EWALD, NB_VDW_FSWITCH)>(c);
-        else launch_force_t<C, false, NB_FLAV(NB_ELEC_EWALD, NB_VDW_FSWITCH)>(c);
+        launch_force_f<C, NB_FLAV(NB_ELEC_EWALD, NB_VDW_FSWITCH)>(c, vir);
         break;
     case NB_FLAV(NB_ELEC_RF, NB_VDW_SHIFT):
-        if (ep) launch_force_t<C, true, NB_FLAV(NB_ELEC_RF, NB_VDW_SHIFT)>(c);
-        else launch_force_t<C, false, NB_FLAV(NB_ELEC_RF, NB_VDW_SHIFT)>(c);
+        launch_force_f<C, NB_FLAV(NB_ELEC_RF, NB_VDW_SHIFT)>(c, vir);
         break;
     default:
-        if (ep) launch_force_t<C, true, NB_FLAV(NB_ELEC_RF, NB_VDW_FSWITCH)>(c);
-        else launch_force_t<C, false, NB_FLAV(NB_ELEC_RF, NB_VDW_FSWITCH)>(c);
+        launch_force_f<C, NB_FLAV(NB_ELEC_RF, NB_VDW_FSWITCH)>(c, vir);
         break;
     }
 }
 
-hipError_t nb_launch_force(nb_ctx *c) {
-    if (c->C == 4) launch_force_c<4>(c);
-    else launch_force_c<8>(c);
+hipError_t nb_launch_force(nb_ctx *c, bool vir) {
+    if (c->C == 4) launch_force_c<4>(c, vir);
+    else launch_force_c<8>(c, vir);
     return hipGetLastError();
 }
 
@@ -331,11 +377,11 @@ hipError_t nb_launch_ewald_corr(nb_ctx *c, const float *x, const float *q) {
     return hipGetLastError();
 }
 
-hipError_t nb_launch_finalize(nb_ctx *c, float *f, double *e) {
+hipError_t nb_launch_finalize(nb_ctx *c, float *f, double *e, double *vir) {
     const int nblk = std::max(1, (c->natoms + NB_FIN_BLOCK - 1) / NB_FIN_BLOCK);
     hipLaunchKernelGGL(k_finalize, dim3(nblk), dim3(NB_FIN_BLOCK), 0, c->stream, c->natoms,
                        c->npad_max, c->slot_of, c->fj, f, c->meta, c->epart, c->cpart,
                        (c->flags & NB_EWALD_CORR) ? (c->natoms + NB_CORR_BLOCK - 1) / NB_CORR_BLOCK : 0,
-                       c->shift_coul, (c->flags & NB_ENERGY_FP64) ? c->fc : 1.0, e);
+                       c->shift_coul, (c->flags & NB_ENERGY_FP64) ? c->fc : 1.0, e, c->vpart, vir);
     return hipGetLastError();
 }

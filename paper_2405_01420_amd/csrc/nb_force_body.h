@@ -28,6 +28,9 @@
 // about that many, and the compiler's unconstrained choice lands just above, at three waves.
 // The FP64-energy variant is register-bound either way and is left to the compiler.
 #define NB_FORCE_OCCUPANCY __attribute__((amdgpu_waves_per_eu(EPREC ? 1 : 4)))
+// With the virial sums (six more accumulators per lane) the FP32 body needs more than 128
+// VGPRs: three waves per SIMD.
+#define NB_FORCE_OCCUPANCY_VIR __attribute__((amdgpu_waves_per_eu(EPREC ? 1 : (VIR ? 3 : 4))))
 
 __device__ __forceinline__ double nb_wave_sum_d(double v) {
 #pragma unroll
@@ -58,18 +61,20 @@ struct nb_etab {
 // the topology mask; without it every unordered pair within rc interacts.  FLAV selects the
 // electrostatics (Ewald real space or reaction field) and the Lennard-Jones cutoff treatment
 // (potential shift or force switch), NB_FLAV(elec, vdw).
-template <int C, bool MASKED, bool EPREC, int FLAV>
+template <int C, bool MASKED, bool EPREC, int FLAV, bool VIR>
 __device__ __forceinline__ void pair_block(const nb_fparams &fp, const float4 *tab, int ntt,
                                            const nb_etab &et, const float *xs, const float *ys,
                                            const float *zs, const float *qi, const int *ti,
                                            nb_jlane &j, float *fix, float *fiy, float *fiz,
                                            double &elj, double &ec, float &qqs, double &qqsd,
-                                           float p4v, float q5v) {
+                                           double *vird, float p4v, float q5v) {
     constexpr bool RF = FLAV / 2 == NB_ELEC_RF;
     constexpr bool FSW = FLAV % 2 == NB_VDW_FSWITCH;
     // FP32 partial sums of the batch's C pair energies, added to the FP64 sums once per batch
     // (starting from -0 lets the first addition fold away)
     float eljb = -0.0f, ecb = -0.0f;
+    // VIR: FP32 partial sums of f d_a d_b over the batch's pairs (xx, yy, zz, xy, xz, yz)
+    float vb[6] = {-0.0f, -0.0f, -0.0f, -0.0f, -0.0f, -0.0f};
 #pragma unroll
     for (int k = 0; k < C; ++k) {
         const float dx = xs[k] - j.x;
@@ -181,6 +186,15 @@ __device__ __forceinline__ void pair_block(const nb_fparams &fp, const float4 *t
             }
         }
         if (!EPREC) eljb += elj_p;
+        if (VIR) {
+            const float tx = fs * dx, ty = fs * dy, tz = fs * dz;
+            vb[0] = __builtin_fmaf(tx, dx, vb[0]);
+            vb[1] = __builtin_fmaf(ty, dy, vb[1]);
+            vb[2] = __builtin_fmaf(tz, dz, vb[2]);
+            vb[3] = __builtin_fmaf(tx, dy, vb[3]);
+            vb[4] = __builtin_fmaf(tx, dz, vb[4]);
+            vb[5] = __builtin_fmaf(ty, dz, vb[5]);
+        }
         fix[k] = __builtin_fmaf(fs, dx, fix[k]);
         fiy[k] = __builtin_fmaf(fs, dy, fiy[k]);
         fiz[k] = __builtin_fmaf(fs, dz, fiz[k]);
@@ -191,6 +205,10 @@ __device__ __forceinline__ void pair_block(const nb_fparams &fp, const float4 *t
     if (!EPREC) {
         elj += (double)eljb;
         ec += (double)ecb;
+    }
+    if (VIR) {
+#pragma unroll
+        for (int m = 0; m < 6; ++m) vird[m] += (double)vb[m];
     }
 }
 
@@ -207,13 +225,14 @@ __device__ __forceinline__ float nb_uniform(float v) {
 // Coulomb shift weight (sum of q_i q_j over interacting pairs).
 struct nb_esum {
     double elj, ec, qq;
+    double v[6];  // with VIR: sum over pairs of f d_a d_b (xx, yy, zz, xy, xz, yz), F_ij = f d
 };
 
 // Forces and energy sums of one work unit, computed by one wavefront: the batches
 // [b0, b0 + nbat) of i-cluster ci's j-list (all of them, or one part of a long list).  fp.L
 // holds the box of the cluster.  Both the j-forces and the unit's i-force sums are added
 // atomically to fj (several units may share an i-cluster); the energy sums are returned.
-template <int C, bool EPREC, int FLAV>
+template <int C, bool EPREC, int FLAV, bool VIR>
 __device__ __forceinline__ nb_esum nb_force_cluster(const nb_fparams &fp, const float4 *tab,
                                                  const nb_etab &et, int ci, int b0, int nbat,
                                                  int cap, int npad_max,
@@ -247,6 +266,7 @@ __device__ __forceinline__ nb_esum nb_force_cluster(const nb_fparams &fp, const 
     for (int k = 0; k < C; ++k) fix[k] = fiy[k] = fiz[k] = 0.0f;
     double elj = 0.0, ec = 0.0, qqsd = 0.0;  // qqsd: FP64-energy mode sum of q_i q_j
     float qqs = 0.0f;                        // FP32 mode: sum of fC q_i q_j (shift weight)
+    double vird[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 
     // the leading coefficients of the erfcx numerator and denominator live in vector registers
     // for the whole list: the first Horner step then reads one scalar register, which is all a
@@ -295,9 +315,9 @@ __device__ __forceinline__ nb_esum nb_force_cluster(const nb_fparams &fp, const 
             }
             const bool full = __ballot(!valid || jv.mcol != FULL) == 0ull;
             if (full)
-                pair_block<C, false, EPREC, FLAV>(fp, tab, ntt, et, xs, ys, zs, qi, ti, jv, fix, fiy, fiz, elj, ec, qqs, qqsd, p4v, q5v);
+                pair_block<C, false, EPREC, FLAV, VIR>(fp, tab, ntt, et, xs, ys, zs, qi, ti, jv, fix, fiy, fiz, elj, ec, qqs, qqsd, vird, p4v, q5v);
             else
-                pair_block<C, true, EPREC, FLAV>(fp, tab, ntt, et, xs, ys, zs, qi, ti, jv, fix, fiy, fiz, elj, ec, qqs, qqsd, p4v, q5v);
+                pair_block<C, true, EPREC, FLAV, VIR>(fp, tab, ntt, et, xs, ys, zs, qi, ti, jv, fix, fiy, fiz, elj, ec, qqs, qqsd, vird, p4v, q5v);
         } else {
             // shifts differ across the batch: per-lane frame offsets
             const int tx = nb_tx(s), ty = nb_ty(s), tz = nb_tz(s);
@@ -317,7 +337,7 @@ __device__ __forceinline__ nb_esum nb_force_cluster(const nb_fparams &fp, const 
                 yl[k] = yi[k] + diy;
                 zl[k] = zi[k] + diz;
             }
-            pair_block<C, true, EPREC, FLAV>(fp, tab, ntt, et, xl, yl, zl, qi, ti, jv, fix, fiy, fiz, elj, ec, qqs, qqsd, p4v, q5v);
+            pair_block<C, true, EPREC, FLAV, VIR>(fp, tab, ntt, et, xl, yl, zl, qi, ti, jv, fix, fiy, fiz, elj, ec, qqs, qqsd, vird, p4v, q5v);
         }
         // about 40% of the lanes of a batch have no pair within rc (their entry was kept for
         // another atom of the group, at rlist); they skip their atomics
@@ -354,5 +374,10 @@ __device__ __forceinline__ nb_esum nb_force_cluster(const nb_fparams &fp, const 
         atomicAdd((float *)(fj + npad_max + p), vy);
         atomicAdd((float *)(fj + 2 * npad_max + p), vz);
     }
-    return nb_esum{elj, ec, qqd};
+    nb_esum out{elj, ec, qqd, {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}};
+    if (VIR) {
+#pragma unroll
+        for (int m = 0; m < 6; ++m) out.v[m] = nb_wave_sum_d(vird[m]);
+    }
+    return out;
 }

@@ -142,7 +142,8 @@ struct nb_ctx {
     int4 *units = nullptr;      // [unit_cap] (i-cluster, first batch, batches, energy slot),
                                 // longest first
     double *epart = nullptr;    // [unit_cap * 4] energy partials (one per force workgroup used)
-    double *cpart = nullptr;    // [2 * blocks] Ewald-correction energy partials (NB_EWALD_CORR)
+    double *cpart = nullptr;    // [NB_CORR_PART * blocks] Ewald-correction partials (NB_EWALD_CORR)
+    double *vpart = nullptr;    // [6 * force workgroups] virial pair sums (nb_forces_virial)
     nb_meta *meta = nullptr;
     float4 *ljtab = nullptr;    // [2 * nt * nt]: (C6, C12, 6 C6, 12 C12), (shift, 1/sigma_ab, 0, 0)
     double2 *etab = nullptr;    // [2 * etab_n]: Hermite segments of erfc(beta r) (FP64 energy mode)
@@ -177,12 +178,14 @@ hipError_t nb_launch_debug_pairs(nb_ctx *c, int64_t cap);
 
 // ---- launchers (nb_force.hip) ----
 hipError_t nb_launch_pack(nb_ctx *c, const float *x, const float *q, const int32_t *type);
-hipError_t nb_launch_force(nb_ctx *c);
-hipError_t nb_launch_finalize(nb_ctx *c, float *f, double *e);
+hipError_t nb_launch_force(nb_ctx *c, bool vir);
+hipError_t nb_launch_finalize(nb_ctx *c, float *f, double *e, double *vir);
 hipError_t nb_launch_ewald_corr(nb_ctx *c, const float *x, const float *q);
 
-// Threads per block of the Ewald-correction kernel (one atom each).
+// Threads per block of the Ewald-correction kernel (one atom each), and its partial sums per
+// block: the exclusion-correction and self energies, then six pair sums for the virial.
 #define NB_CORR_BLOCK 256
+#define NB_CORR_PART 8
 
 // ---- launchers (nb_adjoint.hip) ----
 hipError_t nb_launch_adjoint(nb_ctx *c, const float *gf, const double *ge, float *dx, float *dq,

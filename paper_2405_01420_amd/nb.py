@@ -30,7 +30,7 @@ STATUS_NAMES = {0: "NB_OK", 1: "NB_ERR_ARG", 2: "NB_ERR_CUTOFF", 3: "NB_ERR_OOM"
                 8: "NB_ERR_NONFINITE", 9: "NB_ERR_IO"}
 
 EXPORTS = ["nb_validate_params", "nb_setup", "nb_set_lj", "nb_set_stream", "nb_pairlist",
-           "nb_forces", "nb_check", "nb_backward", "nb_debug_pairs", "nb_get_stats",
+           "nb_forces", "nb_forces_virial", "nb_check", "nb_backward", "nb_debug_pairs", "nb_get_stats",
            "nb_last_error", "nb_destroy", "nb_set_timing", "nb_get_timing", "nb_batch_setup",
            "nb_batch_set_schedule", "nb_batch_pairlist", "nb_batch_forces",
            "nb_batch_graph_forces", "nb_batch_get_info", "nb_batch_last_error",
@@ -94,6 +94,7 @@ def lib():
         L.nb_set_stream.argtypes = [_vp, _vp]
         L.nb_pairlist.argtypes = [_vp, _vp]
         L.nb_forces.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
+        L.nb_forces_virial.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp]
         L.nb_check.argtypes = [_vp]
         L.nb_backward.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, cu]
         L.nb_debug_pairs.argtypes = [_vp, _vp, _vp, ci64, P(ci64)]
@@ -207,6 +208,12 @@ def nb_pairlist(ctx: int, x) -> None:
 
 def nb_forces(ctx: int, x, q, types, f, e) -> None:
     _check(lib().nb_forces(ctx, _ptr(x), _ptr(q), _ptr(types), _ptr(f), _ptr(e)), ctx)
+
+
+def nb_forces_virial(ctx: int, x, q, types, f, e, vir) -> None:
+    """nb_forces plus the virial -1/2 sum d (x) F_ij into vir (device float64, 9 values)."""
+    _check(lib().nb_forces_virial(ctx, _ptr(x), _ptr(q), _ptr(types), _ptr(f), _ptr(e), _ptr(vir)),
+           ctx)
 
 
 def nb_check(ctx: int) -> int:
