@@ -216,6 +216,36 @@ __global__ void __launch_bounds__(NB_CORR_BLOCK) k_ewald_corr(int n, int npad_ma
     }
 }
 
+// Sum over the rows [0, nrow) of the first K columns of a row-major table of row stride S, by
+// one block of NB_FIN_BLOCK threads: rows strided over the threads, then the wave and block
+// trees.  Every thread gets the K sums; the order is fixed, so they are reproducible.
+template <int K>
+__device__ __forceinline__ void fin_block_sum(const double *__restrict__ tab, int nrow, int stride,
+                                              double *out, double (*s)[NB_FIN_BLOCK / NB_WAVE]) {
+    double a[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) a[k] = 0.0;
+#pragma unroll 4
+    for (int r = threadIdx.x; r < nrow; r += NB_FIN_BLOCK) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) a[k] += tab[(size_t)stride * r + k];
+    }
+    const int w = threadIdx.x / NB_WAVE;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        a[k] = nb_wave_sum_d(a[k]);
+        if ((threadIdx.x & (NB_WAVE - 1)) == 0) s[k][w] = a[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        double t = 0.0;
+        for (int j = 0; j < NB_FIN_BLOCK / NB_WAVE; ++j) t += s[k][j];
+        out[k] = t;
+    }
+    __syncthreads();  // s is reused by the next call
+}
+
 // f[atom] in original order, and the FP64 energy sums.  Block 0 additionally adds the energy
 // partials of the force workgroups in order (strided per thread, then the wave and block trees)
 // and applies the Coulomb shift; it is dispatched first, so this runs beside the other blocks'
@@ -231,7 +261,7 @@ __global__ void __launch_bounds__(NB_FIN_BLOCK) k_finalize(int n, int npad_max,
                                                            double *__restrict__ e,
                                                            const double *__restrict__ vpart,
                                                            double *__restrict__ vir) {
-    __shared__ double s[3][NB_FIN_BLOCK / NB_WAVE];
+    __shared__ double s[8][NB_FIN_BLOCK / NB_WAVE];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) {
         const int p = slot_of[i];
@@ -240,67 +270,25 @@ __global__ void __launch_bounds__(NB_FIN_BLOCK) k_finalize(int n, int npad_max,
         f[3 * i + 2] = fj[2 * npad_max + p];
     }
     if (blockIdx.x != 0) return;
+    // energies: the force workgroups' partials; then the Ewald-correction and virial partials
     const int np = (meta->nunits + NB_FORCE_WAVES - 1) / NB_FORCE_WAVES;
-    double x = 0.0, y = 0.0, z = 0.0;
-    // several partials per thread and step: their loads are issued together, not one latency
-    // after another
-    constexpr int U = 4;
-    int k = threadIdx.x;
-    for (; k + (U - 1) * NB_FIN_BLOCK < np; k += U * NB_FIN_BLOCK) {
-        double4 v[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) v[u] = *reinterpret_cast<const double4 *>(epart + 4 * (k + u * NB_FIN_BLOCK));
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            x += v[u].x;
-            y += v[u].y;
-            z += v[u].z;
-        }
-    }
-    for (; k < np; k += NB_FIN_BLOCK) {
-        x += epart[4 * k];
-        y += epart[4 * k + 1];
-        z += epart[4 * k + 2];
-    }
-    x = nb_wave_sum_d(x);
-    y = nb_wave_sum_d(y);
-    z = nb_wave_sum_d(z);
-    const int w = threadIdx.x / NB_WAVE;
-    if ((threadIdx.x & (NB_WAVE - 1)) == 0) {
-        s[0][w] = x;
-        s[1][w] = y;
-        s[2][w] = z;
-    }
-    __syncthreads();
+    double en[3];
+    fin_block_sum<3>(epart, np, 4, en, s);
+    double cp[NB_CORR_PART] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (ncpart > 0) fin_block_sum<NB_CORR_PART>(cpart, ncpart, NB_CORR_PART, cp, s);
+    double vp[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (vir) fin_block_sum<6>(vpart, np, 6, vp, s);
     if (threadIdx.x == 0) {
-        double tx = 0.0, ty = 0.0, tz = 0.0;
-        for (int k = 0; k < NB_FIN_BLOCK / NB_WAVE; ++k) {
-            tx += s[0][k];
-            ty += s[1][k];
-            tz += s[2][k];
-        }
-        e[0] = tx;
-        e[1] = coul_scale * (ty - shift_coul * tz);
-        // Ewald corrections: a few hundred block sums, in block order
-        double vc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        e[0] = en[0];
+        e[1] = coul_scale * (en[1] - shift_coul * en[2]);
         if (ncpart > 0) {
-            double a = 0.0, b = 0.0;
-            for (int k = 0; k < ncpart; ++k) {
-                a += cpart[NB_CORR_PART * k];
-                b += cpart[NB_CORR_PART * k + 1];
-                for (int m = 0; m < 6; ++m) vc[m] += cpart[NB_CORR_PART * k + 2 + m];
-            }
-            e[2] = a;
-            e[3] = b;
+            e[2] = cp[0];
+            e[3] = cp[1];
         }
         if (vir) {
-            // Xi = -1/2 sum over pairs of d (x) F_ij, F_ij = f d: the force workgroups' sums in
-            // order, then the exclusion correction's
-            const int np = (meta->nunits + NB_FORCE_WAVES - 1) / NB_FORCE_WAVES;
-            double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-            for (int k = 0; k < np; ++k)
-                for (int m = 0; m < 6; ++m) v[m] += vpart[6 * k + m];
-            for (int m = 0; m < 6; ++m) v[m] = -0.5 * (v[m] + vc[m]);
+            // Xi = -1/2 sum over pairs of d (x) F_ij with F_ij = f d (xx, yy, zz, xy, xz, yz)
+            double v[6];
+            for (int m = 0; m < 6; ++m) v[m] = -0.5 * (vp[m] + cp[2 + m]);
             vir[0] = v[0];
             vir[4] = v[1];
             vir[8] = v[2];
