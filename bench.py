@@ -56,9 +56,9 @@ REBUILD_EVERY = 10
 # this digest and are reported only while the sources are unchanged.
 K_FORCE_COUNTERS = {
     "sources": ["nb_force_body.h", "nb_force.hip", "nb_device.h", "nb_internal.h", "erfcx_rational.h"],
-    "sha256": "4086f01c464bd0c592a88ebf5bb40cea90fd453fb074f73d95d7ec4bc4bdb260",
-    "read_bytes": 32.84e6, "write_bytes": 83.65e6,
-    "counted_fp32_flop": 72748284.4 * 64,
+    "sha256": "3af4860a32a92a2be3cf8e6c9a256856a4c7a2e96a77313fdee25fcc7e093081",
+    "read_bytes": 32.84e6, "write_bytes": 83.36e6,
+    "counted_fp32_flop": 72748986.6 * 64,
 }
 
 
