@@ -54,7 +54,9 @@ typedef enum nb_status {
                               when nb_pairlist can grow the buffer) */
     NB_ERR_LIST_STALE = 7, /* an atom moved more than buffer/2 since the list was built */
     NB_ERR_NONFINITE = 8,  /* non-finite coordinate seen with NB_CHECK_FINITE */
-    NB_ERR_IO = 9          /* autotune cache could not be read or written */
+    NB_ERR_IO = 9,         /* autotune cache could not be read or written */
+    NB_ERR_RANGE = 10      /* a pair force component exceeded 131072 kJ/mol/nm: the forces'
+                              fixed-point accumulators hold net components up to 524288 */
 } nb_status;
 
 /* flags (nb_params.flags and per-call flags) */
@@ -165,6 +167,10 @@ int nb_pairlist(nb_ctx *ctx, const float *x_dev);
 /* Forces and energies for device inputs x [natoms][3], q [natoms], type [natoms] (0-based
  * LJ type).  x must be the build positions or a continuous motion of them (no re-wrapping
  * since the build); pairs stay exact while every atom moved less than buffer/2.
+ * The forces are summed in fixed point (2^-12 kJ mol^-1 nm^-1 units, integer atomics), so
+ * they do not depend on the order in which the device adds the pair contributions; a pair
+ * contribution above 131072 in any component is reported by nb_check as NB_ERR_RANGE (the
+ * accumulators hold net components up to 524288 kJ mol^-1 nm^-1 per atom).
  * Outputs: f_dev [natoms][3] overwritten in original order; e_dev[0] = E_LJ, e_dev[1] = E_C
  * (device doubles; with NB_EWALD_CORR also e_dev[2] = Ewald exclusion correction, e_dev[3] =
  * self term, and f includes the exclusion-correction forces).  No allocation and no host
@@ -184,7 +190,7 @@ int nb_forces_virial(nb_ctx *ctx, const float *x_dev, const float *q_dev, const 
                      float *f_dev, double *e_dev, double *vir_dev);
 
 /* Synchronise the stream and report device-side conditions recorded since the last check:
- * NB_ERR_LIST_STALE, NB_ERR_NONFINITE, NB_ERR_OVERFLOW; clears them. */
+ * NB_ERR_LIST_STALE, NB_ERR_NONFINITE, NB_ERR_OVERFLOW, NB_ERR_RANGE; clears them. */
 int nb_check(nb_ctx *ctx);
 
 /* Vector-Jacobian product of (F, E_LJ, E_C) for a force-matching loss.

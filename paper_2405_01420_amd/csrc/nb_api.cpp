@@ -571,6 +571,9 @@ int nb_check(nb_ctx *c) {
     if (m.flags & (NB_F_OVERFLOW | NB_F_COLUMN)) return fail(c, NB_ERR_OVERFLOW, "pair list overflow");
     if (m.flags & NB_F_NONFINITE) return fail(c, NB_ERR_NONFINITE, "non-finite coordinates");
     if (m.flags & NB_F_STALE) return fail(c, NB_ERR_LIST_STALE, "an atom moved more than buffer/2 since the list was built");
+    if (m.flags & NB_F_RANGE)
+        return fail(c, NB_ERR_RANGE, "a pair force component exceeded 131072 kJ/mol/nm (or was not finite): "
+                                     "net force components beyond 524288 would not be represented");
     return NB_OK;
 }
 

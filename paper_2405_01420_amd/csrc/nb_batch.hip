@@ -136,9 +136,9 @@ __global__ void __launch_bounds__(256) NB_FORCE_OCCUPANCY k_batch_force(nb_fpara
             f.L[1] = d.L[1];
             f.L[2] = d.L[2];
             // the descriptor's pointers are global memory; typed so, their accesses are global
-            const nb_esum es = nb_force_cluster<C, EPREC, FLAV, false>(
+            const nb_esum es = nb_force_cluster<C, EPREC, FLAV, false, false>(
                 f, tab, et, ci, 0, 1 << 20, d.cap, d.npad_max, nb_g(d.xq), nb_g(d.tsort),
-                nb_g(d.icount), nb_g(d.jl), nb_g(d.fj));
+                nb_g(d.icount), nb_g(d.jl), nb_g(d.fj), nullptr);
             if (lane == 0) {
                 NB_G double *ep = nb_g(d.epart) + 4 * ci;
                 nb_st(ep, es.elj);

@@ -74,7 +74,7 @@ __global__ void __launch_bounds__(NB_FORCE_WAVES * NB_WAVE) NB_FORCE_OCCUPANCY_V
                                                const nb_entry *__restrict__ jl,
                                                const int4 *__restrict__ units, float *__restrict__ fj,
                                                double *__restrict__ epart, double *__restrict__ vpart,
-                                               const nb_meta *meta) {
+                                               nb_meta *meta) {
     extern __shared__ float4 tab[];
     __shared__ double esh[NB_FORCE_WAVES][VIR ? 9 : 3];
     __shared__ int edone;
@@ -97,10 +97,10 @@ __global__ void __launch_bounds__(NB_FORCE_WAVES * NB_WAVE) NB_FORCE_OCCUPANCY_V
     nb_esum es{0.0, 0.0, 0.0, {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}};
     if (u < nunits) {
         const int4 w = units[u];
-        es = nb_force_cluster<C, EPREC, FLAV, VIR>(fp, tab, et, __builtin_amdgcn_readfirstlane(w.x),
+        es = nb_force_cluster<C, EPREC, FLAV, VIR, true>(fp, tab, et, __builtin_amdgcn_readfirstlane(w.x),
                                               __builtin_amdgcn_readfirstlane(w.y),
                                               __builtin_amdgcn_readfirstlane(w.z), cap, npad_max,
-                                              nb_g(xq), nb_g(tsort), nb_g(icount), nb_g(jl), nb_g(fj));
+                                              nb_g(xq), nb_g(tsort), nb_g(icount), nb_g(jl), nb_g(fj), nb_g(&meta->flags));
     }
     int last = 0;
     if (lane == 0) {
@@ -193,9 +193,9 @@ __global__ void __launch_bounds__(NB_CORR_BLOCK) k_ewald_corr(int n, int npad_ma
                 }
             }
             const int p = slot_of[i];
-            fj[p] += (float)fx;
-            fj[npad_max + p] += (float)fy;
-            fj[2 * npad_max + p] += (float)fz;
+            // fixed-point accumulators (the force kernel's layout); this thread owns the slot
+            reinterpret_cast<unsigned long long *>(fj)[p] += nb_fix_xy((float)fx, (float)fy);
+            reinterpret_cast<int *>(fj + 2 * npad_max)[p] += nb_fix((float)fz);
         }
     }
     ex = nb_wave_sum_d(ex);
@@ -265,9 +265,14 @@ __global__ void __launch_bounds__(NB_FIN_BLOCK) k_finalize(int n, int npad_max,
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) {
         const int p = slot_of[i];
-        f[3 * i] = fj[p];
-        f[3 * i + 1] = fj[npad_max + p];
-        f[3 * i + 2] = fj[2 * npad_max + p];
+        // fixed-point sums: x in the low 32 bits of the xy word, y above it, z on its own
+        const unsigned long long w = reinterpret_cast<const unsigned long long *>(fj)[p];
+        const int ix = (int)(unsigned)w;
+        const int iy = (int)((w - (unsigned long long)(long long)ix) >> 32);
+        const int iz = reinterpret_cast<const int *>(fj + 2 * npad_max)[p];
+        f[3 * i] = (float)ix * (1.0f / NB_FSCALE);
+        f[3 * i + 1] = (float)iy * (1.0f / NB_FSCALE);
+        f[3 * i + 2] = (float)iz * (1.0f / NB_FSCALE);
     }
     if (blockIdx.x != 0) return;
     // energies: the force workgroups' partials; then the Ewald-correction and virial partials

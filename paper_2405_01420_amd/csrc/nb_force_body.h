@@ -221,6 +221,38 @@ __device__ __forceinline__ float nb_uniform(float v) {
     return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
 }
 
+// Fixed-point value of a force component (round to nearest; clamped so that the conversion is
+// defined; values that large are flagged by the range check anyway).
+__device__ __forceinline__ int nb_fix(float f) {
+    return (int)__builtin_rintf(fminf(fmaxf(f * NB_FSCALE, -2147483520.0f), 2147483520.0f));
+}
+
+// x and y of one contribution as the 64-bit word x + 2^32 y (sums modulo 2^64 keep both).
+__device__ __forceinline__ unsigned long long nb_fix_xy(float x, float y) {
+    return (unsigned long long)(long long)nb_fix(x) + ((unsigned long long)(unsigned)nb_fix(y) << 32);
+}
+
+// Adds one atom's force contribution (lane-wise, where `on`) to the fixed-point accumulators
+// fxy / fz, or to the FP32 ones (fj[3][npad_max]); the fixed-point form also raises the range
+// flag if any active lane's component exceeds NB_FRANGE (or is not finite).
+template <bool FIX>
+__device__ __forceinline__ void nb_add_force(bool on, int slot, float fx, float fy, float fz,
+                                             NB_G float *fj, int npad_max, NB_G unsigned *flags,
+                                             int lane) {
+    if (FIX) {
+        const float m = fmaxf(fmaxf(fabsf(fx), fabsf(fy)), fabsf(fz));
+        if (__ballot(on && !(m < NB_FRANGE)) != 0ull && lane == 0) atomicOr((unsigned *)flags, NB_F_RANGE);
+        if (on) {
+            atomicAdd((unsigned long long *)fj + slot, nb_fix_xy(fx, fy));
+            atomicAdd((int *)(fj + 2 * npad_max) + slot, nb_fix(fz));
+        }
+    } else if (on) {
+        atomicAdd((float *)(fj + slot), fx);
+        atomicAdd((float *)(fj + npad_max + slot), fy);
+        atomicAdd((float *)(fj + 2 * npad_max + slot), fz);
+    }
+}
+
 // Energy sums of one work unit (every lane holds them): E_LJ, the Coulomb pair sum and the
 // Coulomb shift weight (sum of q_i q_j over interacting pairs).
 struct nb_esum {
@@ -231,8 +263,9 @@ struct nb_esum {
 // Forces and energy sums of one work unit, computed by one wavefront: the batches
 // [b0, b0 + nbat) of i-cluster ci's j-list (all of them, or one part of a long list).  fp.L
 // holds the box of the cluster.  Both the j-forces and the unit's i-force sums are added
-// atomically to fj (several units may share an i-cluster); the energy sums are returned.
-template <int C, bool EPREC, int FLAV, bool VIR>
+// atomically to fj (several units may share an i-cluster), in fixed point with FIX (the layout
+// of nb_add_force), in FP32 otherwise; the energy sums are returned.
+template <int C, bool EPREC, int FLAV, bool VIR, bool FIX>
 __device__ __forceinline__ nb_esum nb_force_cluster(const nb_fparams &fp, const float4 *tab,
                                                  const nb_etab &et, int ci, int b0, int nbat,
                                                  int cap, int npad_max,
@@ -240,7 +273,8 @@ __device__ __forceinline__ nb_esum nb_force_cluster(const nb_fparams &fp, const 
                                                  const NB_G int *__restrict__ tsort,
                                                  const NB_G int *__restrict__ icount,
                                                  const NB_G nb_entry *__restrict__ jl,
-                                                 NB_G float *__restrict__ fj) {
+                                                 NB_G float *__restrict__ fj,
+                                                 NB_G unsigned *__restrict__ flags) {
     constexpr unsigned FULL = (1u << C) - 1u;
     const int nt = fp.ntypes, ntt = nt * nt;
     const int lane = threadIdx.x & (NB_WAVE - 1);
@@ -341,11 +375,8 @@ __device__ __forceinline__ nb_esum nb_force_cluster(const nb_fparams &fp, const 
         }
         // about 40% of the lanes of a batch have no pair within rc (their entry was kept for
         // another atom of the group, at rlist); they skip their atomics
-        if (valid && (jv.fx != 0.0f || jv.fy != 0.0f || jv.fz != 0.0f)) {
-            atomicAdd((float *)(fj + jslot), jv.fx);
-            atomicAdd((float *)(fj + npad_max + jslot), jv.fy);
-            atomicAdd((float *)(fj + 2 * npad_max + jslot), jv.fz);
-        }
+        nb_add_force<FIX>(valid && (jv.fx != 0.0f || jv.fy != 0.0f || jv.fz != 0.0f), jslot, jv.fx,
+                          jv.fy, jv.fz, fj, npad_max, flags, lane);
     }
 #pragma unroll
     for (int k = 0; k < C; ++k) {
@@ -368,12 +399,7 @@ __device__ __forceinline__ nb_esum nb_force_cluster(const nb_fparams &fp, const 
         vy = lane == k ? sy : vy;
         vz = lane == k ? sz : vz;
     }
-    if (lane < C) {
-        const int p = ci * C + lane;
-        atomicAdd((float *)(fj + p), vx);
-        atomicAdd((float *)(fj + npad_max + p), vy);
-        atomicAdd((float *)(fj + 2 * npad_max + p), vz);
-    }
+    nb_add_force<FIX>(lane < C, ci * C + lane, vx, vy, vz, fj, npad_max, flags, lane);
     nb_esum out{elj, ec, qqd, {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}};
     if (VIR) {
 #pragma unroll

@@ -19,6 +19,19 @@
 #define NB_F_STALE 0x2u
 #define NB_F_NONFINITE 0x4u
 #define NB_F_COLUMN 0x8u
+#define NB_F_RANGE 0x10u  // a pair force component beyond the fixed-point accumulators' check
+
+// Fixed-point force accumulation of the single-box path: a component f is added as the 32-bit
+// integer rint(f * NB_FSCALE); x and y of an atom share one 64-bit word (x + 2^32 y, added
+// modulo 2^64, which is exact for the two 32-bit sums as long as each stays within 32 bits),
+// z is a 32-bit word.  Integer sums do not depend on the order of the atomics.  Net components
+// up to 2^31 / NB_FSCALE = 524288 kJ mol^-1 nm^-1 per atom are represented; a contribution
+// above NB_FRANGE (a quarter of that) in any component raises NB_F_RANGE.  (Stiff
+// Lennard-Jones types at liquid density give single contributions above 3e4.)  The unit,
+// 2^-12, adds a rounding error of about 7e-5 per contribution, ~6e-4 per atom component for
+// the ~80 contributions an atom receives at 96k atoms: 1e-6 of typical water forces.
+#define NB_FSCALE 4096.0f
+#define NB_FRANGE 131072.0f
 
 // One j-entry of the cluster-pair list.  The j side of every entry is a group of NB_JG = 4
 // consecutive slots: a whole cluster when C = 4, one half (lower or upper four in z order) of

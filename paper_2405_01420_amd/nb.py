@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(PKG, "libnb.so")
 
 NB_OK, NB_ERR_ARG, NB_ERR_CUTOFF, NB_ERR_OOM, NB_ERR_HIP = 0, 1, 2, 3, 4
 NB_ERR_STATE, NB_ERR_OVERFLOW, NB_ERR_LIST_STALE, NB_ERR_NONFINITE, NB_ERR_IO = 5, 6, 7, 8, 9
+NB_ERR_RANGE = 10
 NB_CHECK_STALE, NB_CHECK_FINITE, NB_REUSE_LIST, NB_ASYNC_BUILD = 0x1, 0x2, 0x4, 0x8
 NB_ENERGY_FP64 = 0x10
 NB_EWALD_CORR = 0x20
@@ -27,7 +28,7 @@ NB_VDW_SHIFT, NB_VDW_FSWITCH = 0, 1
 
 STATUS_NAMES = {0: "NB_OK", 1: "NB_ERR_ARG", 2: "NB_ERR_CUTOFF", 3: "NB_ERR_OOM", 4: "NB_ERR_HIP",
                 5: "NB_ERR_STATE", 6: "NB_ERR_OVERFLOW", 7: "NB_ERR_LIST_STALE",
-                8: "NB_ERR_NONFINITE", 9: "NB_ERR_IO"}
+                8: "NB_ERR_NONFINITE", 9: "NB_ERR_IO", 10: "NB_ERR_RANGE"}
 
 EXPORTS = ["nb_validate_params", "nb_setup", "nb_set_lj", "nb_set_stream", "nb_pairlist",
            "nb_forces", "nb_forces_virial", "nb_check", "nb_backward", "nb_debug_pairs", "nb_get_stats",

@@ -66,7 +66,10 @@ def test_batch_matches_single_box_path(torch_gpu, boxes):
         box.pairlist()
         fs, es = box.forces()
         box.close()
-        assert rel_rms(fa[ao[k]:ao[k + 1]], fs) <= 1e-6
+        # the single-box path sums forces in fixed point (2^-12 kJ/mol/nm units, ~1e-6
+        # relative quantisation at these sizes), the batched one in FP32: they agree to the
+        # force gate, which each also meets against the oracle
+        assert rel_rms(fa[ao[k]:ao[k + 1]], fs) <= FORCE_TOL
         # the same pair terms summed in another grouping (the plain path may split a list
         # over several waves): equal up to the FP32 partial sums, far below the 1e-6 gate
         assert np.all(np.abs(ea[k] - es) <= 1e-7 * np.abs(es))

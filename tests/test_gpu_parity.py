@@ -230,3 +230,33 @@ def test_energies_do_not_depend_on_scheduling(torch_gpu, inst_diff):
         _, e2 = box.forces()
         assert np.array_equal(e1, e2)
     box.close()
+
+
+def test_forces_do_not_depend_on_scheduling(torch_gpu, inst_diff):
+    """The forces are summed in fixed point with integer atomics: repeated calls give
+    bit-identical forces, whatever order the device added the pair contributions in."""
+    box = GpuBox(torch_gpu, inst_diff)
+    box.pairlist()
+    f1, _ = box.forces()
+    for _ in range(5):
+        f2, _ = box.forces()
+        assert np.array_equal(f1, f2)
+    box.close()
+
+
+def test_force_beyond_the_fixed_point_range_is_reported(torch_gpu, inst_tiny):
+    """Two oxygens 0.1 nm apart (a Lennard-Jones force of order 1e7 kJ/mol/nm) raise the range
+    flag, which nb_check reports once and clears."""
+    box = GpuBox(torch_gpu, inst_tiny, flags=nb.NB_ENERGY_FP64)
+    x = inst_tiny.x.copy()
+    x[0] = x[3] + np.array([0.1, 0.0, 0.0], np.float32)  # O of molecule 0 next to O of molecule 1
+    box.set_x(x)
+    box.pairlist()
+    box.forces()
+    assert nb.nb_check(box.ctx) == nb.NB_ERR_RANGE
+    assert nb.nb_check(box.ctx) == nb.NB_OK
+    box.set_x(inst_tiny.x)
+    box.pairlist()
+    box.forces()
+    assert nb.nb_check(box.ctx) == nb.NB_OK
+    box.close()
