@@ -286,6 +286,9 @@ int nb_batch_graph_forces(nb_batch *bt, const float *x, const float *q, const in
                           float *f, double *e);
 
 int nb_batch_get_info(nb_batch *bt, nb_batch_info *info);
+/* Synchronise the batch stream and report NB_ERR_RANGE if a pair force component exceeded the
+ * fixed-point accumulators' check (as for nb_forces) since the last call; clears it. */
+int nb_batch_check(nb_batch *bt);
 const char *nb_batch_last_error(nb_batch *bt);
 int nb_batch_destroy(nb_batch *bt);
 

@@ -102,7 +102,8 @@ __global__ void __launch_bounds__(256) NB_FORCE_OCCUPANCY k_batch_force(nb_fpara
                                                      const int *__restrict__ chunks, int nchunks,
                                                      const float4 *__restrict__ ljtab,
                                                      const double2 *__restrict__ etab, int etab_n,
-                                                     float etab_invh, unsigned *counter) {
+                                                     float etab_invh, unsigned *counter,
+                                                     unsigned *flags) {
     extern __shared__ float4 tab[];
     const int ntt = fp.ntypes * fp.ntypes;
     for (int k = threadIdx.x; k < 2 * ntt; k += blockDim.x) tab[k] = ljtab[k];
@@ -136,9 +137,9 @@ __global__ void __launch_bounds__(256) NB_FORCE_OCCUPANCY k_batch_force(nb_fpara
             f.L[1] = d.L[1];
             f.L[2] = d.L[2];
             // the descriptor's pointers are global memory; typed so, their accesses are global
-            const nb_esum es = nb_force_cluster<C, EPREC, FLAV, false, false>(
+            const nb_esum es = nb_force_cluster<C, EPREC, FLAV, false, true>(
                 f, tab, et, ci, 0, 1 << 20, d.cap, d.npad_max, nb_g(d.xq), nb_g(d.tsort),
-                nb_g(d.icount), nb_g(d.jl), nb_g(d.fj), nullptr);
+                nb_g(d.icount), nb_g(d.jl), nb_g(d.fj), nb_g(flags));
             if (lane == 0) {
                 NB_G double *ep = nb_g(d.epart) + 4 * ci;
                 nb_st(ep, es.elj);
@@ -155,9 +156,14 @@ __global__ void k_batch_finalize(const nb_box_desc *__restrict__ desc, float *__
     if (i >= d.natoms) return;
     const int p = d.slot_of[i];
     const int g = d.atom_off + i;
-    f[3 * g] = d.fj[p];
-    f[3 * g + 1] = d.fj[d.npad_max + p];
-    f[3 * g + 2] = d.fj[2 * d.npad_max + p];
+    // fixed-point sums (the force body's layout): x in the low 32 bits of the xy word, y above
+    const unsigned long long w = reinterpret_cast<const unsigned long long *>(d.fj)[p];
+    const int ix = (int)(unsigned)w;
+    const int iy = (int)((w - (unsigned long long)(long long)ix) >> 32);
+    const int iz = reinterpret_cast<const int *>(d.fj + 2 * d.npad_max)[p];
+    f[3 * g] = (float)ix * (1.0f / NB_FSCALE);
+    f[3 * g + 1] = (float)iy * (1.0f / NB_FSCALE);
+    f[3 * g + 2] = (float)iz * (1.0f / NB_FSCALE);
 }
 
 __global__ void __launch_bounds__(256) k_batch_energy(const nb_box_desc *__restrict__ desc,
@@ -261,7 +267,8 @@ template <int C, bool EPREC, int FLAV>
 void launch_batch_t(nb_batch *bt, int s) {
     hipLaunchKernelGGL((k_batch_force<C, EPREC, FLAV>), dim3(bt->grid[s]), dim3(256), batch_shm(bt),
                        bt->stream, bt->fp, bt->d_desc, bt->d_items[s], bt->d_chunks[s], bt->nchunks[s],
-                       bt->ljtab, bt->etab, bt->etab_n, bt->etab_invh, bt->d_counter + s);
+                       bt->ljtab, bt->etab, bt->etab_n, bt->etab_invh, bt->d_counter + s,
+                       bt->d_counter + 2);
 }
 
 template <int C>
@@ -371,7 +378,9 @@ int nb_batch_setup(nb_batch **out, int32_t nbox, const int32_t *atom_off, const 
     bt->etab_invh = bt->box[0]->etab_invh;
     bt->fc = bt->box[0]->fc;
     hipError_t e = hipMalloc((void **)&bt->d_desc, sizeof(nb_box_desc) * nbox);
-    if (e == hipSuccess) e = hipMalloc((void **)&bt->d_counter, sizeof(unsigned) * 2);
+    // two queue heads (reset by the pack kernel of every call) and the force range flag
+    if (e == hipSuccess) e = hipMalloc((void **)&bt->d_counter, sizeof(unsigned) * 3);
+    if (e == hipSuccess) e = hipMemset(bt->d_counter, 0, sizeof(unsigned) * 3);
     for (int s = 0; s < 2 && e == hipSuccess; ++s) {
         bt->item_cap[s] = (int)std::max<int64_t>(items_max[s], 1);
         e = hipMalloc((void **)&bt->d_items[s], sizeof(int2) * bt->item_cap[s]);
@@ -563,6 +572,23 @@ int nb_batch_get_info(nb_batch *bt, nb_batch_info *info) {
     info->grid_blocks[1] = bt->grid[1];
     info->graph_ready = bt->graph_ready;
     info->build_ms_last = bt->build_ms;
+    return NB_OK;
+}
+
+int nb_batch_check(nb_batch *bt) {
+    if (!bt) return bfail(bt, NB_ERR_ARG, "NULL argument");
+    hipSetDevice(bt->device);
+    unsigned flag = 0u;
+    hipError_t e = hipMemcpyAsync(&flag, bt->d_counter + 2, sizeof(unsigned), hipMemcpyDeviceToHost, bt->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(bt->stream);
+    if (e != hipSuccess) return bfail(bt, NB_ERR_HIP, std::string("read batch status: ") + hipGetErrorString(e));
+    if (flag & NB_F_RANGE) {
+        const unsigned zero = 0u;
+        e = hipMemcpy(bt->d_counter + 2, &zero, sizeof(unsigned), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return bfail(bt, NB_ERR_HIP, std::string("clear batch status: ") + hipGetErrorString(e));
+        return bfail(bt, NB_ERR_RANGE, "a pair force component exceeded 131072 kJ/mol/nm (or was not finite): "
+                                       "net force components beyond 524288 would not be represented");
+    }
     return NB_OK;
 }
 

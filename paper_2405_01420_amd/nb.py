@@ -34,7 +34,7 @@ EXPORTS = ["nb_validate_params", "nb_setup", "nb_set_lj", "nb_set_stream", "nb_p
            "nb_forces", "nb_forces_virial", "nb_check", "nb_backward", "nb_debug_pairs", "nb_get_stats",
            "nb_last_error", "nb_destroy", "nb_set_timing", "nb_get_timing", "nb_batch_setup",
            "nb_batch_set_schedule", "nb_batch_pairlist", "nb_batch_forces",
-           "nb_batch_graph_forces", "nb_batch_get_info", "nb_batch_last_error",
+           "nb_batch_graph_forces", "nb_batch_get_info", "nb_batch_check", "nb_batch_last_error",
            "nb_batch_destroy"]
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -110,6 +110,7 @@ def lib():
         L.nb_batch_forces.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
         L.nb_batch_graph_forces.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
         L.nb_batch_get_info.argtypes = [_vp, P(nb_batch_info)]
+        L.nb_batch_check.argtypes = [_vp]
         L.nb_batch_last_error.argtypes = [_vp]
         L.nb_batch_last_error.restype = ctypes.c_char_p
         L.nb_batch_destroy.argtypes = [_vp]
@@ -300,6 +301,11 @@ def nb_batch_forces(bt: int, x, q, types, f, e) -> None:
 
 def nb_batch_graph_forces(bt: int, x, q, types, f, e) -> None:
     _bcheck(lib().nb_batch_graph_forces(bt, _ptr(x), _ptr(q), _ptr(types), _ptr(f), _ptr(e)), bt)
+
+
+def nb_batch_check(bt: int) -> int:
+    """Status of the batch's device-side checks (0 = none raised); clears them."""
+    return int(lib().nb_batch_check(bt))
 
 
 def nb_batch_get_info(bt: int) -> dict:

@@ -1,8 +1,9 @@
 """Batched form: independent boxes of uneven size in one persistent launch per cluster shape,
 also replayed from a HIP graph.  Checked per box against the FP64 oracle (forces RMS relative
 <= 5e-6, energies relative <= 1e-6, with FP64 pair energies since the boxes hold 3,000-30,000
-atoms) and against the single-box path (same list algorithm, so the two agree to FP32
-summation-order differences)."""
+atoms) and against the single-box path (same list algorithm; both sum forces in fixed point,
+but the single-box path may split a long list over several waves, so the rounded contributions
+differ)."""
 import numpy as np
 import pytest
 
@@ -42,6 +43,7 @@ def test_batch_matches_oracle_per_box(torch_gpu, boxes, clusters):
     ea = e.cpu().numpy().reshape(-1, 2)
     info = nb.nb_batch_get_info(bt)
     print("batch info", info)
+    assert nb.nb_batch_check(bt) == nb.NB_OK
     nb.nb_batch_destroy(bt)
     for k, inst in enumerate(boxes):
         ref = O.instance_forces(inst, cells=True)
@@ -66,9 +68,10 @@ def test_batch_matches_single_box_path(torch_gpu, boxes):
         box.pairlist()
         fs, es = box.forces()
         box.close()
-        # the single-box path sums forces in fixed point (2^-12 kJ/mol/nm units, ~1e-6
-        # relative quantisation at these sizes), the batched one in FP32: they agree to the
-        # force gate, which each also meets against the oracle
+        # both paths sum forces in fixed point (2^-12 kJ/mol/nm units, ~1e-6 relative
+        # quantisation at these sizes), but over differently split lists, so the rounded
+        # contributions differ: they agree to the force gate, which each also meets against
+        # the oracle
         assert rel_rms(fa[ao[k]:ao[k + 1]], fs) <= FORCE_TOL
         # the same pair terms summed in another grouping (the plain path may split a list
         # over several waves): equal up to the FP32 partial sums, far below the 1e-6 gate
@@ -99,3 +102,17 @@ def test_graph_replays_match_eager(torch_gpu, boxes):
             stream.synchronize()
         assert nb.nb_batch_get_info(bt)["graph_ready"] == 1
         nb.nb_batch_destroy(bt)
+
+
+def test_batch_reports_force_beyond_the_fixed_point_range(torch_gpu):
+    """Two oxygens 0.1 nm apart in one box of a batch raise the range flag, which
+    nb_batch_check reports once and clears."""
+    torch = torch_gpu
+    insts = synth.batch(2, sizes=[3000, 4503])
+    x0 = insts[0].x
+    x0[0] = x0[3] + np.array([0.1, 0.0, 0.0], np.float32)
+    bt, ao, dx, dq, dt, f, e = run_batch(torch, insts, [8, 8])
+    nb.nb_batch_forces(bt, dx, dq, dt, f, e)
+    assert nb.nb_batch_check(bt) == nb.NB_ERR_RANGE
+    assert nb.nb_batch_check(bt) == nb.NB_OK
+    nb.nb_batch_destroy(bt)
