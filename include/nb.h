@@ -292,6 +292,45 @@ int nb_batch_check(nb_batch *bt);
 const char *nb_batch_last_error(nb_batch *bt);
 int nb_batch_destroy(nb_batch *bt);
 
+/* ---- Reciprocal-space Ewald: smooth particle-mesh Ewald (PME) ---------------------------
+ * The part that completes the real-space Ewald forces of nb_forces when a run uses PME (the
+ * paper's production runs; section II-C and the PME kernels of Fig. 2), with the same beta:
+ * together with NB_EWALD_CORR (exclusion correction and self term) it gives the full Ewald
+ * electrostatics.  Charges are spread onto a K1 x K2 x K3 grid with cardinal B-splines of order
+ * n, the grid is convolved with the Ewald kernel by FFT (hipFFT, FP64), and the forces are
+ * gathered with the B-spline derivatives:
+ *   E_rec = 1/2 sum_m G(m) |FFT(Q)(m)|^2,
+ *   G(m) = fC / (pi V) exp(-pi^2 |m|^2 / beta^2) / |m|^2 |b1(m1) b2(m2) b3(m3)|^2, G(0) = 0,
+ * an approximation of the Ewald reciprocal sum that converges to it as the grid is refined. */
+typedef struct nb_pme nb_pme;
+
+typedef struct nb_pme_params {
+    double box[3];          /* rectangular box edges Lx, Ly, Lz (nm), > 0 */
+    double ewald_beta;      /* Ewald splitting parameter beta (nm^-1), > 0 */
+    double coulomb_const;   /* fC (kJ mol^-1 nm e^-2), > 0 */
+    int32_t grid[3];        /* K1, K2, K3: grid points per axis, 2 * order .. 1024 */
+    int32_t order;          /* B-spline order n: 4, 6 or 8 */
+    int32_t natoms;         /* 1 .. 2^27 */
+} nb_pme_params;
+
+/* Create a PME context on the current device: device grids, the influence function (computed
+ * in FP64 on the host) and two hipFFT plans bound to hip_stream.
+ * Errors: NB_ERR_ARG (invalid parameters), NB_ERR_OOM, NB_ERR_HIP. */
+int nb_pme_setup(nb_pme **out, const nb_pme_params *p, void *hip_stream);
+
+/* Reciprocal-space forces and energy of the device arrays x [natoms][3] (any periodic images)
+ * and q [natoms]: f_dev [natoms][3] overwritten with the reciprocal forces (FP32, original
+ * order; add them to nb_forces' output), e_dev[0] = E_rec (device double).  The system should
+ * be neutral (a net charge adds no energy here).  Asynchronous on the context's stream; no
+ * allocation.  Errors: NB_ERR_ARG, NB_ERR_HIP. */
+int nb_pme_forces(nb_pme *pme, const float *x_dev, const float *q_dev, float *f_dev, double *e_dev);
+
+/* Message of the last error of this context (or of the last failed nb_pme_setup for NULL). */
+const char *nb_pme_last_error(nb_pme *pme);
+
+/* Synchronise the stream and free the context. */
+int nb_pme_destroy(nb_pme *pme);
+
 #ifdef __cplusplus
 }
 #endif

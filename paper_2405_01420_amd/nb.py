@@ -35,7 +35,7 @@ EXPORTS = ["nb_validate_params", "nb_setup", "nb_set_lj", "nb_set_stream", "nb_p
            "nb_last_error", "nb_destroy", "nb_set_timing", "nb_get_timing", "nb_batch_setup",
            "nb_batch_set_schedule", "nb_batch_pairlist", "nb_batch_forces",
            "nb_batch_graph_forces", "nb_batch_get_info", "nb_batch_check", "nb_batch_last_error",
-           "nb_batch_destroy"]
+           "nb_batch_destroy", "nb_pme_setup", "nb_pme_forces", "nb_pme_last_error", "nb_pme_destroy"]
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _ip = ctypes.POINTER(ctypes.c_int32)
@@ -68,6 +68,12 @@ class nb_batch_info(ctypes.Structure):
                 ("evaluated_pairs", ctypes.c_int64), ("grid_blocks", ctypes.c_int32 * 2),
                 ("graph_ready", ctypes.c_int32), ("pad", ctypes.c_int32),
                 ("build_ms_last", ctypes.c_double)]
+
+
+class nb_pme_params(ctypes.Structure):
+    _fields_ = [("box", ctypes.c_double * 3), ("ewald_beta", ctypes.c_double),
+                ("coulomb_const", ctypes.c_double), ("grid", ctypes.c_int32 * 3),
+                ("order", ctypes.c_int32), ("natoms", ctypes.c_int32)]
 
 
 class NbError(RuntimeError):
@@ -115,9 +121,14 @@ def lib():
         L.nb_batch_last_error.restype = ctypes.c_char_p
         L.nb_batch_destroy.argtypes = [_vp]
         L.nb_get_timing.argtypes = [_vp, P(ctypes.c_double), P(ci64)]
+        L.nb_pme_setup.argtypes = [P(_vp), P(nb_pme_params), _vp]
+        L.nb_pme_forces.argtypes = [_vp, _vp, _vp, _vp, _vp]
+        L.nb_pme_last_error.argtypes = [_vp]
+        L.nb_pme_last_error.restype = ctypes.c_char_p
+        L.nb_pme_destroy.argtypes = [_vp]
         for name in EXPORTS:
             fn = getattr(L, name, None)
-            if fn is not None and name not in ("nb_last_error", "nb_batch_last_error"):
+            if fn is not None and name not in ("nb_last_error", "nb_batch_last_error", "nb_pme_last_error"):
                 fn.restype = ci
         _lib = L
     return _lib
@@ -348,3 +359,41 @@ def concat_instances(insts, cluster: int = 8, flags: int = 0, clusters=None, ele
     q = np.concatenate([i.q for i in insts]).astype(np.float32)
     t = np.concatenate([i.type for i in insts]).astype(np.int32)
     return ao, boxes, params, x, q, t
+
+
+# ---- reciprocal-space Ewald (smooth PME) --------------------------------------------------
+
+def _pcheck(code: int, pme=None):
+    if code != NB_OK:
+        raise NbError(code, lib().nb_pme_last_error(pme).decode(errors="replace"))
+
+
+def pme_params(box, beta: float, coulomb_const: float, grid, order: int, natoms: int) -> nb_pme_params:
+    p = nb_pme_params()
+    b = [box] * 3 if np.isscalar(box) else list(box)
+    for a in range(3):
+        p.box[a] = float(b[a])
+        p.grid[a] = int(grid[a])
+    p.ewald_beta = float(beta)
+    p.coulomb_const = float(coulomb_const)
+    p.order = int(order)
+    p.natoms = int(natoms)
+    return p
+
+
+def nb_pme_setup(params: nb_pme_params, stream=None) -> int:
+    h = _vp()
+    _pcheck(lib().nb_pme_setup(ctypes.byref(h), ctypes.byref(params), _stream(stream)))
+    return h.value
+
+
+def nb_pme_forces(pme: int, x, q, f, e) -> None:
+    _pcheck(lib().nb_pme_forces(pme, _ptr(x), _ptr(q), _ptr(f), _ptr(e)), pme)
+
+
+def nb_pme_last_error(pme: Optional[int]) -> str:
+    return lib().nb_pme_last_error(pme).decode(errors="replace")
+
+
+def nb_pme_destroy(pme: int) -> None:
+    _pcheck(lib().nb_pme_destroy(pme))

@@ -130,3 +130,14 @@ def test_setup_rejects_invalid_params_without_gpu():
     with pytest.raises(nb.NbError) as ei:
         nb.nb_setup(base_params(cutoff=0.95), stream=0)
     assert ei.value.code == nb.NB_ERR_CUTOFF
+
+
+@pytest.mark.parametrize("kw", [dict(order=5), dict(order=10), dict(grid=(6, 32, 32)),
+                                dict(beta=0.0), dict(natoms=0), dict(box=(2.0, -1.0, 2.0))])
+def test_invalid_pme_parameters_are_rejected(kw):
+    args = dict(box=2.0, beta=3.0, coulomb_const=138.935458, grid=(32, 32, 32), order=4, natoms=10)
+    args.update(kw)
+    with pytest.raises(nb.NbError) as ei:
+        nb.nb_pme_setup(nb.pme_params(**args), stream=0)  # rejected before any device call
+    assert ei.value.code == nb.NB_ERR_ARG
+    assert nb.nb_pme_last_error(None) != ""
