@@ -391,7 +391,7 @@ def main():
     tb = time.perf_counter()
     nbuild = 20
     for k in range(nbuild):
-        nb.nb_pairlist(ctx, traj[k])
+        nb.nb_pairlist(ctx, traj[k % len(traj)])
     torch.cuda.synchronize()
     us_build = 1e6 * (time.perf_counter() - tb) / nbuild
 

@@ -11,10 +11,17 @@
 //   E_rec = 1/2 sum_m G(m) |FFT(Q)(m)|^2, F_i = -q_i sum over the atom's grid points of
 //   grad(weights) phi.
 //
-// MI355X layout: one thread per atom for the spread (FP64 atomics into the real grid, n^3 per
-// atom) and the gather (FP64 sums, FP32 forces); the grid and both FFTs are FP64 (hipFFT,
-// D2Z / Z2D); the solve runs over the half-complex grid and keeps per-block FP64 energy
-// partials that one block adds in a fixed order.
+// MI355X layout.  The grid is cut into tiles of about 8^3 points; a per-atom pass computes the
+// spline weights and derivatives once (FP64, kept for the gather) and bins the atoms by the tile
+// of their own grid cell (counts, one-block scan, placement).  The spread runs one workgroup per
+// tile: it accumulates, with FP64 LDS atomics, the contributions of the atoms of its own and the
+// next tile along each axis that land on its points, and stores the finished tile with plain
+// coalesced writes, so the grid needs no clearing and sees no global atomics (every point has one
+// owner).  The gather runs one workgroup per tile as well: it stages the tile's potential plus a
+// halo of n - 1 points below it in LDS and gives each of its atoms n^2 lanes, one per grid row,
+// reduced in a fixed order (deterministic forces, FP64 sums, FP32 output).  The grid and both FFTs
+// are FP64 (hipFFT, D2Z / Z2D); the solve runs over the half-complex grid and keeps per-block
+// FP64 energy partials that one block adds in a fixed order.
 #include <hip/hip_runtime.h>
 #include <hipfft/hipfft.h>
 
@@ -26,6 +33,8 @@
 
 #define NB_PME_BLOCK 256
 #define NB_PME_MAX_ORDER 8
+#define NB_PME_TILE 8
+#define NB_PME_SCAN 1024
 
 struct nb_pme {
     hipStream_t stream = nullptr;
@@ -40,6 +49,21 @@ struct nb_pme {
     double *infl = nullptr;        // [K1][K2][K3/2 + 1] G(m) times the Hermitian weight / 2
     double *part = nullptr;        // energy partials of the solve blocks
     int nsolve_blocks = 0;
+    // tiles: nt[a] per axis, tile t covers points t K / nt .. (t + 1) K / nt - 1 (at least
+    // order - 1 and at most max(NB_PME_TILE, 2 order - 3) points)
+    int nt[3] = {1, 1, 1};
+    int ntiles = 0, tmax[3] = {0, 0, 0};
+    size_t lds_spread = 0, lds_gather = 0;   // dynamic LDS bytes of the spread and gather
+    int *tcount = nullptr;         // [ntiles] atoms per tile (zero between calls)
+    int *toff = nullptr;           // [ntiles + 1] first atom of each tile in tatoms
+    int4 *abase = nullptr;         // [natoms] own grid cell (k1, k2, k3) and tile of each atom
+    int *arank = nullptr;          // [natoms] rank of the atom within its tile
+    // atoms in tile order: index, cell, charge and spline data ([6 order][natoms]: weights of the
+    // three axes, then derivatives)
+    int *sidx = nullptr;
+    int4 *sbase = nullptr;
+    float *sq = nullptr;
+    double *sth = nullptr;
     hipfftHandle fwd = 0, bwd = 0;
     bool have_fwd = false, have_bwd = false;
     std::string err;
@@ -57,72 +81,294 @@ int pfail(nb_pme *p, int code, const std::string &msg) {
 
 // Cardinal B-spline weights M_n(w + j), j = 0 .. n-1, for w in [0, 1), and their derivatives
 // dM_n(w + j) / dx = M_{n-1}(w + j) - M_{n-1}(w + j - 1), by the recursion
-// M_k(x) = x / (k-1) M_{k-1}(x) + (k - x) / (k-1) M_{k-1}(x - 1) evaluated on the n points at once.
-__device__ __forceinline__ void pme_bspline(double w, int n, double *val, double *der) {
-    // order-2 values on the points x_j = w + j: M_2(x) = 1 - |x - 1| on [0, 2]
-    double m[NB_PME_MAX_ORDER + 1];
-#pragma unroll
-    for (int j = 0; j <= NB_PME_MAX_ORDER; ++j) m[j] = 0.0;
-    m[0] = w;          // M_2(w), x in [0, 1)
+// M_k(x) = x / (k-1) M_{k-1}(x) + (k - x) / (k-1) M_{k-1}(x - 1), evaluated on the n points at
+// once and unrolled for the order N.
+template <int N>
+__device__ __forceinline__ void pme_bspline(double w, double (&val)[N], double (&der)[N]) {
+    double m[N];
+    m[0] = w;          // M_2(w)
     m[1] = 1.0 - w;    // M_2(w + 1)
-    // m[j] holds M_k(w + j) for j = 0 .. k-1 (zero beyond)
-    for (int k = 3; k <= n; ++k) {
-        if (k == n) {
 #pragma unroll
-            for (int j = 0; j < NB_PME_MAX_ORDER; ++j)
-                der[j] = (j < n) ? m[j] - (j > 0 ? m[j - 1] : 0.0) : 0.0;
+    for (int j = 2; j < N; ++j) m[j] = 0.0;
+    // m[j] holds M_k(w + j) for j = 0 .. k-1 (zero beyond)
+#pragma unroll
+    for (int k = 3; k <= N; ++k) {
+        if (k == N) {
+#pragma unroll
+            for (int j = 0; j < N; ++j) der[j] = m[j] - (j > 0 ? m[j - 1] : 0.0);
         }
-        const double inv = 1.0 / (k - 1);
+        constexpr double one = 1.0;
+        const double inv = one / (k - 1);
+#pragma unroll
         for (int j = k - 1; j >= 0; --j) {
             const double x = w + j;
-            const double a = x * m[j];
-            const double b = j > 0 ? (k - x) * m[j - 1] : 0.0;
-            m[j] = (a + b) * inv;
+            const double lo = j > 0 ? (k - x) * m[j - 1] : 0.0;
+            m[j] = (x * m[j] + lo) * inv;
         }
     }
 #pragma unroll
-    for (int j = 0; j < NB_PME_MAX_ORDER; ++j) val[j] = j < n ? m[j] : 0.0;
+    for (int j = 0; j < N; ++j) val[j] = m[j];
 }
 
-__device__ __forceinline__ int pme_wrap(int k, int K) {
-    k %= K;
-    return k < 0 ? k + K : k;
+// Own grid cell of a coordinate along one axis: k = floor(K x / L) wrapped into 0 .. K-1, and the
+// fractional part w of K x / L (the spline argument).
+__device__ __forceinline__ int pme_cell(float xa, double La, int Ka, double &w) {
+    const double u = (double)xa / La * Ka;
+    const double fl = floor(u);
+    w = u - fl;
+    int c = (int)fl % Ka;
+    return c + (c < 0 ? Ka : 0);
 }
 
-__global__ void k_pme_zero(size_t n, double *__restrict__ g) {
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) g[i] = 0.0;
+// Binning: each atom's own grid cell, the tile holding it and the atom's rank within the tile.
+// A block first ranks its atoms per tile in an LDS hash table (tile -> count), then adds each
+// table entry to the global tile count with one atomic, whose old value is the entry's base;
+// the tile counts start at zero.
+#define NB_PME_HASH (2 * NB_PME_BLOCK)
+__global__ void __launch_bounds__(NB_PME_BLOCK) k_pme_bin(int natoms, int K1, int K2, int K3, int nt1, int nt2,
+                                                           int nt3, double L1, double L2, double L3,
+                                                           const float *__restrict__ x,
+                                                           int4 *__restrict__ abase, int *__restrict__ arank,
+                                                           int *__restrict__ tcount) {
+    __shared__ int hkey[NB_PME_HASH], hcnt[NB_PME_HASH];
+    for (int h = threadIdx.x; h < NB_PME_HASH; h += NB_PME_BLOCK) {
+        hkey[h] = -1;
+        hcnt[h] = 0;
+    }
+    __syncthreads();
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = i < natoms;
+    int slot = 0, lr = 0;
+    if (live) {
+        double w;
+        const int c1 = pme_cell(x[3 * i], L1, K1, w);
+        const int c2 = pme_cell(x[3 * i + 1], L2, K2, w);
+        const int c3 = pme_cell(x[3 * i + 2], L3, K3, w);
+        const int u1 = ((c1 + 1) * nt1 - 1) / K1, u2 = ((c2 + 1) * nt2 - 1) / K2, u3 = ((c3 + 1) * nt3 - 1) / K3;
+        const int tile = (u1 * nt2 + u2) * nt3 + u3;
+        abase[i] = make_int4(c1, c2, c3, tile);
+        // open addressing; the table has twice as many entries as the block has atoms
+        slot = (int)(((unsigned)tile * 2654435761u) >> 23) & (NB_PME_HASH - 1);
+        for (;;) {
+            const int old = atomicCAS(&hkey[slot], -1, tile);
+            if (old == -1 || old == tile) break;
+            slot = (slot + 1) & (NB_PME_HASH - 1);
+        }
+        lr = atomicAdd(&hcnt[slot], 1);
+    }
+    __syncthreads();
+    for (int h = threadIdx.x; h < NB_PME_HASH; h += NB_PME_BLOCK) {
+        const int k = hkey[h];
+        if (k >= 0) hcnt[h] = atomicAdd(tcount + k, hcnt[h]);
+    }
+    __syncthreads();
+    if (live) arank[i] = hcnt[slot] + lr;
 }
 
-__global__ void __launch_bounds__(NB_PME_BLOCK) k_pme_spread(int natoms, int n, int K1, int K2, int K3,
-                                                              double L1, double L2, double L3,
-                                                              const float *__restrict__ x,
-                                                              const float *__restrict__ q,
-                                                              double *__restrict__ grid) {
+// Exclusive scan of the tile counts into toff (toff[n] = natoms); the counts are reset to zero
+// for the next call.  One block; each thread scans a contiguous run.
+__global__ void __launch_bounds__(NB_PME_SCAN) k_pme_scan(int n, int *__restrict__ cnt, int *__restrict__ off) {
+    __shared__ int ws[NB_PME_SCAN / 64];
+    const int per = (n + NB_PME_SCAN - 1) / NB_PME_SCAN;
+    const int b = min(n, (int)threadIdx.x * per), e = min(n, b + per);
+    int sum = 0;
+    for (int i = b; i < e; ++i) sum += cnt[i];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int inc = sum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += y;
+    }
+    if (lane == 63) ws[w] = inc;
+    __syncthreads();
+    if (w == 0) {
+        int v = lane < NB_PME_SCAN / 64 ? ws[lane] : 0;
+#pragma unroll
+        for (int o = 1; o < NB_PME_SCAN / 64; o <<= 1) {
+            const int y = __shfl_up(v, o, 64);
+            if (lane >= o) v += y;
+        }
+        if (lane < NB_PME_SCAN / 64) ws[lane] = v;
+    }
+    __syncthreads();
+    int run = inc - sum + (w > 0 ? ws[w - 1] : 0);
+    for (int i = b; i < e; ++i) {
+        const int c = cnt[i];
+        off[i] = run;
+        run += c;
+        cnt[i] = 0;
+    }
+    if (threadIdx.x == NB_PME_SCAN - 1) off[n] = run;
+}
+
+// Placement in tile order, with the spline data computed on the way: slot c = toff[tile] + rank
+// receives the atom index, its cell, its charge and, in rows of natoms (structure of arrays), the
+// weights M_n(w_a + j) (rows a N + j) and their derivatives (rows 3 N + a N + j).
+template <int N>
+__global__ void __launch_bounds__(NB_PME_BLOCK) k_pme_place(int natoms, int K1, int K2, int K3, double L1,
+                                                             double L2, double L3, const float *__restrict__ x,
+                                                             const float *__restrict__ q,
+                                                             const int4 *__restrict__ abase,
+                                                             const int *__restrict__ arank,
+                                                             const int *__restrict__ toff,
+                                                             int *__restrict__ sidx, int4 *__restrict__ sbase,
+                                                             float *__restrict__ sq, double *__restrict__ sth) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= natoms) return;
-    const double qi = q[i];
-    if (qi == 0.0) return;
-    double v[3][NB_PME_MAX_ORDER], d[3][NB_PME_MAX_ORDER];
-    int base[3];
+    const int4 kb = abase[i];
+    const int c = toff[kb.w] + arank[i];
+    sidx[c] = i;
+    sbase[c] = kb;
+    sq[c] = q[i];
     const int K[3] = {K1, K2, K3};
     const double L[3] = {L1, L2, L3};
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const double u = (double)x[3 * i + a] / L[a] * K[a];
-        const double fl = floor(u);
-        pme_bspline(u - fl, n, v[a], d[a]);
-        base[a] = pme_wrap((int)fl, K[a]);
-    }
-    for (int j1 = 0; j1 < n; ++j1) {
-        const int k1 = pme_wrap(base[0] - j1, K1);
-        const double w1 = qi * v[0][j1];
-        for (int j2 = 0; j2 < n; ++j2) {
-            const int k2 = pme_wrap(base[1] - j2, K2);
-            const double w12 = w1 * v[1][j2];
-            double *row = grid + ((size_t)k1 * K2 + k2) * K3;
-            for (int j3 = 0; j3 < n; ++j3) atomicAdd(row + pme_wrap(base[2] - j3, K3), w12 * v[2][j3]);
+        double w, v[N], d[N];
+        pme_cell(x[3 * i + a], L[a], K[a], w);
+        pme_bspline<N>(w, v, d);
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            sth[(size_t)(a * N + j) * natoms + c] = v[j];
+            sth[(size_t)(3 * N + a * N + j) * natoms + c] = d[j];
         }
+    }
+}
+
+// Lanes of a wave: N^2 per atom, lane (j2, j3) with j3 fastest, so that the N^2 lanes of an atom
+// cover N rows of N consecutive grid points along the third axis and loop over the first; a
+// wave holds 64 / N^2 atoms (4 for order 4, one for orders 6 and 8).
+template <int N>
+struct pme_lanes {
+    static constexpr int R = N * N;
+    static constexpr int APW = 64 / R;
+    int slot, j2, j3;
+    __device__ pme_lanes(int lane) : slot(lane / R), j2((lane % R) / N), j3(lane % N) {}
+};
+
+// First point and extent of tile t of nt along an axis of K points.
+struct pme_span {
+    int s, z;
+    __device__ pme_span(int t, int nt, int K) : s(t * K / nt), z((t + 1) * K / nt - t * K / nt) {}
+};
+
+// Candidates staged per pass of the spread (and atoms per pass of the gather).
+template <int N>
+struct pme_chunk {
+    static constexpr int SPREAD = N == 4 ? 256 : 128;
+    static constexpr int GATHER = 64;
+};
+
+// One workgroup per tile.  Atom a touches the points k_a - j, j = 0 .. N-1 (wrapped) along each
+// axis; with tiles of at least N - 1 points those lie in the atom's own tile and the one below,
+// so a tile collects the atoms of itself and of the next tile along each axis (2^3 source tiles,
+// fewer where an axis has one or two tiles).  Per pass, the threads test one candidate each,
+// compact the atoms that reach the tile into LDS with their (charge-scaled) weights, and the waves
+// then add those atoms' contributions to the tile with LDS atomics.
+template <int N>
+__global__ void __launch_bounds__(NB_PME_BLOCK) k_pme_spread(int natoms, int K1, int K2, int K3, int nt1,
+                                                              int nt2, int nt3,
+                                                              const int4 *__restrict__ sbase,
+                                                              const float *__restrict__ sq,
+                                                              const double *__restrict__ sth,
+                                                              const int *__restrict__ toff,
+                                                              double *__restrict__ grid) {
+    constexpr int CH = pme_chunk<N>::SPREAD, APW = pme_lanes<N>::APW, WAVES = NB_PME_BLOCK / 64;
+    extern __shared__ double lg[];                 // tile points, then CH x 3N weights
+    __shared__ int4 cb[CH];                        // local cells (l1, l2, l3) of the staged atoms
+    __shared__ int cnum, csrc[9];
+    const int t = blockIdx.x;
+    const int t3 = t % nt3, t2 = (t / nt3) % nt2, t1 = t / (nt3 * nt2);
+    const pme_span a1(t1, nt1, K1), a2(t2, nt2, K2), a3(t3, nt3, K3);
+    const int np = a1.z * a2.z * a3.z;
+    double *wt = lg + np;
+    for (int p = threadIdx.x; p < np; p += NB_PME_BLOCK) lg[p] = 0.0;
+    // candidate ranges of the source tiles, as a running count over them
+    const int n1 = nt1 > 1 ? 2 : 1, n2 = nt2 > 1 ? 2 : 1, n3 = nt3 > 1 ? 2 : 1, ns = n1 * n2 * n3;
+    if (threadIdx.x < 64) {   // lanes 0 .. ns-1 read one source tile each; a scan gives the starts
+        const int d = threadIdx.x;
+        int cnt = 0;
+        if (d < ns) {
+            int u1 = t1 + d / (n2 * n3), u2 = t2 + (d / n3) % n2, u3 = t3 + d % n3;
+            u1 -= u1 >= nt1 ? nt1 : 0;
+            u2 -= u2 >= nt2 ? nt2 : 0;
+            u3 -= u3 >= nt3 ? nt3 : 0;
+            const int ts = (u1 * nt2 + u2) * nt3 + u3;
+            cnt = toff[ts + 1] - toff[ts];
+        }
+        int inc = cnt;
+#pragma unroll
+        for (int o = 1; o < 8; o <<= 1) {
+            const int y = __shfl_up(inc, o, 64);
+            if (d >= o) inc += y;
+        }
+        if (d < ns) csrc[d + 1] = inc;
+        if (d == 0) csrc[0] = 0;
+    }
+    __syncthreads();
+    const int total = csrc[ns];
+    const pme_lanes<N> ln(threadIdx.x & 63);
+    const int wave = threadIdx.x >> 6;
+    for (int c0 = 0; c0 < total; c0 += CH) {
+        if (threadIdx.x == 0) cnum = 0;
+        __syncthreads();
+        const int r = c0 + (int)threadIdx.x;
+        if (threadIdx.x < CH && r < total) {
+            int d = 0;
+            while (r >= csrc[d + 1]) ++d;
+            int u1 = t1 + d / (n2 * n3), u2 = t2 + (d / n3) % n2, u3 = t3 + d % n3;
+            u1 -= u1 >= nt1 ? nt1 : 0;
+            u2 -= u2 >= nt2 ? nt2 : 0;
+            u3 -= u3 >= nt3 ? nt3 : 0;
+            const int c = toff[(u1 * nt2 + u2) * nt3 + u3] + (r - csrc[d]);
+            const int4 kb = sbase[c];
+            // local index of the atom's cell relative to the tile start; the atom reaches the
+            // tile along an axis if some k - j, j < N, falls in it
+            int l1 = kb.x - a1.s, l2 = kb.y - a2.s, l3 = kb.z - a3.s;
+            l1 += l1 < 0 ? K1 : 0;
+            l2 += l2 < 0 ? K2 : 0;
+            l3 += l3 < 0 ? K3 : 0;
+            const bool hit = (l1 < a1.z + N - 1) && (l2 < a2.z + N - 1) && (l3 < a3.z + N - 1);
+            if (hit) {
+                const int s = atomicAdd(&cnum, 1);
+                cb[s] = make_int4(l1, l2, l3, 0);
+                const double qi = sq[c];
+#pragma unroll
+                for (int j = 0; j < 3 * N; ++j) {
+                    const double v = sth[(size_t)j * natoms + c];
+                    wt[s * 3 * N + j] = j < N ? qi * v : v;
+                }
+            }
+        }
+        __syncthreads();
+        const int nc = cnum;
+        for (int g = wave * APW; g < nc; g += WAVES * APW) {
+            const int s = g + ln.slot;
+            if (ln.slot >= APW || s >= nc) continue;
+            const int4 lb = cb[s];
+            // local point (l - j) wrapped: below the tile start it lands at K - ..., outside the
+            // tile unless the tile spans the whole axis
+            int l2 = lb.y - ln.j2, l3 = lb.z - ln.j3;
+            l2 += l2 < 0 ? K2 : 0;
+            l3 += l3 < 0 ? K3 : 0;
+            if ((unsigned)l2 >= (unsigned)a2.z || (unsigned)l3 >= (unsigned)a3.z) continue;
+            const double *w = wt + s * 3 * N;
+            const double w23 = w[N + ln.j2] * w[2 * N + ln.j3];
+            double *row = lg + l2 * a3.z + l3;
+#pragma unroll
+            for (int j1 = 0; j1 < N; ++j1) {
+                int l1 = lb.x - j1;
+                l1 += l1 < 0 ? K1 : 0;
+                if ((unsigned)l1 < (unsigned)a1.z) atomicAdd(row + l1 * (a2.z * a3.z), w23 * w[j1]);
+            }
+        }
+        __syncthreads();
+    }
+    const int zz = a2.z * a3.z;
+    for (int p = threadIdx.x; p < np; p += NB_PME_BLOCK) {
+        const int l1 = p / zz, rr = p - l1 * zz, l2 = rr / a3.z, l3 = rr - l2 * a3.z;
+        grid[((size_t)(a1.s + l1) * K2 + (a2.s + l2)) * K3 + (a3.s + l3)] = lg[p];
     }
 }
 
@@ -168,48 +414,100 @@ __global__ void __launch_bounds__(NB_PME_BLOCK) k_pme_energy(int nblk, const dou
     }
 }
 
-__global__ void __launch_bounds__(NB_PME_BLOCK) k_pme_gather(int natoms, int n, int K1, int K2, int K3,
-                                                              double L1, double L2, double L3,
-                                                              const float *__restrict__ x,
-                                                              const float *__restrict__ q,
+// One workgroup per tile: the potential on the tile and N - 1 points below it along each axis
+// (wrapped) is staged in LDS, and so are the spline data of the tile's atoms, GATHER atoms per
+// pass; each atom gets N^2 lanes (same layout as the spread), each summing its N points along the
+// first axis, and the lanes of an atom are reduced in a fixed order (deterministic forces).
+template <int N>
+__global__ void __launch_bounds__(NB_PME_BLOCK) k_pme_gather(int natoms, int K1, int K2, int K3, int nt1,
+                                                              int nt2, int nt3, double L1, double L2, double L3,
+                                                              const int *__restrict__ sidx,
+                                                              const int4 *__restrict__ sbase,
+                                                              const float *__restrict__ sq,
+                                                              const double *__restrict__ sth,
+                                                              const int *__restrict__ toff,
                                                               const double *__restrict__ phi,
                                                               float *__restrict__ f) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= natoms) return;
-    const double qi = q[i];
-    double v[3][NB_PME_MAX_ORDER], d[3][NB_PME_MAX_ORDER];
-    int base[3];
-    const int K[3] = {K1, K2, K3};
-    const double L[3] = {L1, L2, L3};
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const double u = (double)x[3 * i + a] / L[a] * K[a];
-        const double fl = floor(u);
-        pme_bspline(u - fl, n, v[a], d[a]);
-        base[a] = pme_wrap((int)fl, K[a]);
+    constexpr int CH = pme_chunk<N>::GATHER, R = pme_lanes<N>::R, APW = pme_lanes<N>::APW;
+    constexpr int WAVES = NB_PME_BLOCK / 64;
+    constexpr int RED = APW > 1 ? R : 64;   // reduction width, a power of two
+    extern __shared__ double lp[];          // staged potential, then CH x 6N spline data
+    __shared__ int4 ab[CH];                 // cells, charges and indices of the staged atoms
+    __shared__ float aq[CH];
+    __shared__ int ai[CH];
+    const int t = blockIdx.x;
+    const int t3 = t % nt3, t2 = (t / nt3) % nt2, t1 = t / (nt3 * nt2);
+    const pme_span a1(t1, nt1, K1), a2(t2, nt2, K2), a3(t3, nt3, K3);
+    // staged box: points s_a - (N - 1) .. s_a + z_a - 1 along each axis
+    const int c0 = toff[t], c1 = toff[t + 1];
+    if (c0 == c1) return;   // no atoms in this tile
+    const int h1 = a1.z + N - 1, h2 = a2.z + N - 1, h3 = a3.z + N - 1, hh = h2 * h3;
+    double *sd = lp + h1 * hh;
+    for (int p = threadIdx.x; p < h1 * hh; p += NB_PME_BLOCK) {
+        const int l1 = p / hh, r = p - l1 * hh, l2 = r / h3, l3 = r - l2 * h3;
+        int k1 = a1.s - (N - 1) + l1, k2 = a2.s - (N - 1) + l2, k3 = a3.s - (N - 1) + l3;
+        k1 += k1 < 0 ? K1 : 0;
+        k2 += k2 < 0 ? K2 : 0;
+        k3 += k3 < 0 ? K3 : 0;
+        lp[p] = phi[((size_t)k1 * K2 + k2) * K3 + k3];
     }
-    double gx = 0.0, gy = 0.0, gz = 0.0;
-    if (qi != 0.0) {
-        for (int j1 = 0; j1 < n; ++j1) {
-            const int k1 = pme_wrap(base[0] - j1, K1);
-            for (int j2 = 0; j2 < n; ++j2) {
-                const int k2 = pme_wrap(base[1] - j2, K2);
-                const double *row = phi + ((size_t)k1 * K2 + k2) * K3;
-                double sv = 0.0, sd = 0.0;
-                for (int j3 = 0; j3 < n; ++j3) {
-                    const double p = row[pme_wrap(base[2] - j3, K3)];
-                    sv += v[2][j3] * p;
-                    sd += d[2][j3] * p;
+    const pme_lanes<N> ln(threadIdx.x & 63);
+    const int wave = threadIdx.x >> 6;
+    for (int cb = c0; cb < c1; cb += CH) {
+        const int nc = min(CH, c1 - cb);
+        if (cb != c0) __syncthreads();   // previous pass done with the staged atoms
+        for (int e = threadIdx.x; e < nc * 6 * N; e += NB_PME_BLOCK) {
+            const int j = e / nc, a = e - j * nc;
+            sd[a * 6 * N + j] = sth[(size_t)j * natoms + cb + a];
+        }
+        if (threadIdx.x < nc) {
+            ab[threadIdx.x] = sbase[cb + threadIdx.x];
+            aq[threadIdx.x] = sq[cb + threadIdx.x];
+            ai[threadIdx.x] = sidx[cb + threadIdx.x];
+        }
+        __syncthreads();   // staged potential and atoms ready
+        for (int g = wave * APW; g < nc; g += WAVES * APW) {   // wave-uniform trip count
+            const int s = g + ln.slot;
+            const bool live = ln.slot < APW && s < nc;
+            double gx = 0.0, gy = 0.0, gz = 0.0;
+            if (live) {
+                const int4 kb = ab[s];
+                const double *th = sd + s * 6 * N;
+                const double *dh = th + 3 * N;
+                // local coordinates in the staged box: k_a - j - (s_a - (N - 1)), in 0 .. h_a - 1
+                // (the atom's own cell k_a lies in this tile)
+                const int l2 = kb.y - a2.s + (N - 1) - ln.j2;
+                const int l3 = kb.z - a3.s + (N - 1) - ln.j3;
+                const int l1 = kb.x - a1.s + (N - 1);
+                const double *col = lp + l2 * h3 + l3;
+                double sa = 0.0, sb = 0.0;
+#pragma unroll
+                for (int j1 = 0; j1 < N; ++j1) {
+                    const double p = col[(l1 - j1) * hh];
+                    sa += dh[j1] * p;
+                    sb += th[j1] * p;
                 }
-                gx += d[0][j1] * v[1][j2] * sv;
-                gy += v[0][j1] * d[1][j2] * sv;
-                gz += v[0][j1] * v[1][j2] * sd;
+                const double v2 = th[N + ln.j2], d2 = dh[N + ln.j2];
+                const double v3 = th[2 * N + ln.j3], d3 = dh[2 * N + ln.j3];
+                gx = sa * v2 * v3;
+                gy = sb * d2 * v3;
+                gz = sb * v2 * d3;
+            }
+#pragma unroll
+            for (int o = RED / 2; o > 0; o >>= 1) {
+                gx += __shfl_xor(gx, o, 64);
+                gy += __shfl_xor(gy, o, 64);
+                gz += __shfl_xor(gz, o, 64);
+            }
+            if (live && (threadIdx.x & (RED - 1)) == 0) {
+                const double qi = aq[s];
+                const int i = ai[s];
+                f[3 * i] = (float)(-qi * gx * K1 / L1);
+                f[3 * i + 1] = (float)(-qi * gy * K2 / L2);
+                f[3 * i + 2] = (float)(-qi * gz * K3 / L3);
             }
         }
     }
-    f[3 * i] = (float)(-qi * gx * K1 / L1);
-    f[3 * i + 1] = (float)(-qi * gy * K2 / L2);
-    f[3 * i + 2] = (float)(-qi * gz * K3 / L3);
 }
 
 // Host side: cardinal B-spline values M_n(k), k = 1 .. n-1, and the moduli |b(m)|^2.
@@ -252,7 +550,8 @@ int palloc(nb_pme *p, T **ptr, size_t count, const char *what) {
 void pme_free(nb_pme *p) {
     if (p->have_fwd) hipfftDestroy(p->fwd);
     if (p->have_bwd) hipfftDestroy(p->bwd);
-    void *bufs[] = {p->grid, p->cgrid, p->infl, p->part};
+    void *bufs[] = {p->grid, p->cgrid, p->infl, p->part, p->tcount, p->toff, p->abase, p->arank,
+                    p->sidx, p->sbase, p->sq, p->sth};
     for (void *b : bufs)
         if (b) hipFree(b);
 }
@@ -288,8 +587,34 @@ int nb_pme_setup(nb_pme **out, const nb_pme_params *prm, void *stream) {
     p->nreal = (size_t)K1 * K2 * K3;
     p->ncplx = (size_t)K1 * K2 * K3h;
     p->nsolve_blocks = (int)((p->ncplx + NB_PME_BLOCK - 1) / NB_PME_BLOCK);
+    // tiles of about NB_PME_TILE points, never fewer than order - 1 (so that an atom's points lie
+    // in its own tile and the one below)
+    for (int a = 0; a < 3; ++a) {
+        const int K = p->K[a];
+        p->nt[a] = std::max(1, std::min((K + NB_PME_TILE - 1) / NB_PME_TILE, K / (p->order - 1)));
+        p->tmax[a] = (K + p->nt[a] - 1) / p->nt[a];
+    }
+    p->ntiles = p->nt[0] * p->nt[1] * p->nt[2];
+    {
+        const int n = p->order, chs = n == 4 ? 256 : 128, chg = 64;   // candidates / atoms per pass
+        p->lds_spread = sizeof(double) * ((size_t)p->tmax[0] * p->tmax[1] * p->tmax[2] + (size_t)chs * 3 * n);
+        p->lds_gather = sizeof(double) * ((size_t)(p->tmax[0] + n - 1) * (p->tmax[1] + n - 1) * (p->tmax[2] + n - 1) +
+                                          (size_t)chg * 6 * n);
+        if (p->lds_spread > 49152 || p->lds_gather > 65536) {
+            delete p;
+            return pfail(nullptr, NB_ERR_ARG, "grid tiles exceed the LDS of a workgroup");
+        }
+    }
     int r;
-    if ((r = palloc(p, &p->grid, p->nreal, "grid")) != NB_OK ||
+    if ((r = palloc(p, &p->tcount, (size_t)p->ntiles, "tile counts")) != NB_OK ||
+        (r = palloc(p, &p->toff, (size_t)p->ntiles + 1, "tile offsets")) != NB_OK ||
+        (r = palloc(p, &p->abase, (size_t)p->natoms, "atom cells")) != NB_OK ||
+        (r = palloc(p, &p->arank, (size_t)p->natoms, "atom ranks")) != NB_OK ||
+        (r = palloc(p, &p->sidx, (size_t)p->natoms, "sorted atoms")) != NB_OK ||
+        (r = palloc(p, &p->sbase, (size_t)p->natoms, "sorted cells")) != NB_OK ||
+        (r = palloc(p, &p->sq, (size_t)p->natoms, "sorted charges")) != NB_OK ||
+        (r = palloc(p, &p->sth, (size_t)p->natoms * 6 * p->order, "spline data")) != NB_OK ||
+        (r = palloc(p, &p->grid, p->nreal, "grid")) != NB_OK ||
         (r = palloc(p, &p->cgrid, p->ncplx, "transform")) != NB_OK ||
         (r = palloc(p, &p->infl, 2 * p->ncplx, "influence function")) != NB_OK ||
         (r = palloc(p, &p->part, (size_t)p->nsolve_blocks, "energy partials")) != NB_OK) {
@@ -320,6 +645,7 @@ int nb_pme_setup(nb_pme **out, const nb_pme_params *prm, void *stream) {
         }
     }
     hipError_t e = hipMemcpy(p->infl, g.data(), sizeof(double) * g.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(p->tcount, 0, sizeof(int) * p->ntiles);
     if (e != hipSuccess) {
         pme_free(p);
         delete p;
@@ -345,11 +671,27 @@ int nb_pme_forces(nb_pme *p, const float *x, const float *q, float *f, double *e
     if (!p || !x || !q || !f || !e) return pfail(p, NB_ERR_ARG, "NULL argument");
     hipSetDevice(p->device);
     const int K1 = p->K[0], K2 = p->K[1], K3 = p->K[2];
-    const int ab = (p->natoms + NB_PME_BLOCK - 1) / NB_PME_BLOCK;
-    hipLaunchKernelGGL(k_pme_zero, dim3((unsigned)((p->nreal + NB_PME_BLOCK - 1) / NB_PME_BLOCK)),
-                       dim3(NB_PME_BLOCK), 0, p->stream, p->nreal, p->grid);
-    hipLaunchKernelGGL(k_pme_spread, dim3(ab), dim3(NB_PME_BLOCK), 0, p->stream, p->natoms, p->order,
-                       K1, K2, K3, p->L[0], p->L[1], p->L[2], x, q, p->grid);
+    const unsigned ab = (unsigned)((p->natoms + NB_PME_BLOCK - 1) / NB_PME_BLOCK);
+    const int n = p->order;
+    const size_t lds_spread = p->lds_spread, lds_gather = p->lds_gather;
+    hipLaunchKernelGGL(k_pme_bin, dim3(ab), dim3(NB_PME_BLOCK), 0, p->stream, p->natoms, K1, K2, K3, p->nt[0],
+                       p->nt[1], p->nt[2], p->L[0], p->L[1], p->L[2], x, p->abase, p->arank, p->tcount);
+    hipLaunchKernelGGL(k_pme_scan, dim3(1), dim3(NB_PME_SCAN), 0, p->stream, p->ntiles, p->tcount, p->toff);
+#define NB_PME_PLACE(N)                                                                                \
+    hipLaunchKernelGGL(k_pme_place<N>, dim3(ab), dim3(NB_PME_BLOCK), 0, p->stream, p->natoms, K1, K2, K3, \
+                       p->L[0], p->L[1], p->L[2], x, q, p->abase, p->arank, p->toff, p->sidx, p->sbase,   \
+                       p->sq, p->sth)
+#define NB_PME_SPREAD(N)                                                                                      \
+    hipLaunchKernelGGL(k_pme_spread<N>, dim3(p->ntiles), dim3(NB_PME_BLOCK), lds_spread, p->stream, p->natoms, \
+                       K1, K2, K3, p->nt[0], p->nt[1], p->nt[2], p->sbase, p->sq, p->sth, p->toff, p->grid)
+    if (n == 4) NB_PME_PLACE(4);
+    else if (n == 6) NB_PME_PLACE(6);
+    else NB_PME_PLACE(8);
+    if (n == 4) NB_PME_SPREAD(4);
+    else if (n == 6) NB_PME_SPREAD(6);
+    else NB_PME_SPREAD(8);
+#undef NB_PME_PLACE
+#undef NB_PME_SPREAD
     if (hipGetLastError() != hipSuccess) return pfail(p, NB_ERR_HIP, "spread launch");
     if (hipfftExecD2Z(p->fwd, (hipfftDoubleReal *)p->grid, (hipfftDoubleComplex *)p->cgrid) != HIPFFT_SUCCESS)
         return pfail(p, NB_ERR_HIP, "forward FFT");
@@ -359,8 +701,14 @@ int nb_pme_forces(nb_pme *p, const float *x, const float *q, float *f, double *e
     if (hipGetLastError() != hipSuccess) return pfail(p, NB_ERR_HIP, "solve launch");
     if (hipfftExecZ2D(p->bwd, (hipfftDoubleComplex *)p->cgrid, (hipfftDoubleReal *)p->grid) != HIPFFT_SUCCESS)
         return pfail(p, NB_ERR_HIP, "inverse FFT");
-    hipLaunchKernelGGL(k_pme_gather, dim3(ab), dim3(NB_PME_BLOCK), 0, p->stream, p->natoms, p->order,
-                       K1, K2, K3, p->L[0], p->L[1], p->L[2], x, q, p->grid, f);
+#define NB_PME_GATHER(N)                                                                                      \
+    hipLaunchKernelGGL(k_pme_gather<N>, dim3(p->ntiles), dim3(NB_PME_BLOCK), lds_gather, p->stream, p->natoms, \
+                       K1, K2, K3, p->nt[0], p->nt[1], p->nt[2], p->L[0], p->L[1], p->L[2], p->sidx, p->sbase, \
+                       p->sq, p->sth, p->toff, p->grid, f)
+    if (n == 4) NB_PME_GATHER(4);
+    else if (n == 6) NB_PME_GATHER(6);
+    else NB_PME_GATHER(8);
+#undef NB_PME_GATHER
     if (hipGetLastError() != hipSuccess) return pfail(p, NB_ERR_HIP, "gather launch");
     return NB_OK;
 }

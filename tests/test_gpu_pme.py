@@ -41,7 +41,8 @@ def random_system(n=96, L=(2.0, 2.2, 1.9), seed=7):
     return x, q.astype(np.float32), L
 
 
-@pytest.mark.parametrize("grid,order", [((20, 24, 28), 4), ((16, 18, 21), 6), ((24, 24, 24), 8)])
+@pytest.mark.parametrize("grid,order", [((20, 24, 28), 4), ((16, 18, 21), 6), ((24, 24, 24), 8),
+                                        ((8, 13, 30), 4), ((16, 17, 20), 8)])
 def test_pme_matches_fp64_reference(torch_gpu, grid, order):
     x, q, L = random_system()
     beta = 3.0
@@ -50,6 +51,33 @@ def test_pme_matches_fp64_reference(torch_gpu, grid, order):
     fr, er = rel_rms(f, f0), abs(e - e0) / abs(e0)
     print(f"grid {grid} order {order}: force relRMS {fr:.2e}, energy rel {er:.2e}", flush=True)
     assert fr <= FORCE_TOL and er <= PME_E_TOL
+
+
+def test_pme_clustered_atoms_and_repeated_calls(torch_gpu):
+    """All atoms in a small cube (one or two grid tiles hold every atom), then a second call on
+    the same context with the atoms spread over the box: both match the reference."""
+    torch = torch_gpu
+    L, beta, grid, order = (2.0, 2.2, 1.9), 3.0, (20, 24, 18), 4
+    rng = np.random.default_rng(11)
+    n = 200
+    q = rng.normal(0.0, 0.8, n)
+    q = (q - q.mean()).astype(np.float32)
+    xa = (0.61 + rng.uniform(0.0, 0.15, (n, 3))).astype(np.float32)
+    xb = (rng.uniform(0.0, 1.0, (n, 3)) * np.array(L)).astype(np.float32)
+    pm = nb.nb_pme_setup(nb.pme_params(L, beta, FC, grid, order, n))
+    dq = torch.from_numpy(q).to("cuda:0")
+    for x in (xa, xb):
+        dx = torch.from_numpy(x.reshape(-1)).to("cuda:0")
+        f = torch.zeros(n * 3, dtype=torch.float32, device="cuda:0")
+        e = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+        nb.nb_pme_forces(pm, dx, dq, f, e)
+        torch.cuda.synchronize()
+        e0, f0 = P.pme_reference(x.astype(np.float64), q.astype(np.float64), L, beta, FC, grid, order)
+        fr = rel_rms(f.cpu().numpy().reshape(-1, 3).astype(np.float64), f0)
+        er = abs(float(e.cpu().numpy()[0]) - e0) / abs(e0)
+        print(f"force relRMS {fr:.2e}, energy rel {er:.2e}", flush=True)
+        assert fr <= FORCE_TOL and er <= PME_E_TOL
+    nb.nb_pme_destroy(pm)
 
 
 def test_pme_on_the_water_box(torch_gpu):
