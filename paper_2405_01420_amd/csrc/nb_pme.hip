@@ -253,19 +253,46 @@ struct pme_span {
     __device__ pme_span(int t, int nt, int K) : s(t * K / nt), z((t + 1) * K / nt - t * K / nt) {}
 };
 
-// Candidates staged per pass of the spread (and atoms per pass of the gather).
+// Candidates tested per filter pass and hits staged per spread pass (and atoms per pass of the
+// gather).
 template <int N>
 struct pme_chunk {
+    static constexpr int FILTER = 4 * NB_PME_BLOCK;
     static constexpr int SPREAD = N == 4 ? 256 : 128;
-    static constexpr int GATHER = 64;
+    static constexpr int GATHER = N == 8 ? 32 : 64;
+};
+
+// Decomposition of a running index p = (l1 h2 + l2) h3 + l3 that advances by a fixed step without
+// divisions (one division pair at the start).
+struct pme_walk {
+    int l1, l2, l3, d1, d2, d3, h2, h3;
+    __device__ pme_walk(int p, int step, int h2_, int h3_) : h2(h2_), h3(h3_) {
+        const int hh = h2 * h3;
+        l1 = p / hh;
+        l2 = (p - l1 * hh) / h3;
+        l3 = p - l1 * hh - l2 * h3;
+        d1 = step / hh;
+        d2 = (step - d1 * hh) / h3;
+        d3 = step - d1 * hh - d2 * h3;
+    }
+    __device__ void next() {
+        l3 += d3;
+        const int c3 = l3 >= h3;
+        l3 -= c3 ? h3 : 0;
+        l2 += d2 + c3;
+        const int c2 = l2 >= h2;
+        l2 -= c2 ? h2 : 0;
+        l1 += d1 + c2;
+    }
 };
 
 // One workgroup per tile.  Atom a touches the points k_a - j, j = 0 .. N-1 (wrapped) along each
 // axis; with tiles of at least N - 1 points those lie in the atom's own tile and the one below,
 // so a tile collects the atoms of itself and of the next tile along each axis (2^3 source tiles,
-// fewer where an axis has one or two tiles).  Per pass, the threads test one candidate each,
-// compact the atoms that reach the tile into LDS with their (charge-scaled) weights, and the waves
-// then add those atoms' contributions to the tile with LDS atomics.
+// fewer where an axis has one or two tiles).  A filter pass tests up to FILTER candidates (loads
+// issued together) and lists those that reach the tile; the listed atoms' charge-scaled weights
+// are then staged in LDS, SPREAD at a time, and the waves add their contributions to the tile
+// with LDS atomics.
 template <int N>
 __global__ void __launch_bounds__(NB_PME_BLOCK) k_pme_spread(int natoms, int K1, int K2, int K3, int nt1,
                                                               int nt2, int nt3,
@@ -274,10 +301,12 @@ __global__ void __launch_bounds__(NB_PME_BLOCK) k_pme_spread(int natoms, int K1,
                                                               const double *__restrict__ sth,
                                                               const int *__restrict__ toff,
                                                               double *__restrict__ grid) {
-    constexpr int CH = pme_chunk<N>::SPREAD, APW = pme_lanes<N>::APW, WAVES = NB_PME_BLOCK / 64;
-    extern __shared__ double lg[];                 // tile points, then CH x 3N weights
-    __shared__ int4 cb[CH];                        // local cells (l1, l2, l3) of the staged atoms
-    __shared__ int cnum, csrc[9];
+    constexpr int CF = pme_chunk<N>::FILTER, CH = pme_chunk<N>::SPREAD;
+    constexpr int UF = CF / NB_PME_BLOCK, APW = pme_lanes<N>::APW, WAVES = NB_PME_BLOCK / 64;
+    constexpr int WS = 3 * N + 1;                  // staged doubles per atom (odd: fewer bank conflicts)
+    extern __shared__ double lg[];                 // tile points, then CH x WS weights
+    __shared__ int2 hit[CF];                       // listed atoms: slot, packed local cell
+    __shared__ int nhit, csrc[9], tsrc[8];
     const int t = blockIdx.x;
     const int t3 = t % nt3, t2 = (t / nt3) % nt2, t1 = t / (nt3 * nt2);
     const pme_span a1(t1, nt1, K1), a2(t2, nt2, K2), a3(t3, nt3, K3);
@@ -295,7 +324,9 @@ __global__ void __launch_bounds__(NB_PME_BLOCK) k_pme_spread(int natoms, int K1,
             u2 -= u2 >= nt2 ? nt2 : 0;
             u3 -= u3 >= nt3 ? nt3 : 0;
             const int ts = (u1 * nt2 + u2) * nt3 + u3;
-            cnt = toff[ts + 1] - toff[ts];
+            const int b = toff[ts];
+            cnt = toff[ts + 1] - b;
+            tsrc[d] = b;
         }
         int inc = cnt;
 #pragma unroll
@@ -304,72 +335,95 @@ __global__ void __launch_bounds__(NB_PME_BLOCK) k_pme_spread(int natoms, int K1,
             if (d >= o) inc += y;
         }
         if (d < ns) csrc[d + 1] = inc;
-        if (d == 0) csrc[0] = 0;
+        if (d == 0) {
+            csrc[0] = 0;
+            nhit = 0;
+        }
     }
     __syncthreads();
     const int total = csrc[ns];
     const pme_lanes<N> ln(threadIdx.x & 63);
-    const int wave = threadIdx.x >> 6;
-    for (int c0 = 0; c0 < total; c0 += CH) {
-        if (threadIdx.x == 0) cnum = 0;
-        __syncthreads();
-        const int r = c0 + (int)threadIdx.x;
-        if (threadIdx.x < CH && r < total) {
-            int d = 0;
-            while (r >= csrc[d + 1]) ++d;
-            int u1 = t1 + d / (n2 * n3), u2 = t2 + (d / n3) % n2, u3 = t3 + d % n3;
-            u1 -= u1 >= nt1 ? nt1 : 0;
-            u2 -= u2 >= nt2 ? nt2 : 0;
-            u3 -= u3 >= nt3 ? nt3 : 0;
-            const int c = toff[(u1 * nt2 + u2) * nt3 + u3] + (r - csrc[d]);
-            const int4 kb = sbase[c];
-            // local index of the atom's cell relative to the tile start; the atom reaches the
-            // tile along an axis if some k - j, j < N, falls in it
-            int l1 = kb.x - a1.s, l2 = kb.y - a2.s, l3 = kb.z - a3.s;
-            l1 += l1 < 0 ? K1 : 0;
-            l2 += l2 < 0 ? K2 : 0;
-            l3 += l3 < 0 ? K3 : 0;
-            const bool hit = (l1 < a1.z + N - 1) && (l2 < a2.z + N - 1) && (l3 < a3.z + N - 1);
-            if (hit) {
-                const int s = atomicAdd(&cnum, 1);
-                cb[s] = make_int4(l1, l2, l3, 0);
-                const double qi = sq[c];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int f0 = 0; f0 < total; f0 += CF) {
+        // filter: UF candidates per thread, loads first
+        int4 kb[UF];
+        int cs[UF];
 #pragma unroll
-                for (int j = 0; j < 3 * N; ++j) {
-                    const double v = sth[(size_t)j * natoms + c];
-                    wt[s * 3 * N + j] = j < N ? qi * v : v;
+        for (int u = 0; u < UF; ++u) {
+            const int r = f0 + u * NB_PME_BLOCK + (int)threadIdx.x;
+            cs[u] = -1;
+            if (r < total) {
+                int d = 0;
+#pragma unroll
+                for (int k = 1; k < 8; ++k) d += (k < ns && r >= csrc[k]) ? 1 : 0;
+                cs[u] = tsrc[d] + (r - csrc[d]);
+                kb[u] = sbase[cs[u]];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < UF; ++u) {
+            // local index of the atom's cell relative to the tile start; the atom reaches the tile
+            // along an axis if some k - j, j < N, falls in it
+            bool h = false;
+            int pk = 0;
+            if (cs[u] >= 0) {
+                int l1 = kb[u].x - a1.s, l2 = kb[u].y - a2.s, l3 = kb[u].z - a3.s;
+                l1 += l1 < 0 ? K1 : 0;
+                l2 += l2 < 0 ? K2 : 0;
+                l3 += l3 < 0 ? K3 : 0;
+                h = (l1 < a1.z + N - 1) && (l2 < a2.z + N - 1) && (l3 < a3.z + N - 1);
+                pk = h ? (l1 << 20) | (l2 << 10) | l3 : 0;   // l < tile extent + N - 1 < 1024
+            }
+            const uint64_t m = __ballot(h);
+            int base = 0;
+            if (lane == 0 && m) base = atomicAdd(&nhit, __popcll(m));
+            base = __shfl(base, 0, 64);
+            if (h) hit[base + __popcll(m & ((1ull << lane) - 1ull))] = make_int2(cs[u], pk);
+        }
+        __syncthreads();
+        const int nh = nhit;
+        for (int h0 = 0; h0 < nh; h0 += CH) {
+            const int nc = min(CH, nh - h0);
+            if (threadIdx.x < nc) {
+                const int c = hit[h0 + threadIdx.x].x;
+                const double qi = sq[c];
+                double v[3 * N];
+#pragma unroll
+                for (int j = 0; j < 3 * N; ++j) v[j] = sth[(size_t)j * natoms + c];
+                double *w = wt + threadIdx.x * WS;
+#pragma unroll
+                for (int j = 0; j < 3 * N; ++j) w[j] = j < N ? qi * v[j] : v[j];
+            }
+            __syncthreads();
+            for (int g = wave * APW; g < nc; g += WAVES * APW) {
+                const int s = g + ln.slot;
+                if (ln.slot >= APW || s >= nc) continue;
+                const int pk = hit[h0 + s].y;
+                // local point (l - j) wrapped: below the tile start it lands at K - ..., outside
+                // the tile unless the tile spans the whole axis
+                int l2 = ((pk >> 10) & 1023) - ln.j2, l3 = (pk & 1023) - ln.j3;
+                l2 += l2 < 0 ? K2 : 0;
+                l3 += l3 < 0 ? K3 : 0;
+                if ((unsigned)l2 >= (unsigned)a2.z || (unsigned)l3 >= (unsigned)a3.z) continue;
+                const double *w = wt + s * WS;
+                const double w23 = w[N + ln.j2] * w[2 * N + ln.j3];
+                double *row = lg + l2 * a3.z + l3;
+                const int lb1 = pk >> 20;
+#pragma unroll
+                for (int j1 = 0; j1 < N; ++j1) {
+                    int l1 = lb1 - j1;
+                    l1 += l1 < 0 ? K1 : 0;
+                    if ((unsigned)l1 < (unsigned)a1.z) atomicAdd(row + l1 * (a2.z * a3.z), w23 * w[j1]);
                 }
             }
+            __syncthreads();
         }
-        __syncthreads();
-        const int nc = cnum;
-        for (int g = wave * APW; g < nc; g += WAVES * APW) {
-            const int s = g + ln.slot;
-            if (ln.slot >= APW || s >= nc) continue;
-            const int4 lb = cb[s];
-            // local point (l - j) wrapped: below the tile start it lands at K - ..., outside the
-            // tile unless the tile spans the whole axis
-            int l2 = lb.y - ln.j2, l3 = lb.z - ln.j3;
-            l2 += l2 < 0 ? K2 : 0;
-            l3 += l3 < 0 ? K3 : 0;
-            if ((unsigned)l2 >= (unsigned)a2.z || (unsigned)l3 >= (unsigned)a3.z) continue;
-            const double *w = wt + s * 3 * N;
-            const double w23 = w[N + ln.j2] * w[2 * N + ln.j3];
-            double *row = lg + l2 * a3.z + l3;
-#pragma unroll
-            for (int j1 = 0; j1 < N; ++j1) {
-                int l1 = lb.x - j1;
-                l1 += l1 < 0 ? K1 : 0;
-                if ((unsigned)l1 < (unsigned)a1.z) atomicAdd(row + l1 * (a2.z * a3.z), w23 * w[j1]);
-            }
-        }
+        if (threadIdx.x == 0) nhit = 0;
         __syncthreads();
     }
-    const int zz = a2.z * a3.z;
-    for (int p = threadIdx.x; p < np; p += NB_PME_BLOCK) {
-        const int l1 = p / zz, rr = p - l1 * zz, l2 = rr / a3.z, l3 = rr - l2 * a3.z;
-        grid[((size_t)(a1.s + l1) * K2 + (a2.s + l2)) * K3 + (a3.s + l3)] = lg[p];
-    }
+    pme_walk wk((int)threadIdx.x, NB_PME_BLOCK, a2.z, a3.z);
+    for (int p = threadIdx.x; p < np; p += NB_PME_BLOCK, wk.next())
+        grid[(unsigned)(((a1.s + wk.l1) * K2 + (a2.s + wk.l2)) * K3 + (a3.s + wk.l3))] = lg[p];   // < 2^30
 }
 
 // c(m) <- G(m) c(m) over the half-complex grid; energy partial sum of G |c|^2 with the
@@ -431,7 +485,8 @@ __global__ void __launch_bounds__(NB_PME_BLOCK) k_pme_gather(int natoms, int K1,
     constexpr int CH = pme_chunk<N>::GATHER, R = pme_lanes<N>::R, APW = pme_lanes<N>::APW;
     constexpr int WAVES = NB_PME_BLOCK / 64;
     constexpr int RED = APW > 1 ? R : 64;   // reduction width, a power of two
-    extern __shared__ double lp[];          // staged potential, then CH x 6N spline data
+    constexpr int SD = 6 * N + 1;           // staged doubles per atom (odd: fewer bank conflicts)
+    extern __shared__ double lp[];          // staged potential, then CH x SD spline data
     __shared__ int4 ab[CH];                 // cells, charges and indices of the staged atoms
     __shared__ float aq[CH];
     __shared__ int ai[CH];
@@ -443,22 +498,52 @@ __global__ void __launch_bounds__(NB_PME_BLOCK) k_pme_gather(int natoms, int K1,
     if (c0 == c1) return;   // no atoms in this tile
     const int h1 = a1.z + N - 1, h2 = a2.z + N - 1, h3 = a3.z + N - 1, hh = h2 * h3;
     double *sd = lp + h1 * hh;
-    for (int p = threadIdx.x; p < h1 * hh; p += NB_PME_BLOCK) {
-        const int l1 = p / hh, r = p - l1 * hh, l2 = r / h3, l3 = r - l2 * h3;
-        int k1 = a1.s - (N - 1) + l1, k2 = a2.s - (N - 1) + l2, k3 = a3.s - (N - 1) + l3;
-        k1 += k1 < 0 ? K1 : 0;
-        k2 += k2 < 0 ? K2 : 0;
-        k3 += k3 < 0 ? K3 : 0;
-        lp[p] = phi[((size_t)k1 * K2 + k2) * K3 + k3];
+    {
+        // GU loads per thread issued together, then stored
+        constexpr int GU = 8;
+        const int nbox = h1 * hh;
+        pme_walk wk((int)threadIdx.x, NB_PME_BLOCK, h2, h3);
+        for (int p0 = 0; p0 < nbox; p0 += GU * NB_PME_BLOCK) {
+            double v[GU];
+#pragma unroll
+            for (int u = 0; u < GU; ++u) {
+                const int p = p0 + u * NB_PME_BLOCK + (int)threadIdx.x;
+                if (p < nbox) {
+                    int k1 = a1.s - (N - 1) + wk.l1, k2 = a2.s - (N - 1) + wk.l2, k3 = a3.s - (N - 1) + wk.l3;
+                    k1 += k1 < 0 ? K1 : 0;
+                    k2 += k2 < 0 ? K2 : 0;
+                    k3 += k3 < 0 ? K3 : 0;
+                    v[u] = phi[(unsigned)((k1 * K2 + k2) * K3 + k3)];   // K1 K2 K3 <= 2^30
+                }
+                wk.next();
+            }
+#pragma unroll
+            for (int u = 0; u < GU; ++u) {
+                const int p = p0 + u * NB_PME_BLOCK + (int)threadIdx.x;
+                if (p < nbox) lp[p] = v[u];
+            }
+        }
     }
     const pme_lanes<N> ln(threadIdx.x & 63);
     const int wave = threadIdx.x >> 6;
     for (int cb = c0; cb < c1; cb += CH) {
         const int nc = min(CH, c1 - cb);
         if (cb != c0) __syncthreads();   // previous pass done with the staged atoms
-        for (int e = threadIdx.x; e < nc * 6 * N; e += NB_PME_BLOCK) {
-            const int j = e / nc, a = e - j * nc;
-            sd[a * 6 * N + j] = sth[(size_t)j * natoms + cb + a];
+        {
+            // atom a = thread mod CH, rows j = thread / CH + k NB_PME_BLOCK / CH
+            constexpr int RS = NB_PME_BLOCK / CH, RU = (6 * N + RS - 1) / RS;
+            const int a = threadIdx.x % CH, j0 = threadIdx.x / CH;
+            double v[RU];
+#pragma unroll
+            for (int u = 0; u < RU; ++u) {
+                const int j = j0 + u * RS;
+                if (a < nc && j < 6 * N) v[u] = sth[(size_t)j * natoms + cb + a];
+            }
+#pragma unroll
+            for (int u = 0; u < RU; ++u) {
+                const int j = j0 + u * RS;
+                if (a < nc && j < 6 * N) sd[a * SD + j] = v[u];
+            }
         }
         if (threadIdx.x < nc) {
             ab[threadIdx.x] = sbase[cb + threadIdx.x];
@@ -472,7 +557,7 @@ __global__ void __launch_bounds__(NB_PME_BLOCK) k_pme_gather(int natoms, int K1,
             double gx = 0.0, gy = 0.0, gz = 0.0;
             if (live) {
                 const int4 kb = ab[s];
-                const double *th = sd + s * 6 * N;
+                const double *th = sd + s * SD;
                 const double *dh = th + 3 * N;
                 // local coordinates in the staged box: k_a - j - (s_a - (N - 1)), in 0 .. h_a - 1
                 // (the atom's own cell k_a lies in this tile)
@@ -596,11 +681,12 @@ int nb_pme_setup(nb_pme **out, const nb_pme_params *prm, void *stream) {
     }
     p->ntiles = p->nt[0] * p->nt[1] * p->nt[2];
     {
-        const int n = p->order, chs = n == 4 ? 256 : 128, chg = 64;   // candidates / atoms per pass
-        p->lds_spread = sizeof(double) * ((size_t)p->tmax[0] * p->tmax[1] * p->tmax[2] + (size_t)chs * 3 * n);
+        const int n = p->order, chs = n == 4 ? 256 : 128, chg = n == 8 ? 32 : 64;   // atoms per pass
+        p->lds_spread = sizeof(double) * ((size_t)p->tmax[0] * p->tmax[1] * p->tmax[2] + (size_t)chs * (3 * n + 1));
         p->lds_gather = sizeof(double) * ((size_t)(p->tmax[0] + n - 1) * (p->tmax[1] + n - 1) * (p->tmax[2] + n - 1) +
-                                          (size_t)chg * 6 * n);
-        if (p->lds_spread > 49152 || p->lds_gather > 65536) {
+                                          (size_t)chg * (6 * n + 1));
+        // 64 KiB per workgroup, less the static arrays (spread: candidate list of 8 KiB)
+        if (p->lds_spread > 65536 - 8448 || p->lds_gather > 65536 - 2048) {
             delete p;
             return pfail(nullptr, NB_ERR_ARG, "grid tiles exceed the LDS of a workgroup");
         }
