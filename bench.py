@@ -91,6 +91,10 @@ def parse():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-pme", action="store_true")
+    ap.add_argument("--prune-every", type=int, default=4,
+                    help="rolling-prune measurement: prune every this many calls (0: skip)")
+    ap.add_argument("--prune-inner", type=float, default=0.05,
+                    help="rolling-prune measurement: r_inner - rc (nm)")
     ap.add_argument("--no-tune", action="store_true", help="batched form with C = 8 everywhere")
     ap.add_argument("--energy-fp64", action="store_true",
                     help="evaluate Coulomb pair energies in FP64 (forces stay FP32)")
@@ -348,6 +352,51 @@ def main():
     # the last asynchronous build's status (raises NB_ERR_OVERFLOW if any list had overflowed)
     nb.nb_pairlist(ctx, traj[nsteps - 1])
 
+    # rolling prune: the same walk with the list pruned to rc + prune_inner every prune_every
+    # calls (valid while atoms move less than prune_inner / 2 between prunes: the walk moves
+    # them ~0.0035 nm per call)
+    prune = None
+    if args.prune_every > 0:
+        rin = inst.cutoff + args.prune_inner
+
+        def step_p(k):
+            if k % REBUILD_EVERY == 0:
+                nb.nb_pairlist(ctx, traj[k])
+            if k % args.prune_every == 0:
+                nb.nb_prune(ctx, traj[k], rin)
+            nb.nb_forces(ctx, traj[k], q, t, f, e)
+
+        for k in range(args.warmup):
+            step_p(k)
+        torch.cuda.synchronize()
+        tp = time.perf_counter()
+        for k in range(args.warmup, nsteps):
+            step_p(k)
+        torch.cuda.synchronize()
+        elapsed_p = time.perf_counter() - tp
+        nb.nb_pairlist(ctx, traj[nsteps - 1])
+        nb.nb_prune(ctx, traj[nsteps - 1], rin)
+        kept = nb.nb_get_stats(ctx)["nentries"]
+        reps = 100
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for k in range(reps):
+            nb.nb_prune(ctx, traj[nsteps - 1], rin)
+        ev1.record()
+        torch.cuda.synchronize()
+        us_prune = 1e3 * ev0.elapsed_time(ev1) / reps
+        ev0.record()
+        for k in range(reps):
+            nb.nb_forces(ctx, traj[nsteps - 1], q, t, f, e)
+        ev1.record()
+        torch.cuda.synchronize()
+        prune = {"r_inner": rin, "prune_every": args.prune_every,
+                 "pairs_per_s": useful * args.steps / elapsed_p,
+                 "us_per_call_amortised": 1e6 * elapsed_p / args.steps,
+                 "us_per_prune": us_prune,
+                 "us_per_force_call_pruned": 1e3 * ev0.elapsed_time(ev1) / reps,
+                 "list_entries_pruned": kept, "list_entries_full": stats["nentries"]}
+
     # force call alone (no rebuilds), event-timed on the current stream
     nb.nb_pairlist(ctx, traj[0])
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -437,6 +486,7 @@ def main():
         "us_per_force_call_with_ewald_corrections": us_force_corr,
         "us_per_list_build": us_build,
         "us_per_call_amortised": 1e3 * ms_per_step,
+        "rolling_prune": prune,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
                      "traffic": traffic, "kernel": "k_force", "kernel_us": kernel_us,

@@ -128,7 +128,7 @@ typedef struct nb_stats {
     int32_t work_units;                   /* force-kernel work units (parts of i-cluster lists) */
     int32_t unit_batches;                 /* 64-lane batches per work unit at most */
     int32_t max_list_batches;             /* longest i-cluster list, in 64-lane batches */
-    int32_t pad;
+    int32_t pruned;                       /* 1 if the force calls use a list from nb_prune */
 } nb_stats;
 
 typedef struct nb_ctx nb_ctx;
@@ -163,6 +163,19 @@ int nb_set_stream(nb_ctx *ctx, void *stream);
  * Errors: NB_ERR_ARG, NB_ERR_OVERFLOW (growing failed, or as above), NB_ERR_NONFINITE,
  * NB_ERR_HIP, NB_ERR_OOM. */
 int nb_pairlist(nb_ctx *ctx, const float *x_dev);
+
+/* Rolling (dynamic) prune of the list, the paper's prune-only kernel run between list builds
+ * (section III-A): from the full list of the last nb_pairlist (cluster pairs within
+ * rc + buffer at the build positions), keep for the following force calls only the j-groups
+ * that have an unmasked atom pair within r_inner at the current positions x_dev [natoms][3]
+ * (device).  rc <= r_inner <= rc + buffer.  Each call prunes the full list again, and the next
+ * nb_pairlist restores it.  The pruned list holds every pair within rc while every atom has
+ * moved less than (r_inner - rc)/2 since this call (and less than buffer/2 since the build);
+ * with NB_CHECK_STALE the force calls check the first condition too (nb_check reports
+ * NB_ERR_LIST_STALE).  Also rebuilds the force kernel's work units for the shorter lists.
+ * Asynchronous on the context's stream; allocates the pruned list on first use (and after the
+ * list has grown).  Errors: NB_ERR_ARG, NB_ERR_STATE (no list), NB_ERR_OOM, NB_ERR_HIP. */
+int nb_prune(nb_ctx *ctx, const float *x_dev, double r_inner);
 
 /* Forces and energies for device inputs x [natoms][3], q [natoms], type [natoms] (0-based
  * LJ type).  x must be the build positions or a continuous motion of them (no re-wrapping

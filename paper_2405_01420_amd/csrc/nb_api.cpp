@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <vector>
 
 #include "erfcx_rational.h"
@@ -215,7 +216,7 @@ void free_all(nb_ctx *c) {
                     c->tsort, c->units,  c->fj,     c->bblo,  c->bbhi,      c->icount,
                     c->jl,    c->epart,  c->meta,   c->ljtab, c->excl_off,  c->excl_idx,
                     c->dbg_pairs, c->adj, c->adjj, c->gs, c->tpart, c->excl_slot, c->etab,
-                    c->cpart, c->vpart};
+                    c->cpart, c->vpart, c->jl_p, c->icount_p, c->xprune};
     for (void *p : bufs)
         if (p) hipFree(p);
 }
@@ -443,6 +444,11 @@ int nb_pairlist(nb_ctx *c, const float *x) {
     if (!c || !x) return fail(c, NB_ERR_ARG, "NULL argument");
     hipSetDevice(c->device);
     c->have_list = false;
+    if (c->pruned) {   // the build writes the full list
+        std::swap(c->jl, c->jl_p);
+        std::swap(c->icount, c->icount_p);
+        c->pruned = false;
+    }
     auto t0 = std::chrono::steady_clock::now();
     // NB_ASYNC_BUILD: the status of the previous build was copied to pinned memory behind it
     // on the stream; that copy finished long before the force calls queued after the build,
@@ -500,11 +506,51 @@ int nb_pairlist(nb_ctx *c, const float *x) {
     return fail(c, NB_ERR_OVERFLOW, "pair list still overflowing after regrowing");
 }
 
+int nb_prune(nb_ctx *c, const float *x, double r_inner) {
+    if (!c || !x) return fail(c, NB_ERR_ARG, "NULL argument");
+    if (!(std::isfinite(r_inner) && r_inner >= c->rc && r_inner <= c->rc + c->rb * (1.0 + 1e-12)))
+        return fail(c, NB_ERR_ARG, "r_inner must be in [rc, rc + buffer]");
+    if (!c->have_list) return fail(c, NB_ERR_STATE, "nb_prune called before nb_pairlist");
+    hipSetDevice(c->device);
+    int r;
+    if (!c->pruned && c->jl_p_cap != c->cap) {   // room for the pruned list (the list may have grown)
+        if ((r = dalloc(c, &c->jl_p, (size_t)c->ncl_max * c->cap, "pruned pair list")) != NB_OK) return r;
+        c->jl_p_cap = c->cap;
+    }
+    if (!c->icount_p && (r = dalloc(c, &c->icount_p, (size_t)c->ncl_max, "pruned list lengths")) != NB_OK)
+        return r;
+    if ((c->flags & NB_CHECK_STALE) && !c->xprune &&
+        (r = dalloc(c, &c->xprune, 3 * (size_t)c->natoms, "prune positions")) != NB_OK)
+        return r;
+    // positions in cluster order, as the force calls form them (charges and types are packed
+    // again by the next force call)
+    hipError_t e = nb_launch_pack(c, x, nullptr, nullptr);
+    if (e != hipSuccess) return hip_fail(c, e, "prune: pack launch");
+    // the full list is jl / icount before the first prune after a build, jl_p / icount_p after it
+    const float rin = (float)r_inner;
+    e = c->pruned ? nb_launch_prune(c, x, rin * rin, c->icount_p, c->jl_p, c->icount, c->jl)
+                             : nb_launch_prune(c, x, rin * rin, c->icount, c->jl, c->icount_p, c->jl_p);
+    if (e != hipSuccess) return hip_fail(c, e, "prune launch");
+    if (!c->pruned) {
+        std::swap(c->jl, c->jl_p);
+        std::swap(c->icount, c->icount_p);
+        c->pruned = true;
+    }
+    if (c->flags & NB_CHECK_STALE) {
+        e = hipMemcpyAsync(c->xprune, x, sizeof(float) * 3 * (size_t)c->natoms, hipMemcpyDeviceToDevice, c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "save prune positions");
+        const double h = 0.5 * (r_inner - c->rc);
+        c->stale2_prune = (float)(h * h);
+    }
+    return NB_OK;
+}
+
 static int forces_impl(nb_ctx *c, const float *x, const float *q, const int32_t *type, float *f,
                        double *e, double *vir) {
     if (!c || !x || !q || !type || !f || !e) return fail(c, NB_ERR_ARG, "NULL argument");
     if (!c->have_list) return fail(c, NB_ERR_STATE, "nb_forces called before nb_pairlist");
     hipError_t err = nb_launch_pack(c, x, q, type);
+    if (err == hipSuccess && c->pruned && (c->flags & NB_CHECK_STALE)) err = nb_launch_prune_check(c, x);
     if (c->timing && err == hipSuccess) {
         const size_t kMaxPairs = 4096;
         if (c->ev_used == kMaxPairs) {
@@ -621,6 +667,7 @@ int nb_get_stats(nb_ctx *c, nb_stats *st) {
     st->work_units = m.nunits;
     st->unit_batches = m.split;
     st->max_list_batches = m.maxbatches;
+    st->pruned = c->pruned ? 1 : 0;
     return NB_OK;
 }
 

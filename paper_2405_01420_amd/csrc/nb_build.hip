@@ -691,6 +691,68 @@ __global__ void __launch_bounds__(256) k_pairs(nb_geom g, float rc2, int cap,
     }
 }
 
+// Rolling prune: the pruned list keeps the entries of the full list that have an unmasked atom
+// pair within r_inner at the current positions (the masks are kept as they are; the force
+// kernel still tests r < rc).  One wave per i-cluster with the lanes of the pair export (entry =
+// lane / 4, j-atom = lane % 4, the C i-atoms in a loop), on the positions the per-call pack has
+// just written (so the distances are the ones the force kernel sees).  Kept entries are
+// compacted in order with a ballot per batch.
+template <int C>
+__global__ void __launch_bounds__(256) k_prune(nb_geom g, float rin2, int cap, int ncl_max,
+                                               const float4 *__restrict__ xq,
+                                               const int *__restrict__ icount,
+                                               const nb_entry *__restrict__ jl,
+                                               int *__restrict__ icount_p,
+                                               nb_entry *__restrict__ jl_p, const nb_meta *meta) {
+    const int lane = threadIdx.x & (NB_WAVE - 1);
+    const int ci = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x / NB_WAVE) +
+                                                  threadIdx.x / NB_WAVE);
+    if (ci >= ncl_max) return;
+    if (ci >= meta->nclusters) {
+        if (lane == 0) icount_p[ci] = 0;
+        return;
+    }
+    float4 xi[C];
+#pragma unroll
+    for (int k = 0; k < C; ++k) xi[k] = xq[ci * C + k];
+    const int nj = icount[ci];
+    const int b = lane % NB_JG, eo = lane / NB_JG;
+    int kept = 0;
+    for (int base = 0; base < nj; base += NB_JPB) {   // wave-uniform
+        const int e = base + eo;
+        const nb_entry en = e < nj ? jl[(size_t)ci * cap + e] : nb_make_entry(0, NB_SHIFT_ZERO, 0u);
+        const int s = nb_entry_shift(en);
+        const int tx = nb_tx(s), ty = nb_ty(s), tz = nb_tz(s);
+        const float4 xj = xq[nb_entry_group(en) * NB_JG + b];
+        const float xjs = xj.x + nb_dj(tx, g.L[0]), yjs = xj.y + nb_dj(ty, g.L[1]), zjs = xj.z + nb_dj(tz, g.L[2]);
+        const float dix = nb_di(tx, g.L[0]), diy = nb_di(ty, g.L[1]), diz = nb_di(tz, g.L[2]);
+        const unsigned mcol = nb_mask_column<C>(en.mask, b);   // empty past the end of the list
+        bool hit = false;
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
+            const float dx = (xi[k].x + dix) - xjs, dy = (xi[k].y + diy) - yjs, dz = (xi[k].z + diz) - zjs;
+            hit |= ((mcol >> k) & 1u) && nb_r2(dx, dy, dz) < rin2;
+        }
+        const uint64_t m = __ballot(hit);
+        uint32_t em = 0;   // entries of this batch with a pair in range
+#pragma unroll
+        for (int q = 0; q < NB_JPB; ++q) em |= ((m >> (NB_JG * q)) & 0xFull) ? (1u << q) : 0u;
+        if (b == 0 && ((em >> eo) & 1u))
+            jl_p[(size_t)ci * cap + kept + __popc(em & ((1u << eo) - 1u))] = en;
+        kept += __popc(em);
+    }
+    if (lane == 0) icount_p[ci] = kept;
+}
+
+// Displacement check against the positions of the last prune ((r_inner - rc) / 2).
+__global__ void k_prune_check(int n, const float *__restrict__ x, const float *__restrict__ xp,
+                              float stale2, nb_meta *meta) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float d0 = x[3 * i] - xp[3 * i], d1 = x[3 * i + 1] - xp[3 * i + 1], d2 = x[3 * i + 2] - xp[3 * i + 2];
+    if (!(d0 * d0 + d1 * d1 + d2 * d2 < stale2)) atomicOr(&meta->flags, NB_F_STALE);
+}
+
 template <int C>
 hipError_t build_impl(nb_ctx *c, const float *x) {
     const int n = c->natoms;
@@ -741,4 +803,29 @@ hipError_t nb_launch_build(nb_ctx *c, const float *x) {
 
 hipError_t nb_launch_debug_pairs(nb_ctx *c, int64_t cap) {
     return c->C == 4 ? pairs_impl<4>(c, cap) : pairs_impl<8>(c, cap);
+}
+
+namespace {
+template <int C>
+hipError_t prune_impl(nb_ctx *c, const float *x, float rin2, const int *icount, const nb_entry *jl,
+                      int *icount_p, nb_entry *jl_p) {
+    // the work units of the build stay valid: each covers a batch range of its cluster's full
+    // list and the force kernel stops at the pruned list's end
+    hipLaunchKernelGGL((k_prune<C>), dim3((c->ncl_max + 3) / 4), dim3(256), 0, c->stream, c->geom, rin2,
+                       c->cap, c->ncl_max, c->xq, icount, jl, icount_p, jl_p, c->meta);
+    return hipGetLastError();
+}
+}  // namespace
+
+hipError_t nb_launch_prune(nb_ctx *c, const float *x, float rin2, const int *icount, const nb_entry *jl,
+                           int *icount_p, nb_entry *jl_p) {
+    return c->C == 4 ? prune_impl<4>(c, x, rin2, icount, jl, icount_p, jl_p)
+                     : prune_impl<8>(c, x, rin2, icount, jl, icount_p, jl_p);
+}
+
+hipError_t nb_launch_prune_check(nb_ctx *c, const float *x) {
+    const int tb = 256;
+    hipLaunchKernelGGL(k_prune_check, dim3((c->natoms + tb - 1) / tb), dim3(tb), 0, c->stream, c->natoms, x,
+                       c->xprune, c->stale2_prune, c->meta);
+    return hipGetLastError();
 }

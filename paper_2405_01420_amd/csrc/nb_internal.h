@@ -151,7 +151,16 @@ struct nb_ctx {
                                 // accumulated with atomics by the force kernel
     float4 *bblo = nullptr, *bbhi = nullptr;  // [ncl_max]
     int *icount = nullptr;      // [ncl_max]
-    nb_entry *jl = nullptr;     // [ncl_max * cap]
+    nb_entry *jl = nullptr;     // [ncl_max * cap] the list the force calls use
+    // rolling prune: while `pruned`, jl / icount hold the pruned list and jl_p / icount_p the
+    // build's full list (swapped back by the next build); jl_p has room for jl_p_cap entries
+    // per i-cluster
+    nb_entry *jl_p = nullptr;
+    int *icount_p = nullptr;
+    int jl_p_cap = 0;
+    bool pruned = false;
+    float *xprune = nullptr;    // [natoms*3] positions at the last prune (with NB_CHECK_STALE)
+    float stale2_prune = 0.0f;  // ((r_inner - rc) / 2)^2
     int4 *units = nullptr;      // [unit_cap] (i-cluster, first batch, batches, energy slot),
                                 // longest first
     double *epart = nullptr;    // [unit_cap * 4] energy partials (one per force workgroup used)
@@ -188,6 +197,9 @@ int nb_list_entries(nb_ctx *c, int nclusters, int64_t *total);  // sum of icount
 // ---- launchers (nb_build.hip) ----
 hipError_t nb_launch_build(nb_ctx *c, const float *x);
 hipError_t nb_launch_debug_pairs(nb_ctx *c, int64_t cap);
+hipError_t nb_launch_prune(nb_ctx *c, const float *x, float rin2, const int *icount, const nb_entry *jl,
+                           int *icount_p, nb_entry *jl_p);
+hipError_t nb_launch_prune_check(nb_ctx *c, const float *x);
 
 // ---- launchers (nb_force.hip) ----
 hipError_t nb_launch_pack(nb_ctx *c, const float *x, const float *q, const int32_t *type);

@@ -30,7 +30,7 @@ STATUS_NAMES = {0: "NB_OK", 1: "NB_ERR_ARG", 2: "NB_ERR_CUTOFF", 3: "NB_ERR_OOM"
                 5: "NB_ERR_STATE", 6: "NB_ERR_OVERFLOW", 7: "NB_ERR_LIST_STALE",
                 8: "NB_ERR_NONFINITE", 9: "NB_ERR_IO", 10: "NB_ERR_RANGE"}
 
-EXPORTS = ["nb_validate_params", "nb_setup", "nb_set_lj", "nb_set_stream", "nb_pairlist",
+EXPORTS = ["nb_validate_params", "nb_setup", "nb_set_lj", "nb_set_stream", "nb_pairlist", "nb_prune",
            "nb_forces", "nb_forces_virial", "nb_check", "nb_backward", "nb_debug_pairs", "nb_get_stats",
            "nb_last_error", "nb_destroy", "nb_set_timing", "nb_get_timing", "nb_batch_setup",
            "nb_batch_set_schedule", "nb_batch_pairlist", "nb_batch_forces",
@@ -59,7 +59,7 @@ class nb_stats(ctypes.Structure):
                 ("cluster", ctypes.c_int32), ("ncolumns", ctypes.c_int32),
                 ("build_ms_last", ctypes.c_double), ("work_units", ctypes.c_int32),
                 ("unit_batches", ctypes.c_int32), ("max_list_batches", ctypes.c_int32),
-                ("pad", ctypes.c_int32)]
+                ("pruned", ctypes.c_int32)]
 
 
 class nb_batch_info(ctypes.Structure):
@@ -100,6 +100,7 @@ def lib():
         L.nb_set_lj.argtypes = [_vp, _dp, _dp]
         L.nb_set_stream.argtypes = [_vp, _vp]
         L.nb_pairlist.argtypes = [_vp, _vp]
+        L.nb_prune.argtypes = [_vp, _vp, ctypes.c_double]
         L.nb_forces.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
         L.nb_forces_virial.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp]
         L.nb_check.argtypes = [_vp]
@@ -217,6 +218,11 @@ def nb_set_stream(ctx: int, stream=None) -> None:
 
 def nb_pairlist(ctx: int, x) -> None:
     _check(lib().nb_pairlist(ctx, _ptr(x)), ctx)
+
+
+def nb_prune(ctx: int, x, r_inner: float) -> None:
+    """Rolling prune of the last build's list to the pairs within r_inner at positions x."""
+    _check(lib().nb_prune(ctx, _ptr(x), ctypes.c_double(r_inner)), ctx)
 
 
 def nb_forces(ctx: int, x, q, types, f, e) -> None:

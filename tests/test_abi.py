@@ -31,6 +31,14 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, name), name
 
 
+def test_every_declared_function_has_argument_types():
+    """Without argtypes ctypes passes Python ints as 32-bit C ints, which truncates the context
+    pointers; every declared function gets explicit argument types."""
+    lib = nb.lib()
+    for name in declared_functions():
+        assert getattr(lib, name).argtypes is not None, name
+
+
 def test_binding_names_match_header():
     for name in declared_functions():
         assert hasattr(nb, name), name
