@@ -91,7 +91,7 @@ def parse():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-pme", action="store_true")
-    ap.add_argument("--prune-every", type=int, default=4,
+    ap.add_argument("--prune-every", type=int, default=0,
                     help="rolling-prune measurement: prune every this many calls (0: skip)")
     ap.add_argument("--prune-inner", type=float, default=0.05,
                     help="rolling-prune measurement: r_inner - rc (nm)")
