@@ -56,9 +56,9 @@ REBUILD_EVERY = 10
 # this digest and are reported only while the sources are unchanged.
 K_FORCE_COUNTERS = {
     "sources": ["nb_force_body.h", "nb_force.hip", "nb_device.h", "nb_internal.h", "erfcx_rational.h"],
-    "sha256": "caebc41575aae3b8448d1f9904233a92a4c396d8ee692e3d3e51d24b3cd59f43",
-    "read_bytes": 33.01e6, "write_bytes": 73.72e6,
-    "counted_fp32_flop": 73127958.2 * 64,
+    "sha256": "9847d9debaa3c734859b9c52d40af534d1e44f1ff27bb7f4a448052da2c71004",
+    "read_bytes": 32.94e6, "write_bytes": 73.72e6,
+    "counted_fp32_flop": 4680189322.5,
 }
 
 
