@@ -282,6 +282,19 @@ int nb_batch_setup(nb_batch **out, int32_t nbox, const int32_t *atom_off, const 
  * (0 = as many as fit). Invalidates a captured graph. */
 int nb_batch_set_schedule(nb_batch *bt, int32_t sorted, int32_t blocks_per_cu);
 
+/* Schedule autotuner on the batch's own data (the order of the work decides the tail of the
+ * kernel, the effect the paper's list sorting addresses, section III-A): times nb_batch_forces for each of the
+ * NB_BATCH_NSCHED candidate schedules, in this order: sorted with as many blocks as fit, sorted
+ * with 1, 2 and 4 blocks per compute unit, box order with as many blocks as fit (2 warm-up and
+ * reps timed calls each, HIP events on the batch stream), then applies the fastest.  Inputs as
+ * for nb_batch_forces (f and e are overwritten by the timed calls); us_out: host
+ * [NB_BATCH_NSCHED] microseconds per call, or NULL; best: host [2] (sorted, blocks_per_cu) of
+ * the chosen schedule, or NULL.  Needs a list (nb_batch_pairlist); synchronises.
+ * Errors: NB_ERR_ARG (NULL input, reps < 1), NB_ERR_STATE, NB_ERR_HIP. */
+#define NB_BATCH_NSCHED 5
+int nb_batch_tune_schedule(nb_batch *bt, const float *x, const float *q, const int32_t *type, float *f,
+                           double *e, int32_t reps, double *us_out, int32_t *best);
+
 /* Build every box's pair list from device coordinates x [natoms][3] (concatenated), then the
  * work list.  Synchronises (overflow checks, work-list upload). Not capturable. */
 int nb_batch_pairlist(nb_batch *bt, const float *x_dev);

@@ -527,6 +527,51 @@ int nb_batch_forces(nb_batch *bt, const float *x, const float *q, const int32_t 
     return NB_OK;
 }
 
+int nb_batch_tune_schedule(nb_batch *bt, const float *x, const float *q, const int32_t *type, float *f,
+                           double *e, int32_t reps, double *us_out, int32_t *best) {
+    if (!bt || !x || !q || !type || !f || !e || reps < 1) return bfail(bt, NB_ERR_ARG, "bad argument");
+    if (!bt->have_list) return bfail(bt, NB_ERR_STATE, "nb_batch_tune_schedule before nb_batch_pairlist");
+    hipSetDevice(bt->device);
+    // candidates: cost-sorted items with a persistent grid of as many blocks as fit, or 1, 2, 4
+    // blocks per compute unit; items in box order with as many blocks as fit
+    static const int32_t cand[NB_BATCH_NSCHED][2] = {{1, 0}, {1, 1}, {1, 2}, {1, 4}, {0, 0}};
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    if (hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess) {
+        if (ev[0]) hipEventDestroy(ev[0]);
+        return bfail(bt, NB_ERR_HIP, "hipEventCreate");
+    }
+    int r = NB_OK, pick = 0;
+    double us[NB_BATCH_NSCHED], best_us = 0.0;
+    for (int k = 0; k < NB_BATCH_NSCHED && r == NB_OK; ++k) {
+        if ((r = nb_batch_set_schedule(bt, cand[k][0], cand[k][1])) != NB_OK) break;
+        for (int w = 0; w < 2 && r == NB_OK; ++w) r = nb_batch_forces(bt, x, q, type, f, e);
+        if (r != NB_OK) break;
+        hipError_t err = hipEventRecord(ev[0], bt->stream);
+        for (int i = 0; i < reps && r == NB_OK; ++i) r = nb_batch_forces(bt, x, q, type, f, e);
+        if (err == hipSuccess) err = hipEventRecord(ev[1], bt->stream);
+        float ms = 0.0f;
+        if (err == hipSuccess) err = hipEventSynchronize(ev[1]);
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, ev[0], ev[1]);
+        if (r == NB_OK && err != hipSuccess) r = bfail(bt, NB_ERR_HIP, std::string("schedule timing: ") + hipGetErrorString(err));
+        us[k] = 1e3 * ms / reps;
+        if (r == NB_OK && (k == 0 || us[k] < best_us)) {
+            best_us = us[k];
+            pick = k;
+        }
+    }
+    hipEventDestroy(ev[0]);
+    hipEventDestroy(ev[1]);
+    if (r != NB_OK) return r;
+    if ((r = nb_batch_set_schedule(bt, cand[pick][0], cand[pick][1])) != NB_OK) return r;
+    if (us_out)
+        for (int k = 0; k < NB_BATCH_NSCHED; ++k) us_out[k] = us[k];
+    if (best) {
+        best[0] = cand[pick][0];
+        best[1] = cand[pick][1];
+    }
+    return NB_OK;
+}
+
 int nb_batch_graph_forces(nb_batch *bt, const float *x, const float *q, const int32_t *type,
                           float *f, double *e) {
     if (!bt || !x || !q || !type || !f || !e) return bfail(bt, NB_ERR_ARG, "NULL argument");

@@ -33,7 +33,7 @@ STATUS_NAMES = {0: "NB_OK", 1: "NB_ERR_ARG", 2: "NB_ERR_CUTOFF", 3: "NB_ERR_OOM"
 EXPORTS = ["nb_validate_params", "nb_setup", "nb_set_lj", "nb_set_stream", "nb_pairlist", "nb_prune",
            "nb_forces", "nb_forces_virial", "nb_check", "nb_backward", "nb_debug_pairs", "nb_get_stats",
            "nb_last_error", "nb_destroy", "nb_set_timing", "nb_get_timing", "nb_batch_setup",
-           "nb_batch_set_schedule", "nb_batch_pairlist", "nb_batch_forces",
+           "nb_batch_set_schedule", "nb_batch_tune_schedule", "nb_batch_pairlist", "nb_batch_forces",
            "nb_batch_graph_forces", "nb_batch_get_info", "nb_batch_check", "nb_batch_last_error",
            "nb_batch_destroy", "nb_pme_setup", "nb_pme_forces", "nb_pme_last_error", "nb_pme_destroy"]
 
@@ -113,6 +113,7 @@ def lib():
         L.nb_set_timing.argtypes = [_vp, ci]
         L.nb_batch_setup.argtypes = [P(_vp), ctypes.c_int32, _vp, _vp, _vp, P(nb_params), _vp]
         L.nb_batch_set_schedule.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32]
+        L.nb_batch_tune_schedule.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_int32, _dp, _ip]
         L.nb_batch_pairlist.argtypes = [_vp, _vp]
         L.nb_batch_forces.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
         L.nb_batch_graph_forces.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
@@ -306,6 +307,21 @@ def nb_batch_setup(atom_off, boxes, common: Params, clusters=None, stream=None) 
 
 def nb_batch_set_schedule(bt: int, sorted: bool = True, blocks_per_cu: int = 0) -> None:
     _bcheck(lib().nb_batch_set_schedule(bt, int(bool(sorted)), int(blocks_per_cu)), bt)
+
+
+NB_BATCH_NSCHED = 5
+# the candidate schedules of nb_batch_tune_schedule, in its order: (sorted, blocks_per_cu)
+BATCH_SCHEDULES = [(True, 0), (True, 1), (True, 2), (True, 4), (False, 0)]
+
+
+def nb_batch_tune_schedule(bt: int, x, q, types, f, e, reps: int = 5):
+    """Times the candidate schedules on the batch's data and applies the fastest; returns
+    ((sorted, blocks_per_cu), {schedule: us per call})."""
+    us = (ctypes.c_double * NB_BATCH_NSCHED)()
+    best = (ctypes.c_int32 * 2)()
+    _bcheck(lib().nb_batch_tune_schedule(bt, _ptr(x), _ptr(q), _ptr(types), _ptr(f), _ptr(e), int(reps),
+                                         ctypes.cast(us, _dp), ctypes.cast(best, _ip)), bt)
+    return (bool(best[0]), int(best[1])), {s: us[k] for k, s in enumerate(BATCH_SCHEDULES)}
 
 
 def nb_batch_pairlist(bt: int, x) -> None:

@@ -4,7 +4,8 @@ For every size bucket (logarithmic buckets of the box atom count) the tuner buil
 that bucket's boxes once per candidate cluster size (4 or 8 atoms), times the batched force
 call on the GPU and keeps the fastest shape.  With the per-box shapes fixed it then times the
 schedules of the persistent kernel (work items sorted by cost or in box order; persistent grid
-of 1, 2, 4 blocks per compute unit or as many as fit) on the whole batch.  Decisions are cached
+of 1, 2, 4 blocks per compute unit or as many as fit) on the whole batch, in the library
+(nb_batch_tune_schedule).  Decisions are cached
 in a JSON file keyed by GPU architecture, HIP version, cutoff and bucket, so a later run with the
 same kind of boxes reuses them without timing.  Timing uses torch CUDA events on the batch's
 stream around repeated calls; the tuner itself does no force arithmetic.
@@ -22,7 +23,6 @@ import numpy as np
 from . import nb
 
 CLUSTERS = (4, 8)
-SCHEDULES = [(True, 0), (True, 1), (True, 2), (True, 4), (False, 0)]
 
 
 def bucket_edges(nmin: int = 3000, nmax: int = 30000, nbuckets: int = 5) -> List[float]:
@@ -72,6 +72,25 @@ def _time_batch(torch, insts, clusters, sorted_=True, blocks_per_cu=0, reps=10, 
         nb.nb_batch_destroy(bt)
 
 
+def _tune_schedule(torch, insts, clusters, stream, reps=5):
+    """One batch with the chosen shapes; the library times the candidate schedules on it
+    (nb_batch_tune_schedule) and keeps the fastest."""
+    ao, bx, params, x, q, t = nb.concat_instances(insts, clusters=clusters)
+    bt = nb.nb_batch_setup(ao, bx, params, clusters=list(clusters), stream=stream.cuda_stream)
+    try:
+        with torch.cuda.stream(stream):
+            dx = torch.from_numpy(x.reshape(-1)).to("cuda:0")
+            dq = torch.from_numpy(q).to("cuda:0")
+            dt = torch.from_numpy(t).to("cuda:0")
+            f = torch.empty(len(q) * 3, dtype=torch.float32, device="cuda:0")
+            e = torch.empty(2 * len(insts), dtype=torch.float64, device="cuda:0")
+        stream.synchronize()
+        nb.nb_batch_pairlist(bt, dx)
+        return nb.nb_batch_tune_schedule(bt, dx, dq, dt, f, e, reps)
+    finally:
+        nb.nb_batch_destroy(bt)
+
+
 def autotune(insts, cache_path: Optional[str] = None, max_boxes_per_bucket: int = 16,
              edges: Optional[Sequence[float]] = None, verbose: bool = False) -> Dict:
     """Returns {"clusters": [C per box], "sorted": bool, "blocks_per_cu": int, "tune_s": seconds,
@@ -114,10 +133,7 @@ def autotune(insts, cache_path: Optional[str] = None, max_boxes_per_bucket: int 
     if skey in cache:
         sorted_, bpc = cache[skey]["sorted"], cache[skey]["blocks_per_cu"]
     else:
-        stimes = {}
-        for srt, bpc in SCHEDULES:
-            stimes[(srt, bpc)] = _time_batch(torch, insts, clusters, srt, bpc, reps=5, stream=stream)
-        sorted_, bpc = min(stimes, key=stimes.get)
+        (sorted_, bpc), stimes = _tune_schedule(torch, insts, clusters, stream)
         cache[skey] = {"sorted": sorted_, "blocks_per_cu": bpc,
                        "us": {f"sorted={s},bpc={b}": v for (s, b), v in stimes.items()}}
         if verbose:

@@ -149,3 +149,14 @@ def test_invalid_pme_parameters_are_rejected(kw):
         nb.nb_pme_setup(nb.pme_params(**args), stream=0)  # rejected before any device call
     assert ei.value.code == nb.NB_ERR_ARG
     assert nb.nb_pme_last_error(None) != ""
+
+
+def test_tuner_size_buckets():
+    """Host logic of the autotuner: logarithmic buckets over 3,000-30,000 atoms; sizes outside
+    fall into the first and last buckets."""
+    from paper_2405_01420_amd import tune
+    e = tune.bucket_edges(3000, 30000, 5)
+    assert len(e) == 6 and abs(e[0] - 3000) < 1e-9 and abs(e[-1] - 30000) < 1e-6
+    assert all(abs(e[k + 1] / e[k] - 10 ** 0.2) < 1e-12 for k in range(5))
+    assert tune.bucket_of(100, e) == 0 and tune.bucket_of(3000, e) == 0
+    assert tune.bucket_of(4800, e) == 1 and tune.bucket_of(29999, e) == 4 and tune.bucket_of(10 ** 6, e) == 4
