@@ -259,6 +259,53 @@ def bench_pme(torch, nb, synth, reps=50):
             "us_per_call": 1e3 * ev0.elapsed_time(ev1) / reps}
 
 
+def bench_ewald_step(torch, nb, synth, reps=50):
+    """The complete Ewald force step of the 96k-atom box: real space with the exclusion
+    correction and self term (nb_forces, NB_EWALD_CORR) and the reciprocal part (nb_pme_forces,
+    96^3 grid, order 4).  Timed one after the other, and with the two on separate streams
+    (default priority) joined at the end of every step, the way an MD step would overlap them."""
+    inst = synth.mid()
+    dev = "cuda:0"
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    ctx = nb.nb_setup(nb.Params.from_instance(inst, flags=nb.NB_EWALD_CORR), stream=s1.cuda_stream)
+    pm = nb.nb_pme_setup(nb.pme_params(inst.box, inst.beta, inst.coulomb_const, (96, 96, 96), 4, inst.natoms),
+                         stream=s2.cuda_stream)
+    with torch.cuda.stream(s1):
+        x = torch.from_numpy(inst.x.reshape(-1)).to(dev)
+        q = torch.from_numpy(inst.q).to(dev)
+        t = torch.from_numpy(inst.type).to(dev)
+        fr = torch.zeros(inst.natoms * 3, dtype=torch.float32, device=dev)
+        fk = torch.zeros(inst.natoms * 3, dtype=torch.float32, device=dev)
+        er = torch.zeros(4, dtype=torch.float64, device=dev)
+        ek = torch.zeros(1, dtype=torch.float64, device=dev)
+    s1.synchronize()
+    nb.nb_pairlist(ctx, x)
+
+    def step(overlap):
+        s2.wait_stream(s1)          # the step's inputs are ready on s1
+        nb.nb_forces(ctx, x, q, t, fr, er)
+        if not overlap:
+            s2.wait_stream(s1)
+        nb.nb_pme_forces(pm, x, q, fk, ek)
+        s1.wait_stream(s2)          # both parts done before the next step
+
+    out = {"workload": "96k-atom water box: real-space Ewald + exclusion correction + self term, "
+                       "smooth PME 96^3 order 4 (FP64)"}
+    for name, overlap in (("us_per_step_serial", False), ("us_per_step_two_streams", True)):
+        for _ in range(3):
+            step(overlap)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(s1)
+        for _ in range(reps):
+            step(overlap)
+        ev1.record(s1)
+        torch.cuda.synchronize()
+        out[name] = 1e3 * ev0.elapsed_time(ev1) / reps
+    nb.nb_pme_destroy(pm)
+    nb.nb_destroy(ctx)
+    return out
+
+
 def bench_large(torch, nb, synth, reps=20, warmup=3):
     """3,000,000-atom box (rc 1.2 nm, 5 LJ types): median and IQR of single force calls."""
     import numpy as np
@@ -497,6 +544,7 @@ def main():
         out["adjoint"] = bench_adjoint(torch, nb, synth)
     if not args.no_pme:
         out["pme"] = bench_pme(torch, nb, synth)
+        out["ewald_step"] = bench_ewald_step(torch, nb, synth)
     if not args.no_batch:
         out["batched"] = bench_batched(torch, nb, synth, not args.no_tune)
     if args.large:
