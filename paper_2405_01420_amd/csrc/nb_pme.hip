@@ -11,17 +11,18 @@
 //   E_rec = 1/2 sum_m G(m) |FFT(Q)(m)|^2, F_i = -q_i sum over the atom's grid points of
 //   grad(weights) phi.
 //
-// MI355X layout.  The grid is cut into tiles of about 8^3 points; a per-atom pass computes the
-// spline weights and derivatives once (FP64, kept for the gather) and bins the atoms by the tile
-// of their own grid cell (counts, one-block scan, placement).  The spread runs one workgroup per
-// tile: it accumulates, with FP64 LDS atomics, the contributions of the atoms of its own and the
-// next tile along each axis that land on its points, and stores the finished tile with plain
-// coalesced writes, so the grid needs no clearing and sees no global atomics (every point has one
-// owner).  The gather runs one workgroup per tile as well: it stages the tile's potential plus a
-// halo of n - 1 points below it in LDS and gives each of its atoms n^2 lanes, one per grid row,
-// reduced in a fixed order (deterministic forces, FP64 sums, FP32 output).  The grid and both FFTs
-// are FP64 (hipFFT, D2Z / Z2D); the solve runs over the half-complex grid and keeps per-block
-// FP64 energy partials that one block adds in a fixed order.
+// MI355X layout.  The grid is cut into tiles of about 8^3 points; the atoms are binned by the
+// tile of their own grid cell (counts, one-block scan) and placed in tile order with their
+// coordinates and charge.  The spread runs one workgroup per tile: it lists the atoms of its own
+// and the next tile along each axis that reach its points, computes their FP64 spline weights into
+// LDS, accumulates their contributions with FP64 LDS atomics and stores the finished tile with
+// plain coalesced writes, so the grid needs no clearing and sees no global atomics (every point
+// has one owner).  The gather runs one workgroup per tile as well: it stages the tile's potential
+// plus a halo of n - 1 points below it and the spline weights and derivatives of its atoms in LDS,
+// and gives each atom n^2 lanes, one per grid row, reduced in a fixed order (deterministic forces,
+// FP64 sums, FP32 output).  The grid and both FFTs are FP64 (hipFFT, D2Z / Z2D); the solve runs
+// over the half-complex grid and keeps per-block FP64 energy partials that one block adds in a
+// fixed order.
 #include <hip/hip_runtime.h>
 #include <hipfft/hipfft.h>
 
@@ -58,12 +59,10 @@ struct nb_pme {
     int *toff = nullptr;           // [ntiles + 1] first atom of each tile in tatoms
     int4 *abase = nullptr;         // [natoms] own grid cell (k1, k2, k3) and tile of each atom
     int *arank = nullptr;          // [natoms] rank of the atom within its tile
-    // atoms in tile order: index, cell, charge and spline data ([6 order][natoms]: weights of the
-    // three axes, then derivatives)
+    // atoms in tile order: index, cell, coordinates and charge
     int *sidx = nullptr;
     int4 *sbase = nullptr;
-    float *sq = nullptr;
-    double *sth = nullptr;
+    float4 *sxq = nullptr;
     hipfftHandle fwd = 0, bwd = 0;
     bool have_fwd = false, have_bwd = false;
     std::string err;
@@ -202,38 +201,23 @@ __global__ void __launch_bounds__(NB_PME_SCAN) k_pme_scan(int n, int *__restrict
     if (threadIdx.x == NB_PME_SCAN - 1) off[n] = run;
 }
 
-// Placement in tile order, with the spline data computed on the way: slot c = toff[tile] + rank
-// receives the atom index, its cell, its charge and, in rows of natoms (structure of arrays), the
-// weights M_n(w_a + j) (rows a N + j) and their derivatives (rows 3 N + a N + j).
-template <int N>
-__global__ void __launch_bounds__(NB_PME_BLOCK) k_pme_place(int natoms, int K1, int K2, int K3, double L1,
-                                                             double L2, double L3, const float *__restrict__ x,
+// Placement in tile order: slot c = toff[tile] + rank receives the atom index, its cell and its
+// coordinates with its charge (x, y, z, q); the spread and the gather compute the spline data of
+// the atoms they stage from these.
+__global__ void __launch_bounds__(NB_PME_BLOCK) k_pme_place(int natoms, const float *__restrict__ x,
                                                              const float *__restrict__ q,
                                                              const int4 *__restrict__ abase,
                                                              const int *__restrict__ arank,
                                                              const int *__restrict__ toff,
                                                              int *__restrict__ sidx, int4 *__restrict__ sbase,
-                                                             float *__restrict__ sq, double *__restrict__ sth) {
+                                                             float4 *__restrict__ sxq) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= natoms) return;
     const int4 kb = abase[i];
     const int c = toff[kb.w] + arank[i];
     sidx[c] = i;
     sbase[c] = kb;
-    sq[c] = q[i];
-    const int K[3] = {K1, K2, K3};
-    const double L[3] = {L1, L2, L3};
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        double w, v[N], d[N];
-        pme_cell(x[3 * i + a], L[a], K[a], w);
-        pme_bspline<N>(w, v, d);
-#pragma unroll
-        for (int j = 0; j < N; ++j) {
-            sth[(size_t)(a * N + j) * natoms + c] = v[j];
-            sth[(size_t)(3 * N + a * N + j) * natoms + c] = d[j];
-        }
-    }
+    sxq[c] = make_float4(x[3 * i], x[3 * i + 1], x[3 * i + 2], q[i]);
 }
 
 // Lanes of a wave: N^2 per atom, lane (j2, j3) with j3 fastest, so that the N^2 lanes of an atom
@@ -294,11 +278,10 @@ struct pme_walk {
 // are then staged in LDS, SPREAD at a time, and the waves add their contributions to the tile
 // with LDS atomics.
 template <int N>
-__global__ void __launch_bounds__(NB_PME_BLOCK) k_pme_spread(int natoms, int K1, int K2, int K3, int nt1,
-                                                              int nt2, int nt3,
+__global__ void __launch_bounds__(NB_PME_BLOCK) k_pme_spread(int K1, int K2, int K3, int nt1, int nt2, int nt3,
+                                                              double L1, double L2, double L3,
                                                               const int4 *__restrict__ sbase,
-                                                              const float *__restrict__ sq,
-                                                              const double *__restrict__ sth,
+                                                              const float4 *__restrict__ sxq,
                                                               const int *__restrict__ toff,
                                                               double *__restrict__ grid) {
     constexpr int CF = pme_chunk<N>::FILTER, CH = pme_chunk<N>::SPREAD;
@@ -384,15 +367,20 @@ __global__ void __launch_bounds__(NB_PME_BLOCK) k_pme_spread(int natoms, int K1,
         const int nh = nhit;
         for (int h0 = 0; h0 < nh; h0 += CH) {
             const int nc = min(CH, nh - h0);
-            if (threadIdx.x < nc) {
-                const int c = hit[h0 + threadIdx.x].x;
-                const double qi = sq[c];
-                double v[3 * N];
-#pragma unroll
-                for (int j = 0; j < 3 * N; ++j) v[j] = sth[(size_t)j * natoms + c];
+            if (threadIdx.x < nc) {   // weights of the listed atom, the first axis scaled by q
+                const float4 p = sxq[hit[h0 + threadIdx.x].x];
                 double *w = wt + threadIdx.x * WS;
+                const float xa[3] = {p.x, p.y, p.z};
+                const double La[3] = {L1, L2, L3};
+                const int Ka[3] = {K1, K2, K3};
 #pragma unroll
-                for (int j = 0; j < 3 * N; ++j) w[j] = j < N ? qi * v[j] : v[j];
+                for (int a = 0; a < 3; ++a) {
+                    double u, v[N], d[N];
+                    pme_cell(xa[a], La[a], Ka[a], u);
+                    pme_bspline<N>(u, v, d);
+#pragma unroll
+                    for (int j = 0; j < N; ++j) w[a * N + j] = a == 0 ? (double)p.w * v[j] : v[j];
+                }
             }
             __syncthreads();
             for (int g = wave * APW; g < nc; g += WAVES * APW) {
@@ -473,12 +461,11 @@ __global__ void __launch_bounds__(NB_PME_BLOCK) k_pme_energy(int nblk, const dou
 // pass; each atom gets N^2 lanes (same layout as the spread), each summing its N points along the
 // first axis, and the lanes of an atom are reduced in a fixed order (deterministic forces).
 template <int N>
-__global__ void __launch_bounds__(NB_PME_BLOCK) k_pme_gather(int natoms, int K1, int K2, int K3, int nt1,
-                                                              int nt2, int nt3, double L1, double L2, double L3,
+__global__ void __launch_bounds__(NB_PME_BLOCK) k_pme_gather(int K1, int K2, int K3, int nt1, int nt2, int nt3,
+                                                              double L1, double L2, double L3,
                                                               const int *__restrict__ sidx,
                                                               const int4 *__restrict__ sbase,
-                                                              const float *__restrict__ sq,
-                                                              const double *__restrict__ sth,
+                                                              const float4 *__restrict__ sxq,
                                                               const int *__restrict__ toff,
                                                               const double *__restrict__ phi,
                                                               float *__restrict__ f) {
@@ -529,25 +516,28 @@ __global__ void __launch_bounds__(NB_PME_BLOCK) k_pme_gather(int natoms, int K1,
     for (int cb = c0; cb < c1; cb += CH) {
         const int nc = min(CH, c1 - cb);
         if (cb != c0) __syncthreads();   // previous pass done with the staged atoms
-        {
-            // atom a = thread mod CH, rows j = thread / CH + k NB_PME_BLOCK / CH
-            constexpr int RS = NB_PME_BLOCK / CH, RU = (6 * N + RS - 1) / RS;
-            const int a = threadIdx.x % CH, j0 = threadIdx.x / CH;
-            double v[RU];
+        // spline weights and derivatives of the staged atoms, one (atom, axis) per thread
+        for (int e = threadIdx.x; e < 3 * CH; e += NB_PME_BLOCK) {
+            const int a = e % CH, ax = e / CH;
+            if (a < nc) {
+                const float4 p = sxq[cb + a];
+                const float xa = ax == 0 ? p.x : (ax == 1 ? p.y : p.z);
+                const double La = ax == 0 ? L1 : (ax == 1 ? L2 : L3);
+                const int Ka = ax == 0 ? K1 : (ax == 1 ? K2 : K3);
+                double u, v[N], d[N];
+                pme_cell(xa, La, Ka, u);
+                pme_bspline<N>(u, v, d);
+                double *th = sd + a * SD;
 #pragma unroll
-            for (int u = 0; u < RU; ++u) {
-                const int j = j0 + u * RS;
-                if (a < nc && j < 6 * N) v[u] = sth[(size_t)j * natoms + cb + a];
-            }
-#pragma unroll
-            for (int u = 0; u < RU; ++u) {
-                const int j = j0 + u * RS;
-                if (a < nc && j < 6 * N) sd[a * SD + j] = v[u];
+                for (int j = 0; j < N; ++j) {
+                    th[ax * N + j] = v[j];
+                    th[3 * N + ax * N + j] = d[j];
+                }
             }
         }
         if (threadIdx.x < nc) {
             ab[threadIdx.x] = sbase[cb + threadIdx.x];
-            aq[threadIdx.x] = sq[cb + threadIdx.x];
+            aq[threadIdx.x] = sxq[cb + threadIdx.x].w;
             ai[threadIdx.x] = sidx[cb + threadIdx.x];
         }
         __syncthreads();   // staged potential and atoms ready
@@ -636,7 +626,7 @@ void pme_free(nb_pme *p) {
     if (p->have_fwd) hipfftDestroy(p->fwd);
     if (p->have_bwd) hipfftDestroy(p->bwd);
     void *bufs[] = {p->grid, p->cgrid, p->infl, p->part, p->tcount, p->toff, p->abase, p->arank,
-                    p->sidx, p->sbase, p->sq, p->sth};
+                    p->sidx, p->sbase, p->sxq};
     for (void *b : bufs)
         if (b) hipFree(b);
 }
@@ -698,8 +688,7 @@ int nb_pme_setup(nb_pme **out, const nb_pme_params *prm, void *stream) {
         (r = palloc(p, &p->arank, (size_t)p->natoms, "atom ranks")) != NB_OK ||
         (r = palloc(p, &p->sidx, (size_t)p->natoms, "sorted atoms")) != NB_OK ||
         (r = palloc(p, &p->sbase, (size_t)p->natoms, "sorted cells")) != NB_OK ||
-        (r = palloc(p, &p->sq, (size_t)p->natoms, "sorted charges")) != NB_OK ||
-        (r = palloc(p, &p->sth, (size_t)p->natoms * 6 * p->order, "spline data")) != NB_OK ||
+        (r = palloc(p, &p->sxq, (size_t)p->natoms, "sorted coordinates")) != NB_OK ||
         (r = palloc(p, &p->grid, p->nreal, "grid")) != NB_OK ||
         (r = palloc(p, &p->cgrid, p->ncplx, "transform")) != NB_OK ||
         (r = palloc(p, &p->infl, 2 * p->ncplx, "influence function")) != NB_OK ||
@@ -763,20 +752,14 @@ int nb_pme_forces(nb_pme *p, const float *x, const float *q, float *f, double *e
     hipLaunchKernelGGL(k_pme_bin, dim3(ab), dim3(NB_PME_BLOCK), 0, p->stream, p->natoms, K1, K2, K3, p->nt[0],
                        p->nt[1], p->nt[2], p->L[0], p->L[1], p->L[2], x, p->abase, p->arank, p->tcount);
     hipLaunchKernelGGL(k_pme_scan, dim3(1), dim3(NB_PME_SCAN), 0, p->stream, p->ntiles, p->tcount, p->toff);
-#define NB_PME_PLACE(N)                                                                                \
-    hipLaunchKernelGGL(k_pme_place<N>, dim3(ab), dim3(NB_PME_BLOCK), 0, p->stream, p->natoms, K1, K2, K3, \
-                       p->L[0], p->L[1], p->L[2], x, q, p->abase, p->arank, p->toff, p->sidx, p->sbase,   \
-                       p->sq, p->sth)
 #define NB_PME_SPREAD(N)                                                                                      \
-    hipLaunchKernelGGL(k_pme_spread<N>, dim3(p->ntiles), dim3(NB_PME_BLOCK), lds_spread, p->stream, p->natoms, \
-                       K1, K2, K3, p->nt[0], p->nt[1], p->nt[2], p->sbase, p->sq, p->sth, p->toff, p->grid)
-    if (n == 4) NB_PME_PLACE(4);
-    else if (n == 6) NB_PME_PLACE(6);
-    else NB_PME_PLACE(8);
+    hipLaunchKernelGGL(k_pme_spread<N>, dim3(p->ntiles), dim3(NB_PME_BLOCK), lds_spread, p->stream, K1, K2, K3, \
+                       p->nt[0], p->nt[1], p->nt[2], p->L[0], p->L[1], p->L[2], p->sbase, p->sxq, p->toff, p->grid)
+    hipLaunchKernelGGL(k_pme_place, dim3(ab), dim3(NB_PME_BLOCK), 0, p->stream, p->natoms, x, q, p->abase,
+                       p->arank, p->toff, p->sidx, p->sbase, p->sxq);
     if (n == 4) NB_PME_SPREAD(4);
     else if (n == 6) NB_PME_SPREAD(6);
     else NB_PME_SPREAD(8);
-#undef NB_PME_PLACE
 #undef NB_PME_SPREAD
     if (hipGetLastError() != hipSuccess) return pfail(p, NB_ERR_HIP, "spread launch");
     if (hipfftExecD2Z(p->fwd, (hipfftDoubleReal *)p->grid, (hipfftDoubleComplex *)p->cgrid) != HIPFFT_SUCCESS)
@@ -788,9 +771,9 @@ int nb_pme_forces(nb_pme *p, const float *x, const float *q, float *f, double *e
     if (hipfftExecZ2D(p->bwd, (hipfftDoubleComplex *)p->cgrid, (hipfftDoubleReal *)p->grid) != HIPFFT_SUCCESS)
         return pfail(p, NB_ERR_HIP, "inverse FFT");
 #define NB_PME_GATHER(N)                                                                                      \
-    hipLaunchKernelGGL(k_pme_gather<N>, dim3(p->ntiles), dim3(NB_PME_BLOCK), lds_gather, p->stream, p->natoms, \
-                       K1, K2, K3, p->nt[0], p->nt[1], p->nt[2], p->L[0], p->L[1], p->L[2], p->sidx, p->sbase, \
-                       p->sq, p->sth, p->toff, p->grid, f)
+    hipLaunchKernelGGL(k_pme_gather<N>, dim3(p->ntiles), dim3(NB_PME_BLOCK), lds_gather, p->stream, K1, K2, K3, \
+                       p->nt[0], p->nt[1], p->nt[2], p->L[0], p->L[1], p->L[2], p->sidx, p->sbase, p->sxq,    \
+                       p->toff, p->grid, f)
     if (n == 4) NB_PME_GATHER(4);
     else if (n == 6) NB_PME_GATHER(6);
     else NB_PME_GATHER(8);
