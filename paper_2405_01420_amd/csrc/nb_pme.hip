@@ -47,7 +47,7 @@ struct nb_pme {
     size_t nreal = 0, ncplx = 0;
     double *grid = nullptr;        // [K1][K2][K3] charges, then the potential phi
     double2 *cgrid = nullptr;      // [K1][K2][K3/2 + 1] transform
-    double *infl = nullptr;        // [K1][K2][K3/2 + 1] G(m) times the Hermitian weight / 2
+    double *infl = nullptr;        // [K1][K2][K3/2 + 1] G(m)
     double *part = nullptr;        // energy partials of the solve blocks
     int nsolve_blocks = 0;
     // tiles: nt[a] per axis, tile t covers points t K / nt .. (t + 1) K / nt - 1 (at least
@@ -414,19 +414,21 @@ __global__ void __launch_bounds__(NB_PME_BLOCK) k_pme_spread(int K1, int K2, int
         grid[(unsigned)(((a1.s + wk.l1) * K2 + (a2.s + wk.l2)) * K3 + (a3.s + wk.l3))] = lg[p];   // < 2^30
 }
 
-// c(m) <- G(m) c(m) over the half-complex grid; energy partial sum of G |c|^2 with the
-// Hermitian weights folded into infl (weight / 2, so that the sum is E_rec).
-__global__ void __launch_bounds__(NB_PME_BLOCK) k_pme_solve(size_t ncplx, const double *__restrict__ infl,
-                                                             const double *__restrict__ ewt,
+// c(m) <- G(m) c(m) over the half-complex grid [K1][K2][K3h]; per-block partial sums of the
+// energy 1/2 sum_m G |c|^2 over the full spectrum: a stored k3 other than 0 and K3/2 (even K3)
+// stands for m and -m, so its weight is 1, else 1/2.
+__global__ void __launch_bounds__(NB_PME_BLOCK) k_pme_solve(unsigned ncplx, unsigned K3h, unsigned k3nyq,
+                                                             const double *__restrict__ infl,
                                                              double2 *__restrict__ c,
                                                              double *__restrict__ part) {
     __shared__ double s[NB_PME_BLOCK / 64];
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const unsigned i = blockIdx.x * blockDim.x + threadIdx.x;
     double e = 0.0;
     if (i < ncplx) {
+        const unsigned k3 = i % K3h;
         const double g = infl[i];
         const double2 z = c[i];
-        e = ewt[i] * g * (z.x * z.x + z.y * z.y);
+        e = ((k3 == 0u || k3 == k3nyq) ? 0.5 : 1.0) * g * (z.x * z.x + z.y * z.y);
         c[i] = make_double2(g * z.x, g * z.y);
     }
 #pragma unroll
@@ -440,8 +442,8 @@ __global__ void __launch_bounds__(NB_PME_BLOCK) k_pme_solve(size_t ncplx, const 
     }
 }
 
-__global__ void __launch_bounds__(NB_PME_BLOCK) k_pme_energy(int nblk, const double *__restrict__ part,
-                                                              double *__restrict__ e) {
+// Sum of the solve's energy partials in a fixed order, by one block (the gather's first block).
+__device__ void pme_energy_sum(int nblk, const double *__restrict__ part, double *__restrict__ e) {
     __shared__ double s[NB_PME_BLOCK / 64];
     double t = 0.0;
     for (int k = threadIdx.x; k < nblk; k += NB_PME_BLOCK) t += part[k];
@@ -468,7 +470,9 @@ __global__ void __launch_bounds__(NB_PME_BLOCK) k_pme_gather(int K1, int K2, int
                                                               const float4 *__restrict__ sxq,
                                                               const int *__restrict__ toff,
                                                               const double *__restrict__ phi,
-                                                              float *__restrict__ f) {
+                                                              float *__restrict__ f, int nblk,
+                                                              const double *__restrict__ part,
+                                                              double *__restrict__ e) {
     constexpr int CH = pme_chunk<N>::GATHER, R = pme_lanes<N>::R, APW = pme_lanes<N>::APW;
     constexpr int WAVES = NB_PME_BLOCK / 64;
     constexpr int RED = APW > 1 ? R : 64;   // reduction width, a power of two
@@ -481,6 +485,7 @@ __global__ void __launch_bounds__(NB_PME_BLOCK) k_pme_gather(int K1, int K2, int
     const int t3 = t % nt3, t2 = (t / nt3) % nt2, t1 = t / (nt3 * nt2);
     const pme_span a1(t1, nt1, K1), a2(t2, nt2, K2), a3(t3, nt3, K3);
     // staged box: points s_a - (N - 1) .. s_a + z_a - 1 along each axis
+    if (t == 0) pme_energy_sum(nblk, part, e);
     const int c0 = toff[t], c1 = toff[t + 1];
     if (c0 == c1) return;   // no atoms in this tile
     const int h1 = a1.z + N - 1, h2 = a2.z + N - 1, h3 = a3.z + N - 1, hh = h2 * h3;
@@ -691,18 +696,17 @@ int nb_pme_setup(nb_pme **out, const nb_pme_params *prm, void *stream) {
         (r = palloc(p, &p->sxq, (size_t)p->natoms, "sorted coordinates")) != NB_OK ||
         (r = palloc(p, &p->grid, p->nreal, "grid")) != NB_OK ||
         (r = palloc(p, &p->cgrid, p->ncplx, "transform")) != NB_OK ||
-        (r = palloc(p, &p->infl, 2 * p->ncplx, "influence function")) != NB_OK ||
+        (r = palloc(p, &p->infl, p->ncplx, "influence function")) != NB_OK ||
         (r = palloc(p, &p->part, (size_t)p->nsolve_blocks, "energy partials")) != NB_OK) {
         g_pme_error = p->err;
         pme_free(p);
         delete p;
         return r;
     }
-    // influence function G(m) and the Hermitian energy weights (1 for k3 = 0 and k3 = K3/2 of an
-    // even K3, 2 for the other stored k3, since those stand for m and -m), both halved
+    // influence function G(m)
     const std::vector<double> b1 = bmod2(K1, p->order), b2 = bmod2(K2, p->order), b3 = bmod2(K3, p->order);
     const double V = p->L[0] * p->L[1] * p->L[2];
-    std::vector<double> g(2 * p->ncplx);
+    std::vector<double> g(p->ncplx);
     for (int k1 = 0; k1 < K1; ++k1) {
         const double m1 = (k1 <= K1 / 2 ? k1 : k1 - K1) / p->L[0];
         for (int k2 = 0; k2 < K2; ++k2) {
@@ -714,8 +718,6 @@ int nb_pme_setup(nb_pme **out, const nb_pme_params *prm, void *stream) {
                 g[i] = msq > 0.0 ? p->fc / (M_PI * V) * exp(-M_PI * M_PI * msq / (p->beta * p->beta)) / msq *
                                        b1[k1] * b2[k2] * b3[k3]
                                  : 0.0;
-                const double herm = (k3 == 0 || (K3 % 2 == 0 && k3 == K3 / 2)) ? 1.0 : 2.0;
-                g[p->ncplx + i] = 0.5 * herm;
             }
         }
     }
@@ -764,16 +766,15 @@ int nb_pme_forces(nb_pme *p, const float *x, const float *q, float *f, double *e
     if (hipGetLastError() != hipSuccess) return pfail(p, NB_ERR_HIP, "spread launch");
     if (hipfftExecD2Z(p->fwd, (hipfftDoubleReal *)p->grid, (hipfftDoubleComplex *)p->cgrid) != HIPFFT_SUCCESS)
         return pfail(p, NB_ERR_HIP, "forward FFT");
-    hipLaunchKernelGGL(k_pme_solve, dim3(p->nsolve_blocks), dim3(NB_PME_BLOCK), 0, p->stream, p->ncplx,
-                       p->infl, p->infl + p->ncplx, p->cgrid, p->part);
-    hipLaunchKernelGGL(k_pme_energy, dim3(1), dim3(NB_PME_BLOCK), 0, p->stream, p->nsolve_blocks, p->part, e);
+    hipLaunchKernelGGL(k_pme_solve, dim3(p->nsolve_blocks), dim3(NB_PME_BLOCK), 0, p->stream, (unsigned)p->ncplx,
+                       (unsigned)(K3 / 2 + 1), (unsigned)(K3 % 2 == 0 ? K3 / 2 : 0), p->infl, p->cgrid, p->part);
     if (hipGetLastError() != hipSuccess) return pfail(p, NB_ERR_HIP, "solve launch");
     if (hipfftExecZ2D(p->bwd, (hipfftDoubleComplex *)p->cgrid, (hipfftDoubleReal *)p->grid) != HIPFFT_SUCCESS)
         return pfail(p, NB_ERR_HIP, "inverse FFT");
 #define NB_PME_GATHER(N)                                                                                      \
     hipLaunchKernelGGL(k_pme_gather<N>, dim3(p->ntiles), dim3(NB_PME_BLOCK), lds_gather, p->stream, K1, K2, K3, \
                        p->nt[0], p->nt[1], p->nt[2], p->L[0], p->L[1], p->L[2], p->sidx, p->sbase, p->sxq,    \
-                       p->toff, p->grid, f)
+                       p->toff, p->grid, f, p->nsolve_blocks, p->part, e)
     if (n == 4) NB_PME_GATHER(4);
     else if (n == 6) NB_PME_GATHER(6);
     else NB_PME_GATHER(8);
