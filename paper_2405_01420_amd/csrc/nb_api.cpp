@@ -528,8 +528,8 @@ int nb_prune(nb_ctx *c, const float *x, double r_inner) {
     if (e != hipSuccess) return hip_fail(c, e, "prune: pack launch");
     // the full list is jl / icount before the first prune after a build, jl_p / icount_p after it
     const float rin = (float)r_inner;
-    e = c->pruned ? nb_launch_prune(c, x, rin * rin, c->icount_p, c->jl_p, c->icount, c->jl)
-                             : nb_launch_prune(c, x, rin * rin, c->icount, c->jl, c->icount_p, c->jl_p);
+    e = c->pruned ? nb_launch_prune(c, rin * rin, c->icount_p, c->jl_p, c->icount, c->jl)
+                  : nb_launch_prune(c, rin * rin, c->icount, c->jl, c->icount_p, c->jl_p);
     if (e != hipSuccess) return hip_fail(c, e, "prune launch");
     if (!c->pruned) {
         std::swap(c->jl, c->jl_p);

@@ -807,8 +807,8 @@ hipError_t nb_launch_debug_pairs(nb_ctx *c, int64_t cap) {
 
 namespace {
 template <int C>
-hipError_t prune_impl(nb_ctx *c, const float *x, float rin2, const int *icount, const nb_entry *jl,
-                      int *icount_p, nb_entry *jl_p) {
+hipError_t prune_impl(nb_ctx *c, float rin2, const int *icount, const nb_entry *jl, int *icount_p,
+                      nb_entry *jl_p) {
     // the work units of the build stay valid: each covers a batch range of its cluster's full
     // list and the force kernel stops at the pruned list's end
     hipLaunchKernelGGL((k_prune<C>), dim3((c->ncl_max + 3) / 4), dim3(256), 0, c->stream, c->geom, rin2,
@@ -817,10 +817,9 @@ hipError_t prune_impl(nb_ctx *c, const float *x, float rin2, const int *icount, 
 }
 }  // namespace
 
-hipError_t nb_launch_prune(nb_ctx *c, const float *x, float rin2, const int *icount, const nb_entry *jl,
-                           int *icount_p, nb_entry *jl_p) {
-    return c->C == 4 ? prune_impl<4>(c, x, rin2, icount, jl, icount_p, jl_p)
-                     : prune_impl<8>(c, x, rin2, icount, jl, icount_p, jl_p);
+hipError_t nb_launch_prune(nb_ctx *c, float rin2, const int *icount, const nb_entry *jl, int *icount_p,
+                           nb_entry *jl_p) {
+    return c->C == 4 ? prune_impl<4>(c, rin2, icount, jl, icount_p, jl_p) : prune_impl<8>(c, rin2, icount, jl, icount_p, jl_p);
 }
 
 hipError_t nb_launch_prune_check(nb_ctx *c, const float *x) {

@@ -197,8 +197,8 @@ int nb_list_entries(nb_ctx *c, int nclusters, int64_t *total);  // sum of icount
 // ---- launchers (nb_build.hip) ----
 hipError_t nb_launch_build(nb_ctx *c, const float *x);
 hipError_t nb_launch_debug_pairs(nb_ctx *c, int64_t cap);
-hipError_t nb_launch_prune(nb_ctx *c, const float *x, float rin2, const int *icount, const nb_entry *jl,
-                           int *icount_p, nb_entry *jl_p);
+hipError_t nb_launch_prune(nb_ctx *c, float rin2, const int *icount, const nb_entry *jl, int *icount_p,
+                           nb_entry *jl_p);  // on the positions of the last pack
 hipError_t nb_launch_prune_check(nb_ctx *c, const float *x);
 
 // ---- launchers (nb_force.hip) ----

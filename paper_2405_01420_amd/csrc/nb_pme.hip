@@ -367,7 +367,7 @@ __global__ void __launch_bounds__(NB_PME_BLOCK) k_pme_spread(int K1, int K2, int
         const int nh = nhit;
         for (int h0 = 0; h0 < nh; h0 += CH) {
             const int nc = min(CH, nh - h0);
-            if (threadIdx.x < nc) {   // weights of the listed atom, the first axis scaled by q
+            if ((int)threadIdx.x < nc) {   // weights of the listed atom, the first axis scaled by q
                 const float4 p = sxq[hit[h0 + threadIdx.x].x];
                 double *w = wt + threadIdx.x * WS;
                 const float xa[3] = {p.x, p.y, p.z};
@@ -540,7 +540,7 @@ __global__ void __launch_bounds__(NB_PME_BLOCK) k_pme_gather(int K1, int K2, int
                 }
             }
         }
-        if (threadIdx.x < nc) {
+        if ((int)threadIdx.x < nc) {
             ab[threadIdx.x] = sbase[cb + threadIdx.x];
             aq[threadIdx.x] = sxq[cb + threadIdx.x].w;
             ai[threadIdx.x] = sidx[cb + threadIdx.x];
