@@ -146,3 +146,28 @@ def test_autograd_end_to_end_vs_finite_differences(torch_gpu, problem):
             rel = abs(g[t] - fd) / abs(fd)
             print(f"d{nm}[{t}] gpu {g[t]:.6e} fd {fd:.6e} rel {rel:.2e}")
             assert rel <= G2_TOL
+
+
+def test_adjoint_on_a_pruned_list(torch_gpu, problem):
+    """nb_backward with NB_REUSE_LIST on a list pruned by nb_prune (the pairs within rc are the
+    same, so the VJP matches the oracle's to the G1 bound)."""
+    torch = torch_gpu
+    inst = problem["inst"]
+    box = GpuBox(torch, inst)
+    box.pairlist()
+    nb.nb_prune(box.ctx, box.x, inst.cutoff + 0.02)
+    assert box.stats()["pruned"] == 1
+    gf = dev(torch, problem["gF"].reshape(-1))
+    ge = dev(torch, problem["gE"])
+    dx = torch.empty(inst.natoms * 3, dtype=torch.float32, device="cuda:0")
+    dq = torch.empty(inst.natoms, dtype=torch.float32, device="cuda:0")
+    ds = torch.empty(inst.ntypes, dtype=torch.float64, device="cuda:0")
+    de = torch.empty(inst.ntypes, dtype=torch.float64, device="cuda:0")
+    nb.nb_backward(box.ctx, box.x, box.q, box.t, gf, ge, dx, dq, ds, de, nb.NB_REUSE_LIST)
+    torch.cuda.synchronize()
+    rdx, rdq, _, _ = problem["vjp"]
+    ex = rel_rms(dx.cpu().numpy().reshape(-1, 3).astype(np.float64), rdx)
+    eq = rel_rms(dq.cpu().numpy().astype(np.float64), rdq)
+    print(f"pruned list: dx relRMS {ex:.2e} dq relRMS {eq:.2e}")
+    box.close()
+    assert ex <= G1_TOL and eq <= G1_TOL
