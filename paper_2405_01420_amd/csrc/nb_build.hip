@@ -393,17 +393,23 @@ __global__ void __launch_bounds__(256) k_search(nb_geom g, int cap, const int *_
                 const int ps = pe & 0xffffff;
                 if (ps / C == cj) m &= ~(1ull << ((ps % C) * C + (pe >> 24)));
             }
-            // atom-level prune per j-group (the whole cluster for C = 4, each half for C = 8)
+            // atom-level prune per j-group (the whole cluster for C = 4, each half for C = 8): a
+            // group is kept if it has an unmasked pair and some pair within rlist.  Testing the
+            // distances without the mask keeps a superset of the groups with an unmasked pair in
+            // range (padding sits far away, so only excluded or self pairs can differ; the force
+            // kernel applies the mask), at two VALU instructions less per pair.
 #pragma unroll
             for (int b = 0; b < C; ++b) {
 #pragma unroll
                 for (int a = 0; a < C; ++a) {
                     const float dx = xi[a] - jx[b], dy = yi[a] - jy[b], dz = zi[a] - jz[b];
-                    const bool in = (dx * dx + dy * dy + dz * dz < g.rl2) && ((m >> (b * C + a)) & 1ull);
+                    const bool in = dx * dx + dy * dy + dz * dz < g.rl2;
                     if (b < NB_JG) keep0 |= in;
                     else keep1 |= in;
                 }
             }
+            keep0 = keep0 && (uint32_t)m != 0u;
+            keep1 = keep1 && (uint32_t)(m >> 32) != 0u;
         }
         // kept groups in (lane, half) order: the list stays in queue order, grouped by shift
         const unsigned long long k0 = __ballot(keep0), k1 = __ballot(keep1);
