@@ -345,10 +345,12 @@ typedef struct nb_pme_params {
 int nb_pme_setup(nb_pme **out, const nb_pme_params *p, void *hip_stream);
 
 /* Reciprocal-space forces and energy of the device arrays x [natoms][3] (any periodic images)
- * and q [natoms]: f_dev [natoms][3] overwritten with the reciprocal forces (FP32, original
- * order; add them to nb_forces' output), e_dev[0] = E_rec (device double).  The system should
- * be neutral (a net charge adds no energy here).  Asynchronous on the context's stream; no
- * allocation.  Errors: NB_ERR_ARG, NB_ERR_HIP. */
+ * and q [natoms], by smooth PME (the PME kernels of the paper's Fig. 2): f_dev [natoms][3]
+ * overwritten with the reciprocal forces (FP32, original order; add them to nb_forces' output),
+ * e_dev[0] = E_rec (device double).  The grid, the FFTs and all sums are FP64; the charge spread
+ * adds with FP64 atomics in on-chip memory, so results may differ in the last bits between
+ * calls.  The system should be neutral (a net charge adds no energy here).  Asynchronous on the
+ * context's stream; no allocation.  Errors: NB_ERR_ARG, NB_ERR_HIP. */
 int nb_pme_forces(nb_pme *pme, const float *x_dev, const float *q_dev, float *f_dev, double *e_dev);
 
 /* Message of the last error of this context (or of the last failed nb_pme_setup for NULL). */
