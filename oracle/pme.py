@@ -113,10 +113,12 @@ def pme_reference(x, q, box, beta, fc, grid, order):
         ders.append(d)
     # grid points of atom i along axis a: base - j (mod K)
     idx = [np.mod(base[:, a][:, None] - np.arange(n)[None, :], K[a]) for a in range(3)]
-    Q = np.zeros(tuple(K), dtype=np.float64)
-    for i in range(len(q)):
-        wt = q[i] * vals[0][i][:, None, None] * vals[1][i][None, :, None] * vals[2][i][None, None, :]
-        np.add.at(Q, np.ix_(idx[0][i], idx[1][i], idx[2][i]), wt)
+    # flat index and weight of every (atom, j1, j2, j3): arrays [natoms][n][n][n]
+    flat = (idx[0][:, :, None, None] * K[1] + idx[1][:, None, :, None]) * K[2] + idx[2][:, None, None, :]
+    wt = q[:, None, None, None] * vals[0][:, :, None, None] * vals[1][:, None, :, None] * vals[2][:, None, None, :]
+    Q = np.zeros(int(np.prod(K)), dtype=np.float64)
+    np.add.at(Q, flat.ravel(), wt.ravel())
+    Q = Q.reshape(tuple(K))
     # influence function
     ms = [np.fft.fftfreq(int(K[a]), d=1.0 / K[a]) / L[a] for a in range(3)]   # m_a = k / L
     M1, M2, M3 = np.meshgrid(*ms, indexing="ij")
@@ -127,13 +129,9 @@ def pme_reference(x, q, box, beta, fc, grid, order):
     Qh = np.fft.fftn(Q)
     phi = np.real(np.fft.ifftn(G * Qh)) * float(np.prod(K))   # unnormalised inverse
     e = 0.5 * float(np.sum(Q * phi))
-    f = np.zeros_like(x)
-    for i in range(len(q)):
-        p = phi[np.ix_(idx[0][i], idx[1][i], idx[2][i])]
-        vx, vy, vz = vals[0][i], vals[1][i], vals[2][i]
-        dx_, dy_, dz_ = ders[0][i], ders[1][i], ders[2][i]
-        gx = np.einsum("a,b,c,abc->", dx_, vy, vz, p) * K[0] / L[0]
-        gy = np.einsum("a,b,c,abc->", vx, dy_, vz, p) * K[1] / L[1]
-        gz = np.einsum("a,b,c,abc->", vx, vy, dz_, p) * K[2] / L[2]
-        f[i] = -q[i] * np.array([gx, gy, gz])
+    p = phi.ravel()[flat]                                   # [natoms][n][n][n]
+    gx = np.einsum("ia,ib,ic,iabc->i", ders[0], vals[1], vals[2], p) * K[0] / L[0]
+    gy = np.einsum("ia,ib,ic,iabc->i", vals[0], ders[1], vals[2], p) * K[1] / L[1]
+    gz = np.einsum("ia,ib,ic,iabc->i", vals[0], vals[1], ders[2], p) * K[2] / L[2]
+    f = -q[:, None] * np.stack([gx, gy, gz], axis=1)
     return e, f

@@ -91,6 +91,19 @@ def test_pme_on_the_water_box(torch_gpu):
     assert fr <= FORCE_TOL and er <= PME_E_TOL
 
 
+def test_pme_at_the_benchmark_size(torch_gpu):
+    """The configuration bench.py times: the 96,000-atom water box on a 96^3 grid with order-4
+    B-splines, every atom and the energy against the FP64 reference."""
+    inst = synth.mid()
+    grid, order = (96, 96, 96), 4
+    f, e = run_pme(torch_gpu, inst.x, inst.q, inst.box, inst.beta, grid, order, inst.coulomb_const)
+    e0, f0 = P.pme_reference(inst.x.astype(np.float64), inst.q.astype(np.float64), inst.box, inst.beta,
+                             inst.coulomb_const, grid, order)
+    fr, er = rel_rms(f, f0), abs(e - e0) / abs(e0)
+    print(f"96k atoms, 96^3, order 4: force relRMS {fr:.2e}, energy rel {er:.2e}", flush=True)
+    assert fr <= FORCE_TOL and er <= PME_E_TOL
+
+
 def test_fine_grid_pme_reaches_the_ewald_sum(torch_gpu):
     x, q, L = random_system(n=48)
     beta = 3.0
