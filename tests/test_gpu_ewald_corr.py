@@ -1,7 +1,9 @@
 """Parity of the Ewald exclusion correction and self term (NB_EWALD_CORR) of the HIP path with
 the FP64 oracle: forces (real-space + exclusion-correction forces) RMS relative <= 5e-6, the
 real-space energies as in the plain parity tests, and the two correction energies, which both
-sides compute in FP64, to 1e-12 relative (summation order and libm erf against the device's)."""
+sides compute in FP64: they differ by the order of an N-term sum of same-sign terms (the self
+term) and libm erf against the device's, bounded by N u with u = 2^-53, i.e. 1.1e-11 for the
+96,000-atom box; the bound used is 2^-53 N, at least 1e-12."""
 import numpy as np
 import pytest
 
@@ -14,9 +16,14 @@ pytestmark = pytest.mark.gpu
 CORR_TOL = 1e-12
 
 
-@pytest.mark.parametrize("name,flags", [("tiny", nb.NB_ENERGY_FP64), ("diff", 0)])
+def corr_tol(natoms):
+    return max(CORR_TOL, natoms * 2.0 ** -53)
+
+
+@pytest.mark.parametrize("name,flags", [("tiny", nb.NB_ENERGY_FP64), ("diff", 0), ("mid", 0)])
 def test_ewald_corrections_match_oracle(torch_gpu, name, flags):
-    inst = synth.tiny() if name == "tiny" else synth.diff()
+    """tiny, the 24k-atom box, and the 96k-atom box the benchmark times this call on."""
+    inst = {"tiny": synth.tiny, "diff": synth.diff, "mid": synth.mid}[name]()
     box = GpuBox(torch_gpu, inst, flags=flags | nb.NB_EWALD_CORR)
     box.pairlist()
     f, e = box.forces()
@@ -30,7 +37,7 @@ def test_ewald_corrections_match_oracle(torch_gpu, name, flags):
     rse = abs(e[3] - e_self) / abs(e_self)
     print(f"E_excl {e[2]:.10e} ref {e_excl:.10e} rel {rex:.2e};  E_self rel {rse:.2e}", flush=True)
     assert fr <= FORCE_TOL and elj <= ENERGY_TOL and ec <= ENERGY_TOL
-    assert rex <= CORR_TOL and rse <= CORR_TOL
+    assert rex <= corr_tol(inst.natoms) and rse <= corr_tol(inst.natoms)
 
 
 def test_ewald_corrections_follow_the_positions(torch_gpu):

@@ -36,9 +36,10 @@ def frob_rel(a, b):
     ("tiny", nb.NB_ENERGY_FP64, {}),
     ("diff", 0, {}),
     ("diff", 0, dict(elec=nb.NB_ELEC_RF, epsilon_rf=0.0, vdw=nb.NB_VDW_FSWITCH, rswitch=0.8)),
+    ("mid", 0, {}),   # the 96k-atom box the benchmark times nb_forces_virial on
 ])
 def test_virial_matches_oracle(torch_gpu, name, flags, fl):
-    inst = synth.tiny() if name == "tiny" else synth.diff()
+    inst = {"tiny": synth.tiny, "diff": synth.diff, "mid": synth.mid}[name]()
     f, e, v = run(torch_gpu, inst, flags, **fl)
     okw = dict(elec=fl.get("elec", 0), vdw=fl.get("vdw", 0), epsilon_rf=fl.get("epsilon_rf", 0.0),
                rswitch=fl.get("rswitch", 0.0))
