@@ -9,7 +9,7 @@ import pytest
 
 from oracle import oracle as O
 from paper_2405_01420_amd import nb, synth
-from tests.gpu_helpers import ENERGY_TOL, FORCE_TOL, GpuBox, rel_rms
+from tests.gpu_helpers import ENERGY_TOL, FORCE_TOL, FP32_SMALL_BOX_EC_TOL, GpuBox, rel_rms
 
 pytestmark = pytest.mark.gpu
 
@@ -116,3 +116,41 @@ def test_batch_reports_force_beyond_the_fixed_point_range(torch_gpu):
     assert nb.nb_batch_check(bt) == nb.NB_ERR_RANGE
     assert nb.nb_batch_check(bt) == nb.NB_OK
     nb.nb_batch_destroy(bt)
+
+
+@pytest.mark.parametrize("cluster", [8, 4])
+def test_full_batch_sampled_against_oracle(torch_gpu, cluster):
+    """The batch the benchmark times: 256 boxes of 3,000-30,000 atoms (3.3M atoms), FP32 pair
+    energies, one graph-replayed launch per shape; twelve boxes spread over the size range are
+    checked against the oracle (forces to the force gate, E_LJ to 1e-6, E_C to the FP32 bound of
+    small boxes)."""
+    torch = torch_gpu
+    insts = synth.batch(256)
+    clusters = [cluster] * len(insts)
+    ao, bx, params, x, q, t = nb.concat_instances(insts, clusters=clusters)
+    stream = torch.cuda.Stream()
+    bt = nb.nb_batch_setup(ao, bx, params, clusters=clusters, stream=stream.cuda_stream)
+    with torch.cuda.stream(stream):
+        dx = torch.from_numpy(x.reshape(-1)).to("cuda:0")
+        dq = torch.from_numpy(q).to("cuda:0")
+        dt = torch.from_numpy(t).to("cuda:0")
+        f = torch.zeros(len(q) * 3, dtype=torch.float32, device="cuda:0")
+        e = torch.zeros(2 * len(insts), dtype=torch.float64, device="cuda:0")
+    stream.synchronize()
+    nb.nb_batch_pairlist(bt, dx)
+    for _ in range(2):
+        nb.nb_batch_graph_forces(bt, dx, dq, dt, f, e)
+    stream.synchronize()
+    assert nb.nb_batch_check(bt) == nb.NB_OK
+    fa = f.cpu().numpy().reshape(-1, 3).astype(np.float64)
+    ea = e.cpu().numpy().reshape(-1, 2)
+    nb.nb_batch_destroy(bt)
+    order = np.argsort([b.natoms for b in insts])
+    for k in order[np.linspace(0, len(insts) - 1, 12).astype(int)]:
+        inst = insts[k]
+        ref = O.instance_forces(inst, cells=True)
+        fr = rel_rms(fa[ao[k]:ao[k + 1]], ref.f)
+        elj = abs(ea[k, 0] - ref.e_lj) / abs(ref.e_lj)
+        ec = abs(ea[k, 1] - ref.e_coul) / abs(ref.e_coul)
+        print(f"box {k} n={inst.natoms} f {fr:.2e} elj {elj:.2e} ec {ec:.2e}", flush=True)
+        assert fr <= FORCE_TOL and elj <= ENERGY_TOL and ec <= FP32_SMALL_BOX_EC_TOL
