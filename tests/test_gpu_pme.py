@@ -54,12 +54,13 @@ def test_pme_matches_fp64_reference(torch_gpu, grid, order):
 
 
 def test_pme_clustered_atoms_and_repeated_calls(torch_gpu):
-    """All atoms in a small cube (one or two grid tiles hold every atom), then a second call on
-    the same context with the atoms spread over the box: both match the reference."""
+    """All atoms in a small cube (a few grid tiles hold every atom: several filter passes of
+    1024 candidates and several staging passes per tile), then a second call on the same context
+    with the atoms spread over the box: both match the reference."""
     torch = torch_gpu
     L, beta, grid, order = (2.0, 2.2, 1.9), 3.0, (20, 24, 18), 4
     rng = np.random.default_rng(11)
-    n = 200
+    n = 3000
     q = rng.normal(0.0, 0.8, n)
     q = (q - q.mean()).astype(np.float32)
     xa = (0.61 + rng.uniform(0.0, 0.15, (n, 3))).astype(np.float32)
