@@ -215,7 +215,7 @@ void free_all(nb_ctx *c) {
                     c->colcount, c->colstart, c->colcl, c->perm, c->xs,     c->xq,
                     c->tsort, c->units,  c->fj,     c->bblo,  c->bbhi,      c->icount,
                     c->jl,    c->epart,  c->meta,   c->ljtab, c->excl_off,  c->excl_idx,
-                    c->dbg_pairs, c->adj, c->adjj, c->gs, c->tpart, c->excl_slot, c->etab,
+                    c->dbg_pairs, c->adj, c->adjj, c->gs, c->tpart, c->etab,
                     c->cpart, c->vpart, c->jl_p, c->icount_p, c->xprune};
     for (void *p : bufs)
         if (p) hipFree(p);
@@ -384,7 +384,6 @@ int nb_setup(nb_ctx **out, const nb_params *p, void *stream) {
         int nnz = p->excl_off[n];
         if ((r = dalloc(c, &c->excl_off, (size_t)n + 1, "excl_off")) != NB_OK) goto fail_out;
         if ((r = dalloc(c, &c->excl_idx, (size_t)std::max(nnz, 1), "excl_idx")) != NB_OK) goto fail_out;
-        if ((r = dalloc(c, &c->excl_slot, (size_t)std::max(nnz, 1), "excl_slot")) != NB_OK) goto fail_out;
         c->nnz_excl = nnz;
         hipError_t e = hipMemcpy(c->excl_off, p->excl_off, sizeof(int) * (n + 1), hipMemcpyHostToDevice);
         if (e == hipSuccess && nnz > 0)

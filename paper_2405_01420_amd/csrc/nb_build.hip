@@ -150,7 +150,8 @@ __global__ void k_scatter(int n, int npad_max, const int *__restrict__ col,
 
 // One block per column: sort the column's atoms by (z, index) in LDS (by rank for columns of
 // at most one atom per thread, bitonic otherwise), then lay them out as clusters of C slots;
-// the tail of the last cluster is padding (perm = -1).
+// the tail of the last cluster is padding (perm = -1).  The block then writes the bounding
+// boxes of its clusters over their real atoms (from the slots it has just written).
 template <int C>
 __global__ void __launch_bounds__(256) k_colsort(const float *__restrict__ x,
                                                  const float4 *__restrict__ off,
@@ -159,20 +160,19 @@ __global__ void __launch_bounds__(256) k_colsort(const float *__restrict__ x,
                                                  const int *__restrict__ colcl,
                                                  const int *__restrict__ tmp, int *__restrict__ perm,
                                                  int *__restrict__ slot_of, float4 *__restrict__ xs,
+                                                 float4 *__restrict__ bblo, float4 *__restrict__ bbhi,
                                                  nb_meta *meta) {
     __shared__ unsigned long long key[NB_SORT_MAX];
     const int c = blockIdx.x, tid = threadIdx.x;
     const int n = colcount[c], start = colstart[c];
     const int cl0 = colcl[c], nslot = (colcl[c + 1] - cl0) * C;
-    if (n > NB_SORT_MAX) {
+    if (n > NB_SORT_MAX) {   // reported; the column's clusters are left empty
         if (tid == 0) atomicOr(&meta->flags, NB_F_COLUMN);
         for (int r = tid; r < nslot; r += blockDim.x) {
             perm[cl0 * C + r] = -1;
             xs[cl0 * C + r] = make_float4(-1e5f, -1e5f, -1e5f, 0.0f);
         }
-        return;
-    }
-    if (n <= (int)blockDim.x) {
+    } else if (n <= (int)blockDim.x) {
         // one atom per thread: its place in the sorted column is the number of smaller keys
         // (keys are distinct: the atom index is their low word), read from LDS as broadcasts
         unsigned long long v = ~0ull;
@@ -198,8 +198,7 @@ __global__ void __launch_bounds__(256) k_colsort(const float *__restrict__ x,
             perm[cl0 * C + r] = -1;
             xs[cl0 * C + r] = make_float4(-1e5f, -1e5f, -1e5f, 0.0f);
         }
-        return;
-    }
+    } else {
     int npow = 1;
     while (npow < n) npow <<= 1;
     for (int k = tid; k < npow; k += blockDim.x) {
@@ -242,39 +241,31 @@ __global__ void __launch_bounds__(256) k_colsort(const float *__restrict__ x,
             xs[slot] = make_float4(-1e5f, -1e5f, -1e5f, 0.0f);
         }
     }
-}
-
-template <int C>
-__global__ void k_bbox(int ncl_max, const float4 *__restrict__ xs, const int *__restrict__ perm,
-                       float4 *__restrict__ lo, float4 *__restrict__ hi, const nb_meta *meta) {
-    int cl = blockIdx.x * blockDim.x + threadIdx.x;
-    if (cl >= ncl_max || cl >= meta->nclusters) return;
-    float3 a = make_float3(3e38f, 3e38f, 3e38f), b = make_float3(-3e38f, -3e38f, -3e38f);
-    for (int r = 0; r < C; ++r) {
-        if (perm[cl * C + r] < 0) continue;
-        float4 p = xs[cl * C + r];
-        a.x = fminf(a.x, p.x);
-        a.y = fminf(a.y, p.y);
-        a.z = fminf(a.z, p.z);
-        b.x = fmaxf(b.x, p.x);
-        b.y = fmaxf(b.y, p.y);
-        b.z = fmaxf(b.z, p.z);
     }
-    lo[cl] = make_float4(a.x, a.y, a.z, 0.0f);
-    hi[cl] = make_float4(b.x, b.y, b.z, 0.0f);
+    // the block's writes of perm and xs are visible to the whole block after the barrier
+    __syncthreads();
+    for (int k = tid; k < nslot / C; k += blockDim.x) {
+        const int cl = cl0 + k;
+        float3 a = make_float3(3e38f, 3e38f, 3e38f), b = make_float3(-3e38f, -3e38f, -3e38f);
+        for (int r = 0; r < C; ++r) {
+            if (perm[cl * C + r] < 0) continue;
+            const float4 p = xs[cl * C + r];
+            a.x = fminf(a.x, p.x);
+            a.y = fminf(a.y, p.y);
+            a.z = fminf(a.z, p.z);
+            b.x = fmaxf(b.x, p.x);
+            b.y = fmaxf(b.y, p.y);
+            b.z = fmaxf(b.z, p.z);
+        }
+        bblo[cl] = make_float4(a.x, a.y, a.z, 0.0f);
+        bbhi[cl] = make_float4(b.x, b.y, b.z, 0.0f);
+    }
 }
 
 __device__ __forceinline__ float gap(float alo, float ahi, float blo, float bhi) {
     return fmaxf(0.0f, fmaxf(blo - ahi, alo - bhi));
 }
 
-// Exclusion partners of every slot, as slots: exs[e] = slot_of[excl_idx[e]] for the CSR of
-// the atom in that slot.  Lets the search compare slot numbers without gathering atom indices.
-__global__ void k_excl_slots(int nnz, const int *__restrict__ eidx, const int *__restrict__ slot_of,
-                             int *__restrict__ exs) {
-    int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < nnz) exs[e] = slot_of[eidx[e]];
-}
 
 #define NB_QCAP 128       // candidate queue slots per wavefront
 #define NB_PART_MAX 256   // exclusion partners of one i-cluster held in LDS
@@ -315,7 +306,8 @@ __global__ void __launch_bounds__(256) k_search(nb_geom g, int cap, const int *_
                                                 const int *__restrict__ perm,
                                                 const float4 *__restrict__ xs,
                                                 const int *__restrict__ eoff,
-                                                const int *__restrict__ exs,
+                                                const int *__restrict__ eidx,
+                                                const int *__restrict__ slot_of,
                                                 int *__restrict__ icount,
                                                 nb_entry *__restrict__ jl, nb_meta *meta) {
     __shared__ int q_cj[4][NB_QCAP], q_s[4][NB_QCAP];
@@ -358,7 +350,7 @@ __global__ void __launch_bounds__(256) k_search(nb_geom g, int cap, const int *_
             if (lane == 0) atomicOr(&meta->flags, NB_F_OVERFLOW | NB_F_COLUMN);
             npart = 0;
         } else if (lane < C) {
-            for (int k = 0; k < ne; ++k) part[wv][pre + k] = (lane << 24) | exs[eb + k];
+            for (int k = 0; k < ne; ++k) part[wv][pre + k] = (lane << 24) | slot_of[eidx[eb + k]];
         }
         nb_wave_sync();
     }
@@ -776,15 +768,10 @@ hipError_t build_impl(nb_ctx *c, const float *x) {
                        c->col, c->rank, c->colstart, c->tmp, c->perm);
     hipLaunchKernelGGL((k_colsort<C>), dim3(c->geom.ncol), dim3(256), 0, c->stream, x, c->off,
                        c->colcount, c->colstart, c->colcl, c->tmp, c->perm, c->slot_of, c->xs,
-                       c->meta);
-    hipLaunchKernelGGL((k_bbox<C>), dim3((c->ncl_max + tb - 1) / tb), dim3(tb), 0, c->stream,
-                       c->ncl_max, c->xs, c->perm, c->bblo, c->bbhi, c->meta);
-    if (c->excl_off && c->nnz_excl > 0)
-        hipLaunchKernelGGL(k_excl_slots, dim3((c->nnz_excl + tb - 1) / tb), dim3(tb), 0, c->stream,
-                           c->nnz_excl, c->excl_idx, c->slot_of, c->excl_slot);
+                       c->bblo, c->bbhi, c->meta);
     hipLaunchKernelGGL((k_search<C>), dim3((c->ncl_max + 3) / 4), dim3(256), 0, c->stream,
                        c->geom, c->cap, c->colcl, c->bblo, c->bbhi, c->perm, c->xs,
-                       c->nnz_excl > 0 ? c->excl_off : nullptr, c->excl_slot, c->icount, c->jl,
+                       c->nnz_excl > 0 ? c->excl_off : nullptr, c->excl_idx, c->slot_of, c->icount, c->jl,
                        c->meta);
     hipLaunchKernelGGL(k_units, dim3(1), dim3(1024), 0, c->stream, c->slots, c->unit_cap, c->icount,
                        c->units, c->meta);

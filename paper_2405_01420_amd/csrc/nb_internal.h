@@ -172,7 +172,6 @@ struct nb_ctx {
     int etab_n = 0;
     float etab_invh = 0.0f;     // 1 / segment width, a power of two
     int *excl_off = nullptr, *excl_idx = nullptr;
-    int *excl_slot = nullptr;   // [nnz] exclusion partners as slots (rebuilt with every list)
     int nnz_excl = 0;
     int64_t *dbg_pairs = nullptr;
     int64_t dbg_cap = 0;
