@@ -1,7 +1,7 @@
 """FP64 reference of the reciprocal-space part of Ewald summation (numpy).
 
-TEST INFRASTRUCTURE ONLY: imported by tests/ and by the CPU-baseline leg of bench.py; the
-product path never imports it, and it imports nothing from the product.
+TEST INFRASTRUCTURE ONLY: imported by tests/; the product path never imports it, and it imports
+nothing from the product.
 
 The paper's production runs complete the short-range (real-space) Coulomb interaction with a
 particle-mesh Ewald reciprocal part (section II-C, the PME kernels of Fig. 2); it prints no
