@@ -268,6 +268,9 @@ __device__ __forceinline__ float gap(float alo, float ahi, float blo, float bhi)
 
 
 #define NB_QCAP 128       // candidate queue slots per wavefront
+#ifndef NB_SEARCH_WAVES
+#define NB_SEARCH_WAVES 6
+#endif
 #define NB_PART_MAX 256   // exclusion partners of one i-cluster held in LDS
 
 // Wave-local ordering of LDS writes before reads by other lanes of the same wavefront.
@@ -300,7 +303,7 @@ __device__ __forceinline__ unsigned long long nb_triangle() {
 // the candidate.  Kept group entries are written in queue order, so the entries of one
 // i-cluster are contiguous at jl[ci * cap] and grouped by shift.
 template <int C>
-__global__ void __launch_bounds__(256) k_search(nb_geom g, int cap, const int *__restrict__ colcl,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NB_SEARCH_WAVES))) k_search(nb_geom g, int cap, const int *__restrict__ colcl,
                                                 const float4 *__restrict__ bblo,
                                                 const float4 *__restrict__ bbhi,
                                                 const int *__restrict__ perm,
