@@ -160,3 +160,12 @@ def test_tuner_size_buckets():
     assert all(abs(e[k + 1] / e[k] - 10 ** 0.2) < 1e-12 for k in range(5))
     assert tune.bucket_of(100, e) == 0 and tune.bucket_of(3000, e) == 0
     assert tune.bucket_of(4800, e) == 1 and tune.bucket_of(29999, e) == 4 and tune.bucket_of(10 ** 6, e) == 4
+
+
+def test_null_handles_are_rejected_without_gpu():
+    """Entry points given a NULL context return NB_ERR_ARG before touching the device."""
+    L = nb.lib()
+    assert L.nb_prune(None, None, 1.0) == nb.NB_ERR_ARG
+    assert L.nb_forces(None, None, None, None, None, None) == nb.NB_ERR_ARG
+    assert L.nb_pme_forces(None, None, None, None, None) == nb.NB_ERR_ARG
+    assert L.nb_batch_tune_schedule(None, None, None, None, None, None, 1, None, None) == nb.NB_ERR_ARG
