@@ -21,11 +21,12 @@ def inst_diff():
     return synth.diff()
 
 
-@pytest.mark.parametrize("cluster", [8, 4])
-def test_pruned_walk_matches_oracle(torch_gpu, inst_diff, cluster):
-    """24k atoms, built every 10 calls, pruned every 2 calls to rc + 0.04 nm (valid while atoms
-    move less than 0.02 nm; the walk moves them ~0.003 nm per call)."""
-    box = GpuBox(torch_gpu, inst_diff, cluster=cluster, flags=nb.NB_CHECK_STALE | nb.NB_ENERGY_FP64)
+@pytest.mark.parametrize("cluster,extra", [(8, 0), (4, 0), (8, nb.NB_ASYNC_BUILD)])
+def test_pruned_walk_matches_oracle(torch_gpu, inst_diff, cluster, extra):
+    """24k atoms, built every 10 calls (also with asynchronous builds), pruned every 2 calls to
+    rc + 0.04 nm (valid while atoms move less than 0.02 nm; the walk moves them ~0.003 nm per
+    call)."""
+    box = GpuBox(torch_gpu, inst_diff, cluster=cluster, flags=nb.NB_CHECK_STALE | nb.NB_ENERGY_FP64 | extra)
     rin = inst_diff.cutoff + 0.04
     rng = synth.jitter_stream(23)
     x = inst_diff.x.copy()
