@@ -79,6 +79,7 @@ def parse():
     ap.add_argument("--cluster", type=int, default=0, help="4 or 8 (0 = tuned or default 8)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-baseline-child", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--copy-probe", action="store_true",
                     help="end with one 256 MiB device-to-device copy (calibrates HBM byte counters)")
     ap.add_argument("--elec", choices=["ewald", "rf"], default="ewald",
@@ -101,11 +102,28 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(inst, useful_pairs, seconds):
-    """The FP64 oracle (cell-list enumeration) on the host cores, repeated for about `seconds`."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline_child(seconds):
+    """Runs in a child process started by cpu_baseline (OpenMP placement set in its environment
+    before the runtime starts): the FP64 oracle, cell-list enumeration on the 96,000-atom box
+    repeated for about `seconds`, and the O(N^2) definition on the 648-atom box for about a
+    tenth of that.  Prints one JSON object."""
     from oracle import oracle as O
+    from paper_2405_01420_amd import synth
+    inst = synth.mid()
     O.lib()
-    O.instance_forces(inst, cells=True)  # warm
+    r = O.instance_forces(inst, cells=True)  # warm
+    useful = r.npairs
     t0 = time.perf_counter()
     calls = 0
     while True:
@@ -114,10 +132,46 @@ def cpu_baseline(inst, useful_pairs, seconds):
         el = time.perf_counter() - t0
         if el >= seconds or calls >= 1000:
             break
-    return {"value": useful_pairs * calls / el, "unit": "pair-interactions/s",
-            "cores": O.get_threads(), "kind": "oracle",
-            "sample": f"{calls} full force+energy calls of the FP64 cell-list oracle on the "
-                      f"96,000-atom box ({el:.1f} s); per call {1e6 * el / calls:.0f} us"}
+    tiny = synth.tiny()
+    rt = O.instance_forces(tiny, cells=False)
+    t1 = time.perf_counter()
+    ncalls_t = 0
+    while True:
+        O.instance_forces(tiny, cells=False)
+        ncalls_t += 1
+        el_t = time.perf_counter() - t1
+        if el_t >= 0.1 * seconds or ncalls_t >= 10000:
+            break
+    print(json.dumps({"useful": useful, "calls": calls, "seconds": el, "threads": O.get_threads(),
+                      "tiny_useful": rt.npairs, "tiny_calls": ncalls_t, "tiny_seconds": el_t}))
+
+
+def cpu_baseline(seconds):
+    """The FP64 oracle timed on all host cores in a child process with OMP_PLACES=cores and
+    OMP_PROC_BIND=close (the parent's OpenMP runtime, loaded by torch, has already read its
+    environment)."""
+    import subprocess
+    ncpu = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    env = dict(os.environ)
+    env.setdefault("OMP_NUM_THREADS", str(ncpu))
+    env["OMP_PLACES"] = "cores"
+    env["OMP_PROC_BIND"] = "close"
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-child",
+                        "--cpu-seconds", str(seconds)], env=env, capture_output=True, text=True,
+                       check=True)
+    c = json.loads(r.stdout.strip().splitlines()[-1])
+    per_call = c["seconds"] / c["calls"]
+    per_tiny = c["tiny_seconds"] / c["tiny_calls"]
+    return {"value": c["useful"] / per_call, "unit": "pair-interactions/s",
+            "cores": c["threads"], "kind": "oracle",
+            "sample": f"{c['calls']} full force+energy calls of the FP64 cell-list oracle on the "
+                      f"96,000-atom box ({c['seconds']:.1f} s); per call {1e6 * per_call:.0f} us",
+            "cpu_model": _cpu_model(), "nproc": ncpu, "omp_num_threads": env["OMP_NUM_THREADS"],
+            "omp_places": env["OMP_PLACES"], "omp_proc_bind": env["OMP_PROC_BIND"],
+            "us_per_call_cell_list_96k": 1e6 * per_call,
+            "o_n2_tiny": {"workload": "648-atom water box, O(N^2) brute force (the definition)",
+                          "us_per_call": 1e6 * per_tiny, "calls": c["tiny_calls"],
+                          "pair_interactions_per_s": c["tiny_useful"] / per_tiny}}
 
 
 def _event_us(torch, stream, fn, reps):
@@ -341,6 +395,9 @@ def bench_large(torch, nb, synth, reps=20, warmup=3):
 
 def main():
     args = parse()
+    if args.cpu_baseline_child:
+        cpu_baseline_child(args.cpu_seconds)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the force path is "
               "single-GPU and multi-GPU sharding is not built.", file=sys.stderr)
@@ -388,14 +445,33 @@ def main():
 
     for k in range(args.warmup):
         step(k)
+    # HIP events on the stream at the start of every rebuild period inside the timed region
+    # give the spread over periods (median and IQR of microseconds per call); they add no
+    # synchronisation
+    marks = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.warmup, nsteps):
+        if k % REBUILD_EVERY == 0:
+            ev = torch.cuda.Event(enable_timing=True)
+            ev.record()
+            marks.append((k, ev))
         step(k)
+    end_ev = torch.cuda.Event(enable_timing=True)
+    end_ev.record()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms_per_step = 1e3 * elapsed / args.steps
     value = useful * args.steps / elapsed
+    marks.append((nsteps, end_ev))
+    period_us = [1e3 * a[1].elapsed_time(b[1]) / (b[0] - a[0])
+                 for a, b in zip(marks[:-1], marks[1:]) if b[0] - a[0] == REBUILD_EVERY]
+    period_stats = None
+    if period_us:
+        p25, p50, p75 = (float(v) for v in np.percentile(period_us, [25, 50, 75]))
+        period_stats = {"periods": len(period_us), "us_per_call_median": p50,
+                        "us_per_call_iqr": [p25, p75],
+                        "pair_interactions_per_s_median": useful / (p50 * 1e-6)}
     # the last asynchronous build's status (raises NB_ERR_OVERFLOW if any list had overflowed)
     nb.nb_pairlist(ctx, traj[nsteps - 1])
 
@@ -533,6 +609,7 @@ def main():
         "us_per_force_call_with_ewald_corrections": us_force_corr,
         "us_per_list_build": us_build,
         "us_per_call_amortised": 1e3 * ms_per_step,
+        "rebuild_periods": period_stats,
         "rolling_prune": prune,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
@@ -550,7 +627,7 @@ def main():
     if args.large:
         out["large"] = bench_large(torch, nb, synth)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(inst, useful, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     if args.copy_probe:
         src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)

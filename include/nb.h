@@ -172,7 +172,8 @@ int nb_pairlist(nb_ctx *ctx, const float *x_dev);
  * nb_pairlist restores it.  The pruned list holds every pair within rc while every atom has
  * moved less than (r_inner - rc)/2 since this call (and less than buffer/2 since the build);
  * with NB_CHECK_STALE the force calls check the first condition too (nb_check reports
- * NB_ERR_LIST_STALE).  Also rebuilds the force kernel's work units for the shorter lists.
+ * NB_ERR_LIST_STALE).  Also rebuilds the force kernel's work units for the shorter lists
+ * (long lists are split by the same rule as after a build).
  * Asynchronous on the context's stream; allocates the pruned list on first use (and after the
  * list has grown).  Errors: NB_ERR_ARG, NB_ERR_STATE (no list), NB_ERR_OOM, NB_ERR_HIP. */
 int nb_prune(nb_ctx *ctx, const float *x_dev, double r_inner);
@@ -203,7 +204,8 @@ int nb_forces_virial(nb_ctx *ctx, const float *x_dev, const float *q_dev, const 
                      float *f_dev, double *e_dev, double *vir_dev);
 
 /* Synchronise the stream and report device-side conditions recorded since the last check:
- * NB_ERR_LIST_STALE, NB_ERR_NONFINITE, NB_ERR_OVERFLOW, NB_ERR_RANGE; clears them. */
+ * NB_ERR_LIST_STALE, NB_ERR_NONFINITE, NB_ERR_OVERFLOW, NB_ERR_RANGE; clears them.  Conditions
+ * raised by force calls stay recorded across later list builds until this call reports them. */
 int nb_check(nb_ctx *ctx);
 
 /* Vector-Jacobian product of (F, E_LJ, E_C) for a force-matching loss.

@@ -338,12 +338,16 @@ int oracle_forces_cells(int n, const double *x, const double *q, const int *type
     return 0;
 }
 
-/* Forces on a subset of atoms only (brute force over all partners), for sampled checks at
- * sizes where the full sum is too slow.  fs receives 3 values per listed atom. */
+/* Forces and per-atom energies of a subset of atoms only (brute force over all partners):
+ * the same visits as oracle_forces restricted to the listed atoms i, so every listed row equals
+ * the corresponding row of oracle_forces.  fs receives 3 values per listed atom; es_lj / es_c
+ * (may be NULL) receive each listed atom's half of its pair energies (eatom_lj / eatom_c of
+ * oracle_forces).  Used for finite differences of a loss where one perturbed coordinate or
+ * charge changes only the rows of its neighbours. */
 int oracle_forces_subset(int n, const double *x, const double *q, const int *type, int nt,
                          const double *c6, const double *c12, const double *box, double rc,
                          double beta, double fc, const int *eoff, const int *eidx, int nsub,
-                         const int *sub, double *fs) {
+                         const int *sub, double *fs, double *es_lj, double *es_c) {
 #pragma omp parallel for schedule(dynamic, 4)
     for (int s = 0; s < nsub; ++s) {
         int i = sub[s];
@@ -355,6 +359,8 @@ int oracle_forces_subset(int n, const double *x, const double *q, const int *typ
         fs[3 * s] = fi[0];
         fs[3 * s + 1] = fi[1];
         fs[3 * s + 2] = fi[2];
+        if (es_lj) es_lj[s] = acc.elj;
+        if (es_c) es_c[s] = acc.ec;
     }
     return 0;
 }

@@ -49,7 +49,7 @@ def lib():
         L.oracle_forces_cells.argtypes = fsig
         L.oracle_forces.restype = L.oracle_forces_cells.restype = c_i
         L.oracle_forces_subset.argtypes = [c_i, dp, dp, ip, c_i, dp, dp, dp, c_d, c_d, c_d, ip, ip,
-                                           c_i, ip, dp]
+                                           c_i, ip, dp, dp, dp]
         L.oracle_pairs.argtypes = [c_i, dp, dp, c_d, ip, ip, c_i64, i32p, i32p, dp]
         L.oracle_pairs.restype = c_i64
         L.oracle_vjp.argtypes = [c_i, dp, dp, ip, c_i, dp, dp, dp, c_d, c_d, c_d, ip, ip, dp, dp,
@@ -166,7 +166,9 @@ def forces(x, q, typ, sigma, epsilon, box, rc, beta, fc, excl_off=None, excl_idx
 
 
 def forces_subset(x, q, typ, sigma, epsilon, box, rc, beta, fc, excl_off, excl_idx, subset,
-                  round32: bool = True) -> np.ndarray:
+                  round32: bool = True):
+    """Rows `subset` of the oracle's forces [len(subset), 3] and of its per-atom energy halves
+    (eatom_lj, eatom_c), from visits restricted to those atoms."""
     n, c6, c12, bx = _common(x, q, typ, sigma, epsilon, box, None, round32)
     xa, xp = _d(np.asarray(x, dtype=np.float64).reshape(-1))
     qa, qp = _d(q)
@@ -174,13 +176,18 @@ def forces_subset(x, q, typ, sigma, epsilon, box, rc, beta, fc, excl_off, excl_i
     c6a, c6p = _d(c6.reshape(-1))
     c12a, c12p = _d(c12.reshape(-1))
     ba, bp = _d(bx)
-    oa, op = _i(excl_off)
-    ia, ipp = _i(excl_idx)
+    if excl_off is not None:
+        oa, op = _i(excl_off)
+        ia, ipp = _i(excl_idx if len(excl_idx) else np.zeros(1, np.int32))
+    else:
+        op = ipp = None
     sa, sp = _i(subset)
     fs, fsp = _d(np.zeros(3 * len(sa)))
+    el, elp = _d(np.zeros(len(sa)))
+    ec, ecp = _d(np.zeros(len(sa)))
     lib().oracle_forces_subset(n, xp, qp, tp, len(c6), c6p, c12p, bp, float(rc), float(beta),
-                               float(fc), op, ipp, len(sa), sp, fsp)
-    return fs.reshape(-1, 3)
+                               float(fc), op, ipp, len(sa), sp, fsp, elp, ecp)
+    return fs.reshape(-1, 3), el, ec
 
 
 def pairs(x, box, rc, excl_off=None, excl_idx=None):

@@ -460,7 +460,7 @@ int nb_pairlist(nb_ctx *c, const float *x) {
         const nb_meta m = *c->host_meta;
         if (m.flags & NB_F_COLUMN)
             return fail(c, NB_ERR_OVERFLOW, "a grid column or the exclusions of one cluster exceed the build kernels' capacity");
-        if (m.flags & NB_F_NONFINITE) return fail(c, NB_ERR_NONFINITE, "non-finite coordinates at the previous build");
+        if (m.flags & NB_F_BUILD_NONFINITE) return fail(c, NB_ERR_NONFINITE, "non-finite coordinates at the previous build");
         if (m.flags & NB_F_OVERFLOW) {
             prev_overflow = true;
             // force calls queued after that build still read the old list
@@ -488,7 +488,7 @@ int nb_pairlist(nb_ctx *c, const float *x) {
         if (r != NB_OK) return r;
         if (m.flags & NB_F_COLUMN)
             return fail(c, NB_ERR_OVERFLOW, "a grid column or the exclusions of one cluster exceed the build kernels' capacity");
-        if (m.flags & NB_F_NONFINITE) return fail(c, NB_ERR_NONFINITE, "non-finite coordinates");
+        if (m.flags & NB_F_BUILD_NONFINITE) return fail(c, NB_ERR_NONFINITE, "non-finite coordinates");
         if (m.flags & NB_F_OVERFLOW) {
             c->cap = ((m.maxcount + m.maxcount / 8 + 32) + 31) & ~31;
             if ((r = alloc_list(c)) != NB_OK) return r;
@@ -614,7 +614,7 @@ int nb_check(nb_ctx *c) {
     hipError_t e = hipMemcpy(&c->meta->flags, &zero, sizeof(zero), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(c, e, "clear device flags");
     if (m.flags & (NB_F_OVERFLOW | NB_F_COLUMN)) return fail(c, NB_ERR_OVERFLOW, "pair list overflow");
-    if (m.flags & NB_F_NONFINITE) return fail(c, NB_ERR_NONFINITE, "non-finite coordinates");
+    if (m.flags & (NB_F_NONFINITE | NB_F_BUILD_NONFINITE)) return fail(c, NB_ERR_NONFINITE, "non-finite coordinates");
     if (m.flags & NB_F_STALE) return fail(c, NB_ERR_LIST_STALE, "an atom moved more than buffer/2 since the list was built");
     if (m.flags & NB_F_RANGE)
         return fail(c, NB_ERR_RANGE, "a pair force component exceeded 131072 kJ/mol/nm (or was not finite): "

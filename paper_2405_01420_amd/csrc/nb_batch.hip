@@ -445,7 +445,7 @@ int nb_batch_pairlist(nb_batch *bt, const float *x) {
                 if (nb_read_meta(c, &m) != NB_OK) return bfail(bt, NB_ERR_HIP, c->err);
                 todo[b] = false;
                 if (m.flags & NB_F_COLUMN) return bfail(bt, NB_ERR_OVERFLOW, "a grid column overflowed");
-                if (m.flags & NB_F_NONFINITE) return bfail(bt, NB_ERR_NONFINITE, "non-finite coordinates");
+                if (m.flags & NB_F_BUILD_NONFINITE) return bfail(bt, NB_ERR_NONFINITE, "non-finite coordinates");
                 if (m.flags & NB_F_OVERFLOW) {
                     if (nb_regrow_list(c, m.maxcount) != NB_OK) return bfail(bt, NB_ERR_OOM, c->err);
                     todo[b] = true;

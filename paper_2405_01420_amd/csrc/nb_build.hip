@@ -39,7 +39,7 @@ __global__ void __launch_bounds__(256) k_bin(int n, const float *__restrict__ x,
                 xv[d] = 0.0f;
             }
         }
-        if (!fin) atomicOr(&meta->flags, NB_F_NONFINITE);
+        if (!fin) atomicOr(&meta->flags, NB_F_BUILD_NONFINITE);
         for (int d = 0; d < 3; ++d) {
             const float L = g.L[d];
             o[d] = -floorf(xv[d] / L) * L;
@@ -129,12 +129,17 @@ __global__ void __launch_bounds__(1024) k_colscan(int ncol, int C, const int *__
     if (lane == 0) atomicMax(&meta->maxcolumn, mx);
 }
 
-// Clears the column histogram and the status block before a build (one launch instead of
-// a memset per buffer).
+// Clears the column histogram and the build's part of the status block before a build (one
+// launch instead of a memset per buffer).  Conditions raised by earlier force calls (stale list,
+// non-finite coordinates, force range) stay set until nb_check has reported them.
 __global__ void k_begin(int ncol, int *__restrict__ colcount, nb_meta *meta) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < ncol) colcount[i] = 0;
-    if (i == 0) *meta = nb_meta{};
+    if (i == 0) {
+        const uint32_t keep = meta->flags & NB_F_CALL_MASK;
+        *meta = nb_meta{};
+        meta->flags = keep;
+    }
 }
 
 // Atom indices in column order; also marks every slot of perm empty (-1) for the column sort,
@@ -805,10 +810,11 @@ namespace {
 template <int C>
 hipError_t prune_impl(nb_ctx *c, float rin2, const int *icount, const nb_entry *jl, int *icount_p,
                       nb_entry *jl_p) {
-    // the work units of the build stay valid: each covers a batch range of its cluster's full
-    // list and the force kernel stops at the pruned list's end
     hipLaunchKernelGGL((k_prune<C>), dim3((c->ncl_max + 3) / 4), dim3(256), 0, c->stream, c->geom, rin2,
                        c->cap, c->ncl_max, c->xq, icount, jl, icount_p, jl_p, c->meta);
+    // work units of the pruned lists (the shorter lists are split by the same rule)
+    hipLaunchKernelGGL(k_units, dim3(1), dim3(1024), 0, c->stream, c->slots, c->unit_cap, icount_p,
+                       c->units, c->meta);
     return hipGetLastError();
 }
 }  // namespace

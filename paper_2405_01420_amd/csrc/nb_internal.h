@@ -20,6 +20,9 @@
 #define NB_F_NONFINITE 0x4u
 #define NB_F_COLUMN 0x8u
 #define NB_F_RANGE 0x10u  // a pair force component beyond the fixed-point accumulators' check
+#define NB_F_BUILD_NONFINITE 0x20u  // non-finite coordinates seen by a list build
+// Conditions raised by force calls: kept across list builds until nb_check reports them.
+#define NB_F_CALL_MASK (NB_F_STALE | NB_F_NONFINITE | NB_F_RANGE)
 
 // Fixed-point force accumulation of the single-box path: a component f is added as the 32-bit
 // integer rint(f * NB_FSCALE); x and y of an atom share one 64-bit word (x + 2^32 y, added

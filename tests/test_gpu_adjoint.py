@@ -95,41 +95,35 @@ def test_autograd_end_to_end_vs_finite_differences(torch_gpu, problem):
         L, _ = O.loss(inst, xv, qv, sv, ev, problem["f_t"], problem["e_t"], cells=True)
         return L
 
+    from tests.fd_local import loss_difference, neighbours
     x0 = inst.x.astype(np.float64)
     q0 = inst.q.astype(np.float64)
-    pi, pj, pr = O.pairs(x0[:4000], inst.box, inst.cutoff)  # cheap neighbour screen below
+    r0 = O.loss(inst, x0, q0, inst.sigma, inst.epsilon, problem["f_t"], problem["e_t"], cells=True)[1]
+    e0 = r0.e_lj + r0.e_coul
     rng = np.random.default_rng(7)
-    h = 1e-6
     worst = 0.0
     n_checked = 0
     rmsx = np.sqrt(np.mean(gx ** 2))
     for a in rng.permutation(inst.natoms):
-        d = x0 - x0[a]
-        d -= inst.box * np.rint(d / inst.box)
-        r = np.sqrt((d * d).sum(1))
+        _, r = neighbours(inst, x0, a)
         if np.any(np.abs(r - inst.cutoff) < 1e-4):
             continue
         c = int(rng.integers(3))
         if abs(gx[a, c]) < 1e-2 * rmsx:
             continue
-        xp, xm = x0.copy(), x0.copy()
-        xp[a, c] += h
-        xm[a, c] -= h
-        fd = (oloss(xp, q0, inst.sigma, inst.epsilon) - oloss(xm, q0, inst.sigma, inst.epsilon)) / (2 * h)
+        fd = loss_difference(inst, x0, q0, e0, problem["f_t"], problem["e_t"], a, c)
         worst = max(worst, abs(gx[a, c] - fd) / abs(fd))
         n_checked += 1
-        if n_checked == 16:
+        if n_checked == 64:
             break
-    print("dx vs FD worst rel", worst)
-    assert worst <= G2_TOL
+    print(f"dx vs FD worst rel over {n_checked} coordinates", worst)
+    assert n_checked == 64 and worst <= G2_TOL
     worst = 0.0
-    for a in rng.permutation(inst.natoms)[:16]:
-        qp, qm = q0.copy(), q0.copy()
-        qp[a] += h
-        qm[a] -= h
-        fd = (oloss(x0, qp, inst.sigma, inst.epsilon) - oloss(x0, qm, inst.sigma, inst.epsilon)) / (2 * h)
-        worst = max(worst, abs(gq[a] - fd) / max(abs(fd), 1e-3 * np.sqrt(np.mean(gq ** 2))))
-    print("dq vs FD worst rel", worst)
+    rmsq = np.sqrt(np.mean(gq ** 2))
+    for a in rng.permutation(inst.natoms)[:64]:
+        fd = loss_difference(inst, x0, q0, e0, problem["f_t"], problem["e_t"], a)
+        worst = max(worst, abs(gq[a] - fd) / max(abs(fd), 1e-3 * rmsq))
+    print("dq vs FD worst rel over 64 charges", worst)
     assert worst <= G2_TOL
     for t in np.unique(inst.type):
         if inst.epsilon[t] == 0.0:

@@ -154,6 +154,26 @@ def test_stale_list_is_reported(torch_gpu, inst_diff):
     box.close()
 
 
+@pytest.mark.parametrize("flags", [0, nb.NB_ASYNC_BUILD])
+def test_stale_force_call_survives_a_rebuild(torch_gpu, inst_diff, flags):
+    """A condition raised by a force call (stale list) is still reported by nb_check after a
+    later list build: the build clears only its own status."""
+    box = GpuBox(torch_gpu, inst_diff, flags=nb.NB_CHECK_STALE | flags)
+    box.pairlist()
+    box.forces()
+    assert nb.nb_check(box.ctx) == nb.NB_OK
+    x = inst_diff.x.copy()
+    x[17, 0] += 0.06  # more than buffer / 2 = 0.05 nm
+    box.set_x(x)
+    box.forces()
+    box.pairlist()   # rebuilt at the moved positions: the stale call happened before
+    box.pairlist()
+    box.forces()
+    assert nb.nb_check(box.ctx) == nb.NB_ERR_LIST_STALE
+    assert nb.nb_check(box.ctx) == nb.NB_OK
+    box.close()
+
+
 def test_nonfinite_is_reported(torch_gpu, inst_tiny):
     box = GpuBox(torch_gpu, inst_tiny, flags=nb.NB_CHECK_FINITE)
     x = inst_tiny.x.copy()

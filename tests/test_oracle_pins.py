@@ -81,6 +81,58 @@ def test_lj_minimum_and_zero_crossing(across):
     assert res.f[0, 0] < 0 and res.f[1, 0] > 0
 
 
+def two_types(r, sig, eps):
+    """Atom 0 of type 0 and atom 1 of type 1, r apart, no charges."""
+    x = np.zeros((2, 3))
+    x[:, 1] = 2.0
+    x[0, 0] = 1.0
+    x[1, 0] = 1.0 + r
+    return x, np.zeros(2), np.array([0, 1], dtype=np.int32), np.array(sig), np.array(eps)
+
+
+@pytest.mark.parametrize("sig,eps", [((0.25, 0.40), (0.10, 1.00)), ((0.3166, 0.28), (0.65, 0.2))])
+def test_unlike_types_follow_lorentz_berthelot(sig, eps):
+    """Two atoms of different types interact through sigma_ab = (sigma_a + sigma_b)/2 and
+    eps_ab = sqrt(eps_a eps_b): the pair force vanishes at 2^(1/6) sigma_ab, where the energy is
+    the well depth -eps_ab minus the shift, and the unshifted energy is zero at r = sigma_ab.
+    (A geometric-mean sigma or an arithmetic-mean eps moves the minimum or changes its depth.)"""
+    rc = 1.0
+    sab = 0.5 * (sig[0] + sig[1])
+    eab = math.sqrt(eps[0] * eps[1])
+    shift = 4 * eab * ((sab / rc) ** 12 - (sab / rc) ** 6)
+    x, q, typ, s, e = two_types(2 ** (1 / 6) * sab, sig, eps)
+    res = run(x, q, typ, s, e, 10.0, rc, 3.0)
+    assert abs(res.e_lj - (-eab - shift)) <= 1e-12 * eab
+    assert np.abs(res.f).max() <= 1e-9 * eab / sab
+    x, q, typ, s, e = two_types(sab, sig, eps)
+    res = run(x, q, typ, s, e, 10.0, rc, 3.0)
+    assert abs(res.e_lj + shift) <= 1e-12 * eab
+    # the well is the deepest point: slightly off the minimum on either side the energy is higher
+    for f in (0.999, 1.001):
+        x, q, typ, s, e = two_types(f * 2 ** (1 / 6) * sab, sig, eps)
+        assert run(x, q, typ, s, e, 10.0, rc, 3.0).e_lj > -eab - shift
+
+
+def test_lj_table_hand_computed():
+    """C6 = 4 eps_ab sigma_ab^6 and C12 = 4 eps_ab sigma_ab^12 for a three-type table whose
+    combined parameters are exact decimals: sigma = (0.3, 0.5, 0.4), eps = (1, 4, 0.25) give
+    sigma_01 = 0.4, eps_01 = 2; sigma_02 = 0.35, eps_02 = 0.5; sigma_12 = 0.45, eps_12 = 1."""
+    c6, c12 = O.lj_table([0.3, 0.5, 0.4], [1.0, 4.0, 0.25], round32=False)
+    expect6 = {(0, 0): 4 * 0.000729, (1, 1): 16 * 0.015625, (2, 2): 0.004096,
+               (0, 1): 8 * 0.004096, (0, 2): 2 * 0.001838265625, (1, 2): 4 * 0.008303765625}
+    expect12 = {(0, 0): 4 * 0.000729 ** 2, (1, 1): 16 * 0.015625 ** 2, (2, 2): 0.004096 ** 2,
+                (0, 1): 8 * 0.004096 ** 2, (0, 2): 2 * 0.001838265625 ** 2,
+                (1, 2): 4 * 0.008303765625 ** 2}
+    for (a, b), v in expect6.items():
+        for (i, j) in ((a, b), (b, a)):
+            assert abs(c6[i, j] - v) <= 1e-14 * v, (i, j, c6[i, j], v)
+            assert abs(c12[i, j] - expect12[(a, b)]) <= 1e-14 * expect12[(a, b)], (i, j)
+    # rounded once to FP32: the instance's table
+    r6, r12 = O.lj_table([0.3, 0.5, 0.4], [1.0, 4.0, 0.25], round32=True)
+    assert np.array_equal(r6, c6.astype(np.float32).astype(np.float64))
+    assert np.array_equal(r12, c12.astype(np.float32).astype(np.float64))
+
+
 @pytest.mark.parametrize("across", [False, True])
 def test_plain_coulomb_when_beta_is_zero(across):
     """beta = 0 reduces the Ewald real-space term to the shifted plain Coulomb law:
@@ -241,14 +293,34 @@ def test_explicit_image_enumeration(tiny):
     assert img_set == set(zip(pi.tolist(), pj.tolist()))
 
 
-def test_cell_list_equals_brute_force():
-    inst = synth.diff()
+@pytest.mark.parametrize("which", ["tiny", "diff", "mid"])
+def test_cell_list_equals_brute_force(which):
+    """The cell-list enumeration (used for the 96k- and 3M-atom parity references) gives the same
+    pair set, energies and forces as the O(N^2) definition on the 648-, 24k- and 96k-atom boxes."""
+    inst = getattr(synth, which)()
     a = O.instance_forces(inst, cells=False)
     b = O.instance_forces(inst, cells=True)
     assert a.npairs == b.npairs
     assert abs(a.e_lj - b.e_lj) <= 1e-12 * a.abs_lj
     assert abs(a.e_coul - b.e_coul) <= 1e-12 * a.abs_coul
+    assert abs(a.qq_sum - b.qq_sum) <= 1e-12 * np.abs(inst.q).max() ** 2 * a.npairs
     assert np.abs(a.f - b.f).max() <= 1e-10 * np.abs(a.f).max()
+    if which != "mid":
+        pi, pj, _ = O.pairs(inst.x, inst.box, inst.cutoff, inst.excl_off, inst.excl_idx)
+        assert len(pi) == a.npairs
+
+
+def test_subset_rows_equal_full_rows(small_typed):
+    """oracle_forces_subset restricted to a few atoms reproduces those atoms' force rows and
+    per-atom energy halves of the full O(N^2) sum."""
+    inst = small_typed
+    full = O.instance_forces(inst, cells=False)
+    sub = np.array([0, 5, 17, 299, inst.natoms - 1], dtype=np.int32)
+    fs, el, ec = O.forces_subset(inst.x, inst.q, inst.type, inst.sigma, inst.epsilon, inst.box,
+                                 inst.cutoff, inst.beta, inst.coulomb_const, inst.excl_off,
+                                 inst.excl_idx, sub)
+    assert np.array_equal(fs, full.f[sub])
+    assert np.array_equal(el, full.eatom_lj[sub]) and np.array_equal(ec, full.eatom_c[sub])
 
 
 def test_unshifted_energy_consistency(tiny):

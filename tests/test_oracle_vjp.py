@@ -94,3 +94,22 @@ def test_vjp_lj_parameters(problem):
             v = fd(problem, which, t, 1e-6 * base)
             g = problem[key][t]
             assert abs(v - g) <= 1e-6 * abs(g), (which, t, v, g)
+
+
+def test_local_loss_difference_equals_full(problem):
+    """The neighbour-row form of the loss difference used by the GPU gradient test at 24k atoms
+    (tests/fd_local.py) equals the difference of the full loss, for coordinates and charges."""
+    from tests.fd_local import loss_difference
+    inst = problem["inst"]
+    e0 = O.loss(inst, problem["x"], problem["q"], inst.sigma, inst.epsilon, problem["f_t"],
+                problem["e_t"])[1]
+    e0 = e0.e_lj + e0.e_coul
+    rng = np.random.default_rng(31)
+    for a in rng.permutation(inst.natoms)[:6]:
+        c = int(rng.integers(3))
+        loc = loss_difference(inst, problem["x"], problem["q"], e0, problem["f_t"], problem["e_t"], a, c)
+        full = fd(problem, "x", (a, c), 1e-6)
+        assert abs(loc - full) <= 1e-7 * max(abs(full), 1.0), (a, c, loc, full)
+        loc = loss_difference(inst, problem["x"], problem["q"], e0, problem["f_t"], problem["e_t"], a)
+        full = fd(problem, "q", a, 1e-6)
+        assert abs(loc - full) <= 1e-7 * max(abs(full), 1.0), (a, loc, full)
