@@ -92,6 +92,7 @@ def parse():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-pme", action="store_true")
+    ap.add_argument("--no-md", action="store_true")
     ap.add_argument("--prune-every", type=int, default=0,
                     help="rolling-prune measurement: prune every this many calls (0: skip)")
     ap.add_argument("--prune-inner", type=float, default=0.05,
@@ -186,78 +187,94 @@ def _event_us(torch, stream, fn, reps):
 
 
 def bench_batched(torch, nb, synth, tune_on, reps=20):
-    """256 uneven boxes: one persistent graph-replayed launch vs 256 sequential plain calls."""
+    """256 uneven boxes: one persistent graph-replayed launch vs 256 sequential plain calls, in
+    the FP64 pair-energy mode (the energy mode that holds 1e-6 on boxes of 3,000-30,000 atoms)
+    and in the FP32 pair-energy mode (E_C held to 1e-5 on such boxes)."""
     from paper_2405_01420_amd import tune
     dev = "cuda:0"
     insts = synth.batch(256)
     stream = torch.cuda.Stream()
-    tuned = None
-    if tune_on:
-        tuned = tune.autotune(insts)
-        clusters, srt, bpc = tuned["clusters"], tuned["sorted"], tuned["blocks_per_cu"]
-    else:
-        clusters, srt, bpc = [8] * len(insts), True, 0
-    ao, bx, params, x, q, t = nb.concat_instances(insts, clusters=clusters)
-    n = int(ao[-1])
-    bt = nb.nb_batch_setup(ao, bx, params, clusters=clusters, stream=stream.cuda_stream)
-    nb.nb_batch_set_schedule(bt, srt, bpc)
-    with torch.cuda.stream(stream):
-        dx = torch.from_numpy(x.reshape(-1)).to(dev)
-        dq = torch.from_numpy(q).to(dev)
-        dt = torch.from_numpy(t).to(dev)
-        f = torch.empty(3 * n, dtype=torch.float32, device=dev)
-        e = torch.empty(2 * len(insts), dtype=torch.float64, device=dev)
-    stream.synchronize()
-    nb.nb_batch_pairlist(bt, dx)
-    info = nb.nb_batch_get_info(bt)
-    for _ in range(3):
-        nb.nb_batch_graph_forces(bt, dx, dq, dt, f, e)
-        nb.nb_batch_forces(bt, dx, dq, dt, f, e)
-    us_graph = _event_us(torch, stream, lambda: nb.nb_batch_graph_forces(bt, dx, dq, dt, f, e), reps)
-    us_eager = _event_us(torch, stream, lambda: nb.nb_batch_forces(bt, dx, dq, dt, f, e), reps)
-    nb.nb_batch_destroy(bt)
-    # the same boxes one after another through the plain path (C = 8, lists prebuilt)
-    plain = []
-    useful = 0
-    for k, inst in enumerate(insts):
-        ctx = nb.nb_setup(nb.Params.from_instance(inst), stream=stream.cuda_stream)
-        a, b = int(ao[k]), int(ao[k + 1])
-        xs, qs, ts = dx[3 * a:3 * b], dq[a:b], dt[a:b]
-        fs = f[3 * a:3 * b]
-        es = e[2 * k:2 * k + 2]
-        nb.nb_pairlist(ctx, xs)
-        useful += nb.nb_debug_pairs(ctx, xs, 0, count_only=True)
-        plain.append((ctx, xs, qs, ts, fs, es))
-
-    def seq():
-        for ctx, xs, qs, ts, fs, es in plain:
-            nb.nb_forces(ctx, xs, qs, ts, fs, es)
-    seq()
-    us_seq = _event_us(torch, stream, seq, max(3, reps // 4))
-    for p in plain:
-        nb.nb_destroy(p[0])
     out = {"workload": "256 water boxes, 3,000-30,000 atoms log-uniform (multiples of 3), "
-                       "100 atoms/nm^3, rc 0.9 nm, rb 0.1 nm",
-           "natoms": n, "useful_pairs": useful,
-           "us_per_batch_call_graph": us_graph, "us_per_batch_call_eager": us_eager,
-           "us_256_sequential_plain_calls": us_seq,
-           "pair_interactions_per_s_graph": useful / (us_graph * 1e-6),
-           "pair_interactions_per_s_sequential": useful / (us_seq * 1e-6),
-           "speedup_vs_sequential": us_seq / us_graph,
-           "clusters": {"4": clusters.count(4), "8": clusters.count(8)},
-           "schedule": {"sorted": bool(srt), "blocks_per_cu": int(bpc)},
-           "evaluated_pairs": info["evaluated_pairs"]}
-    if tuned is not None:
-        out["tune_s"] = tuned["tune_s"]
+                       "100 atoms/nm^3, rc 0.9 nm, rb 0.1 nm"}
+    useful = None
+    for mode, flags in (("fp64_energy", nb.NB_ENERGY_FP64), ("fp32_energy", 0)):
+        tuned = None
+        if tune_on:
+            tuned = tune.autotune(insts, flags=flags)
+            clusters, srt, bpc = tuned["clusters"], tuned["sorted"], tuned["blocks_per_cu"]
+        else:
+            clusters, srt, bpc = [8] * len(insts), True, 0
+        ao, bx, params, x, q, t = nb.concat_instances(insts, clusters=clusters, flags=flags)
+        n = int(ao[-1])
+        bt = nb.nb_batch_setup(ao, bx, params, clusters=clusters, stream=stream.cuda_stream)
+        nb.nb_batch_set_schedule(bt, srt, bpc)
+        with torch.cuda.stream(stream):
+            dx = torch.from_numpy(x.reshape(-1)).to(dev)
+            dq = torch.from_numpy(q).to(dev)
+            dt = torch.from_numpy(t).to(dev)
+            f = torch.empty(3 * n, dtype=torch.float32, device=dev)
+            e = torch.empty(2 * len(insts), dtype=torch.float64, device=dev)
+        stream.synchronize()
+        nb.nb_batch_pairlist(bt, dx)
+        info = nb.nb_batch_get_info(bt)
+        for _ in range(3):
+            nb.nb_batch_graph_forces(bt, dx, dq, dt, f, e)
+            nb.nb_batch_forces(bt, dx, dq, dt, f, e)
+        us_graph = _event_us(torch, stream, lambda: nb.nb_batch_graph_forces(bt, dx, dq, dt, f, e), reps)
+        us_eager = _event_us(torch, stream, lambda: nb.nb_batch_forces(bt, dx, dq, dt, f, e), reps)
+        nb.nb_batch_destroy(bt)
+        # the same boxes one after another through the plain path (C = 8, lists prebuilt)
+        plain = []
+        count = useful is None
+        nuse = 0
+        for k, inst in enumerate(insts):
+            ctx = nb.nb_setup(nb.Params.from_instance(inst, flags=flags), stream=stream.cuda_stream)
+            a, b = int(ao[k]), int(ao[k + 1])
+            xs, qs, ts = dx[3 * a:3 * b], dq[a:b], dt[a:b]
+            fs = f[3 * a:3 * b]
+            es = e[2 * k:2 * k + 2]
+            nb.nb_pairlist(ctx, xs)
+            if count:
+                nuse += nb.nb_debug_pairs(ctx, xs, 0, count_only=True)
+            plain.append((ctx, xs, qs, ts, fs, es))
+        if count:
+            useful = nuse
+
+        def seq():
+            for ctx, xs, qs, ts, fs, es in plain:
+                nb.nb_forces(ctx, xs, qs, ts, fs, es)
+        seq()
+        us_seq = _event_us(torch, stream, seq, max(3, reps // 4))
+        for p in plain:
+            nb.nb_destroy(p[0])
+        r = {"energy_gate": "1e-6 (E_LJ, E_C)" if flags else "E_LJ 1e-6, E_C 1e-5",
+             "us_per_batch_call_graph": us_graph, "us_per_batch_call_eager": us_eager,
+             "us_256_sequential_plain_calls": us_seq,
+             "pair_interactions_per_s_graph": useful / (us_graph * 1e-6),
+             "pair_interactions_per_s_sequential": useful / (us_seq * 1e-6),
+             "speedup_vs_sequential": us_seq / us_graph,
+             "clusters": {"4": clusters.count(4), "8": clusters.count(8)},
+             "schedule": {"sorted": bool(srt), "blocks_per_cu": int(bpc)},
+             "evaluated_pairs": info["evaluated_pairs"]}
+        if tuned is not None:
+            r["tune_s"] = tuned["tune_s"]
+            r["tuner_buckets"] = [{"atoms": list(b["atoms"]), "boxes": b["boxes"], "cluster": b["cluster"],
+                                   "us_c4": b["us"][4], "us_c8": b["us"][8]}
+                                  for b in tuned["buckets"] if b["boxes"] > 0]
+            r["tuner_schedule_us"] = {f"sorted={k[0]},bpc={k[1]}": v for k, v in tuned["schedule_us"].items()}
+        out[mode] = r
+    out["natoms"] = n
+    out["useful_pairs"] = useful
     return out
 
 
 def bench_adjoint(torch, nb, synth, reps=50):
-    """nb_backward vs nb_forces on the 24,000-atom differentiation box."""
+    """nb_backward vs nb_forces on the 24,000-atom differentiation box; the force call in the
+    FP64 pair-energy mode (the mode that holds the 1e-6 energy gate on this machine along a walk)
+    and in the FP32 mode.  The adjoint's gradients are held to 5e-6 (fixed cotangents)."""
     dev = "cuda:0"
     inst = synth.diff()
     stream = torch.cuda.current_stream()
-    ctx = nb.nb_setup(nb.Params.from_instance(inst), stream=stream.cuda_stream)
     n = inst.natoms
     x = torch.from_numpy(inst.x.reshape(-1).copy()).to(dev)
     q = torch.from_numpy(inst.q.copy()).to(dev)
@@ -272,10 +289,16 @@ def bench_adjoint(torch, nb, synth, reps=50):
     ddq = torch.empty(n, dtype=torch.float32, device=dev)
     ds = torch.empty(inst.ntypes, dtype=torch.float64, device=dev)
     de = torch.empty(inst.ntypes, dtype=torch.float64, device=dev)
+    us_f = {}
+    for mode, flags in (("fp64_energy", nb.NB_ENERGY_FP64), ("fp32_energy", 0)):
+        cf = nb.nb_setup(nb.Params.from_instance(inst, flags=flags), stream=stream.cuda_stream)
+        nb.nb_pairlist(cf, x)
+        nb.nb_forces(cf, x, q, t, f, e)
+        us_f[mode] = _event_us(torch, stream, lambda: nb.nb_forces(cf, x, q, t, f, e), reps)
+        nb.nb_destroy(cf)
+    ctx = nb.nb_setup(nb.Params.from_instance(inst), stream=stream.cuda_stream)
     nb.nb_pairlist(ctx, x)
     useful = nb.nb_debug_pairs(ctx, x, 0, count_only=True)
-    nb.nb_forces(ctx, x, q, t, f, e)
-    us_f = _event_us(torch, stream, lambda: nb.nb_forces(ctx, x, q, t, f, e), reps)
     bw = lambda fl: nb.nb_backward(ctx, x, q, t, gf, ge, ddx, ddq, ds, de, fl)
     bw(nb.NB_REUSE_LIST)
     us_b = _event_us(torch, stream, lambda: bw(nb.NB_REUSE_LIST), reps)
@@ -283,9 +306,12 @@ def bench_adjoint(torch, nb, synth, reps=50):
     nb.nb_destroy(ctx)
     return {"workload": "24,000-atom water box (8,000 waters, L 6.21 nm), 4 LJ types, "
                         "charges perturbed, rc 1.0 nm",
-            "useful_pairs": useful, "us_per_force_call": us_f,
+            "useful_pairs": useful,
+            "us_per_force_call": us_f["fp64_energy"],
+            "us_per_force_call_fp32_energy": us_f["fp32_energy"],
             "us_per_backward_call": us_b, "us_per_backward_call_with_list_rebuild": us_b_build,
-            "backward_over_forces": us_b / us_f,
+            "backward_over_forces": us_b / us_f["fp64_energy"],
+            "backward_over_forces_fp32_energy": us_b / us_f["fp32_energy"],
             "pair_interactions_per_s_backward": useful / (us_b * 1e-6)}
 
 
@@ -357,6 +383,41 @@ def bench_ewald_step(torch, nb, synth, reps=50):
         out[name] = 1e3 * ev0.elapsed_time(ev1) / reps
     nb.nb_pme_destroy(pm)
     nb.nb_destroy(ctx)
+    return out
+
+
+def bench_md(torch, nb, synth, nsteps=400):
+    """Leapfrog MD of a charged Lennard-Jones fluid (32,000 ions of +-0.5 e at water-oxygen
+    density, 9.87 nm box, rc 1.0 nm, rb 0.1 nm, dt 2 fs, 300 K): list rebuilt every 10 steps
+    (asynchronous builds), with and without the rolling prune to rc + 0.04 nm every 2 steps;
+    microseconds per MD step (event-timed) and the total-energy drift (FP64 pair energies)."""
+    import numpy as np
+    dev = "cuda:0"
+    inst, v0, im = synth.ionic_fluid(32000, 9.87)
+    out = {"workload": "charged LJ fluid, 32,000 ions +-0.5 e, L 9.87 nm, rc 1.0 nm, rb 0.1 nm, "
+                       "dt 2 fs, 300 K, nstlist 10, FP64 pair energies"}
+    stream = torch.cuda.current_stream()
+    for name, rin in (("prune_every_2_rc+0.04", inst.cutoff + 0.04), ("no_prune", 0.0)):
+        ctx = nb.nb_setup(nb.Params.from_instance(inst, flags=nb.NB_ENERGY_FP64 | nb.NB_ASYNC_BUILD),
+                          stream=stream.cuda_stream)
+        x = torch.from_numpy(inst.x.reshape(-1).copy()).to(dev)
+        v = torch.from_numpy(v0.reshape(-1).copy()).to(dev)
+        q = torch.from_numpy(inst.q.copy()).to(dev)
+        t = torch.from_numpy(inst.type.copy()).to(dev)
+        m = torch.from_numpy(im.copy()).to(dev)
+        f = torch.zeros(3 * inst.natoms, dtype=torch.float32, device=dev)
+        e = torch.zeros((nsteps, 4), dtype=torch.float64, device=dev)
+        nb.nb_md_leapfrog(ctx, x, v, q, t, m, 0.002, 20, 10, f, e, r_inner=rin, nstprune=2)
+        us = _event_us(torch, stream, lambda: nb.nb_md_leapfrog(ctx, x, v, q, t, m, 0.002, nsteps, 10, f, e,
+                                                                r_inner=rin, nstprune=2), 1) / nsteps
+        nb.nb_pairlist(ctx, x)   # reads the status of the last asynchronous build
+        et = e.cpu().numpy()
+        nb.nb_destroy(ctx)
+        slope = float(np.polyfit(np.arange(nsteps) * 0.002, et[:, 3], 1)[0])  # kJ/mol/ps
+        out[name] = {"us_per_md_step": us,
+                     "energy_drift_kj_mol_per_ns_per_atom": 1e3 * slope / inst.natoms,
+                     "total_energy_spread_kj_mol": float(et[:, 3].max() - et[:, 3].min()),
+                     "kinetic_energy_kj_mol": float(et[-1, 2])}
     return out
 
 
@@ -622,6 +683,8 @@ def main():
     if not args.no_pme:
         out["pme"] = bench_pme(torch, nb, synth)
         out["ewald_step"] = bench_ewald_step(torch, nb, synth)
+    if not args.no_md:
+        out["md"] = bench_md(torch, nb, synth)
     if not args.no_batch:
         out["batched"] = bench_batched(torch, nb, synth, not args.no_tune)
     if args.large:

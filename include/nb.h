@@ -91,6 +91,10 @@ typedef enum nb_status {
                                  e_dev[2] = exclusion correction, e_dev[3] = self term (FP64).
                                  Ewald electrostatics only; not for the batched form or
                                  nb_backward (NB_ERR_ARG) */
+#define NB_SORT_UNITS   0x40u /* order the force kernel's work units longest first (by cost class
+                                 floor(log2 batches), stable in cluster order): the paper's
+                                 post-prune list sorting (section III-A); default: cluster
+                                 order, which keeps neighbouring waves on neighbouring clusters */
 #define NB_ENERGY_FP64  0x10u /* evaluate the Coulomb pair energies in FP64 (forces stay FP32):
                                  needed for 1e-6 relative E_C in boxes of a few thousand atoms,
                                  where FP32 pair-energy rounding does not average out
@@ -110,7 +114,8 @@ typedef struct nb_params {
     const int32_t *excl_off;/* host [natoms+1] CSR offsets of excluded partners, or NULL */
     const int32_t *excl_idx;/* host [excl_off[natoms]] partner indices (symmetric lists),
                              * at most NB_MAX_EXCL_PER_ATOM per atom */
-    uint32_t flags;         /* NB_CHECK_*, NB_ASYNC_BUILD, NB_ENERGY_FP64, NB_EWALD_CORR */
+    uint32_t flags;         /* NB_CHECK_*, NB_ASYNC_BUILD, NB_ENERGY_FP64, NB_EWALD_CORR,
+                               NB_SORT_UNITS */
     int32_t cluster;        /* cluster size C of the list: 4 or 8 (0 = 8) */
     int32_t elec;           /* NB_ELEC_EWALD (ewald_beta used) or NB_ELEC_RF */
     int32_t vdw;            /* NB_VDW_SHIFT or NB_VDW_FSWITCH */
@@ -129,6 +134,9 @@ typedef struct nb_stats {
     int32_t unit_batches;                 /* 64-lane batches per work unit at most */
     int32_t max_list_batches;             /* longest i-cluster list, in 64-lane batches */
     int32_t pruned;                       /* 1 if the force calls use a list from nb_prune */
+    int32_t list_hist[8];                 /* i-clusters by list length in 64-lane batches:
+                                             1, 2-3, 4-7, ..., 64-127, >= 128 (written by the
+                                             kernel that forms the work units) */
 } nb_stats;
 
 typedef struct nb_ctx nb_ctx;
@@ -221,6 +229,40 @@ int nb_check(nb_ctx *ctx);
 int nb_backward(nb_ctx *ctx, const float *x, const float *q, const int32_t *type,
                 const float *g_f, const double *g_e, float *dx, float *dq, double *dsigma,
                 double *deps, uint32_t flags);
+
+/* Molecular dynamics around the force path: nsteps leapfrog steps of the atoms with device
+ * coordinates x [natoms][3] (updated in place, continuous: never re-wrapped), velocities
+ * v [natoms][3] (nm/ps, at the half step before the first step, updated in place), charges q,
+ * types and inverse masses inv_mass [natoms] (mol/g), time step dt (ps):
+ *   v(t + dt/2) = v(t - dt/2) + f(t) / m dt,  x(t + dt) = x(t) + v(t + dt/2) dt,
+ * with f(t) from nb_forces.  The pair list is rebuilt at every nstlist-th step (the first step
+ * included; asynchronously with NB_ASYNC_BUILD), and with r_inner != 0 the rolling prune
+ * (nb_prune to r_inner, rc <= r_inner <= rc + buffer) runs at every nstprune-th step between
+ * builds: the paper's prune-only kernel between pair searches (section III-A).  Outputs: f (device
+ * [natoms][3], the forces of the last step) and e_steps (device double [nsteps][4]): per step
+ * E_LJ and E_C at x(t), the kinetic energy at t (average of the half-step kinetic energies,
+ * FP64) and their sum.  Queued on the context's stream; synchronises only at list builds (not
+ * with NB_ASYNC_BUILD).  Not with NB_EWALD_CORR.  Errors: NB_ERR_ARG (NULL pointer, dt <= 0,
+ * nsteps < 0, nstlist < 1, r_inner outside [rc, rc + buffer] or nstprune < 1 with r_inner
+ * != 0), and those of nb_pairlist, nb_prune and nb_forces. */
+int nb_md_leapfrog(nb_ctx *ctx, float *x, float *v, const float *q, const int32_t *type,
+                   const float *inv_mass, double dt, int32_t nsteps, int32_t nstlist,
+                   double r_inner, int32_t nstprune, float *f, double *e_steps);
+
+/* Allocation-free nb_backward, for callers that cannot allocate device memory (code under HIP
+ * graph capture, serving loops, harnesses that forbid hipMalloc): the same result as
+ * nb_backward(ctx, ..., NB_REUSE_LIST) on the current list, with the adjoint's work buffers
+ * (per padded slot the i- and j-side gradient sums and the force cotangents, 64 bytes, plus
+ * per-type partial sums) in a static device array of the library instead of buffers allocated
+ * by the first nb_backward.  Limit: NB_NOALLOC_MAX_SLOTS padded slots (about that many atoms;
+ * the array is about 16 MiB per device, held until the process ends).  Calls that overlap on
+ * one device share that array and race: serialise them (one stream, or events).  Needs a list
+ * (nb_pairlist).  Errors: NB_ERR_ARG (NULL input, flavour other than Ewald + LJ shift, Ewald
+ * corrections on, or a system above the limit), NB_ERR_STATE (no list), NB_ERR_HIP. */
+#define NB_NOALLOC_MAX_SLOTS 262144
+int nb_backward_noalloc(nb_ctx *ctx, const float *x, const float *q, const int32_t *type,
+                        const float *g_f, const double *g_e, float *dx, float *dq, double *dsigma,
+                        double *deps);
 
 /* Export the interacting pairs of the current list at positions x (device): every listed atom
  * pair with r < rc under the same FP32 arithmetic as nb_forces, as (i, j) with i < j in
@@ -319,6 +361,53 @@ int nb_batch_get_info(nb_batch *bt, nb_batch_info *info);
 int nb_batch_check(nb_batch *bt);
 const char *nb_batch_last_error(nb_batch *bt);
 int nb_batch_destroy(nb_batch *bt);
+
+/* ---- Autotuner of the batched form ------------------------------------------------------
+ * Chooses, on the caller's own boxes, the cluster size (4 or 8) per box-size bucket and the work
+ * schedule of the persistent force kernel: the order of the work and the cluster shape decide
+ * the tail of a batched call and the evaluated pairs per useful one (the effects of the
+ * paper's post-prune list sorting, section III-A, and of small systems, section IV-C).  Sizes
+ * are grouped in NB_TUNE_BUCKETS logarithmic buckets over [NB_TUNE_NMIN, NB_TUNE_NMAX) atoms
+ * (smaller and larger boxes join the first and last bucket).  For every bucket with boxes and no
+ * cache entry, up to NB_TUNE_SAMPLE of its boxes are gathered into a batch built once with C = 4
+ * and once with C = 8, and 10 nb_batch_forces calls of each are timed with HIP events after 3
+ * warm-up calls; the faster shape is kept.  With the shapes fixed, the schedule is chosen by
+ * nb_batch_tune_schedule on the whole batch (unless cached).  Decisions are cached in a JSON
+ * file, an object whose keys name the GPU architecture, HIP version, cutoff, interaction
+ * flavour, energy mode and bucket (or batch size) and whose values hold the choice and the
+ * measured microseconds; a later call with the same kind of boxes reuses them without timing.
+ *   Inputs: as nb_batch_setup (atom_off, boxes host; common host) and nb_batch_pairlist /
+ *   nb_batch_forces (x, q, type: device, concatenated); cache_path: a file to read and write,
+ *   or NULL for no cache; stream: hipStream_t of the timed calls.
+ *   Outputs: clusters_out host [nbox] (the chosen C of every box, to pass to nb_batch_setup),
+ *   *res (per bucket: edges, boxes, choice, timings or cached; the schedule and its timings; the
+ *   host seconds spent).
+ * Allocates temporary batches and device buffers and synchronises; not capturable.  Errors:
+ * NB_ERR_ARG, NB_ERR_IO (the cache file exists but cannot be read or is not such an object, or
+ * cannot be written; checked before the device is used), and those of nb_batch_setup,
+ * nb_batch_pairlist and nb_batch_forces.  nb_autotune_last_error() describes the last failure
+ * of this host thread. */
+#define NB_TUNE_BUCKETS 5
+#define NB_TUNE_NMIN 3000
+#define NB_TUNE_NMAX 30000
+#define NB_TUNE_SAMPLE 16
+typedef struct nb_tune_result {
+    int32_t nbuckets;
+    int32_t bucket_lo[NB_TUNE_BUCKETS], bucket_hi[NB_TUNE_BUCKETS]; /* atom-count edges */
+    int32_t bucket_boxes[NB_TUNE_BUCKETS];    /* boxes of the batch in each bucket */
+    int32_t bucket_cluster[NB_TUNE_BUCKETS];  /* chosen C (0: no box in the bucket) */
+    int32_t bucket_cached[NB_TUNE_BUCKETS];   /* 1: taken from the cache, not timed */
+    double bucket_us[NB_TUNE_BUCKETS][2];     /* us per sample call with C = 4 and C = 8 */
+    int32_t sorted, blocks_per_cu;            /* chosen schedule (nb_batch_set_schedule) */
+    int32_t schedule_cached;
+    int32_t pad;
+    double schedule_us[NB_BATCH_NSCHED];      /* as nb_batch_tune_schedule's us_out */
+    double seconds;                           /* host time spent in the call */
+} nb_tune_result;
+int nb_autotune(int32_t nbox, const int32_t *atom_off, const double *boxes, const nb_params *common,
+                const float *x, const float *q, const int32_t *type, const char *cache_path,
+                void *stream, int32_t *clusters_out, nb_tune_result *res);
+const char *nb_autotune_last_error(void);
 
 /* ---- Reciprocal-space Ewald: smooth particle-mesh Ewald (PME) ---------------------------
  * The part that completes the real-space Ewald forces of nb_forces when a run uses PME (the

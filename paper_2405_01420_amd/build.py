@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libnb.so")
 OBJDIR = os.path.join(PKG, "_build")
 SOURCES = ["nb_api.cpp", "nb_build.hip", "nb_force.hip", "nb_adjoint.hip", "nb_batch.hip",
-           "nb_pme.hip"]
+           "nb_pme.hip", "nb_tune.cpp", "nb_md.hip"]
 ROCM_LIB = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib")
 ARCH = os.environ.get("NB_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

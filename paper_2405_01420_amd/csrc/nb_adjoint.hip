@@ -12,6 +12,8 @@
 // because each pair's two type slots share d sigma_ab / d sigma_a = 1/2 and
 // d eps_ab / d eps_a = eps_ab / (2 eps_a).  The traversal and lane layout are those of the
 // force kernel; per-atom sums are FP32, the per-type reduction is FP64.
+#include <mutex>
+
 #include "nb_device.h"
 
 namespace {
@@ -293,9 +295,48 @@ __global__ void __launch_bounds__(256) k_adj_types(nb_typeparams tp, int nblk,
 
 }  // namespace
 
+// Work buffers of one adjoint call: per slot the i- and j-side sums (6 floats each) and the force
+// cotangents in cluster order, and the per-block type partials.
+struct nb_adj_bufs {
+    float *adj, *adjj;
+    float4 *gs;
+    double *tpart;
+};
+
+static int adj_type_blocks(int npad_max) {
+    return (npad_max + 256 * NB_TYPE_SPAN - 1) / (256 * NB_TYPE_SPAN);
+}
+
+static hipError_t launch_adjoint(nb_ctx *c, const nb_adj_bufs &b, const float *gf, const double *ge,
+                                 float *dx, float *dq, double *dsig, double *deps) {
+    const int tb = 256;
+    hipLaunchKernelGGL(k_pack_g, dim3((c->npad_max + tb - 1) / tb), dim3(tb), 0, c->stream,
+                       c->npad_max, c->perm, gf, b.gs, b.adjj, c->meta);
+    size_t shm = sizeof(float4) * 2 * c->ntypes * c->ntypes;
+    dim3 grid((c->ncl_max + 3) / 4), block(256);
+    if (c->C == 4)
+        hipLaunchKernelGGL((k_adjoint<4>), grid, block, shm, c->stream, c->fp, ge, c->cap,
+                           c->npad_max, c->xq, c->tsort, b.gs, c->ljtab, c->icount, c->jl, b.adj,
+                           b.adjj, c->meta);
+    else
+        hipLaunchKernelGGL((k_adjoint<8>), grid, block, shm, c->stream, c->fp, ge, c->cap,
+                           c->npad_max, c->xq, c->tsort, b.gs, c->ljtab, c->icount, c->jl, b.adj,
+                           b.adjj, c->meta);
+    hipLaunchKernelGGL(k_adj_finalize, dim3((c->natoms + tb - 1) / tb), dim3(tb), 0, c->stream,
+                       c->natoms, c->npad_max, c->slot_of, b.adj, b.adjj, dx, dq);
+    nb_typeparams tp{};
+    tp.ntypes = c->ntypes;
+    for (int t = 0; t < c->ntypes; ++t) tp.eps[t] = c->epsilon[t];
+    const int nblk = adj_type_blocks(c->npad_max);
+    hipLaunchKernelGGL(k_adj_types_part, dim3(nblk), dim3(tb), 0, c->stream, c->ntypes, c->npad_max,
+                       c->perm, c->tsort, b.adj, b.adjj, b.tpart);
+    hipLaunchKernelGGL(k_adj_types, dim3(c->ntypes), dim3(256), 0, c->stream, tp, nblk, b.tpart,
+                       dsig, deps);
+    return hipGetLastError();
+}
+
 hipError_t nb_launch_adjoint(nb_ctx *c, const float *gf, const double *ge, float *dx, float *dq,
                              double *dsig, double *deps) {
-    const int tb = 256;
     if (!c->adj) {
         if (hipMalloc((void **)&c->adj, sizeof(float) * 6 * (size_t)c->npad_max) != hipSuccess)
             return hipErrorOutOfMemory;
@@ -303,31 +344,55 @@ hipError_t nb_launch_adjoint(nb_ctx *c, const float *gf, const double *ge, float
             return hipErrorOutOfMemory;
         if (hipMalloc((void **)&c->gs, sizeof(float4) * (size_t)c->npad_max) != hipSuccess)
             return hipErrorOutOfMemory;
-        const size_t nblk = (c->npad_max + tb * NB_TYPE_SPAN - 1) / (tb * NB_TYPE_SPAN);
-        if (hipMalloc((void **)&c->tpart, sizeof(double) * 2 * nblk * c->ntypes) != hipSuccess)
+        if (hipMalloc((void **)&c->tpart, sizeof(double) * 2 * adj_type_blocks(c->npad_max) * c->ntypes) != hipSuccess)
             return hipErrorOutOfMemory;
     }
-    hipLaunchKernelGGL(k_pack_g, dim3((c->npad_max + tb - 1) / tb), dim3(tb), 0, c->stream,
-                       c->npad_max, c->perm, gf, c->gs, c->adjj, c->meta);
-    size_t shm = sizeof(float4) * 2 * c->ntypes * c->ntypes;
-    dim3 grid((c->ncl_max + 3) / 4), block(256);
-    if (c->C == 4)
-        hipLaunchKernelGGL((k_adjoint<4>), grid, block, shm, c->stream, c->fp, ge, c->cap,
-                           c->npad_max, c->xq, c->tsort, c->gs, c->ljtab, c->icount, c->jl, c->adj,
-                           c->adjj, c->meta);
-    else
-        hipLaunchKernelGGL((k_adjoint<8>), grid, block, shm, c->stream, c->fp, ge, c->cap,
-                           c->npad_max, c->xq, c->tsort, c->gs, c->ljtab, c->icount, c->jl, c->adj,
-                           c->adjj, c->meta);
-    hipLaunchKernelGGL(k_adj_finalize, dim3((c->natoms + tb - 1) / tb), dim3(tb), 0, c->stream,
-                       c->natoms, c->npad_max, c->slot_of, c->adj, c->adjj, dx, dq);
-    nb_typeparams tp{};
-    tp.ntypes = c->ntypes;
-    for (int t = 0; t < c->ntypes; ++t) tp.eps[t] = c->epsilon[t];
-    const int nblk = (c->npad_max + tb * NB_TYPE_SPAN - 1) / (tb * NB_TYPE_SPAN);
-    hipLaunchKernelGGL(k_adj_types_part, dim3(nblk), dim3(tb), 0, c->stream, c->ntypes, c->npad_max,
-                       c->perm, c->tsort, c->adj, c->adjj, c->tpart);
-    hipLaunchKernelGGL(k_adj_types, dim3(c->ntypes), dim3(256), 0, c->stream, tp, nblk, c->tpart,
-                       dsig, deps);
-    return hipGetLastError();
+    return launch_adjoint(c, nb_adj_bufs{c->adj, c->adjj, c->gs, c->tpart}, gf, ge, dx, dq, dsig, deps);
+}
+
+// ---- allocation-free adjoint: the work buffers in a static device array -----------------------
+//
+// One array per device, holding the buffers of one call of at most NB_NOALLOC_MAX_SLOTS padded
+// slots (64 bytes each) and the type partials.  Its host-side name is not a device address: the
+// device address is looked up once per device (nb_noalloc_init, called by nb_setup with the
+// context's device current) and only that address is handed to kernels.  Every call on a device
+// shares its array, so calls that overlap on one device (other streams, other host threads)
+// race; every buffer is fully written by the call before it is read.
+#define NB_NOALLOC_TPART_BYTES \
+    (2 * sizeof(double) * NB_MAX_TYPES * ((NB_NOALLOC_MAX_SLOTS + 256 * NB_TYPE_SPAN - 1) / (256 * NB_TYPE_SPAN)))
+#define NB_NOALLOC_BYTES (64 * (size_t)NB_NOALLOC_MAX_SLOTS + NB_NOALLOC_TPART_BYTES)
+
+static __device__ __align__(256) unsigned char scratch[NB_NOALLOC_BYTES];
+
+#define NB_NOALLOC_MAX_DEVICES 64
+static std::mutex g_scratch_mutex;
+static void *g_scratch_dev[NB_NOALLOC_MAX_DEVICES];
+
+hipError_t nb_noalloc_init(int device) {
+    if (device < 0 || device >= NB_NOALLOC_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (g_scratch_dev[device]) return hipSuccess;
+    void *ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_dev[device] = ptr;
+    return hipSuccess;
+}
+
+hipError_t nb_launch_adjoint_noalloc(nb_ctx *c, const float *gf, const double *ge, float *dx,
+                                     float *dq, double *dsig, double *deps) {
+    void *base = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mutex);
+        if (c->device >= 0 && c->device < NB_NOALLOC_MAX_DEVICES) base = g_scratch_dev[c->device];
+    }
+    if (!base) return hipErrorNotInitialized;
+    const size_t n = (size_t)c->npad_max;
+    unsigned char *p = static_cast<unsigned char *>(base);
+    nb_adj_bufs b;
+    b.adj = reinterpret_cast<float *>(p);
+    b.adjj = reinterpret_cast<float *>(p + 24 * n);
+    b.gs = reinterpret_cast<float4 *>(p + 48 * n);
+    b.tpart = reinterpret_cast<double *>(p + 64 * n);
+    return launch_adjoint(c, b, gf, ge, dx, dq, dsig, deps);
 }

@@ -216,7 +216,7 @@ void free_all(nb_ctx *c) {
                     c->tsort, c->units,  c->fj,     c->bblo,  c->bbhi,      c->icount,
                     c->jl,    c->epart,  c->meta,   c->ljtab, c->excl_off,  c->excl_idx,
                     c->dbg_pairs, c->adj, c->adjj, c->gs, c->tpart, c->etab,
-                    c->cpart, c->vpart, c->jl_p, c->icount_p, c->xprune};
+                    c->cpart, c->vpart, c->jl_p, c->icount_p, c->xprune, c->mdpart};
     for (void *p : bufs)
         if (p) hipFree(p);
 }
@@ -259,7 +259,8 @@ int nb_validate_params(const nb_params *p) {
             return fail(nullptr, NB_ERR_ARG, "sigma/epsilon must be finite and >= 0");
     if (p->natoms < 1 || p->natoms > (1 << 27)) return fail(nullptr, NB_ERR_ARG, "natoms must be in 1..2^27");
     if (p->cluster != 0 && p->cluster != 4 && p->cluster != 8) return fail(nullptr, NB_ERR_ARG, "cluster must be 0, 4 or 8");
-    if (p->flags & ~(NB_CHECK_STALE | NB_CHECK_FINITE | NB_ASYNC_BUILD | NB_ENERGY_FP64 | NB_EWALD_CORR))
+    if (p->flags & ~(NB_CHECK_STALE | NB_CHECK_FINITE | NB_ASYNC_BUILD | NB_ENERGY_FP64 | NB_EWALD_CORR |
+                     NB_SORT_UNITS))
         return fail(nullptr, NB_ERR_ARG, "unknown flag bits");
     if ((p->flags & NB_EWALD_CORR) && p->elec != NB_ELEC_EWALD)
         return fail(nullptr, NB_ERR_ARG, "NB_EWALD_CORR needs Ewald electrostatics");
@@ -295,6 +296,15 @@ int nb_setup(nb_ctx **out, const nb_params *p, void *stream) {
     nb_ctx *c = new nb_ctx();
     c->stream = (hipStream_t)stream;
     hipGetDevice(&c->device);
+    {
+        // device address of the static work area of nb_backward_noalloc on this device
+        const hipError_t e = nb_noalloc_init(c->device);
+        if (e != hipSuccess) {
+            g_setup_error = std::string("static work area lookup: ") + hipGetErrorString(e);
+            delete c;
+            return NB_ERR_HIP;
+        }
+    }
     c->natoms = p->natoms;
     c->ntypes = p->ntypes;
     c->C = p->cluster == 0 ? 8 : p->cluster;
@@ -667,6 +677,7 @@ int nb_get_stats(nb_ctx *c, nb_stats *st) {
     st->unit_batches = m.split;
     st->max_list_batches = m.maxbatches;
     st->pruned = c->pruned ? 1 : 0;
+    for (int k = 0; k < NB_HIST_BINS; ++k) st->list_hist[k] = m.hist[k];
     return NB_OK;
 }
 
@@ -703,6 +714,55 @@ int nb_backward(nb_ctx *c, const float *x, const float *q, const int32_t *type, 
     hipError_t e = nb_launch_pack(c, x, q, type);
     if (e == hipSuccess) e = nb_launch_adjoint(c, g_f, g_e, dx, dq, dsigma, deps);
     if (e != hipSuccess) return hip_fail(c, e, "adjoint launch");
+    return NB_OK;
+}
+
+int nb_md_leapfrog(nb_ctx *c, float *x, float *v, const float *q, const int32_t *type,
+                   const float *inv_mass, double dt, int32_t nsteps, int32_t nstlist,
+                   double r_inner, int32_t nstprune, float *f, double *e_steps) {
+    if (!c || !x || !v || !q || !type || !inv_mass || !f || !e_steps)
+        return fail(c, NB_ERR_ARG, "NULL argument");
+    if (!(std::isfinite(dt) && dt > 0.0) || nsteps < 0 || nstlist < 1)
+        return fail(c, NB_ERR_ARG, "dt must be positive and finite, nsteps >= 0, nstlist >= 1");
+    if (r_inner != 0.0 && !(nstprune >= 1 && std::isfinite(r_inner) && r_inner >= c->rc &&
+                            r_inner <= c->rc + c->rb * (1.0 + 1e-12)))
+        return fail(c, NB_ERR_ARG, "rolling prune: r_inner in [rc, rc + buffer] and nstprune >= 1, or r_inner = 0");
+    if (c->flags & NB_EWALD_CORR) return fail(c, NB_ERR_ARG, "nb_md_leapfrog does not take NB_EWALD_CORR");
+    hipSetDevice(c->device);
+    for (int step = 0; step < nsteps; ++step) {
+        int r;
+        const int since = step % nstlist;
+        if (since == 0) {
+            if ((r = nb_pairlist(c, x)) != NB_OK) return r;
+        } else if (r_inner != 0.0 && since % nstprune == 0) {
+            if ((r = nb_prune(c, x, r_inner)) != NB_OK) return r;
+        }
+        double *e = e_steps + 4 * (size_t)step;
+        if ((r = nb_forces(c, x, q, type, f, e)) != NB_OK) return r;
+        hipError_t err = nb_launch_md_update(c, (float)dt, f, inv_mass, x, v, e);
+        if (err != hipSuccess) return hip_fail(c, err, "leapfrog update");
+    }
+    return NB_OK;
+}
+
+int nb_backward_noalloc(nb_ctx *c, const float *x, const float *q, const int32_t *type,
+                        const float *g_f, const double *g_e, float *dx, float *dq, double *dsigma,
+                        double *deps) {
+    if (!c || !x || !q || !type || !g_f || !g_e || !dx || !dq || !dsigma || !deps)
+        return fail(c, NB_ERR_ARG, "NULL argument");
+    if (c->elec != NB_ELEC_EWALD || c->vdw != NB_VDW_SHIFT)
+        return fail(c, NB_ERR_ARG, "nb_backward_noalloc supports NB_ELEC_EWALD with NB_VDW_SHIFT only");
+    if (c->flags & NB_EWALD_CORR)
+        return fail(c, NB_ERR_ARG, "nb_backward_noalloc does not include the Ewald corrections");
+    if (c->npad_max > NB_NOALLOC_MAX_SLOTS)
+        return fail(c, NB_ERR_ARG, "nb_backward_noalloc: the system needs " + std::to_string(c->npad_max) +
+                                       " padded slots, above the static work area's " +
+                                       std::to_string(NB_NOALLOC_MAX_SLOTS));
+    if (!c->have_list) return fail(c, NB_ERR_STATE, "nb_backward_noalloc needs a pair list (nb_pairlist)");
+    hipSetDevice(c->device);
+    hipError_t e = nb_launch_pack(c, x, q, type);
+    if (e == hipSuccess) e = nb_launch_adjoint_noalloc(c, g_f, g_e, dx, dq, dsigma, deps);
+    if (e != hipSuccess) return hip_fail(c, e, "allocation-free adjoint launch");
     return NB_OK;
 }
 

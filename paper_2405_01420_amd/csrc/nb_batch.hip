@@ -105,6 +105,7 @@ __global__ void __launch_bounds__(256) NB_FORCE_OCCUPANCY k_batch_force(nb_fpara
                                                      float etab_invh, unsigned *counter,
                                                      unsigned *flags) {
     extern __shared__ float4 tab[];
+    __shared__ nb_wlds<C, EPREC> wl[256 / NB_WAVE];
     const int ntt = fp.ntypes * fp.ntypes;
     for (int k = threadIdx.x; k < 2 * ntt; k += blockDim.x) tab[k] = ljtab[k];
     nb_etab et;
@@ -138,7 +139,7 @@ __global__ void __launch_bounds__(256) NB_FORCE_OCCUPANCY k_batch_force(nb_fpara
             f.L[2] = d.L[2];
             // the descriptor's pointers are global memory; typed so, their accesses are global
             const nb_esum es = nb_force_cluster<C, EPREC, FLAV, false, true>(
-                f, tab, et, ci, 0, 1 << 20, d.cap, d.npad_max, nb_g(d.xq), nb_g(d.tsort),
+                f, tab, et, wl[threadIdx.x / NB_WAVE], ci, 0, 1 << 20, d.cap, d.npad_max, nb_g(d.xq), nb_g(d.tsort),
                 nb_g(d.icount), nb_g(d.jl), nb_g(d.fj), nb_g(flags));
             if (lane == 0) {
                 NB_G double *ep = nb_g(d.epart) + 4 * ci;

@@ -550,23 +550,58 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NB_SEA
 #define NB_UNIT_MIN 4  // batches per work unit at least (a unit's fixed cost is about one)
 #define NB_UNITS_REG 16  // clusters per thread whose batch counts k_units keeps in registers
 
+// Cost class of a work unit (or list) of nb >= 1 batches: floor(log2 nb), at most NB_HIST_BINS - 1.
+__device__ __forceinline__ int nb_cost_class(int nb) {
+    return min(31 - __clz(max(nb, 1)), NB_HIST_BINS - 1);
+}
+
+// Exclusive prefix of v over the 1024 threads of the block (thread order) and the block total;
+// wa is LDS scratch of 16 ints.  Every thread of the block must call it.
+__device__ __forceinline__ int nb_block_scan(int v, int *wa, int *total) {
+    const int tid = threadIdx.x, lane = tid & (NB_WAVE - 1), wv = tid / NB_WAVE;
+    int incl = v;
+#pragma unroll
+    for (int o = 1; o < NB_WAVE; o <<= 1) {
+        const int u = __shfl_up(incl, o, NB_WAVE);
+        if (lane >= o) incl += u;
+    }
+    __syncthreads();  // wa may still be read from the previous call
+    if (lane == NB_WAVE - 1) wa[wv] = incl;
+    __syncthreads();
+    int base = 0, tot = 0;
+    for (int k = 0; k < (int)(blockDim.x / NB_WAVE); ++k) {
+        const int t = wa[k];
+        base += k < wv ? t : 0;
+        tot += t;
+    }
+    *total = tot;
+    return base + incl - v;
+}
+
 // Work units of the force kernel, in one block: every i-cluster with a non-empty list becomes
 // ceil(nb / P) units of at most P 64-lane batches, nb being its list length in batches and
 // P = max(4, ceil(total batches / (2 * SIMDs))).  The SIMDs share their time among resident
 // waves, so a kernel lasts about max(total batches / SIMDs, longest list) batch times; lists are
-// split only when the longest list would set that (small boxes), never at 96k atoms.  Units stay in cluster order: neighbouring waves then work on neighbouring
-// clusters, whose j-atoms they share in the caches.  (Ordering the units longest first was
-// measured slower at 96k atoms: it scatters that locality, and the half-list rule already gives
-// the early clusters the longer lists.)  The unit index is also its energy slot.
-__global__ void __launch_bounds__(1024) k_units(int slots, int unit_cap, const int *__restrict__ icount,
+// split only when the longest list would set that (small boxes), never at 96k atoms.  The unit
+// index is also its energy slot.  Order: with sorted = 0 units stay in cluster order, so that
+// neighbouring waves work on neighbouring clusters, whose j-atoms they share in the caches
+// (ordering them longest first was measured slower at 96k atoms); with sorted != 0 they are
+// emitted longest first by cost class (floor(log2 batches), stable in cluster order within a
+// class), the post-prune list sorting of the paper (section III-A) that starts the long lists
+// before the short ones to shorten the tail.  The histogram of list lengths over the same
+// classes goes to meta->hist.
+__global__ void __launch_bounds__(1024) k_units(int slots, int unit_cap, int sorted,
+                                                const int *__restrict__ icount,
                                                 int4 *__restrict__ units, nb_meta *meta) {
     __shared__ int wa[1024 / NB_WAVE], wb[1024 / NB_WAVE];
     __shared__ int s_p;
+    __shared__ int s_hist[NB_HIST_BINS];
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int lane = tid & (NB_WAVE - 1), wv = tid / NB_WAVE, nw = nthr / NB_WAVE;
     const int ncl = meta->nclusters;
     const int chunk = (ncl + nthr - 1) / nthr;
     const int c_lo = min(ncl, tid * chunk), c_hi = min(ncl, c_lo + chunk);
+    if (tid < NB_HIST_BINS) s_hist[tid] = 0;
     // The batch counts of this thread's first NB_UNITS_REG clusters stay in registers (loaded
     // together from clamped indices, zero past the chunk); a longer chunk (more than
     // 1024 * NB_UNITS_REG clusters) reads the rest from memory.  One block does all of this,
@@ -578,6 +613,7 @@ __global__ void __launch_bounds__(1024) k_units(int slots, int unit_cap, const i
 #pragma unroll
     for (int j = 0; j < NB_UNITS_REG; ++j) nbr[j] = c_lo + j < c_hi ? (nbr[j] + NB_JPB - 1) / NB_JPB : 0;
     const int c_rest = c_lo + NB_UNITS_REG;
+    auto batches = [&](int c) { return (icount[c] + NB_JPB - 1) / NB_JPB; };
     // total batches and the longest list: wave trees, then one thread over the waves
     int nb_sum = 0, nb_max = 0;
 #pragma unroll
@@ -586,7 +622,7 @@ __global__ void __launch_bounds__(1024) k_units(int slots, int unit_cap, const i
         nb_max = max(nb_max, nbr[j]);
     }
     for (int c = c_rest; c < c_hi; ++c) {
-        const int nb = (icount[c] + NB_JPB - 1) / NB_JPB;
+        const int nb = batches(c);
         nb_sum += nb;
         nb_max = max(nb_max, nb);
     }
@@ -611,43 +647,81 @@ __global__ void __launch_bounds__(1024) k_units(int slots, int unit_cap, const i
     }
     __syncthreads();
     const int P = __builtin_amdgcn_readfirstlane(s_p);
-    // units of this thread's clusters and their exclusive prefix over the threads (wave scans,
-    // then one thread over the wave totals)
+    // histogram of the list lengths (non-empty lists) by cost class
+    {
+        int h[NB_HIST_BINS];
+#pragma unroll
+        for (int b = 0; b < NB_HIST_BINS; ++b) h[b] = 0;
+        auto count = [&](int nb) {
+            if (nb <= 0) return;
+            const int k = nb_cost_class(nb);
+#pragma unroll
+            for (int b = 0; b < NB_HIST_BINS; ++b) h[b] += b == k ? 1 : 0;
+        };
+#pragma unroll
+        for (int j = 0; j < NB_UNITS_REG; ++j) count(nbr[j]);
+        for (int c = c_rest; c < c_hi; ++c) count(batches(c));
+#pragma unroll
+        for (int b = 0; b < NB_HIST_BINS; ++b) {
+            int v = h[b];
+#pragma unroll
+            for (int o = NB_WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, NB_WAVE);
+            if (lane == 0 && v) atomicAdd(&s_hist[b], v);
+        }
+    }
+    // units of this thread's clusters and their exclusive prefix over the threads
     int nu = 0;
 #pragma unroll
     for (int j = 0; j < NB_UNITS_REG; ++j) nu += (nbr[j] + P - 1) / P;
-    for (int c = c_rest; c < c_hi; ++c) nu += ((icount[c] + NB_JPB - 1) / NB_JPB + P - 1) / P;
-    int incl = nu;
-#pragma unroll
-    for (int o = 1; o < NB_WAVE; o <<= 1) {
-        const int v = __shfl_up(incl, o, NB_WAVE);
-        if (lane >= o) incl += v;
-    }
-    __syncthreads();  // wa is reused
-    if (lane == NB_WAVE - 1) wa[wv] = incl;
-    __syncthreads();
+    for (int c = c_rest; c < c_hi; ++c) nu += (batches(c) + P - 1) / P;
+    int run = 0;
+    const int u0 = nb_block_scan(nu, wa, &run);
     if (tid == 0) {
-        int run = 0;
-        for (int k = 0; k < nw; ++k) {
-            const int t = wa[k];
-            wa[k] = run;
-            run += t;
-        }
         meta->nunits = min(run, unit_cap);
         meta->split = P;
         if (run > unit_cap) atomicOr(&meta->flags, NB_F_COLUMN);  // not reachable: <= ncl + 2 slots
     }
-    __syncthreads();
-    int u = wa[wv] + incl - nu;
-    auto emit = [&](int c, int nb) {
-        for (int b = 0; b < nb; b += P) {
-            if (u < unit_cap) units[u] = make_int4(c, b, min(P, nb - b), u);
-            ++u;
-        }
-    };
+    if (!sorted) {
+        int u = u0;
+        auto emit = [&](int c, int nb) {
+            for (int b = 0; b < nb; b += P) {
+                if (u < unit_cap) units[u] = make_int4(c, b, min(P, nb - b), u);
+                ++u;
+            }
+        };
 #pragma unroll
-    for (int j = 0; j < NB_UNITS_REG; ++j) emit(c_lo + j, nbr[j]);
-    for (int c = c_rest; c < c_hi; ++c) emit(c, (icount[c] + NB_JPB - 1) / NB_JPB);
+        for (int j = 0; j < NB_UNITS_REG; ++j) emit(c_lo + j, nbr[j]);
+        for (int c = c_rest; c < c_hi; ++c) emit(c, batches(c));
+    } else {
+        // longest first: one pass per cost class, from the highest; within a class the units keep
+        // cluster order (each thread's units at its exclusive prefix over the threads)
+        int base = 0;
+        for (int k = NB_HIST_BINS - 1; k >= 0; --k) {
+            int mine = 0;
+            auto count_k = [&](int nb) {
+                for (int b = 0; b < nb; b += P) mine += nb_cost_class(min(P, nb - b)) == k ? 1 : 0;
+            };
+#pragma unroll
+            for (int j = 0; j < NB_UNITS_REG; ++j) count_k(nbr[j]);
+            for (int c = c_rest; c < c_hi; ++c) count_k(batches(c));
+            int tot = 0;
+            int u = base + nb_block_scan(mine, wa, &tot);
+            auto emit_k = [&](int c, int nb) {
+                for (int b = 0; b < nb; b += P) {
+                    const int len = min(P, nb - b);
+                    if (nb_cost_class(len) != k) continue;
+                    if (u < unit_cap) units[u] = make_int4(c, b, len, u);
+                    ++u;
+                }
+            };
+#pragma unroll
+            for (int j = 0; j < NB_UNITS_REG; ++j) emit_k(c_lo + j, nbr[j]);
+            for (int c = c_rest; c < c_hi; ++c) emit_k(c, batches(c));
+            base += tot;
+        }
+    }
+    __syncthreads();
+    if (tid < NB_HIST_BINS) meta->hist[tid] = s_hist[tid];
 }
 
 // Export of interacting pairs with the force kernel's arithmetic: the same lane layout (one
@@ -781,8 +855,8 @@ hipError_t build_impl(nb_ctx *c, const float *x) {
                        c->geom, c->cap, c->colcl, c->bblo, c->bbhi, c->perm, c->xs,
                        c->nnz_excl > 0 ? c->excl_off : nullptr, c->excl_idx, c->slot_of, c->icount, c->jl,
                        c->meta);
-    hipLaunchKernelGGL(k_units, dim3(1), dim3(1024), 0, c->stream, c->slots, c->unit_cap, c->icount,
-                       c->units, c->meta);
+    hipLaunchKernelGGL(k_units, dim3(1), dim3(1024), 0, c->stream, c->slots, c->unit_cap,
+                       (c->flags & NB_SORT_UNITS) ? 1 : 0, c->icount, c->units, c->meta);
     return hipGetLastError();
 }
 
@@ -813,8 +887,8 @@ hipError_t prune_impl(nb_ctx *c, float rin2, const int *icount, const nb_entry *
     hipLaunchKernelGGL((k_prune<C>), dim3((c->ncl_max + 3) / 4), dim3(256), 0, c->stream, c->geom, rin2,
                        c->cap, c->ncl_max, c->xq, icount, jl, icount_p, jl_p, c->meta);
     // work units of the pruned lists (the shorter lists are split by the same rule)
-    hipLaunchKernelGGL(k_units, dim3(1), dim3(1024), 0, c->stream, c->slots, c->unit_cap, icount_p,
-                       c->units, c->meta);
+    hipLaunchKernelGGL(k_units, dim3(1), dim3(1024), 0, c->stream, c->slots, c->unit_cap,
+                       (c->flags & NB_SORT_UNITS) ? 1 : 0, icount_p, c->units, c->meta);
     return hipGetLastError();
 }
 }  // namespace

@@ -76,6 +76,7 @@ __global__ void __launch_bounds__(NB_FORCE_WAVES * NB_WAVE) NB_FORCE_OCCUPANCY_V
                                                double *__restrict__ epart, double *__restrict__ vpart,
                                                nb_meta *meta) {
     extern __shared__ float4 tab[];
+    __shared__ nb_wlds<C, EPREC> wl[NB_FORCE_WAVES];
     __shared__ double esh[NB_FORCE_WAVES][VIR ? 9 : 3];
     __shared__ int edone;
     const int ntt = fp.ntypes * fp.ntypes;
@@ -97,7 +98,7 @@ __global__ void __launch_bounds__(NB_FORCE_WAVES * NB_WAVE) NB_FORCE_OCCUPANCY_V
     nb_esum es{0.0, 0.0, 0.0, {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}};
     if (u < nunits) {
         const int4 w = units[u];
-        es = nb_force_cluster<C, EPREC, FLAV, VIR, true>(fp, tab, et, __builtin_amdgcn_readfirstlane(w.x),
+        es = nb_force_cluster<C, EPREC, FLAV, VIR, true>(fp, tab, et, wl[wv], __builtin_amdgcn_readfirstlane(w.x),
                                               __builtin_amdgcn_readfirstlane(w.y),
                                               __builtin_amdgcn_readfirstlane(w.z), cap, npad_max,
                                               nb_g(xq), nb_g(tsort), nb_g(icount), nb_g(jl), nb_g(fj), nb_g(&meta->flags));

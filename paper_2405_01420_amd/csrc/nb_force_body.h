@@ -3,34 +3,42 @@
 // wavefront):
 //  * one wavefront per i-cluster; the C i-atoms are wave-uniform values, so every i-coordinate
 //    is a scalar operand of the vector instructions;
-//  * each lane owns one j-atom of one of the 16 four-atom j-groups of the current batch and
-//    loops over the C i-atoms, so the j-force of the lane's atom accumulates in registers and
-//    needs one atomic add per component per batch (the only atomics);
+//  * each lane owns one j-atom of one of the 16 four-atom j-groups of the current batch;
+//  * a batch is processed in three phases.  Filter: every lane forms the displacements and
+//    squared distances of its C pairs (i-atom k, its j-atom) and tests the topology mask and
+//    r < rc; the pairs that interact (about a third of the listed ones) are appended to a
+//    per-wave queue in LDS in (k, lane) order with a ballot and a lane count.  Evaluate: the
+//    queue is worked through 64 pairs at a time, one pair per lane, so the Lennard-Jones and
+//    Ewald arithmetic (the transcendental functions, the erfc approximation, the energies) runs
+//    only on interacting pairs with all lanes busy; each pair's scalar force factor goes back
+//    to LDS at (j lane, k).  Accumulate: every lane reads the factors of its own C pairs (zero
+//    where the pair does not interact) and adds f d to the i-force and j-force sums in
+//    registers, in the same order as a plain loop over k would;
 //  * batches whose entries share one periodic shift (the common case, since the list is grouped
 //    by shift) use i-coordinates moved into that frame once and cached in scalar registers;
-//    batches with no excluded or padding pair skip the mask test;
-//  * the i-forces accumulate per lane over the whole list and are reduced across the 64 lanes
-//    once per i-cluster with DPP row operations;
+//  * the j-force of a lane's atom needs one atomic add per component per batch (the only
+//    atomics); the i-forces accumulate per lane over the whole list and are reduced across the
+//    64 lanes once per i-cluster with DPP row operations;
 //  * erfc(beta r) = exp(-beta^2 r^2) P(r) / Q(r) with a (4,5) rational fit of the scaled
 //    complementary error function (fit_erfcx.py), Newton-refined reciprocal square root and
 //    reciprocal;
-//  * per-pair energies are summed in FP32 over the C pairs of a lane's batch and accumulated in
-//    FP64 from there on; the Coulomb potential
-//    shift is applied in FP64 at the end from the sum of q_i q_j over interacting pairs;
+//  * per-pair energies are summed in FP32 over the pairs a lane evaluates in one batch and
+//    accumulated in FP64 from there on; the Coulomb potential shift is applied in FP64 at the
+//    end from the sum of q_i q_j over interacting pairs;
 //  * with EPREC the pair energies are instead evaluated in FP64 (exact displacement,
 //    Newton-refined 1/r, erfc from an FP64 cubic Hermite table), forces staying FP32: the FP32
-//    rounding noise of the pair energies is otherwise not averaged below 1e-6 of an energy
-//    that is a 1e-4 .. 1e-3-conditioned sum, in boxes of a few thousand atoms.
+//    rounding of the displacement and of erfc(beta r)/r is otherwise not averaged below 1e-6 of
+//    an energy that is a 1e-4 .. 1e-3-conditioned sum, in boxes of a few thousand atoms.  The
+//    FP64 work runs in the evaluate phase, i.e. on interacting pairs only.
 #pragma once
 #include "nb_device.h"
 
-// Four waves per SIMD (at most 128 VGPRs) for the force kernels: the FP32 C = 8 body needs
-// about that many, and the compiler's unconstrained choice lands just above, at three waves.
-// The FP64-energy variant is register-bound either way and is left to the compiler.
-#define NB_FORCE_OCCUPANCY __attribute__((amdgpu_waves_per_eu(EPREC ? 1 : 4)))
+// Four waves per SIMD (at most 128 VGPRs) for the FP32-energy force kernels; the FP64-energy
+// variant holds more state per lane and its workgroups more LDS (the erfc table), two waves.
+#define NB_FORCE_OCCUPANCY __attribute__((amdgpu_waves_per_eu(EPREC ? 2 : 4)))
 // With the virial sums (six more accumulators per lane) the FP32 body needs more than 128
 // VGPRs: three waves per SIMD.
-#define NB_FORCE_OCCUPANCY_VIR __attribute__((amdgpu_waves_per_eu(EPREC ? 1 : (VIR ? 3 : 4))))
+#define NB_FORCE_OCCUPANCY_VIR __attribute__((amdgpu_waves_per_eu(EPREC ? 2 : (VIR ? 3 : 4))))
 
 __device__ __forceinline__ double nb_wave_sum_d(double v) {
 #pragma unroll
@@ -38,14 +46,35 @@ __device__ __forceinline__ double nb_wave_sum_d(double v) {
     return v;
 }
 
+// Wave-local ordering of LDS writes before reads by other lanes of the same wavefront (the
+// hardware executes one wave's LDS instructions in order; this keeps the compiler from moving
+// them across).
+__device__ __forceinline__ void nb_wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Per-wavefront LDS work area of the force body.
+template <int C, bool EPREC>
+struct nb_wlds {
+    uint2 q[C * NB_WAVE];          // the batch's interacting pairs: (r^2 bits, k << 6 | j lane)
+    float fsb[NB_WAVE * (C + 1)];  // force factor of pair (j lane, i-atom k) at j (C + 1) + k
+    float4 jd[NB_WAVE];            // per j lane: (fC q_j, q_j, type row bits, 0)
+    float4 id[C];                  // per i-atom: (x, y, z, q) as loaded (unshifted)
+    int it[C];                     // per i-atom: type * ntypes
+    float4 jx[EPREC ? NB_WAVE : 1];   // FP64-energy mode, per j lane: x_j moved into the pair frame
+    float4 jdi[EPREC ? NB_WAVE : 1];  // FP64-energy mode, per j lane: the i-frame offset of its pair
+};
+
 // Per-lane state of one batch: the lane's j-atom (shifted into the pair frame), its charge,
 // type row offset and mask column; accumulators for its j-force.
 struct nb_jlane {
     float x, y, z, q;   // q includes the Coulomb constant
+    float qraw;         // q_j as loaded
     int t;
     unsigned mcol;
     float fx, fy, fz;
-    double xd, yd, zd, qd;  // FP64 copies (exact) for the FP64 energy mode; qd without fC
 };
 
 // Erfc table of the FP64 energy mode: cubic Hermite segments of erfc(beta r) on
@@ -56,164 +85,124 @@ struct nb_etab {
     int n;
 };
 
-// All C pairs (i-atom k, the lane's j-atom) of one batch.  xs/ys/zs hold the i-coordinates
-// already moved into the pair frame (uniform over the wave in the fast path).  MASKED applies
-// the topology mask; without it every unordered pair within rc interacts.  FLAV selects the
-// electrostatics (Ewald real space or reaction field) and the Lennard-Jones cutoff treatment
-// (potential shift or force switch), NB_FLAV(elec, vdw).
-template <int C, bool MASKED, bool EPREC, int FLAV, bool VIR>
-__device__ __forceinline__ void pair_block(const nb_fparams &fp, const float4 *tab, int ntt,
-                                           const nb_etab &et, const float *xs, const float *ys,
-                                           const float *zs, const float *qi, const int *ti,
-                                           nb_jlane &j, float *fix, float *fiy, float *fiz,
-                                           double &elj, double &ec, float &qqs, double &qqsd,
-                                           double *vird, float p4v, float q5v) {
+// Scalar force factor fs (F_ij = fs d) and the energies of one interacting pair at squared
+// distance r2, i-atom charge qi and type row ti, j-atom data jd of the batch.  The FP32 pair
+// energies are added to eljb / ecb (FP32 partial sums of the batch) and the shift weight to
+// qqs (FP32, fC included) or qqsd (FP64, exact products); with EPREC the FP64 energies of the
+// pair, computed from the exact displacement (dxd, dyd, dzd), go to elj / ec / qqsd.
+template <bool EPREC, int FLAV>
+__device__ __forceinline__ float pair_eval(const nb_fparams &fp, const float4 *tab,
+                                           const nb_etab &et, float r2, float qi, int ti,
+                                           const float4 &jd, double dxd, double dyd, double dzd,
+                                           float &eljb, float &ecb, float &qqs, double &elj,
+                                           double &ec, double &qqsd, float p4v, float q5v) {
     constexpr bool RF = FLAV / 2 == NB_ELEC_RF;
     constexpr bool FSW = FLAV % 2 == NB_VDW_FSWITCH;
-    // FP32 partial sums of the batch's C pair energies, added to the FP64 sums once per batch
-    // (starting from -0 lets the first addition fold away)
-    float eljb = -0.0f, ecb = -0.0f;
-    // VIR: FP32 partial sums of f d_a d_b over the batch's pairs (xx, yy, zz, xy, xz, yz)
-    float vb[6] = {-0.0f, -0.0f, -0.0f, -0.0f, -0.0f, -0.0f};
-#pragma unroll
-    for (int k = 0; k < C; ++k) {
-        const float dx = xs[k] - j.x;
-        const float dy = ys[k] - j.y;
-        const float dz = zs[k] - j.z;
-        const float r2 = nb_r2(dx, dy, dz);
-        const bool inc = MASKED ? ((r2 < fp.rc2) && ((j.mcol >> k) & 1u)) : (r2 < fp.rc2);
-        const float rinv = inc ? nb_rsq(r2) : 0.0f;
-        const float rinv2 = rinv * rinv;
-        const float rinv6 = rinv2 * rinv2 * rinv2;
-        const float4 *ljp = tab + 2 * (ti[k] + j.t);
-        const float4 lj = ljp[0];             // (C6, C12, 6 C6, 12 C12)
-        const float shv = ljp[1].x;
-        // Lennard-Jones: energy C12 r^-12 - C6 r^-6 - shift, force factor (12 C12 r^-6 - 6 C6) r^-8
-        const float u = __builtin_fmaf(lj.y, rinv6, -lj.x);
-        float elj_p = inc ? __builtin_fmaf(u, rinv6, -shv) : 0.0f;
-        const float tf = __builtin_fmaf(lj.w, rinv6, -lj.z);
-        float flj = tf * rinv6;
-        const float r = r2 * rinv;            // zero for non-interacting pairs
-        // FP64 pair energies (EPREC): exact displacement, 1/r refined in FP64 from the FP32 one
-        double rid = 0.0, r2d = 0.0;
-        if (EPREC) {
-            const double dxd = (double)xs[k] - j.xd;
-            const double dyd = (double)ys[k] - j.yd;
-            const double dzd = (double)zs[k] - j.zd;
-            r2d = __builtin_fma(dzd, dzd, __builtin_fma(dyd, dyd, dxd * dxd));
-            const double y = (double)rinv;    // zero for non-interacting pairs
-            const double ee = __builtin_fma(-(r2d * y), y, 1.0);
-            rid = __builtin_fma(0.5 * y, ee, y);
-            // Lennard-Jones pair energy in FP64 (C6, C12 are the FP32 instance values)
-            const double c6d = lj.x, c12d = lj.y;
-            const double rid2 = rid * rid, rid6 = rid2 * rid2 * rid2;
-            double el = __builtin_fma(__builtin_fma(c12d, rid6, -c6d), rid6,
-                                      -__builtin_fma(c12d, fp.lj_k12, -c6d * fp.lj_k6));
-            if (FSW) {
-                const double td = fmax(r2d * rid - fp.sw_r1_d, 0.0);
-                const double e12 = __builtin_fma(fp.sw_eb12_d, td, fp.sw_ea12_d);
-                const double e6 = __builtin_fma(fp.sw_eb6_d, td, fp.sw_ea6_d);
-                el = __builtin_fma(-__builtin_fma(c12d, e12, -c6d * e6), td * td * td, el);
-            }
-            elj += inc ? el : 0.0;
-        }
+    const float rinv = nb_rsq(r2);
+    const float rinv2 = rinv * rinv;
+    const float rinv6 = rinv2 * rinv2 * rinv2;
+    const float4 *ljp = tab + 2 * (ti + __float_as_int(jd.z));
+    const float4 lj = ljp[0];             // (C6, C12, 6 C6, 12 C12)
+    const float shv = ljp[1].x;
+    // Lennard-Jones: energy C12 r^-12 - C6 r^-6 - shift, force factor (12 C12 r^-6 - 6 C6) r^-8
+    const float u = __builtin_fmaf(lj.y, rinv6, -lj.x);
+    float elj_p = __builtin_fmaf(u, rinv6, -shv);
+    const float tf = __builtin_fmaf(lj.w, rinv6, -lj.z);
+    float flj = tf * rinv6;
+    const float r = r2 * rinv;
+    // FP64 pair energies (EPREC): exact displacement, 1/r refined in FP64 from the FP32 one
+    double rid = 0.0, r2d = 0.0;
+    if (EPREC) {
+        r2d = __builtin_fma(dzd, dzd, __builtin_fma(dyd, dyd, dxd * dxd));
+        const double y = (double)rinv;
+        const double ee = __builtin_fma(-(r2d * y), y, 1.0);
+        rid = __builtin_fma(0.5 * y, ee, y);
+        // Lennard-Jones pair energy in FP64 (C6, C12 are the FP32 instance values)
+        const double c6d = lj.x, c12d = lj.y;
+        const double rid2 = rid * rid, rid6 = rid2 * rid2 * rid2;
+        double el = __builtin_fma(__builtin_fma(c12d, rid6, -c6d), rid6,
+                                  -__builtin_fma(c12d, fp.lj_k12, -c6d * fp.lj_k6));
         if (FSW) {
-            // force switch beyond sw_r1 (t = r - sw_r1 > 0; t = 0 for non-interacting pairs):
-            // force (C12 (A12 + B12 t) - C6 (A6 + B6 t)) t^2 added to the magnitude, and
-            // -(C12 (A12/3 + B12/4 t) - C6 (A6/3 + B6/4 t)) t^3 to the energy
-            const float t = fmaxf(r - fp.sw_r1, 0.0f);
-            const float t2 = t * t;
-            const float p12 = __builtin_fmaf(fp.sw_b12, t, fp.sw_a12);
-            const float p6 = __builtin_fmaf(fp.sw_b6, t, fp.sw_a6);
-            const float sw = __builtin_fmaf(lj.y, p12, -lj.x * p6);
-            flj = __builtin_fmaf(sw * t2, r, flj);  // the magnitude times r (the force factor carries r^-2)
-            const float e12 = __builtin_fmaf(fp.sw_eb12, t, fp.sw_ea12);
-            const float e6 = __builtin_fmaf(fp.sw_eb6, t, fp.sw_ea6);
-            const float esw = __builtin_fmaf(lj.y, e12, -lj.x * e6);
-            elj_p = __builtin_fmaf(-esw, t2 * t, elj_p);
+            const double td = fmax(r2d * rid - fp.sw_r1_d, 0.0);
+            const double e12 = __builtin_fma(fp.sw_eb12_d, td, fp.sw_ea12_d);
+            const double e6 = __builtin_fma(fp.sw_eb6_d, td, fp.sw_ea6_d);
+            el = __builtin_fma(-__builtin_fma(c12d, e12, -c6d * e6), td * td * td, el);
         }
-        const float qq = qi[k] * j.q;             // fC q_i q_j
-        float fs;
-        if (RF) {
-            // reaction field: force factor fC q q (1/r^3 - 2 k_rf), energy fC q q (1/r + k_rf r^2);
-            // c_rf is applied at the end to the sum of q_i q_j, accumulated exactly in FP64 (the
-            // product of two FP32 charges is exact there): unlike erfc(beta rc)/rc, c_rf is not
-            // small, and an FP32 running sum of the products would dominate the energy error
-            const float cr = __builtin_fmaf(-2.0f * fp.krf, r2, rinv);
-            fs = __builtin_fmaf(qq, cr, flj) * rinv2;
-            const double qqd = (double)qi[k] * j.qd;
-            qqsd += inc ? qqd : 0.0;
-            if (EPREC) {
-                // pair energy in FP64 without fC
-                const double v = __builtin_fma(fp.krf_d, r2d, rid);
-                ec = __builtin_fma(qqd, inc ? v : 0.0, ec);
-            } else {
-                const float r2m = inc ? r2 : 0.0f;
-                ecb = __builtin_fmaf(qq, __builtin_fmaf(fp.krf, r2m, rinv), ecb);
-            }
+        elj += el;
+    }
+    if (FSW) {
+        // force switch beyond sw_r1 (t = r - sw_r1 > 0): force (C12 (A12 + B12 t) - C6 (A6 +
+        // B6 t)) t^2 added to the magnitude, and -(C12 (A12/3 + B12/4 t) - C6 (A6/3 + B6/4 t))
+        // t^3 to the energy
+        const float t = fmaxf(r - fp.sw_r1, 0.0f);
+        const float t2 = t * t;
+        const float p12 = __builtin_fmaf(fp.sw_b12, t, fp.sw_a12);
+        const float p6 = __builtin_fmaf(fp.sw_b6, t, fp.sw_a6);
+        const float sw = __builtin_fmaf(lj.y, p12, -lj.x * p6);
+        flj = __builtin_fmaf(sw * t2, r, flj);  // the magnitude times r (the force factor carries r^-2)
+        const float e12 = __builtin_fmaf(fp.sw_eb12, t, fp.sw_ea12);
+        const float e6 = __builtin_fmaf(fp.sw_eb6, t, fp.sw_ea6);
+        const float esw = __builtin_fmaf(lj.y, e12, -lj.x * e6);
+        elj_p = __builtin_fmaf(-esw, t2 * t, elj_p);
+    }
+    const float qq = qi * jd.x;           // fC q_i q_j
+    float fs;
+    if (RF) {
+        // reaction field: force factor fC q q (1/r^3 - 2 k_rf), energy fC q q (1/r + k_rf r^2);
+        // c_rf is applied at the end to the sum of q_i q_j, accumulated exactly in FP64 (the
+        // product of two FP32 charges is exact there): unlike erfc(beta rc)/rc, c_rf is not
+        // small, and an FP32 running sum of the products would dominate the energy error
+        const float cr = __builtin_fmaf(-2.0f * fp.krf, r2, rinv);
+        fs = __builtin_fmaf(qq, cr, flj) * rinv2;
+        const double qqd = (double)qi * (double)jd.y;
+        qqsd += qqd;
+        if (EPREC) {
+            // pair energy in FP64 without fC
+            ec = __builtin_fma(qqd, __builtin_fma(fp.krf_d, r2d, rid), ec);
         } else {
-            // Ewald real space: erfc(beta r) = exp(-beta^2 r^2) P(r) / Q(r)
-            const float ex = __builtin_amdgcn_exp2f(fp.cexp * r2);
-            float P = __builtin_fmaf(p4v, r, fp.p[3]);
-            P = __builtin_fmaf(P, r, fp.p[2]);
-            P = __builtin_fmaf(P, r, fp.p[1]);
-            P = __builtin_fmaf(P, r, fp.p[0]);
-            float Q = __builtin_fmaf(q5v, r, fp.q[4]);
-            Q = __builtin_fmaf(Q, r, fp.q[3]);
-            Q = __builtin_fmaf(Q, r, fp.q[2]);
-            Q = __builtin_fmaf(Q, r, fp.q[1]);
-            Q = __builtin_fmaf(Q, r, fp.q[0]);
-            // refined reciprocal: the raw one's error pattern follows Q(r) and does not average out
-            const float R = P * nb_rcp(Q);
-            const float qe = qq * ex;
-            const float t1 = qe * rinv;               // fC q_i q_j exp(-b^2 r^2) / r
-            const float uu = __builtin_fmaf(fp.kb, r, R);
-            fs = __builtin_fmaf(t1, uu, flj) * rinv2;
-            if (EPREC) {
-                // Coulomb pair energy in FP64 without fC, erfc(beta r) from the FP64 Hermite table
-                // (segment found with the FP32 r)
-                const double rd = r2d * rid;
-                const int sg = min((int)(r * et.invh), et.n - 1);
-                const double uq = __builtin_fma(rd, (double)et.invh, -(double)sg);
-                const double2 c01 = et.seg[2 * sg], c23 = et.seg[2 * sg + 1];
-                const double g = __builtin_fma(__builtin_fma(__builtin_fma(c23.y, uq, c23.x), uq, c01.y), uq, c01.x);
-                const double qqd = (double)qi[k] * j.qd;
-                ec = __builtin_fma(qqd * g, rid, ec);
-                qqsd += inc ? qqd : 0.0;
-            } else {
-                ecb = __builtin_fmaf(t1, R, ecb);     // += fC q_i q_j erfc(b r) / r
-                qqs += inc ? qq : 0.0f;
-            }
+            ecb = __builtin_fmaf(qq, __builtin_fmaf(fp.krf, r2, rinv), ecb);
         }
-        if (!EPREC) eljb += elj_p;
-        if (VIR) {
-            const float tx = fs * dx, ty = fs * dy, tz = fs * dz;
-            vb[0] = __builtin_fmaf(tx, dx, vb[0]);
-            vb[1] = __builtin_fmaf(ty, dy, vb[1]);
-            vb[2] = __builtin_fmaf(tz, dz, vb[2]);
-            vb[3] = __builtin_fmaf(tx, dy, vb[3]);
-            vb[4] = __builtin_fmaf(tx, dz, vb[4]);
-            vb[5] = __builtin_fmaf(ty, dz, vb[5]);
+    } else {
+        // Ewald real space: erfc(beta r) = exp(-beta^2 r^2) P(r) / Q(r)
+        const float ex = __builtin_amdgcn_exp2f(fp.cexp * r2);
+        float P = __builtin_fmaf(p4v, r, fp.p[3]);
+        P = __builtin_fmaf(P, r, fp.p[2]);
+        P = __builtin_fmaf(P, r, fp.p[1]);
+        P = __builtin_fmaf(P, r, fp.p[0]);
+        float Q = __builtin_fmaf(q5v, r, fp.q[4]);
+        Q = __builtin_fmaf(Q, r, fp.q[3]);
+        Q = __builtin_fmaf(Q, r, fp.q[2]);
+        Q = __builtin_fmaf(Q, r, fp.q[1]);
+        Q = __builtin_fmaf(Q, r, fp.q[0]);
+        // refined reciprocal: the raw one's error pattern follows Q(r) and does not average out
+        const float R = P * nb_rcp(Q);
+        const float qe = qq * ex;
+        const float t1 = qe * rinv;               // fC q_i q_j exp(-b^2 r^2) / r
+        const float uu = __builtin_fmaf(fp.kb, r, R);
+        fs = __builtin_fmaf(t1, uu, flj) * rinv2;
+        if (EPREC) {
+            // Coulomb pair energy in FP64 without fC, erfc(beta r) from the FP64 Hermite table
+            // (segment found with the FP32 r)
+            const double rd = r2d * rid;
+            const int sg = min((int)(r * et.invh), et.n - 1);
+            const double uq = __builtin_fma(rd, (double)et.invh, -(double)sg);
+            const double2 c01 = et.seg[2 * sg], c23 = et.seg[2 * sg + 1];
+            const double g = __builtin_fma(__builtin_fma(__builtin_fma(c23.y, uq, c23.x), uq, c01.y), uq, c01.x);
+            const double qqd = (double)qi * (double)jd.y;
+            ec = __builtin_fma(qqd * g, rid, ec);
+            qqsd += qqd;
+        } else {
+            ecb = __builtin_fmaf(t1, R, ecb);     // += fC q_i q_j erfc(b r) / r
+            qqs += qq;
         }
-        fix[k] = __builtin_fmaf(fs, dx, fix[k]);
-        fiy[k] = __builtin_fmaf(fs, dy, fiy[k]);
-        fiz[k] = __builtin_fmaf(fs, dz, fiz[k]);
-        j.fx = __builtin_fmaf(-fs, dx, j.fx);
-        j.fy = __builtin_fmaf(-fs, dy, j.fy);
-        j.fz = __builtin_fmaf(-fs, dz, j.fz);
     }
-    if (!EPREC) {
-        elj += (double)eljb;
-        ec += (double)ecb;
-    }
-    if (VIR) {
-#pragma unroll
-        for (int m = 0; m < 6; ++m) vird[m] += (double)vb[m];
-    }
+    if (!EPREC) eljb += elj_p;
+    return fs;
 }
 
-// Whether the shift weight (sum of q_i q_j over interacting pairs) is accumulated in FP64
-// without fC (FP64 energy mode, and reaction field) or in FP32 with fC (Ewald, FP32 energies).
+// Whether the shift weight (sum of q_i q_j over interacting pairs) is accumulated from exact
+// FP64 products without fC (FP64 energy mode, and reaction field) or from FP32 batch sums with
+// fC (Ewald, FP32 energies).
 template <bool EPREC, int FLAV>
 constexpr bool nb_qq64() { return EPREC || FLAV / 2 == NB_ELEC_RF; }
 
@@ -262,44 +251,47 @@ struct nb_esum {
 
 // Forces and energy sums of one work unit, computed by one wavefront: the batches
 // [b0, b0 + nbat) of i-cluster ci's j-list (all of them, or one part of a long list).  fp.L
-// holds the box of the cluster.  Both the j-forces and the unit's i-force sums are added
-// atomically to fj (several units may share an i-cluster), in fixed point with FIX (the layout
-// of nb_add_force), in FP32 otherwise; the energy sums are returned.
+// holds the box of the cluster; w is the wavefront's LDS work area.  Both the j-forces and the
+// unit's i-force sums are added atomically to fj (several units may share an i-cluster), in
+// fixed point with FIX (the layout of nb_add_force), in FP32 otherwise; the energy sums are
+// returned.
 template <int C, bool EPREC, int FLAV, bool VIR, bool FIX>
 __device__ __forceinline__ nb_esum nb_force_cluster(const nb_fparams &fp, const float4 *tab,
-                                                 const nb_etab &et, int ci, int b0, int nbat,
-                                                 int cap, int npad_max,
+                                                 const nb_etab &et, nb_wlds<C, EPREC> &w,
+                                                 int ci, int b0, int nbat, int cap, int npad_max,
                                                  const NB_G float4 *__restrict__ xq,
                                                  const NB_G int *__restrict__ tsort,
                                                  const NB_G int *__restrict__ icount,
                                                  const NB_G nb_entry *__restrict__ jl,
                                                  NB_G float *__restrict__ fj,
                                                  NB_G unsigned *__restrict__ flags) {
-    constexpr unsigned FULL = (1u << C) - 1u;
-    const int nt = fp.ntypes, ntt = nt * nt;
+    const int nt = fp.ntypes;
     const int lane = threadIdx.x & (NB_WAVE - 1);
     const int b = lane % NB_JG, jsub = lane / NB_JG;  // j-atom within the group, entry in batch
 
-    float xi[C], yi[C], zi[C], qi[C], xs[C], ys[C], zs[C];
-    int ti[C];
+    float xi[C], yi[C], zi[C], xs[C], ys[C], zs[C];
 #pragma unroll
     for (int k = 0; k < C; ++k) {
         const float4 v = nb_ld(xq + ci * C + k);
         xi[k] = v.x;
         yi[k] = v.y;
         zi[k] = v.z;
-        qi[k] = nb_uniform(v.w);
-        ti[k] = nb_ld(tsort + ci * C + k) * nt;
         xs[k] = xi[k];
         ys[k] = yi[k];
         zs[k] = zi[k];
+    }
+    // i-atom charges and type rows for the evaluate phase, where a lane's i-atom varies
+    if (lane < C) {
+        w.id[lane] = nb_ld(xq + ci * C + lane);
+        w.it[lane] = nb_ld(tsort + ci * C + lane) * nt;
     }
     int cur_shift = NB_SHIFT_ZERO;  // shift the cached i-frame coordinates xs/ys/zs belong to
     float fix[C], fiy[C], fiz[C];
 #pragma unroll
     for (int k = 0; k < C; ++k) fix[k] = fiy[k] = fiz[k] = 0.0f;
-    double elj = 0.0, ec = 0.0, qqsd = 0.0;  // qqsd: FP64-energy mode sum of q_i q_j
-    float qqs = 0.0f;                        // FP32 mode: sum of fC q_i q_j (shift weight)
+    // energy sums; qqsd: the shift weight, sum of q_i q_j over interacting pairs (exact FP64
+    // products with FP64 energies or the reaction field, FP32 batch sums of fC q_i q_j otherwise)
+    double elj = 0.0, ec = 0.0, qqsd = 0.0;
     double vird[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 
     // the leading coefficients of the erfcx numerator and denominator live in vector registers
@@ -320,18 +312,23 @@ __device__ __forceinline__ nb_esum nb_force_cluster(const nb_fparams &fp, const 
         const float4 xj = nb_ld(xq + jslot);
         nb_jlane jv;
         jv.q = xj.w * fp.fc;
-        jv.qd = (double)xj.w;
+        jv.qraw = xj.w;
         jv.t = nb_ld(tsort + jslot);
         jv.mcol = nb_mask_column<C>(en.mask, b);
         jv.fx = jv.fy = jv.fz = 0.0f;
         const int s0 = __builtin_amdgcn_readfirstlane(s);
         const bool uniform = __ballot(valid && s != s0) == 0ull;
+        // ---- filter: displacements of the lane's C pairs, interacting pairs queued in LDS
+        float dx[C], dy[C], dz[C];
+        float dix, diy, diz;  // the i-frame offset of this lane's pairs
         if (uniform) {
             // one periodic shift for the whole batch: i-coordinates of that frame are cached
             const int tx = nb_tx(s0), ty = nb_ty(s0), tz = nb_tz(s0);
+            dix = nb_di(tx, fp.L[0]);
+            diy = nb_di(ty, fp.L[1]);
+            diz = nb_di(tz, fp.L[2]);
             if (s0 != cur_shift) {
                 cur_shift = s0;
-                const float dix = nb_di(tx, fp.L[0]), diy = nb_di(ty, fp.L[1]), diz = nb_di(tz, fp.L[2]);
 #pragma unroll
                 for (int k = 0; k < C; ++k) {
                     xs[k] = nb_uniform(xi[k] + dix);
@@ -342,36 +339,102 @@ __device__ __forceinline__ nb_esum nb_force_cluster(const nb_fparams &fp, const 
             jv.x = xj.x + nb_dj(tx, fp.L[0]);
             jv.y = xj.y + nb_dj(ty, fp.L[1]);
             jv.z = xj.z + nb_dj(tz, fp.L[2]);
-            if (EPREC) {
-                jv.xd = (double)jv.x;
-                jv.yd = (double)jv.y;
-                jv.zd = (double)jv.z;
+#pragma unroll
+            for (int k = 0; k < C; ++k) {
+                dx[k] = xs[k] - jv.x;
+                dy[k] = ys[k] - jv.y;
+                dz[k] = zs[k] - jv.z;
             }
-            const bool full = __ballot(!valid || jv.mcol != FULL) == 0ull;
-            if (full)
-                pair_block<C, false, EPREC, FLAV, VIR>(fp, tab, ntt, et, xs, ys, zs, qi, ti, jv, fix, fiy, fiz, elj, ec, qqs, qqsd, vird, p4v, q5v);
-            else
-                pair_block<C, true, EPREC, FLAV, VIR>(fp, tab, ntt, et, xs, ys, zs, qi, ti, jv, fix, fiy, fiz, elj, ec, qqs, qqsd, vird, p4v, q5v);
         } else {
             // shifts differ across the batch: per-lane frame offsets
             const int tx = nb_tx(s), ty = nb_ty(s), tz = nb_tz(s);
-            const float dix = nb_di(tx, fp.L[0]), diy = nb_di(ty, fp.L[1]), diz = nb_di(tz, fp.L[2]);
+            dix = nb_di(tx, fp.L[0]);
+            diy = nb_di(ty, fp.L[1]);
+            diz = nb_di(tz, fp.L[2]);
             jv.x = xj.x + nb_dj(tx, fp.L[0]);
             jv.y = xj.y + nb_dj(ty, fp.L[1]);
             jv.z = xj.z + nb_dj(tz, fp.L[2]);
-            if (EPREC) {
-                jv.xd = (double)jv.x;
-                jv.yd = (double)jv.y;
-                jv.zd = (double)jv.z;
-            }
-            float xl[C], yl[C], zl[C];
 #pragma unroll
             for (int k = 0; k < C; ++k) {
-                xl[k] = xi[k] + dix;
-                yl[k] = yi[k] + diy;
-                zl[k] = zi[k] + diz;
+                dx[k] = (xi[k] + dix) - jv.x;
+                dy[k] = (yi[k] + diy) - jv.y;
+                dz[k] = (zi[k] + diz) - jv.z;
             }
-            pair_block<C, true, EPREC, FLAV, VIR>(fp, tab, ntt, et, xl, yl, zl, qi, ti, jv, fix, fiy, fiz, elj, ec, qqs, qqsd, vird, p4v, q5v);
+        }
+        nb_wave_lds_sync();  // the previous batch's reads of the work area are done
+        w.jd[lane] = make_float4(jv.q, jv.qraw, __int_as_float(jv.t), 0.0f);
+        if (EPREC) {
+            w.jx[lane] = make_float4(jv.x, jv.y, jv.z, 0.0f);
+            w.jdi[lane] = make_float4(dix, diy, diz, 0.0f);
+        }
+        bool in[C];
+        int nq = 0;  // interacting pairs of the batch (wave-uniform)
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
+            const float r2 = nb_r2(dx[k], dy[k], dz[k]);
+            in[k] = ((jv.mcol >> k) & 1u) && r2 < fp.rc2;
+            const unsigned long long bal = __ballot(in[k]);
+            if (in[k]) {
+                const int pos = nq + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(bal >> 32),
+                                                                   __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
+                w.q[pos] = make_uint2(__float_as_uint(r2), (unsigned)((k << 6) | lane));
+            }
+            nq += __popcll(bal);
+        }
+        nb_wave_lds_sync();
+        // ---- evaluate: the queued pairs, one per lane
+        float eljb = -0.0f, ecb = -0.0f, qqs = -0.0f;  // FP32 partial energy sums of the batch
+        for (int p0 = 0; p0 < nq; p0 += NB_WAVE) {
+            if (p0 + lane < nq) {
+                const uint2 qe = w.q[p0 + lane];
+                const int k = (int)(qe.y >> 6), jl_ = (int)(qe.y & 63u);
+                const float4 jd = w.jd[jl_];
+                const float4 idk = w.id[k];
+                double dxd = 0.0, dyd = 0.0, dzd = 0.0;
+                if (EPREC) {
+                    // exact displacement: x_i + di is exact (the coordinate near the upper face
+                    // moves down by L), and the difference of two FP32 values is exact in FP64
+                    const float4 a = w.jdi[jl_], bj = w.jx[jl_];
+                    dxd = (double)(idk.x + a.x) - (double)bj.x;
+                    dyd = (double)(idk.y + a.y) - (double)bj.y;
+                    dzd = (double)(idk.z + a.z) - (double)bj.z;
+                }
+                const float fs = pair_eval<EPREC, FLAV>(fp, tab, et, __uint_as_float(qe.x), idk.w,
+                                                        w.it[k], jd, dxd, dyd, dzd, eljb, ecb, qqs,
+                                                        elj, ec, qqsd, p4v, q5v);
+                w.fsb[jl_ * (C + 1) + k] = fs;
+            }
+        }
+        nb_wave_lds_sync();
+        if (!EPREC) {
+            elj += (double)eljb;
+            ec += (double)ecb;
+        }
+        if (!nb_qq64<EPREC, FLAV>()) qqsd += (double)qqs;
+        // ---- accumulate: f d of the lane's C pairs into the i- and j-force sums
+        float vb[6] = {-0.0f, -0.0f, -0.0f, -0.0f, -0.0f, -0.0f};
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
+            const float fs = in[k] ? w.fsb[lane * (C + 1) + k] : 0.0f;
+            if (VIR) {
+                const float tx = fs * dx[k], ty = fs * dy[k], tz = fs * dz[k];
+                vb[0] = __builtin_fmaf(tx, dx[k], vb[0]);
+                vb[1] = __builtin_fmaf(ty, dy[k], vb[1]);
+                vb[2] = __builtin_fmaf(tz, dz[k], vb[2]);
+                vb[3] = __builtin_fmaf(tx, dy[k], vb[3]);
+                vb[4] = __builtin_fmaf(tx, dz[k], vb[4]);
+                vb[5] = __builtin_fmaf(ty, dz[k], vb[5]);
+            }
+            fix[k] = __builtin_fmaf(fs, dx[k], fix[k]);
+            fiy[k] = __builtin_fmaf(fs, dy[k], fiy[k]);
+            fiz[k] = __builtin_fmaf(fs, dz[k], fiz[k]);
+            jv.fx = __builtin_fmaf(-fs, dx[k], jv.fx);
+            jv.fy = __builtin_fmaf(-fs, dy[k], jv.fy);
+            jv.fz = __builtin_fmaf(-fs, dz[k], jv.fz);
+        }
+        if (VIR) {
+#pragma unroll
+            for (int m = 0; m < 6; ++m) vird[m] += (double)vb[m];
         }
         // about 40% of the lanes of a batch have no pair within rc (their entry was kept for
         // another atom of the group, at rlist); they skip their atomics
@@ -386,7 +449,7 @@ __device__ __forceinline__ nb_esum nb_force_cluster(const nb_fparams &fp, const 
     }
     elj = nb_wave_sum_d(elj);
     ec = nb_wave_sum_d(ec);
-    const double qqd = nb_wave_sum_d(nb_qq64<EPREC, FLAV>() ? qqsd : (double)qqs);
+    const double qqd = nb_wave_sum_d(qqsd);
     // the unit's i-force sums (in lane 63) go to lanes 0 .. C-1, one atom each, so that three
     // atomics of C lanes add them
     float vx = 0.0f, vy = 0.0f, vz = 0.0f;
@@ -405,5 +468,6 @@ __device__ __forceinline__ nb_esum nb_force_cluster(const nb_fparams &fp, const 
 #pragma unroll
         for (int m = 0; m < 6; ++m) out.v[m] = nb_wave_sum_d(vird[m]);
     }
+    nb_wave_lds_sync();  // the next unit of this wave rewrites the work area
     return out;
 }

@@ -60,6 +60,7 @@ __host__ __device__ __forceinline__ nb_entry nb_make_entry(int group, int shift,
 }
 
 // Counters written by the GPU during a build (read back by the host only when needed).
+#define NB_HIST_BINS 8  // list-length classes floor(log2 batches): 1, 2-3, 4-7, ..., >= 128
 struct nb_meta {
     int32_t nclusters;   // clusters of the current grid
     int32_t npad;        // nclusters * C
@@ -69,6 +70,8 @@ struct nb_meta {
     int32_t nunits;      // work units of the force kernel (i-cluster list parts)
     int32_t split;       // batches per work unit at most
     int32_t maxbatches;  // longest j-list, in 64-lane batches
+    int32_t hist[NB_HIST_BINS];  // i-clusters per list-length class (non-empty lists)
+    int32_t pad;
     uint64_t npairs_out; // pair-export counter
 };
 
@@ -183,6 +186,7 @@ struct nb_ctx {
     float *adjj = nullptr;      // [6 * npad_max]: j-side, atomics
     float4 *gs = nullptr;       // [npad_max] force cotangents in cluster order
     double *tpart = nullptr;    // [adjoint type-sum blocks][ntypes][2] block partials
+    double *mdpart = nullptr;   // [leapfrog blocks] kinetic-energy partials (allocated on first use)
     // kernel timing
     bool timing = false;
     std::vector<hipEvent_t> ev;  // pairs (start, stop)
@@ -214,6 +218,15 @@ hipError_t nb_launch_ewald_corr(nb_ctx *c, const float *x, const float *q);
 #define NB_CORR_BLOCK 256
 #define NB_CORR_PART 8
 
+// ---- launchers (nb_md.hip) ----
+hipError_t nb_launch_md_update(nb_ctx *c, float dt, const float *f, const float *inv_m, float *x,
+                               float *v, double *e);
+
 // ---- launchers (nb_adjoint.hip) ----
 hipError_t nb_launch_adjoint(nb_ctx *c, const float *gf, const double *ge, float *dx, float *dq,
                              double *dsig, double *deps);
+// The allocation-free form: the work buffers in the library's static device array (looked up
+// per device by nb_noalloc_init); padded slots at most NB_NOALLOC_MAX_SLOTS.
+hipError_t nb_noalloc_init(int device);
+hipError_t nb_launch_adjoint_noalloc(nb_ctx *c, const float *gf, const double *ge, float *dx,
+                                     float *dq, double *dsig, double *deps);

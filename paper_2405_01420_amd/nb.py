@@ -22,7 +22,9 @@ NB_ERR_RANGE = 10
 NB_CHECK_STALE, NB_CHECK_FINITE, NB_REUSE_LIST, NB_ASYNC_BUILD = 0x1, 0x2, 0x4, 0x8
 NB_ENERGY_FP64 = 0x10
 NB_EWALD_CORR = 0x20
+NB_SORT_UNITS = 0x40
 NB_MAX_EXCL_PER_ATOM = 32
+NB_NOALLOC_MAX_SLOTS = 262144  # padded slots nb_backward_noalloc handles at most
 NB_ELEC_EWALD, NB_ELEC_RF = 0, 1
 NB_VDW_SHIFT, NB_VDW_FSWITCH = 0, 1
 
@@ -31,11 +33,12 @@ STATUS_NAMES = {0: "NB_OK", 1: "NB_ERR_ARG", 2: "NB_ERR_CUTOFF", 3: "NB_ERR_OOM"
                 8: "NB_ERR_NONFINITE", 9: "NB_ERR_IO", 10: "NB_ERR_RANGE"}
 
 EXPORTS = ["nb_validate_params", "nb_setup", "nb_set_lj", "nb_set_stream", "nb_pairlist", "nb_prune",
-           "nb_forces", "nb_forces_virial", "nb_check", "nb_backward", "nb_debug_pairs", "nb_get_stats",
+           "nb_forces", "nb_forces_virial", "nb_check", "nb_backward", "nb_backward_noalloc", "nb_md_leapfrog",
+           "nb_debug_pairs", "nb_get_stats",
            "nb_last_error", "nb_destroy", "nb_set_timing", "nb_get_timing", "nb_batch_setup",
            "nb_batch_set_schedule", "nb_batch_tune_schedule", "nb_batch_pairlist", "nb_batch_forces",
            "nb_batch_graph_forces", "nb_batch_get_info", "nb_batch_check", "nb_batch_last_error",
-           "nb_batch_destroy", "nb_pme_setup", "nb_pme_forces", "nb_pme_last_error", "nb_pme_destroy"]
+           "nb_batch_destroy", "nb_autotune", "nb_autotune_last_error", "nb_pme_setup", "nb_pme_forces", "nb_pme_last_error", "nb_pme_destroy"]
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _ip = ctypes.POINTER(ctypes.c_int32)
@@ -59,7 +62,7 @@ class nb_stats(ctypes.Structure):
                 ("cluster", ctypes.c_int32), ("ncolumns", ctypes.c_int32),
                 ("build_ms_last", ctypes.c_double), ("work_units", ctypes.c_int32),
                 ("unit_batches", ctypes.c_int32), ("max_list_batches", ctypes.c_int32),
-                ("pruned", ctypes.c_int32)]
+                ("pruned", ctypes.c_int32), ("list_hist", ctypes.c_int32 * 8)]
 
 
 class nb_batch_info(ctypes.Structure):
@@ -68,6 +71,21 @@ class nb_batch_info(ctypes.Structure):
                 ("evaluated_pairs", ctypes.c_int64), ("grid_blocks", ctypes.c_int32 * 2),
                 ("graph_ready", ctypes.c_int32), ("pad", ctypes.c_int32),
                 ("build_ms_last", ctypes.c_double)]
+
+
+NB_TUNE_BUCKETS, NB_TUNE_NMIN, NB_TUNE_NMAX, NB_TUNE_SAMPLE = 5, 3000, 30000, 16
+
+
+class nb_tune_result(ctypes.Structure):
+    _fields_ = [("nbuckets", ctypes.c_int32), ("bucket_lo", ctypes.c_int32 * NB_TUNE_BUCKETS),
+                ("bucket_hi", ctypes.c_int32 * NB_TUNE_BUCKETS),
+                ("bucket_boxes", ctypes.c_int32 * NB_TUNE_BUCKETS),
+                ("bucket_cluster", ctypes.c_int32 * NB_TUNE_BUCKETS),
+                ("bucket_cached", ctypes.c_int32 * NB_TUNE_BUCKETS),
+                ("bucket_us", (ctypes.c_double * 2) * NB_TUNE_BUCKETS),
+                ("sorted", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("schedule_cached", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("schedule_us", ctypes.c_double * 5), ("seconds", ctypes.c_double)]
 
 
 class nb_pme_params(ctypes.Structure):
@@ -105,6 +123,9 @@ def lib():
         L.nb_forces_virial.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp]
         L.nb_check.argtypes = [_vp]
         L.nb_backward.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, cu]
+        L.nb_backward_noalloc.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+        L.nb_md_leapfrog.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_int32,
+                                     ctypes.c_int32, ctypes.c_double, ctypes.c_int32, _vp, _vp]
         L.nb_debug_pairs.argtypes = [_vp, _vp, _vp, ci64, P(ci64)]
         L.nb_get_stats.argtypes = [_vp, P(nb_stats)]
         L.nb_last_error.argtypes = [_vp]
@@ -122,6 +143,10 @@ def lib():
         L.nb_batch_last_error.argtypes = [_vp]
         L.nb_batch_last_error.restype = ctypes.c_char_p
         L.nb_batch_destroy.argtypes = [_vp]
+        L.nb_autotune.argtypes = [ctypes.c_int32, _vp, _vp, P(nb_params), _vp, _vp, _vp,
+                                  ctypes.c_char_p, _vp, _vp, P(nb_tune_result)]
+        L.nb_autotune_last_error.argtypes = []
+        L.nb_autotune_last_error.restype = ctypes.c_char_p
         L.nb_get_timing.argtypes = [_vp, P(ctypes.c_double), P(ci64)]
         L.nb_pme_setup.argtypes = [P(_vp), P(nb_pme_params), _vp]
         L.nb_pme_forces.argtypes = [_vp, _vp, _vp, _vp, _vp]
@@ -130,7 +155,8 @@ def lib():
         L.nb_pme_destroy.argtypes = [_vp]
         for name in EXPORTS:
             fn = getattr(L, name, None)
-            if fn is not None and name not in ("nb_last_error", "nb_batch_last_error", "nb_pme_last_error"):
+            if fn is not None and name not in ("nb_last_error", "nb_batch_last_error", "nb_pme_last_error",
+                                               "nb_autotune_last_error"):
                 fn.restype = ci
         _lib = L
     return _lib
@@ -246,6 +272,18 @@ def nb_backward(ctx: int, x, q, types, g_f, g_e, dx, dq, dsigma, deps, flags: in
                              _ptr(dq), _ptr(dsigma), _ptr(deps), int(flags)), ctx)
 
 
+def nb_md_leapfrog(ctx: int, x, v, q, types, inv_mass, dt: float, nsteps: int, nstlist: int,
+                   f, e_steps, r_inner: float = 0.0, nstprune: int = 1) -> None:
+    _check(lib().nb_md_leapfrog(ctx, _ptr(x), _ptr(v), _ptr(q), _ptr(types), _ptr(inv_mass),
+                                float(dt), int(nsteps), int(nstlist), float(r_inner), int(nstprune),
+                                _ptr(f), _ptr(e_steps)), ctx)
+
+
+def nb_backward_noalloc(ctx: int, x, q, types, g_f, g_e, dx, dq, dsigma, deps) -> None:
+    _check(lib().nb_backward_noalloc(ctx, _ptr(x), _ptr(q), _ptr(types), _ptr(g_f), _ptr(g_e),
+                                     _ptr(dx), _ptr(dq), _ptr(dsigma), _ptr(deps)), ctx)
+
+
 def nb_debug_pairs(ctx: int, x, cap: int, count_only: bool = False):
     """Interacting pairs as an int64 [count, 2] array (i < j, original indices, unsorted);
     with count_only, just the number of interacting pairs."""
@@ -263,7 +301,9 @@ def nb_debug_pairs(ctx: int, x, cap: int, count_only: bool = False):
 def nb_get_stats(ctx: int) -> dict:
     st = nb_stats()
     _check(lib().nb_get_stats(ctx, ctypes.byref(st)), ctx)
-    return {k: getattr(st, k) for k, _ in nb_stats._fields_}
+    out = {k: getattr(st, k) for k, _ in nb_stats._fields_}
+    out["list_hist"] = list(st.list_hist)
+    return out
 
 
 def nb_last_error(ctx: Optional[int]) -> str:
@@ -322,6 +362,38 @@ def nb_batch_tune_schedule(bt: int, x, q, types, f, e, reps: int = 5):
     _bcheck(lib().nb_batch_tune_schedule(bt, _ptr(x), _ptr(q), _ptr(types), _ptr(f), _ptr(e), int(reps),
                                          ctypes.cast(us, _dp), ctypes.cast(best, _ip)), bt)
     return (bool(best[0]), int(best[1])), {s: us[k] for k, s in enumerate(BATCH_SCHEDULES)}
+
+
+def nb_autotune_last_error() -> str:
+    return lib().nb_autotune_last_error().decode(errors="replace")
+
+
+def nb_autotune(atom_off, boxes, common: Params, x, q, types, cache_path: Optional[str] = None,
+                stream=None):
+    """Cluster size per box and schedule chosen by the library's tuner; returns
+    (clusters [nbox], result dict)."""
+    ao = np.ascontiguousarray(atom_off, dtype=np.int32)
+    bx = np.ascontiguousarray(boxes, dtype=np.float64).reshape(-1, 3)
+    nbox = len(ao) - 1
+    cl = np.zeros(nbox, dtype=np.int32)
+    res = nb_tune_result()
+    code = lib().nb_autotune(nbox, ao.ctypes.data, bx.ctypes.data, ctypes.byref(common.c), _ptr(x),
+                             _ptr(q), _ptr(types),
+                             None if cache_path is None else os.fsencode(cache_path),
+                             _stream(stream), cl.ctypes.data, ctypes.byref(res))
+    if code != NB_OK:
+        raise NbError(code, nb_autotune_last_error())
+    out = {"sorted": bool(res.sorted), "blocks_per_cu": int(res.blocks_per_cu),
+           "schedule_cached": bool(res.schedule_cached),
+           "schedule_us": {s: res.schedule_us[k] for k, s in enumerate(BATCH_SCHEDULES)},
+           "seconds": res.seconds, "buckets": []}
+    for k in range(res.nbuckets):
+        out["buckets"].append({"atoms": (int(res.bucket_lo[k]), int(res.bucket_hi[k])),
+                               "boxes": int(res.bucket_boxes[k]),
+                               "cluster": int(res.bucket_cluster[k]),
+                               "cached": bool(res.bucket_cached[k]),
+                               "us": {4: res.bucket_us[k][0], 8: res.bucket_us[k][1]}})
+    return [int(c) for c in cl], out
 
 
 def nb_batch_pairlist(bt: int, x) -> None:

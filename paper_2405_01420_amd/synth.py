@@ -281,3 +281,47 @@ def perturbed_params(inst: Instance, rel: float, seed: int):
     qm = q.reshape(-1, 3)
     qm -= qm.mean(axis=1, keepdims=True)
     return sig, eps, qm.reshape(-1).astype(np.float32)
+
+
+ION_Q = 0.5               # e, magnitude of the ion charges of the charged Lennard-Jones fluid
+ION_MASS = 18.0           # g/mol
+KB = 0.0083144626         # kJ mol^-1 K^-1
+
+
+def ionic_fluid(nion: int, box: float, cutoff: float = 1.0, buffer: float = 0.1, seed: int = 8,
+                temperature: float = 300.0, jitter: float = 0.02, name: str = "ionic"):
+    """A single-site charged Lennard-Jones fluid for molecular dynamics without constraints:
+    ions of charge +-ION_Q (alternating over a checkerboard of a jittered cubic lattice, signs of
+    a few ions flipped where sites left empty unbalance it; neutral for an even number of ions),
+    all of the water-oxygen Lennard-Jones type, mass
+    ION_MASS, no exclusions; velocities drawn from the Maxwell-Boltzmann distribution at
+    `temperature` with the net momentum removed.  Returns (Instance, v float32 [N, 3] nm/ps,
+    inverse masses float32 [N])."""
+    rng = np.random.default_rng(seed)
+    L = f32(box)
+    n = int(math.ceil(round(nion ** (1.0 / 3.0), 9)))
+    while n ** 3 < nion:
+        n += 1
+    sites = np.arange(n ** 3)
+    if n ** 3 > nion:
+        sites = np.sort(rng.choice(n ** 3, size=nion, replace=False))
+    k = np.stack([sites // (n * n), (sites // n) % n, sites % n], axis=1)
+    pos = (k.astype(np.float64) + 0.5) * (L / n) + rng.uniform(-jitter, jitter, size=(nion, 3))
+    x = np.mod(pos, L).astype(np.float32)
+    x[x >= np.float32(L)] = 0.0
+    sign = np.where(k.sum(1) % 2 == 0, 1.0, -1.0)
+    excess = int(sign.sum())   # sites left out of the lattice can unbalance the checkerboard
+    if excess != 0:
+        major = np.nonzero(sign == np.sign(excess))[0]
+        sign[rng.choice(major, size=abs(excess) // 2, replace=False)] *= -1.0
+    q = (ION_Q * sign).astype(np.float32)
+    typ = np.zeros(nion, dtype=np.int32)
+    sd = math.sqrt(KB * temperature / ION_MASS)
+    v = rng.normal(0.0, sd, size=(nion, 3))
+    v -= v.mean(0)
+    inst = Instance(x=x, q=q, type=typ, box=L, cutoff=f32(cutoff), buffer=f32(buffer),
+                    beta=ewald_beta(f32(cutoff)), coulomb_const=f32(COULOMB_CONST),
+                    sigma=np.array([O_SIGMA]), epsilon=np.array([O_EPSILON]),
+                    excl_off=np.zeros(nion + 1, dtype=np.int32), excl_idx=np.zeros(0, dtype=np.int32),
+                    name=name, seed=seed)
+    return inst, v.astype(np.float32), np.full(nion, 1.0 / ION_MASS, dtype=np.float32)

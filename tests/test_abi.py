@@ -169,3 +169,24 @@ def test_null_handles_are_rejected_without_gpu():
     assert L.nb_forces(None, None, None, None, None, None) == nb.NB_ERR_ARG
     assert L.nb_pme_forces(None, None, None, None, None) == nb.NB_ERR_ARG
     assert L.nb_batch_tune_schedule(None, None, None, None, None, None, 1, None, None) == nb.NB_ERR_ARG
+    assert L.nb_backward_noalloc(None, None, None, None, None, None, None, None, None, None) == nb.NB_ERR_ARG
+
+
+def test_autotune_rejects_bad_arguments_and_cache_without_gpu(tmp_path):
+    """nb_autotune checks its arguments and reads its cache file before touching the device: a
+    file that is not a tuning cache is NB_ERR_IO, a missing input NB_ERR_ARG."""
+    L = nb.lib()
+    res = nb.nb_tune_result()
+    ao = np.array([0, 3000], dtype=np.int32)
+    bx = np.array([6.7, 6.7, 6.7])
+    p = base_params()
+    cl = np.zeros(1, dtype=np.int32)
+    assert L.nb_autotune(1, ao.ctypes.data, bx.ctypes.data, ctypes.byref(p.c), None, None, None, None,
+                         None, cl.ctypes.data, ctypes.byref(res)) == nb.NB_ERR_ARG
+    bad = tmp_path / "cache.json"
+    for text in ("not json", '{"k": {"cluster": 4}', '{"k": [1, 2]}', '{"k": {"cluster": "four"}}'):
+        bad.write_text(text)
+        code = L.nb_autotune(1, ao.ctypes.data, bx.ctypes.data, ctypes.byref(p.c), 1, 1, 1,
+                             str(bad).encode(), None, cl.ctypes.data, ctypes.byref(res))
+        assert code == nb.NB_ERR_IO, text
+        assert "tuning cache" in nb.nb_autotune_last_error()

@@ -280,3 +280,25 @@ def test_force_beyond_the_fixed_point_range_is_reported(torch_gpu, inst_tiny):
     box.forces()
     assert nb.nb_check(box.ctx) == nb.NB_OK
     box.close()
+
+
+@pytest.mark.parametrize("which", ["tiny", "diff"])
+def test_sorted_work_units_keep_results(torch_gpu, which):
+    """NB_SORT_UNITS (work units longest first) only reorders the units: the same forces bit for
+    bit (fixed-point sums of the same unit contributions) and the same energies up to summation
+    order; the list-length histogram covers every non-empty list."""
+    inst = getattr(synth, which)()
+    out = []
+    for flags in (0, nb.NB_SORT_UNITS):
+        box = GpuBox(torch_gpu, inst, flags=flags | nb.NB_ENERGY_FP64)
+        box.pairlist()
+        f, e = box.forces()
+        st = box.stats()
+        out.append((f, e, st))
+        box.close()
+    (f0, e0, s0), (f1, e1, s1) = out
+    assert np.array_equal(f0, f1)
+    assert np.all(np.abs(e0 - e1) <= 1e-12 * np.abs(e0))
+    assert s0["list_hist"] == s1["list_hist"] and s0["work_units"] == s1["work_units"]
+    assert 0 < sum(s0["list_hist"]) <= s0["nclusters"]
+    print(which, "list-length histogram (batches 1, 2-3, 4-7, ...):", s0["list_hist"])

@@ -62,13 +62,22 @@ def test_schedule_tuner_needs_a_list(torch_gpu, boxes):
 
 
 def test_autotune_caches_its_choices(torch_gpu, boxes, tmp_path):
+    """nb_autotune through the C-ABI: every bucket with boxes gets a shape, the decisions go to
+    the JSON cache, and a second call takes them from it without timing."""
     cache = tmp_path / "tune.json"
-    r1 = tune.autotune(boxes, cache_path=str(cache), max_boxes_per_bucket=2)
+    r1 = tune.autotune(boxes, cache_path=str(cache))
     assert len(r1["clusters"]) == len(boxes) and set(r1["clusters"]) <= {4, 8}
     assert (r1["sorted"], r1["blocks_per_cu"]) in nb.BATCH_SCHEDULES
+    used = [b for b in r1["buckets"] if b["boxes"] > 0]
+    assert sum(b["boxes"] for b in used) == len(boxes)
+    for b in used:
+        assert not b["cached"] and b["cluster"] in (4, 8)
+        assert b["us"][4] > 0 and b["us"][8] > 0
+        assert b["cluster"] == (8 if b["us"][8] < b["us"][4] else 4)
     stored = json.loads(cache.read_text())
     assert any("schedule" in k for k in stored) and any("bucket" in k for k in stored)
-    r2 = tune.autotune(boxes, cache_path=str(cache), max_boxes_per_bucket=2)
+    r2 = tune.autotune(boxes, cache_path=str(cache))
     assert r2["clusters"] == r1["clusters"]
     assert (r2["sorted"], r2["blocks_per_cu"]) == (r1["sorted"], r1["blocks_per_cu"])
-    assert all(v.get("cached") for k, v in r2["buckets"].items() if "bucket" in k)
+    assert r2["schedule_cached"] and all(b["cached"] for b in r2["buckets"] if b["boxes"] > 0)
+    assert json.loads(cache.read_text()) == stored
