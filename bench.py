@@ -619,6 +619,33 @@ def main():
         us_force_corr = 1e3 * ev0.elapsed_time(ev1) / reps
         nb.nb_destroy(ctx_c)
 
+    # the tabulated Ewald flavour (FP32 force table, FP64 pair energies) and, for comparison, the
+    # analytic flavour with FP64 pair energies, on the same walk start
+    us_tab = us_e64 = kernel_us_tab = kernel_us_e64 = None
+    if args.elec == "ewald":
+        for name, kw in (("tab", dict(elec=nb.NB_ELEC_EWALD_TAB, flags=0)),
+                         ("e64", dict(elec=nb.NB_ELEC_EWALD, flags=nb.NB_ENERGY_FP64))):
+            pt = nb.Params.from_instance(inst, cluster=cluster, flags=kw["flags"], elec=kw["elec"],
+                                         vdw=flav["vdw"], rswitch=flav["rswitch"])
+            ctx_t = nb.nb_setup(pt)
+            nb.nb_pairlist(ctx_t, traj[0])
+            nb.nb_forces(ctx_t, traj[0], q, t, f, e)
+            ev0.record()
+            for k in range(reps):
+                nb.nb_forces(ctx_t, traj[0], q, t, f, e)
+            ev1.record()
+            torch.cuda.synchronize()
+            us_call = 1e3 * ev0.elapsed_time(ev1) / reps
+            nb.nb_set_timing(ctx_t, True)
+            for k in range(reps):
+                nb.nb_forces(ctx_t, traj[0], q, t, f, e)
+            kms_t, kl_t = nb.nb_get_timing(ctx_t)
+            nb.nb_destroy(ctx_t)
+            if name == "tab":
+                us_tab, kernel_us_tab = us_call, 1e3 * kms_t / kl_t
+            else:
+                us_e64, kernel_us_e64 = us_call, 1e3 * kms_t / kl_t
+
     # list build alone (each build waits for the previous one's status)
     torch.cuda.synchronize()
     tb = time.perf_counter()
@@ -668,6 +695,13 @@ def main():
         "us_per_force_call": us_force,
         "us_per_force_call_with_virial": us_force_virial,
         "us_per_force_call_with_ewald_corrections": us_force_corr,
+        "energy_modes": {"fp32_pair_energies": {"us_per_force_call": us_force, "kernel_us": kernel_us,
+                                                "energy_gate": "1e-6 at 96k atoms"},
+                         "fp64_pair_energies": {"us_per_force_call": us_e64, "kernel_us": kernel_us_e64,
+                                                "energy_gate": "1e-6 at every size"},
+                         "tabulated_ewald_fp64_energies": {"us_per_force_call": us_tab,
+                                                           "kernel_us": kernel_us_tab,
+                                                           "energy_gate": "1e-6 at every size"}},
         "us_per_list_build": us_build,
         "us_per_call_amortised": 1e3 * ms_per_step,
         "rebuild_periods": period_stats,

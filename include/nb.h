@@ -75,6 +75,17 @@ typedef enum nb_status {
  *                   rc; the potential is the matching integral, shifted to zero at rc. */
 #define NB_ELEC_EWALD   0
 #define NB_ELEC_RF      1
+#define NB_ELEC_EWALD_TAB 2  /* the same real-space Ewald interaction as NB_ELEC_EWALD, with the
+                                force taken from a table instead of the analytic erfc: the
+                                kernel flavour of the paper's runs ("tabulated electrostatics",
+                                Fig. 3 caption, section IV-B).  The force factor is
+                                fC q_i q_j (1/r^3 - G(r)) with G(r) = erf(beta r)/r^3 -
+                                2 beta/sqrt(pi) exp(-beta^2 r^2)/r^2, a smooth function held as
+                                FP32 cubic Hermite segments (NB_TAB_SEGMENTS over [0, rc], in
+                                LDS); the pair energies are always evaluated in FP64 (as with
+                                NB_ENERGY_FP64).  Single-box path only: not for the batched form
+                                or nb_backward (NB_ERR_ARG) */
+#define NB_TAB_SEGMENTS 256
 #define NB_VDW_SHIFT    0
 #define NB_VDW_FSWITCH  1
 
@@ -117,7 +128,7 @@ typedef struct nb_params {
     uint32_t flags;         /* NB_CHECK_*, NB_ASYNC_BUILD, NB_ENERGY_FP64, NB_EWALD_CORR,
                                NB_SORT_UNITS */
     int32_t cluster;        /* cluster size C of the list: 4 or 8 (0 = 8) */
-    int32_t elec;           /* NB_ELEC_EWALD (ewald_beta used) or NB_ELEC_RF */
+    int32_t elec;           /* NB_ELEC_EWALD or NB_ELEC_EWALD_TAB (ewald_beta used), NB_ELEC_RF */
     int32_t vdw;            /* NB_VDW_SHIFT or NB_VDW_FSWITCH */
     double epsilon_rf;      /* reaction-field dielectric: 0 (infinity) or >= 1 */
     double rswitch;         /* force-switch start, 0 <= rswitch < cutoff (NB_VDW_FSWITCH) */

@@ -119,7 +119,7 @@ void set_constants(nb_ctx *c) {
         fp.krf = (float)krf;
         fp.krf_d = krf;
         // c_rf; the FP32-energy path sums q_i q_j without fC, so fC goes into the shift there
-        c->shift_coul = (1.0 / rc + krf * rc * rc) * ((c->flags & NB_ENERGY_FP64) ? 1.0 : (double)fp.fc);
+        c->shift_coul = (1.0 / rc + krf * rc * rc) * (nb_energy_fp64(c) ? 1.0 : (double)fp.fc);
     }
     fp.lj_k6 = pow(c->rc, -6.0);
     fp.lj_k12 = pow(c->rc, -12.0);
@@ -173,6 +173,57 @@ int upload_etab(nb_ctx *c) {
     return NB_OK;
 }
 
+// The smooth part of the Ewald real-space force factor, G(r) = erf(beta r)/r^3 -
+// 2 beta/sqrt(pi) exp(-beta^2 r^2)/r^2 (the force factor is 1/r^3 - G(r)), and its derivative,
+// in FP64: from the power series in x = beta r below x = 1 (the closed form cancels there),
+// G = beta^3 S(x), S(x) = 2/sqrt(pi) sum_{n>=1} (-1)^(n+1) 2n x^(2n-2) / (n! (2n+1)).
+void ewald_fcorr(double beta, double r, double *g, double *dg) {
+    const double x = beta * r, k = 2.0 / sqrt(M_PI);
+    if (x < 1.0) {
+        double s = 0.0, ds = 0.0, fact = 1.0, xp = 1.0, xq = x;   // xp = x^(2n-2), xq = x^(2n-3)
+        for (int n = 1; n <= 24; ++n) {
+            fact *= n;
+            const double sg = (n % 2) ? 1.0 : -1.0;
+            s += sg * 2.0 * n * xp / (fact * (2.0 * n + 1.0));
+            if (n >= 2) {
+                ds += sg * 2.0 * n * (2.0 * n - 2.0) * xq / (fact * (2.0 * n + 1.0));
+                xq *= x * x;
+            }
+            xp *= x * x;
+        }
+        *g = k * s * beta * beta * beta;
+        *dg = k * ds * beta * beta * beta * beta;
+    } else {
+        const double ex = exp(-x * x), er = erf(x);
+        const double r2 = r * r, r3 = r2 * r;
+        *g = er / r3 - beta * k * ex / r2;
+        *dg = beta * k * ex * (3.0 / r3 + 2.0 * beta * beta / r) - 3.0 * er / (r3 * r);
+    }
+}
+
+// FP32 cubic Hermite segments of G on [k h, (k+1) h], h = rc / NB_TAB_SEGMENTS: (c0, c1, c2, c3)
+// with G(r) ~ c0 + c1 u + c2 u^2 + c3 u^3, u = r / h - k.
+int upload_ftab(nb_ctx *c) {
+    const int n = NB_TAB_SEGMENTS;
+    const double h = c->rc / n;
+    std::vector<float4> seg(n);
+    for (int k = 0; k < n; ++k) {
+        double g0, d0, g1, d1;
+        ewald_fcorr(c->beta, k * h, &g0, &d0);
+        ewald_fcorr(c->beta, (k + 1) * h, &g1, &d1);
+        d0 *= h;
+        d1 *= h;
+        seg[k] = make_float4((float)g0, (float)d0, (float)(3.0 * (g1 - g0) - 2.0 * d0 - d1),
+                             (float)(2.0 * (g0 - g1) + d0 + d1));
+    }
+    int r = dalloc(c, &c->ftab, seg.size(), "tabulated Ewald force");
+    if (r != NB_OK) return r;
+    hipError_t e = hipMemcpy(c->ftab, seg.data(), sizeof(float4) * seg.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(c, e, "upload tabulated Ewald force");
+    c->fp.tinvh = (float)(n / c->rc);
+    return NB_OK;
+}
+
 int alloc_list(nb_ctx *c) {
     return dalloc(c, &c->jl, (size_t)c->ncl_max * c->cap, "pair list");
 }
@@ -216,7 +267,7 @@ void free_all(nb_ctx *c) {
                     c->tsort, c->units,  c->fj,     c->bblo,  c->bbhi,      c->icount,
                     c->jl,    c->epart,  c->meta,   c->ljtab, c->excl_off,  c->excl_idx,
                     c->dbg_pairs, c->adj, c->adjj, c->gs, c->tpart, c->etab,
-                    c->cpart, c->vpart, c->jl_p, c->icount_p, c->xprune, c->mdpart};
+                    c->cpart, c->vpart, c->jl_p, c->icount_p, c->xprune, c->mdpart, c->ftab};
     for (void *p : bufs)
         if (p) hipFree(p);
 }
@@ -262,9 +313,10 @@ int nb_validate_params(const nb_params *p) {
     if (p->flags & ~(NB_CHECK_STALE | NB_CHECK_FINITE | NB_ASYNC_BUILD | NB_ENERGY_FP64 | NB_EWALD_CORR |
                      NB_SORT_UNITS))
         return fail(nullptr, NB_ERR_ARG, "unknown flag bits");
-    if ((p->flags & NB_EWALD_CORR) && p->elec != NB_ELEC_EWALD)
+    if ((p->flags & NB_EWALD_CORR) && p->elec == NB_ELEC_RF)
         return fail(nullptr, NB_ERR_ARG, "NB_EWALD_CORR needs Ewald electrostatics");
-    if (p->elec != NB_ELEC_EWALD && p->elec != NB_ELEC_RF) return fail(nullptr, NB_ERR_ARG, "elec must be NB_ELEC_EWALD or NB_ELEC_RF");
+    if (p->elec != NB_ELEC_EWALD && p->elec != NB_ELEC_RF && p->elec != NB_ELEC_EWALD_TAB)
+        return fail(nullptr, NB_ERR_ARG, "elec must be NB_ELEC_EWALD, NB_ELEC_EWALD_TAB or NB_ELEC_RF");
     if (p->vdw != NB_VDW_SHIFT && p->vdw != NB_VDW_FSWITCH) return fail(nullptr, NB_ERR_ARG, "vdw must be NB_VDW_SHIFT or NB_VDW_FSWITCH");
     if (p->elec == NB_ELEC_RF && !(isfinite(p->epsilon_rf) && (p->epsilon_rf == 0.0 || p->epsilon_rf >= 1.0)))
         return fail(nullptr, NB_ERR_ARG, "epsilon_rf must be 0 (infinity) or >= 1");
@@ -410,6 +462,7 @@ int nb_setup(nb_ctx **out, const nb_params *p, void *stream) {
     }
     if ((r = upload_lj(c)) != NB_OK) goto fail_out;
     if ((r = upload_etab(c)) != NB_OK) goto fail_out;
+    if (c->elec == NB_ELEC_EWALD_TAB && (r = upload_ftab(c)) != NB_OK) goto fail_out;
     if (c->flags & NB_ASYNC_BUILD) {
         if (hipHostMalloc((void **)&c->host_meta, sizeof(nb_meta), hipHostMallocDefault) != hipSuccess) {
             c->host_meta = nullptr;

@@ -317,6 +317,8 @@ int nb_batch_setup(nb_batch **out, int32_t nbox, const int32_t *atom_off, const 
     if (!out || !atom_off || !boxes || !common || nbox < 1) return bfail(nullptr, NB_ERR_ARG, "bad argument");
     if (common->flags & NB_EWALD_CORR)
         return bfail(nullptr, NB_ERR_ARG, "NB_EWALD_CORR is not available in the batched form");
+    if (common->elec == NB_ELEC_EWALD_TAB)
+        return bfail(nullptr, NB_ERR_ARG, "the tabulated Ewald flavour is not available in the batched form");
     *out = nullptr;
     if (atom_off[0] != 0 || atom_off[nbox] != common->natoms)
         return bfail(nullptr, NB_ERR_ARG, "atom_off must start at 0 and end at common->natoms");

@@ -69,7 +69,7 @@ __global__ void __launch_bounds__(NB_FORCE_WAVES * NB_WAVE) NB_FORCE_OCCUPANCY_V
                                                const int *__restrict__ tsort,
                                                const float4 *__restrict__ ljtab,
                                                const double2 *__restrict__ etab, int etab_n,
-                                               float etab_invh,
+                                               float etab_invh, const float4 *__restrict__ ftab,
                                                const int *__restrict__ icount,
                                                const nb_entry *__restrict__ jl,
                                                const int4 *__restrict__ units, float *__restrict__ fj,
@@ -90,6 +90,11 @@ __global__ void __launch_bounds__(NB_FORCE_WAVES * NB_WAVE) NB_FORCE_OCCUPANCY_V
         double2 *dst = reinterpret_cast<double2 *>(tab + 2 * ntt);
         for (int k = threadIdx.x; k < 2 * etab_n; k += blockDim.x) dst[k] = etab[k];
     }
+    // tabulated Ewald: the force segments after the erfc table
+    float4 *fdst = tab + 2 * ntt + 2 * etab_n;
+    et.fseg = fdst;
+    if (FLAV / 2 == NB_ELEC_EWALD_TAB)
+        for (int k = threadIdx.x; k < NB_TAB_SEGMENTS; k += blockDim.x) fdst[k] = ftab[k];
     __syncthreads();
     const int lane = threadIdx.x & (NB_WAVE - 1), wv = threadIdx.x / NB_WAVE;
     const int u = __builtin_amdgcn_readfirstlane(blockIdx.x * NB_FORCE_WAVES + wv);
@@ -318,23 +323,32 @@ hipError_t nb_launch_pack(nb_ctx *c, const float *x, const float *q, const int32
 
 template <int C, bool EPREC, int FLAV, bool VIR>
 static void launch_force_t(nb_ctx *c) {
+    const bool tabf = FLAV / 2 == NB_ELEC_EWALD_TAB;
     const size_t shm = sizeof(float4) * 2 * c->ntypes * c->ntypes +
-                       (EPREC ? sizeof(double2) * 2 * c->etab_n : 0);
+                       (EPREC ? sizeof(double2) * 2 * c->etab_n : 0) +
+                       (tabf ? sizeof(float4) * NB_TAB_SEGMENTS : 0);
     dim3 grid((c->unit_cap + NB_FORCE_WAVES - 1) / NB_FORCE_WAVES), block(NB_FORCE_WAVES * NB_WAVE);
     hipLaunchKernelGGL((k_force<C, EPREC, FLAV, VIR>), grid, block, shm, c->stream, c->fp, c->cap,
-                       c->npad_max, c->xq, c->tsort, c->ljtab, c->etab, c->etab_n, c->etab_invh,
-                       c->icount, c->jl, c->units, c->fj, c->epart, c->vpart, c->meta);
+                       c->npad_max, c->xq, c->tsort, c->ljtab, c->etab, EPREC ? c->etab_n : 0,
+                       c->etab_invh, c->ftab, c->icount, c->jl, c->units, c->fj, c->epart,
+                       c->vpart, c->meta);
 }
 
 template <int C, int FLAV>
 static void launch_force_f(nb_ctx *c, bool vir) {
-    const bool ep = (c->flags & NB_ENERGY_FP64) != 0;
-    if (vir) {
-        if (ep) launch_force_t<C, true, FLAV, true>(c);
-        else launch_force_t<C, false, FLAV, true>(c);
+    if constexpr (FLAV / 2 == NB_ELEC_EWALD_TAB) {
+        // the tabulated flavour always evaluates its pair energies in FP64
+        if (vir) launch_force_t<C, true, FLAV, true>(c);
+        else launch_force_t<C, true, FLAV, false>(c);
     } else {
-        if (ep) launch_force_t<C, true, FLAV, false>(c);
-        else launch_force_t<C, false, FLAV, false>(c);
+        const bool ep = (c->flags & NB_ENERGY_FP64) != 0;
+        if (vir) {
+            if (ep) launch_force_t<C, true, FLAV, true>(c);
+            else launch_force_t<C, false, FLAV, true>(c);
+        } else {
+            if (ep) launch_force_t<C, true, FLAV, false>(c);
+            else launch_force_t<C, false, FLAV, false>(c);
+        }
     }
 }
 
@@ -349,6 +363,12 @@ static void launch_force_c(nb_ctx *c, bool vir) {
         break;
     case NB_FLAV(NB_ELEC_RF, NB_VDW_SHIFT):
         launch_force_f<C, NB_FLAV(NB_ELEC_RF, NB_VDW_SHIFT)>(c, vir);
+        break;
+    case NB_FLAV(NB_ELEC_EWALD_TAB, NB_VDW_SHIFT):
+        launch_force_f<C, NB_FLAV(NB_ELEC_EWALD_TAB, NB_VDW_SHIFT)>(c, vir);
+        break;
+    case NB_FLAV(NB_ELEC_EWALD_TAB, NB_VDW_FSWITCH):
+        launch_force_f<C, NB_FLAV(NB_ELEC_EWALD_TAB, NB_VDW_FSWITCH)>(c, vir);
         break;
     default:
         launch_force_f<C, NB_FLAV(NB_ELEC_RF, NB_VDW_FSWITCH)>(c, vir);
@@ -376,6 +396,6 @@ hipError_t nb_launch_finalize(nb_ctx *c, float *f, double *e, double *vir) {
     hipLaunchKernelGGL(k_finalize, dim3(nblk), dim3(NB_FIN_BLOCK), 0, c->stream, c->natoms,
                        c->npad_max, c->slot_of, c->fj, f, c->meta, c->epart, c->cpart,
                        (c->flags & NB_EWALD_CORR) ? (c->natoms + NB_CORR_BLOCK - 1) / NB_CORR_BLOCK : 0,
-                       c->shift_coul, (c->flags & NB_ENERGY_FP64) ? c->fc : 1.0, e, c->vpart, vir);
+                       c->shift_coul, nb_energy_fp64(c) ? c->fc : 1.0, e, c->vpart, vir);
     return hipGetLastError();
 }

@@ -83,6 +83,7 @@ struct nb_etab {
     const double2 *seg;
     float invh;
     int n;
+    const float4 *fseg;  // tabulated Ewald: FP32 Hermite segments of G(r), NB_TAB_SEGMENTS of them
 };
 
 // Scalar force factor fs (F_ij = fs d) and the energies of one interacting pair at squared
@@ -97,7 +98,9 @@ __device__ __forceinline__ float pair_eval(const nb_fparams &fp, const float4 *t
                                            float &eljb, float &ecb, float &qqs, double &elj,
                                            double &ec, double &qqsd, float p4v, float q5v) {
     constexpr bool RF = FLAV / 2 == NB_ELEC_RF;
+    constexpr bool TAB = FLAV / 2 == NB_ELEC_EWALD_TAB;
     constexpr bool FSW = FLAV % 2 == NB_VDW_FSWITCH;
+    static_assert(!TAB || EPREC, "the tabulated flavour evaluates its pair energies in FP64");
     const float rinv = nb_rsq(r2);
     const float rinv2 = rinv * rinv;
     const float rinv6 = rinv2 * rinv2 * rinv2;
@@ -162,6 +165,23 @@ __device__ __forceinline__ float pair_eval(const nb_fparams &fp, const float4 *t
         } else {
             ecb = __builtin_fmaf(qq, __builtin_fmaf(fp.krf, r2, rinv), ecb);
         }
+    } else if (TAB) {
+        // tabulated Ewald: force factor fC q q (1/r^3 - G(r)), G from its FP32 Hermite segment
+        const float tr = r * fp.tinvh;
+        const int sg = min((int)tr, NB_TAB_SEGMENTS - 1);
+        const float u = tr - (float)sg;
+        const float4 c = et.fseg[sg];
+        const float G = __builtin_fmaf(__builtin_fmaf(__builtin_fmaf(c.w, u, c.z), u, c.y), u, c.x);
+        fs = __builtin_fmaf(qq, __builtin_fmaf(-r2, G, rinv), flj) * rinv2;
+        // Coulomb pair energy in FP64 without fC, erfc(beta r) from the FP64 Hermite table
+        const double rd = r2d * rid;
+        const int se = min((int)(r * et.invh), et.n - 1);
+        const double uq = __builtin_fma(rd, (double)et.invh, -(double)se);
+        const double2 c01 = et.seg[2 * se], c23 = et.seg[2 * se + 1];
+        const double g = __builtin_fma(__builtin_fma(__builtin_fma(c23.y, uq, c23.x), uq, c01.y), uq, c01.x);
+        const double qqd = (double)qi * (double)jd.y;
+        ec = __builtin_fma(qqd * g, rid, ec);
+        qqsd += qqd;
     } else {
         // Ewald real space: erfc(beta r) = exp(-beta^2 r^2) P(r) / Q(r)
         const float ex = __builtin_amdgcn_exp2f(fp.cexp * r2);

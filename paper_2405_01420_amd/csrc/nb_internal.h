@@ -108,6 +108,8 @@ struct nb_fparams {
     // FP64 pair-energy constants: k_rf; LJ shift constants (value at rc of the r^-6 and r^-12
     // parts: rc^-a, or the force-switch constant); force-switch energy coefficients
     double krf_d, lj_k6, lj_k12, sw_r1_d, sw_ea6_d, sw_eb6_d, sw_ea12_d, sw_eb12_d;
+    // tabulated Ewald force correction G(r): NB_TAB_SEGMENTS segments of width 1 / tinvh
+    float tinvh;
 };
 
 // Flavour of a force kernel: electrostatics * 2 + van der Waals (NB_ELEC_*, NB_VDW_*).
@@ -175,6 +177,8 @@ struct nb_ctx {
     nb_meta *meta = nullptr;
     float4 *ljtab = nullptr;    // [2 * nt * nt]: (C6, C12, 6 C6, 12 C12), (shift, 1/sigma_ab, 0, 0)
     double2 *etab = nullptr;    // [2 * etab_n]: Hermite segments of erfc(beta r) (FP64 energy mode)
+    float4 *ftab = nullptr;     // [NB_TAB_SEGMENTS]: FP32 Hermite segments of the tabulated Ewald
+                                // force correction (NB_ELEC_EWALD_TAB)
     int etab_n = 0;
     float etab_invh = 0.0f;     // 1 / segment width, a power of two
     int *excl_off = nullptr, *excl_idx = nullptr;
@@ -194,6 +198,12 @@ struct nb_ctx {
     double timed_ms = 0;
     int64_t timed_n = 0;
 };
+
+// Whether the force kernel evaluates the pair energies in FP64 (then the Coulomb sums carry no
+// fC): NB_ENERGY_FP64, or the tabulated Ewald flavour, which always does.
+inline bool nb_energy_fp64(const nb_ctx *c) {
+    return (c->flags & NB_ENERGY_FP64) != 0 || c->elec == NB_ELEC_EWALD_TAB;
+}
 
 // ---- host helpers (nb_api.cpp) ----
 int nb_read_meta(nb_ctx *c, nb_meta *m);

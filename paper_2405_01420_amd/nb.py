@@ -25,7 +25,8 @@ NB_EWALD_CORR = 0x20
 NB_SORT_UNITS = 0x40
 NB_MAX_EXCL_PER_ATOM = 32
 NB_NOALLOC_MAX_SLOTS = 262144  # padded slots nb_backward_noalloc handles at most
-NB_ELEC_EWALD, NB_ELEC_RF = 0, 1
+NB_ELEC_EWALD, NB_ELEC_RF, NB_ELEC_EWALD_TAB = 0, 1, 2
+NB_TAB_SEGMENTS = 256
 NB_VDW_SHIFT, NB_VDW_FSWITCH = 0, 1
 
 STATUS_NAMES = {0: "NB_OK", 1: "NB_ERR_ARG", 2: "NB_ERR_CUTOFF", 3: "NB_ERR_OOM", 4: "NB_ERR_HIP",

@@ -69,7 +69,7 @@ def test_valid_parameters_pass():
     ("natoms", 0, nb.NB_ERR_ARG),
     ("cluster", 6, nb.NB_ERR_ARG),
     ("flags", 0x100, nb.NB_ERR_ARG),
-    ("elec", 2, nb.NB_ERR_ARG),
+    ("elec", 3, nb.NB_ERR_ARG),
     ("vdw", 5, nb.NB_ERR_ARG),
 ])
 def test_invalid_parameters_are_rejected(field, value, code):

@@ -144,3 +144,40 @@ def test_backward_rejects_other_flavours(torch_gpu):
         nb.nb_backward(box.ctx, box.x, box.q, box.t, z3, ge, z3.clone(), z1, dt, dt.clone())
     assert ei.value.code == nb.NB_ERR_ARG
     box.close()
+
+
+@pytest.mark.parametrize("which", ["tiny", "diff", "mid"])
+@pytest.mark.parametrize("vdw", [nb.NB_VDW_SHIFT, nb.NB_VDW_FSWITCH])
+def test_tabulated_ewald_matches_oracle(torch_gpu, which, vdw):
+    """NB_ELEC_EWALD_TAB: the Ewald real-space force from the FP32 table of its smooth part, the
+    pair energies in FP64; the same interaction as the analytic flavour, so the oracle's Ewald
+    definition is the reference (forces 5e-6, both energies 1e-6, also on the 648-atom box)."""
+    inst = getattr(synth, which)()
+    rsw = inst.cutoff - 0.2 if vdw == nb.NB_VDW_FSWITCH else 0.0
+    box = GpuBox(torch_gpu, inst, elec=nb.NB_ELEC_EWALD_TAB, vdw=vdw, rswitch=rsw)
+    box.pairlist()
+    f, e = box.forces()
+    box.close()
+    ref = O.instance_forces(inst, vdw=vdw, rswitch=rsw)
+    fr, elj, ec = compare_forces(f, e, ref, f"{which} tabulated Ewald vdw={vdw}")
+    assert fr <= FORCE_TOL and elj <= ENERGY_TOL and ec <= ENERGY_TOL
+
+
+def test_tabulated_ewald_rejected_where_not_built(torch_gpu):
+    inst = synth.tiny()
+    params = nb.Params.from_instance(inst, elec=nb.NB_ELEC_EWALD_TAB)
+    ctx = nb.nb_setup(params)
+    box = GpuBox(torch_gpu, inst, elec=nb.NB_ELEC_EWALD_TAB)
+    box.pairlist()
+    z = torch_gpu.zeros(3 * inst.natoms, dtype=torch_gpu.float32, device="cuda:0")
+    with pytest.raises(nb.NbError) as ei:
+        nb.nb_backward(box.ctx, box.x, box.q, box.t, z, box.e, z, z[:inst.natoms], box.e, box.e,
+                       nb.NB_REUSE_LIST)
+    assert ei.value.code == nb.NB_ERR_ARG
+    box.close()
+    nb.nb_destroy(ctx)
+    insts = synth.batch(2, sizes=[3000, 3600])
+    ao, bx, p, x, q, t = nb.concat_instances(insts, elec=nb.NB_ELEC_EWALD_TAB)
+    with pytest.raises(nb.NbError) as ei:
+        nb.nb_batch_setup(ao, bx, p)
+    assert ei.value.code == nb.NB_ERR_ARG
