@@ -74,5 +74,15 @@ def test_noalloc_backward_rejects_missing_list_and_oversized_system(torch_gpu):
         assert ei.value.code == nb.NB_ERR_STATE
     finally:
         box.close()
-    big = synth.mid()   # 96,000 atoms: within the limit
-    assert big.natoms < nb.NB_NOALLOC_MAX_SLOTS
+    # 90,000 waters (270,000 atoms) need more padded slots than the static work area holds: the
+    # call is refused on the host, before any kernel runs
+    big = synth.water_box(90000, (270000 / 100.0) ** (1.0 / 3.0), 1.0, 0.1, seed=11)
+    assert big.natoms > nb.NB_NOALLOC_MAX_SLOTS
+    box = GpuBox(torch, big)
+    try:
+        with pytest.raises(nb.NbError) as ei:
+            _run(torch, box, big, nb.nb_backward_noalloc)
+        assert ei.value.code == nb.NB_ERR_ARG
+        assert "static work area" in nb.nb_last_error(box.ctx)
+    finally:
+        box.close()
