@@ -148,21 +148,30 @@ void set_constants(nb_ctx *c) {
     fp.shc = (float)c->shift_coul;
 }
 
-// Cubic Hermite segments of erfc(beta r) on [k h, (k+1) h], k = 0 .. n-1, covering [0, rc];
-// h is the largest power of two with at most 1280 segments, so r / h is exact in floating point.
+// Quintic Hermite segments of erfc(beta r) on [k h, (k+1) h], k = 0 .. n-1, covering [0, rc]:
+// on u = r / h - k in [0, 1], the polynomial matching erfc and its first and second derivatives
+// (scaled by h and h^2) at both ends; h is the largest power of two with at most 160 segments, so
+// r / h is exact in floating point.  Interpolation error below 2e-13 (absolute) at rc = 1 nm.
 int upload_etab(nb_ctx *c) {
     double h = 1.0 / 1024.0;
-    while (c->rc / h > 1279.0) h *= 2.0;
+    while (c->rc / h > 159.0) h *= 2.0;
     const int n = (int)ceil(c->rc / h) + 1;
-    std::vector<double2> seg(2 * (size_t)n);
-    const double kb = 2.0 * c->beta / sqrt(M_PI);
+    std::vector<double2> seg(NB_ETAB_W * (size_t)n);
+    const double kb = 2.0 * c->beta / sqrt(M_PI), b2 = c->beta * c->beta;
     for (int k = 0; k < n; ++k) {
         const double r0 = k * h, r1 = (k + 1) * h;
         const double f0 = erfc(c->beta * r0), f1 = erfc(c->beta * r1);
-        const double d0 = -kb * exp(-c->beta * c->beta * r0 * r0) * h;
-        const double d1 = -kb * exp(-c->beta * c->beta * r1 * r1) * h;
-        seg[2 * k] = make_double2(f0, d0);
-        seg[2 * k + 1] = make_double2(3.0 * (f1 - f0) - 2.0 * d0 - d1, 2.0 * (f0 - f1) + d0 + d1);
+        // d/dr erfc(beta r) = -kb exp(-beta^2 r^2), d2/dr2 = 2 beta^2 r kb exp(-beta^2 r^2)
+        const double e0 = exp(-b2 * r0 * r0), e1 = exp(-b2 * r1 * r1);
+        const double d0 = -kb * e0 * h, d1 = -kb * e1 * h;
+        const double s0 = 2.0 * b2 * r0 * kb * e0 * h * h, s1 = 2.0 * b2 * r1 * kb * e1 * h * h;
+        const double df = f1 - f0;
+        const double c3 = 10.0 * df - 6.0 * d0 - 4.0 * d1 - 0.5 * (3.0 * s0 - s1);
+        const double c4 = -15.0 * df + 8.0 * d0 + 7.0 * d1 + 0.5 * (3.0 * s0 - 2.0 * s1);
+        const double c5 = 6.0 * df - 3.0 * (d0 + d1) - 0.5 * (s0 - s1);
+        seg[NB_ETAB_W * k] = make_double2(f0, d0);
+        seg[NB_ETAB_W * k + 1] = make_double2(0.5 * s0, c3);
+        seg[NB_ETAB_W * k + 2] = make_double2(c4, c5);
     }
     int r = dalloc(c, &c->etab, seg.size(), "erfc table");
     if (r != NB_OK) return r;

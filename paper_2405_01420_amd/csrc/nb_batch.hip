@@ -105,16 +105,17 @@ __global__ void __launch_bounds__(256) NB_FORCE_OCCUPANCY k_batch_force(nb_fpara
                                                      float etab_invh, unsigned *counter,
                                                      unsigned *flags) {
     extern __shared__ float4 tab[];
-    __shared__ nb_wlds<C, EPREC> wl[256 / NB_WAVE];
+    __shared__ nb_wlds<C, EPREC, FLAV> wl[256 / NB_WAVE];
     const int ntt = fp.ntypes * fp.ntypes;
     for (int k = threadIdx.x; k < 2 * ntt; k += blockDim.x) tab[k] = ljtab[k];
     nb_etab et;
     et.seg = reinterpret_cast<const double2 *>(tab + 2 * ntt);
     et.invh = etab_invh;
     et.n = etab_n;
+    et.fseg = nullptr;  // the tabulated flavour is not built for batches
     if (EPREC) {
         double2 *dst = reinterpret_cast<double2 *>(tab + 2 * ntt);
-        for (int k = threadIdx.x; k < 2 * etab_n; k += blockDim.x) dst[k] = etab[k];
+        for (int k = threadIdx.x; k < NB_ETAB_W * etab_n; k += blockDim.x) dst[k] = etab[k];
     }
     __syncthreads();
     const int lane = threadIdx.x & (NB_WAVE - 1);
@@ -247,7 +248,7 @@ int upload_desc(nb_batch *bt) {
 }
 
 size_t batch_shm(const nb_batch *bt) {
-    return sizeof(float4) * 2 * bt->ntypes * bt->ntypes + (bt->eprec ? sizeof(double2) * 2 * bt->etab_n : 0);
+    return sizeof(float4) * 2 * bt->ntypes * bt->ntypes + (bt->eprec ? sizeof(double2) * NB_ETAB_W * bt->etab_n : 0);
 }
 
 template <int C>

@@ -76,7 +76,7 @@ __global__ void __launch_bounds__(NB_FORCE_WAVES * NB_WAVE) NB_FORCE_OCCUPANCY_V
                                                double *__restrict__ epart, double *__restrict__ vpart,
                                                nb_meta *meta) {
     extern __shared__ float4 tab[];
-    __shared__ nb_wlds<C, EPREC> wl[NB_FORCE_WAVES];
+    __shared__ nb_wlds<C, EPREC, FLAV> wl[NB_FORCE_WAVES];
     __shared__ double esh[NB_FORCE_WAVES][VIR ? 9 : 3];
     __shared__ int edone;
     const int ntt = fp.ntypes * fp.ntypes;
@@ -88,10 +88,10 @@ __global__ void __launch_bounds__(NB_FORCE_WAVES * NB_WAVE) NB_FORCE_OCCUPANCY_V
     et.n = etab_n;
     if (EPREC) {
         double2 *dst = reinterpret_cast<double2 *>(tab + 2 * ntt);
-        for (int k = threadIdx.x; k < 2 * etab_n; k += blockDim.x) dst[k] = etab[k];
+        for (int k = threadIdx.x; k < NB_ETAB_W * etab_n; k += blockDim.x) dst[k] = etab[k];
     }
     // tabulated Ewald: the force segments after the erfc table
-    float4 *fdst = tab + 2 * ntt + 2 * etab_n;
+    float4 *fdst = tab + 2 * ntt + NB_ETAB_W * etab_n;
     et.fseg = fdst;
     if (FLAV / 2 == NB_ELEC_EWALD_TAB)
         for (int k = threadIdx.x; k < NB_TAB_SEGMENTS; k += blockDim.x) fdst[k] = ftab[k];
@@ -325,7 +325,7 @@ template <int C, bool EPREC, int FLAV, bool VIR>
 static void launch_force_t(nb_ctx *c) {
     const bool tabf = FLAV / 2 == NB_ELEC_EWALD_TAB;
     const size_t shm = sizeof(float4) * 2 * c->ntypes * c->ntypes +
-                       (EPREC ? sizeof(double2) * 2 * c->etab_n : 0) +
+                       (EPREC ? sizeof(double2) * NB_ETAB_W * c->etab_n : 0) +
                        (tabf ? sizeof(float4) * NB_TAB_SEGMENTS : 0);
     dim3 grid((c->unit_cap + NB_FORCE_WAVES - 1) / NB_FORCE_WAVES), block(NB_FORCE_WAVES * NB_WAVE);
     hipLaunchKernelGGL((k_force<C, EPREC, FLAV, VIR>), grid, block, shm, c->stream, c->fp, c->cap,

@@ -35,10 +35,10 @@
 
 // Four waves per SIMD (at most 128 VGPRs) for the FP32-energy force kernels; the FP64-energy
 // variant holds more state per lane and its workgroups more LDS (the erfc table), two waves.
-#define NB_FORCE_OCCUPANCY __attribute__((amdgpu_waves_per_eu(EPREC ? 2 : 4)))
+#define NB_FORCE_OCCUPANCY __attribute__((amdgpu_waves_per_eu(EPREC ? 3 : 4)))
 // With the virial sums (six more accumulators per lane) the FP32 body needs more than 128
 // VGPRs: three waves per SIMD.
-#define NB_FORCE_OCCUPANCY_VIR __attribute__((amdgpu_waves_per_eu(EPREC ? 2 : (VIR ? 3 : 4))))
+#define NB_FORCE_OCCUPANCY_VIR __attribute__((amdgpu_waves_per_eu(EPREC ? 3 : (VIR ? 3 : 4))))
 
 __device__ __forceinline__ double nb_wave_sum_d(double v) {
 #pragma unroll
@@ -55,30 +55,28 @@ __device__ __forceinline__ void nb_wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Per-wavefront LDS work area of the force body.
-template <int C, bool EPREC>
+// Per-wavefront LDS work area of the force body.  RAWQ: the flavour needs the charges as loaded
+// (exact FP64 products q_i q_j: FP64 pair energies, and the reaction-field shift weight).
+template <int C, bool EPREC, int FLAV>
 struct nb_wlds {
-    uint2 q[C * NB_WAVE];          // the batch's interacting pairs: (r^2 bits, k << 6 | j lane)
-    float fsb[NB_WAVE * (C + 1)];  // force factor of pair (j lane, i-atom k) at j (C + 1) + k
-    float4 jd[NB_WAVE];            // per j lane: (fC q_j, q_j, type row bits, 0)
+    static constexpr bool RAWQ = EPREC || FLAV / 2 == NB_ELEC_RF;
+    uint2 q[C * NB_WAVE];          // the batch's interacting pairs: (r^2 bits, pair code)
+    float fsb[C * NB_WAVE];        // force factor of pair (i-atom k, j lane) at 64 k + lane
+    float jqf[NB_WAVE];            // per j lane: fC q_j
     float4 id[C];                  // per i-atom: (x, y, z, q) as loaded (unshifted)
-    int it[C];                     // per i-atom: type * ntypes
+    float jq[RAWQ ? NB_WAVE : 1];     // per j lane: q_j as loaded
     float4 jx[EPREC ? NB_WAVE : 1];   // FP64-energy mode, per j lane: x_j moved into the pair frame
     float4 jdi[EPREC ? NB_WAVE : 1];  // FP64-energy mode, per j lane: the i-frame offset of its pair
 };
 
-// Per-lane state of one batch: the lane's j-atom (shifted into the pair frame), its charge,
-// type row offset and mask column; accumulators for its j-force.
-struct nb_jlane {
-    float x, y, z, q;   // q includes the Coulomb constant
-    float qraw;         // q_j as loaded
-    int t;
-    unsigned mcol;
-    float fx, fy, fz;
-};
+// Pair code of a queued pair: (LJ table row << 9) | (i-atom k << 6) | j lane, the row being
+// t_i * ntypes + t_j (below NB_MAX_TYPES^2 = 2^10); its low 9 bits are the pair's place in fsb.
+#define NB_PC_ROW 9
+#define NB_PC_SLOT 511u
 
-// Erfc table of the FP64 energy mode: cubic Hermite segments of erfc(beta r) on
-// [k h, (k+1) h] with h a power of two, coefficients (c0, c1), (c2, c3) in FP64.
+// Erfc table of the FP64 energy mode: quintic Hermite segments of erfc(beta r) on
+// [k h, (k+1) h] (value and first and second derivatives matched at both ends) with h a power of
+// two, coefficients (c0, c1), (c2, c3), (c4, c5) in FP64.
 struct nb_etab {
     const double2 *seg;
     float invh;
@@ -86,17 +84,30 @@ struct nb_etab {
     const float4 *fseg;  // tabulated Ewald: FP32 Hermite segments of G(r), NB_TAB_SEGMENTS of them
 };
 
+// erfc(beta r) in FP64 from the table, at the FP64 distance rd (segment chosen with the FP32 r).
+__device__ __forceinline__ double nb_erfc_tab(const nb_etab &et, float r, double rd) {
+    const int sg = min((int)(r * et.invh), et.n - 1);
+    const double u = __builtin_fma(rd, (double)et.invh, -(double)sg);
+    const double2 c01 = et.seg[3 * sg], c23 = et.seg[3 * sg + 1], c45 = et.seg[3 * sg + 2];
+    double g = __builtin_fma(c45.y, u, c45.x);
+    g = __builtin_fma(g, u, c23.y);
+    g = __builtin_fma(g, u, c23.x);
+    g = __builtin_fma(g, u, c01.y);
+    return __builtin_fma(g, u, c01.x);
+}
+
 // Scalar force factor fs (F_ij = fs d) and the energies of one interacting pair at squared
-// distance r2, i-atom charge qi and type row ti, j-atom data jd of the batch.  The FP32 pair
-// energies are added to eljb / ecb (FP32 partial sums of the batch) and the shift weight to
-// qqs (FP32, fC included) or qqsd (FP64, exact products); with EPREC the FP64 energies of the
-// pair, computed from the exact displacement (dxd, dyd, dzd), go to elj / ec / qqsd.
+// distance r2 with qq = fC q_i q_j and the LJ row lj (C6, C12, 6 C6, 12 C12) and shift shv.  The
+// FP32 pair energies are added to eljb / ecb (FP32 partial sums of the batch) and the shift
+// weight to qqs (FP32, fC included) or qqsd (FP64, exact products qqd = q_i q_j); with EPREC the
+// FP64 energies of the pair, computed from the exact displacement (dxd, dyd, dzd), go to
+// elj / ec / qqsd.
 template <bool EPREC, int FLAV>
-__device__ __forceinline__ float pair_eval(const nb_fparams &fp, const float4 *tab,
-                                           const nb_etab &et, float r2, float qi, int ti,
-                                           const float4 &jd, double dxd, double dyd, double dzd,
-                                           float &eljb, float &ecb, float &qqs, double &elj,
-                                           double &ec, double &qqsd, float p4v, float q5v) {
+__device__ __forceinline__ float pair_eval(const nb_fparams &fp, const nb_etab &et, float r2,
+                                           float qq, double qqd, const float4 &lj, float shv,
+                                           double dxd, double dyd, double dzd, float &eljb,
+                                           float &ecb, float &qqs, double &elj, double &ec,
+                                           double &qqsd, float p4v, float q5v) {
     constexpr bool RF = FLAV / 2 == NB_ELEC_RF;
     constexpr bool TAB = FLAV / 2 == NB_ELEC_EWALD_TAB;
     constexpr bool FSW = FLAV % 2 == NB_VDW_FSWITCH;
@@ -104,9 +115,6 @@ __device__ __forceinline__ float pair_eval(const nb_fparams &fp, const float4 *t
     const float rinv = nb_rsq(r2);
     const float rinv2 = rinv * rinv;
     const float rinv6 = rinv2 * rinv2 * rinv2;
-    const float4 *ljp = tab + 2 * (ti + __float_as_int(jd.z));
-    const float4 lj = ljp[0];             // (C6, C12, 6 C6, 12 C12)
-    const float shv = ljp[1].x;
     // Lennard-Jones: energy C12 r^-12 - C6 r^-6 - shift, force factor (12 C12 r^-6 - 6 C6) r^-8
     const float u = __builtin_fmaf(lj.y, rinv6, -lj.x);
     float elj_p = __builtin_fmaf(u, rinv6, -shv);
@@ -148,7 +156,6 @@ __device__ __forceinline__ float pair_eval(const nb_fparams &fp, const float4 *t
         const float esw = __builtin_fmaf(lj.y, e12, -lj.x * e6);
         elj_p = __builtin_fmaf(-esw, t2 * t, elj_p);
     }
-    const float qq = qi * jd.x;           // fC q_i q_j
     float fs;
     if (RF) {
         // reaction field: force factor fC q q (1/r^3 - 2 k_rf), energy fC q q (1/r + k_rf r^2);
@@ -157,7 +164,6 @@ __device__ __forceinline__ float pair_eval(const nb_fparams &fp, const float4 *t
         // small, and an FP32 running sum of the products would dominate the energy error
         const float cr = __builtin_fmaf(-2.0f * fp.krf, r2, rinv);
         fs = __builtin_fmaf(qq, cr, flj) * rinv2;
-        const double qqd = (double)qi * (double)jd.y;
         qqsd += qqd;
         if (EPREC) {
             // pair energy in FP64 without fC
@@ -169,18 +175,12 @@ __device__ __forceinline__ float pair_eval(const nb_fparams &fp, const float4 *t
         // tabulated Ewald: force factor fC q q (1/r^3 - G(r)), G from its FP32 Hermite segment
         const float tr = r * fp.tinvh;
         const int sg = min((int)tr, NB_TAB_SEGMENTS - 1);
-        const float u = tr - (float)sg;
+        const float uu = tr - (float)sg;
         const float4 c = et.fseg[sg];
-        const float G = __builtin_fmaf(__builtin_fmaf(__builtin_fmaf(c.w, u, c.z), u, c.y), u, c.x);
+        const float G = __builtin_fmaf(__builtin_fmaf(__builtin_fmaf(c.w, uu, c.z), uu, c.y), uu, c.x);
         fs = __builtin_fmaf(qq, __builtin_fmaf(-r2, G, rinv), flj) * rinv2;
-        // Coulomb pair energy in FP64 without fC, erfc(beta r) from the FP64 Hermite table
-        const double rd = r2d * rid;
-        const int se = min((int)(r * et.invh), et.n - 1);
-        const double uq = __builtin_fma(rd, (double)et.invh, -(double)se);
-        const double2 c01 = et.seg[2 * se], c23 = et.seg[2 * se + 1];
-        const double g = __builtin_fma(__builtin_fma(__builtin_fma(c23.y, uq, c23.x), uq, c01.y), uq, c01.x);
-        const double qqd = (double)qi * (double)jd.y;
-        ec = __builtin_fma(qqd * g, rid, ec);
+        // Coulomb pair energy in FP64 without fC, erfc(beta r) from the FP64 table
+        ec = __builtin_fma(qqd * nb_erfc_tab(et, r, r2d * rid), rid, ec);
         qqsd += qqd;
     } else {
         // Ewald real space: erfc(beta r) = exp(-beta^2 r^2) P(r) / Q(r)
@@ -201,15 +201,8 @@ __device__ __forceinline__ float pair_eval(const nb_fparams &fp, const float4 *t
         const float uu = __builtin_fmaf(fp.kb, r, R);
         fs = __builtin_fmaf(t1, uu, flj) * rinv2;
         if (EPREC) {
-            // Coulomb pair energy in FP64 without fC, erfc(beta r) from the FP64 Hermite table
-            // (segment found with the FP32 r)
-            const double rd = r2d * rid;
-            const int sg = min((int)(r * et.invh), et.n - 1);
-            const double uq = __builtin_fma(rd, (double)et.invh, -(double)sg);
-            const double2 c01 = et.seg[2 * sg], c23 = et.seg[2 * sg + 1];
-            const double g = __builtin_fma(__builtin_fma(__builtin_fma(c23.y, uq, c23.x), uq, c01.y), uq, c01.x);
-            const double qqd = (double)qi * (double)jd.y;
-            ec = __builtin_fma(qqd * g, rid, ec);
+            // Coulomb pair energy in FP64 without fC, erfc(beta r) from the FP64 table
+            ec = __builtin_fma(qqd * nb_erfc_tab(et, r, r2d * rid), rid, ec);
             qqsd += qqd;
         } else {
             ecb = __builtin_fmaf(t1, R, ecb);     // += fC q_i q_j erfc(b r) / r
@@ -277,7 +270,7 @@ struct nb_esum {
 // returned.
 template <int C, bool EPREC, int FLAV, bool VIR, bool FIX>
 __device__ __forceinline__ nb_esum nb_force_cluster(const nb_fparams &fp, const float4 *tab,
-                                                 const nb_etab &et, nb_wlds<C, EPREC> &w,
+                                                 const nb_etab &et, nb_wlds<C, EPREC, FLAV> &w,
                                                  int ci, int b0, int nbat, int cap, int npad_max,
                                                  const NB_G float4 *__restrict__ xq,
                                                  const NB_G int *__restrict__ tsort,
@@ -285,27 +278,25 @@ __device__ __forceinline__ nb_esum nb_force_cluster(const nb_fparams &fp, const 
                                                  const NB_G nb_entry *__restrict__ jl,
                                                  NB_G float *__restrict__ fj,
                                                  NB_G unsigned *__restrict__ flags) {
+    constexpr bool RAWQ = nb_wlds<C, EPREC, FLAV>::RAWQ;
+    constexpr unsigned FULL = (1u << C) - 1u;
     const int nt = fp.ntypes;
     const int lane = threadIdx.x & (NB_WAVE - 1);
     const int b = lane % NB_JG, jsub = lane / NB_JG;  // j-atom within the group, entry in batch
 
-    float xi[C], yi[C], zi[C], xs[C], ys[C], zs[C];
+    // i-atoms: coordinates and charges in LDS (the evaluate phase, where a lane's i-atom varies,
+    // and the frame changes read them); per i-atom the constant part of its pairs' codes,
+    // (t_i ntypes << 9) | (k << 6), wave-uniform
+    if (lane < C) w.id[lane] = nb_ld(xq + ci * C + lane);
+    int pci[C];
 #pragma unroll
-    for (int k = 0; k < C; ++k) {
-        const float4 v = nb_ld(xq + ci * C + k);
-        xi[k] = v.x;
-        yi[k] = v.y;
-        zi[k] = v.z;
-        xs[k] = xi[k];
-        ys[k] = yi[k];
-        zs[k] = zi[k];
-    }
-    // i-atom charges and type rows for the evaluate phase, where a lane's i-atom varies
-    if (lane < C) {
-        w.id[lane] = nb_ld(xq + ci * C + lane);
-        w.it[lane] = nb_ld(tsort + ci * C + lane) * nt;
-    }
-    int cur_shift = NB_SHIFT_ZERO;  // shift the cached i-frame coordinates xs/ys/zs belong to
+    for (int k = 0; k < C; ++k)
+        pci[k] = (__builtin_amdgcn_readfirstlane(nb_ld(tsort + ci * C + k)) * nt << NB_PC_ROW) | (k << 6);
+    nb_wave_lds_sync();
+    int cur_shift = -1;  // shift the cached i-frame coordinates xs/ys/zs belong to (none yet)
+    float xs[C], ys[C], zs[C];
+#pragma unroll
+    for (int k = 0; k < C; ++k) xs[k] = ys[k] = zs[k] = 0.0f;
     float fix[C], fiy[C], fiz[C];
 #pragma unroll
     for (int k = 0; k < C; ++k) fix[k] = fiy[k] = fiz[k] = 0.0f;
@@ -326,20 +317,18 @@ __device__ __forceinline__ nb_esum nb_force_cluster(const nb_fparams &fp, const 
         const int e = base + jsub;
         const bool valid = e < nj;
         // lanes past the end of the list read the i-cluster's own first group with an empty mask
+        // and place their j-atom far outside the box, so that none of its pairs is in range
         const nb_entry en = valid ? nb_ld(lst + e) : nb_make_entry(ci * (C / NB_JG), NB_SHIFT_ZERO, 0u);
         const int s = nb_entry_shift(en);
         const int jslot = nb_entry_group(en) * NB_JG + b;
         const float4 xj = nb_ld(xq + jslot);
-        nb_jlane jv;
-        jv.q = xj.w * fp.fc;
-        jv.qraw = xj.w;
-        jv.t = nb_ld(tsort + jslot);
-        jv.mcol = nb_mask_column<C>(en.mask, b);
-        jv.fx = jv.fy = jv.fz = 0.0f;
+        const int tj = nb_ld(tsort + jslot);
+        const unsigned mcol = nb_mask_column<C>(en.mask, b);
         const int s0 = __builtin_amdgcn_readfirstlane(s);
         const bool uniform = __ballot(valid && s != s0) == 0ull;
         // ---- filter: displacements of the lane's C pairs, interacting pairs queued in LDS
         float dx[C], dy[C], dz[C];
+        float jx, jy, jz;     // the j-atom in the pair frame
         float dix, diy, diz;  // the i-frame offset of this lane's pairs
         if (uniform) {
             // one periodic shift for the whole batch: i-coordinates of that frame are cached
@@ -351,19 +340,21 @@ __device__ __forceinline__ nb_esum nb_force_cluster(const nb_fparams &fp, const 
                 cur_shift = s0;
 #pragma unroll
                 for (int k = 0; k < C; ++k) {
-                    xs[k] = nb_uniform(xi[k] + dix);
-                    ys[k] = nb_uniform(yi[k] + diy);
-                    zs[k] = nb_uniform(zi[k] + diz);
+                    const float4 v = w.id[k];
+                    xs[k] = nb_uniform(v.x + dix);
+                    ys[k] = nb_uniform(v.y + diy);
+                    zs[k] = nb_uniform(v.z + diz);
                 }
             }
-            jv.x = xj.x + nb_dj(tx, fp.L[0]);
-            jv.y = xj.y + nb_dj(ty, fp.L[1]);
-            jv.z = xj.z + nb_dj(tz, fp.L[2]);
+            jx = xj.x + nb_dj(tx, fp.L[0]);
+            jy = xj.y + nb_dj(ty, fp.L[1]);
+            jz = xj.z + nb_dj(tz, fp.L[2]);
+            if (!valid) jx = jy = jz = 1e18f;
 #pragma unroll
             for (int k = 0; k < C; ++k) {
-                dx[k] = xs[k] - jv.x;
-                dy[k] = ys[k] - jv.y;
-                dz[k] = zs[k] - jv.z;
+                dx[k] = xs[k] - jx;
+                dy[k] = ys[k] - jy;
+                dz[k] = zs[k] - jz;
             }
         } else {
             // shifts differ across the batch: per-lane frame offsets
@@ -371,35 +362,54 @@ __device__ __forceinline__ nb_esum nb_force_cluster(const nb_fparams &fp, const 
             dix = nb_di(tx, fp.L[0]);
             diy = nb_di(ty, fp.L[1]);
             diz = nb_di(tz, fp.L[2]);
-            jv.x = xj.x + nb_dj(tx, fp.L[0]);
-            jv.y = xj.y + nb_dj(ty, fp.L[1]);
-            jv.z = xj.z + nb_dj(tz, fp.L[2]);
+            jx = xj.x + nb_dj(tx, fp.L[0]);
+            jy = xj.y + nb_dj(ty, fp.L[1]);
+            jz = xj.z + nb_dj(tz, fp.L[2]);
+            if (!valid) jx = jy = jz = 1e18f;
 #pragma unroll
             for (int k = 0; k < C; ++k) {
-                dx[k] = (xi[k] + dix) - jv.x;
-                dy[k] = (yi[k] + diy) - jv.y;
-                dz[k] = (zi[k] + diz) - jv.z;
+                const float4 v = w.id[k];
+                dx[k] = (v.x + dix) - jx;
+                dy[k] = (v.y + diy) - jy;
+                dz[k] = (v.z + diz) - jz;
             }
         }
         nb_wave_lds_sync();  // the previous batch's reads of the work area are done
-        w.jd[lane] = make_float4(jv.q, jv.qraw, __int_as_float(jv.t), 0.0f);
+        w.jqf[lane] = xj.w * fp.fc;
+        if (RAWQ) w.jq[lane] = xj.w;
         if (EPREC) {
-            w.jx[lane] = make_float4(jv.x, jv.y, jv.z, 0.0f);
+            w.jx[lane] = make_float4(jx, jy, jz, 0.0f);
             w.jdi[lane] = make_float4(dix, diy, diz, 0.0f);
         }
-        bool in[C];
-        int nq = 0;  // interacting pairs of the batch (wave-uniform)
 #pragma unroll
-        for (int k = 0; k < C; ++k) {
-            const float r2 = nb_r2(dx[k], dy[k], dz[k]);
-            in[k] = ((jv.mcol >> k) & 1u) && r2 < fp.rc2;
-            const unsigned long long bal = __ballot(in[k]);
-            if (in[k]) {
-                const int pos = nq + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(bal >> 32),
-                                                                   __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
-                w.q[pos] = make_uint2(__float_as_uint(r2), (unsigned)((k << 6) | lane));
+        for (int k = 0; k < C; ++k) w.fsb[k * NB_WAVE + lane] = 0.0f;
+        // the lane's part of the pair codes
+        const int pcj = (tj << NB_PC_ROW) | lane;
+        int nq = 0;  // interacting pairs of the batch (wave-uniform)
+        auto enqueue = [&](int k, float r2, unsigned long long bal) {
+            const int pos = nq + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(bal >> 32),
+                                                                 __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
+            w.q[pos] = make_uint2(__float_as_uint(r2), (unsigned)(pci[k] + pcj));
+        };
+        if (__ballot(valid && mcol != FULL) == 0ull) {
+            // every listed pair of the batch is unmasked (the common case): the range test alone
+#pragma unroll
+            for (int k = 0; k < C; ++k) {
+                const float r2 = nb_r2(dx[k], dy[k], dz[k]);
+                const bool in = r2 < fp.rc2;
+                const unsigned long long bal = __builtin_amdgcn_ballot_w64(in);
+                if (in) enqueue(k, r2, bal);
+                nq += __popcll(bal);
             }
-            nq += __popcll(bal);
+        } else {
+#pragma unroll
+            for (int k = 0; k < C; ++k) {
+                const float r2 = nb_r2(dx[k], dy[k], dz[k]);
+                const bool in = ((mcol >> k) & 1u) && r2 < fp.rc2;
+                const unsigned long long bal = __builtin_amdgcn_ballot_w64(in);
+                if (in) enqueue(k, r2, bal);
+                nq += __popcll(bal);
+            }
         }
         nb_wave_lds_sync();
         // ---- evaluate: the queued pairs, one per lane
@@ -407,22 +417,27 @@ __device__ __forceinline__ nb_esum nb_force_cluster(const nb_fparams &fp, const 
         for (int p0 = 0; p0 < nq; p0 += NB_WAVE) {
             if (p0 + lane < nq) {
                 const uint2 qe = w.q[p0 + lane];
-                const int k = (int)(qe.y >> 6), jl_ = (int)(qe.y & 63u);
-                const float4 jd = w.jd[jl_];
-                const float4 idk = w.id[k];
-                double dxd = 0.0, dyd = 0.0, dzd = 0.0;
+                const unsigned code = qe.y;
+                const int jl_ = (int)(code & 63u), k = (int)((code >> 6) & 7u);
+                const float4 *ljp = tab + 2 * (code >> NB_PC_ROW);
+                const float4 lj = ljp[0];
+                const float shv = ljp[1].x;
+                const float qi = w.id[k].w;
+                const float qq = qi * w.jqf[jl_];
+                double qqd = 0.0, dxd = 0.0, dyd = 0.0, dzd = 0.0;
+                if (RAWQ) qqd = (double)qi * (double)w.jq[jl_];
                 if (EPREC) {
                     // exact displacement: x_i + di is exact (the coordinate near the upper face
                     // moves down by L), and the difference of two FP32 values is exact in FP64
-                    const float4 a = w.jdi[jl_], bj = w.jx[jl_];
+                    const float4 idk = w.id[k], a = w.jdi[jl_], bj = w.jx[jl_];
                     dxd = (double)(idk.x + a.x) - (double)bj.x;
                     dyd = (double)(idk.y + a.y) - (double)bj.y;
                     dzd = (double)(idk.z + a.z) - (double)bj.z;
                 }
-                const float fs = pair_eval<EPREC, FLAV>(fp, tab, et, __uint_as_float(qe.x), idk.w,
-                                                        w.it[k], jd, dxd, dyd, dzd, eljb, ecb, qqs,
-                                                        elj, ec, qqsd, p4v, q5v);
-                w.fsb[jl_ * (C + 1) + k] = fs;
+                const float fs = pair_eval<EPREC, FLAV>(fp, et, __uint_as_float(qe.x), qq, qqd, lj,
+                                                        shv, dxd, dyd, dzd, eljb, ecb, qqs, elj,
+                                                        ec, qqsd, p4v, q5v);
+                w.fsb[code & NB_PC_SLOT] = fs;
             }
         }
         nb_wave_lds_sync();
@@ -431,11 +446,13 @@ __device__ __forceinline__ nb_esum nb_force_cluster(const nb_fparams &fp, const 
             ec += (double)ecb;
         }
         if (!nb_qq64<EPREC, FLAV>()) qqsd += (double)qqs;
-        // ---- accumulate: f d of the lane's C pairs into the i- and j-force sums
+        // ---- accumulate: f d of the lane's C pairs into the i- and j-force sums (the factor is
+        // zero for pairs that do not interact)
         float vb[6] = {-0.0f, -0.0f, -0.0f, -0.0f, -0.0f, -0.0f};
+        float jfx = 0.0f, jfy = 0.0f, jfz = 0.0f;
 #pragma unroll
         for (int k = 0; k < C; ++k) {
-            const float fs = in[k] ? w.fsb[lane * (C + 1) + k] : 0.0f;
+            const float fs = w.fsb[k * NB_WAVE + lane];
             if (VIR) {
                 const float tx = fs * dx[k], ty = fs * dy[k], tz = fs * dz[k];
                 vb[0] = __builtin_fmaf(tx, dx[k], vb[0]);
@@ -448,9 +465,9 @@ __device__ __forceinline__ nb_esum nb_force_cluster(const nb_fparams &fp, const 
             fix[k] = __builtin_fmaf(fs, dx[k], fix[k]);
             fiy[k] = __builtin_fmaf(fs, dy[k], fiy[k]);
             fiz[k] = __builtin_fmaf(fs, dz[k], fiz[k]);
-            jv.fx = __builtin_fmaf(-fs, dx[k], jv.fx);
-            jv.fy = __builtin_fmaf(-fs, dy[k], jv.fy);
-            jv.fz = __builtin_fmaf(-fs, dz[k], jv.fz);
+            jfx = __builtin_fmaf(-fs, dx[k], jfx);
+            jfy = __builtin_fmaf(-fs, dy[k], jfy);
+            jfz = __builtin_fmaf(-fs, dz[k], jfz);
         }
         if (VIR) {
 #pragma unroll
@@ -458,8 +475,8 @@ __device__ __forceinline__ nb_esum nb_force_cluster(const nb_fparams &fp, const 
         }
         // about 40% of the lanes of a batch have no pair within rc (their entry was kept for
         // another atom of the group, at rlist); they skip their atomics
-        nb_add_force<FIX>(valid && (jv.fx != 0.0f || jv.fy != 0.0f || jv.fz != 0.0f), jslot, jv.fx,
-                          jv.fy, jv.fz, fj, npad_max, flags, lane);
+        nb_add_force<FIX>(valid && (jfx != 0.0f || jfy != 0.0f || jfz != 0.0f), jslot, jfx, jfy,
+                          jfz, fj, npad_max, flags, lane);
     }
 #pragma unroll
     for (int k = 0; k < C; ++k) {

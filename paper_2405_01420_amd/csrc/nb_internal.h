@@ -176,7 +176,7 @@ struct nb_ctx {
     double *vpart = nullptr;    // [6 * force workgroups] virial pair sums (nb_forces_virial)
     nb_meta *meta = nullptr;
     float4 *ljtab = nullptr;    // [2 * nt * nt]: (C6, C12, 6 C6, 12 C12), (shift, 1/sigma_ab, 0, 0)
-    double2 *etab = nullptr;    // [2 * etab_n]: Hermite segments of erfc(beta r) (FP64 energy mode)
+    double2 *etab = nullptr;    // [NB_ETAB_W * etab_n]: Hermite segments of erfc(beta r) (FP64 energy mode)
     float4 *ftab = nullptr;     // [NB_TAB_SEGMENTS]: FP32 Hermite segments of the tabulated Ewald
                                 // force correction (NB_ELEC_EWALD_TAB)
     int etab_n = 0;
@@ -225,6 +225,9 @@ hipError_t nb_launch_ewald_corr(nb_ctx *c, const float *x, const float *q);
 
 // Threads per block of the Ewald-correction kernel (one atom each), and its partial sums per
 // block: the exclusion-correction and self energies, then six pair sums for the virial.
+// double2 per segment of the FP64 erfc table (quintic: six coefficients)
+#define NB_ETAB_W 3
+
 #define NB_CORR_BLOCK 256
 #define NB_CORR_PART 8
 
