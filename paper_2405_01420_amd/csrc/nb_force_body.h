@@ -5,15 +5,17 @@
 //    is a scalar operand of the vector instructions;
 //  * each lane owns one j-atom of one of the 16 four-atom j-groups of the current batch;
 //  * a batch is processed in three phases.  Filter: every lane forms the displacements and
-//    squared distances of its C pairs (i-atom k, its j-atom) and tests the topology mask and
-//    r < rc; the pairs that interact (about a third of the listed ones) are appended to a
-//    per-wave queue in LDS in (k, lane) order with a ballot and a lane count.  Evaluate: the
-//    queue is worked through 64 pairs at a time, one pair per lane, so the Lennard-Jones and
-//    Ewald arithmetic (the transcendental functions, the erfc approximation, the energies) runs
-//    only on interacting pairs with all lanes busy; each pair's scalar force factor goes back
-//    to LDS at (j lane, k).  Accumulate: every lane reads the factors of its own C pairs (zero
-//    where the pair does not interact) and adds f d to the i-force and j-force sums in
-//    registers, in the same order as a plain loop over k would;
+//    squared distances of its C pairs (i-atom k, its j-atom) and tests r < rc, and the topology
+//    mask unless every listed pair of the batch is unmasked (the common case, checked with one
+//    ballot); the pairs that interact (about a third of the listed ones) are appended to a
+//    per-wave queue in LDS in (k, lane) order with a ballot and a lane count, as (r^2, pair
+//    code), the code holding the pair's LJ table row, k and the j lane.  Evaluate: the queue is
+//    worked through 64 pairs at a time, one pair per lane, so the Lennard-Jones and Ewald
+//    arithmetic (the transcendental functions, the erfc approximation, the energies) runs only
+//    on interacting pairs with all lanes busy; each pair's scalar force factor goes to its place
+//    (64 k + lane) in a per-wave area cleared at the start of the batch.  Accumulate: every lane
+//    reads the factors of its own C pairs (zero where the pair does not interact) and adds f d
+//    to the i-force and j-force sums in registers, in the same order as a plain loop over k;
 //  * batches whose entries share one periodic shift (the common case, since the list is grouped
 //    by shift) use i-coordinates moved into that frame once and cached in scalar registers;
 //  * the j-force of a lane's atom needs one atomic add per component per batch (the only
@@ -26,7 +28,7 @@
 //    accumulated in FP64 from there on; the Coulomb potential shift is applied in FP64 at the
 //    end from the sum of q_i q_j over interacting pairs;
 //  * with EPREC the pair energies are instead evaluated in FP64 (exact displacement,
-//    Newton-refined 1/r, erfc from an FP64 cubic Hermite table), forces staying FP32: the FP32
+//    Newton-refined 1/r, erfc from an FP64 quintic Hermite table), forces staying FP32: the FP32
 //    rounding of the displacement and of erfc(beta r)/r is otherwise not averaged below 1e-6 of
 //    an energy that is a 1e-4 .. 1e-3-conditioned sum, in boxes of a few thousand atoms.  The
 //    FP64 work runs in the evaluate phase, i.e. on interacting pairs only.
@@ -34,7 +36,8 @@
 #include "nb_device.h"
 
 // Four waves per SIMD (at most 128 VGPRs) for the FP32-energy force kernels; the FP64-energy
-// variant holds more state per lane and its workgroups more LDS (the erfc table), two waves.
+// variant holds more state per lane and its workgroups more LDS (the erfc table and the j-atom
+// frames), three waves.
 #define NB_FORCE_OCCUPANCY __attribute__((amdgpu_waves_per_eu(EPREC ? 3 : 4)))
 // With the virial sums (six more accumulators per lane) the FP32 body needs more than 128
 // VGPRs: three waves per SIMD.
