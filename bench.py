@@ -93,6 +93,7 @@ def parse():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-pme", action="store_true")
     ap.add_argument("--no-md", action="store_true")
+    ap.add_argument("--no-small", action="store_true")
     ap.add_argument("--prune-every", type=int, default=0,
                     help="rolling-prune measurement: prune every this many calls (0: skip)")
     ap.add_argument("--prune-inner", type=float, default=0.05,
@@ -421,6 +422,46 @@ def bench_md(torch, nb, synth, nsteps=400):
     return out
 
 
+def bench_small_boxes(torch, nb, synth, reps=200):
+    """The plain force kernel on single small water boxes (3,000, 12,000 and 24,000 atoms,
+    rc 0.9 nm, rb 0.1 nm), with its work units in cluster order and longest first
+    (NB_SORT_UNITS, the post-prune list sorting): kernel microseconds (HIP events around each
+    launch), the list-length histogram and the work-unit split."""
+    dev = "cuda:0"
+    out = {"workload": "single water boxes at 100 atoms/nm^3, rc 0.9 nm, rb 0.1 nm, FP32 pair energies"}
+    for natoms in (3000, 12000, 24000):
+        inst = synth.small_box(natoms // 3, 0.9, 0.1, seed=50 + natoms // 3000)
+        x = torch.from_numpy(inst.x.reshape(-1).copy()).to(dev)
+        q = torch.from_numpy(inst.q.copy()).to(dev)
+        t = torch.from_numpy(inst.type.copy()).to(dev)
+        f = torch.empty(3 * inst.natoms, dtype=torch.float32, device=dev)
+        e = torch.empty(2, dtype=torch.float64, device=dev)
+        row = {}
+        for name, flags in (("cluster_order", 0), ("longest_first", nb.NB_SORT_UNITS)):
+            ctx = nb.nb_setup(nb.Params.from_instance(inst, flags=flags))
+            nb.nb_pairlist(ctx, x)
+            for _ in range(5):
+                nb.nb_forces(ctx, x, q, t, f, e)
+            nb.nb_set_timing(ctx, True)
+            nb.nb_get_timing(ctx)
+            for _ in range(reps):
+                nb.nb_forces(ctx, x, q, t, f, e)
+            ms, nl = nb.nb_get_timing(ctx)
+            st = nb.nb_get_stats(ctx)
+            if name == "cluster_order":
+                row["useful_pairs"] = nb.nb_debug_pairs(ctx, x, 0, count_only=True)
+                row["list_hist_log2_batches"] = st["list_hist"]
+                row["work_units"] = st["work_units"]
+                row["max_batches_per_unit"] = st["unit_batches"]
+                row["longest_list_batches"] = st["max_list_batches"]
+            row["kernel_us_" + name] = 1e3 * ms / nl
+            nb.nb_destroy(ctx)
+        row["pair_interactions_per_s_kernel"] = row["useful_pairs"] / (1e-6 * min(
+            row["kernel_us_cluster_order"], row["kernel_us_longest_first"]))
+        out[str(natoms)] = row
+    return out
+
+
 def bench_large(torch, nb, synth, reps=20, warmup=3):
     """3,000,000-atom box (rc 1.2 nm, 5 LJ types): median and IQR of single force calls."""
     import numpy as np
@@ -504,6 +545,9 @@ def main():
             nb.nb_pairlist(ctx, traj[k])
         nb.nb_forces(ctx, traj[k], q, t, f, e)
 
+    # force-kernel time: HIP events around every force kernel launch of the timed region, on the
+    # library's stream (nb_set_timing; its events are created before the warm-up)
+    nb.nb_set_timing(ctx, True)
     for k in range(args.warmup):
         step(k)
     # HIP events on the stream at the start of every rebuild period inside the timed region
@@ -511,6 +555,7 @@ def main():
     # synchronisation
     marks = []
     torch.cuda.synchronize()
+    nb.nb_get_timing(ctx)  # drops the warm-up launches
     t0 = time.perf_counter()
     for k in range(args.warmup, nsteps):
         if k % REBUILD_EVERY == 0:
@@ -522,6 +567,9 @@ def main():
     end_ev.record()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    kms, klaunch = nb.nb_get_timing(ctx)
+    nb.nb_set_timing(ctx, False)
+    kernel_us = 1e3 * kms / klaunch
     ms_per_step = 1e3 * elapsed / args.steps
     value = useful * args.steps / elapsed
     marks.append((nsteps, end_ev))
@@ -655,14 +703,6 @@ def main():
     torch.cuda.synchronize()
     us_build = 1e6 * (time.perf_counter() - tb) / nbuild
 
-    # force kernel alone: HIP events around each launch on the library's stream
-    nb.nb_pairlist(ctx, traj[0])
-    nb.nb_set_timing(ctx, True)
-    for k in range(reps):
-        nb.nb_forces(ctx, traj[0], q, t, f, e)
-    kms, klaunch = nb.nb_get_timing(ctx)
-    nb.nb_set_timing(ctx, False)
-    kernel_us = 1e3 * kms / klaunch
     achieved = flops_per_pair * useful / (kernel_us * 1e-6) / 1e12
     traffic = counted = None
     default_flavour = args.elec == "ewald" and args.vdw == "shift"
@@ -709,6 +749,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
                      "traffic": traffic, "kernel": "k_force", "kernel_us": kernel_us,
+                     "kernel_launches_timed": klaunch,
                      "flops_per_pair": flops_per_pair, "counted_fp32_tflops": counted},
     }
     nb.nb_destroy(ctx)
@@ -721,6 +762,8 @@ def main():
         out["md"] = bench_md(torch, nb, synth)
     if not args.no_batch:
         out["batched"] = bench_batched(torch, nb, synth, not args.no_tune)
+    if not args.no_small:
+        out["small_boxes"] = bench_small_boxes(torch, nb, synth)
     if args.large:
         out["large"] = bench_large(torch, nb, synth)
     if not args.no_cpu:

@@ -661,6 +661,19 @@ int nb_forces_virial(nb_ctx *c, const float *x, const float *q, const int32_t *t
 int nb_set_timing(nb_ctx *c, int on) {
     if (!c) return fail(c, NB_ERR_ARG, "NULL context");
     c->timing = on != 0;
+    // event pairs for the first 1024 timed launches are created here, so that timed loops do
+    // not create events
+    hipSetDevice(c->device);
+    while (c->timing && c->ev.size() < 2 * 1024) {
+        hipEvent_t a, b;
+        if (hipEventCreate(&a) != hipSuccess) return fail(c, NB_ERR_HIP, "hipEventCreate");
+        if (hipEventCreate(&b) != hipSuccess) {
+            hipEventDestroy(a);
+            return fail(c, NB_ERR_HIP, "hipEventCreate");
+        }
+        c->ev.push_back(a);
+        c->ev.push_back(b);
+    }
     return NB_OK;
 }
 

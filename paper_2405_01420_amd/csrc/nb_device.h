@@ -56,19 +56,47 @@ __device__ __forceinline__ unsigned nb_mask_column(uint32_t m, int b) {
     return (m >> (b * C)) & ((1u << C) - 1u);
 }
 
-// Sum of v over the 64 lanes, valid in lane 63 only: butterfly within each 16-lane row with
-// DPP quad permutations and mirrors, then the row sums are chained with the row broadcasts.
+// DPP move of x within 16-lane rows (CTRL: the DPP control word; rows not in ROW_MASK read 0).
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ float nb_dpp(float x) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xf, false));
 }
 
-__device__ __forceinline__ float nb_wave_sum_lane63(float v) {
-    v += nb_dpp<0xB1, 0xf>(v);   // quad_perm [1,0,3,2]
-    v += nb_dpp<0x4E, 0xf>(v);   // quad_perm [2,3,0,1]
-    v += nb_dpp<0x141, 0xf>(v);  // row_half_mirror
-    v += nb_dpp<0x140, 0xf>(v);  // row_mirror
-    v += nb_dpp<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
-    v += nb_dpp<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
-    return v;
+// Reduce-scatter of per-lane partial sums over the 64 lanes.  nb_fold32(a, b): a summed over the
+// lane pairs (l, l + 32) into lanes 0-31 and b into lanes 32-63 (one v_permlane32_swap moves the
+// upper half of a and the lower half of b across); nb_fold16 the same over (l, l ^ 16) within each
+// half, a into the rows with bit 4 clear; nb_fold8 over (l, l ^ 8) within each 16-lane row.
+__device__ __forceinline__ float nb_fold32(float a, float b) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
+__device__ __forceinline__ float nb_fold16(float a, float b) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float nb_fold8(float a, float b, int lane) {
+    const bool hi = (lane & 8) != 0;
+    const float u = hi ? b : a, w = hi ? a : b;
+    return u + nb_dpp<0x128, 0xf>(w);  // row_ror:8
+}
+
+// The C per-lane values v[k] summed over the 64 lanes: value k ends up in every lane of the
+// group of 64 / C lanes with lane / (64 / C) == k.
+template <int C>
+__device__ __forceinline__ float nb_wave_scatter_sum(const float (&v)[C], int lane) {
+    static_assert(C == 4 || C == 8, "clusters of 4 or 8 atoms");
+    float t;
+    if constexpr (C == 8) {
+        const float a0 = nb_fold32(v[0], v[4]), a1 = nb_fold32(v[1], v[5]);
+        const float a2 = nb_fold32(v[2], v[6]), a3 = nb_fold32(v[3], v[7]);
+        t = nb_fold8(nb_fold16(a0, a2), nb_fold16(a1, a3), lane);
+    } else {
+        t = nb_fold16(nb_fold32(v[0], v[2]), nb_fold32(v[1], v[3]));
+        t += nb_dpp<0x128, 0xf>(t);  // row_ror:8
+    }
+    t += nb_dpp<0xB1, 0xf>(t);   // quad_perm [1,0,3,2]
+    t += nb_dpp<0x4E, 0xf>(t);   // quad_perm [2,3,0,1]
+    t += nb_dpp<0x141, 0xf>(t);  // row_half_mirror
+    return t;
+}
+

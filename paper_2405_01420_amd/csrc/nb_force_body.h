@@ -481,28 +481,16 @@ __device__ __forceinline__ nb_esum nb_force_cluster(const nb_fparams &fp, const 
         nb_add_force<FIX>(valid && (jfx != 0.0f || jfy != 0.0f || jfz != 0.0f), jslot, jfx, jfy,
                           jfz, fj, npad_max, flags, lane);
     }
-#pragma unroll
-    for (int k = 0; k < C; ++k) {
-        fix[k] = nb_wave_sum_lane63(fix[k]);
-        fiy[k] = nb_wave_sum_lane63(fiy[k]);
-        fiz[k] = nb_wave_sum_lane63(fiz[k]);
-    }
+    // the unit's i-force sums: atom k's in the lanes with lane / (64 / C) == k, added by the
+    // first lane of each group
+    const float sx = nb_wave_scatter_sum<C>(fix, lane);
+    const float sy = nb_wave_scatter_sum<C>(fiy, lane);
+    const float sz = nb_wave_scatter_sum<C>(fiz, lane);
     elj = nb_wave_sum_d(elj);
     ec = nb_wave_sum_d(ec);
     const double qqd = nb_wave_sum_d(qqsd);
-    // the unit's i-force sums (in lane 63) go to lanes 0 .. C-1, one atom each, so that three
-    // atomics of C lanes add them
-    float vx = 0.0f, vy = 0.0f, vz = 0.0f;
-#pragma unroll
-    for (int k = 0; k < C; ++k) {
-        const float sx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(fix[k]), NB_WAVE - 1));
-        const float sy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(fiy[k]), NB_WAVE - 1));
-        const float sz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(fiz[k]), NB_WAVE - 1));
-        vx = lane == k ? sx : vx;
-        vy = lane == k ? sy : vy;
-        vz = lane == k ? sz : vz;
-    }
-    nb_add_force<FIX>(lane < C, ci * C + lane, vx, vy, vz, fj, npad_max, flags, lane);
+    nb_add_force<FIX>(lane % (NB_WAVE / C) == 0, ci * C + lane / (NB_WAVE / C), sx, sy, sz, fj,
+                      npad_max, flags, lane);
     nb_esum out{elj, ec, qqd, {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}};
     if (VIR) {
 #pragma unroll
