@@ -305,8 +305,33 @@ def bench_adjoint(torch, nb, synth, reps=50):
     us_b = _event_us(torch, stream, lambda: bw(nb.NB_REUSE_LIST), reps)
     us_b_build = _event_us(torch, stream, lambda: bw(0), max(5, reps // 5))
     nb.nb_destroy(ctx)
+    # the adjoint on the headline box (96k atoms), beside its force call
+    mid = synth.mid()
+    nm = mid.natoms
+    xm = torch.from_numpy(mid.x.reshape(-1).copy()).to(dev)
+    qm = torch.from_numpy(mid.q.copy()).to(dev)
+    tm = torch.from_numpy(mid.type.copy()).to(dev)
+    fm = torch.empty(3 * nm, dtype=torch.float32, device=dev)
+    em = torch.empty(2, dtype=torch.float64, device=dev)
+    gfm = torch.randn(3 * nm, generator=g, device=dev)
+    dxm = torch.empty(3 * nm, dtype=torch.float32, device=dev)
+    dqm = torch.empty(nm, dtype=torch.float32, device=dev)
+    dsm = torch.empty(mid.ntypes, dtype=torch.float64, device=dev)
+    dem = torch.empty(mid.ntypes, dtype=torch.float64, device=dev)
+    cm = nb.nb_setup(nb.Params.from_instance(mid), stream=stream.cuda_stream)
+    nb.nb_pairlist(cm, xm)
+    useful_m = nb.nb_debug_pairs(cm, xm, 0, count_only=True)
+    nb.nb_forces(cm, xm, qm, tm, fm, em)
+    us_fm = _event_us(torch, stream, lambda: nb.nb_forces(cm, xm, qm, tm, fm, em), reps)
+    bwm = lambda: nb.nb_backward(cm, xm, qm, tm, gfm, ge, dxm, dqm, dsm, dem, nb.NB_REUSE_LIST)
+    bwm()
+    us_bm = _event_us(torch, stream, bwm, reps)
+    nb.nb_destroy(cm)
     return {"workload": "24,000-atom water box (8,000 waters, L 6.21 nm), 4 LJ types, "
                         "charges perturbed, rc 1.0 nm",
+            "water_96k": {"useful_pairs": useful_m, "us_per_force_call_fp32_energy": us_fm,
+                          "us_per_backward_call": us_bm, "backward_over_forces": us_bm / us_fm,
+                          "pair_interactions_per_s_backward": useful_m / (us_bm * 1e-6)},
             "useful_pairs": useful,
             "us_per_force_call": us_f["fp64_energy"],
             "us_per_force_call_fp32_energy": us_f["fp32_energy"],

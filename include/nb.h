@@ -285,9 +285,10 @@ int nb_debug_pairs(nb_ctx *ctx, const float *x_dev, int64_t *pairs_host, int64_t
 /* List statistics of the current list (synchronises). */
 int nb_get_stats(nb_ctx *ctx, nb_stats *st);
 
-/* Kernel timing: with on != 0, every later nb_forces records a HIP event pair around its force
- * kernel on the context's stream (a few microseconds of host overhead per call; off by default;
- * turning it on creates the events of the first 1024 timed launches).
+/* Kernel timing: with on != 0, the force kernel of every later nb_forces is dispatched with a HIP
+ * event pair that its dispatch stamps with the kernel's start and end (hipExtLaunchKernel; a few
+ * microseconds of host overhead per call; off by default; turning it on creates the events of
+ * the first 1024 timed launches).
  * nb_get_timing synchronises, returns the summed kernel time in milliseconds and the number of
  * timed launches since the last nb_get_timing, and resets both. */
 int nb_set_timing(nb_ctx *ctx, int on);

@@ -29,12 +29,6 @@ __global__ void k_pack_g(int npad_max, const int *__restrict__ perm, const float
     for (int k = 0; k < 6; ++k) adjj[k * npad_max + p] = 0.0f;
 }
 
-__device__ __forceinline__ float wsum(float v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, NB_WAVE);
-    return v;
-}
-
 template <int C>
 __global__ void __launch_bounds__(256) k_adjoint(nb_fparams fp, const double *__restrict__ ge, int cap,
                                                  int npad_max, const float4 *__restrict__ xq,
@@ -171,26 +165,19 @@ __global__ void __launch_bounds__(256) k_adjoint(nb_fparams fp, const double *__
             atomicAdd(&adjj[5 * npad_max + jslot], ju);
         }
     }
-#pragma unroll
-    for (int k = 0; k < C; ++k) {
-        ax[k] = wsum(ax[k]);
-        ay[k] = wsum(ay[k]);
-        az[k] = wsum(az[k]);
-        aq[k] = wsum(aq[k]);
-        aw[k] = wsum(aw[k]);
-        au[k] = wsum(au[k]);
-    }
-    if (lane == 0) {
-#pragma unroll
-        for (int k = 0; k < C; ++k) {
-            const int p = ci * C + k;
-            adj[p] = ax[k];
-            adj[npad_max + p] = ay[k];
-            adj[2 * npad_max + p] = az[k];
-            adj[3 * npad_max + p] = aq[k];
-            adj[4 * npad_max + p] = aw[k];
-            adj[5 * npad_max + p] = au[k];
-        }
+    // the i-side sums: a reduce-scatter across the wave leaves atom k's in the lanes with
+    // lane / (64 / C) == k; the first lane of each group stores them
+    const float sx = nb_wave_scatter_sum<C>(ax, lane), sy = nb_wave_scatter_sum<C>(ay, lane);
+    const float sz = nb_wave_scatter_sum<C>(az, lane), sq = nb_wave_scatter_sum<C>(aq, lane);
+    const float sw = nb_wave_scatter_sum<C>(aw, lane), su = nb_wave_scatter_sum<C>(au, lane);
+    if (lane % (NB_WAVE / C) == 0) {
+        const int p = ci * C + lane / (NB_WAVE / C);
+        adj[p] = sx;
+        adj[npad_max + p] = sy;
+        adj[2 * npad_max + p] = sz;
+        adj[3 * npad_max + p] = sq;
+        adj[4 * npad_max + p] = sw;
+        adj[5 * npad_max + p] = su;
     }
 }
 

@@ -635,13 +635,12 @@ static int forces_impl(nb_ctx *c, const float *x, const float *q, const int32_t 
             c->ev.push_back(a);
             c->ev.push_back(b);
         }
-        err = hipEventRecord(c->ev[2 * c->ev_used], c->stream);
     }
-    if (err == hipSuccess) err = nb_launch_force(c, vir != nullptr);
-    if (c->timing && err == hipSuccess) {
-        err = hipEventRecord(c->ev[2 * c->ev_used + 1], c->stream);
-        c->ev_used += 1;
-    }
+    // with timing on, the kernel's dispatch stamps an event pair with its own start and end
+    if (err == hipSuccess)
+        err = nb_launch_force(c, vir != nullptr, c->timing ? c->ev[2 * c->ev_used] : nullptr,
+                              c->timing ? c->ev[2 * c->ev_used + 1] : nullptr);
+    if (c->timing && err == hipSuccess) c->ev_used += 1;
     if (err == hipSuccess && (c->flags & NB_EWALD_CORR)) err = nb_launch_ewald_corr(c, x, q);
     if (err == hipSuccess) err = nb_launch_finalize(c, f, e, vir);
     if (err != hipSuccess) return hip_fail(c, err, "force launch");

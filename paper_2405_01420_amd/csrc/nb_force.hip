@@ -6,6 +6,8 @@
 // the flavour named in the Fig. 3 caption).  The per-cluster body and its lane layout are in
 // nb_force_body.h; here one wavefront is launched per work unit (an i-cluster's list or a part
 // of a long one).
+#include <hip/hip_ext.h>
+
 #include <algorithm>
 
 #include "nb_force_body.h"
@@ -322,63 +324,63 @@ hipError_t nb_launch_pack(nb_ctx *c, const float *x, const float *q, const int32
 }
 
 template <int C, bool EPREC, int FLAV, bool VIR>
-static void launch_force_t(nb_ctx *c) {
+static void launch_force_t(nb_ctx *c, hipEvent_t ev0, hipEvent_t ev1) {
     const bool tabf = FLAV / 2 == NB_ELEC_EWALD_TAB;
     const size_t shm = sizeof(float4) * 2 * c->ntypes * c->ntypes +
                        (EPREC ? sizeof(double2) * NB_ETAB_W * c->etab_n : 0) +
                        (tabf ? sizeof(float4) * NB_TAB_SEGMENTS : 0);
     dim3 grid((c->unit_cap + NB_FORCE_WAVES - 1) / NB_FORCE_WAVES), block(NB_FORCE_WAVES * NB_WAVE);
-    hipLaunchKernelGGL((k_force<C, EPREC, FLAV, VIR>), grid, block, shm, c->stream, c->fp, c->cap,
+    hipExtLaunchKernelGGL((k_force<C, EPREC, FLAV, VIR>), grid, block, (uint32_t)shm, c->stream, ev0, ev1, 0u, c->fp, c->cap,
                        c->npad_max, c->xq, c->tsort, c->ljtab, c->etab, EPREC ? c->etab_n : 0,
                        c->etab_invh, c->ftab, c->icount, c->jl, c->units, c->fj, c->epart,
                        c->vpart, c->meta);
 }
 
 template <int C, int FLAV>
-static void launch_force_f(nb_ctx *c, bool vir) {
+static void launch_force_f(nb_ctx *c, bool vir, hipEvent_t e0, hipEvent_t e1) {
     if constexpr (FLAV / 2 == NB_ELEC_EWALD_TAB) {
         // the tabulated flavour always evaluates its pair energies in FP64
-        if (vir) launch_force_t<C, true, FLAV, true>(c);
-        else launch_force_t<C, true, FLAV, false>(c);
+        if (vir) launch_force_t<C, true, FLAV, true>(c, e0, e1);
+        else launch_force_t<C, true, FLAV, false>(c, e0, e1);
     } else {
         const bool ep = (c->flags & NB_ENERGY_FP64) != 0;
         if (vir) {
-            if (ep) launch_force_t<C, true, FLAV, true>(c);
-            else launch_force_t<C, false, FLAV, true>(c);
+            if (ep) launch_force_t<C, true, FLAV, true>(c, e0, e1);
+            else launch_force_t<C, false, FLAV, true>(c, e0, e1);
         } else {
-            if (ep) launch_force_t<C, true, FLAV, false>(c);
-            else launch_force_t<C, false, FLAV, false>(c);
+            if (ep) launch_force_t<C, true, FLAV, false>(c, e0, e1);
+            else launch_force_t<C, false, FLAV, false>(c, e0, e1);
         }
     }
 }
 
 template <int C>
-static void launch_force_c(nb_ctx *c, bool vir) {
+static void launch_force_c(nb_ctx *c, bool vir, hipEvent_t e0, hipEvent_t e1) {
     switch (NB_FLAV(c->elec, c->vdw)) {
     case NB_FLAV(NB_ELEC_EWALD, NB_VDW_SHIFT):
-        launch_force_f<C, NB_FLAV(NB_ELEC_EWALD, NB_VDW_SHIFT)>(c, vir);
+        launch_force_f<C, NB_FLAV(NB_ELEC_EWALD, NB_VDW_SHIFT)>(c, vir, e0, e1);
         break;
     case NB_FLAV(NB_ELEC_EWALD, NB_VDW_FSWITCH):
-        launch_force_f<C, NB_FLAV(NB_ELEC_EWALD, NB_VDW_FSWITCH)>(c, vir);
+        launch_force_f<C, NB_FLAV(NB_ELEC_EWALD, NB_VDW_FSWITCH)>(c, vir, e0, e1);
         break;
     case NB_FLAV(NB_ELEC_RF, NB_VDW_SHIFT):
-        launch_force_f<C, NB_FLAV(NB_ELEC_RF, NB_VDW_SHIFT)>(c, vir);
+        launch_force_f<C, NB_FLAV(NB_ELEC_RF, NB_VDW_SHIFT)>(c, vir, e0, e1);
         break;
     case NB_FLAV(NB_ELEC_EWALD_TAB, NB_VDW_SHIFT):
-        launch_force_f<C, NB_FLAV(NB_ELEC_EWALD_TAB, NB_VDW_SHIFT)>(c, vir);
+        launch_force_f<C, NB_FLAV(NB_ELEC_EWALD_TAB, NB_VDW_SHIFT)>(c, vir, e0, e1);
         break;
     case NB_FLAV(NB_ELEC_EWALD_TAB, NB_VDW_FSWITCH):
-        launch_force_f<C, NB_FLAV(NB_ELEC_EWALD_TAB, NB_VDW_FSWITCH)>(c, vir);
+        launch_force_f<C, NB_FLAV(NB_ELEC_EWALD_TAB, NB_VDW_FSWITCH)>(c, vir, e0, e1);
         break;
     default:
-        launch_force_f<C, NB_FLAV(NB_ELEC_RF, NB_VDW_FSWITCH)>(c, vir);
+        launch_force_f<C, NB_FLAV(NB_ELEC_RF, NB_VDW_FSWITCH)>(c, vir, e0, e1);
         break;
     }
 }
 
-hipError_t nb_launch_force(nb_ctx *c, bool vir) {
-    if (c->C == 4) launch_force_c<4>(c, vir);
-    else launch_force_c<8>(c, vir);
+hipError_t nb_launch_force(nb_ctx *c, bool vir, hipEvent_t e0, hipEvent_t e1) {
+    if (c->C == 4) launch_force_c<4>(c, vir, e0, e1);
+    else launch_force_c<8>(c, vir, e0, e1);
     return hipGetLastError();
 }
 

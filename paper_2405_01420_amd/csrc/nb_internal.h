@@ -219,7 +219,8 @@ hipError_t nb_launch_prune_check(nb_ctx *c, const float *x);
 
 // ---- launchers (nb_force.hip) ----
 hipError_t nb_launch_pack(nb_ctx *c, const float *x, const float *q, const int32_t *type);
-hipError_t nb_launch_force(nb_ctx *c, bool vir);
+// ev0 / ev1 (or null): events that the dispatch itself stamps with the kernel's start and end
+hipError_t nb_launch_force(nb_ctx *c, bool vir, hipEvent_t ev0, hipEvent_t ev1);
 hipError_t nb_launch_finalize(nb_ctx *c, float *f, double *e, double *vir);
 hipError_t nb_launch_ewald_corr(nb_ctx *c, const float *x, const float *q);
 
