@@ -9,20 +9,26 @@ The whole trajectory is generated on the GPU before timing, so inputs are reside
 
 value = useful pair interactions per second (unordered, non-excluded pairs with r < rc,
 counted at the start positions) over the timed steps.  The JSON line also carries the
-force-kernel roofline (algorithmic FP32 flops per useful pair x useful pairs / measured kernel
-time, against the FP32 vector peak) and the FP64 oracle timed on the host as cpu_baseline.
+force-kernel roofline (algorithmic FP32 flops per useful pair x useful pairs / the force
+kernel's mean duration over the timed steps, from HIP event pairs that its dispatches stamp,
+against the FP32 vector peak) and the FP64 oracle timed on the host as cpu_baseline.
 
 Beside the headline line the JSON carries the two other forms against the plain kernel:
   batched - 256 independent boxes (3,000-30,000 atoms, log-uniform, rc 0.9 nm) in one persistent
             launch replayed from a HIP graph, with the autotuner's cluster sizes and schedule,
             against 256 sequential plain force calls on the same boxes;
   adjoint - the 24,000-atom four-type box: nb_backward (list reused, and with the list rebuilt
-            from x) against nb_forces on the same box.
+            from x) against nb_forces on the same box; and the adjoint on the 96k-atom box.
+Further legs: small_boxes (the plain kernel on single 3,000-, 12,000- and 24,000-atom boxes with
+its work units in cluster order and longest first, the post-prune list sorting); md (the
+leapfrog loop nb_md_leapfrog on a 32,000-ion charged LJ fluid, with and without the rolling
+prune); pme and ewald_step (the reciprocal part and the complete Ewald step).
 
 With --large it also times single force calls on the 3,000,000-atom box (median of 20).
 
 Usage: python bench.py [--gpus 1] [--steps 1000] [--warmup 20] [--cluster 8] [--cpu-seconds 12]
-                       [--no-batch] [--no-adjoint] [--no-tune] [--no-cpu] [--large]
+                       [--no-batch] [--no-adjoint] [--no-tune] [--no-pme] [--no-md] [--no-small]
+                       [--no-cpu] [--large]
 """
 import argparse
 import json

@@ -249,6 +249,11 @@ int upload_lj(nb_ctx *c) {
     return NB_OK;
 }
 
+// An event of the kernel-timing pairs: without the system-scope fence that a default event adds
+// when it is recorded (a cache write-back and invalidation that would slow the timed kernel);
+// the events are only read for their time stamps.
+hipError_t nb_timing_event(hipEvent_t *e) { return hipEventCreateWithFlags(e, hipEventDisableSystemFence); }
+
 // Sum the recorded event pairs into timed_ms (synchronises on the last stop event).
 int drain_events(nb_ctx *c) {
     for (size_t k = 0; k < c->ev_used; ++k) {
@@ -630,7 +635,7 @@ static int forces_impl(nb_ctx *c, const float *x, const float *q, const int32_t 
         }
         if (c->ev.size() < 2 * (c->ev_used + 1)) {
             hipEvent_t a, b;
-            if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+            if (nb_timing_event(&a) != hipSuccess || nb_timing_event(&b) != hipSuccess)
                 return fail(c, NB_ERR_HIP, "hipEventCreate");
             c->ev.push_back(a);
             c->ev.push_back(b);
@@ -665,8 +670,8 @@ int nb_set_timing(nb_ctx *c, int on) {
     hipSetDevice(c->device);
     while (c->timing && c->ev.size() < 2 * 1024) {
         hipEvent_t a, b;
-        if (hipEventCreate(&a) != hipSuccess) return fail(c, NB_ERR_HIP, "hipEventCreate");
-        if (hipEventCreate(&b) != hipSuccess) {
+        if (nb_timing_event(&a) != hipSuccess) return fail(c, NB_ERR_HIP, "hipEventCreate");
+        if (nb_timing_event(&b) != hipSuccess) {
             hipEventDestroy(a);
             return fail(c, NB_ERR_HIP, "hipEventCreate");
         }
