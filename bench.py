@@ -55,16 +55,16 @@ FLOPS_PER_PAIR_FLAVOUR = {("ewald", "shift"): 65, ("rf", "shift"): 45,
 PEAK_FP32_VECTOR_TFLOPS = 157.3
 REBUILD_EVERY = 10
 
-# rocprofv3 counters of k_force on the 96k-atom box (profiles/k_force_water96k_hbm_counters.md):
+# rocprofv3 counters of k_force on the 96k-atom box (profiles/k_force_water96k_counters.md):
 # HBM bytes per launch from FETCH_SIZE and WRITE_SIZE, each scaled by the reading for a 256 MiB
 # device copy (factors 2.0 and 1.0), and the counted FP32 VALU flops per launch
 # (SQ_INSTS_VALU_FLOPS_FP32 x 64 lanes).  They describe the kernel built from the sources with
 # this digest and are reported only while the sources are unchanged.
 K_FORCE_COUNTERS = {
     "sources": ["nb_force_body.h", "nb_force.hip", "nb_device.h", "nb_internal.h", "erfcx_rational.h"],
-    "sha256": "4b0c710bf41df6a4eed15fedaf64c836b32f939c1b34d90b783a1d34add0d469",
-    "read_bytes": 32.94e6, "write_bytes": 73.72e6,
-    "counted_fp32_flop": 4680189322.5,
+    "sha256": "d8ecabda305549144c874953edf78f721cd82b983a78fb3f0d053f738d24d5ce",
+    "read_bytes": 31.60e6, "write_bytes": 73.72e6,
+    "counted_fp32_flop": 2660883088.9,
 }
 
 
