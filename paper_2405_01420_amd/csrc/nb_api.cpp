@@ -98,9 +98,13 @@ void lj_table(nb_ctx *c, std::vector<float4> &tab) {
 
 void set_constants(nb_ctx *c) {
     nb_fparams &fp = c->fp;
-    for (int k = 0; k < 3; ++k) fp.L[k] = (float)c->box[k];
+    for (int k = 0; k < 3; ++k) {
+        fp.L[k] = (float)c->box[k];
+        fp.nL[k] = -fp.L[k];
+    }
     fp.rc2 = (float)(c->rc * c->rc);
     fp.fc = (float)c->fc;
+    fp.fcs = fp.fc * NB_FSCALE;
     const double beta = c->beta;
     fp.cexp = (float)(-beta * beta * 1.4426950408889634);
     fp.kb = (float)(2.0 * beta / sqrt(M_PI));
@@ -137,6 +141,10 @@ void set_constants(nb_ctx *c) {
         fp.sw_b6 = (float)k6.B;
         fp.sw_a12 = (float)k12.A;
         fp.sw_b12 = (float)k12.B;
+        fp.fsw_a6 = fp.sw_a6 * NB_FSCALE;
+        fp.fsw_b6 = fp.sw_b6 * NB_FSCALE;
+        fp.fsw_a12 = fp.sw_a12 * NB_FSCALE;
+        fp.fsw_b12 = fp.sw_b12 * NB_FSCALE;
         fp.sw_ea6 = (float)(k6.A / 3.0);
         fp.sw_eb6 = (float)(k6.B / 4.0);
         fp.sw_ea12 = (float)(k12.A / 3.0);
@@ -441,8 +449,9 @@ int nb_setup(nb_ctx **out, const nb_params *p, void *stream) {
     NB_ALLOC(colcl, g.ncol + 1);
     NB_ALLOC(perm, c->npad_max);
     NB_ALLOC(xs, c->npad_max);
-    NB_ALLOC(xq, c->npad_max);
-    NB_ALLOC(tsort, c->npad_max);
+    // one j-group more than the slots: the far group that lanes past the end of a j-list read
+    NB_ALLOC(xq, c->npad_max + NB_JG);
+    NB_ALLOC(tsort, c->npad_max + NB_JG);
 
     NB_ALLOC(fj, 3 * (size_t)c->npad_max);
     NB_ALLOC(bblo, c->ncl_max);
@@ -455,6 +464,17 @@ int nb_setup(nb_ctx **out, const nb_params *p, void *stream) {
     NB_ALLOC(meta, 1);
     NB_ALLOC(ljtab, 2 * (size_t)c->ntypes * c->ntypes);
 #undef NB_ALLOC
+    {
+        // the far j-group (slots npad_max ..): far outside any box, type 0; no kernel writes it
+        const float4 far[NB_JG] = {make_float4(-1e5f, -1e5f, -1e5f, 0.0f), make_float4(-1e5f, -1e5f, -1e5f, 0.0f),
+                                   make_float4(-1e5f, -1e5f, -1e5f, 0.0f), make_float4(-1e5f, -1e5f, -1e5f, 0.0f)};
+        const int zero[NB_JG] = {0, 0, 0, 0};
+        if (hipMemcpy(c->xq + c->npad_max, far, sizeof(far), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(c->tsort + c->npad_max, zero, sizeof(zero), hipMemcpyHostToDevice) != hipSuccess) {
+            r = fail(c, NB_ERR_HIP, "nb_setup: initialising the far j-group failed");
+            goto fail_out;
+        }
+    }
     if ((r = alloc_list(c)) != NB_OK) goto fail_out;
     if (p->excl_off) {
         int nnz = p->excl_off[n];

@@ -105,9 +105,9 @@ __global__ void __launch_bounds__(256) NB_FORCE_OCCUPANCY k_batch_force(nb_fpara
                                                      float etab_invh, unsigned *counter,
                                                      unsigned *flags) {
     extern __shared__ float4 tab[];
-    __shared__ nb_wlds<C, EPREC, FLAV> wl[256 / NB_WAVE];
+    __shared__ __attribute__((aligned(C * NB_WAVE * 4))) nb_wg_lds<C, EPREC, FLAV, 256 / NB_WAVE> wl;
     const int ntt = fp.ntypes * fp.ntypes;
-    for (int k = threadIdx.x; k < 2 * ntt; k += blockDim.x) tab[k] = ljtab[k];
+    nb_load_ljtab(tab, ljtab, ntt);
     nb_etab et;
     et.seg = reinterpret_cast<const double2 *>(tab + 2 * ntt);
     et.invh = etab_invh;
@@ -119,6 +119,7 @@ __global__ void __launch_bounds__(256) NB_FORCE_OCCUPANCY k_batch_force(nb_fpara
     }
     __syncthreads();
     const int lane = threadIdx.x & (NB_WAVE - 1);
+    const nb_wv wvw = nb_wave_view(wl, __builtin_amdgcn_readfirstlane(threadIdx.x / NB_WAVE));
     // Every lane executes the queue atomic (lane 0 adds 1, the others 0; the compiler issues
     // one atomic per wave), so no divergent region precedes the uniform exit test; the value
     // lane 0 saw is the chunk of this wave.  The trip count is bounded by nchunks even if the
@@ -138,9 +139,12 @@ __global__ void __launch_bounds__(256) NB_FORCE_OCCUPANCY k_batch_force(nb_fpara
             f.L[0] = d.L[0];
             f.L[1] = d.L[1];
             f.L[2] = d.L[2];
+            f.nL[0] = -d.L[0];
+            f.nL[1] = -d.L[1];
+            f.nL[2] = -d.L[2];
             // the descriptor's pointers are global memory; typed so, their accesses are global
-            const nb_esum es = nb_force_cluster<C, EPREC, FLAV, false, true>(
-                f, tab, et, wl[threadIdx.x / NB_WAVE], ci, 0, 1 << 20, d.cap, d.npad_max, nb_g(d.xq), nb_g(d.tsort),
+            const nb_esum es = nb_force_cluster<C, EPREC, FLAV, false>(
+                f, tab, et, wvw, ci, 0, 1 << 20, d.cap, d.npad_max, nb_g(d.xq), nb_g(d.tsort),
                 nb_g(d.icount), nb_g(d.jl), nb_g(d.fj), nb_g(flags));
             if (lane == 0) {
                 NB_G double *ep = nb_g(d.epart) + 4 * ci;

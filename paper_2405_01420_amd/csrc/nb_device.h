@@ -14,8 +14,13 @@ __device__ __forceinline__ int nb_tz(int s) { return s % 3 - 1; }
 // (Sterbenz) and d = (x_i + di) - (x_j + dj) carries a single rounding.
 //   t = +1: j image near 0 seen from i near L  -> di = -L, dj = 0
 //   t = -1: j near L seen from i near 0        -> di = 0,  dj = -L
-__device__ __forceinline__ float nb_di(int t, float L) { return t > 0 ? -L : 0.0f; }
-__device__ __forceinline__ float nb_dj(int t, float L) { return t < 0 ? -L : 0.0f; }
+// (Integer selects of the bit patterns: with a wave-uniform t they stay on the scalar unit.)
+__device__ __forceinline__ float nb_di(int t, float L) {
+    return __uint_as_float(t > 0 ? __float_as_uint(L) ^ 0x80000000u : 0u);
+}
+__device__ __forceinline__ float nb_dj(int t, float L) {
+    return __uint_as_float(t < 0 ? __float_as_uint(L) ^ 0x80000000u : 0u);
+}
 
 __device__ __forceinline__ float nb_r2(float dx, float dy, float dz) {
     return __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
@@ -49,6 +54,26 @@ template <class T>
 __device__ __forceinline__ T nb_ld(const NB_G T *p) { return *(const T *)p; }
 template <class T>
 __device__ __forceinline__ void nb_st(NB_G T *p, const T &v) { *(T *)p = v; }
+
+// LDS (address space 3) accesses by byte address, for work areas addressed from packed codes.
+#define NB_L __attribute__((address_space(3)))
+__device__ __forceinline__ uint32_t nb_laddr(const void *p) {
+    return (uint32_t)(size_t)(const NB_L void *)p;
+}
+// (The generic pointer made from the LDS one is turned back into LDS accesses by the compiler;
+// HIP's vector types have no operators on address-space-qualified references.)
+template <class T>
+__device__ __forceinline__ T nb_lget(uint32_t a) { return *(const T *)(const NB_L T *)(size_t)a; }
+template <class T>
+__device__ __forceinline__ void nb_lput(uint32_t a, const T &v) { *(T *)(NB_L T *)(size_t)a = v; }
+
+// A value in a vector register that the compiler treats as unknown: bit masks used as VOP3
+// operands (which take no literal constant) stay in registers instead of splitting the op.
+__device__ __forceinline__ uint32_t nb_vreg(uint32_t v) {
+    uint32_t r;
+    asm("v_mov_b32 %0, %1" : "=v"(r) : "s"(v));
+    return r;
+}
 
 // The C mask bits of j-atom b of an entry (bit k: i-atom k interacts with j-atom b).
 template <int C>

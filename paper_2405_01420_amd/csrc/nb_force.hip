@@ -78,12 +78,12 @@ __global__ void __launch_bounds__(NB_FORCE_WAVES * NB_WAVE) NB_FORCE_OCCUPANCY_V
                                                double *__restrict__ epart, double *__restrict__ vpart,
                                                nb_meta *meta) {
     extern __shared__ float4 tab[];
-    __shared__ nb_wlds<C, EPREC, FLAV> wl[NB_FORCE_WAVES];
+    __shared__ __attribute__((aligned(C * NB_WAVE * 4))) nb_wg_lds<C, EPREC, FLAV, NB_FORCE_WAVES> wl;
     __shared__ double esh[NB_FORCE_WAVES][VIR ? 9 : 3];
     __shared__ int edone;
     const int ntt = fp.ntypes * fp.ntypes;
     if (threadIdx.x == 0) edone = 0;
-    for (int k = threadIdx.x; k < 2 * ntt; k += blockDim.x) tab[k] = ljtab[k];
+    nb_load_ljtab(tab, ljtab, ntt);
     nb_etab et;
     et.seg = reinterpret_cast<const double2 *>(tab + 2 * ntt);
     et.invh = etab_invh;
@@ -98,14 +98,15 @@ __global__ void __launch_bounds__(NB_FORCE_WAVES * NB_WAVE) NB_FORCE_OCCUPANCY_V
     if (FLAV / 2 == NB_ELEC_EWALD_TAB)
         for (int k = threadIdx.x; k < NB_TAB_SEGMENTS; k += blockDim.x) fdst[k] = ftab[k];
     __syncthreads();
-    const int lane = threadIdx.x & (NB_WAVE - 1), wv = threadIdx.x / NB_WAVE;
+    const int lane = threadIdx.x & (NB_WAVE - 1);
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / NB_WAVE);
     const int u = __builtin_amdgcn_readfirstlane(blockIdx.x * NB_FORCE_WAVES + wv);
     const int nunits = meta->nunits;
     if (blockIdx.x * NB_FORCE_WAVES >= nunits) return;  // the whole workgroup is idle
     nb_esum es{0.0, 0.0, 0.0, {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}};
     if (u < nunits) {
         const int4 w = units[u];
-        es = nb_force_cluster<C, EPREC, FLAV, VIR, true>(fp, tab, et, wl[wv], __builtin_amdgcn_readfirstlane(w.x),
+        es = nb_force_cluster<C, EPREC, FLAV, VIR>(fp, tab, et, nb_wave_view(wl, wv), __builtin_amdgcn_readfirstlane(w.x),
                                               __builtin_amdgcn_readfirstlane(w.y),
                                               __builtin_amdgcn_readfirstlane(w.z), cap, npad_max,
                                               nb_g(xq), nb_g(tsort), nb_g(icount), nb_g(jl), nb_g(fj), nb_g(&meta->flags));

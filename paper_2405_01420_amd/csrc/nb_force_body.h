@@ -9,18 +9,22 @@
 //    mask unless every listed pair of the batch is unmasked (the common case, checked with one
 //    ballot); the pairs that interact (about a third of the listed ones) are appended to a
 //    per-wave queue in LDS in (k, lane) order with a ballot and a lane count, as (r^2, pair
-//    code), the code holding the pair's LJ table row, k and the j lane.  Evaluate: the queue is
-//    worked through 64 pairs at a time, one pair per lane, so the Lennard-Jones and Ewald
-//    arithmetic (the transcendental functions, the erfc approximation, the energies) runs only
-//    on interacting pairs with all lanes busy; each pair's scalar force factor goes to its place
-//    (64 k + lane) in a per-wave area cleared at the start of the batch.  Accumulate: every lane
-//    reads the factors of its own C pairs (zero where the pair does not interact) and adds f d
-//    to the i-force and j-force sums in registers, in the same order as a plain loop over k;
+//    code), the code holding LDS byte addresses: of the pair's LJ table row, and of its force
+//    factor, i-atom and j lane within the wave's parts of the work area (one shift or one
+//    and-or each to decode).  Evaluate: the queue is worked through 64 pairs at a time, one pair
+//    per lane, so the Lennard-Jones and Ewald arithmetic (the transcendental functions, the erfc
+//    approximation, the energies) runs only on interacting pairs with all lanes busy; each
+//    pair's scalar force factor goes to its place (64 k + lane) in a per-wave area cleared at the
+//    start of the batch.  Accumulate: every lane reads the factors of its own C pairs (zero
+//    where the pair does not interact) and adds f d to the i-force and j-force sums in
+//    registers, in the same order as a plain loop over k;
+//  * force factors come out in fixed-point units (the charge products and the table's force
+//    coefficients carry the scale 2^12), so a sum converts to its integer with one rounding;
 //  * batches whose entries share one periodic shift (the common case, since the list is grouped
 //    by shift) use i-coordinates moved into that frame once and cached in scalar registers;
-//  * the j-force of a lane's atom needs one atomic add per component per batch (the only
-//    atomics); the i-forces accumulate per lane over the whole list and are reduced across the
-//    64 lanes once per i-cluster with DPP row operations;
+//  * the j-force of a lane's atom needs two atomic adds per batch (x and y in one 64-bit word,
+//    z; the only atomics), skipped where the sum is zero; the i-forces accumulate per lane over
+//    the whole list and are reduce-scattered across the 64 lanes once per work unit;
 //  * erfc(beta r) = exp(-beta^2 r^2) P(r) / Q(r) with a (4,5) rational fit of the scaled
 //    complementary error function (fit_erfcx.py), Newton-refined reciprocal square root and
 //    reciprocal;
@@ -58,24 +62,61 @@ __device__ __forceinline__ void nb_wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Per-wavefront LDS work area of the force body.  RAWQ: the flavour needs the charges as loaded
-// (exact FP64 products q_i q_j: FP64 pair energies, and the reaction-field shift weight).
-template <int C, bool EPREC, int FLAV>
-struct nb_wlds {
+// LDS work areas of the force body for the NW wavefronts of a workgroup, one part per wave in
+// every array.  RAWQ: the flavour needs the charges as loaded (exact FP64 products q_i q_j: FP64
+// pair energies, and the reaction-field shift weight).  The evaluate phase addresses fsb, jqf and
+// id from the bits of a pair code: each wave's part of these starts at a multiple of a power of
+// two no smaller than the part (the struct is placed at a multiple of C * 256 bytes, the size of
+// one fsb part), so the element offset is combined with the part's base by a bitwise or.
+template <int C, bool EPREC, int FLAV, int NW>
+struct nb_wg_lds {
     static constexpr bool RAWQ = EPREC || FLAV / 2 == NB_ELEC_RF;
-    uint2 q[C * NB_WAVE];          // the batch's interacting pairs: (r^2 bits, pair code)
-    float fsb[C * NB_WAVE];        // force factor of pair (i-atom k, j lane) at 64 k + lane
-    float jqf[NB_WAVE];            // per j lane: fC q_j
-    float4 id[C];                  // per i-atom: (x, y, z, q) as loaded (unshifted)
-    float jq[RAWQ ? NB_WAVE : 1];     // per j lane: q_j as loaded
-    float4 jx[EPREC ? NB_WAVE : 1];   // FP64-energy mode, per j lane: x_j moved into the pair frame
-    float4 jdi[EPREC ? NB_WAVE : 1];  // FP64-energy mode, per j lane: the i-frame offset of its pair
+    static constexpr int ALIGN = C * NB_WAVE * 4;
+    float fsb[NW][C * NB_WAVE];     // force factor of pair (i-atom k, j lane) at 64 k + lane
+    float jqf[NW][NB_WAVE];         // per j lane: fC NB_FSCALE q_j
+    float4 id[NW][C];               // per i-atom: (x, y, z, q) as loaded (unshifted)
+    uint2 q[NW][C * NB_WAVE];       // the batch's interacting pairs: (r^2 bits, pair code)
+    float jq[NW][RAWQ ? NB_WAVE : 1];     // per j lane: q_j as loaded
+    float4 jx[NW][EPREC ? NB_WAVE : 1];   // FP64-energy mode, per j lane: x_j moved into the pair frame
+    float4 jdi[NW][EPREC ? NB_WAVE : 1];  // FP64-energy mode, per j lane: the i-frame offset of its pair
 };
 
-// Pair code of a queued pair: (LJ table row << 9) | (i-atom k << 6) | j lane, the row being
-// t_i * ntypes + t_j (below NB_MAX_TYPES^2 = 2^10); its low 9 bits are the pair's place in fsb.
-#define NB_PC_ROW 9
-#define NB_PC_SLOT 511u
+// One wavefront's parts of the work area, as LDS byte addresses (wave-uniform).
+struct nb_wv {
+    uint32_t fsb, jqf, id, q, jq, jx, jdi;
+};
+
+template <int C, bool EPREC, int FLAV, int NW>
+__device__ __forceinline__ nb_wv nb_wave_view(nb_wg_lds<C, EPREC, FLAV, NW> &g, int wv) {
+    using G = nb_wg_lds<C, EPREC, FLAV, NW>;
+    static_assert(offsetof(G, fsb) == 0 && offsetof(G, jqf) % (NB_WAVE * 4) == 0 &&
+                      offsetof(G, id) % (C * 16) == 0,
+                  "or-addressed parts must sit at multiples of their size");
+    return nb_wv{nb_laddr(&g.fsb[wv][0]), nb_laddr(&g.jqf[wv][0]), nb_laddr(&g.id[wv][0]),
+                 nb_laddr(&g.q[wv][0]),   nb_laddr(&g.jq[wv][0]),  nb_laddr(&g.jx[wv][0]),
+                 nb_laddr(&g.jdi[wv][0])};
+}
+
+// Pair code of a queued pair: (LDS byte address of its LJ table row << NB_PC_ROW) | (64 k + j
+// lane) * 4 for i-atom k.  The low bits are the byte offset of the pair's force factor in its
+// wave's fsb part; within them, bits 2-7 are 4 x the j lane and bits 8-10 the i-atom.
+#define NB_PC_ROW 11
+#define NB_PC_FSB 0x7FCu  // (64 k + lane) * 4
+#define NB_PC_JQF 0xFCu   // lane * 4
+#define NB_PC_ID 0x70u    // k * 16, from the code shifted right by 4
+
+// The LJ table as the force body reads it: the force coefficients (6 C6, 12 C12) carry the
+// fixed-point scale NB_FSCALE, so that force factors come out in fixed-point units.
+__device__ __forceinline__ void nb_load_ljtab(float4 *tab, const float4 *ljtab, int ntt) {
+    for (int k = threadIdx.x; k < 2 * ntt; k += blockDim.x) {
+        float4 v = ljtab[k];
+        if ((k & 1) == 0) {
+            v.z *= NB_FSCALE;
+            v.w *= NB_FSCALE;
+        }
+        tab[k] = v;
+    }
+}
 
 // Erfc table of the FP64 energy mode: quintic Hermite segments of erfc(beta r) on
 // [k h, (k+1) h] (value and first and second derivatives matched at both ends) with h a power of
@@ -150,8 +191,8 @@ __device__ __forceinline__ float pair_eval(const nb_fparams &fp, const nb_etab &
         // t^3 to the energy
         const float t = fmaxf(r - fp.sw_r1, 0.0f);
         const float t2 = t * t;
-        const float p12 = __builtin_fmaf(fp.sw_b12, t, fp.sw_a12);
-        const float p6 = __builtin_fmaf(fp.sw_b6, t, fp.sw_a6);
+        const float p12 = __builtin_fmaf(fp.fsw_b12, t, fp.fsw_a12);  // force terms: scaled
+        const float p6 = __builtin_fmaf(fp.fsw_b6, t, fp.fsw_a6);
         const float sw = __builtin_fmaf(lj.y, p12, -lj.x * p6);
         flj = __builtin_fmaf(sw * t2, r, flj);  // the magnitude times r (the force factor carries r^-2)
         const float e12 = __builtin_fmaf(fp.sw_eb12, t, fp.sw_ea12);
@@ -222,6 +263,14 @@ __device__ __forceinline__ float pair_eval(const nb_fparams &fp, const nb_etab &
 template <bool EPREC, int FLAV>
 constexpr bool nb_qq64() { return EPREC || FLAV / 2 == NB_ELEC_RF; }
 
+// v where the wave-uniform c holds, else +0: an integer select kept on the scalar unit (the
+// result is opaque to the compiler, which would otherwise move the select to the vector unit).
+__device__ __forceinline__ float nb_sel_s(bool c, float v) {
+    uint32_t r = c ? __float_as_uint(v) : 0u;
+    asm("" : "+s"(r));
+    return __uint_as_float(r);
+}
+
 __device__ __forceinline__ float nb_uniform(float v) {
     return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
 }
@@ -237,24 +286,34 @@ __device__ __forceinline__ unsigned long long nb_fix_xy(float x, float y) {
     return (unsigned long long)(long long)nb_fix(x) + ((unsigned long long)(unsigned)nb_fix(y) << 32);
 }
 
-// Adds one atom's force contribution (lane-wise, where `on`) to the fixed-point accumulators
-// fxy / fz, or to the FP32 ones (fj[3][npad_max]); the fixed-point form also raises the range
-// flag if any active lane's component exceeds NB_FRANGE (or is not finite).
-template <bool FIX>
-__device__ __forceinline__ void nb_add_force(bool on, int slot, float fx, float fy, float fz,
-                                             NB_G float *fj, int npad_max, NB_G unsigned *flags,
-                                             int lane) {
-    if (FIX) {
-        const float m = fmaxf(fmaxf(fabsf(fx), fabsf(fy)), fabsf(fz));
-        if (__ballot(on && !(m < NB_FRANGE)) != 0ull && lane == 0) atomicOr((unsigned *)flags, NB_F_RANGE);
-        if (on) {
-            atomicAdd((unsigned long long *)fj + slot, nb_fix_xy(fx, fy));
-            atomicAdd((int *)(fj + 2 * npad_max) + slot, nb_fix(fz));
-        }
-    } else if (on) {
-        atomicAdd((float *)(fj + slot), fx);
-        atomicAdd((float *)(fj + npad_max + slot), fy);
-        atomicAdd((float *)(fj + 2 * npad_max + slot), fz);
+// Fixed-point value of a force component that already carries the factor NB_FSCALE: rounded to
+// the nearest integer, ties to even (FP32 values of 2^22 and above are multiples of 1/2, so ties
+// are common, and rounding them all one way would bias the sums: the forces on the two atoms of
+// a pair would no longer cancel), then converted by the hardware instruction, whose result is
+// defined for every input (saturating; values that large raise the range flag anyway).
+__device__ __forceinline__ int nb_rne(float v) {
+    int r;
+    asm("v_cvt_i32_f32 %0, %1" : "=v"(r) : "v"(__builtin_rintf(v)));
+    return r;
+}
+
+// Adds one atom's force contribution, in units of 1 / NB_FSCALE (lane-wise, where `on` and not
+// zero), to the fixed-point accumulators: x + 2^32 y in one 64-bit word (x sign-extended, so the
+// high word is y - 1 for negative x), z in a 32-bit word.  Raises the range flag if an active
+// lane's component reaches NB_FRANGE (or is not finite).
+__device__ __forceinline__ void nb_add_fix(bool on, int slot, float fx, float fy, float fz,
+                                           NB_G float *fj, int npad_max, NB_G unsigned *flags,
+                                           int lane) {
+    const float m = fmaxf(fmaxf(fabsf(fx), fabsf(fy)), fabsf(fz));
+    if ((__builtin_amdgcn_ballot_w64(!(m < NB_FRANGE * NB_FSCALE)) & __builtin_amdgcn_ballot_w64(on)) != 0ull &&
+        lane == 0)
+        atomicOr((unsigned *)flags, NB_F_RANGE);
+    if (on && m != 0.0f) {
+        const int ix = nb_rne(fx), iy = nb_rne(fy), iz = nb_rne(fz);
+        const unsigned long long xy =
+            ((unsigned long long)(unsigned)(iy + (ix >> 31)) << 32) | (unsigned long long)(unsigned)ix;
+        atomicAdd((unsigned long long *)fj + slot, xy);
+        atomicAdd((int *)(fj + 2 * npad_max) + slot, iz);
     }
 }
 
@@ -267,34 +326,45 @@ struct nb_esum {
 
 // Forces and energy sums of one work unit, computed by one wavefront: the batches
 // [b0, b0 + nbat) of i-cluster ci's j-list (all of them, or one part of a long list).  fp.L
-// holds the box of the cluster; w is the wavefront's LDS work area.  Both the j-forces and the
-// unit's i-force sums are added atomically to fj (several units may share an i-cluster), in
-// fixed point with FIX (the layout of nb_add_force), in FP32 otherwise; the energy sums are
-// returned.
-template <int C, bool EPREC, int FLAV, bool VIR, bool FIX>
+// holds the box of the cluster; w is the wavefront's part of the LDS work area and tab the LJ
+// table in LDS (nb_load_ljtab).  Both the j-forces and the unit's i-force sums are added
+// atomically to fj in fixed point (nb_add_fix; several units may share an i-cluster); the energy
+// sums are returned.  Force factors are formed in units of 1 / NB_FSCALE (the charge products
+// and the table's force coefficients carry the scale); the energy sums that inherit it are
+// scaled back exactly (a power of two) at the end.
+template <int C, bool EPREC, int FLAV, bool VIR>
 __device__ __forceinline__ nb_esum nb_force_cluster(const nb_fparams &fp, const float4 *tab,
-                                                 const nb_etab &et, nb_wlds<C, EPREC, FLAV> &w,
-                                                 int ci, int b0, int nbat, int cap, int npad_max,
+                                                 const nb_etab &et, const nb_wv &w, int ci,
+                                                 int b0, int nbat, int cap, int npad_max,
                                                  const NB_G float4 *__restrict__ xq,
                                                  const NB_G int *__restrict__ tsort,
                                                  const NB_G int *__restrict__ icount,
                                                  const NB_G nb_entry *__restrict__ jl,
                                                  NB_G float *__restrict__ fj,
                                                  NB_G unsigned *__restrict__ flags) {
-    constexpr bool RAWQ = nb_wlds<C, EPREC, FLAV>::RAWQ;
+    constexpr bool RAWQ = EPREC || FLAV / 2 == NB_ELEC_RF;
     constexpr unsigned FULL = (1u << C) - 1u;
     const int nt = fp.ntypes;
     const int lane = threadIdx.x & (NB_WAVE - 1);
     const int b = lane % NB_JG, jsub = lane / NB_JG;  // j-atom within the group, entry in batch
+    const uint32_t lane4 = (uint32_t)lane * 4u;
 
     // i-atoms: coordinates and charges in LDS (the evaluate phase, where a lane's i-atom varies,
-    // and the frame changes read them); per i-atom the constant part of its pairs' codes,
-    // (t_i ntypes << 9) | (k << 6), wave-uniform
-    if (lane < C) w.id[lane] = nb_ld(xq + ci * C + lane);
-    int pci[C];
+    // and the frame changes read them); per i-atom the constant part of its pairs' codes, the
+    // address of the LJ table row t_i * ntypes and k, wave-uniform
+    // the wave's parts of the work area that are addressed by position
+    float4 *const idp = (float4 *)(NB_L float4 *)(size_t)w.id;
+    float *const fsbp = (float *)(NB_L float *)(size_t)w.fsb;
+    float *const jqfp = (float *)(NB_L float *)(size_t)w.jqf;
+    if (lane < C) idp[lane] = nb_ld(xq + ci * C + lane);
+    const uint32_t tabrow = nb_laddr(tab);
+    uint32_t pci[C];
 #pragma unroll
     for (int k = 0; k < C; ++k)
-        pci[k] = (__builtin_amdgcn_readfirstlane(nb_ld(tsort + ci * C + k)) * nt << NB_PC_ROW) | (k << 6);
+        pci[k] = ((tabrow + 32u * (uint32_t)(__builtin_amdgcn_readfirstlane(nb_ld(tsort + ci * C + k)) * nt))
+                  << NB_PC_ROW) | ((uint32_t)k << 8);
+    // the code masks in vector registers, for single and-or address operations
+    const uint32_t mfsb = nb_vreg(NB_PC_FSB), mjqf = nb_vreg(NB_PC_JQF), mid = nb_vreg(NB_PC_ID);
     nb_wave_lds_sync();
     int cur_shift = -1;  // shift the cached i-frame coordinates xs/ys/zs belong to (none yet)
     float xs[C], ys[C], zs[C];
@@ -319,40 +389,43 @@ __device__ __forceinline__ nb_esum nb_force_cluster(const nb_fparams &fp, const 
     for (int base = b0 * NB_JPB; base < nj; base += NB_JPB) {
         const int e = base + jsub;
         const bool valid = e < nj;
-        // lanes past the end of the list read the i-cluster's own first group with an empty mask
-        // and place their j-atom far outside the box, so that none of its pairs is in range
-        const nb_entry en = valid ? nb_ld(lst + e) : nb_make_entry(ci * (C / NB_JG), NB_SHIFT_ZERO, 0u);
+        // lanes past the end of the list read the far group behind the last slot (coordinates
+        // far outside any box) with an empty mask, so that none of their pairs is in range
+        const nb_entry en = valid ? nb_ld(lst + e) : nb_make_entry(npad_max / NB_JG, NB_SHIFT_ZERO, 0u);
         const int s = nb_entry_shift(en);
         const int jslot = nb_entry_group(en) * NB_JG + b;
         const float4 xj = nb_ld(xq + jslot);
         const int tj = nb_ld(tsort + jslot);
         const unsigned mcol = nb_mask_column<C>(en.mask, b);
         const int s0 = __builtin_amdgcn_readfirstlane(s);
-        const bool uniform = __ballot(valid && s != s0) == 0ull;
+        // (ballots of single compares combined on the scalar unit: a ballot of a compound
+        // condition costs two more vector instructions)
+        const unsigned long long vmask = __builtin_amdgcn_ballot_w64(valid);
+        const bool uniform = (__builtin_amdgcn_ballot_w64(s != s0) & vmask) == 0ull;
         // ---- filter: displacements of the lane's C pairs, interacting pairs queued in LDS
         float dx[C], dy[C], dz[C];
         float jx, jy, jz;     // the j-atom in the pair frame
         float dix, diy, diz;  // the i-frame offset of this lane's pairs
         if (uniform) {
-            // one periodic shift for the whole batch: i-coordinates of that frame are cached
+            // one periodic shift for the whole batch: i-coordinates of that frame are cached, and
+            // the frame offsets are scalar selects
             const int tx = nb_tx(s0), ty = nb_ty(s0), tz = nb_tz(s0);
-            dix = nb_di(tx, fp.L[0]);
-            diy = nb_di(ty, fp.L[1]);
-            diz = nb_di(tz, fp.L[2]);
+            dix = nb_sel_s(tx > 0, fp.nL[0]);
+            diy = nb_sel_s(ty > 0, fp.nL[1]);
+            diz = nb_sel_s(tz > 0, fp.nL[2]);
             if (s0 != cur_shift) {
                 cur_shift = s0;
 #pragma unroll
                 for (int k = 0; k < C; ++k) {
-                    const float4 v = w.id[k];
+                    const float4 v = idp[k];
                     xs[k] = nb_uniform(v.x + dix);
                     ys[k] = nb_uniform(v.y + diy);
                     zs[k] = nb_uniform(v.z + diz);
                 }
             }
-            jx = xj.x + nb_dj(tx, fp.L[0]);
-            jy = xj.y + nb_dj(ty, fp.L[1]);
-            jz = xj.z + nb_dj(tz, fp.L[2]);
-            if (!valid) jx = jy = jz = 1e18f;
+            jx = xj.x + nb_sel_s(tx < 0, fp.nL[0]);
+            jy = xj.y + nb_sel_s(ty < 0, fp.nL[1]);
+            jz = xj.z + nb_sel_s(tz < 0, fp.nL[2]);
 #pragma unroll
             for (int k = 0; k < C; ++k) {
                 dx[k] = xs[k] - jx;
@@ -368,81 +441,91 @@ __device__ __forceinline__ nb_esum nb_force_cluster(const nb_fparams &fp, const 
             jx = xj.x + nb_dj(tx, fp.L[0]);
             jy = xj.y + nb_dj(ty, fp.L[1]);
             jz = xj.z + nb_dj(tz, fp.L[2]);
-            if (!valid) jx = jy = jz = 1e18f;
 #pragma unroll
             for (int k = 0; k < C; ++k) {
-                const float4 v = w.id[k];
+                const float4 v = idp[k];
                 dx[k] = (v.x + dix) - jx;
                 dy[k] = (v.y + diy) - jy;
                 dz[k] = (v.z + diz) - jz;
             }
         }
         nb_wave_lds_sync();  // the previous batch's reads of the work area are done
-        w.jqf[lane] = xj.w * fp.fc;
-        if (RAWQ) w.jq[lane] = xj.w;
+        jqfp[lane] = xj.w * fp.fcs;
+        if (RAWQ) nb_lput<float>(w.jq + lane4, xj.w);
         if (EPREC) {
-            w.jx[lane] = make_float4(jx, jy, jz, 0.0f);
-            w.jdi[lane] = make_float4(dix, diy, diz, 0.0f);
+            nb_lput<float4>(w.jx + 4u * lane4, make_float4(jx, jy, jz, 0.0f));
+            nb_lput<float4>(w.jdi + 4u * lane4, make_float4(dix, diy, diz, 0.0f));
         }
 #pragma unroll
-        for (int k = 0; k < C; ++k) w.fsb[k * NB_WAVE + lane] = 0.0f;
-        // the lane's part of the pair codes
-        const int pcj = (tj << NB_PC_ROW) | lane;
+        for (int k = 0; k < C; ++k) fsbp[k * NB_WAVE + lane] = 0.0f;
+        // the lane's part of the pair codes: its type's table row offset and its lane
+        const uint32_t pcj = ((uint32_t)tj << (NB_PC_ROW + 5)) | lane4;
         int nq = 0;  // interacting pairs of the batch (wave-uniform)
-        auto enqueue = [&](int k, float r2, unsigned long long bal) {
-            const int pos = nq + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(bal >> 32),
-                                                                 __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
-            w.q[pos] = make_uint2(__float_as_uint(r2), (unsigned)(pci[k] + pcj));
+        // the record of a pair: the batch's next free record (qb, formed on the scalar unit before
+        // the divergent branch) plus the rank of the lane among those that enqueue
+        auto enqueue = [&](int k, uint32_t qb, float r2, unsigned long long bal) {
+            const uint32_t pos = __builtin_amdgcn_mbcnt_hi((unsigned)(bal >> 32),
+                                                           __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
+            nb_lput<uint2>(qb + 8u * pos, make_uint2(__float_as_uint(r2), pci[k] + pcj));
         };
-        if (__ballot(valid && mcol != FULL) == 0ull) {
+        if ((__builtin_amdgcn_ballot_w64(mcol != FULL) & vmask) == 0ull) {
             // every listed pair of the batch is unmasked (the common case): the range test alone
 #pragma unroll
             for (int k = 0; k < C; ++k) {
                 const float r2 = nb_r2(dx[k], dy[k], dz[k]);
                 const bool in = r2 < fp.rc2;
                 const unsigned long long bal = __builtin_amdgcn_ballot_w64(in);
-                if (in) enqueue(k, r2, bal);
+                uint32_t qb = w.q + 8u * (uint32_t)nq;
+                asm("" : "+s"(qb));
+                if (in) enqueue(k, qb, r2, bal);
                 nq += __popcll(bal);
             }
         } else {
 #pragma unroll
             for (int k = 0; k < C; ++k) {
                 const float r2 = nb_r2(dx[k], dy[k], dz[k]);
-                const bool in = ((mcol >> k) & 1u) && r2 < fp.rc2;
-                const unsigned long long bal = __builtin_amdgcn_ballot_w64(in);
-                if (in) enqueue(k, r2, bal);
+                const bool inr = r2 < fp.rc2, inm = (mcol & (1u << k)) != 0u;
+                // two ballots of single compares, combined on the scalar unit
+                const unsigned long long bal =
+                    __builtin_amdgcn_ballot_w64(inr) & __builtin_amdgcn_ballot_w64(inm);
+                uint32_t qb = w.q + 8u * (uint32_t)nq;
+                asm("" : "+s"(qb));
+                if (inr && inm) enqueue(k, qb, r2, bal);
                 nq += __popcll(bal);
             }
         }
         nb_wave_lds_sync();
-        // ---- evaluate: the queued pairs, one per lane
+        // ---- evaluate: the queued pairs, one per lane; full passes of 64, then the rest
         float eljb = -0.0f, ecb = -0.0f, qqs = -0.0f;  // FP32 partial energy sums of the batch
-        for (int p0 = 0; p0 < nq; p0 += NB_WAVE) {
-            if (p0 + lane < nq) {
-                const uint2 qe = w.q[p0 + lane];
-                const unsigned code = qe.y;
-                const int jl_ = (int)(code & 63u), k = (int)((code >> 6) & 7u);
-                const float4 *ljp = tab + 2 * (code >> NB_PC_ROW);
-                const float4 lj = ljp[0];
-                const float shv = ljp[1].x;
-                const float qi = w.id[k].w;
-                const float qq = qi * w.jqf[jl_];
-                double qqd = 0.0, dxd = 0.0, dyd = 0.0, dzd = 0.0;
-                if (RAWQ) qqd = (double)qi * (double)w.jq[jl_];
-                if (EPREC) {
-                    // exact displacement: x_i + di is exact (the coordinate near the upper face
-                    // moves down by L), and the difference of two FP32 values is exact in FP64
-                    const float4 idk = w.id[k], a = w.jdi[jl_], bj = w.jx[jl_];
-                    dxd = (double)(idk.x + a.x) - (double)bj.x;
-                    dyd = (double)(idk.y + a.y) - (double)bj.y;
-                    dzd = (double)(idk.z + a.z) - (double)bj.z;
-                }
-                const float fs = pair_eval<EPREC, FLAV>(fp, et, __uint_as_float(qe.x), qq, qqd, lj,
-                                                        shv, dxd, dyd, dzd, eljb, ecb, qqs, elj,
-                                                        ec, qqsd, p4v, q5v);
-                w.fsb[code & NB_PC_SLOT] = fs;
+        auto evaluate = [&](uint32_t qa) {
+            const uint2 qe = nb_lget<uint2>(qa);
+            const uint32_t code = qe.y;
+            const uint32_t ta = code >> NB_PC_ROW;  // the pair's LJ row
+            const float4 lj = nb_lget<float4>(ta);
+            const float shv = nb_lget<float>(ta + 16u);
+            const uint32_t ia = ((code >> 4) & mid) | w.id;  // its i-atom's (x, y, z, q)
+            const uint32_t jo = code & mjqf;                // 4 x its j lane
+            const float qi = nb_lget<float>(ia + 12u);
+            const float qq = qi * nb_lget<float>(jo | w.jqf);
+            double qqd = 0.0, dxd = 0.0, dyd = 0.0, dzd = 0.0;
+            if (RAWQ) qqd = (double)qi * (double)nb_lget<float>(w.jq + jo);
+            if (EPREC) {
+                // exact displacement: x_i + di is exact (the coordinate near the upper face moves
+                // down by L), and the difference of two FP32 values is exact in FP64
+                const float4 idk = nb_lget<float4>(ia), a = nb_lget<float4>(w.jdi + 4u * jo),
+                             bj = nb_lget<float4>(w.jx + 4u * jo);
+                dxd = (double)(idk.x + a.x) - (double)bj.x;
+                dyd = (double)(idk.y + a.y) - (double)bj.y;
+                dzd = (double)(idk.z + a.z) - (double)bj.z;
             }
-        }
+            const float fs = pair_eval<EPREC, FLAV>(fp, et, __uint_as_float(qe.x), qq, qqd, lj, shv,
+                                                    dxd, dyd, dzd, eljb, ecb, qqs, elj, ec, qqsd,
+                                                    p4v, q5v);
+            nb_lput<float>((code & mfsb) | w.fsb, fs);
+        };
+        uint32_t qa = w.q + 8u * (uint32_t)lane;
+        for (int p = 0; p < (nq >> 6); ++p, qa += 8u * NB_WAVE) evaluate(qa);
+        if (lane < (nq & (NB_WAVE - 1))) evaluate(qa);
         nb_wave_lds_sync();
         if (!EPREC) {
             elj += (double)eljb;
@@ -455,7 +538,7 @@ __device__ __forceinline__ nb_esum nb_force_cluster(const nb_fparams &fp, const 
         float jfx = 0.0f, jfy = 0.0f, jfz = 0.0f;
 #pragma unroll
         for (int k = 0; k < C; ++k) {
-            const float fs = w.fsb[k * NB_WAVE + lane];
+            const float fs = fsbp[k * NB_WAVE + lane];
             if (VIR) {
                 const float tx = fs * dx[k], ty = fs * dy[k], tz = fs * dz[k];
                 vb[0] = __builtin_fmaf(tx, dx[k], vb[0]);
@@ -477,9 +560,8 @@ __device__ __forceinline__ nb_esum nb_force_cluster(const nb_fparams &fp, const 
             for (int m = 0; m < 6; ++m) vird[m] += (double)vb[m];
         }
         // about 40% of the lanes of a batch have no pair within rc (their entry was kept for
-        // another atom of the group, at rlist); they skip their atomics
-        nb_add_force<FIX>(valid && (jfx != 0.0f || jfy != 0.0f || jfz != 0.0f), jslot, jfx, jfy,
-                          jfz, fj, npad_max, flags, lane);
+        // another atom of the group, at rlist); their sums are zero and they skip the atomics
+        nb_add_fix(valid, jslot, jfx, jfy, jfz, fj, npad_max, flags, lane);
     }
     // the unit's i-force sums: atom k's in the lanes with lane / (64 / C) == k, added by the
     // first lane of each group
@@ -488,13 +570,18 @@ __device__ __forceinline__ nb_esum nb_force_cluster(const nb_fparams &fp, const 
     const float sz = nb_wave_scatter_sum<C>(fiz, lane);
     elj = nb_wave_sum_d(elj);
     ec = nb_wave_sum_d(ec);
-    const double qqd = nb_wave_sum_d(qqsd);
-    nb_add_force<FIX>(lane % (NB_WAVE / C) == 0, ci * C + lane / (NB_WAVE / C), sx, sy, sz, fj,
-                      npad_max, flags, lane);
+    double qqd = nb_wave_sum_d(qqsd);
+    nb_add_fix(lane % (NB_WAVE / C) == 0, ci * C + lane / (NB_WAVE / C), sx, sy, sz, fj, npad_max,
+               flags, lane);
+    // the FP32-energy Coulomb sums and the FP32 shift weight were formed from the scaled charge
+    // products, the virial from the scaled force factors
+    constexpr double unscale = 1.0 / NB_FSCALE;
+    if (!EPREC) ec *= unscale;
+    if (!nb_qq64<EPREC, FLAV>()) qqd *= unscale;
     nb_esum out{elj, ec, qqd, {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}};
     if (VIR) {
 #pragma unroll
-        for (int m = 0; m < 6; ++m) out.v[m] = nb_wave_sum_d(vird[m]);
+        for (int m = 0; m < 6; ++m) out.v[m] = nb_wave_sum_d(vird[m]) * unscale;
     }
     nb_wave_lds_sync();  // the next unit of this wave rewrites the work area
     return out;

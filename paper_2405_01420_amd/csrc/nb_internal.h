@@ -88,8 +88,10 @@ struct nb_geom {
 // Force-kernel constants (FP32 values derived on the host in FP64).
 struct nb_fparams {
     float L[3];
+    float nL[3];        // -L (frame offsets selected on the scalar unit)
     float rc2;
     float fc;           // Coulomb constant
+    float fcs;          // fC NB_FSCALE (the force body forms force factors in fixed-point units)
     float cexp;         // -beta^2 log2(e):  exp(-beta^2 r^2) = exp2(cexp r^2)
     float kb;           // 2 beta / sqrt(pi)
     // LJ table in LDS/global: per type pair (a * ntypes + b) two float4,
@@ -105,6 +107,7 @@ struct nb_fparams {
     // force switch from sw_r1 to rc: force terms A t^2 + B t^3, energy terms -(A/3) t^3 - (B/4) t^4
     // with t = r - sw_r1, for the r^-6 and r^-12 parts
     float sw_r1, sw_a6, sw_b6, sw_a12, sw_b12, sw_ea6, sw_eb6, sw_ea12, sw_eb12;
+    float fsw_a6, fsw_b6, fsw_a12, fsw_b12;  // the force coefficients times NB_FSCALE
     // FP64 pair-energy constants: k_rf; LJ shift constants (value at rc of the r^-6 and r^-12
     // parts: rc^-a, or the force-switch constant); force-switch energy coefficients
     double krf_d, lj_k6, lj_k12, sw_r1_d, sw_ea6_d, sw_eb6_d, sw_ea12_d, sw_eb12_d;
