@@ -426,7 +426,13 @@ int nb_setup(nb_ctx **out, const nb_params *p, void *stream) {
         if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess || ncu <= 0)
             ncu = 256;
         c->slots = ncu * 4;  // SIMDs
-        c->unit_cap = c->ncl_max + 2 * c->slots + 64;
+        // the last units of the force kernel run while the device drains: halving the lists of
+        // the last three clusters per SIMD shortens that tail (FP32 pair energies; the FP64-energy
+        // kernel, with fewer resident waves and an erfc table to load per workgroup, gains
+        // nothing from more units)
+        c->tail_n = nb_energy_fp64(c) ? 0 : 3 * c->slots;
+        if (const char *ts = getenv("NB_TAIL_CLUSTERS")) c->tail_n = std::max(0, atoi(ts));
+        c->unit_cap = c->ncl_max + std::min(c->tail_n, c->ncl_max) + 2 * c->slots + 64;
     }
     c->cap = estimate_cap(p->natoms, p->box, c->C, rlist);
     if (const char *ov = getenv("NB_LIST_CAP")) {
@@ -460,7 +466,7 @@ int nb_setup(nb_ctx **out, const nb_params *p, void *stream) {
     NB_ALLOC(units, c->unit_cap);
     NB_ALLOC(epart, 4 * (size_t)c->unit_cap);
     if (c->flags & NB_EWALD_CORR) NB_ALLOC(cpart, NB_CORR_PART * (size_t)((n + NB_CORR_BLOCK - 1) / NB_CORR_BLOCK));
-    NB_ALLOC(vpart, 6 * (size_t)((c->unit_cap + 3) / 4));
+    NB_ALLOC(vpart, 6 * (size_t)c->unit_cap);
     NB_ALLOC(meta, 1);
     NB_ALLOC(ljtab, 2 * (size_t)c->ntypes * c->ntypes);
 #undef NB_ALLOC

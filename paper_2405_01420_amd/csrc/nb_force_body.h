@@ -76,14 +76,15 @@ struct nb_wg_lds {
     float jqf[NW][NB_WAVE];         // per j lane: fC NB_FSCALE q_j
     float4 id[NW][C];               // per i-atom: (x, y, z, q) as loaded (unshifted)
     uint2 q[NW][C * NB_WAVE];       // the batch's interacting pairs: (r^2 bits, pair code)
-    float jq[NW][RAWQ ? NB_WAVE : 1];     // per j lane: q_j as loaded
-    float4 jx[NW][EPREC ? NB_WAVE : 1];   // FP64-energy mode, per j lane: x_j moved into the pair frame
-    float4 jdi[NW][EPREC ? NB_WAVE : 1];  // FP64-energy mode, per j lane: the i-frame offset of its pair
+    float jq[NW][RAWQ ? NB_WAVE : 1];  // per j lane: q_j as loaded
+    // FP64-energy mode, per j lane: x_j + dj - di in FP64 (exact), x, y and z in rows of 64, so
+    // that x_i - (x_j + dj - di) is the exact displacement of the pair
+    double jx[NW][EPREC ? 3 * NB_WAVE : 1];
 };
 
 // One wavefront's parts of the work area, as LDS byte addresses (wave-uniform).
 struct nb_wv {
-    uint32_t fsb, jqf, id, q, jq, jx, jdi;
+    uint32_t fsb, jqf, id, q, jq, jx;
 };
 
 template <int C, bool EPREC, int FLAV, int NW>
@@ -93,8 +94,7 @@ __device__ __forceinline__ nb_wv nb_wave_view(nb_wg_lds<C, EPREC, FLAV, NW> &g, 
                       offsetof(G, id) % (C * 16) == 0,
                   "or-addressed parts must sit at multiples of their size");
     return nb_wv{nb_laddr(&g.fsb[wv][0]), nb_laddr(&g.jqf[wv][0]), nb_laddr(&g.id[wv][0]),
-                 nb_laddr(&g.q[wv][0]),   nb_laddr(&g.jq[wv][0]),  nb_laddr(&g.jx[wv][0]),
-                 nb_laddr(&g.jdi[wv][0])};
+                 nb_laddr(&g.q[wv][0]),   nb_laddr(&g.jq[wv][0]),  nb_laddr(&g.jx[wv][0])};
 }
 
 // Pair code of a queued pair: (LDS byte address of its LJ table row << NB_PC_ROW) | (64 k + j
@@ -453,8 +453,10 @@ __device__ __forceinline__ nb_esum nb_force_cluster(const nb_fparams &fp, const 
         jqfp[lane] = xj.w * fp.fcs;
         if (RAWQ) nb_lput<float>(w.jq + lane4, xj.w);
         if (EPREC) {
-            nb_lput<float4>(w.jx + 4u * lane4, make_float4(jx, jy, jz, 0.0f));
-            nb_lput<float4>(w.jdi + 4u * lane4, make_float4(dix, diy, diz, 0.0f));
+            // x_j + dj (FP32, exact) minus the i-frame offset: exact in FP64
+            nb_lput<double>(w.jx + 2u * lane4, (double)jx - (double)dix);
+            nb_lput<double>(w.jx + 2u * lane4 + 8u * NB_WAVE, (double)jy - (double)diy);
+            nb_lput<double>(w.jx + 2u * lane4 + 16u * NB_WAVE, (double)jz - (double)diz);
         }
 #pragma unroll
         for (int k = 0; k < C; ++k) fsbp[k * NB_WAVE + lane] = 0.0f;
@@ -510,13 +512,13 @@ __device__ __forceinline__ nb_esum nb_force_cluster(const nb_fparams &fp, const 
             double qqd = 0.0, dxd = 0.0, dyd = 0.0, dzd = 0.0;
             if (RAWQ) qqd = (double)qi * (double)nb_lget<float>(w.jq + jo);
             if (EPREC) {
-                // exact displacement: x_i + di is exact (the coordinate near the upper face moves
-                // down by L), and the difference of two FP32 values is exact in FP64
-                const float4 idk = nb_lget<float4>(ia), a = nb_lget<float4>(w.jdi + 4u * jo),
-                             bj = nb_lget<float4>(w.jx + 4u * jo);
-                dxd = (double)(idk.x + a.x) - (double)bj.x;
-                dyd = (double)(idk.y + a.y) - (double)bj.y;
-                dzd = (double)(idk.z + a.z) - (double)bj.z;
+                // exact displacement: x_i - (x_j + dj - di), both terms exact in FP64 and their
+                // difference too (a few tens of significant bits at most)
+                const float4 idk = nb_lget<float4>(ia);
+                const uint32_t ja = w.jx + 2u * jo;
+                dxd = (double)idk.x - nb_lget<double>(ja);
+                dyd = (double)idk.y - nb_lget<double>(ja + 8u * NB_WAVE);
+                dzd = (double)idk.z - nb_lget<double>(ja + 16u * NB_WAVE);
             }
             const float fs = pair_eval<EPREC, FLAV>(fp, et, __uint_as_float(qe.x), qq, qqd, lj, shv,
                                                     dxd, dyd, dzd, eljb, ecb, qqs, elj, ec, qqsd,
