@@ -427,10 +427,9 @@ int nb_setup(nb_ctx **out, const nb_params *p, void *stream) {
             ncu = 256;
         c->slots = ncu * 4;  // SIMDs
         // the last units of the force kernel run while the device drains: halving the lists of
-        // the last three clusters per SIMD shortens that tail (FP32 pair energies; the FP64-energy
-        // kernel, with fewer resident waves and an erfc table to load per workgroup, gains
-        // nothing from more units)
-        c->tail_n = nb_energy_fp64(c) ? 0 : 3 * c->slots;
+        // the last three clusters per SIMD (two with FP64 pair energies, whose workgroups load an
+        // erfc table each) shortens that tail
+        c->tail_n = (nb_energy_fp64(c) ? 2 : 3) * c->slots;
         if (const char *ts = getenv("NB_TAIL_CLUSTERS")) c->tail_n = std::max(0, atoi(ts));
         c->unit_cap = c->ncl_max + std::min(c->tail_n, c->ncl_max) + 2 * c->slots + 64;
     }
