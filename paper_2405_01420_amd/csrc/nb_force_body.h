@@ -366,10 +366,17 @@ __device__ __forceinline__ nb_esum nb_force_cluster(const nb_fparams &fp, const 
     // the code masks in vector registers, for single and-or address operations
     const uint32_t mfsb = nb_vreg(NB_PC_FSB), mjqf = nb_vreg(NB_PC_JQF), mid = nb_vreg(NB_PC_ID);
     nb_wave_lds_sync();
-    int cur_shift = -1;  // shift the cached i-frame coordinates xs/ys/zs belong to (none yet)
+    // the cached i-frame coordinates xs/ys/zs and the shift they belong to: first the frame of
+    // the zero shift (most lists start there), i.e. the coordinates as loaded, by scalar loads
+    int cur_shift = NB_SHIFT_ZERO;
     float xs[C], ys[C], zs[C];
 #pragma unroll
-    for (int k = 0; k < C; ++k) xs[k] = ys[k] = zs[k] = 0.0f;
+    for (int k = 0; k < C; ++k) {
+        const float4 v = nb_ld(xq + ci * C + k);
+        xs[k] = v.x;
+        ys[k] = v.y;
+        zs[k] = v.z;
+    }
     float fix[C], fiy[C], fiz[C];
 #pragma unroll
     for (int k = 0; k < C; ++k) fix[k] = fiy[k] = fiz[k] = 0.0f;
