@@ -583,15 +583,15 @@ __device__ __forceinline__ int nb_block_scan(int v, int *wa, int *total) {
 // P = max(4, ceil(total batches / (2 * SIMDs))).  The SIMDs share their time among resident
 // waves, so a kernel lasts about max(total batches / SIMDs, longest list) batch times; lists are
 // split only when the longest list would set that (small boxes), never at 96k atoms.  The lists
-// of the last `tail` clusters are also split in halves (units of ceil(nb / 2) batches):
-// those units run while the device drains, and shorter ones let the SIMDs finish together (at
-// 96k atoms, 82 -> 78 us).  The unit index is also its energy slot.  Order: with sorted = 0 units stay in cluster order, so that
-// neighbouring waves work on neighbouring clusters, whose j-atoms they share in the caches
-// (ordering them longest first was measured slower at 96k atoms); with sorted != 0 they are
-// emitted longest first by cost class (floor(log2 batches), stable in cluster order within a
-// class), the post-prune list sorting of the paper (section III-A) that starts the long lists
-// before the short ones to shorten the tail.  The histogram of list lengths over the same
-// classes goes to meta->hist.
+// of the last `tail` clusters are also split in halves (units of ceil(nb / 2) batches): those
+// units run while the device drains, and shorter ones let the SIMDs finish together (96k atoms:
+// 82 -> 78 us).  The unit index is also its energy slot.  Order: with sorted = 0 units stay in
+// cluster order, so that neighbouring waves work on neighbouring clusters, whose j-atoms they
+// share in the caches (ordering them longest first was measured slower at 96k atoms); with
+// sorted != 0 they are emitted longest first by cost class (floor(log2 batches), stable in
+// cluster order within a class), the post-prune list sorting of the paper (section III-A) that
+// starts the long lists before the short ones to shorten the tail.  The histogram of list
+// lengths over the same classes goes to meta->hist.
 __global__ void __launch_bounds__(1024) k_units(int slots, int unit_cap, int sorted, int tail,
                                                 const int *__restrict__ icount,
                                                 int4 *__restrict__ units, nb_meta *meta) {

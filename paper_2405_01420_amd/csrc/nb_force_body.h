@@ -28,9 +28,9 @@
 //  * erfc(beta r) = exp(-beta^2 r^2) P(r) / Q(r) with a (4,5) rational fit of the scaled
 //    complementary error function (fit_erfcx.py), Newton-refined reciprocal square root and
 //    reciprocal;
-//  * per-pair energies are summed in FP32 over the pairs a lane evaluates in one batch and
-//    accumulated in FP64 from there on; the Coulomb potential shift is applied in FP64 at the
-//    end from the sum of q_i q_j over interacting pairs;
+//  * per-pair energies (FP32) are added to per-lane FP64 sums one pair at a time (no FP32
+//    partial sums, whose rounding would depend on how pairs are grouped); the Coulomb potential
+//    shift is applied in FP64 at the end from the sum of q_i q_j over interacting pairs;
 //  * with EPREC the pair energies are instead evaluated in FP64 (exact displacement,
 //    Newton-refined 1/r, erfc from an FP64 quintic Hermite table), forces staying FP32: the FP32
 //    rounding of the displacement and of erfc(beta r)/r is otherwise not averaged below 1e-6 of
@@ -142,15 +142,14 @@ __device__ __forceinline__ double nb_erfc_tab(const nb_etab &et, float r, double
 
 // Scalar force factor fs (F_ij = fs d) and the energies of one interacting pair at squared
 // distance r2 with qq = fC q_i q_j and the LJ row lj (C6, C12, 6 C6, 12 C12) and shift shv.  The
-// FP32 pair energies are added to eljb / ecb (FP32 partial sums of the batch) and the shift
-// weight to qqs (FP32, fC included) or qqsd (FP64, exact products qqd = q_i q_j); with EPREC the
+// FP32 pair energies and the FP32 shift weight (fC included) are added to the FP64 sums elj / ec /
+// qqsd one pair at a time, or the shift weight as exact FP64 products qqd = q_i q_j; with EPREC the
 // FP64 energies of the pair, computed from the exact displacement (dxd, dyd, dzd), go to
 // elj / ec / qqsd.
 template <bool EPREC, int FLAV>
 __device__ __forceinline__ float pair_eval(const nb_fparams &fp, const nb_etab &et, float r2,
                                            float qq, double qqd, const float4 &lj, float shv,
-                                           double dxd, double dyd, double dzd, float &eljb,
-                                           float &ecb, float &qqs, double &elj, double &ec,
+                                           double dxd, double dyd, double dzd, double &elj, double &ec,
                                            double &qqsd, float p4v, float q5v) {
     constexpr bool RF = FLAV / 2 == NB_ELEC_RF;
     constexpr bool TAB = FLAV / 2 == NB_ELEC_EWALD_TAB;
@@ -213,7 +212,7 @@ __device__ __forceinline__ float pair_eval(const nb_fparams &fp, const nb_etab &
             // pair energy in FP64 without fC
             ec = __builtin_fma(qqd, __builtin_fma(fp.krf_d, r2d, rid), ec);
         } else {
-            ecb = __builtin_fmaf(qq, __builtin_fmaf(fp.krf, r2, rinv), ecb);
+            ec += (double)(qq * __builtin_fmaf(fp.krf, r2, rinv));
         }
     } else if (TAB) {
         // tabulated Ewald: force factor fC q q (1/r^3 - G(r)), G from its FP32 Hermite segment
@@ -249,11 +248,11 @@ __device__ __forceinline__ float pair_eval(const nb_fparams &fp, const nb_etab &
             ec = __builtin_fma(qqd * nb_erfc_tab(et, r, r2d * rid), rid, ec);
             qqsd += qqd;
         } else {
-            ecb = __builtin_fmaf(t1, R, ecb);     // += fC q_i q_j erfc(b r) / r
-            qqs += qq;
+            ec += (double)(t1 * R);  // fC q_i q_j erfc(b r) / r
+            qqsd += (double)qq;
         }
     }
-    if (!EPREC) eljb += elj_p;
+    if (!EPREC) elj += (double)elj_p;
     return fs;
 }
 
@@ -381,7 +380,7 @@ __device__ __forceinline__ nb_esum nb_force_cluster(const nb_fparams &fp, const 
 #pragma unroll
     for (int k = 0; k < C; ++k) fix[k] = fiy[k] = fiz[k] = 0.0f;
     // energy sums; qqsd: the shift weight, sum of q_i q_j over interacting pairs (exact FP64
-    // products with FP64 energies or the reaction field, FP32 batch sums of fC q_i q_j otherwise)
+    // products with FP64 energies or the reaction field, FP32 products fC q_i q_j otherwise)
     double elj = 0.0, ec = 0.0, qqsd = 0.0;
     double vird[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 
@@ -505,7 +504,6 @@ __device__ __forceinline__ nb_esum nb_force_cluster(const nb_fparams &fp, const 
         }
         nb_wave_lds_sync();
         // ---- evaluate: the queued pairs, one per lane; full passes of 64, then the rest
-        float eljb = -0.0f, ecb = -0.0f, qqs = -0.0f;  // FP32 partial energy sums of the batch
         auto evaluate = [&](uint32_t qa) {
             const uint2 qe = nb_lget<uint2>(qa);
             const uint32_t code = qe.y;
@@ -528,7 +526,7 @@ __device__ __forceinline__ nb_esum nb_force_cluster(const nb_fparams &fp, const 
                 dzd = (double)idk.z - nb_lget<double>(ja + 16u * NB_WAVE);
             }
             const float fs = pair_eval<EPREC, FLAV>(fp, et, __uint_as_float(qe.x), qq, qqd, lj, shv,
-                                                    dxd, dyd, dzd, eljb, ecb, qqs, elj, ec, qqsd,
+                                                    dxd, dyd, dzd, elj, ec, qqsd,
                                                     p4v, q5v);
             nb_lput<float>((code & mfsb) | w.fsb, fs);
         };
@@ -536,11 +534,6 @@ __device__ __forceinline__ nb_esum nb_force_cluster(const nb_fparams &fp, const 
         for (int p = 0; p < (nq >> 6); ++p, qa += 8u * NB_WAVE) evaluate(qa);
         if (lane < (nq & (NB_WAVE - 1))) evaluate(qa);
         nb_wave_lds_sync();
-        if (!EPREC) {
-            elj += (double)eljb;
-            ec += (double)ecb;
-        }
-        if (!nb_qq64<EPREC, FLAV>()) qqsd += (double)qqs;
         // ---- accumulate: f d of the lane's C pairs into the i- and j-force sums (the factor is
         // zero for pairs that do not interact)
         float vb[6] = {-0.0f, -0.0f, -0.0f, -0.0f, -0.0f, -0.0f};
