@@ -465,7 +465,7 @@ int nb_setup(nb_ctx **out, const nb_params *p, void *stream) {
     NB_ALLOC(units, c->unit_cap);
     NB_ALLOC(epart, 4 * (size_t)c->unit_cap);
     if (c->flags & NB_EWALD_CORR) NB_ALLOC(cpart, NB_CORR_PART * (size_t)((n + NB_CORR_BLOCK - 1) / NB_CORR_BLOCK));
-    NB_ALLOC(vpart, 6 * (size_t)c->unit_cap);
+    NB_ALLOC(vpart, 6 * (size_t)((c->unit_cap + 3) / 4));
     NB_ALLOC(meta, 1);
     NB_ALLOC(ljtab, 2 * (size_t)c->ntypes * c->ntypes);
 #undef NB_ALLOC

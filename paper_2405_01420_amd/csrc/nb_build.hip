@@ -649,9 +649,13 @@ __global__ void __launch_bounds__(1024) k_units(int slots, int unit_cap, int sor
     }
     __syncthreads();
     const int P = __builtin_amdgcn_readfirstlane(s_p);
-    // the lists of the last `tail` clusters are split into halves (units of ceil(nb / 2) batches)
+    // the lists of the last `tail` clusters are split into halves (units of ceil(nb / 2) batches;
+    // longer than P, they are split by P anyway): batches per unit and units of cluster c,
+    // without a division by a per-cluster value
     const int c_split = ncl - tail;
-    auto pmax = [&](int c, int nb) { return c >= c_split ? min(P, max(1, (nb + 1) / 2)) : P; };
+    auto halve = [&](int c, int nb) { return c >= c_split && nb <= P; };
+    auto pmax = [&](int c, int nb) { return halve(c, nb) ? (nb + 1) >> 1 : P; };
+    auto nunits_of = [&](int c, int nb) { return halve(c, nb) ? min(nb, 2) : (nb + P - 1) / P; };
     // histogram of the list lengths (non-empty lists) by cost class
     {
         int h[NB_HIST_BINS];
@@ -677,11 +681,8 @@ __global__ void __launch_bounds__(1024) k_units(int slots, int unit_cap, int sor
     // units of this thread's clusters and their exclusive prefix over the threads
     int nu = 0;
 #pragma unroll
-    for (int j = 0; j < NB_UNITS_REG; ++j) nu += (nbr[j] + pmax(c_lo + j, nbr[j]) - 1) / pmax(c_lo + j, nbr[j]);
-    for (int c = c_rest; c < c_hi; ++c) {
-        const int nb = batches(c);
-        nu += (nb + pmax(c, nb) - 1) / pmax(c, nb);
-    }
+    for (int j = 0; j < NB_UNITS_REG; ++j) nu += nunits_of(c_lo + j, nbr[j]);
+    for (int c = c_rest; c < c_hi; ++c) nu += nunits_of(c, batches(c));
     int run = 0;
     const int u0 = nb_block_scan(nu, wa, &run);
     if (tid == 0) {

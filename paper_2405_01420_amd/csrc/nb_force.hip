@@ -61,10 +61,12 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // One work unit per wave, NB_FORCE_WAVES consecutive units per workgroup (neighbouring waves work
-// on neighbouring clusters, whose j-atoms they share in the caches).  The energy sums of unit u go
-// to epart[4 u ..] (virial: vpart[6 u ..]), which the finalize adds in unit order.  (Workgroups
-// that take several units in turn, statically or from a shared counter, were measured slower: the
-// former coarsen the tail of the launch, the latter serialise on the counter's atomics.)
+// on neighbouring clusters, whose j-atoms they share in the caches).  The energy sums of the
+// workgroup's waves are combined in LDS by whichever wave finishes last, in wave order, and
+// stored as the workgroup's partial (epart[4 blockIdx ..], virial vpart[6 blockIdx ..]); waves do
+// not wait for each other.  (Workgroups that take several units in turn, statically or from a
+// shared counter, were measured slower: the former coarsen the tail of the launch, the latter
+// serialise on the counter's atomics.)
 #define NB_FORCE_WAVES 4
 
 template <int C, bool EPREC, int FLAV, bool VIR>
@@ -81,9 +83,12 @@ __global__ void __launch_bounds__(NB_FORCE_WAVES * NB_WAVE) NB_FORCE_OCCUPANCY_V
                                                nb_meta *meta) {
     extern __shared__ float4 tab[];
     __shared__ __attribute__((aligned(C * NB_WAVE * 4))) nb_wg_lds<C, EPREC, FLAV, NB_FORCE_WAVES> wl;
+    __shared__ double esh[NB_FORCE_WAVES][VIR ? 9 : 3];
+    __shared__ int edone;
     const int nunits = meta->nunits;
     if (blockIdx.x * NB_FORCE_WAVES >= nunits) return;  // an idle workgroup
     const int ntt = fp.ntypes * fp.ntypes;
+    if (threadIdx.x == 0) edone = 0;
     nb_load_ljtab(tab, ljtab, ntt);
     nb_etab et;
     et.seg = reinterpret_cast<const double2 *>(tab + 2 * ntt);
@@ -100,21 +105,45 @@ __global__ void __launch_bounds__(NB_FORCE_WAVES * NB_WAVE) NB_FORCE_OCCUPANCY_V
         for (int k = threadIdx.x; k < NB_TAB_SEGMENTS; k += blockDim.x) fdst[k] = ftab[k];
     __syncthreads();
     const int lane = threadIdx.x & (NB_WAVE - 1);
-    const nb_wv w = nb_wave_view(wl, __builtin_amdgcn_readfirstlane(threadIdx.x / NB_WAVE));
-    const int u = __builtin_amdgcn_readfirstlane(blockIdx.x * NB_FORCE_WAVES + threadIdx.x / NB_WAVE);
-    if (u >= nunits) return;
-    const int4 wu = units[u];
-    const nb_esum es = nb_force_cluster<C, EPREC, FLAV, VIR>(
-        fp, tab, et, w, __builtin_amdgcn_readfirstlane(wu.x), __builtin_amdgcn_readfirstlane(wu.y),
-        __builtin_amdgcn_readfirstlane(wu.z), cap, npad_max, nb_g(xq), nb_g(tsort), nb_g(icount),
-        nb_g(jl), nb_g(fj), nb_g(&meta->flags));
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / NB_WAVE);
+    const int u = __builtin_amdgcn_readfirstlane(blockIdx.x * NB_FORCE_WAVES + wv);
+    nb_esum es{0.0, 0.0, 0.0, {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}};
+    if (u < nunits) {
+        const int4 wu = units[u];
+        es = nb_force_cluster<C, EPREC, FLAV, VIR>(
+            fp, tab, et, nb_wave_view(wl, wv), __builtin_amdgcn_readfirstlane(wu.x),
+            __builtin_amdgcn_readfirstlane(wu.y), __builtin_amdgcn_readfirstlane(wu.z), cap, npad_max,
+            nb_g(xq), nb_g(tsort), nb_g(icount), nb_g(jl), nb_g(fj), nb_g(&meta->flags));
+    }
     if (lane == 0) {
-        epart[4 * u] = es.elj;
-        epart[4 * u + 1] = es.ec;
-        epart[4 * u + 2] = es.qq;
+        esh[wv][0] = es.elj;
+        esh[wv][1] = es.ec;
+        esh[wv][2] = es.qq;
         if (VIR) {
 #pragma unroll
-            for (int m = 0; m < 6; ++m) vpart[6 * u + m] = es.v[m];
+            for (int m = 0; m < 6; ++m) esh[wv][3 + m] = es.v[m];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        const bool last = __hip_atomic_fetch_add(&edone, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) ==
+                          NB_FORCE_WAVES - 1;
+        if (last) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            double a = 0.0, b = 0.0, c = 0.0;
+            for (int k = 0; k < NB_FORCE_WAVES; ++k) {
+                a += esh[k][0];
+                b += esh[k][1];
+                c += esh[k][2];
+            }
+            epart[4 * blockIdx.x] = a;
+            epart[4 * blockIdx.x + 1] = b;
+            epart[4 * blockIdx.x + 2] = c;
+            if (VIR) {
+                for (int m = 0; m < 6; ++m) {
+                    double v = 0.0;
+                    for (int k = 0; k < NB_FORCE_WAVES; ++k) v += esh[k][3 + m];
+                    vpart[6 * blockIdx.x + m] = v;
+                }
+            }
         }
     }
 }
@@ -259,7 +288,7 @@ __global__ void __launch_bounds__(NB_FIN_BLOCK) k_finalize(int n, int npad_max,
     }
     if (blockIdx.x != 0) return;
     // energies: the force workgroups' partials; then the Ewald-correction and virial partials
-    const int np = meta->nunits;
+    const int np = (meta->nunits + NB_FORCE_WAVES - 1) / NB_FORCE_WAVES;
     double en[3];
     fin_block_sum<3>(epart, np, 4, en, s);
     double cp[NB_CORR_PART] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};

@@ -175,9 +175,9 @@ struct nb_ctx {
     float stale2_prune = 0.0f;  // ((r_inner - rc) / 2)^2
     int4 *units = nullptr;      // [unit_cap] (i-cluster, first batch, batches, energy slot),
                                 // longest first
-    double *epart = nullptr;    // [unit_cap * 4] energy partials (one per force work unit)
+    double *epart = nullptr;    // [unit_cap * 4] energy partials (one per force workgroup used)
     double *cpart = nullptr;    // [NB_CORR_PART * blocks] Ewald-correction partials (NB_EWALD_CORR)
-    double *vpart = nullptr;    // [6 * unit_cap] virial pair sums per work unit (nb_forces_virial)
+    double *vpart = nullptr;    // [6 * force workgroups] virial pair sums (nb_forces_virial)
     nb_meta *meta = nullptr;
     float4 *ljtab = nullptr;    // [2 * nt * nt]: (C6, C12, 6 C6, 12 C12), (shift, 1/sigma_ab, 0, 0)
     double2 *etab = nullptr;    // [NB_ETAB_W * etab_n]: Hermite segments of erfc(beta r) (FP64 energy mode)
