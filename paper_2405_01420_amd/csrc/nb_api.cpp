@@ -289,7 +289,8 @@ void free_all(nb_ctx *c) {
                     c->tsort, c->units,  c->fj,     c->bblo,  c->bbhi,      c->icount,
                     c->jl,    c->epart,  c->meta,   c->ljtab, c->excl_off,  c->excl_idx,
                     c->dbg_pairs, c->adj, c->adjj, c->gs, c->tpart, c->etab,
-                    c->cpart, c->vpart, c->jl_p, c->icount_p, c->xprune, c->mdpart, c->ftab};
+                    c->cpart, c->vpart, c->jl_p, c->icount_p, c->xprune, c->mdpart, c->ftab,
+                    c->colz};
     for (void *p : bufs)
         if (p) hipFree(p);
 }
@@ -415,6 +416,13 @@ int nb_setup(nb_ctx **out, const nb_params *p, void *stream) {
     g.invw[1] = (float)(ncy / p->box[1]);
     const double rlist = p->cutoff + p->buffer;
     g.rl = (float)rlist;
+    {
+        // z bins of half a column width: a cluster window of the search is at most a bin or two
+        // wider on each side than the clusters it has to hold
+        const double dz = 0.5 * w;
+        g.nz = std::max(1, (int)ceil(p->box[2] / dz));
+        g.zinv = (float)(g.nz / p->box[2]);
+    }
     g.rl2 = (float)(rlist * rlist);
     set_constants(c);
 
@@ -452,6 +460,7 @@ int nb_setup(nb_ctx **out, const nb_params *p, void *stream) {
     NB_ALLOC(colcount, g.ncol);
     NB_ALLOC(colstart, g.ncol + 1);
     NB_ALLOC(colcl, g.ncol + 1);
+    NB_ALLOC(colz, (size_t)g.ncol * (g.nz + 1));
     NB_ALLOC(perm, c->npad_max);
     NB_ALLOC(xs, c->npad_max);
     // one j-group more than the slots: the far group that lanes past the end of a j-list read

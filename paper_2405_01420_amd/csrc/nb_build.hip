@@ -156,9 +156,13 @@ __global__ void k_scatter(int n, int npad_max, const int *__restrict__ col,
 // One block per column: sort the column's atoms by (z, index) in LDS (by rank for columns of
 // at most one atom per thread, bitonic otherwise), then lay them out as clusters of C slots;
 // the tail of the last cluster is padding (perm = -1).  The block then writes the bounding
-// boxes of its clusters over their real atoms (from the slots it has just written).
+// boxes of its clusters over their real atoms (from the slots it has just written), and the
+// column's z table: for every bin edge z_k = k / zinv, k = 0 .. nz, the number of its clusters
+// whose upper z bound is below z_k and the number whose lower z bound is at most z_k (both
+// bounds grow with the index, so these are the first cluster that can reach above z_k and the
+// first that lies wholly above it); the end edges count as -inf and +inf.
 template <int C>
-__global__ void __launch_bounds__(256) k_colsort(const float *__restrict__ x,
+__global__ void __launch_bounds__(256) k_colsort(nb_geom g, const float *__restrict__ x,
                                                  const float4 *__restrict__ off,
                                                  const int *__restrict__ colcount,
                                                  const int *__restrict__ colstart,
@@ -166,8 +170,9 @@ __global__ void __launch_bounds__(256) k_colsort(const float *__restrict__ x,
                                                  const int *__restrict__ tmp, int *__restrict__ perm,
                                                  int *__restrict__ slot_of, float4 *__restrict__ xs,
                                                  float4 *__restrict__ bblo, float4 *__restrict__ bbhi,
-                                                 nb_meta *meta) {
+                                                 int2 *__restrict__ colz, nb_meta *meta) {
     __shared__ unsigned long long key[NB_SORT_MAX];
+    __shared__ float zlo[NB_SORT_MAX / C], zhi[NB_SORT_MAX / C];  // the clusters' z bounds
     const int c = blockIdx.x, tid = threadIdx.x;
     const int n = colcount[c], start = colstart[c];
     const int cl0 = colcl[c], nslot = (colcl[c + 1] - cl0) * C;
@@ -264,6 +269,24 @@ __global__ void __launch_bounds__(256) k_colsort(const float *__restrict__ x,
         }
         bblo[cl] = make_float4(a.x, a.y, a.z, 0.0f);
         bbhi[cl] = make_float4(b.x, b.y, b.z, 0.0f);
+        if (k < NB_SORT_MAX / C) {
+            zlo[k] = a.z;
+            zhi[k] = b.z;
+        }
+    }
+    __syncthreads();
+    const int ncl = min(nslot / C, NB_SORT_MAX / C);
+    for (int k = tid; k <= g.nz; k += blockDim.x) {
+        const float zk = (float)k / g.zinv;
+        int below = 0, upto = 0;
+        for (int i = 0; i < ncl; ++i) {
+            below += zhi[i] < zk ? 1 : 0;
+            upto += zlo[i] <= zk ? 1 : 0;
+        }
+        // the end edges stand for -inf and +inf: no coordinate, however rounded, lies outside
+        if (k == 0) below = 0;
+        if (k == g.nz) upto = ncl;
+        colz[(size_t)c * (g.nz + 1) + k] = make_int2(below, upto);
     }
 }
 
@@ -309,6 +332,7 @@ __device__ __forceinline__ unsigned long long nb_triangle() {
 // i-cluster are contiguous at jl[ci * cap] and grouped by shift.
 template <int C>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NB_SEARCH_WAVES))) k_search(nb_geom g, int cap, const int *__restrict__ colcl,
+                                                const int2 *__restrict__ colz,
                                                 const float4 *__restrict__ bblo,
                                                 const float4 *__restrict__ bbhi,
                                                 const int *__restrict__ perm,
@@ -448,33 +472,19 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NB_SEA
             if (c < ncols) {
                 const int col = (cy0 + c / ncx_r) * g.ncx + cx0 + c % ncx_r;
                 cstart = colcl[col];
-                cnt = colcl[col + 1] - cstart;
                 // clusters are z-ordered within a column, so both bounding-box z ends increase
-                // with the index: keep only the run whose z extent meets [z0, z1], widened by
-                // 2^-10 nm so that it contains every cluster the bounding-box test below passes
+                // with the index: keep only a run that holds every cluster whose z extent meets
+                // [z0, z1] widened by 2^-10 nm (all the bounding-box test below can pass), from
+                // the column's z table at the bin edges below and above that range (one bin
+                // further out on each side, so that the rounding of the bin index cannot narrow
+                // the run); the extra clusters fail the bounding-box test
                 const float zw0 = z0 - 0x1p-10f, zw1 = z1 + 0x1p-10f;
-                int a = 0, n = cnt;  // first cluster with hi.z >= z0
-                while (n > 0) {
-                    const int h = n >> 1;
-                    if (bbhi[cstart + a + h].z < zw0) {
-                        a += h + 1;
-                        n -= h + 1;
-                    } else {
-                        n = h;
-                    }
-                }
-                int e = a, m = cnt - a;  // first cluster with lo.z > z1
-                while (m > 0) {
-                    const int h = m >> 1;
-                    if (bblo[cstart + e + h].z <= zw1) {
-                        e += h + 1;
-                        m -= h + 1;
-                    } else {
-                        m = h;
-                    }
-                }
+                const int k0 = min(max((int)floorf(zw0 * g.zinv) - 1, 0), g.nz);
+                const int k1 = min(max((int)ceilf(zw1 * g.zinv) + 1, 0), g.nz);
+                const int a = colz[(size_t)col * (g.nz + 1) + k0].x;  // no cluster before a reaches z0
+                const int e = colz[(size_t)col * (g.nz + 1) + k1].y;  // none from e on starts below z1
                 cstart += a;
-                cnt = e - a;
+                cnt = max(e - a, 0);
             }
             int incl = cnt;  // inclusive prefix sum of the counts over the lanes
 #pragma unroll
@@ -860,11 +870,11 @@ hipError_t build_impl(nb_ctx *c, const float *x) {
     // every slot the per-call pack visits is either written by the column sort or padding
     hipLaunchKernelGGL(k_scatter, dim3((n + tb - 1) / tb), dim3(tb), 0, c->stream, n, c->npad_max,
                        c->col, c->rank, c->colstart, c->tmp, c->perm);
-    hipLaunchKernelGGL((k_colsort<C>), dim3(c->geom.ncol), dim3(256), 0, c->stream, x, c->off,
+    hipLaunchKernelGGL((k_colsort<C>), dim3(c->geom.ncol), dim3(256), 0, c->stream, c->geom, x, c->off,
                        c->colcount, c->colstart, c->colcl, c->tmp, c->perm, c->slot_of, c->xs,
-                       c->bblo, c->bbhi, c->meta);
+                       c->bblo, c->bbhi, c->colz, c->meta);
     hipLaunchKernelGGL((k_search<C>), dim3((c->ncl_max + 3) / 4), dim3(256), 0, c->stream,
-                       c->geom, c->cap, c->colcl, c->bblo, c->bbhi, c->perm, c->xs,
+                       c->geom, c->cap, c->colcl, c->colz, c->bblo, c->bbhi, c->perm, c->xs,
                        c->nnz_excl > 0 ? c->excl_off : nullptr, c->excl_idx, c->slot_of, c->icount, c->jl,
                        c->meta);
     hipLaunchKernelGGL(k_units, dim3(1), dim3(1024), 0, c->stream, c->slots, c->unit_cap,

@@ -83,6 +83,10 @@ struct nb_geom {
     int ncx, ncy, ncol;
     float rl2;          // rlist^2 (search and prune)
     float rl;
+    // z bins of the per-column cluster tables (k_colsort): bin k starts at k / zinv, nz bins
+    // cover [0, L_z]
+    float zinv;
+    int nz;
 };
 
 // Force-kernel constants (FP32 values derived on the host in FP64).
@@ -155,6 +159,7 @@ struct nb_ctx {
     float *xbuild = nullptr;    // [natoms*3] positions at the last build
     int *col = nullptr, *rank = nullptr, *tmp = nullptr, *slot_of = nullptr;  // [natoms]
     int *colcount = nullptr, *colstart = nullptr, *colcl = nullptr;           // [ncol(+1)]
+    int2 *colz = nullptr;   // [ncol * (nz + 1)]: per column and z bin edge, the cluster bounds (k_colsort)
     int *perm = nullptr;        // [npad_max] slot -> atom (-1 = padding)
     float4 *xs = nullptr;       // [npad_max] build positions (wrapped), sorted
     float4 *xq = nullptr;       // [npad_max] per-call positions + charge, sorted
