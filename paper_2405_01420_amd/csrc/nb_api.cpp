@@ -360,6 +360,8 @@ int nb_validate_params(const nb_params *p) {
     double mn = std::min(p->box[0], std::min(p->box[1], p->box[2]));
     if (!(p->cutoff < 0.5 * mn)) return fail(nullptr, NB_ERR_CUTOFF, "cutoff must be below half the smallest box edge");
     if (!(p->cutoff + p->buffer < mn)) return fail(nullptr, NB_ERR_CUTOFF, "cutoff + buffer must be below the smallest box edge");
+    if (!(p->cutoff + p->buffer < NB_PAD_SPACING))
+        return fail(nullptr, NB_ERR_CUTOFF, "cutoff + buffer must be below 16 nm (the spacing of padding slots)");
     return NB_OK;
 }
 
@@ -480,8 +482,8 @@ int nb_setup(nb_ctx **out, const nb_params *p, void *stream) {
 #undef NB_ALLOC
     {
         // the far j-group (slots npad_max ..): far outside any box, type 0; no kernel writes it
-        const float4 far[NB_JG] = {make_float4(-1e5f, -1e5f, -1e5f, 0.0f), make_float4(-1e5f, -1e5f, -1e5f, 0.0f),
-                                   make_float4(-1e5f, -1e5f, -1e5f, 0.0f), make_float4(-1e5f, -1e5f, -1e5f, 0.0f)};
+        const float4 far[NB_JG] = {nb_pad_coord(c->npad_max), nb_pad_coord(c->npad_max + 1),
+                                   nb_pad_coord(c->npad_max + 2), nb_pad_coord(c->npad_max + 3)};
         const int zero[NB_JG] = {0, 0, 0, 0};
         if (hipMemcpy(c->xq + c->npad_max, far, sizeof(far), hipMemcpyHostToDevice) != hipSuccess ||
             hipMemcpy(c->tsort + c->npad_max, zero, sizeof(zero), hipMemcpyHostToDevice) != hipSuccess) {

@@ -86,7 +86,7 @@ __global__ void k_batch_pack(const nb_box_desc *__restrict__ desc, const float *
         d.xq[p] = make_float4(x[3 * g] + o.x, x[3 * g + 1] + o.y, x[3 * g + 2] + o.z, q[g]);
         d.tsort[p] = t;
     } else {
-        d.xq[p] = make_float4(-1e5f, -1e5f, -1e5f, 0.0f);
+        d.xq[p] = nb_pad_coord(p);
         d.tsort[p] = 0;
     }
     d.fj[p] = 0.0f;

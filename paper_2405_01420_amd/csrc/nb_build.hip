@@ -180,7 +180,7 @@ __global__ void __launch_bounds__(256) k_colsort(nb_geom g, const float *__restr
         if (tid == 0) atomicOr(&meta->flags, NB_F_COLUMN);
         for (int r = tid; r < nslot; r += blockDim.x) {
             perm[cl0 * C + r] = -1;
-            xs[cl0 * C + r] = make_float4(-1e5f, -1e5f, -1e5f, 0.0f);
+            xs[cl0 * C + r] = nb_pad_coord(cl0 * C + r);
         }
     } else if (n <= (int)blockDim.x) {
         // one atom per thread: its place in the sorted column is the number of smaller keys
@@ -206,7 +206,7 @@ __global__ void __launch_bounds__(256) k_colsort(nb_geom g, const float *__restr
         }
         for (int r = n + tid; r < nslot; r += blockDim.x) {
             perm[cl0 * C + r] = -1;
-            xs[cl0 * C + r] = make_float4(-1e5f, -1e5f, -1e5f, 0.0f);
+            xs[cl0 * C + r] = nb_pad_coord(cl0 * C + r);
         }
     } else {
     int npow = 1;
@@ -248,7 +248,7 @@ __global__ void __launch_bounds__(256) k_colsort(nb_geom g, const float *__restr
             xs[slot] = make_float4(x[3 * a] + o.x, x[3 * a + 1] + o.y, x[3 * a + 2] + o.z, 1.0f);
         } else {
             perm[slot] = -1;
-            xs[slot] = make_float4(-1e5f, -1e5f, -1e5f, 0.0f);
+            xs[slot] = nb_pad_coord(slot);
         }
     }
     }
@@ -399,18 +399,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NB_SEA
             s = q_s[wv][lane];
             const float sx = nb_tx(s) * g.L[0], sy = nb_ty(s) * g.L[1], sz = nb_tz(s) * g.L[2];
             float jx[C], jy[C], jz[C];
-            unsigned jreal = 0u;
 #pragma unroll
             for (int b = 0; b < C; ++b) {
                 const float4 p = xs[cj * C + b];
                 jx[b] = p.x + sx;
                 jy[b] = p.y + sy;
                 jz[b] = p.z + sz;
-                if (p.w > 0.0f) jreal |= 1u << b;
             }
-#pragma unroll
-            for (int b = 0; b < C; ++b)
-                if ((jreal >> b) & 1u) m |= (unsigned long long)ireal << (b * C);
+            // every pair of the C x C candidate, padding included (its distance excludes it)
+            m = C == 8 ? ~0ull : 0xFFFFull;
             if (cj == ci && s == NB_SHIFT_ZERO) m &= tri;
             for (int k = 0; k < npart; ++k) {
                 const int pe = part[wv][k];

@@ -40,7 +40,7 @@ __global__ void k_pack(int npad_max, const int *__restrict__ perm, const float *
         xq[p] = make_float4(x0 + o.x, x1 + o.y, x2 + o.z, q ? q[a] : 0.0f);
         tsort[p] = t;
     } else {
-        xq[p] = make_float4(-1e5f, -1e5f, -1e5f, 0.0f);
+        xq[p] = nb_pad_coord(p);
         tsort[p] = 0;
     }
     fj[p] = 0.0f;

@@ -36,14 +36,27 @@
 #define NB_FSCALE 4096.0f
 #define NB_FRANGE 131072.0f
 
+// Coordinates of padding slot p (also of the far j-group behind the last slot): far outside the
+// box, and at least NB_PAD_SPACING from every other padding slot (the slot index spread over the
+// three axes, 10 bits each, all values exact in FP32), so that no pair that involves padding lies
+// within the list range (rc + rb < NB_PAD_SPACING is enforced): the topology masks leave padding
+// unmasked and the distance test excludes it.
+#define NB_PAD_SPACING 16.0f
+__host__ __device__ __forceinline__ float4 nb_pad_coord(int p) {
+    return make_float4(-1e5f - NB_PAD_SPACING * (float)(p & 1023),
+                       -1e5f - NB_PAD_SPACING * (float)((p >> 10) & 1023),
+                       -1e5f - NB_PAD_SPACING * (float)((p >> 20) & 1023), 0.0f);
+}
+
 // One j-entry of the cluster-pair list.  The j side of every entry is a group of NB_JG = 4
 // consecutive slots: a whole cluster when C = 4, one half (lower or upper four in z order) of
 // a cluster when C = 8, so an 8-atom i-cluster meets 4-atom j-groups (8 x 4 pairs per entry)
 // and half-clusters with no atom pair in range are not listed.  gs packs the group index and
 // the periodic shift of the j image (x_j + t L); mask bit (b * C + a) is set iff i-atom a and
-// j-atom b of the group are both real, distinct, not excluded and, for the self pair at t = 0,
-// in increasing slot order.  The mask is column-major so that the lane holding j-atom b
-// extracts its C bits with one shift.  Distances are not part of the mask.
+// j-atom b of the group are distinct, not excluded and, for the self pair at t = 0, in
+// increasing slot order.  Padding slots are not masked: they sit far outside the box and far
+// apart (nb_pad_coord), so that the distance test excludes every pair that involves one.  The
+// mask is column-major so that the lane holding j-atom b extracts its C bits with one shift.
 #define NB_JG 4
 #define NB_JPB (NB_WAVE / NB_JG)  // entries per batch of 64 lanes
 struct nb_entry {
