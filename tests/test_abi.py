@@ -102,6 +102,18 @@ def test_rlist_beyond_box_is_rejected():
     assert nb.nb_validate_params(p) == nb.NB_ERR_CUTOFF
 
 
+def test_list_range_beyond_padding_spacing_is_rejected():
+    # padding slots sit 16 nm apart (they are excluded by distance, not by the masks), so the
+    # list range must stay below that even in a box large enough for it
+    p = base_params(buffer=0.1)
+    p.c.box[0] = p.c.box[1] = p.c.box[2] = 50.0
+    p.c.ewald_beta = 0.2  # beta rc within the erfc fit's range
+    p.c.cutoff = 15.95
+    assert nb.nb_validate_params(p) == nb.NB_ERR_CUTOFF
+    p.c.cutoff = 15.8
+    assert nb.nb_validate_params(p) == nb.NB_OK
+
+
 def test_bad_exclusions_are_rejected():
     t = synth.tiny()
     idx = t.excl_idx.copy()
