@@ -505,8 +505,10 @@ int nb_setup(nb_ctx **out, const nb_params *p, void *stream) {
             goto fail_out;
         }
     }
+    // the fixed-point force sums start at zero and are left at zero by every complete force call
     if (hipMemset(c->meta, 0, sizeof(nb_meta)) != hipSuccess ||
-        hipMemset(c->slot_of, 0, sizeof(int) * n) != hipSuccess) {
+        hipMemset(c->slot_of, 0, sizeof(int) * n) != hipSuccess ||
+        hipMemset(c->fj, 0, sizeof(float) * 3 * (size_t)c->npad_max) != hipSuccess) {
         r = fail(c, NB_ERR_HIP, "hipMemset meta");
         goto fail_out;
     }
@@ -661,8 +663,12 @@ static int forces_impl(nb_ctx *c, const float *x, const float *q, const int32_t 
                        double *e, double *vir) {
     if (!c || !x || !q || !type || !f || !e) return fail(c, NB_ERR_ARG, "NULL argument");
     if (!c->have_list) return fail(c, NB_ERR_STATE, "nb_forces called before nb_pairlist");
-    hipError_t err = nb_launch_pack(c, x, q, type);
+    hipError_t err = hipSuccess;
+    // a call that failed between its force kernel and its finalize may have left sums behind
+    if (!c->fj_clean) err = hipMemsetAsync(c->fj, 0, sizeof(float) * 3 * (size_t)c->npad_max, c->stream);
+    if (err == hipSuccess) err = nb_launch_pack(c, x, q, type);
     if (err == hipSuccess && c->pruned && (c->flags & NB_CHECK_STALE)) err = nb_launch_prune_check(c, x);
+    c->fj_clean = false;
     if (c->timing && err == hipSuccess) {
         const size_t kMaxPairs = 4096;
         if (c->ev_used == kMaxPairs) {
@@ -685,6 +691,7 @@ static int forces_impl(nb_ctx *c, const float *x, const float *q, const int32_t 
     if (err == hipSuccess && (c->flags & NB_EWALD_CORR)) err = nb_launch_ewald_corr(c, x, q);
     if (err == hipSuccess) err = nb_launch_finalize(c, f, e, vir);
     if (err != hipSuccess) return hip_fail(c, err, "force launch");
+    c->fj_clean = true;
     return NB_OK;
 }
 

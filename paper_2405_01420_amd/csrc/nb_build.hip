@@ -169,6 +169,7 @@ __global__ void __launch_bounds__(256) k_colsort(nb_geom g, const float *__restr
                                                  const int *__restrict__ colcl,
                                                  const int *__restrict__ tmp, int *__restrict__ perm,
                                                  int *__restrict__ slot_of, float4 *__restrict__ xs,
+                                                 float4 *__restrict__ xq, int *__restrict__ tsort,
                                                  float4 *__restrict__ bblo, float4 *__restrict__ bbhi,
                                                  int2 *__restrict__ colz, nb_meta *meta) {
     __shared__ unsigned long long key[NB_SORT_MAX];
@@ -176,12 +177,18 @@ __global__ void __launch_bounds__(256) k_colsort(nb_geom g, const float *__restr
     const int c = blockIdx.x, tid = threadIdx.x;
     const int n = colcount[c], start = colstart[c];
     const int cl0 = colcl[c], nslot = (colcl[c + 1] - cl0) * C;
+    // a padding slot: far coordinates (distinct per slot) and type 0 in the build's and the force
+    // path's copies; the per-call pack writes only the slots of atoms, so these last until the
+    // next build
+    auto pad = [&](int slot) {
+        perm[slot] = -1;
+        xs[slot] = nb_pad_coord(slot);
+        xq[slot] = nb_pad_coord(slot);
+        tsort[slot] = 0;
+    };
     if (n > NB_SORT_MAX) {   // reported; the column's clusters are left empty
         if (tid == 0) atomicOr(&meta->flags, NB_F_COLUMN);
-        for (int r = tid; r < nslot; r += blockDim.x) {
-            perm[cl0 * C + r] = -1;
-            xs[cl0 * C + r] = nb_pad_coord(cl0 * C + r);
-        }
+        for (int r = tid; r < nslot; r += blockDim.x) pad(cl0 * C + r);
     } else if (n <= (int)blockDim.x) {
         // one atom per thread: its place in the sorted column is the number of smaller keys
         // (keys are distinct: the atom index is their low word), read from LDS as broadcasts
@@ -204,10 +211,7 @@ __global__ void __launch_bounds__(256) k_colsort(nb_geom g, const float *__restr
             const float4 o = off[a];
             xs[slot] = make_float4(x[3 * a] + o.x, x[3 * a + 1] + o.y, x[3 * a + 2] + o.z, 1.0f);
         }
-        for (int r = n + tid; r < nslot; r += blockDim.x) {
-            perm[cl0 * C + r] = -1;
-            xs[cl0 * C + r] = nb_pad_coord(cl0 * C + r);
-        }
+        for (int r = n + tid; r < nslot; r += blockDim.x) pad(cl0 * C + r);
     } else {
     int npow = 1;
     while (npow < n) npow <<= 1;
@@ -247,8 +251,7 @@ __global__ void __launch_bounds__(256) k_colsort(nb_geom g, const float *__restr
             float4 o = off[a];
             xs[slot] = make_float4(x[3 * a] + o.x, x[3 * a + 1] + o.y, x[3 * a + 2] + o.z, 1.0f);
         } else {
-            perm[slot] = -1;
-            xs[slot] = nb_pad_coord(slot);
+            pad(slot);
         }
     }
     }
@@ -864,12 +867,13 @@ hipError_t build_impl(nb_ctx *c, const float *x) {
                        c->meta, lds);
     hipLaunchKernelGGL(k_colscan, dim3(1), dim3(1024), 0, c->stream, c->geom.ncol, C, c->colcount,
                        c->colstart, c->colcl, c->meta);
-    // every slot the per-call pack visits is either written by the column sort or padding
+    // every slot is marked empty here; the column sort fills the slots of its clusters (atoms and
+    // padding), which are the only ones the force path reads
     hipLaunchKernelGGL(k_scatter, dim3((n + tb - 1) / tb), dim3(tb), 0, c->stream, n, c->npad_max,
                        c->col, c->rank, c->colstart, c->tmp, c->perm);
     hipLaunchKernelGGL((k_colsort<C>), dim3(c->geom.ncol), dim3(256), 0, c->stream, c->geom, x, c->off,
                        c->colcount, c->colstart, c->colcl, c->tmp, c->perm, c->slot_of, c->xs,
-                       c->bblo, c->bbhi, c->colz, c->meta);
+                       c->xq, c->tsort, c->bblo, c->bbhi, c->colz, c->meta);
     hipLaunchKernelGGL((k_search<C>), dim3((c->ncl_max + 3) / 4), dim3(256), 0, c->stream,
                        c->geom, c->cap, c->colcl, c->colz, c->bblo, c->bbhi, c->perm, c->xs,
                        c->nnz_excl > 0 ? c->excl_off : nullptr, c->excl_idx, c->slot_of, c->icount, c->jl,

@@ -16,36 +16,32 @@ namespace {
 
 #define NB_FIN_BLOCK 512
 
-__global__ void k_pack(int npad_max, const int *__restrict__ perm, const float *__restrict__ x,
+// Positions (wrapped as at the build), charges and types into the cluster slots, one thread per
+// atom in input order: every load is contiguous across the wave and independent of the others,
+// and each store goes to the atom's slot.  Padding slots keep what the build's column sort wrote
+// into them (far coordinates, type 0).  The fixed-point force sums are zero here already: the
+// finalize clears every slot it reads, and no other slot receives anything (the sums that would
+// reach padding slots are zero, and zero sums are skipped).
+__global__ void k_pack(int n, const int *__restrict__ slot_of, const float *__restrict__ x,
                        const float *__restrict__ q, const int32_t *__restrict__ type, int ntypes,
                        const float4 *__restrict__ off, const float *__restrict__ xbuild,
                        uint32_t checks, float stale2, float4 *__restrict__ xq,
-                       int *__restrict__ tsort, float *__restrict__ fj, nb_meta *meta) {
-    // slots past the current grid's padded count hold perm = -1 (set at every build), so all
-    // npad_max slots are visited without waiting for the grid size
-    int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= npad_max) return;
-    int a = perm[p];
-    if (a >= 0) {
-        float x0 = x[3 * a], x1 = x[3 * a + 1], x2 = x[3 * a + 2];
-        float4 o = off[a];
-        if (checks & NB_CHECK_STALE) {
-            float d0 = x0 - xbuild[3 * a], d1 = x1 - xbuild[3 * a + 1], d2 = x2 - xbuild[3 * a + 2];
-            if (!(d0 * d0 + d1 * d1 + d2 * d2 < stale2)) atomicOr(&meta->flags, NB_F_STALE);
-        }
-        if ((checks & NB_CHECK_FINITE) && !(isfinite(x0) && isfinite(x1) && isfinite(x2)))
-            atomicOr(&meta->flags, NB_F_NONFINITE);
-        int t = type ? type[a] : 0;
-        t = min(max(t, 0), ntypes - 1);
-        xq[p] = make_float4(x0 + o.x, x1 + o.y, x2 + o.z, q ? q[a] : 0.0f);
-        tsort[p] = t;
-    } else {
-        xq[p] = nb_pad_coord(p);
-        tsort[p] = 0;
+                       int *__restrict__ tsort, nb_meta *meta) {
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= n) return;
+    const int p = slot_of[a];
+    const float x0 = x[3 * a], x1 = x[3 * a + 1], x2 = x[3 * a + 2];
+    const float4 o = off[a];
+    if (checks & NB_CHECK_STALE) {
+        float d0 = x0 - xbuild[3 * a], d1 = x1 - xbuild[3 * a + 1], d2 = x2 - xbuild[3 * a + 2];
+        if (!(d0 * d0 + d1 * d1 + d2 * d2 < stale2)) atomicOr(&meta->flags, NB_F_STALE);
     }
-    fj[p] = 0.0f;
-    fj[npad_max + p] = 0.0f;
-    fj[2 * npad_max + p] = 0.0f;
+    if ((checks & NB_CHECK_FINITE) && !(isfinite(x0) && isfinite(x1) && isfinite(x2)))
+        atomicOr(&meta->flags, NB_F_NONFINITE);
+    int t = type ? type[a] : 0;
+    t = min(max(t, 0), ntypes - 1);
+    xq[p] = make_float4(x0 + o.x, x1 + o.y, x2 + o.z, q ? q[a] : 0.0f);
+    tsort[p] = t;
 }
 
 __device__ __forceinline__ float wave_sum(float v) {
@@ -63,8 +59,8 @@ __device__ __forceinline__ double wave_sum(double v) {
 // One work unit per wave, NB_FORCE_WAVES consecutive units per workgroup (neighbouring waves work
 // on neighbouring clusters, whose j-atoms they share in the caches).  The energy sums of the
 // workgroup's waves are combined in LDS by whichever wave finishes last, in wave order, and
-// stored as the workgroup's partial (epart[4 blockIdx ..], virial vpart[6 blockIdx ..]); waves do
-// not wait for each other.  (Workgroups that take several units in turn, statically or from a
+// stored as the workgroup's partial (epart[4 blockIdx ..], virial vpart[6 blockIdx ..]; zeros from
+// workgroups without a unit); waves do not wait for each other.  (Workgroups that take several units in turn, statically or from a
 // shared counter, were measured slower: the former coarsen the tail of the launch, the latter
 // serialise on the counter's atomics.)
 #define NB_FORCE_WAVES 4
@@ -86,7 +82,12 @@ __global__ void __launch_bounds__(NB_FORCE_WAVES * NB_WAVE) NB_FORCE_OCCUPANCY_V
     __shared__ double esh[NB_FORCE_WAVES][VIR ? 9 : 3];
     __shared__ int edone;
     const int nunits = meta->nunits;
-    if (blockIdx.x * NB_FORCE_WAVES >= nunits) return;  // an idle workgroup
+    if (blockIdx.x * NB_FORCE_WAVES >= nunits) {
+        // an idle workgroup: zero partials, so that the finalize can sum every workgroup's
+        if (threadIdx.x < 4) epart[4 * blockIdx.x + threadIdx.x] = 0.0;
+        if (VIR && threadIdx.x < 6) vpart[6 * blockIdx.x + threadIdx.x] = 0.0;
+        return;
+    }
     const int ntt = fp.ntypes * fp.ntypes;
     if (threadIdx.x == 0) edone = 0;
     nb_load_ljtab(tab, ljtab, ntt);
@@ -237,7 +238,7 @@ __device__ __forceinline__ void fin_block_sum(const double *__restrict__ tab, in
     double a[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) a[k] = 0.0;
-#pragma unroll 4
+#pragma unroll 8
     for (int r = threadIdx.x; r < nrow; r += NB_FIN_BLOCK) {
 #pragma unroll
         for (int k = 0; k < K; ++k) a[k] += tab[(size_t)stride * r + k];
@@ -258,14 +259,16 @@ __device__ __forceinline__ void fin_block_sum(const double *__restrict__ tab, in
     __syncthreads();  // s is reused by the next call
 }
 
-// f[atom] in original order, and the FP64 energy sums.  Block 0 additionally adds the energy
-// partials of the force workgroups in order (strided per thread, then the wave and block trees)
-// and applies the Coulomb shift; it is dispatched first, so this runs beside the other blocks'
-// force gathers and needs no inter-block synchronisation.
-__global__ void __launch_bounds__(NB_FIN_BLOCK) k_finalize(int n, int npad_max,
-                                                           const int *__restrict__ slot_of,
-                                                           const float *__restrict__ fj,
-                                                           float *__restrict__ f, const nb_meta *meta,
+// f[atom] in original order, and the FP64 energy sums.  Blocks 1 .. take one cluster slot per
+// thread: its atom index and its fixed-point sums are loaded together (contiguous), the force
+// goes to the atom's place, and the sums are cleared for the next call.  Block 0, dispatched
+// first, adds the energy partials of all np force workgroups in order (strided per thread, then
+// the wave and block trees) and applies the Coulomb shift, beside the other blocks' work and
+// without inter-block synchronisation.
+__global__ void __launch_bounds__(NB_FIN_BLOCK) k_finalize(int npad_max, int np,
+                                                           const int *__restrict__ perm,
+                                                           float *__restrict__ fj,
+                                                           float *__restrict__ f,
                                                            const double *__restrict__ epart,
                                                            const double *__restrict__ cpart,
                                                            int ncpart, double shift_coul,
@@ -274,21 +277,26 @@ __global__ void __launch_bounds__(NB_FIN_BLOCK) k_finalize(int n, int npad_max,
                                                            const double *__restrict__ vpart,
                                                            double *__restrict__ vir) {
     __shared__ double s[8][NB_FIN_BLOCK / NB_WAVE];
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) {
-        const int p = slot_of[i];
+    if (blockIdx.x != 0) {
+        const int p = (blockIdx.x - 1) * blockDim.x + threadIdx.x;
+        if (p >= npad_max) return;
+        const int a = perm[p];
         // fixed-point sums: x in the low 32 bits of the xy word, y above it, z on its own
-        const unsigned long long w = reinterpret_cast<const unsigned long long *>(fj)[p];
+        unsigned long long *const wp = reinterpret_cast<unsigned long long *>(fj) + p;
+        int *const zp = reinterpret_cast<int *>(fj + 2 * npad_max) + p;
+        const unsigned long long w = *wp;
+        const int iz = *zp;
+        if (a < 0) return;
+        *wp = 0ull;
+        *zp = 0;
         const int ix = (int)(unsigned)w;
         const int iy = (int)((w - (unsigned long long)(long long)ix) >> 32);
-        const int iz = reinterpret_cast<const int *>(fj + 2 * npad_max)[p];
-        f[3 * i] = (float)ix * (1.0f / NB_FSCALE);
-        f[3 * i + 1] = (float)iy * (1.0f / NB_FSCALE);
-        f[3 * i + 2] = (float)iz * (1.0f / NB_FSCALE);
+        f[3 * a] = (float)ix * (1.0f / NB_FSCALE);
+        f[3 * a + 1] = (float)iy * (1.0f / NB_FSCALE);
+        f[3 * a + 2] = (float)iz * (1.0f / NB_FSCALE);
+        return;
     }
-    if (blockIdx.x != 0) return;
     // energies: the force workgroups' partials; then the Ewald-correction and virial partials
-    const int np = (meta->nunits + NB_FORCE_WAVES - 1) / NB_FORCE_WAVES;
     double en[3];
     fin_block_sum<3>(epart, np, 4, en, s);
     double cp[NB_CORR_PART] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -321,9 +329,9 @@ __global__ void __launch_bounds__(NB_FIN_BLOCK) k_finalize(int n, int npad_max,
 hipError_t nb_launch_pack(nb_ctx *c, const float *x, const float *q, const int32_t *type) {
     const int tb = 256;
     float stale2 = (float)(0.25 * c->rb * c->rb);
-    hipLaunchKernelGGL(k_pack, dim3((c->npad_max + tb - 1) / tb), dim3(tb), 0, c->stream,
-                       c->npad_max, c->perm, x, q, type, c->ntypes, c->off, c->xbuild, c->flags,
-                       stale2, c->xq, c->tsort, c->fj, c->meta);
+    hipLaunchKernelGGL(k_pack, dim3((c->natoms + tb - 1) / tb), dim3(tb), 0, c->stream, c->natoms,
+                       c->slot_of, x, q, type, c->ntypes, c->off, c->xbuild, c->flags, stale2, c->xq,
+                       c->tsort, c->meta);
     return hipGetLastError();
 }
 
@@ -398,9 +406,9 @@ hipError_t nb_launch_ewald_corr(nb_ctx *c, const float *x, const float *q) {
 }
 
 hipError_t nb_launch_finalize(nb_ctx *c, float *f, double *e, double *vir) {
-    const int nblk = std::max(1, (c->natoms + NB_FIN_BLOCK - 1) / NB_FIN_BLOCK);
-    hipLaunchKernelGGL(k_finalize, dim3(nblk), dim3(NB_FIN_BLOCK), 0, c->stream, c->natoms,
-                       c->npad_max, c->slot_of, c->fj, f, c->meta, c->epart, c->cpart,
+    const int nblk = 1 + (c->npad_max + NB_FIN_BLOCK - 1) / NB_FIN_BLOCK;
+    hipLaunchKernelGGL(k_finalize, dim3(nblk), dim3(NB_FIN_BLOCK), 0, c->stream, c->npad_max,
+                       (c->unit_cap + NB_FORCE_WAVES - 1) / NB_FORCE_WAVES, c->perm, c->fj, f, c->epart, c->cpart,
                        (c->flags & NB_EWALD_CORR) ? (c->natoms + NB_CORR_BLOCK - 1) / NB_CORR_BLOCK : 0,
                        c->shift_coul, nb_energy_fp64(c) ? c->fc : 1.0, e, c->vpart, vir);
     return hipGetLastError();

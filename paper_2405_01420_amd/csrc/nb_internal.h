@@ -177,8 +177,10 @@ struct nb_ctx {
     float4 *xs = nullptr;       // [npad_max] build positions (wrapped), sorted
     float4 *xq = nullptr;       // [npad_max] per-call positions + charge, sorted
     int *tsort = nullptr;       // [npad_max] per-call type, sorted
-    float *fj = nullptr;        // [3 * npad_max] forces in cluster order, SoA (x | y | z),
-                                // accumulated with atomics by the force kernel
+    float *fj = nullptr;        // [3 * npad_max] words: fixed-point force sums in cluster order,
+                                // x + 2^32 y as 64-bit words, then z; added to atomically by the
+                                // force kernel, read and cleared by the finalize
+    bool fj_clean = true;       // fj is all zero (false after a force call that failed part-way)
     float4 *bblo = nullptr, *bbhi = nullptr;  // [ncl_max]
     int *icount = nullptr;      // [ncl_max]
     nb_entry *jl = nullptr;     // [ncl_max * cap] the list the force calls use
