@@ -29,18 +29,21 @@ __global__ void k_pack(int n, const int *__restrict__ slot_of, const float *__re
                        int *__restrict__ tsort, nb_meta *meta) {
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= n) return;
+    // every load first, so that they are in flight together (the charge and type pointers are
+    // null where only positions are packed)
     const int p = slot_of[a];
     const float x0 = x[3 * a], x1 = x[3 * a + 1], x2 = x[3 * a + 2];
     const float4 o = off[a];
+    const float qa = q ? q[a] : 0.0f;
+    int t = type ? type[a] : 0;
     if (checks & NB_CHECK_STALE) {
         float d0 = x0 - xbuild[3 * a], d1 = x1 - xbuild[3 * a + 1], d2 = x2 - xbuild[3 * a + 2];
         if (!(d0 * d0 + d1 * d1 + d2 * d2 < stale2)) atomicOr(&meta->flags, NB_F_STALE);
     }
     if ((checks & NB_CHECK_FINITE) && !(isfinite(x0) && isfinite(x1) && isfinite(x2)))
         atomicOr(&meta->flags, NB_F_NONFINITE);
-    int t = type ? type[a] : 0;
     t = min(max(t, 0), ntypes - 1);
-    xq[p] = make_float4(x0 + o.x, x1 + o.y, x2 + o.z, q ? q[a] : 0.0f);
+    xq[p] = make_float4(x0 + o.x, x1 + o.y, x2 + o.z, qa);
     tsort[p] = t;
 }
 
