@@ -558,7 +558,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NB_SEA
 }
 
 #define NB_UNIT_MIN 4  // batches per work unit at least (a unit's fixed cost is about one)
-#define NB_UNITS_REG 16  // clusters per thread whose batch counts k_units keeps in registers
+#define NB_UNITS_BLOCKS 16   // workgroups of k_units
+#define NB_UNITS_THREADS 1024
+#define NB_UNITS_LOADS 16    // batch counts a k_units thread loads at a time
 
 // Cost class of a work unit (or list) of nb >= 1 batches: floor(log2 nb), at most NB_HIST_BINS - 1.
 __device__ __forceinline__ int nb_cost_class(int nb) {
@@ -588,8 +590,8 @@ __device__ __forceinline__ int nb_block_scan(int v, int *wa, int *total) {
     return base + incl - v;
 }
 
-// Work units of the force kernel, in one block: every i-cluster with a non-empty list becomes
-// ceil(nb / P) units of at most P 64-lane batches, nb being its list length in batches and
+// Work units of the force kernel: every i-cluster with a non-empty list becomes ceil(nb / P)
+// units of at most P 64-lane batches, nb being its list length in batches and
 // P = max(4, ceil(total batches / (2 * SIMDs))).  The SIMDs share their time among resident
 // waves, so a kernel lasts about max(total batches / SIMDs, longest list) batch times; lists are
 // split only when the longest list would set that (small boxes), never at 96k atoms.  The lists
@@ -602,148 +604,176 @@ __device__ __forceinline__ int nb_block_scan(int v, int *wa, int *total) {
 // cluster order within a class), the post-prune list sorting of the paper (section III-A) that
 // starts the long lists before the short ones to shorten the tail.  The histogram of list
 // lengths over the same classes goes to meta->hist.
-__global__ void __launch_bounds__(1024) k_units(int slots, int unit_cap, int sorted, int tail,
-                                                const int *__restrict__ icount,
-                                                int4 *__restrict__ units, nb_meta *meta) {
-    __shared__ int wa[1024 / NB_WAVE], wb[1024 / NB_WAVE];
-    __shared__ int s_p;
+//
+// NB_UNITS_BLOCKS workgroups, each emitting the units of one chunk of consecutive clusters, with
+// no synchronisation between them: every workgroup sums the batch counts of all clusters itself
+// (for P) and counts the units of the clusters before its chunk (for its first unit index, or per
+// cost class in the sorted order), reading the counts in coalesced passes.
+__device__ __forceinline__ int nb_block_sum(int v, int *wa) {
+    int t;
+    nb_block_scan(v, wa, &t);
+    return t;
+}
+
+__global__ void __launch_bounds__(NB_UNITS_THREADS) k_units(int slots, int unit_cap, int sorted, int tail,
+                                                            const int *__restrict__ icount,
+                                                            int4 *__restrict__ units, nb_meta *meta) {
+    __shared__ int wa[NB_UNITS_THREADS / NB_WAVE];
+    __shared__ int s_cnt[2][NB_HIST_BINS];  // per cost class: units before the chunk, all units
     __shared__ int s_hist[NB_HIST_BINS];
-    const int tid = threadIdx.x, nthr = blockDim.x;
-    const int lane = tid & (NB_WAVE - 1), wv = tid / NB_WAVE, nw = nthr / NB_WAVE;
+    const int tid = threadIdx.x, nthr = blockDim.x, lane = tid & (NB_WAVE - 1);
+    const bool lead = blockIdx.x == 0, last = blockIdx.x == gridDim.x - 1;
     const int ncl = meta->nclusters;
-    const int chunk = (ncl + nthr - 1) / nthr;
-    const int c_lo = min(ncl, tid * chunk), c_hi = min(ncl, c_lo + chunk);
-    if (tid < NB_HIST_BINS) s_hist[tid] = 0;
-    // The batch counts of this thread's first NB_UNITS_REG clusters stay in registers (loaded
-    // together from clamped indices, zero past the chunk); a longer chunk (more than
-    // 1024 * NB_UNITS_REG clusters) reads the rest from memory.  One block does all of this,
-    // so the per-cluster work is kept to a few instructions.
-    int nbr[NB_UNITS_REG];
-    const int c_last = max(ncl - 1, 0);
-#pragma unroll
-    for (int j = 0; j < NB_UNITS_REG; ++j) nbr[j] = icount[min(c_lo + j, c_last)];
-#pragma unroll
-    for (int j = 0; j < NB_UNITS_REG; ++j) nbr[j] = c_lo + j < c_hi ? (nbr[j] + NB_JPB - 1) / NB_JPB : 0;
-    const int c_rest = c_lo + NB_UNITS_REG;
-    auto batches = [&](int c) { return (icount[c] + NB_JPB - 1) / NB_JPB; };
-    // total batches and the longest list: wave trees, then one thread over the waves
-    int nb_sum = 0, nb_max = 0;
-#pragma unroll
-    for (int j = 0; j < NB_UNITS_REG; ++j) {
-        nb_sum += nbr[j];
-        nb_max = max(nb_max, nbr[j]);
+    const int chunk = (ncl + gridDim.x - 1) / gridDim.x;
+    const int lo = min(ncl, (int)blockIdx.x * chunk), hi = min(ncl, lo + chunk);
+    if (tid < NB_HIST_BINS) {
+        s_hist[tid] = 0;
+        s_cnt[0][tid] = 0;
+        s_cnt[1][tid] = 0;
     }
-    for (int c = c_rest; c < c_hi; ++c) {
-        const int nb = batches(c);
+    __syncthreads();
+    auto batches = [&](int c) { return (icount[c] + NB_JPB - 1) / NB_JPB; };
+    // the batch counts of clusters c0 + j nthr + tid (j < NB_UNITS_LOADS) below `end`, loaded
+    // together from clamped indices (zero past the end), passed to f(c, nb)
+    auto pass = [&](int end, auto &&f) {
+        for (int c0 = 0; c0 < end; c0 += NB_UNITS_LOADS * nthr) {
+            int nb[NB_UNITS_LOADS];
+#pragma unroll
+            for (int j = 0; j < NB_UNITS_LOADS; ++j) nb[j] = icount[min(c0 + j * nthr + tid, end - 1)];
+#pragma unroll
+            for (int j = 0; j < NB_UNITS_LOADS; ++j) {
+                const int c = c0 + j * nthr + tid;
+                f(c, c < end ? (nb[j] + NB_JPB - 1) / NB_JPB : 0);
+            }
+        }
+    };
+    // pass over all clusters: total batches, longest list; the list-length histogram (first
+    // workgroup; per-wave counts from ballots)
+    int nb_sum = 0, nb_max = 0;
+    int hw[NB_HIST_BINS];
+#pragma unroll
+    for (int b = 0; b < NB_HIST_BINS; ++b) hw[b] = 0;
+    pass(ncl, [&](int c, int nb) {
         nb_sum += nb;
         nb_max = max(nb_max, nb);
-    }
+        if (lead) {
+            const int k = nb > 0 ? nb_cost_class(nb) : -1;
 #pragma unroll
-    for (int o = NB_WAVE / 2; o > 0; o >>= 1) {
-        nb_sum += __shfl_xor(nb_sum, o, NB_WAVE);
-        nb_max = max(nb_max, __shfl_xor(nb_max, o, NB_WAVE));
-    }
-    if (lane == 0) {
-        wa[wv] = nb_sum;
-        wb[wv] = nb_max;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        int t = 0, m = 0;
-        for (int k = 0; k < nw; ++k) {
-            t += wa[k];
-            m = max(m, wb[k]);
+            for (int b = 0; b < NB_HIST_BINS; ++b) hw[b] += __popcll(__builtin_amdgcn_ballot_w64(k == b));
         }
-        s_p = max(NB_UNIT_MIN, (t + 2 * slots - 1) / (2 * slots));
-        meta->maxbatches = m;
+    });
+    if (lead && lane == 0) {
+#pragma unroll
+        for (int b = 0; b < NB_HIST_BINS; ++b)
+            if (hw[b]) atomicAdd(&s_hist[b], hw[b]);
     }
+    nb_sum = nb_block_sum(nb_sum, wa);
+    int m = nb_max;
+#pragma unroll
+    for (int o = NB_WAVE / 2; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o, NB_WAVE));
     __syncthreads();
-    const int P = __builtin_amdgcn_readfirstlane(s_p);
+    if (lane == 0) wa[tid / NB_WAVE] = m;
+    __syncthreads();
+    for (int k = 0; k < nthr / NB_WAVE; ++k) m = max(m, wa[k]);
+    const int P = max(NB_UNIT_MIN, (nb_sum + 2 * slots - 1) / (2 * slots));
     // the lists of the last `tail` clusters are split into halves (units of ceil(nb / 2) batches;
-    // longer than P, they are split by P anyway): batches per unit and units of cluster c,
-    // without a division by a per-cluster value
+    // longer than P, they are split by P anyway): batches per unit and units of cluster c
     const int c_split = ncl - tail;
     auto halve = [&](int c, int nb) { return c >= c_split && nb <= P; };
     auto pmax = [&](int c, int nb) { return halve(c, nb) ? (nb + 1) >> 1 : P; };
-    auto nunits_of = [&](int c, int nb) { return halve(c, nb) ? min(nb, 2) : (nb + P - 1) / P; };
-    // histogram of the list lengths (non-empty lists) by cost class
-    {
-        int h[NB_HIST_BINS];
-#pragma unroll
-        for (int b = 0; b < NB_HIST_BINS; ++b) h[b] = 0;
-        auto count = [&](int nb) {
-            if (nb <= 0) return;
-            const int k = nb_cost_class(nb);
-#pragma unroll
-            for (int b = 0; b < NB_HIST_BINS; ++b) h[b] += b == k ? 1 : 0;
-        };
-#pragma unroll
-        for (int j = 0; j < NB_UNITS_REG; ++j) count(nbr[j]);
-        for (int c = c_rest; c < c_hi; ++c) count(batches(c));
-#pragma unroll
-        for (int b = 0; b < NB_HIST_BINS; ++b) {
-            int v = h[b];
-#pragma unroll
-            for (int o = NB_WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, NB_WAVE);
-            if (lane == 0 && v) atomicAdd(&s_hist[b], v);
-        }
-    }
-    // units of this thread's clusters and their exclusive prefix over the threads
-    int nu = 0;
-#pragma unroll
-    for (int j = 0; j < NB_UNITS_REG; ++j) nu += nunits_of(c_lo + j, nbr[j]);
-    for (int c = c_rest; c < c_hi; ++c) nu += nunits_of(c, batches(c));
-    int run = 0;
-    const int u0 = nb_block_scan(nu, wa, &run);
-    if (tid == 0) {
-        meta->nunits = min(run, unit_cap);
-        meta->split = P;
-        if (run > unit_cap) atomicOr(&meta->flags, NB_F_COLUMN);  // not reachable: <= ncl + tail + 2 slots
-    }
+    auto nunits_of = [&](int c, int nb) {
+        return halve(c, nb) ? min(nb, 2) : (nb <= P ? (nb > 0 ? 1 : 0) : (nb + P - 1) / P);
+    };
+    // this thread's clusters of the chunk: a contiguous run, so that unit order is cluster order
+    const int sub = (hi - lo + nthr - 1) / nthr;
+    const int t_lo = min(hi, lo + tid * sub), t_hi = min(hi, t_lo + sub);
     if (!sorted) {
-        int u = u0;
-        auto emit = [&](int c, int nb) {
-            const int pc = pmax(c, nb);
+        // units before the chunk, then the exclusive prefix over the chunk's threads
+        int before = 0;
+        pass(lo, [&](int c, int nb) { before += nunits_of(c, nb); });
+        before = nb_block_sum(before, wa);
+        int mine = 0;
+        for (int c = t_lo; c < t_hi; ++c) mine += nunits_of(c, batches(c));
+        int tot = 0;
+        int u = before + nb_block_scan(mine, wa, &tot);
+        if (last && tid == 0) {
+            const int run = before + tot;
+            meta->nunits = min(run, unit_cap);
+            if (run > unit_cap) atomicOr(&meta->flags, NB_F_COLUMN);  // not reachable: <= ncl + tail + 2 slots
+        }
+        for (int c = t_lo; c < t_hi; ++c) {
+            const int nb = batches(c), pc = pmax(c, nb);
             for (int b = 0; b < nb; b += pc) {
                 if (u < unit_cap) units[u] = make_int4(c, b, min(pc, nb - b), u);
                 ++u;
             }
-        };
-#pragma unroll
-        for (int j = 0; j < NB_UNITS_REG; ++j) emit(c_lo + j, nbr[j]);
-        for (int c = c_rest; c < c_hi; ++c) emit(c, batches(c));
+        }
     } else {
-        // longest first: one pass per cost class, from the highest; within a class the units keep
-        // cluster order (each thread's units at its exclusive prefix over the threads)
+        // per cost class: the units before the chunk and all units (a cluster's units are all
+        // of length pc but the last)
+        int hb[2][NB_HIST_BINS];
+#pragma unroll
+        for (int b = 0; b < NB_HIST_BINS; ++b) hb[0][b] = hb[1][b] = 0;
+        pass(ncl, [&](int c, int nb) {
+            if (nb <= 0) return;
+            const int nu = nunits_of(c, nb), pc = pmax(c, nb);
+            const int kf = nb_cost_class(pc), kl = nb_cost_class(nb - (nu - 1) * pc);
+            const int w = c < lo ? 0 : 1;
+#pragma unroll
+            for (int b = 0; b < NB_HIST_BINS; ++b) {
+                const int add = (b == kf ? nu - 1 : 0) + (b == kl ? 1 : 0);
+                hb[1][b] += add;
+                if (w == 0) hb[0][b] += add;
+            }
+        });
+#pragma unroll
+        for (int b = 0; b < NB_HIST_BINS; ++b) {
+#pragma unroll
+            for (int w = 0; w < 2; ++w) {
+                int v = hb[w][b];
+#pragma unroll
+                for (int o = NB_WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, NB_WAVE);
+                if (lane == 0 && v) atomicAdd(&s_cnt[w][b], v);
+            }
+        }
+        __syncthreads();
+        if (last && tid == 0) {
+            int run = 0;
+            for (int b = 0; b < NB_HIST_BINS; ++b) run += s_cnt[1][b];
+            meta->nunits = min(run, unit_cap);
+            if (run > unit_cap) atomicOr(&meta->flags, NB_F_COLUMN);
+        }
+        // one pass per cost class, from the highest: the class's units of the chunk follow those
+        // of all higher classes and the class's units before the chunk
         int base = 0;
         for (int k = NB_HIST_BINS - 1; k >= 0; --k) {
             int mine = 0;
-            auto count_k = [&](int c, int nb) {
-                const int pc = pmax(c, nb);
+            for (int c = t_lo; c < t_hi; ++c) {
+                const int nb = batches(c), pc = pmax(c, nb);
                 for (int b = 0; b < nb; b += pc) mine += nb_cost_class(min(pc, nb - b)) == k ? 1 : 0;
-            };
-#pragma unroll
-            for (int j = 0; j < NB_UNITS_REG; ++j) count_k(c_lo + j, nbr[j]);
-            for (int c = c_rest; c < c_hi; ++c) count_k(c, batches(c));
+            }
             int tot = 0;
-            int u = base + nb_block_scan(mine, wa, &tot);
-            auto emit_k = [&](int c, int nb) {
-                const int pc = pmax(c, nb);
+            int u = base + s_cnt[0][k] + nb_block_scan(mine, wa, &tot);
+            for (int c = t_lo; c < t_hi; ++c) {
+                const int nb = batches(c), pc = pmax(c, nb);
                 for (int b = 0; b < nb; b += pc) {
                     const int len = min(pc, nb - b);
                     if (nb_cost_class(len) != k) continue;
                     if (u < unit_cap) units[u] = make_int4(c, b, len, u);
                     ++u;
                 }
-            };
-#pragma unroll
-            for (int j = 0; j < NB_UNITS_REG; ++j) emit_k(c_lo + j, nbr[j]);
-            for (int c = c_rest; c < c_hi; ++c) emit_k(c, batches(c));
-            base += tot;
+            }
+            base += s_cnt[1][k];
         }
     }
-    __syncthreads();
-    if (tid < NB_HIST_BINS) meta->hist[tid] = s_hist[tid];
+    if (lead) {
+        __syncthreads();
+        if (tid < NB_HIST_BINS) meta->hist[tid] = s_hist[tid];
+        if (tid == 0) {
+            meta->maxbatches = m;
+            meta->split = P;
+        }
+    }
 }
 
 // Export of interacting pairs with the force kernel's arithmetic: the same lane layout (one
@@ -878,15 +908,17 @@ hipError_t build_impl(nb_ctx *c, const float *x) {
                        c->geom, c->cap, c->colcl, c->colz, c->bblo, c->bbhi, c->perm, c->xs,
                        c->nnz_excl > 0 ? c->excl_off : nullptr, c->excl_idx, c->slot_of, c->icount, c->jl,
                        c->meta);
-    hipLaunchKernelGGL(k_units, dim3(1), dim3(1024), 0, c->stream, c->slots, c->unit_cap,
-                       (c->flags & NB_SORT_UNITS) ? 1 : 0, c->tail_n, c->icount, c->units, c->meta);
+    hipLaunchKernelGGL(k_units, dim3(NB_UNITS_BLOCKS), dim3(NB_UNITS_THREADS), 0, c->stream, c->slots,
+                       c->unit_cap, (c->flags & NB_SORT_UNITS) ? 1 : 0, c->tail_n, c->icount, c->units,
+                       c->meta);
     return hipGetLastError();
 }
 
 template <int C>
 hipError_t pairs_impl(nb_ctx *c, int64_t cap) {
     unsigned long long *counter = (unsigned long long *)&c->meta->npairs_out;
-    hipMemsetAsync(counter, 0, sizeof(unsigned long long), c->stream);
+    const hipError_t e = hipMemsetAsync(counter, 0, sizeof(unsigned long long), c->stream);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_pairs<C>), dim3((c->ncl_max + 3) / 4), dim3(256), 0, c->stream, c->geom,
                        c->fp.rc2, c->cap, c->xq, c->perm, c->icount, c->jl, c->meta, counter, cap,
                        c->dbg_pairs);
@@ -910,8 +942,9 @@ hipError_t prune_impl(nb_ctx *c, float rin2, const int *icount, const nb_entry *
     hipLaunchKernelGGL((k_prune<C>), dim3((c->ncl_max + 3) / 4), dim3(256), 0, c->stream, c->geom, rin2,
                        c->cap, c->ncl_max, c->xq, icount, jl, icount_p, jl_p, c->meta);
     // work units of the pruned lists (the shorter lists are split by the same rule)
-    hipLaunchKernelGGL(k_units, dim3(1), dim3(1024), 0, c->stream, c->slots, c->unit_cap,
-                       (c->flags & NB_SORT_UNITS) ? 1 : 0, c->tail_n, icount_p, c->units, c->meta);
+    hipLaunchKernelGGL(k_units, dim3(NB_UNITS_BLOCKS), dim3(NB_UNITS_THREADS), 0, c->stream, c->slots,
+                       c->unit_cap, (c->flags & NB_SORT_UNITS) ? 1 : 0, c->tail_n, icount_p, c->units,
+                       c->meta);
     return hipGetLastError();
 }
 }  // namespace
