@@ -153,6 +153,8 @@ __global__ void k_scatter(int n, int npad_max, const int *__restrict__ col,
     tmp[colstart[col[i]] + rank[i]] = i;
 }
 
+#define NB_COLSORT_THREADS 256
+
 // One block per column: sort the column's atoms by (z, index) in LDS (by rank for columns of
 // at most one atom per thread, bitonic otherwise), then lay them out as clusters of C slots;
 // the tail of the last cluster is padding (perm = -1).  The block then writes the bounding
@@ -162,7 +164,7 @@ __global__ void k_scatter(int n, int npad_max, const int *__restrict__ col,
 // bounds grow with the index, so these are the first cluster that can reach above z_k and the
 // first that lies wholly above it); the end edges count as -inf and +inf.
 template <int C>
-__global__ void __launch_bounds__(256) k_colsort(nb_geom g, const float *__restrict__ x,
+__global__ void __launch_bounds__(NB_COLSORT_THREADS) k_colsort(nb_geom g, const float *__restrict__ x,
                                                  const float4 *__restrict__ off,
                                                  const int *__restrict__ colcount,
                                                  const int *__restrict__ colstart,
@@ -174,6 +176,9 @@ __global__ void __launch_bounds__(256) k_colsort(nb_geom g, const float *__restr
                                                  int2 *__restrict__ colz, nb_meta *meta) {
     __shared__ unsigned long long key[NB_SORT_MAX];
     __shared__ float zlo[NB_SORT_MAX / C], zhi[NB_SORT_MAX / C];  // the clusters' z bounds
+    // columns of at most one atom per thread: the slots' positions (w = 1 for an atom, 0 for
+    // padding), from which the bounding boxes are formed
+    __shared__ float4 spos[NB_COLSORT_THREADS + C];
     const int c = blockIdx.x, tid = threadIdx.x;
     const int n = colcount[c], start = colstart[c];
     const int cl0 = colcl[c], nslot = (colcl[c + 1] - cl0) * C;
@@ -194,9 +199,14 @@ __global__ void __launch_bounds__(256) k_colsort(nb_geom g, const float *__restr
         // (keys are distinct: the atom index is their low word), read from LDS as broadcasts
         unsigned long long v = ~0ull;
         int a = -1;
+        float4 pa = make_float4(0.0f, 0.0f, 0.0f, 1.0f);
         if (tid < n) {
             a = tmp[start + tid];
-            float z = x[3 * a + 2] + off[a].z;
+            const float4 o = off[a];
+            pa.x = x[3 * a] + o.x;
+            pa.y = x[3 * a + 1] + o.y;
+            pa.z = x[3 * a + 2] + o.z;
+            float z = pa.z;
             if (!(z > 0.0f)) z = 0.0f;
             v = ((unsigned long long)__float_as_uint(z) << 32) | (unsigned)a;
             key[tid] = v;
@@ -208,10 +218,13 @@ __global__ void __launch_bounds__(256) k_colsort(nb_geom g, const float *__restr
             const int slot = cl0 * C + rank;
             perm[slot] = a;
             slot_of[a] = slot;
-            const float4 o = off[a];
-            xs[slot] = make_float4(x[3 * a] + o.x, x[3 * a + 1] + o.y, x[3 * a + 2] + o.z, 1.0f);
+            xs[slot] = pa;
+            spos[rank] = pa;
         }
-        for (int r = n + tid; r < nslot; r += blockDim.x) pad(cl0 * C + r);
+        for (int r = n + tid; r < nslot; r += blockDim.x) {
+            pad(cl0 * C + r);
+            spos[r] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        }
     } else {
     int npow = 1;
     while (npow < n) npow <<= 1;
@@ -255,14 +268,21 @@ __global__ void __launch_bounds__(256) k_colsort(nb_geom g, const float *__restr
         }
     }
     }
-    // the block's writes of perm and xs are visible to the whole block after the barrier
+    // the block's writes of perm, xs and spos are visible to the whole block after the barrier
     __syncthreads();
+    const bool lds_pos = n <= (int)blockDim.x;
     for (int k = tid; k < nslot / C; k += blockDim.x) {
         const int cl = cl0 + k;
         float3 a = make_float3(3e38f, 3e38f, 3e38f), b = make_float3(-3e38f, -3e38f, -3e38f);
         for (int r = 0; r < C; ++r) {
-            if (perm[cl * C + r] < 0) continue;
-            const float4 p = xs[cl * C + r];
+            float4 p;
+            if (lds_pos) {
+                p = spos[k * C + r];
+                if (p.w == 0.0f) continue;
+            } else {
+                if (perm[cl * C + r] < 0) continue;
+                p = xs[cl * C + r];
+            }
             a.x = fminf(a.x, p.x);
             a.y = fminf(a.y, p.y);
             a.z = fminf(a.z, p.z);
@@ -901,7 +921,7 @@ hipError_t build_impl(nb_ctx *c, const float *x) {
     // padding), which are the only ones the force path reads
     hipLaunchKernelGGL(k_scatter, dim3((n + tb - 1) / tb), dim3(tb), 0, c->stream, n, c->npad_max,
                        c->col, c->rank, c->colstart, c->tmp, c->perm);
-    hipLaunchKernelGGL((k_colsort<C>), dim3(c->geom.ncol), dim3(256), 0, c->stream, c->geom, x, c->off,
+    hipLaunchKernelGGL((k_colsort<C>), dim3(c->geom.ncol), dim3(NB_COLSORT_THREADS), 0, c->stream, c->geom, x, c->off,
                        c->colcount, c->colstart, c->colcl, c->tmp, c->perm, c->slot_of, c->xs,
                        c->xq, c->tsort, c->bblo, c->bbhi, c->colz, c->meta);
     hipLaunchKernelGGL((k_search<C>), dim3((c->ncl_max + 3) / 4), dim3(256), 0, c->stream,

@@ -29,8 +29,9 @@
 //    complementary error function (fit_erfcx.py), Newton-refined reciprocal square root and
 //    reciprocal;
 //  * per-pair energies (FP32) are added to per-lane FP64 sums one pair at a time (no FP32
-//    partial sums, whose rounding would depend on how pairs are grouped); the Coulomb potential
-//    shift is applied in FP64 at the end from the sum of q_i q_j over interacting pairs;
+//    partial sums, whose rounding would depend on how pairs are grouped); the Ewald potential
+//    shift is part of each pair's energy, the reaction-field one (not small) is applied in FP64
+//    at the end from the sum of q_i q_j over interacting pairs;
 //  * with EPREC the pair energies are instead evaluated in FP64 (exact displacement,
 //    Newton-refined 1/r, erfc from an FP64 quintic Hermite table), forces staying FP32: the FP32
 //    rounding of the displacement and of erfc(beta r)/r is otherwise not averaged below 1e-6 of
@@ -142,10 +143,10 @@ __device__ __forceinline__ double nb_erfc_tab(const nb_etab &et, float r, double
 
 // Scalar force factor fs (F_ij = fs d) and the energies of one interacting pair at squared
 // distance r2 with qq = fC q_i q_j and the LJ row lj (C6, C12, 6 C6, 12 C12) and shift shv.  The
-// FP32 pair energies and the FP32 shift weight (fC included) are added to the FP64 sums elj / ec /
-// qqsd one pair at a time, or the shift weight as exact FP64 products qqd = q_i q_j; with EPREC the
-// FP64 energies of the pair, computed from the exact displacement (dxd, dyd, dzd), go to
-// elj / ec / qqsd.
+// FP32 pair energies (the Ewald one shifted) are added to the FP64 sums elj / ec one pair at a
+// time; the reaction field adds its shift weight as exact FP64 products qqd = q_i q_j to qqsd;
+// with EPREC the FP64 energies of the pair, computed from the exact displacement (dxd, dyd,
+// dzd), go to elj / ec and the products qqd to qqsd.
 template <bool EPREC, int FLAV>
 __device__ __forceinline__ float pair_eval(const nb_fparams &fp, const nb_etab &et, float r2,
                                            float qq, double qqd, const float4 &lj, float shv,
@@ -248,8 +249,10 @@ __device__ __forceinline__ float pair_eval(const nb_fparams &fp, const nb_etab &
             ec = __builtin_fma(qqd * nb_erfc_tab(et, r, r2d * rid), rid, ec);
             qqsd += qqd;
         } else {
-            ec += (double)(t1 * R);  // fC q_i q_j erfc(b r) / r
-            qqsd += (double)qq;
+            // fC q_i q_j (erfc(b r) / r - erfc(b rc) / rc): the potential shift is about 1e-5 of
+            // the pair's energy, so one FP32 rounding of the difference is all it adds (the
+            // shift weight stays zero in this mode)
+            ec += (double)__builtin_fmaf(t1, R, -qq * fp.shc);
         }
     }
     if (!EPREC) elj += (double)elj_p;
@@ -257,8 +260,8 @@ __device__ __forceinline__ float pair_eval(const nb_fparams &fp, const nb_etab &
 }
 
 // Whether the shift weight (sum of q_i q_j over interacting pairs) is accumulated from exact
-// FP64 products without fC (FP64 energy mode, and reaction field) or from FP32 batch sums with
-// fC (Ewald, FP32 energies).
+// FP64 products without fC (FP64 energy mode, and reaction field); otherwise (Ewald, FP32
+// energies) it is zero, the shift being part of the pair energies.
 template <bool EPREC, int FLAV>
 constexpr bool nb_qq64() { return EPREC || FLAV / 2 == NB_ELEC_RF; }
 
@@ -299,12 +302,12 @@ __device__ __forceinline__ int nb_rne(float v) {
 // Adds one atom's force contribution, in units of 1 / NB_FSCALE (lane-wise, where `on` and not
 // zero), to the fixed-point accumulators: x + 2^32 y in one 64-bit word (x sign-extended, so the
 // high word is y - 1 for negative x), z in a 32-bit word.  Raises the range flag if an active
-// lane's component reaches NB_FRANGE (or is not finite).
-__device__ __forceinline__ void nb_add_fix(bool on, int slot, float fx, float fy, float fz,
-                                           NB_G float *fj, int npad_max, NB_G unsigned *flags,
-                                           int lane) {
+// lane's component reaches NB_FRANGE (or is not finite).  onmask: the ballot of `on`.
+__device__ __forceinline__ void nb_add_fix(bool on, unsigned long long onmask, int slot, float fx,
+                                           float fy, float fz, NB_G float *fj, int npad_max,
+                                           NB_G unsigned *flags, int lane) {
     const float m = fmaxf(fmaxf(fabsf(fx), fabsf(fy)), fabsf(fz));
-    if ((__builtin_amdgcn_ballot_w64(!(m < NB_FRANGE * NB_FSCALE)) & __builtin_amdgcn_ballot_w64(on)) != 0ull &&
+    if ((__builtin_amdgcn_ballot_w64(!(m < NB_FRANGE * NB_FSCALE)) & onmask) != 0ull &&
         lane == 0)
         atomicOr((unsigned *)flags, NB_F_RANGE);
     if (on && m != 0.0f) {
@@ -380,7 +383,8 @@ __device__ __forceinline__ nb_esum nb_force_cluster(const nb_fparams &fp, const 
 #pragma unroll
     for (int k = 0; k < C; ++k) fix[k] = fiy[k] = fiz[k] = 0.0f;
     // energy sums; qqsd: the shift weight, sum of q_i q_j over interacting pairs (exact FP64
-    // products with FP64 energies or the reaction field, FP32 products fC q_i q_j otherwise)
+    // products with FP64 energies or the reaction field; zero for Ewald with FP32 energies,
+    // whose pair energies carry the shift)
     double elj = 0.0, ec = 0.0, qqsd = 0.0;
     double vird[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 
@@ -394,7 +398,10 @@ __device__ __forceinline__ nb_esum nb_force_cluster(const nb_fparams &fp, const 
     const NB_G nb_entry *lst = jl + (size_t)ci * cap;
     for (int base = b0 * NB_JPB; base < nj; base += NB_JPB) {
         const int e = base + jsub;
-        const bool valid = e < nj;
+        // the lanes of entries below nj: the first nvl (formed on the scalar unit)
+        const int nvl = min(NB_WAVE, NB_JG * (nj - base));
+        const bool valid = lane < nvl;
+        const unsigned long long vmask = nvl >= NB_WAVE ? ~0ull : (1ull << nvl) - 1ull;
         // lanes past the end of the list read the far group behind the last slot (coordinates
         // far outside any box) with an empty mask, so that none of their pairs is in range
         const nb_entry en = valid ? nb_ld(lst + e) : nb_make_entry(npad_max / NB_JG, NB_SHIFT_ZERO, 0u);
@@ -406,7 +413,6 @@ __device__ __forceinline__ nb_esum nb_force_cluster(const nb_fparams &fp, const 
         const int s0 = __builtin_amdgcn_readfirstlane(s);
         // (ballots of single compares combined on the scalar unit: a ballot of a compound
         // condition costs two more vector instructions)
-        const unsigned long long vmask = __builtin_amdgcn_ballot_w64(valid);
         const bool uniform = (__builtin_amdgcn_ballot_w64(s != s0) & vmask) == 0ull;
         // ---- filter: displacements of the lane's C pairs, interacting pairs queued in LDS
         float dx[C], dy[C], dz[C];
@@ -531,6 +537,7 @@ __device__ __forceinline__ nb_esum nb_force_cluster(const nb_fparams &fp, const 
             nb_lput<float>((code & mfsb) | w.fsb, fs);
         };
         uint32_t qa = w.q + 8u * (uint32_t)lane;
+#pragma unroll 2
         for (int p = 0; p < (nq >> 6); ++p, qa += 8u * NB_WAVE) evaluate(qa);
         if (lane < (nq & (NB_WAVE - 1))) evaluate(qa);
         nb_wave_lds_sync();
@@ -563,7 +570,7 @@ __device__ __forceinline__ nb_esum nb_force_cluster(const nb_fparams &fp, const 
         }
         // about 40% of the lanes of a batch have no pair within rc (their entry was kept for
         // another atom of the group, at rlist); their sums are zero and they skip the atomics
-        nb_add_fix(valid, jslot, jfx, jfy, jfz, fj, npad_max, flags, lane);
+        nb_add_fix(valid, vmask, jslot, jfx, jfy, jfz, fj, npad_max, flags, lane);
     }
     // the unit's i-force sums: atom k's in the lanes with lane / (64 / C) == k, added by the
     // first lane of each group
@@ -573,10 +580,11 @@ __device__ __forceinline__ nb_esum nb_force_cluster(const nb_fparams &fp, const 
     elj = nb_wave_sum_d(elj);
     ec = nb_wave_sum_d(ec);
     double qqd = nb_wave_sum_d(qqsd);
-    nb_add_fix(lane % (NB_WAVE / C) == 0, ci * C + lane / (NB_WAVE / C), sx, sy, sz, fj, npad_max,
-               flags, lane);
-    // the FP32-energy Coulomb sums and the FP32 shift weight were formed from the scaled charge
-    // products, the virial from the scaled force factors
+    const bool head = lane % (NB_WAVE / C) == 0;
+    nb_add_fix(head, __builtin_amdgcn_ballot_w64(head), ci * C + lane / (NB_WAVE / C), sx, sy, sz, fj,
+               npad_max, flags, lane);
+    // the FP32-energy Coulomb sums were formed from the scaled charge products, the virial from
+    // the scaled force factors
     constexpr double unscale = 1.0 / NB_FSCALE;
     if (!EPREC) ec *= unscale;
     if (!nb_qq64<EPREC, FLAV>()) qqd *= unscale;
