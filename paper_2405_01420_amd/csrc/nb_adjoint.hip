@@ -29,6 +29,28 @@ __global__ void k_pack_g(int npad_max, const int *__restrict__ perm, const float
     for (int k = 0; k < 6; ++k) adjj[k * npad_max + p] = 0.0f;
 }
 
+// One wavefront per i-cluster, the lanes of the force kernel (one j-atom each, 16 j-groups per
+// batch).  A batch is worked through in halves of four i-atoms: a filter forms each lane's pairs
+// with the half's i-atoms and appends the interacting ones (r < rc, unmasked) to a per-wave
+// queue in LDS as (d, pair code); the queued pairs are then evaluated one per lane, each writing
+// its six terms to its place (4-atom half index, lane) in LDS areas cleared for the half; and
+// every lane adds the terms of its own pairs (zero where a pair does not interact) to the i- and
+// j-side sums in registers, in the same order as a plain loop over the cluster's atoms.  So the
+// pair arithmetic runs only on interacting pairs, with all lanes busy.  The pair code holds LDS
+// byte addresses: (LJ table row << NB_ADJ_ROW) | (64 kk + lane) * 4 for i-atom 4 h + kk.
+#define NB_ADJ_ROW 11
+#define NB_ADJ_HALF 4            // i-atoms per half batch
+#define NB_ADJ_SLOTS (NB_ADJ_HALF * NB_WAVE)
+
+template <int C>
+struct adj_lds {
+    float out[6][NB_ADJ_SLOTS];  // per (kk, lane): v_x, v_y, v_z, A, u, w of the pair
+    float4 rec[NB_ADJ_SLOTS];    // the half's interacting pairs: (d_x, d_y, d_z, code bits)
+    float4 jg[NB_WAVE];          // per lane: the j-atom's (g_x, g_y, g_z, q)
+    float4 id[C];                // per i-atom: (x, y, z, q) as loaded
+    float4 ig[C];                // per i-atom: (g_x, g_y, g_z, -)
+};
+
 template <int C>
 __global__ void __launch_bounds__(256) k_adjoint(nb_fparams fp, const double *__restrict__ ge, int cap,
                                                  int npad_max, const float4 *__restrict__ xq,
@@ -39,35 +61,46 @@ __global__ void __launch_bounds__(256) k_adjoint(nb_fparams fp, const double *__
                                                  const nb_entry *__restrict__ jl,
                                                  float *__restrict__ adj, float *__restrict__ adjj,
                                                  const nb_meta *meta) {
+    static_assert(C % NB_ADJ_HALF == 0, "clusters of 4 or 8 atoms");
     extern __shared__ float4 tab[];
+    __shared__ __attribute__((aligned(NB_ADJ_SLOTS * 4))) adj_lds<C> wls[256 / NB_WAVE];
     const int nt = fp.ntypes, ntt = nt * nt;
     for (int k = threadIdx.x; k < 2 * ntt; k += blockDim.x) tab[k] = ljtab[k];
     __syncthreads();
     const int lane = threadIdx.x & (NB_WAVE - 1);
-    const int ci = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x / NB_WAVE) +
-                                                  threadIdx.x / NB_WAVE);
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / NB_WAVE);
+    const int ci = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x / NB_WAVE) + wv);
     if (ci >= meta->nclusters) return;
+    adj_lds<C> &w = wls[wv];
     const int b = lane % NB_JG, jsub = lane / NB_JG;
+    const uint32_t lane4 = (uint32_t)lane * 4u;
     // energy cotangents (dL/dE_LJ, dL/dE_C), read on the device: no host round trip
     const float s_lj = (float)ge[0], s_c = (float)ge[1];
 
-    float xi[C], yi[C], zi[C], qi[C], gxi[C], gyi[C], gzi[C];
-    int ti[C];
-    float ax[C], ay[C], az[C], aq[C], aw[C], au[C];
+    // the i-atoms: coordinates, charges and cotangents (wave-uniform), and in LDS for the
+    // evaluate phase; per i-atom the constant part of its pair codes (LJ row of its type)
+    float xi[C], yi[C], zi[C], qi[C];
+    uint32_t pci[C];
+    const uint32_t tabrow = nb_laddr(tab);
 #pragma unroll
     for (int k = 0; k < C; ++k) {
-        float4 v = xq[ci * C + k];
+        const float4 v = xq[ci * C + k];
         xi[k] = v.x;
         yi[k] = v.y;
         zi[k] = v.z;
         qi[k] = v.w;
-        float4 gv = gs[ci * C + k];
-        gxi[k] = gv.x;
-        gyi[k] = gv.y;
-        gzi[k] = gv.z;
-        ti[k] = tsort[ci * C + k] * nt;
-        ax[k] = ay[k] = az[k] = aq[k] = aw[k] = au[k] = 0.0f;
+        pci[k] = ((tabrow + 32u * (uint32_t)(tsort[ci * C + k] * nt)) << NB_ADJ_ROW) |
+                 ((uint32_t)(k % NB_ADJ_HALF) << 8);
     }
+    if (lane < C) {
+        w.id[lane] = xq[ci * C + lane];
+        w.ig[lane] = gs[ci * C + lane];
+    }
+    const uint32_t out0 = nb_laddr(&w.out[0][0]);
+    const uint32_t recb = nb_laddr(&w.rec[0]);
+    float ax[C], ay[C], az[C], aq[C], aw[C], au[C];
+#pragma unroll
+    for (int k = 0; k < C; ++k) ax[k] = ay[k] = az[k] = aq[k] = aw[k] = au[k] = 0.0f;
     const int nj = icount[ci];
     const nb_entry *lst = jl + (size_t)ci * cap;
     for (int base = 0; base < nj; base += NB_JPB) {
@@ -85,75 +118,132 @@ __global__ void __launch_bounds__(256) k_adjoint(nb_fparams fp, const double *__
         const float dix = nb_di(tx, fp.L[0]), diy = nb_di(ty, fp.L[1]), diz = nb_di(tz, fp.L[2]);
         const float qj = xj.w;
         const unsigned mcol = nb_mask_column<C>(en.mask, b);
+        const uint32_t pcj = ((uint32_t)tj << (NB_ADJ_ROW + 5)) | lane4;
+        nb_wave_lds_sync();  // the previous batch's reads of the work area are done
+        w.jg[lane] = make_float4(gj.x, gj.y, gj.z, qj);
         float jx = 0.0f, jy = 0.0f, jz = 0.0f, jq = 0.0f, jw = 0.0f, ju = 0.0f;
 #pragma unroll
-        for (int k = 0; k < C; ++k) {
-            const float dx = (xi[k] + dix) - xjs;
-            const float dy = (yi[k] + diy) - yjs;
-            const float dz = (zi[k] + diz) - zjs;
-            const float r2 = nb_r2(dx, dy, dz);
-            const bool inc = (r2 < fp.rc2) && ((mcol >> k) & 1u);
-            const float rinv = inc ? nb_rsq(r2) : 0.0f;
-            const float m1 = inc ? 1.0f : 0.0f;
-            const float rinv2 = rinv * rinv;
-            const float rinv4 = rinv2 * rinv2;
-            const float rinv6 = rinv4 * rinv2;
-            const float4 lj = tab[2 * (ti[k] + tj)];       // (C6, C12, 6 C6, 12 C12)
-            const float4 lj2 = tab[2 * (ti[k] + tj) + 1];  // (shift, 1/sigma_ab, -, -)
-            const float ddx = gxi[k] - gj.x, ddy = gyi[k] - gj.y, ddz = gzi[k] - gj.z;
-            const float dd = __builtin_fmaf(dz, ddz, __builtin_fmaf(dy, ddy, dx * ddx));
-            // Lennard-Jones
-            const float tf = __builtin_fmaf(lj.w, rinv6, -lj.z);      // 12 C12 r^-6 - 6 C6
-            const float flj = tf * rinv6 * rinv2;                      // force factor
-            const float dflj = __builtin_fmaf(-14.0f * lj.w, rinv6, 8.0f * lj.z) * rinv6 * rinv4;
-            // Ewald real space
-            const float r = r2 * rinv;
-            const float ex = __builtin_amdgcn_exp2f(fp.cexp * r2);
-            float P = fp.p[4];
-            P = __builtin_fmaf(P, r, fp.p[3]);
-            P = __builtin_fmaf(P, r, fp.p[2]);
-            P = __builtin_fmaf(P, r, fp.p[1]);
-            P = __builtin_fmaf(P, r, fp.p[0]);
-            float Q = fp.q[5];
-            Q = __builtin_fmaf(Q, r, fp.q[4]);
-            Q = __builtin_fmaf(Q, r, fp.q[3]);
-            Q = __builtin_fmaf(Q, r, fp.q[2]);
-            Q = __builtin_fmaf(Q, r, fp.q[1]);
-            Q = __builtin_fmaf(Q, r, fp.q[0]);
-            const float R = P * nb_rcp(Q);             // erfcx(b r)
-            const float fe = fp.fc * ex * rinv;                        // fC e^{-b^2r^2} / r
-            const float H = fe * __builtin_fmaf(fp.kb, r, R) * rinv2;  // fC h(r)
-            const float G = __builtin_fmaf(fe, R, -m1 * fp.fc * fp.shc);  // fC g(r)
-            // d/dr of fC h(r), divided by r
-            const float dH = -fe * rinv4 *
-                             __builtin_fmaf(fp.kb * r, __builtin_fmaf(2.0f * fp.b2, r2, 3.0f), 3.0f * R);
-            const float qq = qi[k] * qj;
-            const float fcl = qq * H;
-            const float f = flj + fcl;
-            const float dfr = dflj + qq * dH;
-            const float coef = __builtin_fmaf(dfr, dd, -__builtin_fmaf(s_lj, flj, s_c * fcl));
-            const float vx = __builtin_fmaf(f, ddx, coef * dx);
-            const float vy = __builtin_fmaf(f, ddy, coef * dy);
-            const float vz = __builtin_fmaf(f, ddz, coef * dz);
-            const float A = __builtin_fmaf(H, dd, s_c * G);
-            // LJ parameters
-            const float r8 = rinv6 * rinv2;
-            const float G6 = -6.0f * r8 * dd - s_lj * (rinv6 - m1 * fp.irc6);
-            const float G12 = 12.0f * r8 * rinv6 * dd + s_lj * (rinv6 * rinv6 - m1 * fp.irc12);
-            const float u = __builtin_fmaf(G6, lj.x, G12 * lj.y);
-            const float w = __builtin_fmaf(G6, lj.z, G12 * lj.w) * lj2.y;
-            ax[k] += vx;
-            ay[k] += vy;
-            az[k] += vz;
-            aq[k] = __builtin_fmaf(qj, A, aq[k]);
-            au[k] += u;
-            aw[k] += w;
-            jx -= vx;
-            jy -= vy;
-            jz -= vz;
-            jq = __builtin_fmaf(qi[k], A, jq);
-            ju += u;
-            jw += w;
+        for (int h = 0; h < C / NB_ADJ_HALF; ++h) {
+            // ---- filter: the lane's pairs with the half's i-atoms; interacting ones queued
+#pragma unroll
+            for (int a = 0; a < 6; ++a)
+#pragma unroll
+                for (int kk = 0; kk < NB_ADJ_HALF; ++kk) w.out[a][kk * NB_WAVE + lane] = 0.0f;
+            int nq = 0;
+#pragma unroll
+            for (int kk = 0; kk < NB_ADJ_HALF; ++kk) {
+                const int k = h * NB_ADJ_HALF + kk;
+                const float dx = (xi[k] + dix) - xjs;
+                const float dy = (yi[k] + diy) - yjs;
+                const float dz = (zi[k] + diz) - zjs;
+                const float r2 = nb_r2(dx, dy, dz);
+                const bool inr = r2 < fp.rc2, inm = ((mcol >> k) & 1u) != 0u;
+                const unsigned long long bal =
+                    __builtin_amdgcn_ballot_w64(inr) & __builtin_amdgcn_ballot_w64(inm);
+                uint32_t qb = recb + 16u * (uint32_t)nq;
+                asm("" : "+s"(qb));
+                if (inr && inm) {
+                    const uint32_t pos = __builtin_amdgcn_mbcnt_hi((unsigned)(bal >> 32),
+                                                                   __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
+                    nb_lput<float4>(qb + 16u * pos, make_float4(dx, dy, dz, __uint_as_float(pci[k] + pcj)));
+                }
+                nq += __popcll(bal);
+            }
+            nb_wave_lds_sync();
+            // ---- evaluate: the queued pairs, one per lane
+            const int i0 = h * NB_ADJ_HALF;
+            auto evaluate = [&](uint32_t qa) {
+                const float4 rr = nb_lget<float4>(qa);
+                const uint32_t code = __float_as_uint(rr.w);
+                const uint32_t ta = code >> NB_ADJ_ROW;
+                const float4 lj = nb_lget<float4>(ta);         // (C6, C12, 6 C6, 12 C12)
+                const float4 lj2 = nb_lget<float4>(ta + 16u);  // (shift, 1/sigma_ab, -, -)
+                const uint32_t kk = (code >> 8) & (NB_ADJ_HALF - 1);
+                const float4 ip = w.id[i0 + kk];
+                const float4 igk = w.ig[i0 + kk];
+                const float4 jgl = nb_lget<float4>(nb_laddr(&w.jg[0]) + ((code & 0xFCu) << 2));
+                const float dx = rr.x, dy = rr.y, dz = rr.z;
+                const float r2 = nb_r2(dx, dy, dz);
+                const float rinv = nb_rsq(r2);
+                const float rinv2 = rinv * rinv;
+                const float rinv4 = rinv2 * rinv2;
+                const float rinv6 = rinv4 * rinv2;
+                const float ddx = igk.x - jgl.x, ddy = igk.y - jgl.y, ddz = igk.z - jgl.z;
+                const float dd = __builtin_fmaf(dz, ddz, __builtin_fmaf(dy, ddy, dx * ddx));
+                // Lennard-Jones
+                const float tf = __builtin_fmaf(lj.w, rinv6, -lj.z);      // 12 C12 r^-6 - 6 C6
+                const float flj = tf * rinv6 * rinv2;                      // force factor
+                const float dflj = __builtin_fmaf(-14.0f * lj.w, rinv6, 8.0f * lj.z) * rinv6 * rinv4;
+                // Ewald real space
+                const float r = r2 * rinv;
+                const float ex = __builtin_amdgcn_exp2f(fp.cexp * r2);
+                float P = fp.p[4];
+                P = __builtin_fmaf(P, r, fp.p[3]);
+                P = __builtin_fmaf(P, r, fp.p[2]);
+                P = __builtin_fmaf(P, r, fp.p[1]);
+                P = __builtin_fmaf(P, r, fp.p[0]);
+                float Q = fp.q[5];
+                Q = __builtin_fmaf(Q, r, fp.q[4]);
+                Q = __builtin_fmaf(Q, r, fp.q[3]);
+                Q = __builtin_fmaf(Q, r, fp.q[2]);
+                Q = __builtin_fmaf(Q, r, fp.q[1]);
+                Q = __builtin_fmaf(Q, r, fp.q[0]);
+                const float R = P * nb_rcp(Q);             // erfcx(b r)
+                const float fe = fp.fc * ex * rinv;                        // fC e^{-b^2r^2} / r
+                const float H = fe * __builtin_fmaf(fp.kb, r, R) * rinv2;  // fC h(r)
+                const float G = __builtin_fmaf(fe, R, -fp.fc * fp.shc);    // fC g(r)
+                // d/dr of fC h(r), divided by r
+                const float dH = -fe * rinv4 *
+                                 __builtin_fmaf(fp.kb * r, __builtin_fmaf(2.0f * fp.b2, r2, 3.0f), 3.0f * R);
+                const float qq = ip.w * jgl.w;
+                const float fcl = qq * H;
+                const float f = flj + fcl;
+                const float dfr = dflj + qq * dH;
+                const float coef = __builtin_fmaf(dfr, dd, -__builtin_fmaf(s_lj, flj, s_c * fcl));
+                const float vx = __builtin_fmaf(f, ddx, coef * dx);
+                const float vy = __builtin_fmaf(f, ddy, coef * dy);
+                const float vz = __builtin_fmaf(f, ddz, coef * dz);
+                const float A = __builtin_fmaf(H, dd, s_c * G);
+                // LJ parameters
+                const float r8 = rinv6 * rinv2;
+                const float G6 = -6.0f * r8 * dd - s_lj * (rinv6 - fp.irc6);
+                const float G12 = 12.0f * r8 * rinv6 * dd + s_lj * (rinv6 * rinv6 - fp.irc12);
+                const float u = __builtin_fmaf(G6, lj.x, G12 * lj.y);
+                const float wv6 = __builtin_fmaf(G6, lj.z, G12 * lj.w) * lj2.y;
+                const uint32_t o = out0 + (code & 0x3FCu);
+                nb_lput<float>(o, vx);
+                nb_lput<float>(o + 4u * NB_ADJ_SLOTS, vy);
+                nb_lput<float>(o + 8u * NB_ADJ_SLOTS, vz);
+                nb_lput<float>(o + 12u * NB_ADJ_SLOTS, A);
+                nb_lput<float>(o + 16u * NB_ADJ_SLOTS, u);
+                nb_lput<float>(o + 20u * NB_ADJ_SLOTS, wv6);
+            };
+            uint32_t qa = recb + 16u * (uint32_t)lane;
+            for (int p = 0; p < (nq >> 6); ++p, qa += 16u * NB_WAVE) evaluate(qa);
+            if (lane < (nq & (NB_WAVE - 1))) evaluate(qa);
+            nb_wave_lds_sync();
+            // ---- accumulate: the terms of the lane's pairs of this half (zero where a pair does
+            // not interact), in i-atom order
+#pragma unroll
+            for (int kk = 0; kk < NB_ADJ_HALF; ++kk) {
+                const int k = h * NB_ADJ_HALF + kk;
+                const float vx = w.out[0][kk * NB_WAVE + lane], vy = w.out[1][kk * NB_WAVE + lane];
+                const float vz = w.out[2][kk * NB_WAVE + lane], A = w.out[3][kk * NB_WAVE + lane];
+                const float u = w.out[4][kk * NB_WAVE + lane], wv6 = w.out[5][kk * NB_WAVE + lane];
+                ax[k] += vx;
+                ay[k] += vy;
+                az[k] += vz;
+                aq[k] = __builtin_fmaf(qj, A, aq[k]);
+                au[k] += u;
+                aw[k] += wv6;
+                jx -= vx;
+                jy -= vy;
+                jz -= vz;
+                jq = __builtin_fmaf(qi[k], A, jq);
+                ju += u;
+                jw += wv6;
+            }
+            nb_wave_lds_sync();  // the next half rewrites the work area
         }
         // lanes without an interacting pair in this batch (all six sums zero) skip the atomics
         if (valid && (jx != 0.0f || jy != 0.0f || jz != 0.0f || jq != 0.0f || jw != 0.0f || ju != 0.0f)) {

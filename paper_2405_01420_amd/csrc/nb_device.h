@@ -67,6 +67,15 @@ __device__ __forceinline__ T nb_lget(uint32_t a) { return *(const T *)(const NB_
 template <class T>
 __device__ __forceinline__ void nb_lput(uint32_t a, const T &v) { *(T *)(NB_L T *)(size_t)a = v; }
 
+// Wave-local ordering of LDS writes before reads by other lanes of the same wavefront (the
+// hardware executes one wave's LDS instructions in order; this keeps the compiler from moving
+// them across).
+__device__ __forceinline__ void nb_wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // A value in a vector register that the compiler treats as unknown: bit masks used as VOP3
 // operands (which take no literal constant) stay in registers instead of splitting the op.
 __device__ __forceinline__ uint32_t nb_vreg(uint32_t v) {

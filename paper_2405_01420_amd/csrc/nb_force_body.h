@@ -54,15 +54,6 @@ __device__ __forceinline__ double nb_wave_sum_d(double v) {
     return v;
 }
 
-// Wave-local ordering of LDS writes before reads by other lanes of the same wavefront (the
-// hardware executes one wave's LDS instructions in order; this keeps the compiler from moving
-// them across).
-__device__ __forceinline__ void nb_wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // LDS work areas of the force body for the NW wavefronts of a workgroup, one part per wave in
 // every array.  RAWQ: the flavour needs the charges as loaded (exact FP64 products q_i q_j: FP64
 // pair energies, and the reaction-field shift weight).  The evaluate phase addresses fsb, jqf and
