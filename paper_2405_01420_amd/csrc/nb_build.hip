@@ -154,9 +154,11 @@ __global__ void k_scatter(int n, int npad_max, const int *__restrict__ col,
 }
 
 #define NB_COLSORT_THREADS 256
+#define NB_COLSORT_POS 512  // columns of at most this many atoms keep the slot positions in LDS
+static_assert(NB_COLSORT_POS == 2 * NB_COLSORT_THREADS, "the rank sort takes up to two atoms per thread");
 
 // One block per column: sort the column's atoms by (z, index) in LDS (by rank for columns of
-// at most one atom per thread, bitonic otherwise), then lay them out as clusters of C slots;
+// at most two atoms per thread, bitonic otherwise), then lay them out as clusters of C slots;
 // the tail of the last cluster is padding (perm = -1).  The block then writes the bounding
 // boxes of its clusters over their real atoms (from the slots it has just written), and the
 // column's z table: for every bin edge z_k = k / zinv, k = 0 .. nz, the number of its clusters
@@ -176,9 +178,9 @@ __global__ void __launch_bounds__(NB_COLSORT_THREADS) k_colsort(nb_geom g, const
                                                  int2 *__restrict__ colz, nb_meta *meta) {
     __shared__ unsigned long long key[NB_SORT_MAX];
     __shared__ float zlo[NB_SORT_MAX / C], zhi[NB_SORT_MAX / C];  // the clusters' z bounds
-    // columns of at most one atom per thread: the slots' positions (w = 1 for an atom, 0 for
-    // padding), from which the bounding boxes are formed
-    __shared__ float4 spos[NB_COLSORT_THREADS + C];
+    // the slots' positions (w = 1 for an atom, 0 for padding), from which the bounding boxes are
+    // formed, for columns of at most NB_COLSORT_POS + C slots
+    __shared__ float4 spos[NB_COLSORT_POS + C];
     const int c = blockIdx.x, tid = threadIdx.x;
     const int n = colcount[c], start = colstart[c];
     const int cl0 = colcl[c], nslot = (colcl[c + 1] - cl0) * C;
@@ -194,32 +196,49 @@ __global__ void __launch_bounds__(NB_COLSORT_THREADS) k_colsort(nb_geom g, const
     if (n > NB_SORT_MAX) {   // reported; the column's clusters are left empty
         if (tid == 0) atomicOr(&meta->flags, NB_F_COLUMN);
         for (int r = tid; r < nslot; r += blockDim.x) pad(cl0 * C + r);
-    } else if (n <= (int)blockDim.x) {
-        // one atom per thread: its place in the sorted column is the number of smaller keys
-        // (keys are distinct: the atom index is their low word), read from LDS as broadcasts
-        unsigned long long v = ~0ull;
-        int a = -1;
-        float4 pa = make_float4(0.0f, 0.0f, 0.0f, 1.0f);
-        if (tid < n) {
-            a = tmp[start + tid];
-            const float4 o = off[a];
-            pa.x = x[3 * a] + o.x;
-            pa.y = x[3 * a + 1] + o.y;
-            pa.z = x[3 * a + 2] + o.z;
-            float z = pa.z;
-            if (!(z > 0.0f)) z = 0.0f;
-            v = ((unsigned long long)__float_as_uint(z) << 32) | (unsigned)a;
-            key[tid] = v;
+    } else if (n <= 2 * (int)blockDim.x) {
+        // one or two atoms per thread: an atom's place in the sorted column is the number of
+        // smaller (z, index) keys (distinct: the atom index is their low word), read from LDS
+        // as broadcasts
+        const bool two = n > (int)blockDim.x;
+        unsigned long long v[2] = {~0ull, ~0ull};
+        int a[2] = {-1, -1};
+        float4 pa[2];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int idx = tid + j * (int)blockDim.x;
+            pa[j] = make_float4(0.0f, 0.0f, 0.0f, 1.0f);
+            if (idx < n) {
+                a[j] = tmp[start + idx];
+                const float4 o = off[a[j]];
+                pa[j].x = x[3 * a[j]] + o.x;
+                pa[j].y = x[3 * a[j] + 1] + o.y;
+                pa[j].z = x[3 * a[j] + 2] + o.z;
+                float z = pa[j].z;
+                if (!(z > 0.0f)) z = 0.0f;
+                v[j] = ((unsigned long long)__float_as_uint(z) << 32) | (unsigned)a[j];
+                key[idx] = v[j];
+            }
         }
         __syncthreads();
-        if (tid < n) {
-            int rank = 0;
-            for (int k = 0; k < n; ++k) rank += key[k] < v ? 1 : 0;
-            const int slot = cl0 * C + rank;
-            perm[slot] = a;
-            slot_of[a] = slot;
-            xs[slot] = pa;
-            spos[rank] = pa;
+        int rank[2] = {0, 0};
+        if (two) {
+            for (int k = 0; k < n; ++k) {
+                const unsigned long long kk = key[k];
+                rank[0] += kk < v[0] ? 1 : 0;
+                rank[1] += kk < v[1] ? 1 : 0;
+            }
+        } else {
+            for (int k = 0; k < n; ++k) rank[0] += key[k] < v[0] ? 1 : 0;
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            if (a[j] < 0) continue;
+            const int slot = cl0 * C + rank[j];
+            perm[slot] = a[j];
+            slot_of[a[j]] = slot;
+            xs[slot] = pa[j];
+            spos[rank[j]] = pa[j];
         }
         for (int r = n + tid; r < nslot; r += blockDim.x) {
             pad(cl0 * C + r);
@@ -257,32 +276,45 @@ __global__ void __launch_bounds__(NB_COLSORT_THREADS) k_colsort(nb_geom g, const
     __syncthreads();
     for (int r = tid; r < nslot; r += blockDim.x) {
         int slot = cl0 * C + r;
+        float4 pa = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         if (r < n) {
             int a = (int)(key[r] & 0xffffffffu);
             perm[slot] = a;
             slot_of[a] = slot;
             float4 o = off[a];
-            xs[slot] = make_float4(x[3 * a] + o.x, x[3 * a + 1] + o.y, x[3 * a + 2] + o.z, 1.0f);
+            pa = make_float4(x[3 * a] + o.x, x[3 * a + 1] + o.y, x[3 * a + 2] + o.z, 1.0f);
+            xs[slot] = pa;
         } else {
             pad(slot);
         }
+        if (r < NB_COLSORT_POS + C) spos[r] = pa;
     }
     }
     // the block's writes of perm, xs and spos are visible to the whole block after the barrier
     __syncthreads();
-    const bool lds_pos = n <= (int)blockDim.x;
+    // (larger columns read the slots back from memory, all C of a cluster at once)
+    const bool lds_pos = n <= NB_SORT_MAX && nslot <= NB_COLSORT_POS + C;
     for (int k = tid; k < nslot / C; k += blockDim.x) {
         const int cl = cl0 + k;
         float3 a = make_float3(3e38f, 3e38f, 3e38f), b = make_float3(-3e38f, -3e38f, -3e38f);
-        for (int r = 0; r < C; ++r) {
-            float4 p;
-            if (lds_pos) {
-                p = spos[k * C + r];
-                if (p.w == 0.0f) continue;
-            } else {
-                if (perm[cl * C + r] < 0) continue;
-                p = xs[cl * C + r];
+        float4 ps[C];
+        if (lds_pos) {
+#pragma unroll
+            for (int r = 0; r < C; ++r) ps[r] = spos[k * C + r];
+        } else {
+            int pr[C];
+#pragma unroll
+            for (int r = 0; r < C; ++r) {
+                pr[r] = perm[cl * C + r];
+                ps[r] = xs[cl * C + r];
             }
+#pragma unroll
+            for (int r = 0; r < C; ++r) ps[r].w = pr[r] < 0 ? 0.0f : 1.0f;
+        }
+#pragma unroll
+        for (int r = 0; r < C; ++r) {
+            const float4 p = ps[r];
+            if (p.w == 0.0f) continue;
             a.x = fminf(a.x, p.x);
             a.y = fminf(a.y, p.y);
             a.z = fminf(a.z, p.z);
