@@ -285,13 +285,15 @@ int nb_debug_pairs(nb_ctx *ctx, const float *x_dev, int64_t *pairs_host, int64_t
 /* List statistics of the current list (synchronises). */
 int nb_get_stats(nb_ctx *ctx, nb_stats *st);
 
-/* Kernel timing: with on != 0, the force kernel of every later nb_forces is dispatched with a HIP
- * event pair that its dispatch stamps with the kernel's start and end (hipExtLaunchKernel; a few
- * microseconds of host overhead per call; off by default; turning it on creates the events of
- * the first 1024 timed launches).
+/* Kernel timing: with every >= 1, the force kernel of every every-th later nb_forces call (the
+ * first, the (every+1)-th, ...; 1: all of them) is dispatched with a HIP event pair that its
+ * dispatch stamps with the kernel's start and end (hipExtLaunchKernel; a few microseconds of
+ * overhead per stamped call, on the device too: the calls in between run unstamped); every <= 0
+ * turns it off (the default).  Turning it on creates the events of the first 1024 timed
+ * launches and restarts the count.
  * nb_get_timing synchronises, returns the summed kernel time in milliseconds and the number of
  * timed launches since the last nb_get_timing, and resets both. */
-int nb_set_timing(nb_ctx *ctx, int on);
+int nb_set_timing(nb_ctx *ctx, int every);
 int nb_get_timing(nb_ctx *ctx, double *force_kernel_ms, int64_t *launches);
 
 /* Text of the last error on this context (never NULL; "" if none). */

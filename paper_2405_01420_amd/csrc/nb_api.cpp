@@ -664,12 +664,13 @@ static int forces_impl(nb_ctx *c, const float *x, const float *q, const int32_t 
     if (!c || !x || !q || !type || !f || !e) return fail(c, NB_ERR_ARG, "NULL argument");
     if (!c->have_list) return fail(c, NB_ERR_STATE, "nb_forces called before nb_pairlist");
     hipError_t err = hipSuccess;
+    const bool stamp = c->timing && (c->timing_count++ % c->timing_every) == 0;
     // a call that failed between its force kernel and its finalize may have left sums behind
     if (!c->fj_clean) err = hipMemsetAsync(c->fj, 0, sizeof(float) * 3 * (size_t)c->npad_max, c->stream);
     if (err == hipSuccess) err = nb_launch_pack(c, x, q, type);
     if (err == hipSuccess && c->pruned && (c->flags & NB_CHECK_STALE)) err = nb_launch_prune_check(c, x);
     c->fj_clean = false;
-    if (c->timing && err == hipSuccess) {
+    if (stamp && err == hipSuccess) {
         const size_t kMaxPairs = 4096;
         if (c->ev_used == kMaxPairs) {
             int r = drain_events(c);
@@ -685,9 +686,9 @@ static int forces_impl(nb_ctx *c, const float *x, const float *q, const int32_t 
     }
     // with timing on, the kernel's dispatch stamps an event pair with its own start and end
     if (err == hipSuccess)
-        err = nb_launch_force(c, vir != nullptr, c->timing ? c->ev[2 * c->ev_used] : nullptr,
-                              c->timing ? c->ev[2 * c->ev_used + 1] : nullptr);
-    if (c->timing && err == hipSuccess) c->ev_used += 1;
+        err = nb_launch_force(c, vir != nullptr, stamp ? c->ev[2 * c->ev_used] : nullptr,
+                              stamp ? c->ev[2 * c->ev_used + 1] : nullptr);
+    if (stamp && err == hipSuccess) c->ev_used += 1;
     if (err == hipSuccess && (c->flags & NB_EWALD_CORR)) err = nb_launch_ewald_corr(c, x, q);
     if (err == hipSuccess) err = nb_launch_finalize(c, f, e, vir);
     if (err != hipSuccess) return hip_fail(c, err, "force launch");
@@ -705,9 +706,11 @@ int nb_forces_virial(nb_ctx *c, const float *x, const float *q, const int32_t *t
     return forces_impl(c, x, q, type, f, e, vir);
 }
 
-int nb_set_timing(nb_ctx *c, int on) {
+int nb_set_timing(nb_ctx *c, int every) {
     if (!c) return fail(c, NB_ERR_ARG, "NULL context");
-    c->timing = on != 0;
+    c->timing = every > 0;
+    c->timing_every = every > 0 ? every : 1;
+    c->timing_count = 0;
     // event pairs for the first 1024 timed launches are created here, so that timed loops do
     // not create events
     hipSetDevice(c->device);

@@ -215,8 +215,10 @@ struct nb_ctx {
     float4 *gs = nullptr;       // [npad_max] force cotangents in cluster order
     double *tpart = nullptr;    // [adjoint type-sum blocks][ntypes][2] block partials
     double *mdpart = nullptr;   // [leapfrog blocks] kinetic-energy partials (allocated on first use)
-    // kernel timing
+    // kernel timing: every timing_every-th force launch (counted from nb_set_timing) is stamped
     bool timing = false;
+    int timing_every = 1;
+    int64_t timing_count = 0;
     std::vector<hipEvent_t> ev;  // pairs (start, stop)
     size_t ev_used = 0;          // pairs recorded
     double timed_ms = 0;

@@ -315,8 +315,9 @@ def nb_destroy(ctx: int) -> None:
     _check(lib().nb_destroy(ctx))
 
 
-def nb_set_timing(ctx: int, on: bool) -> None:
-    _check(lib().nb_set_timing(ctx, int(bool(on))), ctx)
+def nb_set_timing(ctx: int, every) -> None:
+    """Stamp every `every`-th force launch with a HIP event pair (True: all; False or 0: off)."""
+    _check(lib().nb_set_timing(ctx, int(every)), ctx)
 
 
 def nb_get_timing(ctx: int):

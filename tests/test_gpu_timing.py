@@ -1,37 +1,29 @@
-"""Kernel timing (nb_set_timing / nb_get_timing): with timing on, the force kernel is dispatched
-with an event pair that the dispatch stamps; the results are the same bits as without timing (the
-force sums are fixed point, the energies summed in a fixed order), every timed launch is counted,
-more launches than the event pairs created up front are handled, and reading the timing resets
-it."""
-import numpy as np
+"""Kernel timing through the C-ABI: every n-th force launch is stamped (nb_set_timing)."""
 import pytest
+import torch
 
 from paper_2405_01420_amd import nb, synth
-from tests.gpu_helpers import GpuBox
 
 pytestmark = pytest.mark.gpu
 
 
-def test_timing_counts_launches_and_keeps_results(torch_gpu):
+@pytest.mark.parametrize("every, calls, stamped", [(1, 5, 5), (3, 10, 4), (7, 7, 1), (0, 4, 0)])
+def test_every_nth_force_launch_is_stamped(every, calls, stamped):
     inst = synth.tiny()
-    box = GpuBox(torch_gpu, inst)
+    dev = "cuda:0"
+    x = torch.from_numpy(inst.x.reshape(-1).copy()).to(dev)
+    q = torch.from_numpy(inst.q.copy()).to(dev)
+    t = torch.from_numpy(inst.type.copy()).to(dev)
+    f = torch.zeros(3 * inst.natoms, dtype=torch.float32, device=dev)
+    e = torch.zeros(2, dtype=torch.float64, device=dev)
+    ctx = nb.nb_setup(nb.Params.from_instance(inst))
     try:
-        box.pairlist()
-        f0, e0 = box.forces()
-        nb.nb_set_timing(box.ctx, True)
-        ms, n = nb.nb_get_timing(box.ctx)
-        assert n == 0 and ms == 0.0
-        for _ in range(1100):  # more than the 1024 event pairs created when timing is turned on
-            nb.nb_forces(box.ctx, box.x, box.q, box.t, box.f, box.e)
-        f1, e1 = box.forces()  # one more timed launch
-        ms, n = nb.nb_get_timing(box.ctx)
-        print(f"timed launches {n}, mean {1e3 * ms / n:.2f} us", flush=True)
-        assert n == 1101 and ms > 0.0
-        assert np.array_equal(f0, f1) and np.array_equal(e0, e1)
-        ms, n = nb.nb_get_timing(box.ctx)
-        assert n == 0 and ms == 0.0
-        nb.nb_set_timing(box.ctx, False)
-        box.forces()
-        assert nb.nb_get_timing(box.ctx)[1] == 0
+        nb.nb_pairlist(ctx, x)
+        nb.nb_set_timing(ctx, every)
+        for _ in range(calls):
+            nb.nb_forces(ctx, x, q, t, f, e)
+        ms, n = nb.nb_get_timing(ctx)
+        assert n == stamped
+        assert (ms > 0.0) == (stamped > 0)
     finally:
-        box.close()
+        nb.nb_destroy(ctx)
