@@ -64,7 +64,7 @@ TIMING_EVERY = 7
 
 K_FORCE_COUNTERS = {
     "sources": ["nb_force_body.h", "nb_force.hip", "nb_device.h", "nb_internal.h", "erfcx_rational.h"],
-    "sha256": "4216f9c6ac55615d09af066e9b8a67eada0d89ff5ddf6120e2e18d8113225112",
+    "sha256": "a8cfcbb62e51c35b04a11acb9f01831835759d4908748dffda2944a03f1cd3f0",
     "read_bytes": 31.84e6, "write_bytes": 74.04e6,
     "counted_fp32_flop": 2580713401.7,
 }

@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstring>
 #include <vector>
 
 #include "erfcx_rational.h"
@@ -90,9 +91,19 @@ void lj_table(nb_ctx *c, std::vector<float4> &tab) {
             double c6 = 4.0 * e * s6, c12 = 4.0 * e * s6 * s6;
             float c6f = (float)c6, c12f = (float)c12;
             double sh = (double)c12f * irc12 - (double)c6f * irc6;
-            // two float4 per type pair, side by side: one address serves both LDS reads
+            // the FP64 shift of the FP64 pair energies: C12 k12 - C6 k6 with the kernels' FP64
+            // constants, rounded as a device fused multiply-add would round it
+            const double shd = std::fma((double)c12f, c->fp.lj_k12, -((double)c6f * c->fp.lj_k6));
+            unsigned long long bits;
+            std::memcpy(&bits, &shd, sizeof(bits));
+            // two float4 per type pair, side by side: one address serves both LDS reads;
+            // (C6, C12, 6 C6, 12 C12), (shift, 1 / sigma_ab, FP64 shift as two words)
             tab[2 * (a * nt + b)] = make_float4(c6f, c12f, (float)(6.0 * c6), (float)(12.0 * c12));
-            tab[2 * (a * nt + b) + 1] = make_float4((float)sh, s > 0.0 ? (float)(1.0 / s) : 0.0f, 0.0f, 0.0f);
+            float lo, hi;
+            const uint32_t wlo = (uint32_t)bits, whi = (uint32_t)(bits >> 32);
+            std::memcpy(&lo, &wlo, sizeof(lo));
+            std::memcpy(&hi, &whi, sizeof(hi));
+            tab[2 * (a * nt + b) + 1] = make_float4((float)sh, s > 0.0 ? (float)(1.0 / s) : 0.0f, lo, hi);
         }
 }
 

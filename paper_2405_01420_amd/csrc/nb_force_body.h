@@ -38,6 +38,8 @@
 //    an energy that is a 1e-4 .. 1e-3-conditioned sum, in boxes of a few thousand atoms.  The
 //    FP64 work runs in the evaluate phase, i.e. on interacting pairs only.
 #pragma once
+#include <type_traits>
+
 #include "nb_device.h"
 
 // Four waves per SIMD (at most 128 VGPRs) for the FP32-energy force kernels; the FP64-energy
@@ -68,7 +70,8 @@ struct nb_wg_lds {
     float jqf[NW][NB_WAVE];         // per j lane: fC NB_FSCALE q_j
     float4 id[NW][C];               // per i-atom: (x, y, z, q) as loaded (unshifted)
     uint2 q[NW][C * NB_WAVE];       // the batch's interacting pairs: (r^2 bits, pair code)
-    float jq[NW][RAWQ ? NB_WAVE : 1];  // per j lane: q_j as loaded
+    // per j lane: q_j as loaded, exactly in FP64 (a placeholder word where unused)
+    typename std::conditional<RAWQ, double, float>::type jq[NW][RAWQ ? NB_WAVE : 1];
     // FP64-energy mode, per j lane: x_j + dj - di in FP64 (exact), x, y and z in rows of 64, so
     // that x_i - (x_j + dj - di) is the exact displacement of the pair
     double jx[NW][EPREC ? 3 * NB_WAVE : 1];
@@ -133,7 +136,8 @@ __device__ __forceinline__ double nb_erfc_tab(const nb_etab &et, float r, double
 }
 
 // Scalar force factor fs (F_ij = fs d) and the energies of one interacting pair at squared
-// distance r2 with qq = fC q_i q_j and the LJ row lj (C6, C12, 6 C6, 12 C12) and shift shv.  The
+// distance r2 with qq = fC q_i q_j and the LJ row lj (C6, C12, 6 C6, 12 C12) and shift shv (shd:
+// the row's FP64 shift, used with EPREC).  The
 // FP32 pair energies (the Ewald one shifted) are added to the FP64 sums elj / ec one pair at a
 // time; the reaction field adds its shift weight as exact FP64 products qqd = q_i q_j to qqsd;
 // with EPREC the FP64 energies of the pair, computed from the exact displacement (dxd, dyd,
@@ -141,8 +145,9 @@ __device__ __forceinline__ double nb_erfc_tab(const nb_etab &et, float r, double
 template <bool EPREC, int FLAV>
 __device__ __forceinline__ float pair_eval(const nb_fparams &fp, const nb_etab &et, float r2,
                                            float qq, double qqd, const float4 &lj, float shv,
-                                           double dxd, double dyd, double dzd, double &elj, double &ec,
-                                           double &qqsd, float p4v, float q5v) {
+                                           double shd, double dxd, double dyd, double dzd,
+                                           double &elj, double &ec, double &qqsd, float p4v,
+                                           float q5v) {
     constexpr bool RF = FLAV / 2 == NB_ELEC_RF;
     constexpr bool TAB = FLAV / 2 == NB_ELEC_EWALD_TAB;
     constexpr bool FSW = FLAV % 2 == NB_VDW_FSWITCH;
@@ -166,8 +171,7 @@ __device__ __forceinline__ float pair_eval(const nb_fparams &fp, const nb_etab &
         // Lennard-Jones pair energy in FP64 (C6, C12 are the FP32 instance values)
         const double c6d = lj.x, c12d = lj.y;
         const double rid2 = rid * rid, rid6 = rid2 * rid2 * rid2;
-        double el = __builtin_fma(__builtin_fma(c12d, rid6, -c6d), rid6,
-                                  -__builtin_fma(c12d, fp.lj_k12, -c6d * fp.lj_k6));
+        double el = __builtin_fma(__builtin_fma(c12d, rid6, -c6d), rid6, -shd);
         if (FSW) {
             const double td = fmax(r2d * rid - fp.sw_r1_d, 0.0);
             const double e12 = __builtin_fma(fp.sw_eb12_d, td, fp.sw_ea12_d);
@@ -454,7 +458,7 @@ __device__ __forceinline__ nb_esum nb_force_cluster(const nb_fparams &fp, const 
         }
         nb_wave_lds_sync();  // the previous batch's reads of the work area are done
         jqfp[lane] = xj.w * fp.fcs;
-        if (RAWQ) nb_lput<float>(w.jq + lane4, xj.w);
+        if (RAWQ) nb_lput<double>(w.jq + 2u * lane4, (double)xj.w);
         if (EPREC) {
             // x_j + dj (FP32, exact) minus the i-frame offset: exact in FP64
             nb_lput<double>(w.jx + 2u * lane4, (double)jx - (double)dix);
@@ -507,12 +511,14 @@ __device__ __forceinline__ nb_esum nb_force_cluster(const nb_fparams &fp, const 
             const uint32_t ta = code >> NB_PC_ROW;  // the pair's LJ row
             const float4 lj = nb_lget<float4>(ta);
             const float shv = nb_lget<float>(ta + 16u);
+            // the row's FP64 potential shift (FP64 pair energies only)
+            const double shd = EPREC ? nb_lget<double>(ta + 24u) : 0.0;
             const uint32_t ia = ((code >> 4) & mid) | w.id;  // its i-atom's (x, y, z, q)
             const uint32_t jo = code & mjqf;                // 4 x its j lane
             const float qi = nb_lget<float>(ia + 12u);
             const float qq = qi * nb_lget<float>(jo | w.jqf);
             double qqd = 0.0, dxd = 0.0, dyd = 0.0, dzd = 0.0;
-            if (RAWQ) qqd = (double)qi * (double)nb_lget<float>(w.jq + jo);
+            if (RAWQ) qqd = (double)qi * nb_lget<double>(w.jq + 2u * jo);
             if (EPREC) {
                 // exact displacement: x_i - (x_j + dj - di), both terms exact in FP64 and their
                 // difference too (a few tens of significant bits at most)
@@ -522,7 +528,7 @@ __device__ __forceinline__ nb_esum nb_force_cluster(const nb_fparams &fp, const 
                 dyd = (double)idk.y - nb_lget<double>(ja + 8u * NB_WAVE);
                 dzd = (double)idk.z - nb_lget<double>(ja + 16u * NB_WAVE);
             }
-            const float fs = pair_eval<EPREC, FLAV>(fp, et, __uint_as_float(qe.x), qq, qqd, lj, shv,
+            const float fs = pair_eval<EPREC, FLAV>(fp, et, __uint_as_float(qe.x), qq, qqd, lj, shv, shd,
                                                     dxd, dyd, dzd, elj, ec, qqsd,
                                                     p4v, q5v);
             nb_lput<float>((code & mfsb) | w.fsb, fs);

@@ -112,7 +112,8 @@ struct nb_fparams {
     float cexp;         // -beta^2 log2(e):  exp(-beta^2 r^2) = exp2(cexp r^2)
     float kb;           // 2 beta / sqrt(pi)
     // LJ table in LDS/global: per type pair (a * ntypes + b) two float4,
-    // (C6, C12, 6 C6, 12 C12) and (potential shift, 1 / sigma_ab, 0, 0)
+    // (C6, C12, 6 C6, 12 C12) and (potential shift, 1 / sigma_ab, FP64 potential shift as two
+    // words: C12 lj_k12 - C6 lj_k6, for FP64 pair energies)
     float p[5];         // erfcx numerator coefficients scaled by beta^k (argument r)
     float q[6];         // erfcx denominator coefficients scaled by beta^k
     float b2;           // beta^2
