@@ -245,12 +245,16 @@ __global__ void __launch_bounds__(256) k_adjoint(nb_fparams fp, const double *__
             }
             nb_wave_lds_sync();  // the next half rewrites the work area
         }
-        // lanes without an interacting pair in this batch (all six sums zero) skip the atomics
-        if (valid && (jx != 0.0f || jy != 0.0f || jz != 0.0f || jq != 0.0f || jw != 0.0f || ju != 0.0f)) {
+        // lanes without an interacting pair in this batch skip the atomics, and lanes whose
+        // LJ-parameter sums are zero (atoms of a type without LJ, such as water hydrogens) skip
+        // those two
+        if (valid && (jx != 0.0f || jy != 0.0f || jz != 0.0f || jq != 0.0f)) {
             atomicAdd(&adjj[jslot], jx);
             atomicAdd(&adjj[npad_max + jslot], jy);
             atomicAdd(&adjj[2 * npad_max + jslot], jz);
             atomicAdd(&adjj[3 * npad_max + jslot], jq);
+        }
+        if (valid && (jw != 0.0f || ju != 0.0f)) {
             atomicAdd(&adjj[4 * npad_max + jslot], jw);
             atomicAdd(&adjj[5 * npad_max + jslot], ju);
         }

@@ -38,8 +38,6 @@
 //    an energy that is a 1e-4 .. 1e-3-conditioned sum, in boxes of a few thousand atoms.  The
 //    FP64 work runs in the evaluate phase, i.e. on interacting pairs only.
 #pragma once
-#include <type_traits>
-
 #include "nb_device.h"
 
 // Four waves per SIMD (at most 128 VGPRs) for the FP32-energy force kernels; the FP64-energy
@@ -70,8 +68,7 @@ struct nb_wg_lds {
     float jqf[NW][NB_WAVE];         // per j lane: fC NB_FSCALE q_j
     float4 id[NW][C];               // per i-atom: (x, y, z, q) as loaded (unshifted)
     uint2 q[NW][C * NB_WAVE];       // the batch's interacting pairs: (r^2 bits, pair code)
-    // per j lane: q_j as loaded, exactly in FP64 (a placeholder word where unused)
-    typename std::conditional<RAWQ, double, float>::type jq[NW][RAWQ ? NB_WAVE : 1];
+    float jq[NW][RAWQ ? NB_WAVE : 1];  // per j lane: q_j as loaded
     // FP64-energy mode, per j lane: x_j + dj - di in FP64 (exact), x, y and z in rows of 64, so
     // that x_i - (x_j + dj - di) is the exact displacement of the pair
     double jx[NW][EPREC ? 3 * NB_WAVE : 1];
@@ -458,7 +455,7 @@ __device__ __forceinline__ nb_esum nb_force_cluster(const nb_fparams &fp, const 
         }
         nb_wave_lds_sync();  // the previous batch's reads of the work area are done
         jqfp[lane] = xj.w * fp.fcs;
-        if (RAWQ) nb_lput<double>(w.jq + 2u * lane4, (double)xj.w);
+        if (RAWQ) nb_lput<float>(w.jq + lane4, xj.w);
         if (EPREC) {
             // x_j + dj (FP32, exact) minus the i-frame offset: exact in FP64
             nb_lput<double>(w.jx + 2u * lane4, (double)jx - (double)dix);
@@ -518,7 +515,7 @@ __device__ __forceinline__ nb_esum nb_force_cluster(const nb_fparams &fp, const 
             const float qi = nb_lget<float>(ia + 12u);
             const float qq = qi * nb_lget<float>(jo | w.jqf);
             double qqd = 0.0, dxd = 0.0, dyd = 0.0, dzd = 0.0;
-            if (RAWQ) qqd = (double)qi * nb_lget<double>(w.jq + 2u * jo);
+            if (RAWQ) qqd = (double)qi * (double)nb_lget<float>(w.jq + jo);
             if (EPREC) {
                 // exact displacement: x_i - (x_j + dj - di), both terms exact in FP64 and their
                 // difference too (a few tens of significant bits at most)
