@@ -64,7 +64,7 @@ TIMING_EVERY = 7
 
 K_FORCE_COUNTERS = {
     "sources": ["nb_force_body.h", "nb_force.hip", "nb_device.h", "nb_internal.h", "erfcx_rational.h"],
-    "sha256": "86a511767cbf2fb35c6ea50e5f45dc6026438930dcd321c3b5c0b86e2dd55553",
+    "sha256": "d08835ff78032cc6dc476a7dc3da28a31d9828b70befb723d26c3a002154ea71",
     "read_bytes": 31.84e6, "write_bytes": 74.04e6,
     "counted_fp32_flop": 2580713401.7,
 }

@@ -62,10 +62,10 @@ __device__ __forceinline__ double wave_sum(double v) {
 // One work unit per wave, NB_FORCE_WAVES consecutive units per workgroup (neighbouring waves work
 // on neighbouring clusters, whose j-atoms they share in the caches).  The energy sums of the
 // workgroup's waves are combined in LDS by whichever wave finishes last, in wave order, and
-// stored as the workgroup's partial (epart[4 blockIdx ..], virial vpart[6 blockIdx ..]; zeros from
-// workgroups without a unit); waves do not wait for each other.  (Workgroups that take several units in turn, statically or from a
-// shared counter, were measured slower: the former coarsen the tail of the launch, the latter
-// serialise on the counter's atomics.)
+// stored as the workgroup's partial (epart[4 blockIdx ..], virial vpart[6 blockIdx ..]; zeros
+// from workgroups without a unit); waves do not wait for each other.  (Workgroups that take
+// several units in turn, statically or from a shared counter, were measured slower: the former
+// coarsen the tail of the launch, the latter serialise on the counter's atomics.)
 #define NB_FORCE_WAVES 4
 
 template <int C, bool EPREC, int FLAV, bool VIR>
@@ -86,7 +86,8 @@ __global__ void __launch_bounds__(NB_FORCE_WAVES * NB_WAVE) NB_FORCE_OCCUPANCY_V
     __shared__ int edone;
     const int nunits = meta->nunits;
     if (blockIdx.x * NB_FORCE_WAVES >= nunits) {
-        // an idle workgroup: zero partials, so that the finalize can sum every workgroup's
+        // an idle workgroup writes zero partials, so that the finalize can sum every
+        // workgroup's row
         if (threadIdx.x < 4) epart[4 * blockIdx.x + threadIdx.x] = 0.0;
         if (VIR && threadIdx.x < 6) vpart[6 * blockIdx.x + threadIdx.x] = 0.0;
         return;
