@@ -182,6 +182,8 @@ def test_null_handles_are_rejected_without_gpu():
     assert L.nb_pme_forces(None, None, None, None, None) == nb.NB_ERR_ARG
     assert L.nb_batch_tune_schedule(None, None, None, None, None, None, 1, None, None) == nb.NB_ERR_ARG
     assert L.nb_backward_noalloc(None, None, None, None, None, None, None, None, None, None) == nb.NB_ERR_ARG
+    assert L.nb_set_timing(None, 7) == nb.NB_ERR_ARG
+    assert L.nb_get_timing(None, None, None) == nb.NB_ERR_ARG
 
 
 def test_autotune_rejects_bad_arguments_and_cache_without_gpu(tmp_path):
