@@ -763,26 +763,26 @@ __global__ void __launch_bounds__(NB_UNITS_THREADS) k_units(int slots, int unit_
     } else {
         // per cost class: the units before the chunk and all units (a cluster's units are all
         // of length pc but the last)
-        int hb[2][NB_HIST_BINS];
-#pragma unroll
-        for (int b = 0; b < NB_HIST_BINS; ++b) hb[0][b] = hb[1][b] = 0;
+        int hb[NB_HIST_BINS], ha[NB_HIST_BINS];  // before the chunk, all (selects on the values,
+#pragma unroll                                // so that both stay in registers)
+        for (int b = 0; b < NB_HIST_BINS; ++b) hb[b] = ha[b] = 0;
         pass(ncl, [&](int c, int nb) {
             if (nb <= 0) return;
             const int nu = nunits_of(c, nb), pc = pmax(c, nb);
             const int kf = nb_cost_class(pc), kl = nb_cost_class(nb - (nu - 1) * pc);
-            const int w = c < lo ? 0 : 1;
+            const bool before = c < lo;
 #pragma unroll
             for (int b = 0; b < NB_HIST_BINS; ++b) {
                 const int add = (b == kf ? nu - 1 : 0) + (b == kl ? 1 : 0);
-                hb[1][b] += add;
-                if (w == 0) hb[0][b] += add;
+                ha[b] += add;
+                hb[b] += before ? add : 0;
             }
         });
 #pragma unroll
         for (int b = 0; b < NB_HIST_BINS; ++b) {
 #pragma unroll
             for (int w = 0; w < 2; ++w) {
-                int v = hb[w][b];
+                int v = w == 0 ? hb[b] : ha[b];
 #pragma unroll
                 for (int o = NB_WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, NB_WAVE);
                 if (lane == 0 && v) atomicAdd(&s_cnt[w][b], v);
