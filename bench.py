@@ -730,14 +730,17 @@ def main():
             else:
                 us_e64, kernel_us_e64 = us_call, 1e3 * kms_t / kl_t
 
-    # list build alone (each build waits for the previous one's status)
+    # list build alone: each build waits for the previous one's status, so the interval between
+    # the returns of successive calls spans one build; median and IQR of those intervals (the
+    # host's wait varies from build to build)
     torch.cuda.synchronize()
-    tb = time.perf_counter()
-    nbuild = 20
-    for k in range(nbuild):
+    nbuild = 60
+    stamps = []
+    for k in range(nbuild + 1):
         nb.nb_pairlist(ctx, traj[k % len(traj)])
+        stamps.append(time.perf_counter())
     torch.cuda.synchronize()
-    us_build = 1e6 * (time.perf_counter() - tb) / nbuild
+    b25, us_build, b75 = (float(v) for v in np.percentile(1e6 * np.diff(stamps), [25, 50, 75]))
 
     achieved = flops_per_pair * useful / (kernel_us * 1e-6) / 1e12
     traffic = counted = None
@@ -779,6 +782,7 @@ def main():
                                                            "kernel_us": kernel_us_tab,
                                                            "energy_gate": "1e-6 at every size"}},
         "us_per_list_build": us_build,
+        "us_per_list_build_iqr": [b25, b75],
         "us_per_call_amortised": 1e3 * ms_per_step,
         "rebuild_periods": period_stats,
         "rolling_prune": prune,
