@@ -1,0 +1,73 @@
+"""The smallest systems the method accepts, through the C-ABI: one atom (no pair: zero forces and
+energies, an empty pair set), two atoms inside the cutoff (directly and across a periodic face),
+two atoms beyond it, an excluded pair, and a pair whose type has no Lennard-Jones term and no
+charge.  Such boxes leave most columns of the grid empty and hold a single cluster.  Forces and
+energies are compared with the oracle (interacting pairs) or are exactly zero (no pair)."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2405_01420_amd import nb, synth
+from tests.gpu_helpers import ENERGY_TOL, FORCE_TOL, GpuBox, rel_rms
+
+pytestmark = pytest.mark.gpu
+
+L, RC, RB = 2.5, 0.9, 0.1
+SIGMA = np.array([0.3166, 0.0])   # an oxygen-like type and a null type (no LJ)
+EPS = np.array([0.65, 0.0])
+
+
+def make(x, q, types, excl=()):
+    n = len(q)
+    partners = [[] for _ in range(n)]
+    for a, b in excl:
+        partners[a].append(b)
+        partners[b].append(a)
+    off = np.zeros(n + 1, dtype=np.int32)
+    off[1:] = np.cumsum([len(p) for p in partners])
+    idx = np.array([b for p in partners for b in sorted(p)], dtype=np.int32)
+    return synth.Instance(x=np.asarray(x, dtype=np.float32).reshape(n, 3),
+                          q=np.asarray(q, dtype=np.float32), type=np.asarray(types, dtype=np.int32),
+                          box=synth.f32(L), cutoff=synth.f32(RC), buffer=synth.f32(RB),
+                          beta=synth.ewald_beta(RC), coulomb_const=synth.f32(138.935458),
+                          sigma=SIGMA.copy(), epsilon=EPS.copy(), excl_off=off, excl_idx=idx,
+                          name="degenerate")
+
+
+CASES = {
+    "one_atom": (make([[1.2, 0.7, 2.1]], [0.8], [0]), False),
+    "pair_inside": (make([[0.6, 1.1, 1.3], [1.05, 1.3, 1.5]], [0.8, -0.8], [0, 0]), True),
+    "pair_across_face": (make([[0.1, 1.2, 0.8], [2.25, 1.3, 0.7]], [0.8, -0.4], [0, 0]), True),
+    "pair_beyond_cutoff": (make([[0.3, 0.3, 0.3], [1.25, 0.3, 0.3]], [0.8, -0.8], [0, 0]), False),
+    "pair_excluded": (make([[0.6, 1.1, 1.3], [0.7, 1.1, 1.3]], [0.8, -0.8], [0, 0], excl=[(0, 1)]),
+                      False),
+    "pair_null_type": (make([[0.6, 1.1, 1.3], [0.9, 1.2, 1.3]], [0.0, 0.0], [1, 1]), False),
+}
+
+
+@pytest.mark.parametrize("cluster", [8, 4])
+@pytest.mark.parametrize("flags", [0, nb.NB_ENERGY_FP64])
+@pytest.mark.parametrize("name", list(CASES))
+def test_smallest_systems(torch_gpu, name, cluster, flags):
+    inst, interacting = CASES[name]
+    print(f"case {name} C={cluster} flags={flags}", flush=True)
+    box = GpuBox(torch_gpu, inst, cluster=cluster, flags=flags)
+    try:
+        box.pairlist()
+        f, e = box.forces()
+        pairs = np.asarray(box.pairs(), dtype=np.int64).reshape(-1, 2)
+        assert nb.nb_check(box.ctx) == nb.NB_OK
+    finally:
+        box.close()
+    pi, pj, _ = O.pairs(inst.x, inst.box, inst.cutoff, inst.excl_off, inst.excl_idx)
+    assert sorted(map(tuple, pairs.tolist())) == sorted(zip(pi.tolist(), pj.tolist()))
+    if not interacting:   # (the null-type pair is in the pair set, with zero force and energy)
+        assert np.all(f == 0.0) and e[0] == 0.0 and e[1] == 0.0
+        return
+    ref = O.instance_forces(inst, cells=False)
+    fr = rel_rms(f, ref.f)
+    elj = abs(e[0] - ref.e_lj) / abs(ref.e_lj)
+    ec = abs(e[1] - ref.e_coul) / abs(ref.e_coul)
+    print(f"force relRMS {fr:.2e} E_LJ rel {elj:.2e} E_C rel {ec:.2e}", flush=True)
+    assert fr <= FORCE_TOL and elj <= ENERGY_TOL and ec <= ENERGY_TOL
+    assert np.abs(f.sum(0)).max() <= 1e-6 * np.abs(f).max()  # the two forces cancel
