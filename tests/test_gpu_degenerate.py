@@ -71,3 +71,48 @@ def test_smallest_systems(torch_gpu, name, cluster, flags):
     print(f"force relRMS {fr:.2e} E_LJ rel {elj:.2e} E_C rel {ec:.2e}", flush=True)
     assert fr <= FORCE_TOL and elj <= ENERGY_TOL and ec <= ENERGY_TOL
     assert np.abs(f.sum(0)).max() <= 1e-6 * np.abs(f).max()  # the two forces cancel
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_smallest_systems_in_a_batch(torch_gpu, graph):
+    """The same boxes between two water boxes in one batched launch (FP64 pair energies, the
+    mode gated at 1e-6 on small boxes): each box's forces and energies against the oracle, or
+    exactly zero where it has no interacting pair."""
+    torch = torch_gpu
+    water = [synth.small_box(300, RC, RB, 5), synth.small_box(400, RC, RB, 6)]
+    insts = [water[0]] + [CASES[k][0] for k in CASES] + [water[1]]
+    interacting = [True] + [CASES[k][1] for k in CASES] + [True]
+    assert all(np.array_equal(i.sigma, SIGMA) and np.array_equal(i.epsilon, EPS) and i.beta == insts[0].beta
+               for i in insts)
+    print(f"batch of {len(insts)} boxes, graph={graph}", flush=True)
+    ao, bx, params, x, q, t = nb.concat_instances(insts, clusters=[8] * len(insts), flags=nb.NB_ENERGY_FP64)
+    stream = torch.cuda.Stream()
+    bt = nb.nb_batch_setup(ao, bx, params, clusters=[8] * len(insts), stream=stream.cuda_stream)
+    try:
+        with torch.cuda.stream(stream):
+            dx = torch.from_numpy(x.reshape(-1)).to("cuda:0")
+            dq = torch.from_numpy(q).to("cuda:0")
+            dt = torch.from_numpy(t).to("cuda:0")
+            f = torch.zeros(len(q) * 3, dtype=torch.float32, device="cuda:0")
+            e = torch.zeros(2 * len(insts), dtype=torch.float64, device="cuda:0")
+        stream.synchronize()
+        nb.nb_batch_pairlist(bt, dx)
+        for _ in range(2):
+            (nb.nb_batch_graph_forces if graph else nb.nb_batch_forces)(bt, dx, dq, dt, f, e)
+        stream.synchronize()
+        assert nb.nb_batch_check(bt) == nb.NB_OK
+        fa = f.cpu().numpy().reshape(-1, 3).astype(np.float64)
+        ea = e.cpu().numpy().reshape(-1, 2)
+    finally:
+        nb.nb_batch_destroy(bt)
+    for k, inst in enumerate(insts):
+        fk, ek = fa[ao[k]:ao[k + 1]], ea[k]
+        if not interacting[k]:
+            assert np.all(fk == 0.0) and ek[0] == 0.0 and ek[1] == 0.0, k
+            continue
+        ref = O.instance_forces(inst, cells=False)
+        fr = rel_rms(fk, ref.f)
+        elj = abs(ek[0] - ref.e_lj) / abs(ref.e_lj)
+        ec = abs(ek[1] - ref.e_coul) / abs(ref.e_coul)
+        print(f"box {k} n={inst.natoms} force relRMS {fr:.2e} E_LJ rel {elj:.2e} E_C rel {ec:.2e}", flush=True)
+        assert fr <= FORCE_TOL and elj <= ENERGY_TOL and ec <= ENERGY_TOL, k
