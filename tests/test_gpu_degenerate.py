@@ -8,7 +8,7 @@ import pytest
 
 from oracle import oracle as O
 from paper_2405_01420_amd import nb, synth
-from tests.gpu_helpers import ENERGY_TOL, FORCE_TOL, GpuBox, rel_rms
+from tests.gpu_helpers import ENERGY_TOL, FORCE_TOL, GpuBox, dev, rel_rms
 
 pytestmark = pytest.mark.gpu
 
@@ -116,3 +116,42 @@ def test_smallest_systems_in_a_batch(torch_gpu, graph):
         ec = abs(ek[1] - ref.e_coul) / abs(ref.e_coul)
         print(f"box {k} n={inst.natoms} force relRMS {fr:.2e} E_LJ rel {elj:.2e} E_C rel {ec:.2e}", flush=True)
         assert fr <= FORCE_TOL and elj <= ENERGY_TOL and ec <= ENERGY_TOL, k
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_smallest_systems_backward(torch_gpu, name):
+    """The adjoint on the same boxes with seeded cotangents: dx, dq and the LJ-parameter
+    gradients of the oracle's analytic VJP (relative <= 5e-6), or exactly zero without an
+    interacting pair (also for the null-type pair, whose terms all carry a zero factor)."""
+    torch = torch_gpu
+    inst, interacting = CASES[name]
+    print(f"case {name}", flush=True)
+    rng = np.random.default_rng(11)
+    gF = rng.standard_normal((inst.natoms, 3)).astype(np.float32)
+    gE = np.array([0.7, -1.3])
+    box = GpuBox(torch, inst)
+    try:
+        gf, ge = dev(torch, gF.reshape(-1)), dev(torch, gE)
+        dx = torch.empty(inst.natoms * 3, dtype=torch.float32, device="cuda:0")
+        dq = torch.empty(inst.natoms, dtype=torch.float32, device="cuda:0")
+        ds = torch.empty(inst.ntypes, dtype=torch.float64, device="cuda:0")
+        de = torch.empty(inst.ntypes, dtype=torch.float64, device="cuda:0")
+        nb.nb_backward(box.ctx, box.x, box.q, box.t, gf, ge, dx, dq, ds, de, 0)
+        torch.cuda.synchronize()
+        assert nb.nb_check(box.ctx) == nb.NB_OK
+        gx = dx.cpu().numpy().reshape(-1, 3).astype(np.float64)
+        gq = dq.cpu().numpy().astype(np.float64)
+        gs, ge_ = ds.cpu().numpy(), de.cpu().numpy()
+    finally:
+        box.close()
+    if not interacting:
+        assert np.all(gx == 0.0) and np.all(gq == 0.0) and np.all(gs == 0.0) and np.all(ge_ == 0.0)
+        return
+    rdx, rdq, rds, rde = O.vjp(inst.x, inst.q, inst.type, inst.sigma, inst.epsilon, inst.box,
+                               inst.cutoff, inst.beta, inst.coulomb_const, inst.excl_off,
+                               inst.excl_idx, gF.astype(np.float64), gE)
+    ex, eq = rel_rms(gx, rdx), rel_rms(gq, rdq)
+    es, ee = abs(gs[0] - rds[0]) / abs(rds[0]), abs(ge_[0] - rde[0]) / abs(rde[0])
+    print(f"dx {ex:.2e} dq {eq:.2e} dsigma {es:.2e} deps {ee:.2e}", flush=True)
+    assert ex <= FORCE_TOL and eq <= FORCE_TOL and es <= FORCE_TOL and ee <= FORCE_TOL
+    assert gs[1] == 0.0 and ge_[1] == 0.0   # the null type has no pair here
