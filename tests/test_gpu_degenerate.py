@@ -155,3 +155,51 @@ def test_smallest_systems_backward(torch_gpu, name):
     print(f"dx {ex:.2e} dq {eq:.2e} dsigma {es:.2e} deps {ee:.2e}", flush=True)
     assert ex <= FORCE_TOL and eq <= FORCE_TOL and es <= FORCE_TOL and ee <= FORCE_TOL
     assert gs[1] == 0.0 and ge_[1] == 0.0   # the null type has no pair here
+
+
+def column_stack(n):
+    """n atoms of the null type, uncharged, stacked along z in one grid column of a 20 nm box
+    (the grid's column width there is 2.5 nm), 20 / n nm apart."""
+    Lb = 20.0
+    x = np.zeros((n, 3), dtype=np.float32)
+    x[:, 0], x[:, 1] = 1.0, 1.0
+    x[:, 2] = (np.arange(n) + 0.5) * (Lb / n)
+    inst = make(x, np.zeros(n), np.ones(n, dtype=np.int32))
+    inst.box = synth.f32(Lb)
+    inst.name = f"column_{n}"
+    return inst
+
+
+@pytest.mark.parametrize("cluster", [8, 4])
+def test_column_at_the_sort_limit(torch_gpu, cluster):
+    """A column of the largest size the build sorts (4096 atoms): the pair set is the oracle's
+    and the forces and energies of the null type are zero."""
+    inst = column_stack(4096)
+    print(f"column of {inst.natoms} atoms, C={cluster}", flush=True)
+    box = GpuBox(torch_gpu, inst, cluster=cluster)
+    try:
+        box.pairlist()
+        assert box.stats()["nclusters"] == 4096 // cluster   # all in one column
+        f, e = box.forces()
+        pairs = np.asarray(box.pairs(), dtype=np.int64).reshape(-1, 2)
+        assert nb.nb_check(box.ctx) == nb.NB_OK
+    finally:
+        box.close()
+    pi, pj, _ = O.pairs(inst.x, inst.box, inst.cutoff, inst.excl_off, inst.excl_idx)
+    n = inst.natoms
+    assert len(pairs) == len(pi) > 0
+    assert np.array_equal(np.sort(pairs[:, 0] * n + pairs[:, 1]), np.sort(pi.astype(np.int64) * n + pj))
+    assert np.all(f == 0.0) and e[0] == 0.0 and e[1] == 0.0
+
+
+def test_column_over_the_sort_limit_is_reported(torch_gpu):
+    """One atom more than the build sorts in a column: nb_pairlist reports NB_ERR_OVERFLOW."""
+    inst = column_stack(4097)
+    print(f"column of {inst.natoms} atoms", flush=True)
+    box = GpuBox(torch_gpu, inst)
+    try:
+        with pytest.raises(nb.NbError) as ei:
+            box.pairlist()
+        assert ei.value.code == nb.NB_ERR_OVERFLOW
+    finally:
+        box.close()
