@@ -2,13 +2,15 @@
 energies, an empty pair set), two atoms inside the cutoff (directly and across a periodic face),
 two atoms beyond it, an excluded pair, and a pair whose type has no Lennard-Jones term and no
 charge.  Such boxes leave most columns of the grid empty and hold a single cluster.  Forces and
-energies are compared with the oracle (interacting pairs) or are exactly zero (no pair)."""
+energies are compared with the oracle (interacting pairs) or are exactly zero (no pair).  Also
+the limits the library states: a grid column of the largest size the build sorts (and one atom
+more, reported as an overflow) and the largest LJ type table."""
 import numpy as np
 import pytest
 
 from oracle import oracle as O
 from paper_2405_01420_amd import nb, synth
-from tests.gpu_helpers import ENERGY_TOL, FORCE_TOL, GpuBox, dev, rel_rms
+from tests.gpu_helpers import ENERGY_TOL, FORCE_TOL, FP32_SMALL_BOX_EC_TOL, GpuBox, dev, rel_rms
 
 pytestmark = pytest.mark.gpu
 
@@ -203,3 +205,28 @@ def test_column_over_the_sort_limit_is_reported(torch_gpu):
         assert ei.value.code == nb.NB_ERR_OVERFLOW
     finally:
         box.close()
+
+
+@pytest.mark.parametrize("cluster", [8, 4])
+@pytest.mark.parametrize("flags", [0, nb.NB_ENERGY_FP64])
+def test_largest_type_table(torch_gpu, cluster, flags):
+    """32 LJ types, the most the library takes (the type-pair table then fills 32 KB of the
+    force kernel's LDS): the 648-atom water box with 30 extra types on 90% of its oxygens,
+    against the oracle (E_C to the FP32 bound of so small a box with FP32 pair energies)."""
+    inst = synth.retype(synth.tiny(), 30, 0.9, seed=3)
+    assert inst.ntypes == 32 and len(np.unique(inst.type)) > 20
+    print(f"32 types, C={cluster} flags={flags}", flush=True)
+    box = GpuBox(torch_gpu, inst, cluster=cluster, flags=flags)
+    try:
+        box.pairlist()
+        f, e = box.forces()
+        assert nb.nb_check(box.ctx) == nb.NB_OK
+    finally:
+        box.close()
+    ref = O.instance_forces(inst, cells=False)
+    fr = rel_rms(f, ref.f)
+    elj = abs(e[0] - ref.e_lj) / abs(ref.e_lj)
+    ec = abs(e[1] - ref.e_coul) / abs(ref.e_coul)
+    print(f"force relRMS {fr:.2e} E_LJ rel {elj:.2e} E_C rel {ec:.2e}", flush=True)
+    assert fr <= FORCE_TOL and elj <= ENERGY_TOL
+    assert ec <= (ENERGY_TOL if flags & nb.NB_ENERGY_FP64 else FP32_SMALL_BOX_EC_TOL)
