@@ -230,3 +230,59 @@ def test_largest_type_table(torch_gpu, cluster, flags):
     print(f"force relRMS {fr:.2e} E_LJ rel {elj:.2e} E_C rel {ec:.2e}", flush=True)
     assert fr <= FORCE_TOL and elj <= ENERGY_TOL
     assert ec <= (ENERGY_TOL if flags & nb.NB_ENERGY_FP64 else FP32_SMALL_BOX_EC_TOL)
+
+
+def test_largest_type_table_tabulated_ewald_and_backward(torch_gpu):
+    """32 LJ types with the kernels that hold more tables beside the type table in LDS: the
+    tabulated Ewald flavour (its FP32 force table and the FP64 erfc table) against the oracle at
+    the 1e-6 energy gate, and the adjoint against the oracle's VJP (normwise, 5e-6)."""
+    torch = torch_gpu
+    inst = synth.retype(synth.tiny(), 30, 0.9, seed=3)
+    print("32 types: tabulated Ewald", flush=True)
+    box = GpuBox(torch, inst, elec=nb.NB_ELEC_EWALD_TAB)
+    try:
+        box.pairlist()
+        f, e = box.forces()
+        assert nb.nb_check(box.ctx) == nb.NB_OK
+    finally:
+        box.close()
+    ref = O.instance_forces(inst, cells=False)
+    fr = rel_rms(f, ref.f)
+    elj = abs(e[0] - ref.e_lj) / abs(ref.e_lj)
+    ec = abs(e[1] - ref.e_coul) / abs(ref.e_coul)
+    print(f"force relRMS {fr:.2e} E_LJ rel {elj:.2e} E_C rel {ec:.2e}", flush=True)
+    assert fr <= FORCE_TOL and elj <= ENERGY_TOL and ec <= ENERGY_TOL
+    print("32 types: backward", flush=True)
+    rng = np.random.default_rng(12)
+    gF = rng.standard_normal((inst.natoms, 3)).astype(np.float32)
+    gE = np.array([0.7, -1.3])
+    box = GpuBox(torch, inst)
+    try:
+        gf, ge = dev(torch, gF.reshape(-1)), dev(torch, gE)
+        dx = torch.empty(inst.natoms * 3, dtype=torch.float32, device="cuda:0")
+        dq = torch.empty(inst.natoms, dtype=torch.float32, device="cuda:0")
+        ds = torch.empty(inst.ntypes, dtype=torch.float64, device="cuda:0")
+        de = torch.empty(inst.ntypes, dtype=torch.float64, device="cuda:0")
+        nb.nb_backward(box.ctx, box.x, box.q, box.t, gf, ge, dx, dq, ds, de, 0)
+        torch.cuda.synchronize()
+        assert nb.nb_check(box.ctx) == nb.NB_OK
+        gx = dx.cpu().numpy().reshape(-1, 3).astype(np.float64)
+        gq = dq.cpu().numpy().astype(np.float64)
+        gs, ge_ = ds.cpu().numpy(), de.cpu().numpy()
+    finally:
+        box.close()
+    rdx, rdq, rds, rde = O.vjp(inst.x, inst.q, inst.type, inst.sigma, inst.epsilon, inst.box,
+                               inst.cutoff, inst.beta, inst.coulomb_const, inst.excl_off,
+                               inst.excl_idx, gF.astype(np.float64), gE)
+    ex, eq = rel_rms(gx, rdx), rel_rms(gq, rdq)
+    print(f"dx {ex:.2e} dq {eq:.2e}", flush=True)
+    assert ex <= FORCE_TOL and eq <= FORCE_TOL
+    # the LJ-parameter gradients normwise over the types present, like dx and dq: with ~6 atoms
+    # per type and random cotangents a single type's sum cancels to a few percent of its terms,
+    # so its elementwise relative error says more about that cancellation than about the kernel
+    present = [t for t in np.unique(inst.type) if inst.epsilon[t] > 0.0]
+    es, ee = rel_rms(gs[present], rds[present]), rel_rms(ge_[present], rde[present])
+    worst = max(max(abs(gs[t] - rds[t]) / abs(rds[t]), abs(ge_[t] - rde[t]) / abs(rde[t])) for t in present)
+    print(f"{len(present)} LJ types present: dsigma {es:.2e} deps {ee:.2e} (worst single type "
+          f"{worst:.2e})", flush=True)
+    assert es <= FORCE_TOL and ee <= FORCE_TOL
