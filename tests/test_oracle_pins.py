@@ -334,3 +334,24 @@ def test_pair_count_matches_uniform_density():
     r = O.instance_forces(inst, cells=True)
     est = O.useful_pair_estimate(inst.natoms, inst.box, inst.cutoff, inst.natoms // 3)
     assert abs(r.npairs / est - 1) < 0.01
+
+
+@pytest.mark.parametrize("n", [4096, 4097, 1024])
+def test_pair_count_of_an_evenly_spaced_periodic_line(n):
+    """n atoms d = L / n apart on a line along z of a periodic box (L = 20 nm): every atom has
+    exactly floor(rc / d) neighbours on each side within rc (none at rc exactly here), so the
+    pair set holds n floor(rc / d) pairs, those across the periodic face included, and each
+    pair's distance is a multiple of d."""
+    L, rc = 20.0, np.float32(0.9)
+    x = np.zeros((n, 3), dtype=np.float32)
+    x[:, 0] = x[:, 1] = 1.0
+    x[:, 2] = (np.arange(n) + 0.5) * (L / n)
+    pi, pj, pr = O.pairs(x, np.float32(L), rc)
+    d = L / n
+    k = math.floor(float(rc) / d)
+    assert abs(k * d - float(rc)) > 1e-4 and abs((k + 1) * d - float(rc)) > 1e-4
+    assert len(pi) == n * k
+    steps = np.rint(pr / d)
+    assert np.all((steps >= 1) & (steps <= k)) and np.allclose(pr, steps * d, atol=1e-5)
+    # every separation 1 .. k occurs n times, counting the pairs that wrap around the box
+    assert np.array_equal(np.bincount(steps.astype(int), minlength=k + 1)[1:], np.full(k, n))
