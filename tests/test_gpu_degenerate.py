@@ -286,3 +286,41 @@ def test_largest_type_table_tabulated_ewald_and_backward(torch_gpu):
     print(f"{len(present)} LJ types present: dsigma {es:.2e} deps {ee:.2e} (worst single type "
           f"{worst:.2e})", flush=True)
     assert es <= FORCE_TOL and ee <= FORCE_TOL
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_largest_type_table_in_a_batch(torch_gpu, graph):
+    """32 LJ types in the batched kernel (FP64 pair energies): two water boxes whose oxygens take
+    30 extra types, against the oracle."""
+    torch = torch_gpu
+    insts = [synth.retype(synth.small_box(300, RC, RB, 5), 30, 0.9, seed=3),
+             synth.retype(synth.small_box(400, RC, RB, 6), 30, 0.9, seed=3)]
+    assert np.array_equal(insts[0].sigma, insts[1].sigma) and insts[0].ntypes == 32
+    print(f"32 types in a batch, graph={graph}", flush=True)
+    ao, bx, params, x, q, t = nb.concat_instances(insts, clusters=[8, 8], flags=nb.NB_ENERGY_FP64)
+    stream = torch.cuda.Stream()
+    bt = nb.nb_batch_setup(ao, bx, params, clusters=[8, 8], stream=stream.cuda_stream)
+    try:
+        with torch.cuda.stream(stream):
+            dx = torch.from_numpy(x.reshape(-1)).to("cuda:0")
+            dq = torch.from_numpy(q).to("cuda:0")
+            dt = torch.from_numpy(t).to("cuda:0")
+            f = torch.zeros(len(q) * 3, dtype=torch.float32, device="cuda:0")
+            e = torch.zeros(2 * len(insts), dtype=torch.float64, device="cuda:0")
+        stream.synchronize()
+        nb.nb_batch_pairlist(bt, dx)
+        for _ in range(2):
+            (nb.nb_batch_graph_forces if graph else nb.nb_batch_forces)(bt, dx, dq, dt, f, e)
+        stream.synchronize()
+        assert nb.nb_batch_check(bt) == nb.NB_OK
+        fa = f.cpu().numpy().reshape(-1, 3).astype(np.float64)
+        ea = e.cpu().numpy().reshape(-1, 2)
+    finally:
+        nb.nb_batch_destroy(bt)
+    for k, inst in enumerate(insts):
+        ref = O.instance_forces(inst, cells=False)
+        fr = rel_rms(fa[ao[k]:ao[k + 1]], ref.f)
+        elj = abs(ea[k, 0] - ref.e_lj) / abs(ref.e_lj)
+        ec = abs(ea[k, 1] - ref.e_coul) / abs(ref.e_coul)
+        print(f"box {k} n={inst.natoms} force relRMS {fr:.2e} E_LJ rel {elj:.2e} E_C rel {ec:.2e}", flush=True)
+        assert fr <= FORCE_TOL and elj <= ENERGY_TOL and ec <= ENERGY_TOL, k
